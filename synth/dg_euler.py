@@ -1,0 +1,465 @@
+"""Seeded synthetic workload: the DG Jacobian of the 2D Euler equations.
+
+This module generates the *input* of the solver (a block-sparse matrix A, a
+manufactured solution x* and b = A x*).  It holds none of the solver's
+arithmetic (no nested dissection, no factorization, no Krylov method); both
+the CPU oracle and the GPU path consume what it produces.
+
+What is assembled (paper, Sec. "Flow Solver", Eqs. (1)-(8)):
+
+* Euler equations u_t + div F = 0 with u = (rho, rho*u, rho*v, E)  (Eq. 1),
+  gamma = 1.4.
+* K = n*n square quad elements on [0,1]^2 (Eq. 2), element e = j*n + i
+  covers [i h,(i+1) h] x [j h,(j+1) h], h = 1/n.
+* Modal expansion (Eq. 3) in the orthonormal tensor Legendre basis
+  psi_ab(xi,eta) = P~_a(xi) P~_b(eta), P~_a = sqrt((2a+1)/2) P_a, 0<=a,b<=p.
+  Mode index m = a(p+1)+b; local dof index 4m + c (mode-major, variable-
+  minor), so one block row has b = 4 (p+1)^2 unknowns.
+* Weak form / residual R = -int F . grad(psi) + oint F* . n psi  (Eqs. 4, 7)
+  linearised about a per-element-constant base state; Lax-Friedrichs
+  numerical flux F* = 1/2 (F_L + F_R).n - 1/2 lambda (u_R - u_L) with the
+  spectral radius lambda (nomenclature) frozen at the base state.
+* Mass matrix M_k = (h/2)^2 I (Eq. 6 with an orthonormal basis) and the
+  pseudo-time system A = M / dtau + dR/du (Eq. 5) with
+  dtau = CFL / max_k lambda_k (Eq. 8), lambda_k = (2p+1)(|v_k| + c_k)/h.
+
+Boundaries: periodic in x, Lax-Friedrichs far-field against the free stream
+in y (contributes to the diagonal block only).
+
+Base state: primitive variables w in {rho, u, v, p} of the free stream
+(rho=1, |V|=1 at angle alpha, p = 1/(gamma M^2)) times
+(1 + amp sin(2 pi x_c + phi_w) sin(2 pi y_c + psi_w)) at the element
+centroid; the eight phases are the first draws of
+numpy.random.default_rng(seed), x* ~ N(0,1) the next N draws.
+
+Every integrand is a polynomial because the base state is constant per
+element, so the operators below are closed forms (the volume term uses
+S_ca = int P~_c P~_a' = sqrt((2a+1)(2c+1)) for c<a, a+c odd).
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+GAMMA = 1.4
+
+
+@dataclasses.dataclass(frozen=True)
+class DGConfig:
+    n: int = 16                 # grid is n x n elements
+    p: int = 1                  # polynomial order
+    mach: float = 0.5
+    alpha_deg: float = 2.0
+    amp: float = 0.05           # relative amplitude of the base-state perturbation
+    cfl: float = 10.0
+    seed: int = 0
+    periodic_x: bool = True
+    periodic_y: bool = False    # False: far-field in y
+
+    @property
+    def K(self) -> int:
+        return self.n * self.n
+
+    @property
+    def b(self) -> int:
+        return 4 * (self.p + 1) ** 2
+
+    @property
+    def N(self) -> int:
+        return self.K * self.b
+
+
+@dataclasses.dataclass
+class BSR:
+    """Block-sparse row matrix: row-major b x b blocks, ascending columns."""
+    n_brows: int
+    bs: int
+    rowptr: np.ndarray   # int32 [n_brows+1]
+    colind: np.ndarray   # int32 [nnzb]
+    val: np.ndarray      # float64 [nnzb, bs, bs]
+
+    @property
+    def nnzb(self) -> int:
+        return int(self.colind.shape[0])
+
+    @property
+    def N(self) -> int:
+        return self.n_brows * self.bs
+
+    def to_scipy(self):
+        import scipy.sparse as sp
+        return sp.bsr_matrix((self.val, self.colind, self.rowptr),
+                             shape=(self.N, self.N))
+
+    def matvec(self, x: np.ndarray) -> np.ndarray:
+        return self.to_scipy() @ x
+
+
+# ---------------------------------------------------------------- physics
+
+def primitive_to_conserved(rho, u, v, p):
+    E = p / (GAMMA - 1.0) + 0.5 * rho * (u * u + v * v)
+    return np.stack([rho, rho * u, rho * v, E], axis=-1)
+
+
+def conserved_to_primitive(U):
+    rho = U[..., 0]
+    u = U[..., 1] / rho
+    v = U[..., 2] / rho
+    p = (GAMMA - 1.0) * (U[..., 3] - 0.5 * rho * (u * u + v * v))
+    return rho, u, v, p
+
+
+def euler_flux(U):
+    """Physical fluxes F (x) and G (y) of Eq. (1); U [...,4] -> ([...,4], [...,4])."""
+    rho, u, v, p = conserved_to_primitive(U)
+    E = U[..., 3]
+    F = np.stack([rho * u, rho * u * u + p, rho * u * v, u * (E + p)], axis=-1)
+    G = np.stack([rho * v, rho * u * v, rho * v * v + p, v * (E + p)], axis=-1)
+    return F, G
+
+
+def flux_jacobians(U):
+    """Closed-form dF/dU and dG/dU, shape [..., 4, 4]."""
+    rho, u, v, p = conserved_to_primitive(U)
+    E = U[..., 3]
+    g1 = GAMMA - 1.0
+    q2 = u * u + v * v
+    H = (E + p) / rho
+    z = np.zeros_like(rho)
+    o = np.ones_like(rho)
+    A = np.stack([
+        np.stack([z, o, z, z], -1),
+        np.stack([0.5 * g1 * q2 - u * u, (3.0 - GAMMA) * u, -g1 * v, g1 * o], -1),
+        np.stack([-u * v, v, u, z], -1),
+        np.stack([u * (0.5 * g1 * q2 - H), H - g1 * u * u, -g1 * u * v, GAMMA * u], -1),
+    ], -2)
+    B = np.stack([
+        np.stack([z, z, o, z], -1),
+        np.stack([-u * v, v, u, z], -1),
+        np.stack([0.5 * g1 * q2 - v * v, -g1 * u, (3.0 - GAMMA) * v, g1 * o], -1),
+        np.stack([v * (0.5 * g1 * q2 - H), -g1 * u * v, H - g1 * v * v, GAMMA * v], -1),
+    ], -2)
+    return A, B
+
+
+def sound_speed(U):
+    rho, _, _, p = conserved_to_primitive(U)
+    return np.sqrt(GAMMA * p / rho)
+
+
+def freestream(cfg: DGConfig):
+    a = math.radians(cfg.alpha_deg)
+    return primitive_to_conserved(np.float64(1.0), np.float64(math.cos(a)),
+                                  np.float64(math.sin(a)),
+                                  np.float64(1.0 / (GAMMA * cfg.mach ** 2)))
+
+
+def draw_phases(rng):
+    return rng.uniform(0.0, 2.0 * math.pi, size=8)
+
+
+def base_state(cfg: DGConfig, phases: np.ndarray, amp: float | None = None):
+    """Per-element conserved base state, shape [K, 4] (element e = j n + i)."""
+    amp = cfg.amp if amp is None else amp
+    n = cfg.n
+    h = 1.0 / n
+    xc = (np.arange(n) + 0.5) * h
+    X = np.tile(xc, n)            # i fastest
+    Y = np.repeat(xc, n)
+    a = math.radians(cfg.alpha_deg)
+    winf = [1.0, math.cos(a), math.sin(a), 1.0 / (GAMMA * cfg.mach ** 2)]
+    w = []
+    for q in range(4):
+        f = 1.0 + amp * np.sin(2 * math.pi * X + phases[q]) * np.sin(2 * math.pi * Y + phases[4 + q])
+        w.append(winf[q] * f)
+    return primitive_to_conserved(*w)
+
+
+# ---------------------------------------------------------------- basis
+
+def legendre_trace(p):
+    """P~_a(+1), P~_a(-1) for a = 0..p."""
+    a = np.arange(p + 1)
+    s = np.sqrt((2 * a + 1) / 2.0)
+    return s, s * (-1.0) ** a
+
+
+def stiffness_1d(p):
+    """S[c, a] = int_{-1}^{1} P~_c P~_a' dxi (closed form)."""
+    S = np.zeros((p + 1, p + 1))
+    for a in range(p + 1):
+        for c in range(a):
+            if (a + c) % 2 == 1:
+                S[c, a] = math.sqrt((2 * a + 1) * (2 * c + 1))
+    return S
+
+
+def mode_operators(p):
+    """Mode-space coupling matrices, indexed [test m=(a,b), trial m'=(c,d)].
+
+    Returns a dict with 'Sx','Sy' (volume) and face trace products
+    'xR_kk','xR_kn','xL_kk','xL_kn','yT_kk','yT_kn','yB_kk','yB_kn'.
+    """
+    q = p + 1
+    I = np.eye(q)
+    S = stiffness_1d(p)           # S[c, a]
+    Pp, Pm = legendre_trace(p)
+    # test index (a,b) -> row, trial (c,d) -> column, m = a*q + b
+    Sx = np.kron(S.T, I)          # [ (a,b), (c,d) ] = S[c,a] delta_bd
+    Sy = np.kron(I, S.T)          # delta_ac S[d,b]
+    ops = {"Sx": Sx, "Sy": Sy}
+    ops["xR_kk"] = np.kron(np.outer(Pp, Pp), I)   # P~_a(1) P~_c(1) d_bd
+    ops["xR_kn"] = np.kron(np.outer(Pp, Pm), I)   # P~_a(1) P~_c(-1)
+    ops["xL_kk"] = np.kron(np.outer(Pm, Pm), I)
+    ops["xL_kn"] = np.kron(np.outer(Pm, Pp), I)
+    ops["yT_kk"] = np.kron(I, np.outer(Pp, Pp))   # d_ac P~_b(1) P~_d(1)
+    ops["yT_kn"] = np.kron(I, np.outer(Pp, Pm))
+    ops["yB_kk"] = np.kron(I, np.outer(Pm, Pm))
+    ops["yB_kn"] = np.kron(I, np.outer(Pm, Pp))
+    return ops
+
+
+# ---------------------------------------------------------------- assembly
+
+def _neighbours(cfg: DGConfig):
+    """Neighbour element ids (or -1 for a far-field face) in order R, L, T, B."""
+    n = cfg.n
+    e = np.arange(cfg.K)
+    i = e % n
+    j = e // n
+
+    def nb(di, dj):
+        ii = i + di
+        jj = j + dj
+        ok = np.ones(cfg.K, dtype=bool)
+        if cfg.periodic_x:
+            ii = ii % n
+        else:
+            ok &= (ii >= 0) & (ii < n)
+        if cfg.periodic_y:
+            jj = jj % n
+        else:
+            ok &= (jj >= 0) & (jj < n)
+        return np.where(ok, jj * n + ii, -1)
+
+    return nb(1, 0), nb(-1, 0), nb(0, 1), nb(0, -1)
+
+
+def face_lambda(U, UN, nx, ny):
+    """Frozen LF spectral radius max(|v_n| + c) over both sides of a face."""
+    def lam(W):
+        rho, u, v, _ = conserved_to_primitive(W)
+        return np.abs(u * nx + v * ny) + sound_speed(W)
+    return np.maximum(lam(U), lam(UN))
+
+
+def pseudo_time_step(cfg: DGConfig, U):
+    rho, u, v, _ = conserved_to_primitive(U)
+    h = 1.0 / cfg.n
+    lam = (2 * cfg.p + 1) * (np.sqrt(u * u + v * v) + sound_speed(U)) / h
+    return cfg.cfl / lam.max()
+
+
+def _pattern(cfg: DGConfig):
+    """Block pattern (rows, cols) of A with duplicates merged; returns
+    rowptr, colind and, per (element, face) contribution, its block slot."""
+    R, Lf, T, Bf = _neighbours(cfg)
+    K = cfg.K
+    e = np.arange(K)
+    rows = [e]
+    cols = [e]
+    for nbr in (R, Lf, T, Bf):
+        m = nbr >= 0
+        rows.append(e[m])
+        cols.append(nbr[m])
+    rows = np.concatenate(rows)
+    cols = np.concatenate(cols)
+    key = rows.astype(np.int64) * K + cols
+    ukey, inv = np.unique(key, return_inverse=True)
+    urow = (ukey // K).astype(np.int64)
+    ucol = (ukey % K).astype(np.int32)
+    rowptr = np.zeros(K + 1, dtype=np.int64)
+    np.add.at(rowptr, urow + 1, 1)
+    rowptr = np.cumsum(rowptr)
+    slots = []
+    off = 0
+    slots.append(inv[off:off + K]); off += K
+    for nbr in (R, Lf, T, Bf):
+        cnt = int((nbr >= 0).sum())
+        s = np.full(K, -1, dtype=np.int64)
+        s[nbr >= 0] = inv[off:off + cnt]
+        off += cnt
+        slots.append(s)
+    return rowptr.astype(np.int32), ucol, slots, (R, Lf, T, Bf)
+
+
+def assemble(cfg: DGConfig, amp: float | None = None, include_mass: bool = True,
+             phases: np.ndarray | None = None):
+    """Assemble A = M/dtau + dR/du (BSR, float64).  Returns (A, info)."""
+    rng = np.random.default_rng(cfg.seed)
+    if phases is None:
+        phases = draw_phases(rng)
+    U = base_state(cfg, phases, amp)
+    Ainf = freestream(cfg)
+    Ax, By = flux_jacobians(U)
+    c = sound_speed(U)
+    rho, u, v, _ = conserved_to_primitive(U)
+    h = 1.0 / cfg.n
+    hh = 0.5 * h
+    ops = mode_operators(cfg.p)
+    q2 = (cfg.p + 1) ** 2
+    bsz = cfg.b
+    rowptr, colind, slots, (R, Lf, T, Bf) = _pattern(cfg)
+    nnzb = colind.shape[0]
+    val = np.zeros((nnzb, bsz, bsz))
+    I4 = np.eye(4)
+    K = cfg.K
+    e = np.arange(K)
+
+    def kron_add(slot, mode_mat, flux):
+        # val[slot][4m+i, 4m'+j] += mode_mat[m,m'] * flux[k,i,j]
+        # slots are distinct within one call (one face side per element)
+        blk = np.einsum("mn,kij->kminj", mode_mat, flux).reshape(-1, bsz, bsz)
+        val[slot] += blk
+
+    # volume term
+    diag = slots[0]
+    kron_add(diag, ops["Sx"], -hh * Ax)
+    kron_add(diag, ops["Sy"], -hh * By)
+    # faces: (neighbour array, slot, normal, flux jac of self/nbr, ops keys)
+    Uinf = np.broadcast_to(Ainf, U.shape)
+    Ainf_x, Binf_y = flux_jacobians(Ainf[None, :])
+    faces = [
+        (R, slots[1], (1.0, 0.0), Ax, 1.0, "xR_kk", "xR_kn"),
+        (Lf, slots[2], (-1.0, 0.0), Ax, -1.0, "xL_kk", "xL_kn"),
+        (T, slots[3], (0.0, 1.0), By, 1.0, "yT_kk", "yT_kn"),
+        (Bf, slots[4], (0.0, -1.0), By, -1.0, "yB_kk", "yB_kn"),
+    ]
+    for nbr, slot, (nx, ny), Jac, sgn, kk, kn in faces:
+        inner = nbr >= 0
+        UN = np.where(inner[:, None], U[np.maximum(nbr, 0)], Uinf)
+        lam = face_lambda(U, UN, nx, ny)
+        # self contribution: (h/2)(1/2 A_n(u_k) + 1/2 lam I)
+        fk = hh * (0.5 * sgn * Jac + 0.5 * lam[:, None, None] * I4)
+        kron_add(diag, ops[kk], fk)
+        if inner.any():
+            nb_e = nbr[inner]
+            fn = hh * (0.5 * sgn * Jac[nb_e] - 0.5 * lam[inner][:, None, None] * I4)
+            kron_add(slot[inner], ops[kn], fn)
+    dtau = pseudo_time_step(cfg, U)
+    if include_mass:
+        mass = hh * hh / dtau
+        idx = np.arange(bsz)
+        val[diag[:, None], idx[None, :], idx[None, :]] += mass
+    A = BSR(K, bsz, rowptr, colind.astype(np.int32), val)
+    info = dict(U=U, phases=phases, dtau=dtau, rng=rng, q2=q2)
+    return A, info
+
+
+def make_problem(cfg: DGConfig):
+    """A, x* ~ N(0,1), b = A x* (all float64) for the seeded config."""
+    A, info = assemble(cfg)
+    rng = info["rng"]
+    xstar = rng.standard_normal(cfg.N)
+    b = A.matvec(xstar)
+    return A, xstar, b, info
+
+
+# ---------------------------------------------------------------- residual
+
+def _gauss(npts):
+    x, w = np.polynomial.legendre.leggauss(npts)
+    return x, w
+
+
+def _legendre_vals(p, x):
+    """P~_a(x) and P~_a'(x) for a=0..p at points x -> [p+1, len(x)]."""
+    V = np.zeros((p + 1, len(x)))
+    D = np.zeros((p + 1, len(x)))
+    for a in range(p + 1):
+        c = np.zeros(a + 1); c[a] = 1.0
+        s = math.sqrt((2 * a + 1) / 2.0)
+        V[a] = s * np.polynomial.legendre.legval(x, c)
+        D[a] = s * np.polynomial.legendre.legval(x, np.polynomial.legendre.legder(c))
+    return V, D
+
+
+def residual(cfg: DGConfig, uhat: np.ndarray, lam_state: np.ndarray):
+    """Nonlinear spatial residual R(u) of Eq. (7), evaluated by Gauss-Legendre
+    quadrature with p+2 points per direction, LF spectral radius frozen at the
+    per-element state ``lam_state`` [K,4].  ``uhat`` is [K, (p+1)^2, 4] modal.
+    Returns [K, (p+1)^2, 4]."""
+    p = cfg.p
+    q = p + 1
+    n = cfg.n
+    h = 1.0 / n
+    hh = 0.5 * h
+    xg, wg = _gauss(p + 2)
+    V, D = _legendre_vals(p, xg)
+    Pp, Pm = legendre_trace(p)
+    K = cfg.K
+    # values at volume points: u(xi_r, eta_s) = sum_ab uhat[ab] V[a,r] V[b,s]
+    uh = uhat.reshape(K, q, q, 4)
+    Uq = np.einsum("kabc,ar,bs->krsc", uh, V, V)
+    F, G = euler_flux(Uq)
+    W = np.outer(wg, wg)
+    # -(h/2) sum w [F d_xi psi + G d_eta psi]
+    Rv = -hh * (np.einsum("krsc,rs,ar,bs->kabc", F, W, D, V)
+                + np.einsum("krsc,rs,ar,bs->kabc", G, W, V, D))
+    Res = Rv.copy()
+    R_, L_, T_, B_ = _neighbours(cfg)
+    Uinf = freestream(cfg)
+
+    def trace_x(uh_k, side):     # side: +1 -> xi=1, -1 -> xi=-1; returns [K, npts, 4]
+        t = Pp if side > 0 else Pm
+        return np.einsum("kabc,a,bs->ksc", uh_k, t, V)
+
+    def trace_y(uh_k, side):
+        t = Pp if side > 0 else Pm
+        return np.einsum("kabc,b,as->ksc", uh_k, t, V)
+
+    def lf(UL, UR, nx, ny, lam):
+        FL, GL = euler_flux(UL)
+        FR, GR = euler_flux(UR)
+        return 0.5 * ((FL + FR) * nx + (GL + GR) * ny) - 0.5 * lam[..., None] * (UR - UL)
+
+    faces = [(R_, 1, 0, +1, "x"), (L_, -1, 0, -1, "x"), (T_, 0, 1, +1, "y"), (B_, 0, -1, -1, "y")]
+    for nbr, nx, ny, side, ax in faces:
+        inner = nbr >= 0
+        lamN = np.where(inner[:, None], lam_state[np.maximum(nbr, 0)], Uinf[None, :])
+        lam = face_lambda(lam_state, lamN, nx, ny)
+        if ax == "x":
+            UL = trace_x(uh, side)
+            UR = trace_x(uh[np.maximum(nbr, 0)], -side)
+            tt = Pp if side > 0 else Pm
+        else:
+            UL = trace_y(uh, side)
+            UR = trace_y(uh[np.maximum(nbr, 0)], -side)
+            tt = Pp if side > 0 else Pm
+        UR = np.where(inner[:, None, None], UR, Uinf[None, None, :])
+        Fs = lf(UL, UR, nx, ny, lam[:, None])
+        if ax == "x":
+            Res += hh * np.einsum("ksc,s,a,bs->kabc", Fs, wg, tt, V)
+        else:
+            Res += hh * np.einsum("ksc,s,b,as->kabc", Fs, wg, tt, V)
+    return Res.reshape(K, q * q, 4)
+
+
+def state_to_modal(cfg: DGConfig, U: np.ndarray):
+    """Per-element constant state -> modal coefficients (mode 0 only)."""
+    q2 = (cfg.p + 1) ** 2
+    uh = np.zeros((cfg.K, q2, 4))
+    uh[:, 0, :] = U * 2.0        # psi_00 = P~_0 P~_0 = 1/2
+    return uh
+
+
+def modal_to_vector(uh: np.ndarray) -> np.ndarray:
+    """[K, (p+1)^2, 4] -> dof vector with local index 4m + c."""
+    return uh.reshape(-1)
+
+
+def vector_to_modal(cfg: DGConfig, x: np.ndarray) -> np.ndarray:
+    return x.reshape(cfg.K, (cfg.p + 1) ** 2, 4)
