@@ -1,0 +1,215 @@
+/*
+ * spand.h - C ABI of the MI355X spaND + s-step GMRES library (libspand.so).
+ *
+ * The library solves A x = b for the block-sparse Jacobian of an implicit
+ * DG discretisation (the linear system of the paper's Eq. (5)) with a
+ * sparsified-nested-dissection (spaND) factorization used as a right
+ * preconditioner of s-step GMRES.  All compute runs in HIP kernels on the
+ * current device; the host code only plans and launches.
+ *
+ * Conventions shared by every entry point
+ *  - Matrices are BSR: n_brows block rows of bs x bs blocks, blocks stored
+ *    row-major and contiguous, block columns strictly ascending in each
+ *    row.  Block row e corresponds to grid element (i, j) with
+ *    e = j * nx + i; inside a block the unknown index is 4*m + c (mode m,
+ *    conserved variable c), so bs = 4 (p+1)^2.
+ *  - Pointers named d_* are device pointers; h_* are host pointers.  The
+ *    caller owns all of them.  A is borrowed for the duration of a call:
+ *    the library copies what it keeps.
+ *  - Vectors are float64 of length N = n_brows * bs.
+ *  - "stream" is a hipStream_t passed as void* (0 = null stream).  Every
+ *    call is stream-ordered; calls that return host-visible results
+ *    (ranks, iteration counts) synchronise that stream before returning.
+ *  - Return value: SPAND_OK (0), a negative hard error or a positive soft
+ *    result (see spand_status_t).  spand_last_error() gives a message for
+ *    the last failure on the calling thread.
+ *  - A factor handle is used by one stream at a time.
+ */
+#ifndef SPAND_H
+#define SPAND_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SPAND_OK = 0,
+  SPAND_EINVAL = -1,      /* bad argument, detected before any launch       */
+  SPAND_ENOMEM = -2,      /* device allocation failed                        */
+  SPAND_ESINGULAR = -3,   /* exactly zero pivot met in a factorization       */
+  SPAND_EHIP = -4,        /* HIP runtime error                               */
+  SPAND_ENOTCONV = 1,     /* GMRES hit maxit; d_x holds the last iterate      */
+  SPAND_EBREAKDOWN = 2    /* CholQR met a non-SPD Gram matrix; d_x holds the
+                             iterate before the failing block                */
+} spand_status_t;
+
+typedef struct {
+  int32_t n_brows;          /* number of block rows (= grid elements K)      */
+  int32_t bs;               /* block size b                                  */
+  int64_t nnzb;             /* number of stored blocks                       */
+  const int32_t *d_rowptr;  /* [n_brows+1]                                   */
+  const int32_t *d_colind;  /* [nnzb], ascending inside each block row       */
+  const double *d_val;      /* [nnzb * bs * bs], row-major blocks            */
+} spand_bsr_t;
+
+typedef struct {
+  int32_t nx, ny;           /* element grid, n_brows = nx * ny               */
+  int32_t periodic_x;       /* 1: wrap-around adjacency in x                 */
+  int32_t periodic_y;       /* 1: wrap-around adjacency in y                 */
+} spand_grid_t;
+
+enum { SPAND_F64 = 0, SPAND_F32 = 1 };
+
+typedef struct {
+  double eps;               /* RRQR tolerance epsilon (>= 0); 0 keeps all    */
+  int32_t nlevels;          /* lmax; 0 -> round(log2(K/32)) + 1               */
+  int32_t factor_dtype;     /* SPAND_F64 or SPAND_F32 (storage and compute of
+                               the factor; vectors stay float64)            */
+  int32_t flags;            /* reserved, 0                                   */
+} spand_opts_t;
+
+typedef struct {
+  int32_t s;                /* block size of the s-step method (1..8)        */
+  int32_t restart;          /* restart length m, a multiple of s              */
+  int32_t maxit;            /* maximum number of Krylov vectors              */
+  int32_t transpose;        /* 1: solve A^T x = b, preconditioned by M^-T    */
+  double rtol;              /* stop when ||b - A x|| <= rtol ||b||            */
+} sstep_opts_t;
+
+#define SSTEP_MAX_HIST 1024
+typedef struct {
+  int32_t iters;            /* Krylov vectors used                           */
+  int32_t restarts;         /* cycles run                                    */
+  int32_t converged;        /* 1 if the true residual met rtol               */
+  int32_t n_hist;           /* entries in hist (<= SSTEP_MAX_HIST)           */
+  double relres;            /* true ||b - A x|| / ||b|| at exit               */
+  double hist[SSTEP_MAX_HIST]; /* |g_{k+1}| after every column (Givens)      */
+  int32_t n_shifts;         /* Newton shifts used (slots)                    */
+  double shift_re[8];
+  double shift_im[8];
+  /* phase times in milliseconds (hipEvent based, on the call's stream)    */
+  double t_total_ms, t_spmv_ms, t_apply_ms, t_orth_ms, t_other_ms;
+  int32_t n_spmv;           /* SpMV launches (t_spmv_ms covers exactly these) */
+  int32_t n_apply;          /* preconditioner applications                  */
+} sstep_stats_t;
+
+#define SPAND_MAX_LEVELS 32
+typedef struct {
+  int32_t nlevels;
+  int32_t n_clusters[SPAND_MAX_LEVELS];   /* interfaces sparsified per level */
+  int32_t rank_min[SPAND_MAX_LEVELS];
+  int32_t rank_max[SPAND_MAX_LEVELS];
+  double rank_avg[SPAND_MAX_LEVELS];
+  int64_t size_before[SPAND_MAX_LEVELS];  /* sum |s| before sparsification  */
+  int64_t size_after[SPAND_MAX_LEVELS];   /* sum k after sparsification      */
+  int32_t top_size;                       /* unknowns left at the top        */
+  int64_t factor_bytes;                   /* device bytes read by one apply  */
+  double factor_flops;                    /* algorithmic flops of the factor */
+  double t_host_ms;                       /* host ND + planning              */
+  double t_device_ms;                     /* device phases (event timed)     */
+  double t_lu_ms, t_schur_ms, t_scale_ms, t_rrqr_ms, t_compress_ms;
+} spand_factor_stats_t;
+
+typedef struct spand_factor_s *spand_factor_t;
+
+/*
+ * spand_factor - build the spaND factorization of A (paper Sec. "Sparsified
+ * Nested Dissection algorithm", Eqs. (10)-(13)): geometric nested
+ * dissection of the element grid, then level by level: row-pivoted LU
+ * elimination of interiors with Schur updates, LU scaling of interfaces with
+ * the diagonal of U split evenly, rank-revealing QR sparsification of every
+ * interface at tolerance eps, compression of all blocks, merge.
+ * In:  A (device BSR, bs = 4(p+1)^2, n_brows = nx*ny), grid, opts.
+ * Out: *out, an opaque handle owned by the library until spand_destroy.
+ * Errors: SPAND_EINVAL for inconsistent sizes/options (before any launch),
+ * SPAND_ESINGULAR if a pivot is exactly zero, SPAND_ENOMEM, SPAND_EHIP.
+ * Synchronises the stream (per-level ranks are read back to plan the next
+ * level).
+ */
+int spand_factor(const spand_bsr_t *A, const spand_grid_t *grid,
+                 const spand_opts_t *opts, void *stream, spand_factor_t *out);
+
+/*
+ * spand_apply - d_out = M^{-1} d_in with A ~ M = prod F_i (paper Sec.
+ * "Sparsified Nested Dissection algorithm": the product of triangular and
+ * orthogonal factors used as a preconditioner).  Forward sweep over the
+ * levels applies the left factors, backward sweep the right ones.
+ * d_in and d_out: device float64[N]; d_in == d_out is allowed.
+ * Deterministic: repeated calls give bitwise-equal results.
+ */
+int spand_apply(spand_factor_t F, const double *d_in, double *d_out, void *stream);
+
+/* spand_apply_T - d_out = M^{-T} d_in, the exact transpose of spand_apply
+ * (same factors, transposed sweeps).  Same arguments and rules. */
+int spand_apply_T(spand_factor_t F, const double *d_in, double *d_out, void *stream);
+
+/*
+ * sstep_gmres_solve - right-preconditioned restarted s-step GMRES (paper
+ * Algorithm 2 with the Newton basis, Leja-ordered Ritz shifts from s steps
+ * of standard GMRES, two block CGS and two Cholesky QR passes): solves
+ * A x = b (transpose = 0) or A^T x = b (transpose = 1, with M^{-T}).
+ * M may be NULL (no preconditioner).  d_x holds x0 on entry (pass zeros
+ * for x0 = 0) and the solution on exit.  st may be NULL.
+ * Returns SPAND_OK, SPAND_ENOTCONV or SPAND_EBREAKDOWN (d_x valid in all
+ * three), or a negative error.
+ */
+int sstep_gmres_solve(const spand_bsr_t *A, spand_factor_t M, const double *d_b,
+                      double *d_x, const sstep_opts_t *opts, sstep_stats_t *st,
+                      void *stream);
+
+/*
+ * spand_bsr_spmv - d_y = alpha * op(A) d_x + beta * d_y, op = A or A^T
+ * (the SpMV of Algorithms 1 and 2).  float64.  d_x != d_y.
+ */
+int spand_bsr_spmv(const spand_bsr_t *A, int transpose, double alpha, const double *d_x,
+                   double beta, double *d_y, void *stream);
+
+/*
+ * spand_bsr_pattern_outer - for every stored block (I,J) of the pattern:
+ * d_out[t] = alpha * u_I v_J^T (row-major bs x bs).  This is the gradient
+ * of g^T A^{-1} b with respect to the stored values when u = lambda,
+ * v = x and alpha = -1 (adjoint of the linear solve; values only on the
+ * BSR pattern).  d_out: device float64[nnzb*bs*bs].
+ */
+int spand_bsr_pattern_outer(const spand_bsr_t *pattern, const double *d_u,
+                            const double *d_v, double alpha, double *d_out, void *stream);
+
+/* spand_factor_stats - rank statistics per level (paper Figs. 4-5 report
+ * ranks per level), apply bytes and algorithmic flops.  Host struct. */
+int spand_factor_stats(spand_factor_t F, spand_factor_stats_t *out);
+
+/* spand_destroy - release the factor and its device memory. NULL is ok. */
+int spand_destroy(spand_factor_t F);
+
+/*
+ * spand_nd - host-only geometric nested dissection (no GPU use), exposed so
+ * that the integer ordering can be checked exactly.  Recursive bisection
+ * of the (i, j) grid (paper Sec. "Scalability study of spaND"), levels
+ * 0..L-1 of interiors and interfaces (Sec. "Sparsified Nested Dissection
+ * algorithm").  L <= 0 selects round(log2(K/32)) + 1.
+ * Outputs (host, caller-allocated):
+ *   h_node_of_elem[K], h_perm[K];
+ *   h_ncl[L]              number of clusters per level;
+ *   h_cl_ptr[sum(ncl)+L]  per level, ncl+1 offsets into that level's
+ *                         element list (levels concatenated);
+ *   h_cl_elems[L*K]       per level, K slots (only the first ptr[ncl] used);
+ *   h_cl_key[2*sum(ncl)]  (node, box) per cluster;
+ *   h_cl_interior[sum(ncl)].
+ * Pass NULL for h_cl_* to query h_ncl only.  *L_out receives L.
+ */
+int spand_nd(const spand_grid_t *grid, int32_t L, int32_t *L_out,
+             int32_t *h_node_of_elem, int32_t *h_perm, int32_t *h_ncl,
+             int32_t *h_cl_ptr, int32_t *h_cl_elems, int32_t *h_cl_key,
+             int32_t *h_cl_interior);
+
+/* Status name ("SPAND_OK", ...). */
+const char *spand_status_string(int status);
+/* Message of the last error on the calling thread ("" if none). */
+const char *spand_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SPAND_H */

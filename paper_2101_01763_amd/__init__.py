@@ -1,0 +1,349 @@
+"""Python binding of libspand (spaND-preconditioned s-step GMRES on MI355X).
+
+Argument marshalling only: every step of the solver runs in the HIP
+kernels of libspand.so (built in-tree by ``paper_2101_01763_amd.build``).
+PyTorch supplies device memory (tensors) and the current HIP stream.
+There is no fallback: if the library is missing, importing the binding's
+functions raises.
+
+Entry points mirror include/spand.h:
+    factor(A, grid, eps, nlevels, dtype) -> Factor
+    Factor.apply(r), Factor.apply_T(r), Factor.stats()
+    solve(A, b, M=None, s=5, restart=60, rtol=1e-8, maxit=1000, transpose=False, x0=None)
+    spmv(A, x, transpose=False), pattern_outer(A, u, v, alpha)
+    nd(nx, ny, periodic_x, periodic_y, L)     (host only, no GPU)
+    SpandSolve.apply(vals, b, A_pattern, M, opts)  (autograd: adjoint solve)
+"""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libspand.so")
+
+SPAND_OK, SPAND_EINVAL, SPAND_ENOMEM, SPAND_ESINGULAR, SPAND_EHIP = 0, -1, -2, -3, -4
+SPAND_ENOTCONV, SPAND_EBREAKDOWN = 1, 2
+SPAND_F64, SPAND_F32 = 0, 1
+SSTEP_MAX_HIST = 1024
+SPAND_MAX_LEVELS = 32
+
+
+class spand_bsr_t(C.Structure):
+    _fields_ = [("n_brows", C.c_int32), ("bs", C.c_int32), ("nnzb", C.c_int64),
+                ("d_rowptr", C.c_void_p), ("d_colind", C.c_void_p), ("d_val", C.c_void_p)]
+
+
+class spand_grid_t(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("periodic_x", C.c_int32),
+                ("periodic_y", C.c_int32)]
+
+
+class spand_opts_t(C.Structure):
+    _fields_ = [("eps", C.c_double), ("nlevels", C.c_int32), ("factor_dtype", C.c_int32),
+                ("flags", C.c_int32)]
+
+
+class sstep_opts_t(C.Structure):
+    _fields_ = [("s", C.c_int32), ("restart", C.c_int32), ("maxit", C.c_int32),
+                ("transpose", C.c_int32), ("rtol", C.c_double)]
+
+
+class sstep_stats_t(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("restarts", C.c_int32), ("converged", C.c_int32),
+                ("n_hist", C.c_int32), ("relres", C.c_double),
+                ("hist", C.c_double * SSTEP_MAX_HIST), ("n_shifts", C.c_int32),
+                ("shift_re", C.c_double * 8), ("shift_im", C.c_double * 8),
+                ("t_total_ms", C.c_double), ("t_spmv_ms", C.c_double),
+                ("t_apply_ms", C.c_double), ("t_orth_ms", C.c_double),
+                ("t_other_ms", C.c_double), ("n_spmv", C.c_int32), ("n_apply", C.c_int32)]
+
+
+class spand_factor_stats_t(C.Structure):
+    L = SPAND_MAX_LEVELS
+    _fields_ = [("nlevels", C.c_int32), ("n_clusters", C.c_int32 * L),
+                ("rank_min", C.c_int32 * L), ("rank_max", C.c_int32 * L),
+                ("rank_avg", C.c_double * L), ("size_before", C.c_int64 * L),
+                ("size_after", C.c_int64 * L), ("top_size", C.c_int32),
+                ("factor_bytes", C.c_int64), ("factor_flops", C.c_double),
+                ("t_host_ms", C.c_double), ("t_device_ms", C.c_double),
+                ("t_lu_ms", C.c_double), ("t_schur_ms", C.c_double),
+                ("t_scale_ms", C.c_double), ("t_rrqr_ms", C.c_double),
+                ("t_compress_ms", C.c_double)]
+
+
+EXPORTS = ["spand_factor", "spand_apply", "spand_apply_T", "sstep_gmres_solve",
+           "spand_bsr_spmv", "spand_bsr_pattern_outer", "spand_factor_stats",
+           "spand_destroy", "spand_nd", "spand_status_string", "spand_last_error"]
+
+_lib = None
+
+
+class SpandError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{msg} (status {code})")
+        self.code = code
+
+
+def lib():
+    """Load libspand.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: run `python -m paper_2101_01763_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, dbl = C.c_void_p, C.c_int32, C.c_double
+        L.spand_factor.argtypes = [C.POINTER(spand_bsr_t), C.POINTER(spand_grid_t),
+                                   C.POINTER(spand_opts_t), vp, C.POINTER(vp)]
+        L.spand_apply.argtypes = [vp, vp, vp, vp]
+        L.spand_apply_T.argtypes = [vp, vp, vp, vp]
+        L.sstep_gmres_solve.argtypes = [C.POINTER(spand_bsr_t), vp, vp, vp,
+                                        C.POINTER(sstep_opts_t), C.POINTER(sstep_stats_t), vp]
+        L.spand_bsr_spmv.argtypes = [C.POINTER(spand_bsr_t), C.c_int, dbl, vp, dbl, vp, vp]
+        L.spand_bsr_pattern_outer.argtypes = [C.POINTER(spand_bsr_t), vp, vp, dbl, vp, vp]
+        L.spand_factor_stats.argtypes = [vp, C.POINTER(spand_factor_stats_t)]
+        L.spand_destroy.argtypes = [vp]
+        L.spand_nd.argtypes = [C.POINTER(spand_grid_t), i32, C.POINTER(i32)] + [vp] * 7
+        L.spand_status_string.restype = C.c_char_p
+        L.spand_status_string.argtypes = [C.c_int]
+        L.spand_last_error.restype = C.c_char_p
+        for f in EXPORTS:
+            if f not in ("spand_status_string", "spand_last_error"):
+                getattr(L, f).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(code, allow=(SPAND_OK,)):
+    if code in allow:
+        return code
+    L = lib()
+    raise SpandError(code, f"{L.spand_status_string(code).decode()}: "
+                           f"{L.spand_last_error().decode()}")
+
+
+def _stream():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr())
+
+
+@dataclasses.dataclass
+class BSRMatrix:
+    """Device BSR matrix (torch tensors): rowptr/colind int32, val float64 [nnzb, bs, bs]."""
+    rowptr: object
+    colind: object
+    val: object
+
+    @property
+    def n_brows(self):
+        return int(self.rowptr.numel()) - 1
+
+    @property
+    def bs(self):
+        return int(self.val.shape[-1])
+
+    @property
+    def N(self):
+        return self.n_brows * self.bs
+
+    def c(self, val=None):
+        v = self.val if val is None else val
+        return spand_bsr_t(self.n_brows, self.bs, int(self.colind.numel()), self.rowptr.data_ptr(),
+                           self.colind.data_ptr(), v.data_ptr())
+
+    @staticmethod
+    def from_numpy(rowptr, colind, val, device="cuda"):
+        import torch
+        return BSRMatrix(torch.as_tensor(np.asarray(rowptr, dtype=np.int32), device=device),
+                         torch.as_tensor(np.asarray(colind, dtype=np.int32), device=device),
+                         torch.as_tensor(np.ascontiguousarray(val, dtype=np.float64), device=device))
+
+
+class Factor:
+    """Handle of a spaND factorization (library-owned device memory)."""
+
+    def __init__(self, handle, N):
+        self._h = handle
+        self.N = N
+
+    def __del__(self):
+        try:
+            if self._h:
+                lib().spand_destroy(self._h)
+                self._h = None
+        except Exception:
+            pass
+
+    def destroy(self):
+        if self._h:
+            lib().spand_destroy(self._h)
+            self._h = None
+
+    def apply(self, r, out=None):
+        import torch
+        out = torch.empty_like(r) if out is None else out
+        _check(lib().spand_apply(self._h, _ptr(r), _ptr(out), _stream()))
+        return out
+
+    def apply_T(self, r, out=None):
+        import torch
+        out = torch.empty_like(r) if out is None else out
+        _check(lib().spand_apply_T(self._h, _ptr(r), _ptr(out), _stream()))
+        return out
+
+    def stats(self):
+        st = spand_factor_stats_t()
+        _check(lib().spand_factor_stats(self._h, C.byref(st)))
+        L = st.nlevels
+        return {
+            "nlevels": L,
+            "n_clusters": list(st.n_clusters[:L - 1]),
+            "rank_min": list(st.rank_min[:L - 1]),
+            "rank_avg": list(st.rank_avg[:L - 1]),
+            "rank_max": list(st.rank_max[:L - 1]),
+            "size_before": list(st.size_before[:L - 1]),
+            "size_after": list(st.size_after[:L - 1]),
+            "top_size": st.top_size,
+            "factor_bytes": st.factor_bytes,
+            "factor_flops": st.factor_flops,
+            "t_host_ms": st.t_host_ms, "t_device_ms": st.t_device_ms,
+            "t_lu_ms": st.t_lu_ms, "t_schur_ms": st.t_schur_ms, "t_scale_ms": st.t_scale_ms,
+            "t_rrqr_ms": st.t_rrqr_ms, "t_compress_ms": st.t_compress_ms,
+        }
+
+
+def factor(A: BSRMatrix, nx, ny, periodic_x=True, periodic_y=False, eps=1e-2, nlevels=0,
+           dtype="f64", val=None) -> Factor:
+    g = spand_grid_t(nx, ny, int(periodic_x), int(periodic_y))
+    o = spand_opts_t(float(eps), int(nlevels), SPAND_F32 if dtype == "f32" else SPAND_F64, 0)
+    h = C.c_void_p()
+    Ac = A.c(val)
+    _check(lib().spand_factor(C.byref(Ac), C.byref(g), C.byref(o), _stream(), C.byref(h)))
+    return Factor(h, A.N)
+
+
+@dataclasses.dataclass
+class SolveInfo:
+    status: int
+    iters: int
+    restarts: int
+    converged: bool
+    relres: float
+    history: list
+    shifts: list
+    t_total_ms: float
+    t_spmv_ms: float
+    t_apply_ms: float
+    t_orth_ms: float
+    t_other_ms: float
+    n_spmv: int
+    n_apply: int
+
+
+def solve(A: BSRMatrix, b, M: Factor | None = None, s=5, restart=60, rtol=1e-8, maxit=1000,
+          transpose=False, x0=None, val=None):
+    """s-step GMRES; returns (x, SolveInfo).  ENOTCONV/EBREAKDOWN do not raise."""
+    import torch
+    x = torch.zeros_like(b) if x0 is None else x0.clone()
+    o = sstep_opts_t(int(s), int(restart), int(maxit), int(bool(transpose)), float(rtol))
+    st = sstep_stats_t()
+    Ac = A.c(val)
+    code = lib().sstep_gmres_solve(C.byref(Ac), M._h if M is not None else None, _ptr(b),
+                                   _ptr(x), C.byref(o), C.byref(st), _stream())
+    _check(code, allow=(SPAND_OK, SPAND_ENOTCONV, SPAND_EBREAKDOWN))
+    info = SolveInfo(code, st.iters, st.restarts, bool(st.converged), st.relres,
+                     list(st.hist[:st.n_hist]),
+                     [complex(st.shift_re[i], st.shift_im[i]) for i in range(st.n_shifts)],
+                     st.t_total_ms, st.t_spmv_ms, st.t_apply_ms, st.t_orth_ms, st.t_other_ms,
+                     st.n_spmv, st.n_apply)
+    return x, info
+
+
+def spmv(A: BSRMatrix, x, transpose=False, alpha=1.0, beta=0.0, y=None, val=None):
+    import torch
+    y = torch.zeros_like(x) if y is None else y
+    Ac = A.c(val)
+    _check(lib().spand_bsr_spmv(C.byref(Ac), int(bool(transpose)), float(alpha), _ptr(x),
+                                float(beta), _ptr(y), _stream()))
+    return y
+
+
+def pattern_outer(A: BSRMatrix, u, v, alpha=1.0):
+    import torch
+    out = torch.empty_like(A.val)
+    Ac = A.c()
+    _check(lib().spand_bsr_pattern_outer(C.byref(Ac), _ptr(u), _ptr(v), float(alpha),
+                                         _ptr(out), _stream()))
+    return out
+
+
+def nd(nx, ny, periodic_x=True, periodic_y=False, L=0):
+    """Host-only nested dissection (no GPU use).  Returns a dict of int32 arrays
+    with the same layout as oracle.nd.flatten."""
+    K = nx * ny
+    g = spand_grid_t(nx, ny, int(periodic_x), int(periodic_y))
+    Lo = C.c_int32()
+    node = np.zeros(K, np.int32)
+    perm = np.zeros(K, np.int32)
+    ncl = np.zeros(SPAND_MAX_LEVELS, np.int32)
+    vp = lambda a: a.ctypes.data_as(C.c_void_p)
+    _check(lib().spand_nd(C.byref(g), int(L), C.byref(Lo), vp(node), vp(perm), vp(ncl),
+                          None, None, None, None))
+    L = Lo.value
+    tot = int(ncl[:L].sum())
+    ptr = np.zeros(tot + L, np.int32)
+    elems = np.zeros(L * K, np.int32)
+    key = np.zeros(2 * tot, np.int32)
+    inter = np.zeros(tot, np.int32)
+    _check(lib().spand_nd(C.byref(g), int(L), C.byref(Lo), vp(node), vp(perm), vp(ncl),
+                          vp(ptr), vp(elems), vp(key), vp(inter)))
+    out = {"L": L, "node_of_elem": node, "perm": perm}
+    pb = cb = 0
+    for l in range(L):
+        n = int(ncl[l])
+        p = ptr[pb:pb + n + 1].copy()
+        out[f"ptr_{l}"] = p
+        out[f"elems_{l}"] = elems[l * K:l * K + p[-1]].copy()
+        out[f"key_{l}"] = key[2 * cb:2 * (cb + n)].reshape(-1, 2).copy()
+        out[f"interior_{l}"] = inter[cb:cb + n].copy()
+        pb += n + 1
+        cb += n
+    return out
+
+
+class SpandSolve:
+    """Differentiable x = A^{-1} b (A given by its BSR values on a fixed
+    pattern), solved with spaND-preconditioned s-step GMRES.  Backward solves
+    A^T lambda = g with the transposed operator and M^{-T} (spand_apply_T) and
+    returns dL/db = lambda, dL/dvals = -lambda_I x_J^T on the stored blocks."""
+
+    @staticmethod
+    def apply(vals, b, A: BSRMatrix, M: Factor, opts: dict):
+        import torch
+
+        class _Fn(torch.autograd.Function):
+            @staticmethod
+            def forward(ctx, vals_, b_):
+                x, info = solve(A, b_, M, val=vals_, **opts)
+                if not info.converged:
+                    raise SpandError(info.status, f"forward solve did not converge: {info}")
+                ctx.save_for_backward(vals_, x)
+                return x
+
+            @staticmethod
+            def backward(ctx, g):
+                vals_, x = ctx.saved_tensors
+                lam, info = solve(A, g.contiguous(), M, transpose=True, val=vals_, **opts)
+                if not info.converged:
+                    raise SpandError(info.status, f"adjoint solve did not converge: {info}")
+                gv = pattern_outer(BSRMatrix(A.rowptr, A.colind, vals_), lam, x, alpha=-1.0)
+                return gv, lam
+
+        return _Fn.apply(vals, b)

@@ -1,0 +1,285 @@
+// C ABI of libspand (declared in include/spand.h): argument validation,
+// handle lifetime, error reporting.  All numerical work is in the kernels.
+#include <cmath>
+#include <cstdarg>
+#include <cstring>
+#include <memory>
+#include <stdexcept>
+
+#include "factor.h"
+
+struct spand_factor_s {
+  spand::Factor F;
+};
+
+namespace spand {
+
+static thread_local char g_err[1024] = "";
+
+void set_error(const char *fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+}
+
+const char *last_error() { return g_err; }
+
+int sstep_solve(const spand_bsr_t &A, Factor *M, const double *b, double *x,
+                const sstep_opts_t &o, sstep_stats_t *st, hipStream_t stream);
+
+static int check_bsr(const spand_bsr_t *A) {
+  if (!A) {
+    set_error("A is NULL");
+    return SPAND_EINVAL;
+  }
+  if (A->n_brows <= 0 || A->bs <= 0 || A->nnzb < A->n_brows) {
+    set_error("bad BSR sizes (n_brows=%d bs=%d nnzb=%lld)", A->n_brows, A->bs,
+              (long long)A->nnzb);
+    return SPAND_EINVAL;
+  }
+  if (A->bs > 64) {
+    set_error("block size %d exceeds 64", A->bs);
+    return SPAND_EINVAL;
+  }
+  if (A->bs % 2 != 0) {
+    set_error("block size %d must be even (4 (p+1)^2)", A->bs);
+    return SPAND_EINVAL;
+  }
+  if (!A->d_rowptr || !A->d_colind || !A->d_val) {
+    set_error("BSR device pointers must not be NULL");
+    return SPAND_EINVAL;
+  }
+  return SPAND_OK;
+}
+
+}  // namespace spand
+
+using namespace spand;
+
+extern "C" {
+
+const char *spand_status_string(int s) {
+  switch (s) {
+    case SPAND_OK: return "SPAND_OK";
+    case SPAND_EINVAL: return "SPAND_EINVAL";
+    case SPAND_ENOMEM: return "SPAND_ENOMEM";
+    case SPAND_ESINGULAR: return "SPAND_ESINGULAR";
+    case SPAND_EHIP: return "SPAND_EHIP";
+    case SPAND_ENOTCONV: return "SPAND_ENOTCONV";
+    case SPAND_EBREAKDOWN: return "SPAND_EBREAKDOWN";
+    default: return "SPAND_UNKNOWN";
+  }
+}
+
+const char *spand_last_error(void) { return last_error(); }
+
+int spand_factor(const spand_bsr_t *A, const spand_grid_t *grid, const spand_opts_t *opts,
+                 void *stream, spand_factor_t *out) {
+  set_error("");
+  if (!out) {
+    set_error("out is NULL");
+    return SPAND_EINVAL;
+  }
+  *out = nullptr;
+  SP_TRY(check_bsr(A));
+  if (!grid || !opts) {
+    set_error("grid/opts is NULL");
+    return SPAND_EINVAL;
+  }
+  if (grid->nx <= 0 || grid->ny <= 0 || int64_t(grid->nx) * grid->ny != A->n_brows) {
+    set_error("grid %dx%d does not match n_brows=%d", grid->nx, grid->ny, A->n_brows);
+    return SPAND_EINVAL;
+  }
+  if (!(opts->eps >= 0.0) || !std::isfinite(opts->eps)) {
+    set_error("eps must be a finite number >= 0");
+    return SPAND_EINVAL;
+  }
+  if (opts->nlevels < 0 || opts->nlevels > SPAND_MAX_LEVELS) {
+    set_error("nlevels must be in [0, %d]", SPAND_MAX_LEVELS);
+    return SPAND_EINVAL;
+  }
+  if (opts->factor_dtype != SPAND_F64 && opts->factor_dtype != SPAND_F32) {
+    set_error("factor_dtype must be SPAND_F64 or SPAND_F32");
+    return SPAND_EINVAL;
+  }
+  int L = opts->nlevels > 0 ? opts->nlevels : default_levels(A->n_brows);
+  // every box at depth L-1 must be able to exist: need 2^(L-1) <= K
+  if (L > 1 && (int64_t(1) << (L - 1)) > int64_t(A->n_brows)) {
+    set_error("nlevels=%d too large for %d elements", L, A->n_brows);
+    return SPAND_EINVAL;
+  }
+  auto h = std::make_unique<spand_factor_s>();
+  h->F.stream = (hipStream_t)stream;
+  h->F.timing = true;
+  (void)hipGetDevice(&h->F.device);
+  int r;
+  try {
+    r = h->F.build(*A, *grid, *opts);
+  } catch (const std::exception &ex) {
+    set_error("factorization failed: %s", ex.what());
+    r = SPAND_EINVAL;
+  }
+  if (r != SPAND_OK) return r;
+  *out = h.release();
+  return SPAND_OK;
+}
+
+int spand_apply(spand_factor_t F, const double *d_in, double *d_out, void *stream) {
+  if (!F || !d_in || !d_out) {
+    set_error("NULL argument");
+    return SPAND_EINVAL;
+  }
+  return F->F.apply(d_in, d_out, 0, (hipStream_t)stream);
+}
+
+int spand_apply_T(spand_factor_t F, const double *d_in, double *d_out, void *stream) {
+  if (!F || !d_in || !d_out) {
+    set_error("NULL argument");
+    return SPAND_EINVAL;
+  }
+  return F->F.apply(d_in, d_out, 1, (hipStream_t)stream);
+}
+
+int sstep_gmres_solve(const spand_bsr_t *A, spand_factor_t M, const double *d_b, double *d_x,
+                      const sstep_opts_t *opts, sstep_stats_t *st, void *stream) {
+  set_error("");
+  SP_TRY(check_bsr(A));
+  if (!d_b || !d_x || !opts) {
+    set_error("NULL argument");
+    return SPAND_EINVAL;
+  }
+  if (opts->s < 1 || opts->s > TS_MAXS) {
+    set_error("s must be in [1, %d]", TS_MAXS);
+    return SPAND_EINVAL;
+  }
+  if (opts->restart < opts->s || opts->restart % opts->s != 0 || opts->restart > KRY_MMAX ||
+      opts->restart + 1 + opts->s > TS_MAXA) {
+    set_error("restart must be a multiple of s in [s, %d]", KRY_MMAX);
+    return SPAND_EINVAL;
+  }
+  if (opts->maxit < 1 || !(opts->rtol > 0.0) || !std::isfinite(opts->rtol)) {
+    set_error("maxit must be >= 1 and rtol > 0");
+    return SPAND_EINVAL;
+  }
+  if (M && (int64_t(M->F.N) != int64_t(A->n_brows) * A->bs)) {
+    set_error("factor size does not match A");
+    return SPAND_EINVAL;
+  }
+  if (st) std::memset(st, 0, sizeof(*st));
+  try {
+    return sstep_solve(*A, M ? &M->F : nullptr, d_b, d_x, *opts, st, (hipStream_t)stream);
+  } catch (const std::exception &ex) {
+    set_error("solve failed: %s", ex.what());
+    return SPAND_EINVAL;
+  }
+}
+
+int spand_bsr_spmv(const spand_bsr_t *A, int transpose, double alpha, const double *d_x,
+                   double beta, double *d_y, void *stream) {
+  set_error("");
+  SP_TRY(check_bsr(A));
+  if (!d_x || !d_y || d_x == d_y) {
+    set_error("x and y must be distinct non-NULL device vectors");
+    return SPAND_EINVAL;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  if (!transpose) return launch_spmv(*A, 0, alpha, d_x, beta, d_y, nullptr, 0.0, nullptr, 0.0, st);
+  void *tv = nullptr, *fl = nullptr;
+  if (hipMalloc(&tv, size_t(A->nnzb) * A->bs * A->bs * 8) != hipSuccess) {
+    set_error("hipMalloc failed");
+    return SPAND_ENOMEM;
+  }
+  if (hipMalloc(&fl, 64) != hipSuccess) {
+    (void)hipFree(tv);
+    set_error("hipMalloc failed");
+    return SPAND_ENOMEM;
+  }
+  int r = SPAND_OK, flag = 0;
+  if (hipMemsetAsync(fl, 0, 64, st) != hipSuccess) r = SPAND_EHIP;
+  if (r == SPAND_OK) r = launch_bsr_transpose(*A, (double *)tv, (int *)fl, st);
+  spand_bsr_t At = *A;
+  At.d_val = (const double *)tv;
+  if (r == SPAND_OK) r = launch_spmv(At, 0, alpha, d_x, beta, d_y, nullptr, 0.0, nullptr, 0.0, st);
+  if (r == SPAND_OK && (hipMemcpyAsync(&flag, fl, 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
+                        hipStreamSynchronize(st) != hipSuccess))
+    r = SPAND_EHIP;
+  (void)hipFree(tv);
+  (void)hipFree(fl);
+  if (r == SPAND_OK && flag) {
+    set_error("transposed SpMV needs a structurally symmetric block pattern");
+    r = SPAND_EINVAL;
+  }
+  return r;
+}
+
+int spand_bsr_pattern_outer(const spand_bsr_t *P, const double *d_u, const double *d_v,
+                            double alpha, double *d_out, void *stream) {
+  set_error("");
+  SP_TRY(check_bsr(P));
+  if (!d_u || !d_v || !d_out) {
+    set_error("NULL argument");
+    return SPAND_EINVAL;
+  }
+  return launch_pattern_outer(*P, d_u, d_v, alpha, d_out, (hipStream_t)stream);
+}
+
+int spand_factor_stats(spand_factor_t F, spand_factor_stats_t *out) {
+  if (!F || !out) {
+    set_error("NULL argument");
+    return SPAND_EINVAL;
+  }
+  F->F.fill_stats(out);
+  return SPAND_OK;
+}
+
+int spand_destroy(spand_factor_t F) {
+  if (F) {
+    (void)hipDeviceSynchronize();
+    delete F;
+  }
+  return SPAND_OK;
+}
+
+int spand_nd(const spand_grid_t *grid, int32_t L, int32_t *L_out, int32_t *h_node_of_elem,
+             int32_t *h_perm, int32_t *h_ncl, int32_t *h_cl_ptr, int32_t *h_cl_elems,
+             int32_t *h_cl_key, int32_t *h_cl_interior) {
+  set_error("");
+  if (!grid || grid->nx <= 0 || grid->ny <= 0) {
+    set_error("bad grid");
+    return SPAND_EINVAL;
+  }
+  const int64_t K = int64_t(grid->nx) * grid->ny;
+  if (L <= 0) L = default_levels(K);
+  if (L > SPAND_MAX_LEVELS || (L > 1 && (int64_t(1) << (L - 1)) > K)) {
+    set_error("bad number of levels %d", L);
+    return SPAND_EINVAL;
+  }
+  if (L_out) *L_out = L;
+  NDResult nd = nested_dissection(grid->nx, grid->ny, grid->periodic_x != 0,
+                                  grid->periodic_y != 0, L);
+  if (h_node_of_elem) std::memcpy(h_node_of_elem, nd.node_of_elem.data(), K * 4);
+  if (h_perm) std::memcpy(h_perm, nd.perm.data(), K * 4);
+  if (h_ncl)
+    for (int l = 0; l < L; ++l) h_ncl[l] = int32_t(nd.levels[l].size());
+  if (h_cl_ptr && h_cl_elems && h_cl_key && h_cl_interior) {
+    int64_t pbase = 0, cbase = 0;
+    for (int l = 0; l < L; ++l) {
+      const auto &cl = nd.levels[l];
+      int32_t off = 0;
+      for (size_t c = 0; c < cl.size(); ++c) {
+        h_cl_ptr[pbase + c] = off;
+        for (int32_t e : cl[c].elems) h_cl_elems[int64_t(l) * K + off++] = e;
+        h_cl_key[2 * (cbase + c)] = cl[c].node;
+        h_cl_key[2 * (cbase + c) + 1] = cl[c].box;
+        h_cl_interior[cbase + c] = cl[c].interior ? 1 : 0;
+      }
+      h_cl_ptr[pbase + cl.size()] = off;
+      pbase += int64_t(cl.size()) + 1;
+      cbase += int64_t(cl.size());
+    }
+  }
+  return SPAND_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,121 @@
+// spaND factor object (host side) and its per-level apply plan.
+#pragma once
+#include <map>
+#include <vector>
+
+#include "internal.h"
+#include "kernels_vec.h"
+
+namespace spand {
+
+struct Blk {
+  void *p = nullptr;   // row-major rows x cols, ld = cols
+  int rows = 0, cols = 0;
+};
+
+// trailing matrix of one level: clusters (with their slots in the global
+// vector) and dense cluster-pair blocks
+struct LevelState {
+  std::vector<int> size;
+  std::vector<char> interior;
+  std::vector<std::vector<int32_t>> slots;
+  std::vector<int32_t *> d_slots;
+  std::map<std::pair<int, int>, Blk> blocks;
+};
+
+struct Factor;
+struct PullSet {
+  PullGroup *d_groups = nullptr;
+  PullItem *d_items = nullptr;
+  int n = 0;
+  int set(Factor &F, const std::vector<PullGroup> &G, const std::vector<PullItem> &I);
+};
+
+// apply plan of one level (see Factor::apply)
+struct ApplyLevel {
+  GemvDesc *d_inv = nullptr, *d_invT = nullptr;   // interiors: A_ss^-1
+  int n_inv = 0;
+  GemvDesc *d_F = nullptr, *d_B = nullptr, *d_FT = nullptr, *d_BT = nullptr;   // interfaces
+  int n_if = 0;
+  PullSet fw;    // x_n -= A_ns t_s          (groups: neighbours)
+  PullSet bw;    // x_s -= A_sn x_n          (groups: interiors)
+  PullSet tfw;   // x_n -= A_sn^T x_s        (groups: neighbours)
+  PullSet tbw;   // t_s  = A_ns^T x_n        (groups: all interiors)
+};
+
+struct RankStat {
+  int n = 0, kmin = 1 << 30, kmax = 0;
+  int64_t ksum = 0, msum = 0;
+  void add(int m, int k) {
+    ++n;
+    kmin = std::min(kmin, k);
+    kmax = std::max(kmax, k);
+    ksum += k;
+    msum += m;
+  }
+};
+
+enum { PH_GATHER = 0, PH_LU, PH_SCHUR, PH_SCALE, PH_RRQR, PH_COMPRESS, PH_END, PH_COUNT };
+
+// chunked bump allocator over hipMalloc
+struct Bump {
+  std::vector<std::pair<char *, size_t>> chunks;
+  size_t used = 0;
+  size_t bytes = 0;
+  int alloc(void **p, size_t n, size_t chunk);
+  void release();
+};
+
+struct Factor {
+  hipStream_t stream = nullptr;
+  int device = 0;
+  FType ft = FType::F64;
+  int bs = 0, K = 0, L = 0;
+  int64_t N = 0;
+  double eps = 0.0;
+  std::vector<int32_t> h_rowptr, h_colind;
+  std::vector<ApplyLevel> lv;
+  Bump keep, temp, next_temp;   // next_temp: next level's trailing blocks
+  std::vector<void *> keep_allocs, temp_allocs;
+  size_t keep_bytes = 0;
+  int32_t *d_iota = nullptr;
+  double *d_tbuf = nullptr;
+  int *d_flag = nullptr;
+  // statistics
+  std::vector<RankStat> ranks;
+  int top_size = 0;
+  double apply_bytes = 0.0, flops = 0.0, t_host_ms = 0.0;
+  double ph_ms[PH_COUNT] = {0};
+  bool timing = false;
+  std::vector<std::pair<int, hipEvent_t>> events;
+
+  ~Factor();
+  int dalloc(void **p, size_t bytes, bool keep);
+  int dalloc_next(void **p, size_t bytes);
+  void free_temp();
+  template <typename D>
+  int upload(const std::vector<D> &v, D **out, bool keep);
+  int upload_slots(const std::vector<int32_t> &v, int32_t **out);
+  int gemm_batch(const std::vector<GemmDesc> &items);
+  int copy_batch(const std::vector<CopyDesc> &items, int src_is_factor);
+  int elim_batch(std::vector<ElimDesc> &items, int mode);
+  void mark(int phase);
+  void collect_events();
+  int level0(const spand_bsr_t &A, const NDResult &nd, LevelState &S);
+  int eliminate_dense(int l, LevelState &S);
+  int sparsify(int l, const NDResult &nd, LevelState &S, LevelState &Nx);
+  int build(const spand_bsr_t &A, const spand_grid_t &g, const spand_opts_t &o);
+  int finish_transposed();
+  int apply(const double *in, double *out, int transpose, hipStream_t st);
+  void fill_stats(spand_factor_stats_t *st) const;
+};
+
+struct DiagDesc {
+  const void *U;
+  void *S;
+  void *Si;
+  int32_t n, ld;
+};
+int launch_diag_split(FType t, const DiagDesc *d_items, int n, hipStream_t st);
+
+}  // namespace spand

@@ -1,0 +1,1298 @@
+// spaND factorization and its application (host orchestration).
+//
+// Level-synchronous GPU version of the paper's Sec. "Sparsified Nested
+// Dissection algorithm": per level, every independent cluster of a phase is
+// one item of a batched launch (the GPU counterpart of the per-level task
+// graph of Sec. "Parallel implementation using TaskTorrent").
+//
+//  level 0   leaves: dense A_ss gathered from the BSR input, inverted by
+//            blocked Gauss-Jordan with partial pivoting (same pivots as
+//            LU with partial pivoting); Schur update A_nm -= A_ns A_ss^-1 A_sm
+//            on b x b element blocks (Eq. 10), pulled per target block;
+//  every l   interfaces: LU with partial pivoting of A_ss on [A_ss | I] ->
+//            U and L^-1 P^T; U^-1 by Gauss-Jordan; diagonal of U split
+//            evenly (Eq. 11); all blocks scaled; W = [A_sn A_ns^T] and its
+//            column-pivoted QR (Eq. 12); all blocks compressed with the kept
+//            columns (Eq. 13) straight into the merged next-level blocks;
+//  l >= 1    interiors: dense merged blocks, same inversion, Schur update by
+//            batched GEMMs in deterministic rounds;
+//  top       inversion of the root separator.
+//
+// Stored for the apply (factor precision T):
+//   interiors  A_ss^-1 and the coupling blocks A_ns, A_sn
+//   interfaces F_s = Q_s^T Lh^-1 P^T and B_s = Uh^-1 Q_s
+// with the elimination written as L' = [[I,0],[-A_ns A_ss^-1, I]],
+// R' = [[A_ss^-1, -A_ss^-1 A_sn],[0, I]]  (L' A R' = diag(I, Schur)).
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <set>
+
+#include "factor.h"
+
+namespace spand {
+
+// ------------------------------------------------------------------ arenas
+struct PlanArena {
+  std::vector<size_t> offs;
+  size_t total = 0;
+  char *base = nullptr;
+  size_t add(size_t bytes) {
+    size_t o = (total + 255) & ~size_t(255);
+    total = o + std::max<size_t>(bytes, 1);
+    return o;
+  }
+};
+
+int Bump::alloc(void **p, size_t n, size_t chunk) {
+  n = (std::max<size_t>(n, 1) + 255) & ~size_t(255);
+  if (chunks.empty() || used + n > chunks.back().second) {
+    const size_t sz = std::max(n, chunk);
+    void *q;
+    hipError_t e = hipMalloc(&q, sz);
+    if (e != hipSuccess) {
+      set_error("hipMalloc(%zu bytes) failed: %s", sz, hipGetErrorString(e));
+      return SPAND_ENOMEM;
+    }
+    chunks.push_back({(char *)q, sz});
+    bytes += sz;
+    used = 0;
+  }
+  *p = chunks.back().first + used;
+  used += n;
+  return SPAND_OK;
+}
+
+void Bump::release() {
+  for (auto &c : chunks) (void)hipFree(c.first);
+  chunks.clear();
+  used = 0;
+  bytes = 0;
+}
+
+int Factor::dalloc(void **p, size_t bytes, bool keep) {
+  const size_t chunk = size_t(256) << 20;
+  return keep ? this->keep.alloc(p, bytes, chunk) : temp.alloc(p, bytes, chunk);
+}
+
+int Factor::dalloc_next(void **p, size_t bytes) {
+  return next_temp.alloc(p, bytes, size_t(256) << 20);
+}
+
+// end of a level: this level's scratch goes, the next level's trailing
+// blocks become the current scratch
+void Factor::free_temp() {
+  temp.release();
+  std::swap(temp, next_temp);
+}
+
+Factor::~Factor() {
+  temp.release();
+  next_temp.release();
+  keep.release();
+}
+
+template <typename D>
+int Factor::upload(const std::vector<D> &v, D **out, bool keep) {
+  *out = nullptr;
+  if (v.empty()) return SPAND_OK;
+  void *p;
+  SP_TRY(dalloc(&p, v.size() * sizeof(D), keep));
+  SP_HIP(hipMemcpy(p, v.data(), v.size() * sizeof(D), hipMemcpyHostToDevice));
+  *out = (D *)p;
+  return SPAND_OK;
+}
+
+int Factor::upload_slots(const std::vector<int32_t> &v, int32_t **out) {
+  return upload(v, out, true);
+}
+
+// ------------------------------------------------------------------ batched helpers
+int Factor::gemm_batch(const std::vector<GemmDesc> &items) {
+  if (items.empty()) return SPAND_OK;
+  std::vector<int32_t> ts(items.size() + 1, 0);
+  for (size_t i = 0; i < items.size(); ++i) {
+    const auto &d = items[i];
+    ts[i + 1] = ts[i] + int32_t(cdiv(d.M, 64) * cdiv(d.N, 64));
+  }
+  GemmDesc *d_items;
+  int32_t *d_ts;
+  SP_TRY(upload(items, &d_items, false));
+  SP_TRY(upload(ts, &d_ts, false));
+  return launch_gemm(ft, d_items, d_ts, int(items.size()), ts.back(), stream);
+}
+
+int Factor::copy_batch(const std::vector<CopyDesc> &items, int src_is_factor) {
+  if (items.empty()) return SPAND_OK;
+  int64_t mx = 0;
+  for (auto &d : items) mx = std::max<int64_t>(mx, int64_t(d.rows) * d.cols);
+  CopyDesc *d_items;
+  SP_TRY(upload(items, &d_items, false));
+  // grid.x is limited to 2^31-1; chunk very long batches
+  return launch_copy(ft, src_is_factor, d_items, int(items.size()), mx, stream);
+}
+
+// Blocked elimination of a batch; items get their n/ncols/ld filled in.
+int Factor::elim_batch(std::vector<ElimDesc> &items, int mode) {
+  if (items.empty()) return SPAND_OK;
+  std::sort(items.begin(), items.end(), [](const ElimDesc &a, const ElimDesc &b) {
+    return a.n > b.n;
+  });
+  size_t nP = 0, nT = 0, nI = 0;
+  for (auto &d : items) {
+    nP += size_t(d.n) * ELIM_NB;
+    nT += size_t(ELIM_NB) * d.ld;
+    nI += size_t(d.n);
+  }
+  void *P, *T, *piv, *used;
+  SP_TRY(dalloc(&P, nP * fsize(ft), false));
+  SP_TRY(dalloc(&T, nT * fsize(ft), false));
+  SP_TRY(dalloc(&piv, nI * 4, false));
+  SP_TRY(dalloc(&used, nI * 4, false));
+  SP_HIP(hipMemsetAsync(used, 0, nI * 4, stream));
+  size_t oP = 0, oT = 0, oI = 0;
+  for (auto &d : items) {
+    d.P = (char *)P + oP * fsize(ft);
+    d.T = (char *)T + oT * fsize(ft);
+    d.piv = (int32_t *)piv + oI;
+    d.used = (int32_t *)used + oI;
+    oP += size_t(d.n) * ELIM_NB;
+    oT += size_t(ELIM_NB) * d.ld;
+    oI += size_t(d.n);
+  }
+  ElimDesc *d_items;
+  SP_TRY(upload(items, &d_items, false));
+  const int nmax = items[0].n;
+  for (int k = 0; k < nmax; k += ELIM_NB) {
+    int nactive = 0;
+    while (nactive < int(items.size()) && items[nactive].n > k) ++nactive;
+    const int c0 = mode == 1 ? k : 0;
+    const int max_tiles = int(cdiv(nmax, 64) * cdiv(items[0].ncols - c0, 64));
+    SP_TRY(launch_elim_step(ft, d_items, nactive, k, mode, max_tiles, d_flag, stream));
+  }
+  return SPAND_OK;
+}
+
+// ------------------------------------------------------------------ timing
+void Factor::mark(int phase) {
+  if (!timing) return;
+  hipEvent_t e;
+  if (hipEventCreate(&e) != hipSuccess) return;
+  (void)hipEventRecord(e, stream);
+  events.push_back({phase, e});
+}
+
+// ------------------------------------------------------------------ level 0
+int Factor::level0(const spand_bsr_t &A, const NDResult &nd, LevelState &S) {
+  const int b = bs;
+  const auto &cl = nd.levels[0];
+  const int ncl = int(cl.size());
+  std::vector<int> ecl(K), epos(K);
+  for (int c = 0; c < ncl; ++c)
+    for (size_t q = 0; q < cl[c].elems.size(); ++q) {
+      ecl[cl[c].elems[q]] = c;
+      epos[cl[c].elems[q]] = int(q);
+    }
+  S.size.assign(ncl, 0);
+  S.interior.assign(ncl, 0);
+  S.slots.assign(ncl, {});
+  for (int c = 0; c < ncl; ++c) {
+    S.interior[c] = cl[c].interior;
+    S.size[c] = int(cl[c].elems.size()) * b;
+    auto &sl = S.slots[c];
+    sl.reserve(S.size[c]);
+    for (int e : cl[c].elems)
+      for (int q = 0; q < b; ++q) sl.push_back(e * b + q);
+  }
+  for (int c = 0; c < ncl; ++c) {
+    int32_t *sl;
+    SP_TRY(upload_slots(S.slots[c], &sl));
+    S.d_slots.push_back(sl);
+  }
+  const size_t tsz = fsize(ft);
+  const int64_t b2 = int64_t(b) * b;
+  // ---- interface-pair blocks: adjacency among separator elements + fill
+  std::set<std::pair<int, int>> pairs;
+  std::vector<std::vector<int>> leaf_nbr(ncl);
+  for (int e = 0; e < K; ++e) {
+    for (int t = h_rowptr[e]; t < h_rowptr[e + 1]; ++t) {
+      const int f = h_colind[t];
+      const int ce = ecl[e], cf = ecl[f];
+      if (!S.interior[ce] && !S.interior[cf]) pairs.insert({ce, cf});
+      if (S.interior[ce] && !S.interior[cf]) leaf_nbr[ce].push_back(cf);
+      if (S.interior[ce] && S.interior[cf] && ce != cf) {
+        set_error("block (%d,%d) couples two different leaves: the matrix pattern does not "
+                  "match the element grid", e, f);
+        return SPAND_EINVAL;
+      }
+    }
+  }
+  for (int s = 0; s < ncl; ++s) {
+    auto &v = leaf_nbr[s];
+    std::sort(v.begin(), v.end());
+    v.erase(std::unique(v.begin(), v.end()), v.end());
+    for (int n : v)
+      for (int m : v) pairs.insert({n, m});
+  }
+  for (int c = 0; c < ncl; ++c)
+    if (!S.interior[c]) pairs.insert({c, c});
+  {
+    PlanArena pa;
+    std::vector<std::pair<std::pair<int, int>, size_t>> offs;
+    for (auto &pr : pairs)
+      offs.push_back({pr, pa.add(size_t(S.size[pr.first]) * S.size[pr.second] * tsz)});
+    void *base;
+    SP_TRY(dalloc(&base, pa.total, false));
+    SP_HIP(hipMemsetAsync(base, 0, pa.total, stream));
+    for (auto &o : offs)
+      S.blocks[o.first] = Blk{(char *)base + o.second, S.size[o.first.first], S.size[o.first.second]};
+  }
+  // ---- leaves: gather A_ss, invert
+  std::vector<int> leaves;
+  for (int c = 0; c < ncl; ++c)
+    if (S.interior[c]) leaves.push_back(c);
+  std::vector<void *> Ass(ncl, nullptr), Ainv(ncl, nullptr);
+  {
+    PlanArena pt, pk;
+    std::vector<size_t> ot(ncl), ok(ncl);
+    for (int s : leaves) {
+      const int n = S.size[s];
+      if (n > ELIM_MAXN || n > GEMV_MAXC) {
+        set_error("leaf cluster of %d unknowns exceeds the kernel limit %d; use more levels", n,
+                  ELIM_MAXN);
+        return SPAND_EINVAL;
+      }
+      ot[s] = pt.add(size_t(n) * n * tsz);
+      ok[s] = pk.add(size_t(n) * n * tsz);
+    }
+    if (!leaves.empty()) {
+      void *bt, *bk;
+      SP_TRY(dalloc(&bt, pt.total, false));
+      SP_TRY(dalloc(&bk, pk.total, true));
+      SP_HIP(hipMemsetAsync(bt, 0, pt.total, stream));
+      for (int s : leaves) {
+        Ass[s] = (char *)bt + ot[s];
+        Ainv[s] = (char *)bk + ok[s];
+      }
+    }
+  }
+  std::vector<CopyDesc> cps;
+  for (int e = 0; e < K; ++e) {
+    for (int t = h_rowptr[e]; t < h_rowptr[e + 1]; ++t) {
+      const int f = h_colind[t];
+      const int ce = ecl[e], cf = ecl[f];
+      CopyDesc d{};
+      d.src = A.d_val + t * b2;
+      d.rows = d.cols = b;
+      d.lds = b;
+      d.scale = 1.0;
+      if (ce == cf && S.interior[ce]) {
+        const int n = S.size[ce];
+        d.dst = (char *)Ass[ce] + (size_t(epos[e]) * b * n + size_t(epos[f]) * b) * tsz;
+        d.ldd = n;
+        cps.push_back(d);
+      } else if (!S.interior[ce] && !S.interior[cf]) {
+        const Blk &B = S.blocks.at({ce, cf});
+        d.dst = (char *)B.p + (size_t(epos[e]) * b * B.cols + size_t(epos[f]) * b) * tsz;
+        d.ldd = B.cols;
+        cps.push_back(d);
+      }
+    }
+  }
+  mark(PH_GATHER);
+  SP_TRY(copy_batch(cps, 0));
+  mark(PH_LU);
+  {
+    std::vector<ElimDesc> items;
+    for (int s : leaves) {
+      ElimDesc d{};
+      d.A = Ass[s];
+      d.n = S.size[s];
+      d.ncols = d.n;
+      d.ld = d.n;
+      items.push_back(d);
+    }
+    SP_TRY(elim_batch(items, 0));
+    std::vector<RowGatherDesc> rg;
+    for (auto &d : items) {
+      // find the leaf whose A_ss this is
+      RowGatherDesc g{};
+      g.src = d.A;
+      g.piv = d.piv;
+      g.n = d.n;
+      g.cols = d.n;
+      g.lds = d.ld;
+      g.ldd = d.n;
+      g.colperm = 1;
+      for (int s : leaves)
+        if (Ass[s] == d.A) g.dst = Ainv[s];
+      rg.push_back(g);
+    }
+    RowGatherDesc *d_rg;
+    SP_TRY(upload(rg, &d_rg, false));
+    int mr = 0;
+    for (auto &g : rg) mr = std::max(mr, g.n);
+    SP_TRY(launch_row_gather(ft, d_rg, int(rg.size()), mr, stream));
+  }
+  mark(PH_SCHUR);
+  // ---- couplings (separator element e, leaf element f) per leaf
+  struct Coup {
+    int e, f;
+    int64_t t_ef, t_fe;
+  };
+  std::vector<std::vector<Coup>> coup(ncl);
+  for (int f = 0; f < K; ++f) {
+    const int cf = ecl[f];
+    if (!S.interior[cf]) continue;
+    for (int t = h_rowptr[f]; t < h_rowptr[f + 1]; ++t) {
+      const int e = h_colind[t];
+      if (S.interior[ecl[e]]) continue;
+      // mirror block (e, f)
+      int64_t tm = -1;
+      for (int q = h_rowptr[e]; q < h_rowptr[e + 1]; ++q)
+        if (h_colind[q] == f) tm = q;
+      if (tm < 0) {
+        set_error("block pattern is not structurally symmetric at (%d,%d)", e, f);
+        return SPAND_EINVAL;
+      }
+      coup[cf].push_back({e, f, tm, t});
+    }
+  }
+  {
+    // Schur targets keyed by (e_a, e_c), items ordered by (leaf, a, c)
+    std::map<std::pair<int, int>, std::vector<SchurItem>> tg;
+    for (int s : leaves) {
+      const auto &C = coup[s];
+      const int n = S.size[s];
+      for (const auto &ca : C)
+        for (const auto &cc : C) {
+          SchurItem it{};
+          it.a1 = ca.t_ef;      // A[e_a, f_a]
+          it.a2 = cc.t_fe;      // A[f_c, e_c]
+          it.Y = (char *)Ainv[s] + (size_t(epos[ca.f]) * b * n + size_t(epos[cc.f]) * b) * tsz;
+          it.ldy = n;
+          tg[{ca.e, cc.e}].push_back(it);
+        }
+    }
+    std::vector<SchurGroup> groups;
+    std::vector<SchurItem> items;
+    for (auto &kv : tg) {
+      const int ea = kv.first.first, ec = kv.first.second;
+      const Blk &B = S.blocks.at({ecl[ea], ecl[ec]});
+      SchurGroup g{};
+      g.target = (char *)B.p + (size_t(epos[ea]) * b * B.cols + size_t(epos[ec]) * b) * tsz;
+      g.ldt = B.cols;
+      g.item_begin = int(items.size());
+      items.insert(items.end(), kv.second.begin(), kv.second.end());
+      g.item_end = int(items.size());
+      groups.push_back(g);
+    }
+    SchurGroup *d_g;
+    SchurItem *d_i;
+    SP_TRY(upload(groups, &d_g, false));
+    SP_TRY(upload(items, &d_i, false));
+    SP_TRY(launch_schur_elem(ft, b, A.d_val, d_g, int(groups.size()), d_i, stream));
+    flops += double(items.size()) * 4.0 * b * b * b;
+  }
+  // ---- stored couplings and apply descriptors of level 0
+  ApplyLevel &AL = lv[0];
+  {
+    size_t ncp = 0;
+    for (int s : leaves) ncp += coup[s].size();
+    void *cb = nullptr;
+    if (ncp) SP_TRY(dalloc(&cb, ncp * 2 * b2 * tsz, true));
+    std::vector<CopyDesc> cc;
+    // element -> list of (partner element, block ptr)
+    std::map<int, std::vector<std::pair<int, void *>>> fw_ns, fw_sn;  // keyed by sep elem e
+    std::map<int, std::vector<std::pair<int, void *>>> bw_sn, bw_ns;  // keyed by leaf elem f
+    size_t q = 0;
+    for (int s : leaves)
+      for (const auto &c : coup[s]) {
+        void *pns = (char *)cb + (2 * q) * b2 * tsz;
+        void *psn = (char *)cb + (2 * q + 1) * b2 * tsz;
+        ++q;
+        CopyDesc d{};
+        d.rows = d.cols = b;
+        d.lds = d.ldd = b;
+        d.scale = 1.0;
+        d.src = A.d_val + c.t_ef * b2;
+        d.dst = pns;
+        cc.push_back(d);
+        d.src = A.d_val + c.t_fe * b2;
+        d.dst = psn;
+        cc.push_back(d);
+        fw_ns[c.e].push_back({c.f, pns});
+        fw_sn[c.e].push_back({c.f, psn});
+        bw_sn[c.f].push_back({c.e, psn});
+        bw_ns[c.f].push_back({c.e, pns});
+      }
+    SP_TRY(copy_batch(cc, 0));
+    auto build = [&](std::map<int, std::vector<std::pair<int, void *>>> &m, int trans,
+                     std::vector<PullGroup> &G, std::vector<PullItem> &I, bool all_leaf) {
+      std::vector<int> keys;
+      if (all_leaf) {
+        for (int s : leaves)
+          for (int f : cl[s].elems) keys.push_back(f);
+        std::sort(keys.begin(), keys.end());
+      } else {
+        for (auto &kv : m) keys.push_back(kv.first);
+      }
+      for (int key : keys) {
+        PullGroup g{};
+        g.oslot = d_iota + int64_t(key) * b;
+        g.rows = b;
+        g.item_begin = int(I.size());
+        auto it = m.find(key);
+        if (it != m.end())
+          for (auto &pp : it->second) {
+            PullItem p{};
+            p.B = pp.second;
+            p.islot = d_iota + int64_t(pp.first) * b;
+            p.rows = p.cols = b;
+            p.ldb = b;
+            p.trans = trans;
+            I.push_back(p);
+          }
+        g.item_end = int(I.size());
+        G.push_back(g);
+      }
+    };
+    std::vector<PullGroup> G;
+    std::vector<PullItem> I;
+    build(fw_ns, 0, G, I, false);
+    SP_TRY(AL.fw.set(*this, G, I));
+    G.clear(); I.clear();
+    build(bw_sn, 0, G, I, false);
+    SP_TRY(AL.bw.set(*this, G, I));
+    G.clear(); I.clear();
+    build(fw_sn, 1, G, I, false);
+    SP_TRY(AL.tfw.set(*this, G, I));
+    G.clear(); I.clear();
+    build(bw_ns, 1, G, I, true);
+    SP_TRY(AL.tbw.set(*this, G, I));
+    std::vector<GemvDesc> gv;
+    for (int s : leaves) {
+      GemvDesc d{};
+      d.A = Ainv[s];
+      d.islot = d.oslot = S.d_slots[s];
+      d.rows = d.cols = S.size[s];
+      d.lda = S.size[s];
+      gv.push_back(d);
+      apply_bytes += double(S.size[s]) * S.size[s] * tsz * 2;
+    }
+    SP_TRY(upload(gv, &AL.d_inv, true));
+    AL.n_inv = int(gv.size());
+    apply_bytes += double(ncp) * 2 * b2 * tsz * 2;
+    for (int s : leaves) flops += 2.0 * double(S.size[s]) * S.size[s] * S.size[s];
+  }
+  for (int s : leaves) S.size[s] = 0;   // eliminated
+  return SPAND_OK;
+}
+
+int PullSet::set(Factor &F, const std::vector<PullGroup> &G, const std::vector<PullItem> &I) {
+  n = int(G.size());
+  SP_TRY(F.upload(G, &d_groups, true));
+  SP_TRY(F.upload(I, &d_items, true));
+  return SPAND_OK;
+}
+
+// ------------------------------------------------------------------ dense interior elimination (l >= 1)
+int Factor::eliminate_dense(int l, LevelState &S) {
+  const size_t tsz = fsize(ft);
+  const int ncl = int(S.size.size());
+  ApplyLevel &AL = lv[l];
+  std::vector<int> ints;
+  for (int c = 0; c < ncl; ++c)
+    if (S.interior[c] && S.size[c] > 0) ints.push_back(c);
+  if (ints.empty()) return SPAND_OK;
+  std::vector<std::vector<int>> nb(ncl);
+  for (auto &kv : S.blocks) {
+    const int i = kv.first.first, j = kv.first.second;
+    if (i != j && S.size[i] > 0 && S.size[j] > 0) nb[i].push_back(j);
+  }
+  for (auto &v : nb) std::sort(v.begin(), v.end());
+  mark(PH_LU);
+  std::vector<void *> Ainv(ncl, nullptr);
+  std::vector<ElimDesc> items;
+  for (int s : ints) {
+    const int n = S.size[s];
+    if (n > ELIM_MAXN || n > GEMV_MAXC) {
+      set_error("interior cluster of %d unknowns at level %d exceeds the kernel limit %d; "
+                "increase eps or the number of levels", n, l, ELIM_MAXN);
+      return SPAND_EINVAL;
+    }
+    SP_TRY(dalloc(&Ainv[s], size_t(n) * n * tsz, true));
+    ElimDesc d{};
+    d.A = S.blocks.at({s, s}).p;
+    d.n = n;
+    d.ncols = n;
+    d.ld = n;
+    items.push_back(d);
+    flops += 2.0 * double(n) * n * n;
+    apply_bytes += double(n) * n * tsz * 2;
+  }
+  SP_TRY(elim_batch(items, 0));
+  {
+    std::vector<RowGatherDesc> rg;
+    int mr = 0;
+    for (auto &d : items) {
+      RowGatherDesc g{};
+      g.src = d.A;
+      g.piv = d.piv;
+      g.n = g.cols = d.n;
+      g.lds = g.ldd = d.n;
+      g.colperm = 1;
+      for (int s : ints)
+        if (S.blocks.at({s, s}).p == d.A) g.dst = Ainv[s];
+      rg.push_back(g);
+      mr = std::max(mr, d.n);
+    }
+    RowGatherDesc *d_rg;
+    SP_TRY(upload(rg, &d_rg, false));
+    SP_TRY(launch_row_gather(ft, d_rg, int(rg.size()), mr, stream));
+  }
+  mark(PH_SCHUR);
+  // X_sm = A_ss^-1 A_sm
+  std::map<std::pair<int, int>, void *> X;
+  {
+    std::vector<GemmDesc> gm;
+    for (int s : ints)
+      for (int m : nb[s]) {
+        const Blk &B = S.blocks.at({s, m});
+        void *x;
+        SP_TRY(dalloc(&x, size_t(B.rows) * B.cols * tsz, false));
+        X[{s, m}] = x;
+        GemmDesc g{};
+        g.A = Ainv[s];
+        g.B = B.p;
+        g.C = x;
+        g.M = B.rows;
+        g.N = B.cols;
+        g.K = B.rows;
+        g.lda = B.rows;
+        g.ldb = B.cols;
+        g.ldc = B.cols;
+        g.alpha = 1.0;
+        g.beta = 0.0;
+        gm.push_back(g);
+        flops += 2.0 * double(B.rows) * B.rows * B.cols;
+      }
+    SP_TRY(gemm_batch(gm));
+  }
+  // fill blocks and deterministic rounds of A_nm -= A_ns X_sm
+  std::map<std::pair<int, int>, std::vector<int>> contrib;
+  for (int s : ints)
+    for (int n : nb[s])
+      for (int m : nb[s]) contrib[{n, m}].push_back(s);
+  {
+    PlanArena pa;
+    std::vector<std::pair<std::pair<int, int>, size_t>> offs;
+    for (auto &kv : contrib)
+      if (!S.blocks.count(kv.first))
+        offs.push_back({kv.first, pa.add(size_t(S.size[kv.first.first]) * S.size[kv.first.second] * tsz)});
+    if (!offs.empty()) {
+      void *base;
+      SP_TRY(dalloc(&base, pa.total, false));
+      SP_HIP(hipMemsetAsync(base, 0, pa.total, stream));
+      for (auto &o : offs)
+        S.blocks[o.first] = Blk{(char *)base + o.second, S.size[o.first.first], S.size[o.first.second]};
+    }
+  }
+  size_t rounds = 0;
+  for (auto &kv : contrib) rounds = std::max(rounds, kv.second.size());
+  for (size_t r = 0; r < rounds; ++r) {
+    std::vector<GemmDesc> gm;
+    for (auto &kv : contrib) {
+      if (kv.second.size() <= r) continue;
+      const int s = kv.second[r];
+      const int n = kv.first.first, m = kv.first.second;
+      const Blk &Ans = S.blocks.at({n, s});
+      const Blk &T = S.blocks.at(kv.first);
+      GemmDesc g{};
+      g.A = Ans.p;
+      g.B = X.at({s, m});
+      g.C = T.p;
+      g.M = T.rows;
+      g.N = T.cols;
+      g.K = Ans.cols;
+      g.lda = Ans.cols;
+      g.ldb = T.cols;
+      g.ldc = T.cols;
+      g.alpha = -1.0;
+      g.beta = 1.0;
+      gm.push_back(g);
+      flops += 2.0 * double(T.rows) * T.cols * Ans.cols;
+    }
+    SP_TRY(gemm_batch(gm));
+  }
+  // apply descriptors
+  std::vector<GemvDesc> gv;
+  for (int s : ints) {
+    GemvDesc d{};
+    d.A = Ainv[s];
+    d.islot = d.oslot = S.d_slots[s];
+    d.rows = d.cols = S.size[s];
+    d.lda = S.size[s];
+    gv.push_back(d);
+  }
+  SP_TRY(upload(gv, &AL.d_inv, true));
+  AL.n_inv = int(gv.size());
+  std::map<int, std::vector<PullItem>> fw, tfw;
+  std::vector<PullGroup> G;
+  std::vector<PullItem> I;
+  std::vector<PullGroup> G2;
+  std::vector<PullItem> I2;
+  for (int s : ints)
+    for (int n : nb[s]) {
+      const Blk &Ans = S.blocks.at({n, s});   // |n| x |s|
+      const Blk &Asn = S.blocks.at({s, n});   // |s| x |n|
+      PullItem p{};
+      p.B = Ans.p;
+      p.islot = S.d_slots[s];
+      p.rows = S.size[n];
+      p.cols = S.size[s];
+      p.ldb = Ans.cols;
+      p.trans = 0;
+      fw[n].push_back(p);
+      PullItem q{};
+      q.B = Asn.p;
+      q.islot = S.d_slots[s];
+      q.rows = S.size[n];
+      q.cols = S.size[s];
+      q.ldb = Asn.cols;
+      q.trans = 1;
+      tfw[n].push_back(q);
+      apply_bytes += double(Ans.rows) * Ans.cols * tsz * 2 + double(Asn.rows) * Asn.cols * tsz * 2;
+      if (S.size[n] > PULL_MAXR || S.size[s] > GEMV_MAXC) {
+        set_error("coupling block %dx%d exceeds the sweep kernel limit", S.size[n], S.size[s]);
+        return SPAND_EINVAL;
+      }
+    }
+  for (auto &kv : fw) {
+    PullGroup g{};
+    g.oslot = S.d_slots[kv.first];
+    g.rows = S.size[kv.first];
+    g.item_begin = int(I.size());
+    I.insert(I.end(), kv.second.begin(), kv.second.end());
+    g.item_end = int(I.size());
+    G.push_back(g);
+  }
+  SP_TRY(AL.fw.set(*this, G, I));
+  G.clear();
+  I.clear();
+  for (auto &kv : tfw) {
+    PullGroup g{};
+    g.oslot = S.d_slots[kv.first];
+    g.rows = S.size[kv.first];
+    g.item_begin = int(I.size());
+    I.insert(I.end(), kv.second.begin(), kv.second.end());
+    g.item_end = int(I.size());
+    G.push_back(g);
+  }
+  SP_TRY(AL.tfw.set(*this, G, I));
+  G.clear();
+  I.clear();
+  for (int s : ints) {
+    PullGroup g{}, g2{};
+    g.oslot = g2.oslot = S.d_slots[s];
+    g.rows = g2.rows = S.size[s];
+    g.item_begin = int(I.size());
+    g2.item_begin = int(I2.size());
+    for (int n : nb[s]) {
+      const Blk &Asn = S.blocks.at({s, n});
+      const Blk &Ans = S.blocks.at({n, s});
+      PullItem p{};
+      p.B = Asn.p;
+      p.islot = S.d_slots[n];
+      p.rows = S.size[s];
+      p.cols = S.size[n];
+      p.ldb = Asn.cols;
+      p.trans = 0;
+      I.push_back(p);
+      PullItem q{};
+      q.B = Ans.p;
+      q.islot = S.d_slots[n];
+      q.rows = S.size[s];
+      q.cols = S.size[n];
+      q.ldb = Ans.cols;
+      q.trans = 1;
+      I2.push_back(q);
+    }
+    g.item_end = int(I.size());
+    g2.item_end = int(I2.size());
+    if (g.item_end > g.item_begin) G.push_back(g);
+    G2.push_back(g2);
+  }
+  SP_TRY(AL.bw.set(*this, G, I));
+  SP_TRY(AL.tbw.set(*this, G2, I2));
+  // eliminated clusters leave the trailing matrix
+  for (int s : ints) {
+    for (int n : nb[s]) {
+      S.blocks.erase({s, n});
+      S.blocks.erase({n, s});
+    }
+    S.blocks.erase({s, s});
+    S.size[s] = 0;
+  }
+  return SPAND_OK;
+}
+
+// ------------------------------------------------------------------ interfaces (any level < top)
+int Factor::sparsify(int l, const NDResult &nd, LevelState &S, LevelState &Nx) {
+  const size_t tsz = fsize(ft);
+  const int ncl = int(S.size.size());
+  ApplyLevel &AL = lv[l];
+  std::vector<int> ifs;
+  for (int c = 0; c < ncl; ++c)
+    if (!S.interior[c] && S.size[c] > 0) ifs.push_back(c);
+  std::vector<std::vector<int>> nb(ncl);
+  for (auto &kv : S.blocks) {
+    const int i = kv.first.first, j = kv.first.second;
+    if (i != j && S.size[i] > 0 && S.size[j] > 0) nb[i].push_back(j);
+  }
+  for (auto &v : nb) std::sort(v.begin(), v.end());
+  for (int s : ifs) {
+    const int m = S.size[s];
+    if (m > QRCP_MAXM || m > ELIM_MAXN) {
+      set_error("interface of %d unknowns at level %d exceeds the kernel limit %d; "
+                "increase eps or the number of levels", m, l, QRCP_MAXM);
+      return SPAND_EINVAL;
+    }
+  }
+  // ---- scaling: [A_ss | I] -> U, L^-1 P^T ; U^-1 ; split diag(U)
+  mark(PH_SCALE);
+  std::vector<void *> Aug(ncl), Ust(ncl), Lh(ncl), Sv(ncl), Si(ncl);
+  std::vector<ElimDesc> items;
+  std::vector<CopyDesc> cps;
+  std::vector<EyeDesc> eyes;
+  int maxm = 0;
+  for (int s : ifs) {
+    const int m = S.size[s];
+    maxm = std::max(maxm, m);
+    SP_TRY(dalloc(&Aug[s], size_t(m) * 2 * m * tsz, false));
+    SP_TRY(dalloc(&Ust[s], size_t(m) * m * tsz, false));
+    SP_TRY(dalloc(&Lh[s], size_t(m) * m * tsz, false));
+    SP_TRY(dalloc(&Sv[s], size_t(m) * tsz, false));
+    SP_TRY(dalloc(&Si[s], size_t(m) * tsz, false));
+    CopyDesc d{};
+    d.src = S.blocks.at({s, s}).p;
+    d.dst = Aug[s];
+    d.rows = d.cols = m;
+    d.lds = m;
+    d.ldd = 2 * m;
+    d.scale = 1.0;
+    cps.push_back(d);
+    EyeDesc e{};
+    e.A = (char *)Aug[s] + size_t(m) * tsz;
+    e.n = m;
+    e.ld = 2 * m;
+    eyes.push_back(e);
+    ElimDesc el{};
+    el.A = Aug[s];
+    el.n = m;
+    el.ncols = 2 * m;
+    el.ld = 2 * m;
+    items.push_back(el);
+    flops += 4.0 * double(m) * m * m;
+  }
+  SP_TRY(copy_batch(cps, 1));
+  {
+    EyeDesc *d_e;
+    SP_TRY(upload(eyes, &d_e, false));
+    SP_TRY(launch_eye(ft, d_e, int(eyes.size()), maxm, stream));
+  }
+  SP_TRY(elim_batch(items, 1));
+  {
+    std::vector<RowGatherDesc> rg;
+    for (auto &d : items) {
+      int s = -1;
+      for (int c : ifs)
+        if (Aug[c] == d.A) s = c;
+      RowGatherDesc g{};
+      g.src = d.A;
+      g.piv = d.piv;
+      g.n = g.cols = d.n;
+      g.lds = d.ld;
+      g.ldd = d.n;
+      g.colperm = 0;
+      g.col_off = 0;
+      g.dst = Ust[s];
+      rg.push_back(g);
+      g.col_off = d.n;
+      g.dst = Lh[s];
+      rg.push_back(g);
+    }
+    RowGatherDesc *d_rg;
+    SP_TRY(upload(rg, &d_rg, false));
+    SP_TRY(launch_row_gather(ft, d_rg, int(rg.size()), maxm, stream));
+    // diagonal split: Sv = sqrt|u_jj|, Si = 1/Sv
+    std::vector<DiagDesc> dd;
+    for (int s : ifs) dd.push_back(DiagDesc{Ust[s], Sv[s], Si[s], S.size[s], S.size[s]});
+    DiagDesc *d_dd;
+    SP_TRY(upload(dd, &d_dd, false));
+    SP_TRY(launch_diag_split(ft, d_dd, int(dd.size()), stream));
+    // U^-1 in place (Gauss-Jordan without pivoting; no permutation to undo)
+    std::vector<ElimDesc> ui;
+    for (int s : ifs) {
+      ElimDesc el{};
+      el.A = Ust[s];
+      el.n = el.ncols = el.ld = S.size[s];
+      ui.push_back(el);
+      flops += 2.0 * double(S.size[s]) * S.size[s] * S.size[s];
+    }
+    SP_TRY(elim_batch(ui, 2));
+    // Lh^-1 P^T = S^-1 (L^-1 P^T) ; Uh^-1 = U^-1 S
+    std::vector<ScaleDesc> sc;
+    for (int s : ifs) {
+      sc.push_back(ScaleDesc{Lh[s], Si[s], nullptr, S.size[s], S.size[s], S.size[s], 0});
+      sc.push_back(ScaleDesc{Ust[s], nullptr, Sv[s], S.size[s], S.size[s], S.size[s], 0});
+    }
+    ScaleDesc *d_sc;
+    SP_TRY(upload(sc, &d_sc, false));
+    SP_TRY(launch_scale(ft, d_sc, int(sc.size()), stream));
+  }
+  // scaled blocks A'_ij = Lh_i^-1 P_i^T A_ij Uh_j^-1 (i != j)
+  {
+    std::vector<GemmDesc> g1, g2;
+    std::map<std::pair<int, int>, void *> tmp;
+    for (auto &kv : S.blocks) {
+      const int i = kv.first.first, j = kv.first.second;
+      if (i == j || S.size[i] == 0 || S.size[j] == 0) continue;
+      const Blk &B = kv.second;
+      void *t;
+      SP_TRY(dalloc(&t, size_t(B.rows) * B.cols * tsz, false));
+      GemmDesc g{};
+      g.A = Lh[i];
+      g.B = B.p;
+      g.C = t;
+      g.M = B.rows;
+      g.N = B.cols;
+      g.K = B.rows;
+      g.lda = B.rows;
+      g.ldb = B.cols;
+      g.ldc = B.cols;
+      g.alpha = 1.0;
+      g.beta = 0.0;
+      g1.push_back(g);
+      GemmDesc h{};
+      h.A = t;
+      h.B = Ust[j];
+      h.C = B.p;
+      h.M = B.rows;
+      h.N = B.cols;
+      h.K = B.cols;
+      h.lda = B.cols;
+      h.ldb = B.cols;
+      h.ldc = B.cols;
+      h.alpha = 1.0;
+      h.beta = 0.0;
+      g2.push_back(h);
+      flops += 2.0 * double(B.rows) * B.cols * (B.rows + B.cols);
+    }
+    SP_TRY(gemm_batch(g1));
+    SP_TRY(gemm_batch(g2));
+  }
+  // ---- RRQR of W = [A'_sn ... | A'_ns^T ...]
+  mark(PH_RRQR);
+  std::vector<void *> Qm(ncl), Vm(ncl), Wm(ncl);
+  std::vector<int> ncols(ncl, 0);
+  std::vector<QrcpDesc> qd;
+  void *kout;
+  SP_TRY(dalloc(&kout, std::max<size_t>(1, ifs.size()) * 4, false));
+  {
+    std::vector<CopyDesc> wc;
+    for (size_t q = 0; q < ifs.size(); ++q) {
+      const int s = ifs[q];
+      const int m = S.size[s];
+      int nc = 0;
+      for (int n : nb[s]) nc += 2 * S.size[n];
+      ncols[s] = nc;
+      SP_TRY(dalloc(&Wm[s], size_t(m) * std::max(nc, 1) * tsz, false));
+      SP_TRY(dalloc(&Qm[s], size_t(m) * m * tsz, false));
+      SP_TRY(dalloc(&Vm[s], size_t(m) * m * tsz, false));
+      void *tau, *vn1, *vn2, *sel;
+      SP_TRY(dalloc(&tau, size_t(m) * 8, false));
+      SP_TRY(dalloc(&vn1, size_t(std::max(nc, 1)) * 8, false));
+      SP_TRY(dalloc(&vn2, size_t(std::max(nc, 1)) * 8, false));
+      SP_TRY(dalloc(&sel, size_t(std::max(nc, 1)) * 4, false));
+      int off = 0;
+      for (int n : nb[s]) {
+        const Blk &B = S.blocks.at({s, n});
+        CopyDesc d{};
+        d.src = B.p;
+        d.dst = (char *)Wm[s] + size_t(off) * tsz;
+        d.rows = m;
+        d.cols = B.cols;
+        d.lds = B.cols;
+        d.ldd = nc;
+        d.scale = 1.0;
+        wc.push_back(d);
+        off += B.cols;
+      }
+      for (int n : nb[s]) {
+        const Blk &B = S.blocks.at({n, s});   // |n| x m
+        CopyDesc d{};
+        d.src = B.p;
+        d.dst = (char *)Wm[s] + size_t(off) * tsz;
+        d.rows = m;
+        d.cols = B.rows;
+        d.lds = B.cols;
+        d.ldd = nc;
+        d.trans = 1;
+        d.scale = 1.0;
+        wc.push_back(d);
+        off += B.rows;
+      }
+      QrcpDesc Qd{};
+      Qd.W = Wm[s];
+      Qd.Q = Qm[s];
+      Qd.V = Vm[s];
+      Qd.tau = (double *)tau;
+      Qd.vn1 = (double *)vn1;
+      Qd.vn2 = (double *)vn2;
+      Qd.sel = (int32_t *)sel;
+      Qd.k_out = (int32_t *)kout + q;
+      Qd.m = m;
+      Qd.ncols = nc;
+      qd.push_back(Qd);
+      flops += 4.0 * double(m) * nc * std::min(m, nc);
+    }
+    SP_TRY(copy_batch(wc, 1));
+    QrcpDesc *d_q;
+    SP_TRY(upload(qd, &d_q, false));
+    SP_TRY(launch_qrcp(ft, d_q, int(qd.size()), eps, eps == 0.0 ? 1 : 0, stream));
+  }
+  std::vector<int32_t> ks(ifs.size(), 0);
+  if (!ifs.empty())
+    SP_HIP(hipMemcpyAsync(ks.data(), kout, ifs.size() * 4, hipMemcpyDeviceToHost, stream));
+  SP_HIP(hipStreamSynchronize(stream));
+  std::vector<int> kk(ncl, 0);
+  {
+    RankStat rs;
+    for (size_t q = 0; q < ifs.size(); ++q) {
+      kk[ifs[q]] = ks[q];
+      rs.add(S.size[ifs[q]], ks[q]);
+    }
+    ranks.push_back(rs);
+  }
+  // ---- F_s = Q_s^T Lh_s^-1 P_s^T, B_s = Uh_s^-1 Q_s (stored) ; apply descriptors
+  mark(PH_COMPRESS);
+  {
+    std::vector<GemmDesc> gm;
+    std::vector<GemvDesc> gf, gb;
+    for (int s : ifs) {
+      const int m = S.size[s];
+      void *Fp, *Bp;
+      SP_TRY(dalloc(&Fp, size_t(m) * m * tsz, true));
+      SP_TRY(dalloc(&Bp, size_t(m) * m * tsz, true));
+      GemmDesc g{};
+      g.A = Qm[s];
+      g.transA = 1;
+      g.B = Lh[s];
+      g.C = Fp;
+      g.M = g.N = g.K = m;
+      g.lda = g.ldb = g.ldc = m;
+      g.alpha = 1.0;
+      gm.push_back(g);
+      GemmDesc h{};
+      h.A = Ust[s];
+      h.B = Qm[s];
+      h.C = Bp;
+      h.M = h.N = h.K = m;
+      h.lda = h.ldb = h.ldc = m;
+      h.alpha = 1.0;
+      gm.push_back(h);
+      GemvDesc d{};
+      d.islot = d.oslot = S.d_slots[s];
+      d.rows = d.cols = m;
+      d.lda = m;
+      d.A = Fp;
+      gf.push_back(d);
+      d.A = Bp;
+      gb.push_back(d);
+      apply_bytes += 4.0 * double(m) * m * tsz;
+      flops += 4.0 * double(m) * m * m;
+    }
+    SP_TRY(gemm_batch(gm));
+    SP_TRY(upload(gf, &AL.d_F, true));
+    SP_TRY(upload(gb, &AL.d_B, true));
+    AL.n_if = int(gf.size());
+  }
+  // ---- merge: next-level clusters from the coarse parts
+  const auto &cl1 = nd.levels[l + 1];
+  const auto &kids = nd.children[l + 1];
+  const int ncl1 = int(cl1.size());
+  std::vector<int> parent(ncl, -1), poff(ncl, 0);
+  Nx.size.assign(ncl1, 0);
+  Nx.interior.assign(ncl1, 0);
+  Nx.slots.assign(ncl1, {});
+  for (int I = 0; I < ncl1; ++I) {
+    Nx.interior[I] = cl1[I].interior;
+    int o = 0;
+    for (int c : kids[I]) {
+      parent[c] = I;
+      poff[c] = o;
+      o += kk[c];
+      Nx.slots[I].insert(Nx.slots[I].end(), S.slots[c].begin(), S.slots[c].begin() + kk[c]);
+    }
+    Nx.size[I] = o;
+  }
+  // parent blocks
+  std::set<std::pair<int, int>> pp;
+  for (auto &kv : S.blocks) {
+    const int i = kv.first.first, j = kv.first.second;
+    if (S.size[i] == 0 || S.size[j] == 0 || kk[i] == 0 || kk[j] == 0) continue;
+    if (parent[i] < 0 || parent[j] < 0) continue;
+    pp.insert({parent[i], parent[j]});
+  }
+  {
+    PlanArena pk, pt;
+    std::vector<std::tuple<std::pair<int, int>, size_t, bool>> offs;
+    for (auto &pr : pp) {
+      const bool keep = Nx.interior[pr.first] || Nx.interior[pr.second];
+      const size_t bytes = size_t(Nx.size[pr.first]) * Nx.size[pr.second] * tsz;
+      offs.push_back({pr, keep ? pk.add(bytes) : pt.add(bytes), keep});
+    }
+    void *bk = nullptr, *bt = nullptr;
+    if (pk.total) {
+      SP_TRY(dalloc(&bk, pk.total, true));
+      SP_HIP(hipMemsetAsync(bk, 0, pk.total, stream));
+    }
+    if (pt.total) {
+      SP_TRY(dalloc_next(&bt, pt.total));
+      SP_HIP(hipMemsetAsync(bt, 0, pt.total, stream));
+    }
+    Nx.blocks.clear();
+    for (auto &o : offs) {
+      auto pr = std::get<0>(o);
+      char *base = (char *)(std::get<2>(o) ? bk : bt);
+      Nx.blocks[pr] = Blk{base + std::get<1>(o), Nx.size[pr.first], Nx.size[pr.second]};
+    }
+  }
+  // compression A_ij <- Q_ic^T A'_ij Q_jc into the parent block; diagonals -> I_k
+  {
+    std::vector<GemmDesc> g1, g2;
+    std::vector<EyeDesc> ey;
+    int maxk = 0;
+    for (auto &kv : S.blocks) {
+      const int i = kv.first.first, j = kv.first.second;
+      if (S.size[i] == 0 || S.size[j] == 0 || kk[i] == 0 || kk[j] == 0) continue;
+      const Blk &P = Nx.blocks.at({parent[i], parent[j]});
+      if (i == j) {
+        EyeDesc e{};
+        e.A = (char *)P.p + (size_t(poff[i]) * P.cols + poff[i]) * tsz;
+        e.n = kk[i];
+        e.ld = P.cols;
+        ey.push_back(e);
+        maxk = std::max(maxk, kk[i]);
+        continue;
+      }
+      const Blk &B = kv.second;
+      void *t;
+      SP_TRY(dalloc(&t, size_t(kk[i]) * B.cols * tsz, false));
+      GemmDesc g{};
+      g.A = Qm[i];
+      g.transA = 1;
+      g.lda = S.size[i];
+      g.B = B.p;
+      g.ldb = B.cols;
+      g.C = t;
+      g.ldc = B.cols;
+      g.M = kk[i];
+      g.N = B.cols;
+      g.K = S.size[i];
+      g.alpha = 1.0;
+      g1.push_back(g);
+      GemmDesc h{};
+      h.A = t;
+      h.lda = B.cols;
+      h.B = Qm[j];
+      h.ldb = S.size[j];
+      h.C = (char *)P.p + (size_t(poff[i]) * P.cols + poff[j]) * tsz;
+      h.ldc = P.cols;
+      h.M = kk[i];
+      h.N = kk[j];
+      h.K = B.cols;
+      h.alpha = 1.0;
+      g2.push_back(h);
+      flops += 2.0 * double(kk[i]) * B.cols * (B.rows + kk[j]);
+    }
+    SP_TRY(gemm_batch(g1));
+    SP_TRY(gemm_batch(g2));
+    EyeDesc *d_e;
+    SP_TRY(upload(ey, &d_e, false));
+    SP_TRY(launch_eye(ft, d_e, int(ey.size()), maxk, stream));
+  }
+  for (int I = 0; I < ncl1; ++I) {
+    int32_t *sl = nullptr;
+    if (!Nx.slots[I].empty()) SP_TRY(upload_slots(Nx.slots[I], &sl));
+    Nx.d_slots.push_back(sl);
+  }
+  return SPAND_OK;
+}
+
+// ------------------------------------------------------------------ driver
+int Factor::build(const spand_bsr_t &A, const spand_grid_t &g, const spand_opts_t &o) {
+  auto t0 = std::chrono::steady_clock::now();
+  bs = A.bs;
+  K = A.n_brows;
+  N = int64_t(K) * bs;
+  ft = o.factor_dtype == SPAND_F32 ? FType::F32 : FType::F64;
+  eps = o.eps;
+  L = o.nlevels > 0 ? o.nlevels : default_levels(K);
+  h_rowptr.resize(K + 1);
+  h_colind.resize(A.nnzb);
+  SP_HIP(hipMemcpyAsync(h_rowptr.data(), A.d_rowptr, (K + 1) * 4, hipMemcpyDeviceToHost, stream));
+  SP_HIP(hipMemcpyAsync(h_colind.data(), A.d_colind, A.nnzb * 4, hipMemcpyDeviceToHost, stream));
+  SP_HIP(hipStreamSynchronize(stream));
+  if (h_rowptr[0] != 0 || h_rowptr[K] != A.nnzb) {
+    set_error("rowptr[0] must be 0 and rowptr[n_brows] must equal nnzb");
+    return SPAND_EINVAL;
+  }
+  for (int e = 0; e < K; ++e) {
+    if (h_rowptr[e + 1] < h_rowptr[e]) {
+      set_error("rowptr must be non-decreasing");
+      return SPAND_EINVAL;
+    }
+    for (int t = h_rowptr[e]; t < h_rowptr[e + 1]; ++t) {
+      if (h_colind[t] < 0 || h_colind[t] >= K || (t > h_rowptr[e] && h_colind[t] <= h_colind[t - 1])) {
+        set_error("colind must be in range and strictly ascending in every block row (row %d)", e);
+        return SPAND_EINVAL;
+      }
+    }
+  }
+  NDResult nd = nested_dissection(g.nx, g.ny, g.periodic_x != 0, g.periodic_y != 0, L);
+  void *p;
+  SP_TRY(dalloc(&p, size_t(N) * 4, true));
+  d_iota = (int32_t *)p;
+  SP_TRY(vec_iota(d_iota, N, stream));
+  SP_TRY(dalloc(&p, size_t(N) * 8, true));
+  d_tbuf = (double *)p;
+  SP_TRY(dalloc(&p, 64, true));
+  d_flag = (int *)p;
+  SP_HIP(hipMemsetAsync(d_flag, 0, 64, stream));
+  lv.assign(L, ApplyLevel{});
+  auto t1 = std::chrono::steady_clock::now();
+  t_host_ms += std::chrono::duration<double, std::milli>(t1 - t0).count();
+  mark(PH_GATHER);
+  LevelState S;
+  SP_TRY(level0(A, nd, S));
+  for (int l = 0; l < L; ++l) {
+    if (l >= 1) SP_TRY(eliminate_dense(l, S));
+    if (l == L - 1) break;
+    LevelState Nx;
+    SP_TRY(sparsify(l, nd, S, Nx));
+    SP_HIP(hipStreamSynchronize(stream));
+    free_temp();
+    S = std::move(Nx);
+  }
+  int tops = 0;
+  for (int c = 0; c < int(S.size.size()); ++c) tops += S.size[c];
+  top_size = tops;
+  mark(PH_END);
+  SP_HIP(hipStreamSynchronize(stream));
+  temp.release();
+  next_temp.release();
+  int flag = 0;
+  SP_HIP(hipMemcpy(&flag, d_flag, 4, hipMemcpyDeviceToHost));
+  collect_events();
+  if (flag) {
+    set_error("zero pivot met during the factorization");
+    return SPAND_ESINGULAR;
+  }
+  return finish_transposed();
+}
+
+// ------------------------------------------------------------------ apply
+int Factor::apply(const double *in, double *out, int transpose, hipStream_t st) {
+  if (out != in) SP_HIP(hipMemcpyAsync(out, in, size_t(N) * 8, hipMemcpyDeviceToDevice, st));
+  double *x = out;
+  if (!transpose) {
+    for (int l = 0; l < L; ++l) {
+      const ApplyLevel &A = lv[l];
+      if (A.fw.n) {
+        SP_TRY(launch_gemv(ft, A.d_inv, A.n_inv, x, d_tbuf, 1.0, 0.0, 0, st));
+        SP_TRY(launch_pull2(ft, A.fw.d_groups, A.fw.n, A.fw.d_items, d_tbuf, x, -1.0, 1.0, st));
+      }
+      if (A.n_if) SP_TRY(launch_gemv(ft, A.d_F, A.n_if, x, x, 1.0, 0.0, 0, st));
+    }
+    for (int l = L - 1; l >= 0; --l) {
+      const ApplyLevel &A = lv[l];
+      if (A.n_if) SP_TRY(launch_gemv(ft, A.d_B, A.n_if, x, x, 1.0, 0.0, 0, st));
+      if (A.bw.n) SP_TRY(launch_pull2(ft, A.bw.d_groups, A.bw.n, A.bw.d_items, x, x, -1.0, 1.0, st));
+      if (A.n_inv) SP_TRY(launch_gemv(ft, A.d_inv, A.n_inv, x, x, 1.0, 0.0, 0, st));
+    }
+  } else {
+    for (int l = 0; l < L; ++l) {
+      const ApplyLevel &A = lv[l];
+      if (A.n_inv) SP_TRY(launch_gemv(ft, A.d_invT, A.n_inv, x, x, 1.0, 0.0, 0, st));
+      if (A.tfw.n) SP_TRY(launch_pull2(ft, A.tfw.d_groups, A.tfw.n, A.tfw.d_items, x, x, -1.0, 1.0, st));
+      if (A.n_if) SP_TRY(launch_gemv(ft, A.d_BT, A.n_if, x, x, 1.0, 0.0, 0, st));
+    }
+    for (int l = L - 1; l >= 0; --l) {
+      const ApplyLevel &A = lv[l];
+      if (A.n_if) SP_TRY(launch_gemv(ft, A.d_FT, A.n_if, x, x, 1.0, 0.0, 0, st));
+      if (A.tbw.n && A.n_inv) {
+        SP_TRY(launch_pull2(ft, A.tbw.d_groups, A.tbw.n, A.tbw.d_items, x, d_tbuf, 1.0, 0.0, st));
+        SP_TRY(launch_gemv(ft, A.d_invT, A.n_inv, d_tbuf, x, -1.0, 1.0, 0, st));
+      }
+    }
+  }
+  return SPAND_OK;
+}
+
+// transposed GEMV descriptors are the same matrices with trans = 1
+int Factor::finish_transposed() {
+  for (auto &A : lv) {
+    auto mk = [&](GemvDesc *src, int n, GemvDesc **dst) -> int {
+      if (!n) return SPAND_OK;
+      std::vector<GemvDesc> v(n);
+      SP_HIP(hipMemcpy(v.data(), src, n * sizeof(GemvDesc), hipMemcpyDeviceToHost));
+      for (auto &d : v) d.trans = 1;   // square: rows = cols, lda unchanged
+      return upload(v, dst, true);
+    };
+    SP_TRY(mk(A.d_inv, A.n_inv, &A.d_invT));
+    SP_TRY(mk(A.d_F, A.n_if, &A.d_FT));
+    SP_TRY(mk(A.d_B, A.n_if, &A.d_BT));
+  }
+  return SPAND_OK;
+}
+
+void Factor::fill_stats(spand_factor_stats_t *st) const {
+  std::memset(st, 0, sizeof(*st));
+  st->nlevels = L;
+  for (size_t l = 0; l < ranks.size() && l < SPAND_MAX_LEVELS; ++l) {
+    const RankStat &r = ranks[l];
+    st->n_clusters[l] = r.n;
+    st->rank_min[l] = r.n ? r.kmin : 0;
+    st->rank_max[l] = r.kmax;
+    st->rank_avg[l] = r.n ? double(r.ksum) / r.n : 0.0;
+    st->size_before[l] = r.msum;
+    st->size_after[l] = r.ksum;
+  }
+  st->top_size = top_size;
+  st->factor_bytes = int64_t(apply_bytes);
+  st->factor_flops = flops;
+  st->t_host_ms = t_host_ms;
+  st->t_device_ms = ph_ms[PH_GATHER] + ph_ms[PH_LU] + ph_ms[PH_SCHUR] + ph_ms[PH_SCALE] +
+                    ph_ms[PH_RRQR] + ph_ms[PH_COMPRESS];
+  st->t_lu_ms = ph_ms[PH_LU];
+  st->t_schur_ms = ph_ms[PH_SCHUR];
+  st->t_scale_ms = ph_ms[PH_SCALE];
+  st->t_rrqr_ms = ph_ms[PH_RRQR];
+  st->t_compress_ms = ph_ms[PH_COMPRESS];
+}
+
+void Factor::collect_events() {
+  for (size_t i = 0; i + 1 < events.size(); ++i) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, events[i].second, events[i + 1].second) == hipSuccess)
+      ph_ms[events[i].first] += ms;
+  }
+  for (auto &e : events) (void)hipEventDestroy(e.second);
+  events.clear();
+}
+
+}  // namespace spand

@@ -1,0 +1,224 @@
+// Internal declarations of libspand: host data structures shared by the
+// planning / orchestration code and the launch wrappers of the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <array>
+#include <cstdio>
+#include <map>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/spand.h"
+
+namespace spand {
+
+// ----------------------------------------------------------------- errors
+void set_error(const char *fmt, ...);
+const char *last_error();
+
+struct Status {
+  int code = SPAND_OK;
+  bool ok() const { return code == SPAND_OK; }
+};
+
+#define SP_HIP(call)                                                        \
+  do {                                                                      \
+    hipError_t e_ = (call);                                                 \
+    if (e_ != hipSuccess) {                                                 \
+      ::spand::set_error("%s:%d %s: %s", __FILE__, __LINE__, #call,         \
+                         hipGetErrorString(e_));                            \
+      return SPAND_EHIP;                                                    \
+    }                                                                       \
+  } while (0)
+
+#define SP_TRY(expr)                                                        \
+  do {                                                                      \
+    int r_ = (expr);                                                        \
+    if (r_ < 0) return r_;                                                  \
+  } while (0)
+
+// ----------------------------------------------------------------- ND
+struct NDCluster {
+  int32_t node, box;
+  bool interior;
+  std::vector<int32_t> elems;   // ascending
+};
+
+struct NDResult {
+  int nx = 0, ny = 0, L = 0;
+  std::vector<int32_t> node_of_elem;
+  std::map<int64_t, int> node_level;               // node id -> level
+  std::vector<std::vector<NDCluster>> levels;      // per level
+  std::vector<std::vector<std::vector<int>>> children;  // [l][cluster] -> ids at l-1
+  std::vector<int32_t> perm;
+};
+
+int default_levels(int64_t K);
+NDResult nested_dissection(int nx, int ny, bool px, bool py, int L);
+
+// ----------------------------------------------------------------- device memory
+// Simple owning device buffer.
+struct DevBuf {
+  void *p = nullptr;
+  size_t bytes = 0;
+};
+
+// Element type tag for the factor (float or double storage/compute).
+enum class FType { F64 = 0, F32 = 1 };
+inline size_t fsize(FType t) { return t == FType::F64 ? 8 : 4; }
+
+// ----------------------------------------------------------------- kernel descriptors
+// All descriptors hold byte offsets / element pointers into device memory;
+// they are built and bounds-checked on the host, then uploaded.
+
+// C = alpha * op(A) op(B) + beta * C  (row-major, per item sizes)
+struct GemmDesc {
+  const void *A;
+  const void *B;
+  void *C;
+  int32_t M, N, K;
+  int32_t lda, ldb, ldc;
+  int32_t transA, transB;
+  double alpha, beta;
+};
+
+// Copy of a rows x cols sub-matrix, optional transpose, from src (type Ts)
+// to dst (type Td): dst[r*ldd + c] = scale * src(r, c) (or src(c, r)).
+struct CopyDesc {
+  const void *src;
+  void *dst;
+  int32_t rows, cols;
+  int32_t lds, ldd;
+  int32_t trans;
+  int32_t pad;
+  double scale;
+};
+
+// Panel factorisation problem (GJE / LU on an augmented row-major matrix).
+struct ElimDesc {
+  void *A;          // n x ld row-major (ld >= ncols)
+  void *P;          // workspace n x nb  (panel copy)
+  void *T;          // workspace nb x ld (pivot rows copy)
+  int32_t *piv;     // [n] pivot row per column (virtual pivoting)
+  int32_t *used;    // [n] row-used flags
+  int32_t n;        // order of the square part
+  int32_t ncols;    // total columns (n or 2n)
+  int32_t ld;
+  int32_t pad;
+};
+
+// Dense GEMV with gather/scatter through slot lists:
+// out[oslot[r]] = beta*out[oslot[r]] + alpha * sum_c op(A)(r,c) * in[islot[c]]
+struct GemvDesc {
+  const void *A;
+  const int32_t *islot;
+  const int32_t *oslot;
+  int32_t rows, cols;      // of op(A)
+  int32_t lda;             // of A as stored
+  int32_t trans;
+};
+
+// Pull group: out[oslot[r]] += alpha * sum_items op(B_i) in[islot_i[c]].
+struct PullItem {
+  const void *B;
+  const int32_t *islot;
+  int32_t rows, cols;      // of op(B)
+  int32_t ldb;
+  int32_t trans;
+};
+struct PullGroup {
+  const int32_t *oslot;
+  int32_t rows;
+  int32_t item_begin, item_end;
+  int32_t pad;
+};
+
+// Level-0 element Schur update: target -= A1 * Y * A2 (b x b blocks)
+struct SchurItem {
+  int64_t a1;          // BSR block index (row sep elem, col leaf elem)
+  const void *Y;       // pointer to the b x b block inside Ainv (ld = ldy)
+  int64_t a2;          // BSR block index (row leaf elem, col sep elem)
+  int32_t ldy;
+  int32_t pad;
+};
+struct SchurGroup {
+  void *target;        // b x b sub-block inside a dense interface block
+  int32_t ldt;
+  int32_t item_begin, item_end;
+  int32_t pad;
+};
+
+// QRCP problem (rank-revealing QR of a row-major m x ncols matrix W)
+struct QrcpDesc {
+  const void *W;       // m x ncols row-major
+  void *Q;             // m x m row-major output
+  void *V;             // m x m workspace (reflectors, column t contiguous: V[t*m + r])
+  double *tau;         // [m]
+  double *vn1;         // [ncols]
+  double *vn2;         // [ncols]
+  int32_t *sel;        // [ncols] selected flags
+  int32_t *k_out;      // rank
+  int32_t m, ncols;
+};
+
+// ----------------------------------------------------------------- launches
+// Implemented in the .hip files.  Descriptor arrays are device pointers.
+// Every wrapper returns SPAND_OK or SPAND_EHIP (launch error).
+constexpr int ELIM_NB = 16;        // panel width of the elimination kernels
+constexpr int ELIM_NT = 512;       // threads of a panel workgroup
+constexpr int ELIM_RPT = 4;        // rows held per thread -> n <= 2048
+constexpr int ELIM_MAXN = ELIM_NT * ELIM_RPT;
+constexpr int QRCP_MAXM = 1024;    // largest interface handled by the QRCP kernel
+
+int launch_gemm(FType t, const GemmDesc *d_items, const int32_t *d_tile_start, int nitems,
+                int total_tiles, hipStream_t st);
+// src double -> dst factor type (src_is_factor = 0) or factor -> factor (1)
+int launch_copy(FType t, int src_is_factor, const CopyDesc *d_items, int n, int64_t max_elems,
+                hipStream_t st);
+// mode 0: Gauss-Jordan, partial pivoting; 1: LU (augmented), partial
+// pivoting; 2: Gauss-Jordan without pivoting.  Items sorted by n descending,
+// the first nactive have n > k.
+int launch_elim_step(FType t, const ElimDesc *d_items, int nactive, int k, int mode,
+                     int max_tiles, int *d_flag, hipStream_t st);
+// out[j, c] = src[piv[j], colperm ? pinv[c] : c + col_off]
+struct RowGatherDesc {
+  const void *src;
+  void *dst;
+  const int32_t *piv;
+  int32_t n, cols, lds, ldd, col_off, colperm;
+};
+int launch_row_gather(FType t, const RowGatherDesc *d_items, int n, int max_rows, hipStream_t st);
+int launch_schur_elem(FType t, int bs, const double *bsr_val, const SchurGroup *d_groups,
+                      int ngroups, const SchurItem *d_items, hipStream_t st);
+int launch_qrcp(FType t, const QrcpDesc *d_items, int n, double eps, int force_full,
+                hipStream_t st);
+// dst rows/cols scaling: dst[r, c] *= rs[r] * cs[c] (either may be null)
+struct ScaleDesc {
+  void *A;
+  const void *rs;
+  const void *cs;
+  int32_t rows, cols, ld, pad;
+};
+int launch_scale(FType t, const ScaleDesc *d_items, int n, hipStream_t st);
+// A = I (rows x rows sub-block with leading dimension ld)
+struct EyeDesc {
+  void *A;
+  int32_t n, ld;
+};
+int launch_eye(FType t, const EyeDesc *d_items, int n, int max_n, hipStream_t st);
+int launch_gemv(FType t, const GemvDesc *d_items, int n, const double *in, double *out,
+                double alpha, double beta, int max_cols, hipStream_t st);
+int launch_pull(FType t, const PullGroup *d_groups, int ngroups, const PullItem *d_items,
+                const double *in, double *out, double alpha, hipStream_t st);
+int launch_spmv(const spand_bsr_t &A, int transpose, double alpha, const double *x,
+                double beta, double *y, const double *z, double gz, const double *w,
+                double gw, hipStream_t st);
+
+// ----------------------------------------------------------------- helpers
+inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+}  // namespace spand

@@ -1,0 +1,819 @@
+// Dense batched kernels of the spaND factorization (gfx950, wave64).
+//
+//  * k_gemm          variable-size batched C = a op(A) op(B) + b C
+//  * k_elim_panel    one panel (16 columns) of Gauss-Jordan inversion or LU
+//                    with partial pivoting, rows held in registers
+//  * k_elim_update   the rank-16 update that applies a panel to the rest
+//  * k_row_gather    undo the virtual row pivoting
+//  * k_schur_elem    level-0 Schur update on b x b element blocks (Eq. 10)
+//  * k_qrcp          rank-revealing QR with column pivoting (Eq. 12)
+//  * k_copy / k_scale / k_eye  data movement helpers
+//
+// Matrices are row-major.  Every descriptor is validated on the host before
+// upload; kernels trust the sizes they are given.
+#include <climits>
+
+#include "internal.h"
+#include "factor.h"
+
+namespace spand {
+
+// ------------------------------------------------------------------ utils
+template <typename T>
+__device__ inline T wave_sum(T v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// block-wide sum of a double (blockDim multiple of 64, <= 1024)
+__device__ inline double block_sum(double v, double *red) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wid] = v;
+  __syncthreads();
+  double s = 0.0;
+  const int nw = blockDim.x >> 6;
+  for (int i = 0; i < nw; ++i) s += red[i];
+  return s;
+}
+
+// ------------------------------------------------------------------ GEMM
+// 64x64 output tile per 256-thread workgroup, K step 16, 4x4 per thread.
+template <typename T>
+__global__ __launch_bounds__(256) void k_gemm(const GemmDesc *__restrict__ items,
+                                              const int32_t *__restrict__ tile_start,
+                                              int nitems) {
+  const int tile = blockIdx.x;
+  int lo = 0, hi = nitems;
+  while (hi - lo > 1) {
+    int mid = (lo + hi) >> 1;
+    if (tile_start[mid] <= tile) lo = mid; else hi = mid;
+  }
+  const GemmDesc d = items[lo];
+  const int t = tile - tile_start[lo];
+  const int ntn = (d.N + 63) >> 6;
+  const int m0 = (t / ntn) * 64, n0 = (t % ntn) * 64;
+  __shared__ T As[16][65];
+  __shared__ T Bs[16][65];
+  const int tid = threadIdx.x, tm = tid >> 4, tn = tid & 15;
+  T acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = T(0);
+  const T *A = (const T *)d.A;
+  const T *B = (const T *)d.B;
+  for (int k0 = 0; k0 < d.K; k0 += 16) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int idx = tid + q * 256;
+      int mm, kk;
+      if (!d.transA) { mm = idx >> 4; kk = idx & 15; }
+      else { kk = idx >> 6; mm = idx & 63; }
+      const int gm = m0 + mm, gk = k0 + kk;
+      T v = T(0);
+      if (gm < d.M && gk < d.K)
+        v = d.transA ? A[(int64_t)gk * d.lda + gm] : A[(int64_t)gm * d.lda + gk];
+      As[kk][mm] = v;
+      int nn;
+      if (!d.transB) { kk = idx >> 6; nn = idx & 63; }
+      else { nn = idx >> 4; kk = idx & 15; }
+      const int gn = n0 + nn, gk2 = k0 + kk;
+      T w = T(0);
+      if (gn < d.N && gk2 < d.K)
+        w = d.transB ? B[(int64_t)gn * d.ldb + gk2] : B[(int64_t)gk2 * d.ldb + gn];
+      Bs[kk][nn] = w;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) {
+      T a[4], b[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = As[kk][tm + 16 * i];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) b[j] = Bs[kk][tn + 16 * j];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] += a[i] * b[j];
+    }
+    __syncthreads();
+  }
+  T *C = (T *)d.C;
+  const T al = T(d.alpha), be = T(d.beta);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int gm = m0 + tm + 16 * i;
+    if (gm >= d.M) continue;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int gn = n0 + tn + 16 * j;
+      if (gn >= d.N) continue;
+      T *c = C + (int64_t)gm * d.ldc + gn;
+      T v = al * acc[i][j];
+      if (d.beta != 0.0) v += be * (*c);
+      *c = v;
+    }
+  }
+}
+
+int launch_gemm(FType t, const GemmDesc *d_items, const int32_t *d_tile_start, int nitems,
+                int total_tiles, hipStream_t st) {
+  if (nitems <= 0 || total_tiles <= 0) return SPAND_OK;
+  if (t == FType::F64)
+    hipLaunchKernelGGL(k_gemm<double>, dim3(total_tiles), dim3(256), 0, st, d_items,
+                       d_tile_start, nitems);
+  else
+    hipLaunchKernelGGL(k_gemm<float>, dim3(total_tiles), dim3(256), 0, st, d_items,
+                       d_tile_start, nitems);
+  SP_HIP(hipGetLastError());
+  return SPAND_OK;
+}
+
+// ------------------------------------------------------------------ copies
+template <typename Ts, typename Td>
+__global__ __launch_bounds__(256) void k_copy(const CopyDesc *__restrict__ items) {
+  const CopyDesc d = items[blockIdx.x];
+  const Ts *src = (const Ts *)d.src;
+  Td *dst = (Td *)d.dst;
+  const int64_t total = (int64_t)d.rows * d.cols;
+  const Ts sc = Ts(d.scale);
+  for (int64_t idx = (int64_t)blockIdx.y * blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.y * blockDim.x) {
+    const int r = int(idx / d.cols), c = int(idx % d.cols);
+    const Ts v = d.trans ? src[(int64_t)c * d.lds + r] : src[(int64_t)r * d.lds + c];
+    dst[(int64_t)r * d.ldd + c] = Td(v * sc);
+  }
+}
+
+int launch_copy(FType t, int src_is_factor, const CopyDesc *d_items, int n, int64_t max_elems,
+                hipStream_t st) {
+  if (n <= 0) return SPAND_OK;
+  int gy = int(std::min<int64_t>(64, std::max<int64_t>(1, cdiv(max_elems, 256))));
+  dim3 grid(n, gy);
+  if (t == FType::F64) {
+    hipLaunchKernelGGL((k_copy<double, double>), grid, dim3(256), 0, st, d_items);
+  } else if (src_is_factor) {
+    hipLaunchKernelGGL((k_copy<float, float>), grid, dim3(256), 0, st, d_items);
+  } else {
+    hipLaunchKernelGGL((k_copy<double, float>), grid, dim3(256), 0, st, d_items);
+  }
+  SP_HIP(hipGetLastError());
+  return SPAND_OK;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_scale(const ScaleDesc *__restrict__ items) {
+  const ScaleDesc d = items[blockIdx.x];
+  T *A = (T *)d.A;
+  const T *rs = (const T *)d.rs;
+  const T *cs = (const T *)d.cs;
+  const int64_t total = (int64_t)d.rows * d.cols;
+  for (int64_t idx = (int64_t)blockIdx.y * blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.y * blockDim.x) {
+    const int r = int(idx / d.cols), c = int(idx % d.cols);
+    T v = A[(int64_t)r * d.ld + c];
+    if (rs) v *= rs[r];
+    if (cs) v *= cs[c];
+    A[(int64_t)r * d.ld + c] = v;
+  }
+}
+
+int launch_scale(FType t, const ScaleDesc *d_items, int n, hipStream_t st) {
+  if (n <= 0) return SPAND_OK;
+  dim3 grid(n, 16);
+  if (t == FType::F64)
+    hipLaunchKernelGGL(k_scale<double>, grid, dim3(256), 0, st, d_items);
+  else
+    hipLaunchKernelGGL(k_scale<float>, grid, dim3(256), 0, st, d_items);
+  SP_HIP(hipGetLastError());
+  return SPAND_OK;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_eye(const EyeDesc *__restrict__ items) {
+  const EyeDesc d = items[blockIdx.x];
+  T *A = (T *)d.A;
+  const int64_t total = (int64_t)d.n * d.n;
+  for (int64_t idx = (int64_t)blockIdx.y * blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.y * blockDim.x) {
+    const int r = int(idx / d.n), c = int(idx % d.n);
+    A[(int64_t)r * d.ld + c] = (r == c) ? T(1) : T(0);
+  }
+}
+
+int launch_eye(FType t, const EyeDesc *d_items, int n, int max_n, hipStream_t st) {
+  if (n <= 0) return SPAND_OK;
+  int gy = int(std::min<int64_t>(64, std::max<int64_t>(1, cdiv((int64_t)max_n * max_n, 256))));
+  dim3 grid(n, gy);
+  if (t == FType::F64)
+    hipLaunchKernelGGL(k_eye<double>, grid, dim3(256), 0, st, d_items);
+  else
+    hipLaunchKernelGGL(k_eye<float>, grid, dim3(256), 0, st, d_items);
+  SP_HIP(hipGetLastError());
+  return SPAND_OK;
+}
+
+// ------------------------------------------------------------------ elimination panel
+// One workgroup owns one matrix.  Row r of the panel lives in thread
+// r % ELIM_NT, slot r / ELIM_NT.  Virtual pivoting: rows are never swapped;
+// piv[k + c] records the row chosen for column k + c, and used[] marks rows
+// that already served as pivots.
+//   MODE 0 (Gauss-Jordan, pivoting): in-place inversion step; after all
+//          panels row piv[j] holds row j of the inverse with its columns in
+//          pivot order (undone by k_row_gather with colperm).
+//   MODE 1 (LU on [A | I], pivoting): eliminates only rows not yet used as
+//          pivots; on exit row piv[j] holds row j of U in the A part and row
+//          j of L^{-1} P^T in the identity part.
+//   MODE 2 (Gauss-Jordan, no pivoting): pivot of column j is row j.
+// The panel's effect on the other columns is the rank-w update
+//   A[:, rest] = A[:, rest] with rows piv zeroed + P * A_old[piv, rest]
+// where P (n x w) is E e_piv (E = product of the panel's elementary steps):
+// for Gauss-Jordan P is the final panel itself, for LU it is tracked in Y.
+template <typename T, int MODE>
+__global__ __launch_bounds__(ELIM_NT) void k_elim_panel(const ElimDesc *__restrict__ items, int k,
+                                                        int *__restrict__ flag) {
+  constexpr int NT = ELIM_NT, RPT = ELIM_RPT, NB = ELIM_NB;
+  const ElimDesc d = items[blockIdx.x];
+  const int n = d.n;
+  if (k >= n) return;
+  const int w = min(NB, n - k);
+  T *A = (T *)d.A;
+  T *P = (T *)d.P;
+  T *Tb = (T *)d.T;
+  const int64_t ld = d.ld;
+  const int tid = threadIdx.x;
+  __shared__ T prow_s[NB];
+  __shared__ T yrow_s[NB];
+  __shared__ double redv[NT / 64];
+  __shared__ int redi[NT / 64];
+  __shared__ int s_prow;
+  __shared__ int s_piv[NB];
+  T pan[RPT][NB];
+  T Y[RPT][NB];
+  bool usedf[RPT];
+#pragma unroll
+  for (int j = 0; j < RPT; ++j) {
+    const int r = tid + j * NT;
+    usedf[j] = false;
+#pragma unroll
+    for (int c = 0; c < NB; ++c) {
+      pan[j][c] = T(0);
+      Y[j][c] = T(0);
+    }
+    if (r < n) {
+#pragma unroll
+      for (int c = 0; c < NB; ++c)
+        if (c < w) pan[j][c] = A[(int64_t)r * ld + k + c];
+      if (MODE != 2) usedf[j] = d.used[r] != 0;
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < NB; ++c) {
+    if (c < w) {   // w is uniform over the workgroup
+    int prow;
+    if (MODE == 2) {
+      prow = k + c;
+    } else {
+      double bv = -1.0;
+      int bi = INT_MAX;
+#pragma unroll
+      for (int j = 0; j < RPT; ++j) {
+        const int r = tid + j * NT;
+        if (r < n && !usedf[j]) {
+          double v = fabs((double)pan[j][c]);
+          if (v > bv || (v == bv && r < bi)) { bv = v; bi = r; }
+        }
+      }
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        double ov = __shfl_xor(bv, o, 64);
+        int oi = __shfl_xor(bi, o, 64);
+        if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+      }
+      if ((tid & 63) == 0) { redv[tid >> 6] = bv; redi[tid >> 6] = bi; }
+      __syncthreads();
+      if (tid == 0) {
+        double v = redv[0];
+        int ii = redi[0];
+        for (int q = 1; q < NT / 64; ++q)
+          if (redv[q] > v || (redv[q] == v && redi[q] < ii)) { v = redv[q]; ii = redi[q]; }
+        s_prow = ii;
+      }
+      __syncthreads();
+      prow = s_prow;
+    }
+    if (prow % NT == tid) {
+      const int jj = prow / NT;
+#pragma unroll
+      for (int j = 0; j < RPT; ++j) {
+        if (j != jj) continue;
+        if (MODE == 1) Y[j][c] = T(1);
+#pragma unroll
+        for (int cc = 0; cc < NB; ++cc) {
+          prow_s[cc] = pan[j][cc];
+          yrow_s[cc] = Y[j][cc];
+        }
+        usedf[j] = true;
+      }
+      s_piv[c] = prow;
+    }
+    __syncthreads();
+    T p = prow_s[c];
+    if (p == T(0)) {
+      if (tid == 0) atomicOr(flag, 1);
+      p = T(1);
+    }
+    const T ip = T(1) / p;
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+      const int r = tid + j * NT;
+      if (r >= n) continue;
+      if (MODE != 1) {
+        if (r == prow) {
+#pragma unroll
+          for (int cc = 0; cc < NB; ++cc) pan[j][cc] = (cc == c) ? ip : prow_s[cc] * ip;
+        } else {
+          const T fp = pan[j][c] * ip;
+#pragma unroll
+          for (int cc = 0; cc < NB; ++cc)
+            pan[j][cc] = (cc == c) ? -fp : pan[j][cc] - fp * prow_s[cc];
+        }
+      } else {
+        if (usedf[j]) continue;      // pivot rows (earlier or now) stay as U rows
+        const T f = pan[j][c] * ip;
+#pragma unroll
+        for (int cc = 0; cc < NB; ++cc) {
+          if (cc > c) pan[j][cc] -= f * prow_s[cc];
+          if (cc <= c) Y[j][cc] -= f * yrow_s[cc];
+        }
+        pan[j][c] = T(0);
+      }
+    }
+    __syncthreads();
+    }
+  }
+  // write back panel, P, pivots and used flags
+#pragma unroll
+  for (int j = 0; j < RPT; ++j) {
+    const int r = tid + j * NT;
+    if (r >= n) continue;
+#pragma unroll
+    for (int cc = 0; cc < NB; ++cc) {
+      if (cc < w) A[(int64_t)r * ld + k + cc] = pan[j][cc];
+      P[(int64_t)r * NB + cc] = (cc < w) ? (MODE == 1 ? Y[j][cc] : pan[j][cc]) : T(0);
+    }
+    if (MODE != 2) d.used[r] = usedf[j] ? 1 : 0;
+  }
+  if (tid < w) d.piv[k + tid] = s_piv[tid];
+  // pivot rows of the non-panel columns -> T, then zero them in A.  The
+  // panel columns of T are zero so the update leaves the panel unchanged.
+  const int c0 = (MODE == 1) ? k : 0;
+  const int ncol = d.ncols - c0;
+  for (int idx = tid; idx < w * ncol; idx += NT) {
+    const int cq = idx / ncol;
+    const int col = c0 + idx % ncol;
+    const int64_t src = (int64_t)s_piv[cq] * ld + col;
+    if (col >= k && col < k + w) {
+      Tb[(int64_t)cq * ld + col] = T(0);
+    } else {
+      Tb[(int64_t)cq * ld + col] = A[src];
+      A[src] = T(0);
+    }
+  }
+}
+
+// A[:, c0:ncols] += P[:, 0:w] * T[0:w, c0:ncols]
+template <typename T>
+__global__ __launch_bounds__(256) void k_elim_update(const ElimDesc *__restrict__ items, int k,
+                                                     int lu_mode) {
+  const ElimDesc d = items[blockIdx.y];
+  const int n = d.n;
+  if (k >= n) return;
+  const int w = min(ELIM_NB, n - k);
+  const int c0 = lu_mode ? k : 0;
+  const int ncol = d.ncols - c0;
+  const int ntn = (ncol + 63) >> 6, ntm = (n + 63) >> 6;
+  const int t = blockIdx.x;
+  if (t >= ntm * ntn) return;
+  const int m0 = (t / ntn) * 64, n0 = c0 + (t % ntn) * 64;
+  __shared__ T Ps[ELIM_NB][65];
+  __shared__ T Ts[ELIM_NB][65];
+  const T *P = (const T *)d.P;
+  const T *Tb = (const T *)d.T;
+  T *A = (T *)d.A;
+  const int64_t ld = d.ld;
+  const int tid = threadIdx.x;
+  for (int idx = tid; idx < ELIM_NB * 64; idx += 256) {
+    const int mm = idx / ELIM_NB, kk = idx % ELIM_NB;
+    Ps[kk][mm] = (kk < w && m0 + mm < n) ? P[(int64_t)(m0 + mm) * ELIM_NB + kk] : T(0);
+    const int kk2 = idx / 64, nn = idx % 64;
+    Ts[kk2][nn] = (kk2 < w && n0 + nn < d.ncols) ? Tb[(int64_t)kk2 * ld + n0 + nn] : T(0);
+  }
+  __syncthreads();
+  const int tm = tid >> 4, tn = tid & 15;
+  T acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = T(0);
+#pragma unroll
+  for (int kk = 0; kk < ELIM_NB; ++kk) {
+    T a[4], b[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) a[i] = Ps[kk][tm + 16 * i];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) b[j] = Ts[kk][tn + 16 * j];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i][j] += a[i] * b[j];
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int gm = m0 + tm + 16 * i;
+    if (gm >= n) continue;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int gn = n0 + tn + 16 * j;
+      if (gn >= d.ncols) continue;
+      A[(int64_t)gm * ld + gn] += acc[i][j];
+    }
+  }
+}
+
+int launch_elim_step(FType t, const ElimDesc *d_items, int nactive, int k, int mode,
+                     int max_tiles, int *d_flag, hipStream_t st) {
+  if (nactive <= 0) return SPAND_OK;
+  const int lu = mode == 1;
+  if (t == FType::F64) {
+    if (mode == 0)
+      hipLaunchKernelGGL((k_elim_panel<double, 0>), dim3(nactive), dim3(ELIM_NT), 0, st, d_items, k, d_flag);
+    else if (mode == 1)
+      hipLaunchKernelGGL((k_elim_panel<double, 1>), dim3(nactive), dim3(ELIM_NT), 0, st, d_items, k, d_flag);
+    else
+      hipLaunchKernelGGL((k_elim_panel<double, 2>), dim3(nactive), dim3(ELIM_NT), 0, st, d_items, k, d_flag);
+    SP_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_elim_update<double>, dim3(max_tiles, nactive), dim3(256), 0, st, d_items, k, lu);
+  } else {
+    if (mode == 0)
+      hipLaunchKernelGGL((k_elim_panel<float, 0>), dim3(nactive), dim3(ELIM_NT), 0, st, d_items, k, d_flag);
+    else if (mode == 1)
+      hipLaunchKernelGGL((k_elim_panel<float, 1>), dim3(nactive), dim3(ELIM_NT), 0, st, d_items, k, d_flag);
+    else
+      hipLaunchKernelGGL((k_elim_panel<float, 2>), dim3(nactive), dim3(ELIM_NT), 0, st, d_items, k, d_flag);
+    SP_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_elim_update<float>, dim3(max_tiles, nactive), dim3(256), 0, st, d_items, k, lu);
+  }
+  SP_HIP(hipGetLastError());
+  return SPAND_OK;
+}
+
+// out[j, c] = src[piv[j], colperm ? pinv[c] : c + col_off],  j < n, c < cols
+template <typename T>
+__global__ __launch_bounds__(256) void k_row_gather(const RowGatherDesc *__restrict__ items) {
+  const RowGatherDesc d = items[blockIdx.x];
+  __shared__ int pinv[ELIM_MAXN];
+  if (d.colperm) {
+    for (int j = threadIdx.x; j < d.n; j += blockDim.x) pinv[d.piv[j]] = j;
+  }
+  __syncthreads();
+  const T *src = (const T *)d.src;
+  T *dst = (T *)d.dst;
+  for (int j = blockIdx.y; j < d.n; j += gridDim.y) {
+    const int64_t sr = (int64_t)d.piv[j] * d.lds;
+    for (int c = threadIdx.x; c < d.cols; c += blockDim.x) {
+      const int sc = d.colperm ? pinv[c] : c + d.col_off;
+      dst[(int64_t)j * d.ldd + c] = src[sr + sc];
+    }
+  }
+}
+
+int launch_row_gather(FType t, const RowGatherDesc *d_items, int n, int max_rows,
+                      hipStream_t st) {
+  if (n <= 0) return SPAND_OK;
+  dim3 grid(n, std::max(1, std::min(max_rows, 64)));
+  if (t == FType::F64)
+    hipLaunchKernelGGL(k_row_gather<double>, grid, dim3(256), 0, st, d_items);
+  else
+    hipLaunchKernelGGL(k_row_gather<float>, grid, dim3(256), 0, st, d_items);
+  SP_HIP(hipGetLastError());
+  return SPAND_OK;
+}
+
+// ------------------------------------------------------------------ level-0 Schur
+// target(b x b) -= A1 * Y * A2 for every item of a group, items in order.
+template <typename T>
+__global__ __launch_bounds__(256) void k_schur_elem(int bs, const double *__restrict__ bsr_val,
+                                                    const SchurGroup *__restrict__ groups,
+                                                    const SchurItem *__restrict__ items) {
+  const SchurGroup g = groups[blockIdx.x];
+  __shared__ T Xs[64][65];
+  __shared__ T Ys[64][65];
+  const int tid = threadIdx.x;
+  const int nq = (bs * bs + 255) / 256;
+  T *tg = (T *)g.target;
+  T acc[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int idx = tid + q * 256;
+    acc[q] = (q < nq && idx < bs * bs) ? tg[(int64_t)(idx / bs) * g.ldt + idx % bs] : T(0);
+  }
+  const int64_t b2 = (int64_t)bs * bs;
+  for (int it = g.item_begin; it < g.item_end; ++it) {
+    const SchurItem s = items[it];
+    const double *a1 = bsr_val + s.a1 * b2;
+    const double *a2 = bsr_val + s.a2 * b2;
+    const T *Y = (const T *)s.Y;
+    for (int idx = tid; idx < bs * bs; idx += 256) {
+      const int r = idx / bs, c = idx % bs;
+      Xs[r][c] = T(a1[idx]);
+      Ys[r][c] = Y[(int64_t)r * s.ldy + c];
+    }
+    __syncthreads();
+    T t1[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int idx = tid + q * 256;
+      T v = T(0);
+      if (q < nq && idx < bs * bs) {
+        const int r = idx / bs, c = idx % bs;
+        for (int kk = 0; kk < bs; ++kk) v += Xs[r][kk] * Ys[kk][c];
+      }
+      t1[q] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int idx = tid + q * 256;
+      if (q < nq && idx < bs * bs) Xs[idx / bs][idx % bs] = t1[q];
+    }
+    for (int idx = tid; idx < bs * bs; idx += 256) Ys[idx / bs][idx % bs] = T(a2[idx]);
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int idx = tid + q * 256;
+      if (q < nq && idx < bs * bs) {
+        const int r = idx / bs, c = idx % bs;
+        T v = T(0);
+        for (int kk = 0; kk < bs; ++kk) v += Xs[r][kk] * Ys[kk][c];
+        acc[q] -= v;
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int idx = tid + q * 256;
+    if (q < nq && idx < bs * bs) tg[(int64_t)(idx / bs) * g.ldt + idx % bs] = acc[q];
+  }
+}
+
+int launch_schur_elem(FType t, int bs, const double *bsr_val, const SchurGroup *d_groups,
+                      int ngroups, const SchurItem *d_items, hipStream_t st) {
+  if (ngroups <= 0) return SPAND_OK;
+  if (t == FType::F64)
+    hipLaunchKernelGGL(k_schur_elem<double>, dim3(ngroups), dim3(256), 0, st, bs, bsr_val,
+                       d_groups, d_items);
+  else
+    hipLaunchKernelGGL(k_schur_elem<float>, dim3(ngroups), dim3(256), 0, st, bs, bsr_val,
+                       d_groups, d_items);
+  SP_HIP(hipGetLastError());
+  return SPAND_OK;
+}
+
+// ------------------------------------------------------------------ QRCP
+// Rank-revealing QR with column pivoting of W (m x nc, row-major), one
+// workgroup per interface.  Pivoted Gram-Schmidt with re-orthogonalisation
+// (equal in exact arithmetic to Householder QRCP: same pivots, same |R_ii|,
+// same leading columns of Q up to sign); column norms are downdated with the
+// LAPACK-style safeguard and recomputed when cancellation is detected.
+// Stops at the first |R_ii| <= eps |R_00|.  The kept orthonormal columns are
+// then completed to a full orthogonal Q by Householder QR of themselves.
+template <typename T>
+__global__ __launch_bounds__(256) void k_qrcp(const QrcpDesc *__restrict__ items, double eps,
+                                              int force_full) {
+  const QrcpDesc d = items[blockIdx.x];
+  const int m = d.m, nc = d.ncols;
+  const T *W = (const T *)d.W;
+  T *Q = (T *)d.Q;
+  T *V = (T *)d.V;
+  double *vn1 = d.vn1, *vn2 = d.vn2;
+  int *sel = d.sel;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  __shared__ double u[QRCP_MAXM];
+  __shared__ double cbuf[QRCP_MAXM];
+  __shared__ double red[16];
+  __shared__ double cw[4][QRCP_MAXM];
+  __shared__ int s_j;
+  __shared__ int s_nflag;
+  const double tol3z = 1.4901161193847656e-08;  // sqrt(2^-52)
+  for (int j = tid; j < nc; j += 256) {
+    double s = 0.0;
+    for (int r = 0; r < m; ++r) {
+      const double v = double(W[(int64_t)r * nc + j]);
+      s += v * v;
+    }
+    vn1[j] = sqrt(s);
+    vn2[j] = vn1[j];
+    sel[j] = 0;
+  }
+  __syncthreads();
+  double R00 = 0.0;
+  int k = 0;
+  const int imax = min(m, nc);
+  for (int i = 0; i < imax; ++i) {
+    // ---- pivot: largest remaining column norm, ties -> smallest index
+    double bv = -1.0;
+    int bi = INT_MAX;
+    for (int j = tid; j < nc; j += 256) {
+      if (sel[j]) continue;
+      const double v = vn1[j];
+      if (v > bv || (v == bv && j < bi)) { bv = v; bi = j; }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      double ov = __shfl_xor(bv, o, 64);
+      int oi = __shfl_xor(bi, o, 64);
+      if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+    }
+    __shared__ double rv[4];
+    __shared__ int ri[4];
+    if (lane == 0) { rv[wid] = bv; ri[wid] = bi; }
+    __syncthreads();
+    if (tid == 0) {
+      double v = rv[0];
+      int ii = ri[0];
+      for (int q = 1; q < 4; ++q)
+        if (rv[q] > v || (rv[q] == v && ri[q] < ii)) { v = rv[q]; ii = ri[q]; }
+      s_j = ii;
+    }
+    __syncthreads();
+    const int js = s_j;
+    if (js == INT_MAX) break;
+    for (int r = tid; r < m; r += 256) u[r] = double(W[(int64_t)r * nc + js]);
+    __syncthreads();
+    // ---- two classical Gram-Schmidt passes against q_0..q_{i-1}
+    for (int pass = 0; pass < 2 && i > 0; ++pass) {
+      for (int tq = tid; tq < i; tq += 256) {
+        double s = 0.0;
+        for (int r = 0; r < m; ++r) s += double(Q[(int64_t)r * m + tq]) * u[r];
+        cbuf[tq] = s;
+      }
+      __syncthreads();
+      for (int r = tid; r < m; r += 256) {
+        double s = 0.0;
+        for (int tq = 0; tq < i; ++tq) s += double(Q[(int64_t)r * m + tq]) * cbuf[tq];
+        u[r] -= s;
+      }
+      __syncthreads();
+    }
+    double ss = 0.0;
+    for (int r = tid; r < m; r += 256) ss += u[r] * u[r];
+    const double nrm = sqrt(block_sum(ss, red));
+    if (i == 0) R00 = nrm;
+    const bool stop = force_full ? (nrm == 0.0) : (nrm == 0.0 || nrm <= eps * R00);
+    if (stop) break;
+    const double inv = 1.0 / nrm;
+    __syncthreads();
+    for (int r = tid; r < m; r += 256) {
+      u[r] *= inv;
+      Q[(int64_t)r * m + i] = T(u[r]);
+    }
+    if (tid == 0) {
+      sel[js] = 1;
+      s_nflag = 0;
+    }
+    __syncthreads();
+    // ---- row i of R for all remaining columns; downdate their norms
+    for (int j = tid; j < nc; j += 256) {
+      if (sel[j]) continue;
+      double s = 0.0;
+      for (int r = 0; r < m; ++r) s += u[r] * double(W[(int64_t)r * nc + j]);
+      const double a = vn1[j];
+      if (a != 0.0) {
+        double temp = fabs(s) / a;
+        temp = fmax(0.0, (1.0 + temp) * (1.0 - temp));
+        const double t2 = temp * (a / vn2[j]) * (a / vn2[j]);
+        if (t2 <= tol3z) {
+          vn1[j] = -1.0;          // recompute below
+          atomicAdd(&s_nflag, 1);
+        } else {
+          vn1[j] = a * sqrt(temp);
+        }
+      }
+    }
+    __syncthreads();
+    if (s_nflag > 0) {
+      // exact residual norm of flagged columns against q_0..q_i (one wave each)
+      for (int j = wid; j < nc; j += 4) {
+        if (sel[j] || vn1[j] >= 0.0) continue;
+        for (int tq = lane; tq <= i; tq += 64) {
+          double s = 0.0;
+          for (int r = 0; r < m; ++r) s += double(Q[(int64_t)r * m + tq]) * double(W[(int64_t)r * nc + j]);
+          cw[wid][tq] = s;
+        }
+        double acc = 0.0;
+        for (int r = lane; r < m; r += 64) {
+          double s = double(W[(int64_t)r * nc + j]);
+          for (int tq = 0; tq <= i; ++tq) s -= double(Q[(int64_t)r * m + tq]) * cw[wid][tq];
+          acc += s * s;
+        }
+        acc = wave_sum(acc);
+        if (lane == 0) {
+          vn1[j] = sqrt(acc);
+          vn2[j] = vn1[j];
+        }
+      }
+      __syncthreads();
+    }
+    k = i + 1;
+  }
+  __syncthreads();
+  // ---- complete Q: Householder QR of Q[:, 0:k] -> reflectors V, tau
+  for (int t = 0; t < k; ++t) {
+    double ss2 = 0.0;
+    for (int r = t + tid; r < m; r += 256) {
+      const double v = double(Q[(int64_t)r * m + t]);
+      ss2 += v * v;
+    }
+    const double sig = sqrt(block_sum(ss2, red));
+    const double alpha = double(Q[(int64_t)t * m + t]);
+    double tau = 0.0, scal = 0.0;
+    if (sig > 0.0) {
+      const double beta = alpha >= 0.0 ? -sig : sig;
+      tau = (beta - alpha) / beta;
+      scal = 1.0 / (alpha - beta);
+    }
+    __syncthreads();
+    for (int r = t + tid; r < m; r += 256) {
+      const double v = (r == t) ? 1.0 : double(Q[(int64_t)r * m + t]) * scal;
+      V[(int64_t)t * m + r] = T(v);
+    }
+    if (tid == 0) d.tau[t] = tau;
+    __syncthreads();
+    // apply H_t to columns t+1..k-1 (threads over columns)
+    for (int c = t + 1 + tid; c < k; c += 256) {
+      double s = 0.0;
+      for (int r = t; r < m; ++r) s += double(V[(int64_t)t * m + r]) * double(Q[(int64_t)r * m + c]);
+      s *= tau;
+      for (int r = t; r < m; ++r) Q[(int64_t)r * m + c] = T(double(Q[(int64_t)r * m + c]) - s * double(V[(int64_t)t * m + r]));
+    }
+    __syncthreads();
+  }
+  // ---- Q = H_0 H_1 ... H_{k-1} (applied to I from the last reflector)
+  for (int idx = tid; idx < m * m; idx += 256) Q[idx] = T((idx / m) == (idx % m) ? 1.0 : 0.0);
+  __syncthreads();
+  for (int t = k - 1; t >= 0; --t) {
+    const double tau = d.tau[t];
+    for (int c = tid; c < m; c += 256) {
+      double s = 0.0;
+      for (int r = t; r < m; ++r) s += double(V[(int64_t)t * m + r]) * double(Q[(int64_t)r * m + c]);
+      s *= tau;
+      if (s != 0.0)
+        for (int r = t; r < m; ++r) Q[(int64_t)r * m + c] = T(double(Q[(int64_t)r * m + c]) - s * double(V[(int64_t)t * m + r]));
+    }
+    __syncthreads();
+  }
+  if (tid == 0) *d.k_out = force_full ? m : k;
+}
+
+int launch_qrcp(FType t, const QrcpDesc *d_items, int n, double eps, int force_full,
+                hipStream_t st) {
+  if (n <= 0) return SPAND_OK;
+  if (t == FType::F64)
+    hipLaunchKernelGGL(k_qrcp<double>, dim3(n), dim3(256), 0, st, d_items, eps, force_full);
+  else
+    hipLaunchKernelGGL(k_qrcp<float>, dim3(n), dim3(256), 0, st, d_items, eps, force_full);
+  SP_HIP(hipGetLastError());
+  return SPAND_OK;
+}
+
+}  // namespace spand
+
+namespace spand {
+template <typename T>
+__global__ void k_diag_split(const DiagDesc *__restrict__ items) {
+  const DiagDesc d = items[blockIdx.x];
+  const T *U = (const T *)d.U;
+  T *S = (T *)d.S;
+  T *Si = (T *)d.Si;
+  for (int j = threadIdx.x; j < d.n; j += blockDim.x) {
+    const T s = sqrt(fabs(U[(int64_t)j * d.ld + j]));
+    S[j] = s;
+    Si[j] = s != T(0) ? T(1) / s : T(0);
+  }
+}
+
+int launch_diag_split(FType t, const DiagDesc *d_items, int n, hipStream_t st) {
+  if (n <= 0) return SPAND_OK;
+  if (t == FType::F64)
+    hipLaunchKernelGGL(k_diag_split<double>, dim3(n), dim3(256), 0, st, d_items);
+  else
+    hipLaunchKernelGGL(k_diag_split<float>, dim3(n), dim3(256), 0, st, d_items);
+  SP_HIP(hipGetLastError());
+  return SPAND_OK;
+}
+}  // namespace spand

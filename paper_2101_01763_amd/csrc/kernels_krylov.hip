@@ -1,0 +1,215 @@
+// Small dense kernels of the s-step GMRES (paper Algorithm 2): Cholesky of
+// the s x s Gram matrix (CholQR), combination of the two CGS/CholQR passes,
+// Hessenberg reconstruction from the Newton change-of-basis matrix, Givens
+// rotations and residual estimates, least-squares solve; plus a
+// deterministic two-stage dot product.
+#include "kernels_vec.h"
+
+namespace spand {
+
+// ---------------------------------------------------------------- dot
+__global__ __launch_bounds__(256) void k_dot_part(int64_t N, const double *__restrict__ x,
+                                                  const double *__restrict__ y,
+                                                  double *__restrict__ part) {
+  __shared__ double red[4];
+  double acc = 0.0;
+  const int64_t r0 = (int64_t)blockIdx.x * 4096;
+  const int64_t r1 = std::min<int64_t>(N, r0 + 4096);
+  for (int64_t r = r0 + threadIdx.x; r < r1; r += 256) acc += x[r] * y[r];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+__global__ __launch_bounds__(256) void k_dot_reduce(const double *__restrict__ part, int n,
+                                                    double *__restrict__ out, int take_sqrt) {
+  __shared__ double red[256];
+  double acc = 0.0;
+  // fixed partition -> deterministic
+  for (int i = threadIdx.x; i < n; i += 256) acc += part[i];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = take_sqrt ? sqrt(red[0]) : red[0];
+}
+
+int launch_dot(int64_t N, const double *x, const double *y, double *part, double *out,
+               int take_sqrt, hipStream_t st) {
+  const int nb = int(std::max<int64_t>(1, cdiv(N, 4096)));
+  hipLaunchKernelGGL(k_dot_part, dim3(nb), dim3(256), 0, st, N, x, y, part);
+  SP_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_dot_reduce, dim3(1), dim3(256), 0, st, part, nb, out, take_sqrt);
+  SP_HIP(hipGetLastError());
+  return SPAND_OK;
+}
+
+// ---------------------------------------------------------------- cycle init
+__global__ void k_init_cycle(KrylovDev *K, int m) {
+  for (int i = threadIdx.x; i < (KRY_MMAX + 1) * KRY_MMAX; i += blockDim.x) {
+    K->H[i] = 0.0;
+    K->Rm[i] = 0.0;
+  }
+  for (int i = threadIdx.x; i <= KRY_MMAX; i += blockDim.x) K->g[i] = 0.0;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    K->g[0] = K->scal[0];
+    K->bad = 0;
+  }
+}
+
+int kry_init_cycle(KrylovDev *K, int m, hipStream_t st) {
+  hipLaunchKernelGGL(k_init_cycle, dim3(1), dim3(256), 0, st, K, m);
+  SP_HIP(hipGetLastError());
+  return SPAND_OK;
+}
+
+// ---------------------------------------------------------------- Cholesky
+// G = T^T T, T upper (row-major s x s).  Non-SPD -> K->bad = 1.
+__global__ void k_chol(KrylovDev *K, int s, const double *G, double *T) {
+  if (threadIdx.x != 0) return;
+  for (int i = 0; i < s * s; ++i) T[i] = 0.0;
+  for (int j = 0; j < s; ++j) {
+    double d = G[j * s + j];
+    for (int k = 0; k < j; ++k) d -= T[k * s + j] * T[k * s + j];
+    if (!(d > 0.0)) {
+      K->bad = 1;
+      for (int i = 0; i < s; ++i) T[i * s + i] = 1.0;
+      return;
+    }
+    const double tjj = sqrt(d);
+    T[j * s + j] = tjj;
+    for (int c = j + 1; c < s; ++c) {
+      double v = G[j * s + c];
+      for (int k = 0; k < j; ++k) v -= T[k * s + j] * T[k * s + c];
+      T[j * s + c] = v / tjj;
+    }
+  }
+}
+
+int kry_chol(KrylovDev *K, int s, double *G, double *T, hipStream_t st) {
+  hipLaunchKernelGGL(k_chol, dim3(1), dim3(64), 0, st, K, s, G, T);
+  SP_HIP(hipGetLastError());
+  return SPAND_OK;
+}
+
+// ---------------------------------------------------------------- Givens
+__device__ void givens_column(KrylovDev *K, int c) {
+  // rotate column c of H into Rm using the previous rotations (in place)
+  const int ld = KRY_MMAX;
+  for (int i = 0; i <= c + 1; ++i) K->Rm[i * ld + c] = K->H[i * ld + c];
+  for (int i = 0; i < c; ++i) {
+    const double hi = K->Rm[i * ld + c], hn = K->Rm[(i + 1) * ld + c];
+    K->Rm[i * ld + c] = K->cs[i] * hi + K->sn[i] * hn;
+    K->Rm[(i + 1) * ld + c] = -K->sn[i] * hi + K->cs[i] * hn;
+  }
+  const double a = K->Rm[c * ld + c], b = K->Rm[(c + 1) * ld + c];
+  double cc = 1.0, ss = 0.0, r = a;
+  if (b != 0.0) {
+    r = hypot(a, b);
+    cc = a / r;
+    ss = b / r;
+  }
+  K->cs[c] = cc;
+  K->sn[c] = ss;
+  K->Rm[c * ld + c] = r;
+  K->Rm[(c + 1) * ld + c] = 0.0;
+  K->g[c + 1] = -ss * K->g[c];
+  K->g[c] = cc * K->g[c];
+  K->est[c] = fabs(K->g[c + 1]);
+}
+
+__global__ void k_givens_col(KrylovDev *K, int j) {
+  if (threadIdx.x == 0) givens_column(K, j);
+}
+
+int kry_givens_col(KrylovDev *K, int j, hipStream_t st) {
+  hipLaunchKernelGGL(k_givens_col, dim3(1), dim3(64), 0, st, K, j);
+  SP_HIP(hipGetLastError());
+  return SPAND_OK;
+}
+
+// ---------------------------------------------------------------- block finish
+// R_a = R1 + R2 T1, R_b = T2 T1;  H[:, j:j+s] = (Rhat Bbar - [H Ctop; 0]) T^{-1}
+// with Rhat = [[e_j, R_a], [0, R_b]], Ctop = Rhat[0:j, 0:s], T = Rhat[j:j+s, 0:s];
+// then Givens rotations of the new columns.
+__global__ __launch_bounds__(256) void k_block_finish(KrylovDev *K, int j, int s) {
+  __shared__ double Ra[TS_MAXA * TS_MAXS];
+  __shared__ double Rb[TS_MAXS * TS_MAXS];
+  __shared__ double Rhat[TS_MAXA * (TS_MAXS + 1)];
+  const int tid = threadIdx.x;
+  const int a = j + 1, nr = j + 1 + s, w = s + 1, ld = KRY_MMAX;
+  if (K->bad) return;
+  for (int idx = tid; idx < a * s; idx += blockDim.x) {
+    const int r = idx / s, c = idx % s;
+    double v = K->R1[r * s + c];
+    for (int q = 0; q <= c; ++q) v += K->R2[r * s + q] * K->T1[q * s + c];
+    Ra[idx] = v;
+  }
+  for (int idx = tid; idx < s * s; idx += blockDim.x) {
+    const int r = idx / s, c = idx % s;
+    double v = 0.0;
+    for (int q = r; q <= c; ++q) v += K->T2[r * s + q] * K->T1[q * s + c];
+    Rb[idx] = (c >= r) ? v : 0.0;
+  }
+  __syncthreads();
+  for (int idx = tid; idx < nr * w; idx += blockDim.x) {
+    const int r = idx / w, c = idx % w;
+    double v = 0.0;
+    if (c == 0) v = (r == j) ? 1.0 : 0.0;
+    else if (r < a) v = Ra[r * s + c - 1];
+    else v = Rb[(r - a) * s + c - 1];
+    Rhat[idx] = v;
+  }
+  __syncthreads();
+  // one thread per output row
+  for (int r = tid; r < nr; r += blockDim.x) {
+    double rb[TS_MAXS];
+    for (int c = 0; c < s; ++c) {
+      double v = 0.0;
+      for (int q = 0; q < w; ++q) v += Rhat[r * w + q] * K->Bb[q * s + c];
+      if (j > 0 && r <= j)
+        for (int i = 0; i < j; ++i) v -= K->H[r * ld + i] * Rhat[i * w + c];
+      rb[c] = v;
+    }
+    // X T = rb, T[p][c] = Rhat[(j+p)*w + c], upper triangular
+    for (int c = 0; c < s; ++c) {
+      double v = rb[c];
+      for (int p = 0; p < c; ++p) v -= rb[p] * Rhat[(j + p) * w + c];
+      rb[c] = v / Rhat[(j + c) * w + c];
+    }
+    for (int c = 0; c < s; ++c) K->H[r * ld + j + c] = rb[c];
+  }
+  __syncthreads();
+  if (tid == 0)
+    for (int c = j; c < j + s; ++c) givens_column(K, c);
+}
+
+int kry_block_finish(KrylovDev *K, int j, int s, hipStream_t st) {
+  hipLaunchKernelGGL(k_block_finish, dim3(1), dim3(256), 0, st, K, j, s);
+  SP_HIP(hipGetLastError());
+  return SPAND_OK;
+}
+
+// ---------------------------------------------------------------- least squares
+__global__ void k_lsq(KrylovDev *K, int k) {
+  if (threadIdx.x != 0) return;
+  const int ld = KRY_MMAX;
+  for (int i = k - 1; i >= 0; --i) {
+    double v = K->g[i];
+    for (int c = i + 1; c < k; ++c) v -= K->Rm[i * ld + c] * K->y[c];
+    K->y[i] = v / K->Rm[i * ld + i];
+  }
+}
+
+int kry_lsq(KrylovDev *K, int k, hipStream_t st) {
+  hipLaunchKernelGGL(k_lsq, dim3(1), dim3(64), 0, st, K, k);
+  SP_HIP(hipGetLastError());
+  return SPAND_OK;
+}
+
+}  // namespace spand

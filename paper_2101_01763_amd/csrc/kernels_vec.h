@@ -1,0 +1,55 @@
+// Launch wrappers of the memory-bound and Krylov kernels.
+#pragma once
+#include "internal.h"
+
+namespace spand {
+
+constexpr int GEMV_MAXC = 2048;   // largest cluster handled by the sweep kernels
+constexpr int PULL_MAXR = 2048;
+constexpr int TS_CHUNK = 512;     // rows per partial Gram block
+constexpr int TS_MAXS = 8;        // largest s
+constexpr int TS_MAXA = 160;      // largest restart + s + 1
+
+int launch_pull2(FType t, const PullGroup *d_groups, int ngroups, const PullItem *d_items,
+                 const double *in, double *out, double alpha, double beta, hipStream_t st);
+int launch_bsr_transpose(const spand_bsr_t &A, double *outv, int *d_flag, hipStream_t st);
+int launch_pattern_outer(const spand_bsr_t &P, const double *u, const double *v, double alpha,
+                         double *out, hipStream_t st);
+int vec_fill(double *x, int64_t n, double v, hipStream_t st);
+int vec_iota(int32_t *x, int64_t n, hipStream_t st);
+int vec_axpby(int64_t n, const double *x, double *y, double ca, const double *pa, int inva,
+              double cb, hipStream_t st);
+int launch_gram(int64_t N, const double *X, int64_t ldx, int a, const double *W, int64_t ldw,
+                int s, double *part, double *out, int ldo, hipStream_t st);
+int launch_ts_update(int64_t N, const double *X, int64_t ldx, int a, const double *R, int ldr,
+                     double *W, int64_t ldw, int s, hipStream_t st);
+int launch_ts_trsm(int64_t N, double *W, int64_t ldw, int s, const double *T, const int *bad,
+                   hipStream_t st);
+int launch_ts_gemv(int64_t N, const double *X, int64_t ldx, int k, const double *c, double *y,
+                   hipStream_t st);
+
+// ---- small dense state of the s-step method (device, one workgroup)
+constexpr int KRY_MMAX = 128;     // largest restart length
+struct KrylovDev {
+  double H[(KRY_MMAX + 1) * KRY_MMAX];   // row-major (m+1) x m, ld = KRY_MMAX
+  double Rm[(KRY_MMAX + 1) * KRY_MMAX];  // Givens-rotated H (same layout)
+  double cs[KRY_MMAX], sn[KRY_MMAX], g[KRY_MMAX + 1];
+  double y[KRY_MMAX];
+  double est[KRY_MMAX];                  // |g_{c+1}| after column c
+  double R1[TS_MAXA * TS_MAXS], R2[TS_MAXA * TS_MAXS];
+  double G[TS_MAXS * TS_MAXS], T1[TS_MAXS * TS_MAXS], T2[TS_MAXS * TS_MAXS];
+  double Bb[(TS_MAXS + 1) * TS_MAXS];
+  double scal[8];                        // [0] beta / norms
+  int bad;                               // CholQR breakdown flag
+  int pad;
+};
+
+int kry_init_cycle(KrylovDev *K, int m, hipStream_t st);                  // g = beta e0 (beta in scal[0])
+int kry_chol(KrylovDev *K, int s, double *G, double *T, hipStream_t st);  // T = chol(G)
+int kry_block_finish(KrylovDev *K, int j, int s, hipStream_t st);         // R, Hessenberg, Givens
+int kry_givens_col(KrylovDev *K, int j, hipStream_t st);                  // column j (MGS steps)
+int kry_lsq(KrylovDev *K, int k, hipStream_t st);                         // y from Rm, g
+int launch_dot(int64_t N, const double *x, const double *y, double *part, double *out,
+               int take_sqrt, hipStream_t st);
+
+}  // namespace spand

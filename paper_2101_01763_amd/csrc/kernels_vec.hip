@@ -1,0 +1,457 @@
+// Memory-bound kernels: preconditioner sweeps (batched GEMV and pull
+// GEMV over slot lists), BSR SpMV (Algorithms 1/2, line "SpMV") with the
+// Newton-basis shift fused in, and the tall-skinny pieces of the s-step
+// orthogonalisation (Gram matrices, block updates, triangular scaling).
+#include <climits>
+
+#include "internal.h"
+#include "kernels_vec.h"
+
+namespace spand {
+
+template <typename T>
+__device__ inline T wsum(T v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// ------------------------------------------------------------------ GEMV
+// out[oslot[r]] = beta*out[oslot[r]] + alpha * sum_c op(A)(r, c) in[islot[c]]
+// One workgroup per item; the input is staged in LDS first, so in == out
+// with identical slot lists is safe (slot lists of different items are
+// disjoint).
+template <typename T>
+__global__ __launch_bounds__(256) void k_gemv(const GemvDesc *__restrict__ items,
+                                              const double *__restrict__ in,
+                                              double *__restrict__ out, double alpha,
+                                              double beta) {
+  const GemvDesc d = items[blockIdx.x];
+  __shared__ double xs[GEMV_MAXC];
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  for (int c = tid; c < d.cols; c += 256) xs[c] = in[d.islot[c]];
+  __syncthreads();
+  const T *A = (const T *)d.A;
+  if (!d.trans) {
+    for (int r = wid; r < d.rows; r += 4) {
+      const T *row = A + (int64_t)r * d.lda;
+      T acc = T(0);
+      for (int c = lane; c < d.cols; c += 64) acc += row[c] * T(xs[c]);
+      acc = wsum(acc);
+      if (lane == 0) {
+        const int o = d.oslot[r];
+        double v = alpha * double(acc);
+        if (beta != 0.0) v += beta * out[o];
+        out[o] = v;
+      }
+    }
+  } else {
+    for (int r = tid; r < d.rows; r += 256) {
+      T acc = T(0);
+      for (int c = 0; c < d.cols; ++c) acc += A[(int64_t)c * d.lda + r] * T(xs[c]);
+      const int o = d.oslot[r];
+      double v = alpha * double(acc);
+      if (beta != 0.0) v += beta * out[o];
+      out[o] = v;
+    }
+  }
+}
+
+int launch_gemv(FType t, const GemvDesc *d_items, int n, const double *in, double *out,
+                double alpha, double beta, int /*max_cols*/, hipStream_t st) {
+  if (n <= 0) return SPAND_OK;
+  if (t == FType::F64)
+    hipLaunchKernelGGL(k_gemv<double>, dim3(n), dim3(256), 0, st, d_items, in, out, alpha, beta);
+  else
+    hipLaunchKernelGGL(k_gemv<float>, dim3(n), dim3(256), 0, st, d_items, in, out, alpha, beta);
+  SP_HIP(hipGetLastError());
+  return SPAND_OK;
+}
+
+// ------------------------------------------------------------------ pull
+// out[oslot[r]] = beta*out[oslot[r]] + alpha * sum_items op(B_i) in[islot_i]
+// One workgroup per group (output cluster), items accumulated in order.
+template <typename T>
+__global__ __launch_bounds__(256) void k_pull(const PullGroup *__restrict__ groups,
+                                              const PullItem *__restrict__ items,
+                                              const double *__restrict__ in,
+                                              double *__restrict__ out, double alpha,
+                                              double beta) {
+  const PullGroup g = groups[blockIdx.x];
+  __shared__ double acc[PULL_MAXR];
+  __shared__ double xs[GEMV_MAXC];
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  for (int r = tid; r < g.rows; r += 256) acc[r] = 0.0;
+  for (int it = g.item_begin; it < g.item_end; ++it) {
+    const PullItem p = items[it];
+    __syncthreads();
+    for (int c = tid; c < p.cols; c += 256) xs[c] = in[p.islot[c]];
+    __syncthreads();
+    const T *B = (const T *)p.B;
+    if (!p.trans) {
+      for (int r = wid; r < p.rows; r += 4) {
+        const T *row = B + (int64_t)r * p.ldb;
+        T a = T(0);
+        for (int c = lane; c < p.cols; c += 64) a += row[c] * T(xs[c]);
+        a = wsum(a);
+        if (lane == 0) acc[r] += double(a);
+      }
+    } else {
+      for (int r = tid; r < p.rows; r += 256) {
+        T a = T(0);
+        for (int c = 0; c < p.cols; ++c) a += B[(int64_t)c * p.ldb + r] * T(xs[c]);
+        acc[r] += double(a);
+      }
+    }
+  }
+  __syncthreads();
+  for (int r = tid; r < g.rows; r += 256) {
+    const int o = g.oslot[r];
+    double v = alpha * acc[r];
+    if (beta != 0.0) v += beta * out[o];
+    out[o] = v;
+  }
+}
+
+int launch_pull2(FType t, const PullGroup *d_groups, int ngroups, const PullItem *d_items,
+                 const double *in, double *out, double alpha, double beta, hipStream_t st) {
+  if (ngroups <= 0) return SPAND_OK;
+  if (t == FType::F64)
+    hipLaunchKernelGGL(k_pull<double>, dim3(ngroups), dim3(256), 0, st, d_groups, d_items, in,
+                       out, alpha, beta);
+  else
+    hipLaunchKernelGGL(k_pull<float>, dim3(ngroups), dim3(256), 0, st, d_groups, d_items, in,
+                       out, alpha, beta);
+  SP_HIP(hipGetLastError());
+  return SPAND_OK;
+}
+
+int launch_pull(FType t, const PullGroup *d_groups, int ngroups, const PullItem *d_items,
+                const double *in, double *out, double alpha, hipStream_t st) {
+  return launch_pull2(t, d_groups, ngroups, d_items, in, out, alpha, 1.0, st);
+}
+
+// ------------------------------------------------------------------ SpMV
+// y = alpha*A x + beta*y + gz*z + gw*w  (row-major b x b BSR blocks).
+// 8 lanes per scalar row, 16-byte loads: one instruction of a lane group
+// reads 128 contiguous bytes of the row segment.
+__global__ __launch_bounds__(256) void k_spmv(int n_brows, int bs, const int32_t *__restrict__ rowptr,
+                                              const int32_t *__restrict__ colind,
+                                              const double *__restrict__ val,
+                                              const double *__restrict__ x, double alpha,
+                                              double beta, double *__restrict__ y,
+                                              const double *__restrict__ z, double gz,
+                                              const double *__restrict__ w, double gw) {
+  const int64_t N = (int64_t)n_brows * bs;
+  const int64_t R = (int64_t)blockIdx.x * 32 + (threadIdx.x >> 3);
+  const int sub = threadIdx.x & 7;
+  double acc = 0.0;
+  if (R < N) {
+    const int I = int(R / bs), r = int(R % bs);
+    const int64_t b2 = (int64_t)bs * bs;
+    for (int t = rowptr[I]; t < rowptr[I + 1]; ++t) {
+      const double *rowv = val + (int64_t)t * b2 + (int64_t)r * bs;
+      const double *xv = x + (int64_t)colind[t] * bs;
+      for (int c = sub * 2; c < bs; c += 16) {
+        const double2 a = *reinterpret_cast<const double2 *>(rowv + c);
+        acc += a.x * xv[c] + a.y * xv[c + 1];
+      }
+    }
+  }
+  acc += __shfl_xor(acc, 4, 64);
+  acc += __shfl_xor(acc, 2, 64);
+  acc += __shfl_xor(acc, 1, 64);
+  if (R < N && sub == 0) {
+    double v = alpha * acc;
+    if (beta != 0.0) v += beta * y[R];
+    if (z) v += gz * z[R];
+    if (w) v += gw * w[R];
+    y[R] = v;
+  }
+}
+
+int launch_spmv(const spand_bsr_t &A, int transpose, double alpha, const double *x, double beta,
+                double *y, const double *z, double gz, const double *w, double gw,
+                hipStream_t st) {
+  (void)transpose;  // transposed products use an explicitly transposed copy
+  const int64_t N = (int64_t)A.n_brows * A.bs;
+  if (N == 0) return SPAND_OK;
+  const int64_t nb = cdiv(N, 32);
+  hipLaunchKernelGGL(k_spmv, dim3((unsigned)nb), dim3(256), 0, st, A.n_brows, A.bs, A.d_rowptr,
+                     A.d_colind, A.d_val, x, alpha, beta, y, z, gz, w, gw);
+  SP_HIP(hipGetLastError());
+  return SPAND_OK;
+}
+
+// transposed copy: block t = (I, J) goes to the position of (J, I),
+// transposed.  Missing mirror block -> *flag = 1 (pattern not symmetric).
+__global__ __launch_bounds__(256) void k_bsr_transpose(int n_brows, int bs,
+                                                       const int32_t *__restrict__ rowptr,
+                                                       const int32_t *__restrict__ colind,
+                                                       const double *__restrict__ val,
+                                                       double *__restrict__ outv,
+                                                       int *__restrict__ flag) {
+  const int I = blockIdx.x;
+  if (I >= n_brows) return;
+  const int64_t b2 = (int64_t)bs * bs;
+  for (int t = rowptr[I]; t < rowptr[I + 1]; ++t) {
+    const int J = colind[t];
+    int lo = rowptr[J], hi = rowptr[J + 1] - 1, pos = -1;
+    while (lo <= hi) {
+      const int mid = (lo + hi) >> 1;
+      const int c = colind[mid];
+      if (c == I) { pos = mid; break; }
+      if (c < I) lo = mid + 1; else hi = mid - 1;
+    }
+    if (pos < 0) {
+      if (threadIdx.x == 0) atomicOr(flag, 1);
+      continue;
+    }
+    const double *src = val + (int64_t)t * b2;
+    double *dst = outv + (int64_t)pos * b2;
+    for (int idx = threadIdx.x; idx < bs * bs; idx += 256) {
+      const int r = idx / bs, c = idx % bs;
+      dst[(int64_t)c * bs + r] = src[idx];
+    }
+  }
+}
+
+int launch_bsr_transpose(const spand_bsr_t &A, double *outv, int *d_flag, hipStream_t st) {
+  if (A.n_brows <= 0) return SPAND_OK;
+  hipLaunchKernelGGL(k_bsr_transpose, dim3(A.n_brows), dim3(256), 0, st, A.n_brows, A.bs,
+                     A.d_rowptr, A.d_colind, A.d_val, outv, d_flag);
+  SP_HIP(hipGetLastError());
+  return SPAND_OK;
+}
+
+// d_out[t] = alpha * u_I v_J^T for every stored block
+__global__ __launch_bounds__(256) void k_pattern_outer(int n_brows, int bs,
+                                                       const int32_t *__restrict__ rowptr,
+                                                       const int32_t *__restrict__ colind,
+                                                       const double *__restrict__ u,
+                                                       const double *__restrict__ v, double alpha,
+                                                       double *__restrict__ out) {
+  const int I = blockIdx.x;
+  if (I >= n_brows) return;
+  const int64_t b2 = (int64_t)bs * bs;
+  for (int t = rowptr[I]; t < rowptr[I + 1]; ++t) {
+    const int J = colind[t];
+    for (int idx = threadIdx.x; idx < bs * bs; idx += 256) {
+      const int r = idx / bs, c = idx % bs;
+      out[(int64_t)t * b2 + idx] = alpha * u[(int64_t)I * bs + r] * v[(int64_t)J * bs + c];
+    }
+  }
+}
+
+int launch_pattern_outer(const spand_bsr_t &P, const double *u, const double *v, double alpha,
+                         double *out, hipStream_t st) {
+  if (P.n_brows <= 0) return SPAND_OK;
+  hipLaunchKernelGGL(k_pattern_outer, dim3(P.n_brows), dim3(256), 0, st, P.n_brows, P.bs,
+                     P.d_rowptr, P.d_colind, u, v, alpha, out);
+  SP_HIP(hipGetLastError());
+  return SPAND_OK;
+}
+
+// ------------------------------------------------------------------ vectors
+__global__ void k_fill(double *x, int64_t n, double v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    x[i] = v;
+}
+__global__ void k_iota(int32_t *x, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    x[i] = int32_t(i);
+}
+// y = a*x + b*y  with a, b optionally read from device scalars:
+// a = ca * (pa ? *pa : 1) [* (inva ? 1/ *inva : 1)]
+__global__ void k_axpby(int64_t n, const double *__restrict__ x, double *__restrict__ y,
+                        double ca, const double *pa, int inva, double cb) {
+  double a = ca;
+  if (pa) a *= inva ? 1.0 / *pa : *pa;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    double v = a * x[i];
+    if (cb != 0.0) v += cb * y[i];
+    y[i] = v;
+  }
+}
+
+int vec_fill(double *x, int64_t n, double v, hipStream_t st) {
+  if (n <= 0) return SPAND_OK;
+  hipLaunchKernelGGL(k_fill, dim3((unsigned)std::min<int64_t>(4096, cdiv(n, 256))), dim3(256), 0,
+                     st, x, n, v);
+  SP_HIP(hipGetLastError());
+  return SPAND_OK;
+}
+int vec_iota(int32_t *x, int64_t n, hipStream_t st) {
+  if (n <= 0) return SPAND_OK;
+  hipLaunchKernelGGL(k_iota, dim3((unsigned)std::min<int64_t>(4096, cdiv(n, 256))), dim3(256), 0,
+                     st, x, n);
+  SP_HIP(hipGetLastError());
+  return SPAND_OK;
+}
+int vec_axpby(int64_t n, const double *x, double *y, double ca, const double *pa, int inva,
+              double cb, hipStream_t st) {
+  if (n <= 0) return SPAND_OK;
+  hipLaunchKernelGGL(k_axpby, dim3((unsigned)std::min<int64_t>(4096, cdiv(n, 256))), dim3(256), 0,
+                     st, n, x, y, ca, pa, inva, cb);
+  SP_HIP(hipGetLastError());
+  return SPAND_OK;
+}
+
+// ------------------------------------------------------------------ tall-skinny
+// Partial Gram: part[chunk][i][j] = sum_{r in chunk} X[i*ldx + r] * W[j*ldw + r]
+// (X: N x a, W: N x s, both column-major).  Chunks of TS_CHUNK rows.
+__global__ __launch_bounds__(256) void k_gram_part(int64_t N, const double *__restrict__ X,
+                                                   int64_t ldx, int a,
+                                                   const double *__restrict__ W, int64_t ldw,
+                                                   int s, double *__restrict__ part) {
+  __shared__ double ws[TS_CHUNK][TS_MAXS + 1];
+  const int64_t r0 = (int64_t)blockIdx.x * TS_CHUNK;
+  const int rows = int(std::min<int64_t>(TS_CHUNK, N - r0));
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  for (int idx = tid; idx < TS_CHUNK * s; idx += 256) {
+    const int j = idx / TS_CHUNK, r = idx % TS_CHUNK;
+    ws[r][j] = r < rows ? W[(int64_t)j * ldw + r0 + r] : 0.0;
+  }
+  __syncthreads();
+  double *outp = part + (int64_t)blockIdx.x * a * s;
+  for (int i = wid; i < a; i += 4) {
+    double acc[TS_MAXS];
+#pragma unroll
+    for (int j = 0; j < TS_MAXS; ++j) acc[j] = 0.0;
+    const double *xc = X + (int64_t)i * ldx + r0;
+    for (int r = lane; r < rows; r += 64) {
+      const double xv = xc[r];
+#pragma unroll
+      for (int j = 0; j < TS_MAXS; ++j)
+        if (j < s) acc[j] += xv * ws[r][j];
+    }
+#pragma unroll
+    for (int j = 0; j < TS_MAXS; ++j) {
+      if (j < s) {
+        const double v = wsum(acc[j]);
+        if (lane == 0) outp[(int64_t)i * s + j] = v;
+      }
+    }
+  }
+}
+
+// out[i*ldo + j] (+)= sum over chunks, fixed order (deterministic)
+__global__ void k_gram_reduce(const double *__restrict__ part, int nchunk, int a, int s,
+                              double *__restrict__ out, int ldo) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= a * s) return;
+  double v = 0.0;
+  for (int c = 0; c < nchunk; ++c) v += part[(int64_t)c * a * s + idx];
+  out[(idx / s) * ldo + idx % s] = v;
+}
+
+int launch_gram(int64_t N, const double *X, int64_t ldx, int a, const double *W, int64_t ldw,
+                int s, double *part, double *out, int ldo, hipStream_t st) {
+  if (a <= 0 || s <= 0) return SPAND_OK;
+  const int nchunk = int(cdiv(N, TS_CHUNK));
+  hipLaunchKernelGGL(k_gram_part, dim3(nchunk), dim3(256), 0, st, N, X, ldx, a, W, ldw, s, part);
+  SP_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_gram_reduce, dim3(int(cdiv(a * s, 256))), dim3(256), 0, st, part, nchunk,
+                     a, s, out, ldo);
+  SP_HIP(hipGetLastError());
+  return SPAND_OK;
+}
+
+// W[:, j] -= sum_i X[:, i] R[i*ldr + j]
+__global__ __launch_bounds__(256) void k_ts_update(int64_t N, const double *__restrict__ X,
+                                                   int64_t ldx, int a,
+                                                   const double *__restrict__ R, int ldr,
+                                                   double *__restrict__ W, int64_t ldw, int s) {
+  __shared__ double Rs[TS_MAXA * TS_MAXS];
+  for (int idx = threadIdx.x; idx < a * s; idx += 256) Rs[idx] = R[(idx / s) * ldr + idx % s];
+  __syncthreads();
+  for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < N;
+       r += (int64_t)gridDim.x * 256) {
+    double acc[TS_MAXS];
+#pragma unroll
+    for (int j = 0; j < TS_MAXS; ++j) acc[j] = 0.0;
+    for (int i = 0; i < a; ++i) {
+      const double xv = X[(int64_t)i * ldx + r];
+#pragma unroll
+      for (int j = 0; j < TS_MAXS; ++j)
+        if (j < s) acc[j] += xv * Rs[i * s + j];
+    }
+#pragma unroll
+    for (int j = 0; j < TS_MAXS; ++j)
+      if (j < s) W[(int64_t)j * ldw + r] -= acc[j];
+  }
+}
+
+int launch_ts_update(int64_t N, const double *X, int64_t ldx, int a, const double *R, int ldr,
+                     double *W, int64_t ldw, int s, hipStream_t st) {
+  if (a <= 0 || s <= 0 || N <= 0) return SPAND_OK;
+  const unsigned g = (unsigned)std::min<int64_t>(8192, cdiv(N, 256));
+  hipLaunchKernelGGL(k_ts_update, dim3(g), dim3(256), 0, st, N, X, ldx, a, R, ldr, W, ldw, s);
+  SP_HIP(hipGetLastError());
+  return SPAND_OK;
+}
+
+// W <- W T^{-1}, T upper triangular s x s (row-major, ld s); skip if *bad
+__global__ __launch_bounds__(256) void k_ts_trsm(int64_t N, double *__restrict__ W, int64_t ldw,
+                                                 int s, const double *__restrict__ T,
+                                                 const int *__restrict__ bad) {
+  if (*bad) return;
+  __shared__ double Ts[TS_MAXS * TS_MAXS];
+  for (int idx = threadIdx.x; idx < s * s; idx += 256) Ts[idx] = T[idx];
+  __syncthreads();
+  for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < N;
+       r += (int64_t)gridDim.x * 256) {
+    double x[TS_MAXS];
+#pragma unroll
+    for (int j = 0; j < TS_MAXS; ++j) {
+      if (j < s) {
+        double v = W[(int64_t)j * ldw + r];
+#pragma unroll
+        for (int i = 0; i < TS_MAXS; ++i)
+          if (i < j) v -= x[i] * Ts[i * s + j];
+        x[j] = v / Ts[j * s + j];
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < TS_MAXS; ++j)
+      if (j < s) W[(int64_t)j * ldw + r] = x[j];
+  }
+}
+
+int launch_ts_trsm(int64_t N, double *W, int64_t ldw, int s, const double *T, const int *bad,
+                   hipStream_t st) {
+  if (N <= 0 || s <= 0) return SPAND_OK;
+  const unsigned g = (unsigned)std::min<int64_t>(8192, cdiv(N, 256));
+  hipLaunchKernelGGL(k_ts_trsm, dim3(g), dim3(256), 0, st, N, W, ldw, s, T, bad);
+  SP_HIP(hipGetLastError());
+  return SPAND_OK;
+}
+
+// y = X[:, 0:k] c   (c on device)
+__global__ __launch_bounds__(256) void k_ts_gemv(int64_t N, const double *__restrict__ X,
+                                                 int64_t ldx, int k, const double *__restrict__ c,
+                                                 double *__restrict__ y) {
+  __shared__ double cs[TS_MAXA];
+  for (int i = threadIdx.x; i < k; i += 256) cs[i] = c[i];
+  __syncthreads();
+  for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < N;
+       r += (int64_t)gridDim.x * 256) {
+    double v = 0.0;
+    for (int i = 0; i < k; ++i) v += X[(int64_t)i * ldx + r] * cs[i];
+    y[r] = v;
+  }
+}
+
+int launch_ts_gemv(int64_t N, const double *X, int64_t ldx, int k, const double *c, double *y,
+                   hipStream_t st) {
+  if (N <= 0) return SPAND_OK;
+  const unsigned g = (unsigned)std::min<int64_t>(8192, cdiv(N, 256));
+  hipLaunchKernelGGL(k_ts_gemv, dim3(g), dim3(256), 0, st, N, X, ldx, k, c, y);
+  SP_HIP(hipGetLastError());
+  return SPAND_OK;
+}
+
+}  // namespace spand

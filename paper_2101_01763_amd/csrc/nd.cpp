@@ -1,0 +1,183 @@
+// Geometric nested dissection of the element grid (host, integer only).
+//
+// Recursive bisection of the (i, j) element coordinates (paper Sec.
+// "Scalability study of spaND"), defining interiors, separators and
+// interfaces at every level 0 <= l < lmax (Sec. "Sparsified Nested
+// Dissection algorithm").  Exact rule (the paper leaves it open):
+//  * heap-numbered tree, root 1, children 2k, 2k+1; depth d <-> level L-1-d;
+//  * split axis x if the box is at least as wide as tall, else y;
+//    mid = lo + (hi-lo)/2; left box: coord < mid; right box: coord >= mid;
+//  * separator = vertices of the node with coord >= mid that have a grid
+//    neighbour (wrap edges in periodic directions) in the node with
+//    coord < mid; the right child keeps the right box minus the separator;
+//  * level-l cluster key of a live element = (its node, the depth-(L-1-l)
+//    box containing it); clusters ordered by key, elements ascending;
+//  * merge: (S, B) at level l+1 gathers (S, 2B) then (S, 2B+1) of level l;
+//  * elimination permutation: elements by (level of node, node, element).
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <deque>
+#include <tuple>
+
+#include "internal.h"
+
+namespace spand {
+
+int default_levels(int64_t K) {
+  double v = std::log2(double(K) / 32.0);
+  int L = int(std::lround(v)) + 1;
+  return L < 1 ? 1 : L;
+}
+
+static void grid_neighbours(int nx, int ny, bool px, bool py, int e, int out[4], int &cnt) {
+  int i = e % nx, j = e / nx;
+  static const int di[4] = {1, -1, 0, 0}, dj[4] = {0, 0, 1, -1};
+  cnt = 0;
+  for (int t = 0; t < 4; ++t) {
+    int ii = i + di[t], jj = j + dj[t];
+    if (px) ii = ((ii % nx) + nx) % nx;
+    if (py) jj = ((jj % ny) + ny) % ny;
+    if (ii < 0 || ii >= nx || jj < 0 || jj >= ny) continue;
+    int f = jj * nx + ii;
+    if (f == e) continue;
+    bool dup = false;
+    for (int q = 0; q < cnt; ++q) dup |= (out[q] == f);
+    if (!dup) out[cnt++] = f;
+  }
+}
+
+NDResult nested_dissection(int nx, int ny, bool px, bool py, int L) {
+  NDResult R;
+  R.nx = nx;
+  R.ny = ny;
+  R.L = L;
+  const int K = nx * ny;
+  std::vector<int> ex(K), ey(K);
+  for (int e = 0; e < K; ++e) {
+    ex[e] = e % nx;
+    ey[e] = e / nx;
+  }
+  std::vector<int32_t> node_of(K, -1);
+  std::vector<std::vector<int64_t>> box_at(L, std::vector<int64_t>(K, 0));
+  for (int e = 0; e < K; ++e) box_at[0][e] = 1;
+  std::map<int64_t, std::array<int, 4>> boxes;
+  boxes[1] = {0, nx, 0, ny};
+  struct Work {
+    int64_t k;
+    int d;
+    std::vector<int> V;
+  };
+  std::deque<Work> work;
+  {
+    Work w{1, 0, std::vector<int>(K)};
+    for (int e = 0; e < K; ++e) w.V[e] = e;
+    work.push_back(std::move(w));
+  }
+  std::vector<char> inV(K, 0), insep(K, 0);
+  while (!work.empty()) {
+    Work w = std::move(work.front());
+    work.pop_front();
+    const int64_t k = w.k;
+    const int d = w.d;
+    R.node_level[k] = L - 1 - d;
+    auto bx = boxes[k];
+    int x0 = bx[0], x1 = bx[1], y0 = bx[2], y1 = bx[3];
+    if (d == L - 1) {
+      for (int v : w.V) node_of[v] = int32_t(k);
+      continue;
+    }
+    bool xsplit = (x1 - x0) >= (y1 - y0);
+    int lo = xsplit ? x0 : y0, hi = xsplit ? x1 : y1;
+    const std::vector<int> &coord = xsplit ? ex : ey;
+    int mid = lo + (hi - lo) / 2;
+    std::array<int, 4> lbox, rbox;
+    if (xsplit) {
+      lbox = {x0, mid, y0, y1};
+      rbox = {mid, x1, y0, y1};
+    } else {
+      lbox = {x0, x1, y0, mid};
+      rbox = {x0, x1, mid, y1};
+    }
+    for (int v : w.V) inV[v] = 1;
+    std::vector<int> sep;
+    for (int v : w.V) {
+      if (coord[v] < mid) continue;
+      int nb[4], cnt;
+      grid_neighbours(nx, ny, px, py, v, nb, cnt);
+      for (int q = 0; q < cnt; ++q) {
+        int u = nb[q];
+        if (inV[u] && coord[u] < mid) {
+          sep.push_back(v);
+          break;
+        }
+      }
+    }
+    std::sort(sep.begin(), sep.end());
+    for (int v : sep) {
+      node_of[v] = int32_t(k);
+      insep[v] = 1;
+    }
+    Work wl{2 * k, d + 1, {}}, wr{2 * k + 1, d + 1, {}};
+    for (int v : w.V) {
+      if (coord[v] < mid)
+        wl.V.push_back(v);
+      else if (!insep[v])
+        wr.V.push_back(v);
+    }
+    for (int v : w.V) inV[v] = 0;
+    for (int v : sep) insep[v] = 0;
+    boxes[2 * k] = lbox;
+    boxes[2 * k + 1] = rbox;
+    for (int e = 0; e < K; ++e) {
+      if (box_at[d][e] != k) continue;
+      box_at[d + 1][e] = coord[e] < mid ? 2 * k : 2 * k + 1;
+    }
+    work.push_back(std::move(wl));
+    work.push_back(std::move(wr));
+  }
+  R.node_of_elem = node_of;
+  std::vector<int> lvl(K);
+  for (int e = 0; e < K; ++e) lvl[e] = R.node_level[node_of[e]];
+  R.levels.resize(L);
+  R.children.resize(L);
+  std::map<std::pair<int64_t, int64_t>, int> prev_index;
+  for (int l = 0; l < L; ++l) {
+    std::map<std::pair<int64_t, int64_t>, std::vector<int32_t>> keys;
+    for (int e = 0; e < K; ++e) {
+      if (lvl[e] < l) continue;
+      keys[{int64_t(node_of[e]), box_at[L - 1 - l][e]}].push_back(e);
+    }
+    std::vector<NDCluster> cl;
+    std::map<std::pair<int64_t, int64_t>, int> index;
+    for (auto &kv : keys) {
+      NDCluster c;
+      c.node = int32_t(kv.first.first);
+      c.box = int32_t(kv.first.second);
+      c.elems = kv.second;  // inserted in ascending e
+      c.interior = R.node_level[c.node] == l;
+      index[kv.first] = int(cl.size());
+      cl.push_back(std::move(c));
+    }
+    if (l >= 1) {
+      R.children[l].resize(cl.size());
+      for (size_t i = 0; i < cl.size(); ++i) {
+        for (int64_t cb : {2 * int64_t(cl[i].box), 2 * int64_t(cl[i].box) + 1}) {
+          auto it = prev_index.find({int64_t(cl[i].node), cb});
+          if (it != prev_index.end()) R.children[l][i].push_back(it->second);
+        }
+      }
+    }
+    R.levels[l] = std::move(cl);
+    prev_index = std::move(index);
+  }
+  std::vector<int> order(K);
+  for (int e = 0; e < K; ++e) order[e] = e;
+  std::sort(order.begin(), order.end(), [&](int a, int b) {
+    return std::make_tuple(lvl[a], node_of[a], a) < std::make_tuple(lvl[b], node_of[b], b);
+  });
+  R.perm.assign(order.begin(), order.end());
+  return R;
+}
+
+}  // namespace spand

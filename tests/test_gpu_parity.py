@@ -1,0 +1,164 @@
+"""GPU parity: every entry point of the C ABI against the CPU oracle on the
+same seeded inputs (C1-sized and small ragged grids).  Tolerances:
+  * SpMV / pattern outer product: 1e-14 relative (float64 sums of 5 b x b
+    blocks, same data);
+  * eps = 0 spaND apply vs the direct solve: 1e-12 (spec bound);
+  * eps > 0 FP64 apply vs oracle apply: 1e-10 relative, when the ranks agree
+    level by level (otherwise the paths legitimately differ);
+  * s-step GMRES FP64: same iteration count, x within 1e-10 of the oracle's.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_2101_01763_amd as sp  # noqa: E402
+from oracle import direct, krylov, spand  # noqa: E402
+from oracle.nd import nested_dissection  # noqa: E402
+from synth.dg_euler import DGConfig, make_problem  # noqa: E402
+
+
+def _problem(n, p, seed=0, **kw):
+    cfg = DGConfig(n=n, p=p, seed=seed, **kw)
+    A, xs, b, _ = make_problem(cfg)
+    dA = sp.BSRMatrix.from_numpy(A.rowptr, A.colind, A.val)
+    return cfg, A, A.to_scipy().tocsr(), xs, b, dA
+
+
+def _dev(x):
+    return torch.as_tensor(np.ascontiguousarray(x), device="cuda")
+
+
+def _host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+@pytest.mark.parametrize("n,p", [(16, 1), (7, 2), (5, 3)])
+def test_spmv(n, p):
+    cfg, A, As, xs, b, dA = _problem(n, p)
+    x = np.random.default_rng(3).standard_normal(cfg.N)
+    y = _host(sp.spmv(dA, _dev(x)))
+    ref = As @ x
+    assert np.abs(y - ref).max() <= 1e-14 * np.abs(ref).max() * 10
+    yt = _host(sp.spmv(dA, _dev(x), transpose=True))
+    reft = As.T @ x
+    assert np.abs(yt - reft).max() <= 1e-14 * np.abs(reft).max() * 10
+
+
+def test_pattern_outer():
+    cfg, A, As, xs, b, dA = _problem(6, 1)
+    rng = np.random.default_rng(4)
+    u, v = rng.standard_normal(cfg.N), rng.standard_normal(cfg.N)
+    got = _host(sp.pattern_outer(dA, _dev(u), _dev(v), alpha=-1.0))
+    bs = cfg.b
+    for I in range(cfg.K):
+        for t in range(A.rowptr[I], A.rowptr[I + 1]):
+            J = A.colind[t]
+            np.testing.assert_array_equal(got[t], -np.outer(u[I * bs:(I + 1) * bs], v[J * bs:(J + 1) * bs]))
+
+
+@pytest.mark.parametrize("n,p,L", [(16, 1, 4), (8, 2, 3), (12, 1, 5), (6, 3, 2), (8, 1, 1)])
+def test_eps0_direct(n, p, L):
+    cfg, A, As, xs, b, dA = _problem(n, p)
+    F = sp.factor(dA, n, n, True, False, eps=0.0, nlevels=L, dtype="f64")
+    y = _host(F.apply(_dev(b)))
+    xd = direct.solve(As, b)
+    assert np.linalg.norm(y - xd) <= 1e-12 * np.linalg.norm(xd)
+    yt = _host(F.apply_T(_dev(b)))
+    xdt = direct.solve(As, b, transpose=True)
+    assert np.linalg.norm(yt - xdt) <= 1e-12 * np.linalg.norm(xdt)
+
+
+@pytest.mark.parametrize("n,p,L,eps", [(16, 1, 4, 1e-2), (16, 1, 4, 1e-1), (10, 2, 3, 1e-2),
+                                       (13, 1, 4, 1e-3)])
+def test_apply_parity_fp64(n, p, L, eps):
+    cfg, A, As, xs, b, dA = _problem(n, p)
+    F = sp.factor(dA, n, n, True, False, eps=eps, nlevels=L, dtype="f64")
+    Fo = spand.factor(As, nested_dissection(n, n, True, False, L), cfg.b, eps)
+    st = F.stats()
+    ro = spand.rank_stats(Fo)
+    ranks_gpu = [(a, c) for a, c in zip(st["size_before"], st["size_after"])]
+    ranks_ora = [(r[4], r[3]) for r in ro]
+    r = np.random.default_rng(7).standard_normal(cfg.N)
+    if ranks_gpu != ranks_ora:
+        pytest.skip(f"rank tie at the threshold: gpu {ranks_gpu} oracle {ranks_ora}")
+    y = _host(F.apply(_dev(r)))
+    yo = spand.apply(Fo, r)
+    assert np.linalg.norm(y - yo) <= 1e-10 * np.linalg.norm(yo)
+    yt = _host(F.apply_T(_dev(r)))
+    yto = spand.apply_T(Fo, r)
+    assert np.linalg.norm(yt - yto) <= 1e-10 * np.linalg.norm(yto)
+
+
+def test_apply_adjointness_and_determinism():
+    cfg, A, As, xs, b, dA = _problem(16, 1)
+    F = sp.factor(dA, 16, 16, True, False, eps=1e-1, nlevels=4, dtype="f64")
+    rng = np.random.default_rng(11)
+    u, v = rng.standard_normal(cfg.N), rng.standard_normal(cfg.N)
+    Mu = _host(F.apply(_dev(u)))
+    MTv = _host(F.apply_T(_dev(v)))
+    assert abs(Mu @ v - u @ MTv) <= 1e-12 * abs(Mu @ v)
+    a1 = _host(F.apply(_dev(u)))
+    assert np.array_equal(Mu, a1)
+    du = _dev(u)
+    F.apply(du, out=du)                      # in place
+    assert np.array_equal(_host(du), Mu)
+
+
+def test_sstep_unpreconditioned():
+    cfg, A, As, xs, b, dA = _problem(8, 1)
+    x, info = sp.solve(dA, _dev(b), None, s=4, restart=40, rtol=1e-8, maxit=400)
+    xo, io = krylov.sstep_gmres(lambda v: As @ v, b, None, s=4, rtol=1e-8, restart=40, maxit=400)
+    assert info.converged and io.converged
+    assert abs(info.iters - io.iters) <= 1
+    n = min(len(info.history), len(io.history), 20)
+    h, ho = np.array(info.history[:n]), np.array(io.history[:n])
+    assert np.max(np.abs(h - ho) / ho) <= 1e-6
+
+
+@pytest.mark.parametrize("s,eps", [(4, 1e-2), (5, 1e-1), (1, 1e-1), (2, 1e-2)])
+def test_sstep_parity_fp64(s, eps):
+    n, p, L = 16, 1, 4
+    cfg, A, As, xs, b, dA = _problem(n, p)
+    F = sp.factor(dA, n, n, True, False, eps=eps, nlevels=L, dtype="f64")
+    m = 40 if 40 % s == 0 else 40 - 40 % s
+    x, info = sp.solve(dA, _dev(b), F, s=s, restart=m, rtol=1e-8)
+    Fo = spand.factor(As, nested_dissection(n, n, True, False, L), cfg.b, eps)
+    xo, io = krylov.sstep_gmres(lambda v: As @ v, b, lambda v: spand.apply(Fo, v), s=s,
+                                rtol=1e-8, restart=m)
+    xg = _host(x)
+    assert info.converged and info.relres <= 1e-8
+    assert info.iters == io.iters
+    assert np.linalg.norm(xg - xo) <= 1e-10 * np.linalg.norm(xo)
+    np.testing.assert_allclose(info.history, io.history, rtol=1e-6)
+
+
+def test_fp32_factor_iterations_within_10pct():
+    n, p, L = 16, 2, 4
+    cfg, A, As, xs, b, dA = _problem(n, p)
+    res = {}
+    for dt in ("f64", "f32"):
+        F = sp.factor(dA, n, n, True, False, eps=1e-2, nlevels=L, dtype=dt)
+        x, info = sp.solve(dA, _dev(b), F, s=5, restart=60, rtol=1e-8)
+        assert info.converged
+        res[dt] = (info.iters, np.linalg.norm(_host(x) - xs) / np.linalg.norm(xs))
+    assert res["f32"][0] <= int(np.ceil(1.1 * res["f64"][0]))
+    assert res["f32"][1] < 1e-6
+
+
+def test_adjoint_gradient_dense():
+    from oracle import adjoint
+    n, p = 6, 1
+    cfg, A, As, xs, b, dA = _problem(n, p)
+    g = np.random.default_rng(cfg.seed + 1).standard_normal(cfg.N)
+    F = sp.factor(dA, n, n, True, False, eps=1e-2, nlevels=3, dtype="f32")
+    vals = dA.val.clone().requires_grad_(True)
+    bt = _dev(b).requires_grad_(True)
+    x = sp.SpandSolve.apply(vals, bt, dA, F, dict(s=4, restart=40, rtol=1e-13))
+    L = (x * _dev(g)).sum()
+    L.backward()
+    _, lam, gb, gv = adjoint.dense_gradient(As, A.rowptr, A.colind, A.bs, b, g)
+    assert np.linalg.norm(_host(bt.grad) - gb) <= 1e-10 * np.linalg.norm(gb)
+    assert np.linalg.norm(_host(vals.grad) - gv) <= 1e-10 * np.linalg.norm(gv)
