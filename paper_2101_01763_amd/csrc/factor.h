@@ -31,12 +31,25 @@ struct PullSet {
   int set(Factor &F, const std::vector<PullGroup> &G, const std::vector<PullItem> &I);
 };
 
+// batched GEMVs of one sweep step, split into bands of output rows; for
+// in-place use the union of output slots is copied back from scratch
+struct GemvSet {
+  GemvDesc *d_items = nullptr;
+  GemvChunk *d_chunks = nullptr;
+  int nchunks = 0;
+  int n = 0;
+  int32_t *d_slots = nullptr;
+  int64_t nslots = 0;
+  int set(Factor &F, std::vector<GemvDesc> items, const std::vector<const std::vector<int32_t> *> &oslots,
+          int trans);
+};
+
+inline int ld4(int n) { return (n + 3) & ~3; }
+
 // apply plan of one level (see Factor::apply)
 struct ApplyLevel {
-  GemvDesc *d_inv = nullptr, *d_invT = nullptr;   // interiors: A_ss^-1
-  int n_inv = 0;
-  GemvDesc *d_F = nullptr, *d_B = nullptr, *d_FT = nullptr, *d_BT = nullptr;   // interfaces
-  int n_if = 0;
+  GemvSet inv, invT;            // interiors: A_ss^-1
+  GemvSet F, B, FT, BT;         // interfaces
   PullSet fw;    // x_n -= A_ns t_s          (groups: neighbours)
   PullSet bw;    // x_s -= A_sn x_n          (groups: interiors)
   PullSet tfw;   // x_n -= A_sn^T x_s        (groups: neighbours)
@@ -105,7 +118,6 @@ struct Factor {
   int eliminate_dense(int l, LevelState &S);
   int sparsify(int l, const NDResult &nd, LevelState &S, LevelState &Nx);
   int build(const spand_bsr_t &A, const spand_grid_t &g, const spand_opts_t &o);
-  int finish_transposed();
   int apply(const double *in, double *out, int transpose, hipStream_t st);
   void fill_stats(spand_factor_stats_t *st) const;
 };

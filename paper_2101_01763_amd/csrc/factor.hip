@@ -265,7 +265,7 @@ int Factor::level0(const spand_bsr_t &A, const NDResult &nd, LevelState &S) {
         return SPAND_EINVAL;
       }
       ot[s] = pt.add(size_t(n) * n * tsz);
-      ok[s] = pk.add(size_t(n) * n * tsz);
+      ok[s] = pk.add(size_t(n) * ld4(n) * tsz);
     }
     if (!leaves.empty()) {
       void *bt, *bk;
@@ -326,6 +326,7 @@ int Factor::level0(const spand_bsr_t &A, const NDResult &nd, LevelState &S) {
       g.lds = d.ld;
       g.ldd = d.n;
       g.colperm = 1;
+      g.ldd = ld4(d.n);
       for (int s : leaves)
         if (Ass[s] == d.A) g.dst = Ainv[s];
       rg.push_back(g);
@@ -371,8 +372,8 @@ int Factor::level0(const spand_bsr_t &A, const NDResult &nd, LevelState &S) {
           SchurItem it{};
           it.a1 = ca.t_ef;      // A[e_a, f_a]
           it.a2 = cc.t_fe;      // A[f_c, e_c]
-          it.Y = (char *)Ainv[s] + (size_t(epos[ca.f]) * b * n + size_t(epos[cc.f]) * b) * tsz;
-          it.ldy = n;
+          it.Y = (char *)Ainv[s] + (size_t(epos[ca.f]) * b * ld4(n) + size_t(epos[cc.f]) * b) * tsz;
+          it.ldy = ld4(n);
           tg[{ca.e, cc.e}].push_back(it);
         }
     }
@@ -473,17 +474,19 @@ int Factor::level0(const spand_bsr_t &A, const NDResult &nd, LevelState &S) {
     build(bw_ns, 1, G, I, true);
     SP_TRY(AL.tbw.set(*this, G, I));
     std::vector<GemvDesc> gv;
+    std::vector<const std::vector<int32_t> *> os;
     for (int s : leaves) {
       GemvDesc d{};
       d.A = Ainv[s];
       d.islot = d.oslot = S.d_slots[s];
       d.rows = d.cols = S.size[s];
-      d.lda = S.size[s];
+      d.lda = ld4(S.size[s]);
       gv.push_back(d);
+      os.push_back(&S.slots[s]);
       apply_bytes += double(S.size[s]) * S.size[s] * tsz * 2;
     }
-    SP_TRY(upload(gv, &AL.d_inv, true));
-    AL.n_inv = int(gv.size());
+    SP_TRY(AL.inv.set(*this, gv, os, 0));
+    SP_TRY(AL.invT.set(*this, gv, os, 1));
     apply_bytes += double(ncp) * 2 * b2 * tsz * 2;
     for (int s : leaves) flops += 2.0 * double(S.size[s]) * S.size[s] * S.size[s];
   }
@@ -495,6 +498,27 @@ int PullSet::set(Factor &F, const std::vector<PullGroup> &G, const std::vector<P
   n = int(G.size());
   SP_TRY(F.upload(G, &d_groups, true));
   SP_TRY(F.upload(I, &d_items, true));
+  return SPAND_OK;
+}
+
+int GemvSet::set(Factor &F, std::vector<GemvDesc> items,
+                 const std::vector<const std::vector<int32_t> *> &oslots, int trans) {
+  n = int(items.size());
+  if (!n) return SPAND_OK;
+  const int R = trans ? 256 : 64;
+  std::vector<GemvChunk> ch;
+  std::vector<int32_t> sl;
+  for (int i = 0; i < n; ++i) {
+    items[i].trans = trans;
+    for (int r0 = 0; r0 < items[i].rows; r0 += R)
+      ch.push_back(GemvChunk{i, r0, std::min(R, items[i].rows - r0), 0});
+    sl.insert(sl.end(), oslots[i]->begin(), oslots[i]->begin() + items[i].rows);
+  }
+  nchunks = int(ch.size());
+  nslots = int64_t(sl.size());
+  SP_TRY(F.upload(items, &d_items, true));
+  SP_TRY(F.upload(ch, &d_chunks, true));
+  SP_TRY(F.upload(sl, &d_slots, true));
   return SPAND_OK;
 }
 
@@ -523,7 +547,7 @@ int Factor::eliminate_dense(int l, LevelState &S) {
                 "increase eps or the number of levels", n, l, ELIM_MAXN);
       return SPAND_EINVAL;
     }
-    SP_TRY(dalloc(&Ainv[s], size_t(n) * n * tsz, true));
+    SP_TRY(dalloc(&Ainv[s], size_t(n) * ld4(n) * tsz, true));
     ElimDesc d{};
     d.A = S.blocks.at({s, s}).p;
     d.n = n;
@@ -542,7 +566,8 @@ int Factor::eliminate_dense(int l, LevelState &S) {
       g.src = d.A;
       g.piv = d.piv;
       g.n = g.cols = d.n;
-      g.lds = g.ldd = d.n;
+      g.lds = d.n;
+      g.ldd = ld4(d.n);
       g.colperm = 1;
       for (int s : ints)
         if (S.blocks.at({s, s}).p == d.A) g.dst = Ainv[s];
@@ -571,7 +596,7 @@ int Factor::eliminate_dense(int l, LevelState &S) {
         g.M = B.rows;
         g.N = B.cols;
         g.K = B.rows;
-        g.lda = B.rows;
+        g.lda = ld4(B.rows);
         g.ldb = B.cols;
         g.ldc = B.cols;
         g.alpha = 1.0;
@@ -629,16 +654,18 @@ int Factor::eliminate_dense(int l, LevelState &S) {
   }
   // apply descriptors
   std::vector<GemvDesc> gv;
+  std::vector<const std::vector<int32_t> *> os;
   for (int s : ints) {
     GemvDesc d{};
     d.A = Ainv[s];
     d.islot = d.oslot = S.d_slots[s];
     d.rows = d.cols = S.size[s];
-    d.lda = S.size[s];
+    d.lda = ld4(S.size[s]);
     gv.push_back(d);
+    os.push_back(&S.slots[s]);
   }
-  SP_TRY(upload(gv, &AL.d_inv, true));
-  AL.n_inv = int(gv.size());
+  SP_TRY(AL.inv.set(*this, gv, os, 0));
+  SP_TRY(AL.invT.set(*this, gv, os, 1));
   std::map<int, std::vector<PullItem>> fw, tfw;
   std::vector<PullGroup> G;
   std::vector<PullItem> I;
@@ -902,14 +929,27 @@ int Factor::sparsify(int l, const NDResult &nd, LevelState &S, LevelState &Nx) {
   void *kout;
   SP_TRY(dalloc(&kout, std::max<size_t>(1, ifs.size()) * 4, false));
   {
+    // all W in one zeroed region (padding columns must read as zero)
+    PlanArena pw;
+    std::vector<size_t> wo(ncl, 0);
+    for (int s : ifs) {
+      int nc = 0;
+      for (int n : nb[s]) nc += 2 * S.size[n];
+      ncols[s] = nc;
+      wo[s] = pw.add(size_t(S.size[s]) * ld4(std::max(nc, 1)) * tsz);
+    }
+    void *wbase = nullptr;
+    if (!ifs.empty()) {
+      SP_TRY(dalloc(&wbase, pw.total, false));
+      SP_HIP(hipMemsetAsync(wbase, 0, pw.total, stream));
+    }
     std::vector<CopyDesc> wc;
     for (size_t q = 0; q < ifs.size(); ++q) {
       const int s = ifs[q];
       const int m = S.size[s];
-      int nc = 0;
-      for (int n : nb[s]) nc += 2 * S.size[n];
-      ncols[s] = nc;
-      SP_TRY(dalloc(&Wm[s], size_t(m) * std::max(nc, 1) * tsz, false));
+      const int nc = ncols[s];
+      const int ldw = ld4(std::max(nc, 1));
+      Wm[s] = (char *)wbase + wo[s];
       SP_TRY(dalloc(&Qm[s], size_t(m) * m * tsz, false));
       SP_TRY(dalloc(&Vm[s], size_t(m) * m * tsz, false));
       void *tau, *vn1, *vn2, *sel;
@@ -926,7 +966,7 @@ int Factor::sparsify(int l, const NDResult &nd, LevelState &S, LevelState &Nx) {
         d.rows = m;
         d.cols = B.cols;
         d.lds = B.cols;
-        d.ldd = nc;
+        d.ldd = ldw;
         d.scale = 1.0;
         wc.push_back(d);
         off += B.cols;
@@ -939,7 +979,7 @@ int Factor::sparsify(int l, const NDResult &nd, LevelState &S, LevelState &Nx) {
         d.rows = m;
         d.cols = B.rows;
         d.lds = B.cols;
-        d.ldd = nc;
+        d.ldd = ldw;
         d.trans = 1;
         d.scale = 1.0;
         wc.push_back(d);
@@ -956,6 +996,7 @@ int Factor::sparsify(int l, const NDResult &nd, LevelState &S, LevelState &Nx) {
       Qd.k_out = (int32_t *)kout + q;
       Qd.m = m;
       Qd.ncols = nc;
+      Qd.ldw = ldw;
       qd.push_back(Qd);
       flops += 4.0 * double(m) * nc * std::min(m, nc);
     }
@@ -982,18 +1023,20 @@ int Factor::sparsify(int l, const NDResult &nd, LevelState &S, LevelState &Nx) {
   {
     std::vector<GemmDesc> gm;
     std::vector<GemvDesc> gf, gb;
+    std::vector<const std::vector<int32_t> *> os;
     for (int s : ifs) {
       const int m = S.size[s];
       void *Fp, *Bp;
-      SP_TRY(dalloc(&Fp, size_t(m) * m * tsz, true));
-      SP_TRY(dalloc(&Bp, size_t(m) * m * tsz, true));
+      SP_TRY(dalloc(&Fp, size_t(m) * ld4(m) * tsz, true));
+      SP_TRY(dalloc(&Bp, size_t(m) * ld4(m) * tsz, true));
       GemmDesc g{};
       g.A = Qm[s];
       g.transA = 1;
       g.B = Lh[s];
       g.C = Fp;
       g.M = g.N = g.K = m;
-      g.lda = g.ldb = g.ldc = m;
+      g.lda = g.ldb = m;
+      g.ldc = ld4(m);
       g.alpha = 1.0;
       gm.push_back(g);
       GemmDesc h{};
@@ -1001,24 +1044,27 @@ int Factor::sparsify(int l, const NDResult &nd, LevelState &S, LevelState &Nx) {
       h.B = Qm[s];
       h.C = Bp;
       h.M = h.N = h.K = m;
-      h.lda = h.ldb = h.ldc = m;
+      h.lda = h.ldb = m;
+      h.ldc = ld4(m);
       h.alpha = 1.0;
       gm.push_back(h);
       GemvDesc d{};
       d.islot = d.oslot = S.d_slots[s];
       d.rows = d.cols = m;
-      d.lda = m;
+      d.lda = ld4(m);
       d.A = Fp;
       gf.push_back(d);
       d.A = Bp;
       gb.push_back(d);
+      os.push_back(&S.slots[s]);
       apply_bytes += 4.0 * double(m) * m * tsz;
       flops += 4.0 * double(m) * m * m;
     }
     SP_TRY(gemm_batch(gm));
-    SP_TRY(upload(gf, &AL.d_F, true));
-    SP_TRY(upload(gb, &AL.d_B, true));
-    AL.n_if = int(gf.size());
+    SP_TRY(AL.F.set(*this, gf, os, 0));
+    SP_TRY(AL.B.set(*this, gb, os, 0));
+    SP_TRY(AL.FT.set(*this, gf, os, 1));
+    SP_TRY(AL.BT.set(*this, gb, os, 1));
   }
   // ---- merge: next-level clusters from the coarse parts
   const auto &cl1 = nd.levels[l + 1];
@@ -1202,60 +1248,51 @@ int Factor::build(const spand_bsr_t &A, const spand_grid_t &g, const spand_opts_
     set_error("zero pivot met during the factorization");
     return SPAND_ESINGULAR;
   }
-  return finish_transposed();
+  return SPAND_OK;
 }
 
 // ------------------------------------------------------------------ apply
+// y = M^-1 r:  forward over levels applies L' (interiors: x_n -= A_ns A_ss^-1 x_s)
+// and F_s (interfaces); backward applies B_s and R' (x_s = A_ss^-1 (x_s - A_sn x_n)).
+// y = M^-T r:  forward applies R'^T and B_s^T, backward F_s^T and L'^T.
 int Factor::apply(const double *in, double *out, int transpose, hipStream_t st) {
   if (out != in) SP_HIP(hipMemcpyAsync(out, in, size_t(N) * 8, hipMemcpyDeviceToDevice, st));
   double *x = out;
+  auto inplace = [&](const GemvSet &g) -> int {
+    if (!g.n) return SPAND_OK;
+    SP_TRY(launch_gemv(ft, g.d_items, g.d_chunks, g.nchunks, x, d_tbuf, 1.0, 0.0, st));
+    return launch_slot_copy(g.d_slots, g.nslots, d_tbuf, x, st);
+  };
   if (!transpose) {
     for (int l = 0; l < L; ++l) {
       const ApplyLevel &A = lv[l];
       if (A.fw.n) {
-        SP_TRY(launch_gemv(ft, A.d_inv, A.n_inv, x, d_tbuf, 1.0, 0.0, 0, st));
+        SP_TRY(launch_gemv(ft, A.inv.d_items, A.inv.d_chunks, A.inv.nchunks, x, d_tbuf, 1.0, 0.0, st));
         SP_TRY(launch_pull2(ft, A.fw.d_groups, A.fw.n, A.fw.d_items, d_tbuf, x, -1.0, 1.0, st));
       }
-      if (A.n_if) SP_TRY(launch_gemv(ft, A.d_F, A.n_if, x, x, 1.0, 0.0, 0, st));
+      SP_TRY(inplace(A.F));
     }
     for (int l = L - 1; l >= 0; --l) {
       const ApplyLevel &A = lv[l];
-      if (A.n_if) SP_TRY(launch_gemv(ft, A.d_B, A.n_if, x, x, 1.0, 0.0, 0, st));
+      SP_TRY(inplace(A.B));
       if (A.bw.n) SP_TRY(launch_pull2(ft, A.bw.d_groups, A.bw.n, A.bw.d_items, x, x, -1.0, 1.0, st));
-      if (A.n_inv) SP_TRY(launch_gemv(ft, A.d_inv, A.n_inv, x, x, 1.0, 0.0, 0, st));
+      SP_TRY(inplace(A.inv));
     }
   } else {
     for (int l = 0; l < L; ++l) {
       const ApplyLevel &A = lv[l];
-      if (A.n_inv) SP_TRY(launch_gemv(ft, A.d_invT, A.n_inv, x, x, 1.0, 0.0, 0, st));
+      SP_TRY(inplace(A.invT));
       if (A.tfw.n) SP_TRY(launch_pull2(ft, A.tfw.d_groups, A.tfw.n, A.tfw.d_items, x, x, -1.0, 1.0, st));
-      if (A.n_if) SP_TRY(launch_gemv(ft, A.d_BT, A.n_if, x, x, 1.0, 0.0, 0, st));
+      SP_TRY(inplace(A.BT));
     }
     for (int l = L - 1; l >= 0; --l) {
       const ApplyLevel &A = lv[l];
-      if (A.n_if) SP_TRY(launch_gemv(ft, A.d_FT, A.n_if, x, x, 1.0, 0.0, 0, st));
-      if (A.tbw.n && A.n_inv) {
+      SP_TRY(inplace(A.FT));
+      if (A.tbw.n && A.invT.n) {
         SP_TRY(launch_pull2(ft, A.tbw.d_groups, A.tbw.n, A.tbw.d_items, x, d_tbuf, 1.0, 0.0, st));
-        SP_TRY(launch_gemv(ft, A.d_invT, A.n_inv, d_tbuf, x, -1.0, 1.0, 0, st));
+        SP_TRY(launch_gemv(ft, A.invT.d_items, A.invT.d_chunks, A.invT.nchunks, d_tbuf, x, -1.0, 1.0, st));
       }
     }
-  }
-  return SPAND_OK;
-}
-
-// transposed GEMV descriptors are the same matrices with trans = 1
-int Factor::finish_transposed() {
-  for (auto &A : lv) {
-    auto mk = [&](GemvDesc *src, int n, GemvDesc **dst) -> int {
-      if (!n) return SPAND_OK;
-      std::vector<GemvDesc> v(n);
-      SP_HIP(hipMemcpy(v.data(), src, n * sizeof(GemvDesc), hipMemcpyDeviceToHost));
-      for (auto &d : v) d.trans = 1;   // square: rows = cols, lda unchanged
-      return upload(v, dst, true);
-    };
-    SP_TRY(mk(A.d_inv, A.n_inv, &A.d_invT));
-    SP_TRY(mk(A.d_F, A.n_if, &A.d_FT));
-    SP_TRY(mk(A.d_B, A.n_if, &A.d_BT));
   }
   return SPAND_OK;
 }

@@ -118,8 +118,12 @@ struct GemvDesc {
   const int32_t *islot;
   const int32_t *oslot;
   int32_t rows, cols;      // of op(A)
-  int32_t lda;             // of A as stored
+  int32_t lda;             // of A as stored (a multiple of 4)
   int32_t trans;
+};
+// a band of output rows of one GEMV item (one workgroup)
+struct GemvChunk {
+  int32_t item, row0, nrows, pad;
 };
 
 // Pull group: out[oslot[r]] += alpha * sum_items op(B_i) in[islot_i[c]].
@@ -163,6 +167,8 @@ struct QrcpDesc {
   int32_t *sel;        // [ncols] selected flags
   int32_t *k_out;      // rank
   int32_t m, ncols;
+  int32_t ldw;         // leading dimension of W (multiple of 4, padding zero)
+  int32_t pad;
 };
 
 // ----------------------------------------------------------------- launches
@@ -210,8 +216,10 @@ struct EyeDesc {
   int32_t n, ld;
 };
 int launch_eye(FType t, const EyeDesc *d_items, int n, int max_n, hipStream_t st);
-int launch_gemv(FType t, const GemvDesc *d_items, int n, const double *in, double *out,
-                double alpha, double beta, int max_cols, hipStream_t st);
+int launch_gemv(FType t, const GemvDesc *d_items, const GemvChunk *d_chunks, int nchunks,
+                const double *in, double *out, double alpha, double beta, hipStream_t st);
+int launch_slot_copy(const int32_t *slots, int64_t n, const double *src, double *dst,
+                     hipStream_t st);
 int launch_pull(FType t, const PullGroup *d_groups, int ngroups, const PullItem *d_items,
                 const double *in, double *out, double alpha, hipStream_t st);
 int launch_spmv(const spand_bsr_t &A, int transpose, double alpha, const double *x,

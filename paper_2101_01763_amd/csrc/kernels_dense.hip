@@ -12,6 +12,7 @@
 // Matrices are row-major.  Every descriptor is validated on the host before
 // upload; kernels trust the sizes they are given.
 #include <climits>
+#include <type_traits>
 
 #include "internal.h"
 #include "factor.h"
@@ -597,6 +598,10 @@ __global__ __launch_bounds__(256) void k_qrcp(const QrcpDesc *__restrict__ items
                                               int force_full) {
   const QrcpDesc d = items[blockIdx.x];
   const int m = d.m, nc = d.ncols;
+  const int64_t ldw = d.ldw;
+  constexpr int VN = 16 / sizeof(T);            // columns per 16-byte load
+  using VT = typename std::conditional<sizeof(T) == 4, float4, double2>::type;
+  const int ngrp = (nc + VN - 1) / VN;
   const T *W = (const T *)d.W;
   T *Q = (T *)d.Q;
   T *V = (T *)d.V;
@@ -610,15 +615,39 @@ __global__ __launch_bounds__(256) void k_qrcp(const QrcpDesc *__restrict__ items
   __shared__ int s_j;
   __shared__ int s_nflag;
   const double tol3z = 1.4901161193847656e-08;  // sqrt(2^-52)
-  for (int j = tid; j < nc; j += 256) {
-    double s = 0.0;
-    for (int r = 0; r < m; ++r) {
-      const double v = double(W[(int64_t)r * nc + j]);
-      s += v * v;
+  // column norms, VN adjacent columns per thread with 16-byte loads
+  for (int g = tid; g < ngrp; g += 256) {
+    double acc[VN];
+#pragma unroll
+    for (int q = 0; q < VN; ++q) acc[q] = 0.0;
+    const T *base = W + (int64_t)g * VN;
+    int r = 0;
+    for (; r + 4 <= m; r += 4) {
+      VT v[4];
+#pragma unroll
+      for (int u4 = 0; u4 < 4; ++u4) v[u4] = *reinterpret_cast<const VT *>(base + (int64_t)(r + u4) * ldw);
+#pragma unroll
+      for (int u4 = 0; u4 < 4; ++u4) {
+        const T *e = reinterpret_cast<const T *>(&v[u4]);
+#pragma unroll
+        for (int q = 0; q < VN; ++q) acc[q] += double(e[q]) * double(e[q]);
+      }
     }
-    vn1[j] = sqrt(s);
-    vn2[j] = vn1[j];
-    sel[j] = 0;
+    for (; r < m; ++r) {
+      const VT v = *reinterpret_cast<const VT *>(base + (int64_t)r * ldw);
+      const T *e = reinterpret_cast<const T *>(&v);
+#pragma unroll
+      for (int q = 0; q < VN; ++q) acc[q] += double(e[q]) * double(e[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < VN; ++q) {
+      const int j = g * VN + q;
+      if (j < nc) {
+        vn1[j] = sqrt(acc[q]);
+        vn2[j] = vn1[j];
+        sel[j] = 0;
+      }
+    }
   }
   __syncthreads();
   double R00 = 0.0;
@@ -653,7 +682,7 @@ __global__ __launch_bounds__(256) void k_qrcp(const QrcpDesc *__restrict__ items
     __syncthreads();
     const int js = s_j;
     if (js == INT_MAX) break;
-    for (int r = tid; r < m; r += 256) u[r] = double(W[(int64_t)r * nc + js]);
+    for (int r = tid; r < m; r += 256) u[r] = double(W[(int64_t)r * ldw + js]);
     __syncthreads();
     // ---- two classical Gram-Schmidt passes against q_0..q_{i-1}
     for (int pass = 0; pass < 2 && i > 0; ++pass) {
@@ -688,20 +717,45 @@ __global__ __launch_bounds__(256) void k_qrcp(const QrcpDesc *__restrict__ items
     }
     __syncthreads();
     // ---- row i of R for all remaining columns; downdate their norms
-    for (int j = tid; j < nc; j += 256) {
-      if (sel[j]) continue;
-      double s = 0.0;
-      for (int r = 0; r < m; ++r) s += u[r] * double(W[(int64_t)r * nc + j]);
-      const double a = vn1[j];
-      if (a != 0.0) {
-        double temp = fabs(s) / a;
-        temp = fmax(0.0, (1.0 + temp) * (1.0 - temp));
-        const double t2 = temp * (a / vn2[j]) * (a / vn2[j]);
-        if (t2 <= tol3z) {
-          vn1[j] = -1.0;          // recompute below
-          atomicAdd(&s_nflag, 1);
-        } else {
-          vn1[j] = a * sqrt(temp);
+    for (int g = tid; g < ngrp; g += 256) {
+      double acc[VN];
+#pragma unroll
+      for (int q = 0; q < VN; ++q) acc[q] = 0.0;
+      const T *base = W + (int64_t)g * VN;
+      int r = 0;
+      for (; r + 4 <= m; r += 4) {
+        VT v[4];
+#pragma unroll
+        for (int u4 = 0; u4 < 4; ++u4) v[u4] = *reinterpret_cast<const VT *>(base + (int64_t)(r + u4) * ldw);
+#pragma unroll
+        for (int u4 = 0; u4 < 4; ++u4) {
+          const T *e = reinterpret_cast<const T *>(&v[u4]);
+          const double ur = u[r + u4];
+#pragma unroll
+          for (int q = 0; q < VN; ++q) acc[q] += ur * double(e[q]);
+        }
+      }
+      for (; r < m; ++r) {
+        const VT v = *reinterpret_cast<const VT *>(base + (int64_t)r * ldw);
+        const T *e = reinterpret_cast<const T *>(&v);
+#pragma unroll
+        for (int q = 0; q < VN; ++q) acc[q] += u[r] * double(e[q]);
+      }
+#pragma unroll
+      for (int q = 0; q < VN; ++q) {
+        const int j = g * VN + q;
+        if (j >= nc || sel[j]) continue;
+        const double a = vn1[j];
+        if (a != 0.0) {
+          double temp = fabs(acc[q]) / a;
+          temp = fmax(0.0, (1.0 + temp) * (1.0 - temp));
+          const double t2 = temp * (a / vn2[j]) * (a / vn2[j]);
+          if (t2 <= tol3z) {
+            vn1[j] = -1.0;          // recompute below
+            atomicAdd(&s_nflag, 1);
+          } else {
+            vn1[j] = a * sqrt(temp);
+          }
         }
       }
     }
@@ -712,12 +766,12 @@ __global__ __launch_bounds__(256) void k_qrcp(const QrcpDesc *__restrict__ items
         if (sel[j] || vn1[j] >= 0.0) continue;
         for (int tq = lane; tq <= i; tq += 64) {
           double s = 0.0;
-          for (int r = 0; r < m; ++r) s += double(Q[(int64_t)r * m + tq]) * double(W[(int64_t)r * nc + j]);
+          for (int r = 0; r < m; ++r) s += double(Q[(int64_t)r * m + tq]) * double(W[(int64_t)r * ldw + j]);
           cw[wid][tq] = s;
         }
         double acc = 0.0;
         for (int r = lane; r < m; r += 64) {
-          double s = double(W[(int64_t)r * nc + j]);
+          double s = double(W[(int64_t)r * ldw + j]);
           for (int tq = 0; tq <= i; ++tq) s -= double(Q[(int64_t)r * m + tq]) * cw[wid][tq];
           acc += s * s;
         }

@@ -18,25 +18,53 @@ __device__ inline T wsum(T v) {
 
 // ------------------------------------------------------------------ GEMV
 // out[oslot[r]] = beta*out[oslot[r]] + alpha * sum_c op(A)(r, c) in[islot[c]]
-// One workgroup per item; the input is staged in LDS first, so in == out
-// with identical slot lists is safe (slot lists of different items are
-// disjoint).
+// One workgroup per band of output rows (GemvChunk).  The input is staged
+// in LDS.  Bands of one item may run concurrently, so in == out is not
+// allowed (in-place sweeps write a scratch vector and copy back).
+template <typename T>
+struct Vec16;
+template <>
+struct Vec16<float> {
+  using V = float4;
+  static constexpr int N = 4;
+  __device__ static inline void get(const V &v, float *o) { o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w; }
+};
+template <>
+struct Vec16<double> {
+  using V = double2;
+  static constexpr int N = 2;
+  __device__ static inline void get(const V &v, double *o) { o[0] = v.x; o[1] = v.y; }
+};
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_gemv(const GemvDesc *__restrict__ items,
+                                              const GemvChunk *__restrict__ chunks,
                                               const double *__restrict__ in,
                                               double *__restrict__ out, double alpha,
                                               double beta) {
-  const GemvDesc d = items[blockIdx.x];
+  using VW = Vec16<T>;
+  constexpr int VN = VW::N;
+  const GemvChunk ch = chunks[blockIdx.x];
+  const GemvDesc d = items[ch.item];
   __shared__ double xs[GEMV_MAXC];
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   for (int c = tid; c < d.cols; c += 256) xs[c] = in[d.islot[c]];
   __syncthreads();
   const T *A = (const T *)d.A;
   if (!d.trans) {
-    for (int r = wid; r < d.rows; r += 4) {
+    const int cv = d.cols / VN * VN;     // vectorised part (lda is a multiple of 4)
+    for (int rr = wid; rr < ch.nrows; rr += 4) {
+      const int r = ch.row0 + rr;
       const T *row = A + (int64_t)r * d.lda;
       T acc = T(0);
-      for (int c = lane; c < d.cols; c += 64) acc += row[c] * T(xs[c]);
+      for (int c = lane * VN; c < cv; c += 64 * VN) {
+        const typename VW::V v = *reinterpret_cast<const typename VW::V *>(row + c);
+        T e[VN];
+        VW::get(v, e);
+#pragma unroll
+        for (int q = 0; q < VN; ++q) acc += e[q] * T(xs[c + q]);
+      }
+      for (int c = cv + lane; c < d.cols; c += 64) acc += row[c] * T(xs[c]);
       acc = wsum(acc);
       if (lane == 0) {
         const int o = d.oslot[r];
@@ -46,7 +74,8 @@ __global__ __launch_bounds__(256) void k_gemv(const GemvDesc *__restrict__ items
       }
     }
   } else {
-    for (int r = tid; r < d.rows; r += 256) {
+    const int r = ch.row0 + tid;
+    if (tid < ch.nrows) {
       T acc = T(0);
       for (int c = 0; c < d.cols; ++c) acc += A[(int64_t)c * d.lda + r] * T(xs[c]);
       const int o = d.oslot[r];
@@ -57,13 +86,33 @@ __global__ __launch_bounds__(256) void k_gemv(const GemvDesc *__restrict__ items
   }
 }
 
-int launch_gemv(FType t, const GemvDesc *d_items, int n, const double *in, double *out,
-                double alpha, double beta, int /*max_cols*/, hipStream_t st) {
-  if (n <= 0) return SPAND_OK;
+int launch_gemv(FType t, const GemvDesc *d_items, const GemvChunk *d_chunks, int nchunks,
+                const double *in, double *out, double alpha, double beta, hipStream_t st) {
+  if (nchunks <= 0) return SPAND_OK;
   if (t == FType::F64)
-    hipLaunchKernelGGL(k_gemv<double>, dim3(n), dim3(256), 0, st, d_items, in, out, alpha, beta);
+    hipLaunchKernelGGL(k_gemv<double>, dim3(nchunks), dim3(256), 0, st, d_items, d_chunks, in, out,
+                       alpha, beta);
   else
-    hipLaunchKernelGGL(k_gemv<float>, dim3(n), dim3(256), 0, st, d_items, in, out, alpha, beta);
+    hipLaunchKernelGGL(k_gemv<float>, dim3(nchunks), dim3(256), 0, st, d_items, d_chunks, in, out,
+                       alpha, beta);
+  SP_HIP(hipGetLastError());
+  return SPAND_OK;
+}
+
+__global__ void k_slot_copy(const int32_t *__restrict__ slots, int64_t n,
+                            const double *__restrict__ src, double *__restrict__ dst) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int s = slots[i];
+    dst[s] = src[s];
+  }
+}
+
+int launch_slot_copy(const int32_t *slots, int64_t n, const double *src, double *dst,
+                     hipStream_t st) {
+  if (n <= 0) return SPAND_OK;
+  hipLaunchKernelGGL(k_slot_copy, dim3((unsigned)std::min<int64_t>(8192, cdiv(n, 256))), dim3(256),
+                     0, st, slots, n, src, dst);
   SP_HIP(hipGetLastError());
   return SPAND_OK;
 }
@@ -338,14 +387,22 @@ __global__ __launch_bounds__(256) void k_gram_part(int64_t N, const double *__re
   }
 }
 
-// out[i*ldo + j] (+)= sum over chunks, fixed order (deterministic)
-__global__ void k_gram_reduce(const double *__restrict__ part, int nchunk, int a, int s,
-                              double *__restrict__ out, int ldo) {
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= a * s) return;
+// out[i*ldo + j] = sum over chunks; one workgroup per output, fixed
+// partition and tree order (deterministic)
+__global__ __launch_bounds__(256) void k_gram_reduce(const double *__restrict__ part, int nchunk,
+                                                     int a, int s, double *__restrict__ out,
+                                                     int ldo) {
+  __shared__ double red[256];
+  const int idx = blockIdx.x;
   double v = 0.0;
-  for (int c = 0; c < nchunk; ++c) v += part[(int64_t)c * a * s + idx];
-  out[(idx / s) * ldo + idx % s] = v;
+  for (int c = threadIdx.x; c < nchunk; c += 256) v += part[(int64_t)c * a * s + idx];
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[(idx / s) * ldo + idx % s] = red[0];
 }
 
 int launch_gram(int64_t N, const double *X, int64_t ldx, int a, const double *W, int64_t ldw,
@@ -354,8 +411,7 @@ int launch_gram(int64_t N, const double *X, int64_t ldx, int a, const double *W,
   const int nchunk = int(cdiv(N, TS_CHUNK));
   hipLaunchKernelGGL(k_gram_part, dim3(nchunk), dim3(256), 0, st, N, X, ldx, a, W, ldw, s, part);
   SP_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_gram_reduce, dim3(int(cdiv(a * s, 256))), dim3(256), 0, st, part, nchunk,
-                     a, s, out, ldo);
+  hipLaunchKernelGGL(k_gram_reduce, dim3(a * s), dim3(256), 0, st, part, nchunk, a, s, out, ldo);
   SP_HIP(hipGetLastError());
   return SPAND_OK;
 }
