@@ -1001,9 +1001,19 @@ int Factor::sparsify(int l, const NDResult &nd, LevelState &S, LevelState &Nx) {
       flops += 4.0 * double(m) * nc * std::min(m, nc);
     }
     SP_TRY(copy_batch(wc, 1));
+    int mq = 1, mg = 1;
+    for (auto &Qd : qd) {
+      mq = std::max(mq, Qd.m);
+      mg = std::max(mg, Qd.ldw / 2);     // column groups of 2 (FP64) or 4 (FP32)
+    }
+    const size_t lds = size_t(6) * mq * 8 + size_t(mg) * 4;
+    if (lds > 64 * 1024) {
+      set_error("RRQR problem too large for one workgroup (m=%d, %d column groups)", mq, mg);
+      return SPAND_EINVAL;
+    }
     QrcpDesc *d_q;
     SP_TRY(upload(qd, &d_q, false));
-    SP_TRY(launch_qrcp(ft, d_q, int(qd.size()), eps, eps == 0.0 ? 1 : 0, stream));
+    SP_TRY(launch_qrcp(ft, d_q, int(qd.size()), eps, eps == 0.0 ? 1 : 0, mq, mg, stream));
   }
   std::vector<int32_t> ks(ifs.size(), 0);
   if (!ifs.empty())

@@ -168,7 +168,7 @@ struct QrcpDesc {
   int32_t *k_out;      // rank
   int32_t m, ncols;
   int32_t ldw;         // leading dimension of W (multiple of 4, padding zero)
-  int32_t pad;
+  int32_t pad;         // LDS stride (largest m of the launch), set by the host
 };
 
 // ----------------------------------------------------------------- launches
@@ -200,8 +200,8 @@ struct RowGatherDesc {
 int launch_row_gather(FType t, const RowGatherDesc *d_items, int n, int max_rows, hipStream_t st);
 int launch_schur_elem(FType t, int bs, const double *bsr_val, const SchurGroup *d_groups,
                       int ngroups, const SchurItem *d_items, hipStream_t st);
-int launch_qrcp(FType t, const QrcpDesc *d_items, int n, double eps, int force_full,
-                hipStream_t st);
+int launch_qrcp(FType t, const QrcpDesc *d_items, int n, double eps, int force_full, int maxm,
+                int maxgrp, hipStream_t st);
 // dst rows/cols scaling: dst[r, c] *= rs[r] * cs[c] (either may be null)
 struct ScaleDesc {
   void *A;

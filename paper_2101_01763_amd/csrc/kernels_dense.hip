@@ -595,7 +595,7 @@ int launch_schur_elem(FType t, int bs, const double *bsr_val, const SchurGroup *
 // then completed to a full orthogonal Q by Householder QR of themselves.
 template <typename T>
 __global__ __launch_bounds__(256) void k_qrcp(const QrcpDesc *__restrict__ items, double eps,
-                                              int force_full) {
+                                              int force_full, int MS, int GS) {
   const QrcpDesc d = items[blockIdx.x];
   const int m = d.m, nc = d.ncols;
   const int64_t ldw = d.ldw;
@@ -608,10 +608,14 @@ __global__ __launch_bounds__(256) void k_qrcp(const QrcpDesc *__restrict__ items
   double *vn1 = d.vn1, *vn2 = d.vn2;
   int *sel = d.sel;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-  __shared__ double u[QRCP_MAXM];
-  __shared__ double cbuf[QRCP_MAXM];
+  // dynamic LDS: u[MS], cbuf[MS], cw[4][MS] (MS = largest m of the launch),
+  // then the list of active column groups (GS = largest group count)
+  extern __shared__ double qsm[];
+  double *u = qsm, *cbuf = qsm + MS;
+  auto cw = [&](int w, int t) -> double & { return qsm[(2 + w) * MS + t]; };
+  int *act = reinterpret_cast<int *>(qsm + 6 * MS);
+  __shared__ int s_nact;
   __shared__ double red[16];
-  __shared__ double cw[4][QRCP_MAXM];
   __shared__ int s_j;
   __shared__ int s_nflag;
   const double tol3z = 1.4901161193847656e-08;  // sqrt(2^-52)
@@ -650,6 +654,33 @@ __global__ __launch_bounds__(256) void k_qrcp(const QrcpDesc *__restrict__ items
     }
   }
   __syncthreads();
+  // Pruning: residual column norms never grow, so a column whose norm is
+  // already <= eps*|R_00| (= eps * largest column norm) can never be chosen
+  // before the rank test stops the factorisation.  Such columns leave every
+  // later pass (the pivots, ranks and Q are unchanged).
+  double cmax = 0.0;
+  for (int j = tid; j < nc; j += 256) cmax = fmax(cmax, vn1[j]);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) cmax = fmax(cmax, __shfl_xor(cmax, o, 64));
+  if (lane == 0) red[wid] = cmax;
+  __syncthreads();
+  cmax = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+  const double thr = force_full ? 0.0 : eps * cmax * (1.0 - 1e-4);
+  auto rebuild = [&]() {
+    if (tid == 0) s_nact = 0;
+    __syncthreads();
+    for (int g = tid; g < ngrp; g += 256) {
+      bool a = false;
+#pragma unroll
+      for (int q = 0; q < VN; ++q) {
+        const int j = g * VN + q;
+        if (j < nc && !sel[j] && vn1[j] > thr) a = true;
+      }
+      if (a) act[atomicAdd(&s_nact, 1)] = g;
+    }
+    __syncthreads();
+  };
+  rebuild();
   double R00 = 0.0;
   int k = 0;
   const int imax = min(m, nc);
@@ -657,10 +688,16 @@ __global__ __launch_bounds__(256) void k_qrcp(const QrcpDesc *__restrict__ items
     // ---- pivot: largest remaining column norm, ties -> smallest index
     double bv = -1.0;
     int bi = INT_MAX;
-    for (int j = tid; j < nc; j += 256) {
-      if (sel[j]) continue;
-      const double v = vn1[j];
-      if (v > bv || (v == bv && j < bi)) { bv = v; bi = j; }
+    const int nact = s_nact;
+    for (int qa = tid; qa < nact; qa += 256) {
+      const int g = act[qa];
+#pragma unroll
+      for (int q = 0; q < VN; ++q) {
+        const int j = g * VN + q;
+        if (j >= nc || sel[j]) continue;
+        const double v = vn1[j];
+        if (v > bv || (v == bv && j < bi)) { bv = v; bi = j; }
+      }
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
@@ -716,8 +753,9 @@ __global__ __launch_bounds__(256) void k_qrcp(const QrcpDesc *__restrict__ items
       s_nflag = 0;
     }
     __syncthreads();
-    // ---- row i of R for all remaining columns; downdate their norms
-    for (int g = tid; g < ngrp; g += 256) {
+    // ---- row i of R for all remaining active columns; downdate their norms
+    for (int qa = tid; qa < nact; qa += 256) {
+      const int g = act[qa];
       double acc[VN];
 #pragma unroll
       for (int q = 0; q < VN; ++q) acc[q] = 0.0;
@@ -767,12 +805,12 @@ __global__ __launch_bounds__(256) void k_qrcp(const QrcpDesc *__restrict__ items
         for (int tq = lane; tq <= i; tq += 64) {
           double s = 0.0;
           for (int r = 0; r < m; ++r) s += double(Q[(int64_t)r * m + tq]) * double(W[(int64_t)r * ldw + j]);
-          cw[wid][tq] = s;
+          cw(wid, tq) = s;
         }
         double acc = 0.0;
         for (int r = lane; r < m; r += 64) {
           double s = double(W[(int64_t)r * ldw + j]);
-          for (int tq = 0; tq <= i; ++tq) s -= double(Q[(int64_t)r * m + tq]) * cw[wid][tq];
+          for (int tq = 0; tq <= i; ++tq) s -= double(Q[(int64_t)r * m + tq]) * cw(wid, tq);
           acc += s * s;
         }
         acc = wave_sum(acc);
@@ -784,6 +822,7 @@ __global__ __launch_bounds__(256) void k_qrcp(const QrcpDesc *__restrict__ items
       __syncthreads();
     }
     k = i + 1;
+    rebuild();
   }
   __syncthreads();
   // ---- complete Q: Householder QR of Q[:, 0:k] -> reflectors V, tau
@@ -834,13 +873,16 @@ __global__ __launch_bounds__(256) void k_qrcp(const QrcpDesc *__restrict__ items
   if (tid == 0) *d.k_out = force_full ? m : k;
 }
 
-int launch_qrcp(FType t, const QrcpDesc *d_items, int n, double eps, int force_full,
-                hipStream_t st) {
+int launch_qrcp(FType t, const QrcpDesc *d_items, int n, double eps, int force_full, int maxm,
+                int maxgrp, hipStream_t st) {
   if (n <= 0) return SPAND_OK;
+  const int MS = std::max(maxm, 1);
+  const int GS = std::max(maxgrp, 1);
+  const size_t lds = size_t(6) * MS * sizeof(double) + size_t(GS) * sizeof(int);
   if (t == FType::F64)
-    hipLaunchKernelGGL(k_qrcp<double>, dim3(n), dim3(256), 0, st, d_items, eps, force_full);
+    hipLaunchKernelGGL(k_qrcp<double>, dim3(n), dim3(256), lds, st, d_items, eps, force_full, MS, GS);
   else
-    hipLaunchKernelGGL(k_qrcp<float>, dim3(n), dim3(256), 0, st, d_items, eps, force_full);
+    hipLaunchKernelGGL(k_qrcp<float>, dim3(n), dim3(256), lds, st, d_items, eps, force_full, MS, GS);
   SP_HIP(hipGetLastError());
   return SPAND_OK;
 }
