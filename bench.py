@@ -6,10 +6,13 @@ scaling, RRQR sparsification, merge; FP32 or FP64 factor), and the s-step
 GMRES solve (FP64 SpMV / Gram / CholQR / Hessenberg) to rtol 1e-8.
 value = N / (t_factor + t_solve) in DOF/s, inputs resident in HBM.
 
-Prints ONE JSON line (rank 0).  Extra fields: the roofline of the SpMV
-kernel (HBM-bound, bytes per launch from the BSR sizes, duration from HIP
-events around every SpMV launch in the timed region) and the CPU oracle
-timed on a bounded sample of the same operator family.
+Prints ONE JSON line.  Extra fields: the roofline of the dominant kernel
+(the rank-revealing QR: algorithmic bytes per launch from the factor's
+counters, duration from HIP events around every launch in the timed region;
+HBM traffic from the committed PMC measurement while its kernel source is
+unchanged), the SpMV roofline, a one-step comparison with the other factor
+precision, and the CPU oracle timed on a bounded sample of the same operator
+family.
 """
 from __future__ import annotations
 
@@ -25,10 +28,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 WORKLOADS = {
-    # name: (n, p, eps, L, s, restart)
+    # name: (n, p, eps, L, s, restart).  C3 uses L = 13: leaves of 3x3
+    # elements = 576 unknowns, the closest to the paper's ~512-unknown leaves
+    # (32 elements x 16 at p = 1); the Table 1/2 element rule would give L = 12.
     "c1": (16, 1, 1e-2, 4, 4, 40),
     "c2": (128, 2, 1e-2, 10, 5, 60),
-    "c3": (256, 3, 1e-2, 12, 5, 60),
+    "c3": (256, 3, 1e-2, 13, 5, 60),
+    "c5": (192, 2, 1e-2, 11, 5, 60),
 }
 HBM_PEAK_GBS = 8000.0
 
@@ -64,6 +70,20 @@ def cpu_baseline(p, eps, s, restart, budget_s=30.0):
             "t_factor_s": t1 - t0, "t_solve_s": t2 - t1}
 
 
+def pmc_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed PMC measurement
+    (profiles/pmc_traffic.json), or None if the kernel source changed since."""
+    import hashlib
+    try:
+        rec = json.load(open(os.path.join(ROOT, "profiles", "pmc_traffic.json")))
+        src = open(os.path.join(ROOT, rec["source"]), "rb").read()
+        if rec["kernel"] == kernel and hashlib.sha256(src).hexdigest() == rec["source_sha256"]:
+            return rec["traffic_bytes_per_launch"]
+    except (OSError, ValueError, KeyError):
+        pass
+    return None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -74,6 +94,10 @@ def main():
     ap.add_argument("--levels", type=int, default=0)
     ap.add_argument("--eps", type=float, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip the one-step FP64-factor comparison run")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB device copy (PMC byte-counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -81,6 +105,16 @@ def main():
         sys.exit(2)
 
     import torch
+
+    if args.calibrate_copy:
+        a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")    # 1 GiB
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration": "device copy", "bytes_read": a.numel() * 8,
+                          "bytes_written": b.numel() * 8, "launches": 3}))
+        return
 
     import paper_2101_01763_amd as sp
     from synth.dg_euler import DGConfig, make_problem
@@ -117,6 +151,7 @@ def main():
     torch.cuda.synchronize()
     tfs, tss, infos = [], [], []
     spmv_ms, spmv_n = 0.0, 0
+    qrcp_ms, qrcp_n, qrcp_bytes, qrcp_flops = 0.0, 0, 0.0, 0.0
     t_start = time.perf_counter()
     for k in range(args.steps):
         F, x, info, tf, ts = step()
@@ -126,6 +161,10 @@ def main():
         spmv_ms += info.t_spmv_ms
         spmv_n += info.n_spmv
         st = F.stats()
+        qrcp_ms += st["t_qrcp_ms"]
+        qrcp_n += st["n_qrcp"]
+        qrcp_bytes += st["qrcp_bytes"]
+        qrcp_flops += st["qrcp_flops"]
         log(f"step {k}: factor {tf * 1e3:.1f} ms solve {ts * 1e3:.1f} ms iters {info.iters} "
             f"relres {info.relres:.2e}")
         del F
@@ -142,6 +181,11 @@ def main():
     spmv_bytes = 8 * nnzb * bsz * bsz + 4 * nnzb + 4 * (cfg.K + 1) + 16 * cfg.N
     spmv_avg_ms = spmv_ms / max(spmv_n, 1)
     achieved = spmv_bytes / (spmv_avg_ms * 1e-3) / 1e9 if spmv_n else 0.0
+    # dominant kernel of the step: the rank-revealing QR (one launch per level)
+    q_avg_ms = qrcp_ms / max(qrcp_n, 1)
+    q_bytes_launch = qrcp_bytes / max(qrcp_n, 1)
+    q_ach = q_bytes_launch / (q_avg_ms * 1e-3) / 1e9 if qrcp_n else 0.0
+    traffic = pmc_traffic("k_qrcp")
     out = {
         "metric": "spaND factor+s-step GMRES time to rtol 1e-8, FP32- vs FP64-spaND; DOF/s",
         "value": value,
@@ -170,12 +214,35 @@ def main():
                          ("top_size", "factor_bytes", "factor_flops", "rank_avg", "rank_max")},
         "solve_phases_ms": {"spmv": infos[-1].t_spmv_ms, "apply": infos[-1].t_apply_ms,
                             "orth": infos[-1].t_orth_ms, "other": infos[-1].t_other_ms},
-        "roofline": {"kernel": "k_spmv (BSR SpMV, FP64)", "bound": "hbm",
-                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "bytes_per_launch": spmv_bytes, "avg_launch_ms": spmv_avg_ms,
-                     "launches": spmv_n},
+        "roofline": {"kernel": "k_qrcp (column-pivoted QR of [A_sn A_ns^T], all interfaces "
+                               "of one level per launch)", "bound": "hbm",
+                     "achieved": q_ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": q_ach / HBM_PEAK_GBS, "traffic": traffic,
+                     "bytes_per_launch": q_bytes_launch, "avg_launch_ms": q_avg_ms,
+                     "launches": qrcp_n,
+                     "algorithmic_bytes": "each W (m x ncols) read once + each Q (m x m) "
+                                          "written once, factor precision",
+                     "flops_per_launch": qrcp_flops / max(qrcp_n, 1)},
+        "roofline_spmv": {"kernel": "k_spmv (BSR SpMV, FP64)", "bound": "hbm",
+                          "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                          "frac": achieved / HBM_PEAK_GBS, "bytes_per_launch": spmv_bytes,
+                          "avg_launch_ms": spmv_avg_ms, "launches": spmv_n},
     }
+    if not args.no_compare:
+        other = "f64" if args.dtype == "f32" else "f32"
+        t0 = time.perf_counter()
+        F2 = sp.factor(dA, n, n, True, False, eps=eps, nlevels=L, dtype=other)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        x2, info2 = sp.solve(dA, db, F2, s=s, restart=m, rtol=1e-8)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        out[f"compare_{other}_factor"] = {
+            "t_factor_ms": 1e3 * (t1 - t0), "t_solve_ms": 1e3 * (t2 - t1),
+            "iters": info2.iters, "relres": info2.relres,
+            "rel_err_vs_xstar": float(torch.linalg.norm(x2 - dxs) / torch.linalg.norm(dxs)),
+            "dof_per_s": cfg.N / (t2 - t0)}
+        del F2
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, eps, s, m)
     print(json.dumps(out), flush=True)

@@ -110,6 +110,13 @@ typedef struct {
   double t_host_ms;                       /* host ND + planning              */
   double t_device_ms;                     /* device phases (event timed)     */
   double t_lu_ms, t_schur_ms, t_scale_ms, t_rrqr_ms, t_compress_ms;
+  /* the rank-revealing QR kernel alone (HIP events around each launch) */
+  double t_qrcp_ms;                       /* summed kernel time              */
+  int32_t n_qrcp;                         /* launches (one per level)        */
+  int32_t pad0;
+  double qrcp_bytes;                      /* algorithmic bytes: every W read
+                                             once, every Q written once     */
+  double qrcp_flops;                      /* 4mck - 2k^2(m+c) + 4k^3/3 sums  */
 } spand_factor_stats_t;
 
 typedef struct spand_factor_s *spand_factor_t;

@@ -72,7 +72,9 @@ class spand_factor_stats_t(C.Structure):
                 ("t_host_ms", C.c_double), ("t_device_ms", C.c_double),
                 ("t_lu_ms", C.c_double), ("t_schur_ms", C.c_double),
                 ("t_scale_ms", C.c_double), ("t_rrqr_ms", C.c_double),
-                ("t_compress_ms", C.c_double)]
+                ("t_compress_ms", C.c_double), ("t_qrcp_ms", C.c_double),
+                ("n_qrcp", C.c_int32), ("pad0", C.c_int32), ("qrcp_bytes", C.c_double),
+                ("qrcp_flops", C.c_double)]
 
 
 EXPORTS = ["spand_factor", "spand_apply", "spand_apply_T", "sstep_gmres_solve",
@@ -216,6 +218,8 @@ class Factor:
             "t_host_ms": st.t_host_ms, "t_device_ms": st.t_device_ms,
             "t_lu_ms": st.t_lu_ms, "t_schur_ms": st.t_schur_ms, "t_scale_ms": st.t_scale_ms,
             "t_rrqr_ms": st.t_rrqr_ms, "t_compress_ms": st.t_compress_ms,
+            "t_qrcp_ms": st.t_qrcp_ms, "n_qrcp": st.n_qrcp, "qrcp_bytes": st.qrcp_bytes,
+            "qrcp_flops": st.qrcp_flops,
         }
 
 

@@ -101,6 +101,9 @@ struct Factor {
   double ph_ms[PH_COUNT] = {0};
   bool timing = false;
   std::vector<std::pair<int, hipEvent_t>> events;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> qrcp_events;
+  double qrcp_ms = 0.0, qrcp_bytes = 0.0, qrcp_flops = 0.0;
+  int n_qrcp = 0;
 
   ~Factor();
   int dalloc(void **p, size_t bytes, bool keep);

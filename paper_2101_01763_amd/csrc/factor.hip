@@ -1013,7 +1013,17 @@ int Factor::sparsify(int l, const NDResult &nd, LevelState &S, LevelState &Nx) {
     }
     QrcpDesc *d_q;
     SP_TRY(upload(qd, &d_q, false));
+    hipEvent_t qe0 = nullptr, qe1 = nullptr;
+    if (timing) {
+      (void)hipEventCreate(&qe0);
+      (void)hipEventCreate(&qe1);
+      (void)hipEventRecord(qe0, stream);
+    }
     SP_TRY(launch_qrcp(ft, d_q, int(qd.size()), eps, eps == 0.0 ? 1 : 0, mq, mg, stream));
+    if (timing) {
+      (void)hipEventRecord(qe1, stream);
+      qrcp_events.push_back({qe0, qe1});
+    }
   }
   std::vector<int32_t> ks(ifs.size(), 0);
   if (!ifs.empty())
@@ -1025,6 +1035,9 @@ int Factor::sparsify(int l, const NDResult &nd, LevelState &S, LevelState &Nx) {
     for (size_t q = 0; q < ifs.size(); ++q) {
       kk[ifs[q]] = ks[q];
       rs.add(S.size[ifs[q]], ks[q]);
+      const double m = S.size[ifs[q]], c = ncols[ifs[q]], k = ks[q];
+      qrcp_bytes += (m * c + m * m) * double(tsz);
+      qrcp_flops += 4.0 * m * c * k - 2.0 * k * k * (m + c) + 4.0 * k * k * k / 3.0;
     }
     ranks.push_back(rs);
   }
@@ -1330,6 +1343,10 @@ void Factor::fill_stats(spand_factor_stats_t *st) const {
   st->t_scale_ms = ph_ms[PH_SCALE];
   st->t_rrqr_ms = ph_ms[PH_RRQR];
   st->t_compress_ms = ph_ms[PH_COMPRESS];
+  st->t_qrcp_ms = qrcp_ms;
+  st->n_qrcp = n_qrcp;
+  st->qrcp_bytes = qrcp_bytes;
+  st->qrcp_flops = qrcp_flops;
 }
 
 void Factor::collect_events() {
@@ -1340,6 +1357,14 @@ void Factor::collect_events() {
   }
   for (auto &e : events) (void)hipEventDestroy(e.second);
   events.clear();
+  for (auto &e : qrcp_events) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, e.first, e.second) == hipSuccess) qrcp_ms += ms;
+    (void)hipEventDestroy(e.first);
+    (void)hipEventDestroy(e.second);
+  }
+  n_qrcp += int(qrcp_events.size());
+  qrcp_events.clear();
 }
 
 }  // namespace spand
