@@ -112,6 +112,7 @@ struct Factor {
   template <typename D>
   int upload(const std::vector<D> &v, D **out, bool keep);
   int upload_slots(const std::vector<int32_t> &v, int32_t **out);
+  int upload_level_slots(LevelState &S);
   int gemm_batch(const std::vector<GemmDesc> &items);
   int copy_batch(const std::vector<CopyDesc> &items, int src_is_factor);
   int elim_batch(std::vector<ElimDesc> &items, int mode);

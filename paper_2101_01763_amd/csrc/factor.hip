@@ -109,6 +109,22 @@ int Factor::upload_slots(const std::vector<int32_t> &v, int32_t **out) {
   return upload(v, out, true);
 }
 
+// all slot lists of a level in one upload
+int Factor::upload_level_slots(LevelState &S) {
+  std::vector<int32_t> all;
+  std::vector<size_t> off(S.slots.size());
+  for (size_t c = 0; c < S.slots.size(); ++c) {
+    off[c] = all.size();
+    all.insert(all.end(), S.slots[c].begin(), S.slots[c].end());
+  }
+  int32_t *base = nullptr;
+  SP_TRY(upload(all, &base, true));
+  S.d_slots.assign(S.slots.size(), nullptr);
+  for (size_t c = 0; c < S.slots.size(); ++c)
+    if (!S.slots[c].empty()) S.d_slots[c] = base + off[c];
+  return SPAND_OK;
+}
+
 // ------------------------------------------------------------------ batched helpers
 int Factor::gemm_batch(const std::vector<GemmDesc> &items) {
   if (items.empty()) return SPAND_OK;
@@ -126,12 +142,31 @@ int Factor::gemm_batch(const std::vector<GemmDesc> &items) {
 
 int Factor::copy_batch(const std::vector<CopyDesc> &items, int src_is_factor) {
   if (items.empty()) return SPAND_OK;
+  // straight copies and transposed copies go to different kernels
+  std::vector<CopyDesc> st, tr;
   int64_t mx = 0;
-  for (auto &d : items) mx = std::max<int64_t>(mx, int64_t(d.rows) * d.cols);
-  CopyDesc *d_items;
-  SP_TRY(upload(items, &d_items, false));
-  // grid.x is limited to 2^31-1; chunk very long batches
-  return launch_copy(ft, src_is_factor, d_items, int(items.size()), mx, stream);
+  int mr = 0, mc = 0;
+  for (auto &d : items) {
+    if (d.trans) {
+      tr.push_back(d);
+      mr = std::max(mr, d.rows);
+      mc = std::max(mc, d.cols);
+    } else {
+      st.push_back(d);
+      mx = std::max<int64_t>(mx, int64_t(d.rows) * d.cols);
+    }
+  }
+  if (!st.empty()) {
+    CopyDesc *d_items;
+    SP_TRY(upload(st, &d_items, false));
+    SP_TRY(launch_copy(ft, src_is_factor, d_items, int(st.size()), mx, stream));
+  }
+  if (!tr.empty()) {
+    CopyDesc *d_items;
+    SP_TRY(upload(tr, &d_items, false));
+    SP_TRY(launch_copy_t(ft, src_is_factor, d_items, int(tr.size()), mr, mc, stream));
+  }
+  return SPAND_OK;
 }
 
 // Blocked elimination of a batch; items get their n/ncols/ld filled in.
@@ -206,11 +241,7 @@ int Factor::level0(const spand_bsr_t &A, const NDResult &nd, LevelState &S) {
     for (int e : cl[c].elems)
       for (int q = 0; q < b; ++q) sl.push_back(e * b + q);
   }
-  for (int c = 0; c < ncl; ++c) {
-    int32_t *sl;
-    SP_TRY(upload_slots(S.slots[c], &sl));
-    S.d_slots.push_back(sl);
-  }
+  SP_TRY(upload_level_slots(S));
   const size_t tsz = fsize(ft);
   const int64_t b2 = int64_t(b) * b;
   // ---- interface-pair blocks: adjacency among separator elements + fill
@@ -1194,11 +1225,7 @@ int Factor::sparsify(int l, const NDResult &nd, LevelState &S, LevelState &Nx) {
     SP_TRY(upload(ey, &d_e, false));
     SP_TRY(launch_eye(ft, d_e, int(ey.size()), maxk, stream));
   }
-  for (int I = 0; I < ncl1; ++I) {
-    int32_t *sl = nullptr;
-    if (!Nx.slots[I].empty()) SP_TRY(upload_slots(Nx.slots[I], &sl));
-    Nx.d_slots.push_back(sl);
-  }
+  SP_TRY(upload_level_slots(Nx));
   return SPAND_OK;
 }
 

@@ -185,6 +185,9 @@ int launch_gemm(FType t, const GemmDesc *d_items, const int32_t *d_tile_start, i
 // src double -> dst factor type (src_is_factor = 0) or factor -> factor (1)
 int launch_copy(FType t, int src_is_factor, const CopyDesc *d_items, int n, int64_t max_elems,
                 hipStream_t st);
+// transposed copies (trans = 1), 32 x 32 tiles through LDS
+int launch_copy_t(FType t, int src_is_factor, const CopyDesc *d_items, int n, int max_rows,
+                  int max_cols, hipStream_t st);
 // mode 0: Gauss-Jordan, partial pivoting; 1: LU (augmented), partial
 // pivoting; 2: Gauss-Jordan without pivoting.  Items sorted by n descending,
 // the first nactive have n > k.

@@ -165,6 +165,45 @@ int launch_copy(FType t, int src_is_factor, const CopyDesc *d_items, int n, int6
   return SPAND_OK;
 }
 
+// dst(r, c) = scale * src(c, r): tile (32 x 32) read along the source rows
+// into LDS, written along the destination rows (both coalesced).
+template <typename Ts, typename Td>
+__global__ __launch_bounds__(256) void k_copy_t(const CopyDesc *__restrict__ items, int tiles_c) {
+  const CopyDesc d = items[blockIdx.x];
+  const int tr = blockIdx.y / tiles_c, tc = blockIdx.y % tiles_c;
+  const int r0 = tr * 32, c0 = tc * 32;
+  if (r0 >= d.rows || c0 >= d.cols) return;
+  __shared__ Ts tile[32][33];
+  const Ts *src = (const Ts *)d.src;
+  Td *dst = (Td *)d.dst;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;    // 32 x 8
+  for (int k = ty; k < 32; k += 8) {
+    const int c = c0 + k, r = r0 + tx;                      // source row c, column r
+    tile[k][tx] = (c < d.cols && r < d.rows) ? src[(int64_t)c * d.lds + r] : Ts(0);
+  }
+  __syncthreads();
+  const Ts sc = Ts(d.scale);
+  for (int k = ty; k < 32; k += 8) {
+    const int r = r0 + k, c = c0 + tx;
+    if (r < d.rows && c < d.cols) dst[(int64_t)r * d.ldd + c] = Td(tile[tx][k] * sc);
+  }
+}
+
+int launch_copy_t(FType t, int src_is_factor, const CopyDesc *d_items, int n, int max_rows,
+                  int max_cols, hipStream_t st) {
+  if (n <= 0) return SPAND_OK;
+  const int tiles_c = int(cdiv(max_cols, 32));
+  dim3 grid(n, unsigned(cdiv(max_rows, 32) * tiles_c));   // tiles <= 64*64 < 65536
+  if (t == FType::F64)
+    hipLaunchKernelGGL((k_copy_t<double, double>), grid, dim3(256), 0, st, d_items, tiles_c);
+  else if (src_is_factor)
+    hipLaunchKernelGGL((k_copy_t<float, float>), grid, dim3(256), 0, st, d_items, tiles_c);
+  else
+    hipLaunchKernelGGL((k_copy_t<double, float>), grid, dim3(256), 0, st, d_items, tiles_c);
+  SP_HIP(hipGetLastError());
+  return SPAND_OK;
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_scale(const ScaleDesc *__restrict__ items) {
   const ScaleDesc d = items[blockIdx.x];
@@ -390,14 +429,14 @@ __global__ __launch_bounds__(ELIM_NT) void k_elim_panel(const ElimDesc *__restri
 template <typename T>
 __global__ __launch_bounds__(256) void k_elim_update(const ElimDesc *__restrict__ items, int k,
                                                      int lu_mode) {
-  const ElimDesc d = items[blockIdx.y];
+  const ElimDesc d = items[blockIdx.x];
   const int n = d.n;
   if (k >= n) return;
   const int w = min(ELIM_NB, n - k);
   const int c0 = lu_mode ? k : 0;
   const int ncol = d.ncols - c0;
   const int ntn = (ncol + 63) >> 6, ntm = (n + 63) >> 6;
-  const int t = blockIdx.x;
+  const int t = blockIdx.y;
   if (t >= ntm * ntn) return;
   const int m0 = (t / ntn) * 64, n0 = c0 + (t % ntn) * 64;
   __shared__ T Ps[ELIM_NB][65];
@@ -457,7 +496,7 @@ int launch_elim_step(FType t, const ElimDesc *d_items, int nactive, int k, int m
     else
       hipLaunchKernelGGL((k_elim_panel<double, 2>), dim3(nactive), dim3(ELIM_NT), 0, st, d_items, k, d_flag);
     SP_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_elim_update<double>, dim3(max_tiles, nactive), dim3(256), 0, st, d_items, k, lu);
+    hipLaunchKernelGGL(k_elim_update<double>, dim3(nactive, max_tiles), dim3(256), 0, st, d_items, k, lu);
   } else {
     if (mode == 0)
       hipLaunchKernelGGL((k_elim_panel<float, 0>), dim3(nactive), dim3(ELIM_NT), 0, st, d_items, k, d_flag);
@@ -466,7 +505,7 @@ int launch_elim_step(FType t, const ElimDesc *d_items, int nactive, int k, int m
     else
       hipLaunchKernelGGL((k_elim_panel<float, 2>), dim3(nactive), dim3(ELIM_NT), 0, st, d_items, k, d_flag);
     SP_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_elim_update<float>, dim3(max_tiles, nactive), dim3(256), 0, st, d_items, k, lu);
+    hipLaunchKernelGGL(k_elim_update<float>, dim3(nactive, max_tiles), dim3(256), 0, st, d_items, k, lu);
   }
   SP_HIP(hipGetLastError());
   return SPAND_OK;
