@@ -62,12 +62,16 @@ typedef struct {
 
 enum { SPAND_F64 = 0, SPAND_F32 = 1 };
 
+/* spand_opts_t.flags */
+#define SPAND_FLAG_NO_GRAPH 1   /* run the sweeps eagerly instead of replaying
+                                   a captured hipGraph                        */
+
 typedef struct {
   double eps;               /* RRQR tolerance epsilon (>= 0); 0 keeps all    */
   int32_t nlevels;          /* lmax; 0 -> round(log2(K/32)) + 1               */
   int32_t factor_dtype;     /* SPAND_F64 or SPAND_F32 (storage and compute of
                                the factor; vectors stay float64)            */
-  int32_t flags;            /* reserved, 0                                   */
+  int32_t flags;            /* SPAND_FLAG_* bits, 0 by default               */
 } spand_opts_t;
 
 typedef struct {
@@ -117,6 +121,9 @@ typedef struct {
   double qrcp_bytes;                      /* algorithmic bytes: every W read
                                              once, every Q written once     */
   double qrcp_flops;                      /* 4mck - 2k^2(m+c) + 4k^3/3 sums  */
+  double t_alloc_ms;                      /* host time in hipMalloc/hipFree
+                                             (blocks not found in the cache) */
+  int64_t resident_bytes;                 /* device memory the factor keeps  */
 } spand_factor_stats_t;
 
 typedef struct spand_factor_s *spand_factor_t;
@@ -183,6 +190,31 @@ int spand_bsr_spmv(const spand_bsr_t *A, int transpose, double alpha, const doub
 int spand_bsr_pattern_outer(const spand_bsr_t *pattern, const double *d_u,
                             const double *d_v, double alpha, double *d_out, void *stream);
 
+/*
+ * spand_factor_batched - factor n independent systems of possibly different
+ * sizes (A[i], grids[i], opts[i]).  The systems run concurrently on
+ * library-owned HIP streams from a pool of host workers (SPAND_BATCH_STREAMS,
+ * default 8); the call waits on `stream` first and makes `stream` wait for
+ * all of them at the end, so results are ordered on `stream` as usual.
+ * out[i] receives each handle (NULL for a system that failed).  Returns
+ * SPAND_OK, or the first negative status (out[] still holds the successful
+ * handles, which the caller destroys).
+ */
+int spand_factor_batched(int32_t n, const spand_bsr_t *A, const spand_grid_t *grids,
+                         const spand_opts_t *opts, void *stream, spand_factor_t *out);
+
+/*
+ * sstep_gmres_solve_batched - n independent s-step GMRES solves, concurrent
+ * like spand_factor_batched.  M[i] may be NULL; d_b[i], d_x[i] device
+ * float64 vectors (x0 in, solution out); opts[i]; st may be NULL or an
+ * array of n stats.  Returns SPAND_OK if every system converged, otherwise
+ * the most severe status (negative errors first, then SPAND_EBREAKDOWN,
+ * SPAND_ENOTCONV); per-system results are in st[i].
+ */
+int sstep_gmres_solve_batched(int32_t n, const spand_bsr_t *A, const spand_factor_t *M,
+                              const double *const *d_b, double *const *d_x,
+                              const sstep_opts_t *opts, sstep_stats_t *st, void *stream);
+
 /* spand_factor_stats - rank statistics per level (paper Figs. 4-5 report
  * ranks per level), apply bytes and algorithmic flops.  Host struct. */
 int spand_factor_stats(spand_factor_t F, spand_factor_stats_t *out);
@@ -210,6 +242,17 @@ int spand_nd(const spand_grid_t *grid, int32_t L, int32_t *L_out,
              int32_t *h_node_of_elem, int32_t *h_perm, int32_t *h_ncl,
              int32_t *h_cl_ptr, int32_t *h_cl_elems, int32_t *h_cl_key,
              int32_t *h_cl_interior);
+
+/*
+ * spand_pool_trim - return every device block the library keeps cached.
+ * Factorizations and solves take their device memory from a per-process
+ * cache of blocks (sizes rounded up to 2 MiB, at most SPAND_POOL_MB MiB
+ * cached, default 65536) so that repeated builds and solves neither call
+ * hipMalloc/hipFree again nor synchronise the device for each release.
+ * Blocks held by live factors are not affected.  Call with no library call
+ * running on another thread.  Always returns SPAND_OK.
+ */
+int spand_pool_trim(void);
 
 /* Status name ("SPAND_OK", ...). */
 const char *spand_status_string(int status);

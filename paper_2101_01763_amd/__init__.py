@@ -74,12 +74,15 @@ class spand_factor_stats_t(C.Structure):
                 ("t_scale_ms", C.c_double), ("t_rrqr_ms", C.c_double),
                 ("t_compress_ms", C.c_double), ("t_qrcp_ms", C.c_double),
                 ("n_qrcp", C.c_int32), ("pad0", C.c_int32), ("qrcp_bytes", C.c_double),
-                ("qrcp_flops", C.c_double)]
+                ("qrcp_flops", C.c_double), ("t_alloc_ms", C.c_double),
+                ("resident_bytes", C.c_int64)]
 
 
 EXPORTS = ["spand_factor", "spand_apply", "spand_apply_T", "sstep_gmres_solve",
            "spand_bsr_spmv", "spand_bsr_pattern_outer", "spand_factor_stats",
-           "spand_destroy", "spand_nd", "spand_status_string", "spand_last_error"]
+           "spand_destroy", "spand_nd", "spand_status_string", "spand_last_error",
+           "spand_factor_batched", "sstep_gmres_solve_batched", "spand_pool_trim"]
+SPAND_FLAG_NO_GRAPH = 1
 
 _lib = None
 
@@ -109,6 +112,12 @@ def lib():
         L.spand_factor_stats.argtypes = [vp, C.POINTER(spand_factor_stats_t)]
         L.spand_destroy.argtypes = [vp]
         L.spand_nd.argtypes = [C.POINTER(spand_grid_t), i32, C.POINTER(i32)] + [vp] * 7
+        L.spand_factor_batched.argtypes = [i32, C.POINTER(spand_bsr_t), C.POINTER(spand_grid_t),
+                                           C.POINTER(spand_opts_t), vp, C.POINTER(vp)]
+        L.sstep_gmres_solve_batched.argtypes = [i32, C.POINTER(spand_bsr_t), C.POINTER(vp),
+                                                C.POINTER(vp), C.POINTER(vp),
+                                                C.POINTER(sstep_opts_t), C.POINTER(sstep_stats_t), vp]
+        L.spand_pool_trim.argtypes = []
         L.spand_status_string.restype = C.c_char_p
         L.spand_status_string.argtypes = [C.c_int]
         L.spand_last_error.restype = C.c_char_p
@@ -220,13 +229,15 @@ class Factor:
             "t_rrqr_ms": st.t_rrqr_ms, "t_compress_ms": st.t_compress_ms,
             "t_qrcp_ms": st.t_qrcp_ms, "n_qrcp": st.n_qrcp, "qrcp_bytes": st.qrcp_bytes,
             "qrcp_flops": st.qrcp_flops,
+            "t_alloc_ms": st.t_alloc_ms, "resident_bytes": st.resident_bytes,
         }
 
 
 def factor(A: BSRMatrix, nx, ny, periodic_x=True, periodic_y=False, eps=1e-2, nlevels=0,
-           dtype="f64", val=None) -> Factor:
+           dtype="f64", val=None, graphs=True) -> Factor:
     g = spand_grid_t(nx, ny, int(periodic_x), int(periodic_y))
-    o = spand_opts_t(float(eps), int(nlevels), SPAND_F32 if dtype == "f32" else SPAND_F64, 0)
+    o = spand_opts_t(float(eps), int(nlevels), SPAND_F32 if dtype == "f32" else SPAND_F64,
+                     0 if graphs else SPAND_FLAG_NO_GRAPH)
     h = C.c_void_p()
     Ac = A.c(val)
     _check(lib().spand_factor(C.byref(Ac), C.byref(g), C.byref(o), _stream(), C.byref(h)))
@@ -268,6 +279,60 @@ def solve(A: BSRMatrix, b, M: Factor | None = None, s=5, restart=60, rtol=1e-8, 
                      st.t_total_ms, st.t_spmv_ms, st.t_apply_ms, st.t_orth_ms, st.t_other_ms,
                      st.n_spmv, st.n_apply)
     return x, info
+
+
+def _info(code, st):
+    return SolveInfo(code, st.iters, st.restarts, bool(st.converged), st.relres,
+                     list(st.hist[:st.n_hist]),
+                     [complex(st.shift_re[i], st.shift_im[i]) for i in range(st.n_shifts)],
+                     st.t_total_ms, st.t_spmv_ms, st.t_apply_ms, st.t_orth_ms, st.t_other_ms,
+                     st.n_spmv, st.n_apply)
+
+
+def levels_for(N, box_unknowns=1024):
+    """Number of ND levels whose leaf boxes hold about `box_unknowns`
+    unknowns: round(log2(N / box_unknowns)) + 1 (C2 -> 10, C3 -> 13, C5 -> 11)."""
+    import math
+    return max(1, int(round(math.log2(max(N, 1) / box_unknowns))) + 1)
+
+
+def factor_batched(systems, eps=1e-2, nlevels=0, dtype="f32", graphs=True):
+    """Factor several systems concurrently.  systems: list of
+    (BSRMatrix, nx, ny, periodic_x, periodic_y).  Returns a list of Factor."""
+    n = len(systems)
+    As = (spand_bsr_t * n)(*[s[0].c() for s in systems])
+    gs = (spand_grid_t * n)(*[spand_grid_t(s[1], s[2], int(s[3]), int(s[4])) for s in systems])
+    nl = nlevels if isinstance(nlevels, (list, tuple)) else [nlevels] * n
+    os_ = (spand_opts_t * n)(*[spand_opts_t(float(eps), int(nl[i]),
+                                            SPAND_F32 if dtype == "f32" else SPAND_F64,
+                                            0 if graphs else SPAND_FLAG_NO_GRAPH) for i in range(n)])
+    hs = (C.c_void_p * n)()
+    code = lib().spand_factor_batched(n, As, gs, os_, _stream(), hs)
+    fs = [Factor(C.c_void_p(hs[i]), systems[i][0].N) if hs[i] else None for i in range(n)]
+    _check(code)
+    return fs
+
+
+def solve_batched(As, bs, Ms=None, s=5, restart=60, rtol=1e-8, maxit=1000):
+    """Concurrent s-step GMRES solves; returns (list of x, list of SolveInfo)."""
+    import torch
+    n = len(As)
+    xs = [torch.zeros_like(b) for b in bs]
+    Ac = (spand_bsr_t * n)(*[A.c() for A in As])
+    Mh = (C.c_void_p * n)(*[(m._h.value if m is not None else None) for m in (Ms or [None] * n)])
+    pb = (C.c_void_p * n)(*[b.data_ptr() for b in bs])
+    px = (C.c_void_p * n)(*[x.data_ptr() for x in xs])
+    o = (sstep_opts_t * n)(*[sstep_opts_t(int(s), int(restart), int(maxit), 0, float(rtol))
+                             for _ in range(n)])
+    st = (sstep_stats_t * n)()
+    code = lib().sstep_gmres_solve_batched(n, Ac, Mh, pb, px, o, st, _stream())
+    _check(code, allow=(SPAND_OK, SPAND_ENOTCONV, SPAND_EBREAKDOWN))
+    return xs, [_info(code, st[i]) for i in range(n)]
+
+
+def pool_trim():
+    """Return the library's cached device blocks to the driver."""
+    _check(lib().spand_pool_trim())
 
 
 def spmv(A: BSRMatrix, x, transpose=False, alpha=1.0, beta=0.0, y=None, val=None):

@@ -5,6 +5,13 @@
 #include <cstring>
 #include <memory>
 #include <stdexcept>
+#include <atomic>
+#include <cstdlib>
+#include <thread>
+#include <vector>
+
+#include <functional>
+#include <string>
 
 #include "factor.h"
 
@@ -74,9 +81,13 @@ const char *spand_status_string(int s) {
 
 const char *spand_last_error(void) { return last_error(); }
 
-int spand_factor(const spand_bsr_t *A, const spand_grid_t *grid, const spand_opts_t *opts,
-                 void *stream, spand_factor_t *out) {
-  set_error("");
+}  // extern "C"
+
+// Validate, build, and (when `graphs`) capture the sweep graphs.  Batched
+// callers build on worker threads with graphs=false and capture afterwards,
+// once the workers have joined.
+static int factor_one(const spand_bsr_t *A, const spand_grid_t *grid, const spand_opts_t *opts,
+                      void *stream, spand_factor_t *out, bool graphs) {
   if (!out) {
     set_error("out is NULL");
     return SPAND_EINVAL;
@@ -121,8 +132,18 @@ int spand_factor(const spand_bsr_t *A, const spand_grid_t *grid, const spand_opt
     r = SPAND_EINVAL;
   }
   if (r != SPAND_OK) return r;
+  h->F.stream = nullptr;     // the build stream may be a worker's, destroyed later
+  if (graphs) SP_TRY(h->F.capture_graphs());
   *out = h.release();
   return SPAND_OK;
+}
+
+extern "C" {
+
+int spand_factor(const spand_bsr_t *A, const spand_grid_t *grid, const spand_opts_t *opts,
+                 void *stream, spand_factor_t *out) {
+  set_error("");
+  return factor_one(A, grid, opts, stream, out, true);
 }
 
 int spand_apply(spand_factor_t F, const double *d_in, double *d_out, void *stream) {
@@ -222,6 +243,118 @@ int spand_bsr_pattern_outer(const spand_bsr_t *P, const double *d_u, const doubl
     return SPAND_EINVAL;
   }
   return launch_pattern_outer(*P, d_u, d_v, alpha, d_out, (hipStream_t)stream);
+}
+
+// Run job(i, stream) for i < n on a pool of worker threads, each with its own
+// non-blocking stream (default priority) ordered after `stream`; `stream`
+// then waits for every worker stream.  Returns the per-item statuses.
+static int run_batched(int n, hipStream_t stream, const std::function<int(int, hipStream_t)> &job,
+                       std::vector<int> &status) {
+  status.assign(n, SPAND_OK);
+  int dev = 0;
+  SP_HIP(hipGetDevice(&dev));
+  int nw = 8;
+  if (const char *e = std::getenv("SPAND_BATCH_STREAMS")) nw = std::max(1, std::atoi(e));
+  nw = std::min(nw, n);
+  hipEvent_t start;
+  SP_HIP(hipEventCreateWithFlags(&start, hipEventDisableTiming));
+  SP_HIP(hipEventRecord(start, stream));
+  std::vector<hipStream_t> ss(nw, nullptr);
+  for (int w = 0; w < nw; ++w) {
+    SP_HIP(hipStreamCreateWithFlags(&ss[w], hipStreamNonBlocking));
+    SP_HIP(hipStreamWaitEvent(ss[w], start, 0));
+  }
+  std::atomic<int> next(0);
+  std::vector<std::string> errs(n);
+  auto worker = [&](int w) {
+    (void)hipSetDevice(dev);
+    for (;;) {
+      const int i = next.fetch_add(1);
+      if (i >= n) break;
+      int r;
+      try {
+        r = job(i, ss[w]);
+      } catch (const std::exception &ex) {
+        set_error("system %d: %s", i, ex.what());
+        r = SPAND_EINVAL;
+      }
+      status[i] = r;
+      if (r != SPAND_OK) errs[i] = last_error();
+    }
+  };
+  std::vector<std::thread> th;
+  for (int w = 1; w < nw; ++w) th.emplace_back(worker, w);
+  worker(0);
+  for (auto &t : th) t.join();
+  for (int w = 0; w < nw; ++w) {
+    hipEvent_t e;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess) {
+      (void)hipEventRecord(e, ss[w]);
+      (void)hipStreamWaitEvent(stream, e, 0);
+      (void)hipEventDestroy(e);
+    }
+  }
+  (void)hipStreamSynchronize(stream);
+  for (auto &q : ss) (void)hipStreamDestroy(q);
+  (void)hipEventDestroy(start);
+  for (int i = 0; i < n; ++i)
+    if (status[i] < 0) {
+      set_error("system %d: %s", i, errs[i].c_str());
+      break;
+    }
+  return SPAND_OK;
+}
+
+int spand_factor_batched(int32_t n, const spand_bsr_t *A, const spand_grid_t *grids,
+                         const spand_opts_t *opts, void *stream, spand_factor_t *out) {
+  set_error("");
+  if (n < 0 || (n > 0 && (!A || !grids || !opts || !out))) {
+    set_error("bad batched arguments");
+    return SPAND_EINVAL;
+  }
+  for (int i = 0; i < n; ++i) out[i] = nullptr;
+  std::vector<int> st;
+  SP_TRY(run_batched(n, (hipStream_t)stream, [&](int i, hipStream_t s) {
+    set_error("");
+    return factor_one(&A[i], &grids[i], &opts[i], (void *)s, &out[i], false);
+  }, st));
+  for (int i = 0; i < n; ++i)
+    if (st[i] < 0) return st[i];
+  for (int i = 0; i < n; ++i) {
+    const int r = out[i]->F.capture_graphs();
+    if (r != SPAND_OK) {
+      set_error("system %d: %s", i, std::string(last_error()).c_str());
+      return r;
+    }
+  }
+  return SPAND_OK;
+}
+
+int sstep_gmres_solve_batched(int32_t n, const spand_bsr_t *A, const spand_factor_t *M,
+                              const double *const *d_b, double *const *d_x,
+                              const sstep_opts_t *opts, sstep_stats_t *stv, void *stream) {
+  set_error("");
+  if (n < 0 || (n > 0 && (!A || !d_b || !d_x || !opts))) {
+    set_error("bad batched arguments");
+    return SPAND_EINVAL;
+  }
+  std::vector<int> st;
+  SP_TRY(run_batched(n, (hipStream_t)stream, [&](int i, hipStream_t s) {
+    return sstep_gmres_solve(&A[i], M ? M[i] : nullptr, d_b[i], d_x[i], &opts[i],
+                             stv ? &stv[i] : nullptr, (void *)s);
+  }, st));
+  int worst = SPAND_OK;
+  for (int i = 0; i < n; ++i) {
+    if (st[i] < 0) return st[i];
+    if (st[i] == SPAND_EBREAKDOWN) worst = SPAND_EBREAKDOWN;
+    else if (st[i] == SPAND_ENOTCONV && worst == SPAND_OK) worst = SPAND_ENOTCONV;
+  }
+  return worst;
+}
+
+int spand_pool_trim(void) {
+  pool_trim();
+  return SPAND_OK;
 }
 
 int spand_factor_stats(spand_factor_t F, spand_factor_stats_t *out) {

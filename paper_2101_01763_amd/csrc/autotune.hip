@@ -1,0 +1,150 @@
+// Autotuner for the two tile-shape knobs of the hot memory-bound kernels:
+//   * BSR SpMV: lanes per scalar row (4, 8 or 16), per block size b;
+//   * preconditioner sweeps: rows per workgroup band of the GEMV (32, 64,
+//     128), per factor precision and block size.
+// Each candidate is timed with HIP events on the caller's stream on the real
+// operands (median of 3), once per key and process.  Results are kept in a
+// process-wide table and, when SPAND_AUTOTUNE_CACHE names a file, appended to
+// it ("spmv <bs> <lanes>" / "gemv <ftype> <bs> <rows>" lines) and read back
+// by later processes.
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "factor.h"
+
+namespace spand {
+
+static std::mutex g_tune_mu;
+static bool g_cache_loaded = false;
+static std::map<int, int> g_spmv;                    // bs -> lanes
+static std::map<std::pair<int, int>, int> g_gemv;    // (ftype, bs) -> rows
+
+static void load_cache_locked() {
+  if (g_cache_loaded) return;
+  g_cache_loaded = true;
+  const char *path = std::getenv("SPAND_AUTOTUNE_CACHE");
+  if (!path || !*path) return;
+  FILE *f = std::fopen(path, "r");
+  if (!f) return;
+  char kind[16];
+  int a, b, c;
+  while (std::fscanf(f, "%15s", kind) == 1) {
+    if (std::string(kind) == "spmv" && std::fscanf(f, "%d %d", &a, &b) == 2) {
+      g_spmv[a] = b;
+      set_spmv_lanes(a, b);
+    } else if (std::string(kind) == "gemv" && std::fscanf(f, "%d %d %d", &a, &b, &c) == 3) {
+      g_gemv[{a, b}] = c;
+    } else {
+      break;
+    }
+  }
+  std::fclose(f);
+}
+
+static void append_cache(const std::string &line) {
+  const char *path = std::getenv("SPAND_AUTOTUNE_CACHE");
+  if (!path || !*path) return;
+  FILE *f = std::fopen(path, "a");
+  if (!f) return;
+  std::fprintf(f, "%s\n", line.c_str());
+  std::fclose(f);
+}
+
+template <typename F>
+static float time_median(hipStream_t st, F &&fn) {
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return 1e30f;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return 1e30f;
+  }
+  std::vector<float> t;
+  (void)fn();   // warm
+  for (int r = 0; r < 3; ++r) {
+    (void)hipEventRecord(e0, st);
+    if (fn() != SPAND_OK) {
+      t.push_back(1e30f);
+      continue;
+    }
+    (void)hipEventRecord(e1, st);
+    (void)hipEventSynchronize(e1);
+    float ms = 1e30f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    t.push_back(ms);
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  std::sort(t.begin(), t.end());
+  return t[t.size() / 2];
+}
+
+int autotune_spmv(const spand_bsr_t &A, double *x, double *y, hipStream_t st) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  load_cache_locked();
+  if (g_spmv.count(A.bs)) return SPAND_OK;
+  int best = 8;
+  float bt = 1e30f;
+  for (int G : {4, 8, 16}) {
+    if (2 * G > A.bs && G != 4) continue;        // a lane group wider than a block row
+    const float t = time_median(st, [&]() {
+      return launch_spmv_g(A, G, 1.0, x, 0.0, y, nullptr, 0.0, nullptr, 0.0, st);
+    });
+    if (t < bt) {
+      bt = t;
+      best = G;
+    }
+  }
+  g_spmv[A.bs] = best;
+  set_spmv_lanes(A.bs, best);
+  append_cache("spmv " + std::to_string(A.bs) + " " + std::to_string(best));
+  return SPAND_OK;
+}
+
+int tuned_gemv_rows(FType t, int bs) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  load_cache_locked();
+  auto it = g_gemv.find({int(t), bs});
+  return it == g_gemv.end() ? 0 : it->second;
+}
+
+// Times the forward sweep GEMV of one level with each band height and keeps
+// the fastest for (precision, bs).  `sets` builds a GemvSet for a band height.
+int autotune_gemv(FType t, int bs, const std::function<int(int, GemvSet &)> &build,
+                  double *in, double *out, hipStream_t st, int *rows_out) {
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    load_cache_locked();
+    auto it = g_gemv.find({int(t), bs});
+    if (it != g_gemv.end()) {
+      *rows_out = it->second;
+      return SPAND_OK;
+    }
+  }
+  int best = 64;
+  float bt = 1e30f;
+  for (int R : {32, 64, 128}) {
+    GemvSet g;
+    SP_TRY(build(R, g));
+    const float tm = time_median(st, [&]() {
+      return launch_gemv(t, g.d_items, g.d_chunks, g.nchunks, in, out, 1.0, 0.0, st);
+    });
+    if (tm < bt) {
+      bt = tm;
+      best = R;
+    }
+  }
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_gemv[{int(t), bs}] = best;
+  append_cache("gemv " + std::to_string(int(t)) + " " + std::to_string(bs) + " " +
+               std::to_string(best));
+  *rows_out = best;
+  return SPAND_OK;
+}
+
+}  // namespace spand

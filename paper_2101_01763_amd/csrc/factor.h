@@ -1,5 +1,6 @@
 // spaND factor object (host side) and its per-level apply plan.
 #pragma once
+#include <functional>
 #include <map>
 #include <vector>
 
@@ -41,7 +42,7 @@ struct GemvSet {
   int32_t *d_slots = nullptr;
   int64_t nslots = 0;
   int set(Factor &F, std::vector<GemvDesc> items, const std::vector<const std::vector<int32_t> *> &oslots,
-          int trans);
+          int trans, int rows = 0);
 };
 
 inline int ld4(int n) { return (n + 3) & ~3; }
@@ -70,7 +71,7 @@ struct RankStat {
 
 enum { PH_GATHER = 0, PH_LU, PH_SCHUR, PH_SCALE, PH_RRQR, PH_COMPRESS, PH_END, PH_COUNT };
 
-// chunked bump allocator over hipMalloc
+// chunked bump allocator over the device block cache
 struct Bump {
   std::vector<std::pair<char *, size_t>> chunks;
   size_t used = 0;
@@ -89,7 +90,6 @@ struct Factor {
   std::vector<int32_t> h_rowptr, h_colind;
   std::vector<ApplyLevel> lv;
   Bump keep, temp, next_temp;   // next_temp: next level's trailing blocks
-  std::vector<void *> keep_allocs, temp_allocs;
   size_t keep_bytes = 0;
   int32_t *d_iota = nullptr;
   double *d_tbuf = nullptr;
@@ -103,9 +103,17 @@ struct Factor {
   std::vector<std::pair<int, hipEvent_t>> events;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> qrcp_events;
   double qrcp_ms = 0.0, qrcp_bytes = 0.0, qrcp_flops = 0.0;
+  double alloc_ms = 0.0;
   int n_qrcp = 0;
 
+  int gemv_rows = 64;              // band height of the sweep GEMVs (autotuned)
+  bool use_graphs = true;          // replay the sweeps from captured hipGraphs
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};
+  double *d_xg = nullptr;          // the graphs' fixed input/output vector
   ~Factor();
+  int sweeps(double *x, int transpose, hipStream_t st);
+  int capture(int transpose);
+  int capture_graphs();
   int dalloc(void **p, size_t bytes, bool keep);
   int dalloc_next(void **p, size_t bytes);
   void free_temp();
@@ -133,5 +141,10 @@ struct DiagDesc {
   int32_t n, ld;
 };
 int launch_diag_split(FType t, const DiagDesc *d_items, int n, hipStream_t st);
+
+int autotune_spmv(const spand_bsr_t &A, double *x, double *y, hipStream_t st);
+int tuned_gemv_rows(FType t, int bs);
+int autotune_gemv(FType t, int bs, const std::function<int(int, GemvSet &)> &build, double *in,
+                  double *out, hipStream_t st, int *rows_out);
 
 }  // namespace spand

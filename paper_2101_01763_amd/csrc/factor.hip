@@ -25,7 +25,9 @@
 // R' = [[A_ss^-1, -A_ss^-1 A_sn],[0, I]]  (L' A R' = diag(I, Schur)).
 #include <algorithm>
 #include <chrono>
+#include <mutex>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <numeric>
 #include <set>
@@ -49,15 +51,11 @@ struct PlanArena {
 int Bump::alloc(void **p, size_t n, size_t chunk) {
   n = (std::max<size_t>(n, 1) + 255) & ~size_t(255);
   if (chunks.empty() || used + n > chunks.back().second) {
-    const size_t sz = std::max(n, chunk);
     void *q;
-    hipError_t e = hipMalloc(&q, sz);
-    if (e != hipSuccess) {
-      set_error("hipMalloc(%zu bytes) failed: %s", sz, hipGetErrorString(e));
-      return SPAND_ENOMEM;
-    }
-    chunks.push_back({(char *)q, sz});
-    bytes += sz;
+    size_t got = 0;
+    SP_TRY(pool_alloc(&q, std::max(n, chunk), &got));
+    chunks.push_back({(char *)q, got});
+    bytes += got;
     used = 0;
   }
   *p = chunks.back().first + used;
@@ -65,8 +63,9 @@ int Bump::alloc(void **p, size_t n, size_t chunk) {
   return SPAND_OK;
 }
 
+// Callers have synchronised the work that used the chunks.
 void Bump::release() {
-  for (auto &c : chunks) (void)hipFree(c.first);
+  for (auto &c : chunks) pool_release(c.first, c.second);
   chunks.clear();
   used = 0;
   bytes = 0;
@@ -89,6 +88,10 @@ void Factor::free_temp() {
 }
 
 Factor::~Factor() {
+  // a build that failed may have left work queued on its chunks
+  (void)hipDeviceSynchronize();
+  for (auto &g : gexec)
+    if (g) (void)hipGraphExecDestroy(g);
   temp.release();
   next_temp.release();
   keep.release();
@@ -516,6 +519,14 @@ int Factor::level0(const spand_bsr_t &A, const NDResult &nd, LevelState &S) {
       os.push_back(&S.slots[s]);
       apply_bytes += double(S.size[s]) * S.size[s] * tsz * 2;
     }
+    // band height of the sweep GEMVs: autotuned once per (precision, b)
+    {
+      void *tin;
+      SP_TRY(dalloc(&tin, size_t(N) * 8, false));
+      SP_HIP(hipMemsetAsync(tin, 0, size_t(N) * 8, stream));
+      auto build_set = [&](int R, GemvSet &g) { return g.set(*this, gv, os, 0, R); };
+      SP_TRY(autotune_gemv(ft, bs, build_set, (double *)tin, d_tbuf, stream, &gemv_rows));
+    }
     SP_TRY(AL.inv.set(*this, gv, os, 0));
     SP_TRY(AL.invT.set(*this, gv, os, 1));
     apply_bytes += double(ncp) * 2 * b2 * tsz * 2;
@@ -533,10 +544,10 @@ int PullSet::set(Factor &F, const std::vector<PullGroup> &G, const std::vector<P
 }
 
 int GemvSet::set(Factor &F, std::vector<GemvDesc> items,
-                 const std::vector<const std::vector<int32_t> *> &oslots, int trans) {
+                 const std::vector<const std::vector<int32_t> *> &oslots, int trans, int rows) {
   n = int(items.size());
   if (!n) return SPAND_OK;
-  const int R = trans ? 256 : 64;
+  const int R = trans ? 256 : (rows > 0 ? rows : F.gemv_rows);
   std::vector<GemvChunk> ch;
   std::vector<int32_t> sl;
   for (int i = 0; i < n; ++i) {
@@ -1232,6 +1243,7 @@ int Factor::sparsify(int l, const NDResult &nd, LevelState &S, LevelState &Nx) {
 // ------------------------------------------------------------------ driver
 int Factor::build(const spand_bsr_t &A, const spand_grid_t &g, const spand_opts_t &o) {
   auto t0 = std::chrono::steady_clock::now();
+  const double drv0 = pool_driver_ms();
   bs = A.bs;
   K = A.n_brows;
   N = int64_t(K) * bs;
@@ -1266,6 +1278,13 @@ int Factor::build(const spand_bsr_t &A, const spand_grid_t &g, const spand_opts_
   SP_TRY(vec_iota(d_iota, N, stream));
   SP_TRY(dalloc(&p, size_t(N) * 8, true));
   d_tbuf = (double *)p;
+  SP_TRY(dalloc(&p, size_t(N) * 8, true));
+  d_xg = (double *)p;
+  use_graphs = (o.flags & SPAND_FLAG_NO_GRAPH) == 0 && !std::getenv("SPAND_NO_GRAPH");
+  {
+    const int tr = tuned_gemv_rows(ft, bs);
+    if (tr > 0) gemv_rows = tr;
+  }
   SP_TRY(dalloc(&p, 64, true));
   d_flag = (int *)p;
   SP_HIP(hipMemsetAsync(d_flag, 0, 64, stream));
@@ -1291,6 +1310,7 @@ int Factor::build(const spand_bsr_t &A, const spand_grid_t &g, const spand_opts_
   SP_HIP(hipStreamSynchronize(stream));
   temp.release();
   next_temp.release();
+  alloc_ms = pool_driver_ms() - drv0;
   int flag = 0;
   SP_HIP(hipMemcpy(&flag, d_flag, 4, hipMemcpyDeviceToHost));
   collect_events();
@@ -1305,9 +1325,7 @@ int Factor::build(const spand_bsr_t &A, const spand_grid_t &g, const spand_opts_
 // y = M^-1 r:  forward over levels applies L' (interiors: x_n -= A_ns A_ss^-1 x_s)
 // and F_s (interfaces); backward applies B_s and R' (x_s = A_ss^-1 (x_s - A_sn x_n)).
 // y = M^-T r:  forward applies R'^T and B_s^T, backward F_s^T and L'^T.
-int Factor::apply(const double *in, double *out, int transpose, hipStream_t st) {
-  if (out != in) SP_HIP(hipMemcpyAsync(out, in, size_t(N) * 8, hipMemcpyDeviceToDevice, st));
-  double *x = out;
+int Factor::sweeps(double *x, int transpose, hipStream_t st) {
   auto inplace = [&](const GemvSet &g) -> int {
     if (!g.n) return SPAND_OK;
     SP_TRY(launch_gemv(ft, g.d_items, g.d_chunks, g.nchunks, x, d_tbuf, 1.0, 0.0, st));
@@ -1347,6 +1365,60 @@ int Factor::apply(const double *in, double *out, int transpose, hipStream_t st) 
   return SPAND_OK;
 }
 
+// Capture the sweeps on the fixed vector d_xg once; replays need one launch.
+int Factor::capture(int transpose) {
+  hipStream_t cs;
+  SP_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  hipGraph_t g = nullptr;
+  int r = SPAND_OK;
+  if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    set_error("hipStreamBeginCapture failed");
+    r = SPAND_EHIP;
+  }
+  if (r == SPAND_OK) {
+    const int rs = sweeps(d_xg, transpose, cs);
+    const hipError_t e = hipStreamEndCapture(cs, &g);
+    if (rs != SPAND_OK) r = rs;
+    else if (e != hipSuccess || !g) {
+      set_error("hipStreamEndCapture failed: %s", hipGetErrorString(e));
+      r = SPAND_EHIP;
+    }
+  }
+  if (r == SPAND_OK && hipGraphInstantiate(&gexec[transpose], g, nullptr, nullptr, 0) != hipSuccess) {
+    set_error("hipGraphInstantiate failed");
+    gexec[transpose] = nullptr;
+    r = SPAND_EHIP;
+  }
+  if (g) (void)hipGraphDestroy(g);
+  (void)hipStreamDestroy(cs);
+  return r;
+}
+
+// Both sweeps are captured once, right after the factorization, by the thread
+// that asked for it and with no worker thread of this library alive: a
+// capture never overlaps another thread's hipMalloc/hipFree/stream creation
+// issued from here.  The mutex keeps captures of concurrent host callers apart.
+static std::mutex g_capture_mu;
+
+int Factor::capture_graphs() {
+  if (!use_graphs) return SPAND_OK;
+  std::lock_guard<std::mutex> lk(g_capture_mu);
+  for (int t = 0; t < 2; ++t)
+    if (!gexec[t]) SP_TRY(capture(t));
+  return SPAND_OK;
+}
+
+int Factor::apply(const double *in, double *out, int transpose, hipStream_t st) {
+  if (!use_graphs || !gexec[transpose]) {
+    if (out != in) SP_HIP(hipMemcpyAsync(out, in, size_t(N) * 8, hipMemcpyDeviceToDevice, st));
+    return sweeps(out, transpose, st);
+  }
+  SP_HIP(hipMemcpyAsync(d_xg, in, size_t(N) * 8, hipMemcpyDeviceToDevice, st));
+  SP_HIP(hipGraphLaunch(gexec[transpose], st));
+  SP_HIP(hipMemcpyAsync(out, d_xg, size_t(N) * 8, hipMemcpyDeviceToDevice, st));
+  return SPAND_OK;
+}
+
 void Factor::fill_stats(spand_factor_stats_t *st) const {
   std::memset(st, 0, sizeof(*st));
   st->nlevels = L;
@@ -1374,6 +1446,8 @@ void Factor::fill_stats(spand_factor_stats_t *st) const {
   st->n_qrcp = n_qrcp;
   st->qrcp_bytes = qrcp_bytes;
   st->qrcp_flops = qrcp_flops;
+  st->t_alloc_ms = alloc_ms;
+  st->resident_bytes = int64_t(keep.bytes);
 }
 
 void Factor::collect_events() {

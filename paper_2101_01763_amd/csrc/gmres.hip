@@ -59,6 +59,8 @@ static void eig2(double a, double b, double c, double d, std::complex<double> &l
 static bool hessenberg_eigs(std::vector<double> H, int n, std::vector<std::complex<double>> &ev) {
   auto h = [&](int i, int j) -> double & { return H[size_t(i) * n + j]; };
   ev.assign(n, 0.0);
+  for (double v : H)
+    if (!std::isfinite(v)) return false;
   int hi = n - 1, iter = 0;
   const double eps = 2.220446049250313e-16;
   while (hi >= 0) {
@@ -184,6 +186,7 @@ static std::vector<Slot> leja_slots(std::vector<std::complex<double>> vals, int 
       const std::complex<double> zp(z.real(), std::fabs(z.imag())), zm = std::conj(zp);
       for (auto target : {zp, zm}) {
         int bi = 0;
+        if (vals.empty()) break;
         for (int i = 1; i < int(vals.size()); ++i)
           if (std::abs(vals[i] - target) < std::abs(vals[bi] - target)) bi = i;
         vals.erase(vals.begin() + bi);
@@ -242,16 +245,15 @@ int sstep_solve(const spand_bsr_t &A0, Factor *M, const double *b, double *x,
   const double rtol = o.rtol;
   const int maxit = o.maxit;
   const int tr = o.transpose != 0;
-  std::vector<void *> allocs;
+  std::vector<std::pair<void *, size_t>> allocs;
   auto cleanup = [&]() {
-    for (void *p : allocs) (void)hipFree(p);
+    (void)hipStreamSynchronize(stream);     // nothing queued may still use them
+    for (auto &a : allocs) pool_release(a.first, a.second);
   };
   auto alloc = [&](void **p, size_t bytes) -> int {
-    if (hipMalloc(p, std::max<size_t>(bytes, 256)) != hipSuccess) {
-      set_error("hipMalloc(%zu) failed in sstep_gmres_solve", bytes);
-      return SPAND_ENOMEM;
-    }
-    allocs.push_back(*p);
+    size_t got = 0;
+    SP_TRY(pool_alloc(p, bytes, &got));
+    allocs.push_back({*p, got});
     return SPAND_OK;
   };
 #define GTRY(e)            \
@@ -288,6 +290,8 @@ int sstep_solve(const spand_bsr_t &A0, Factor *M, const double *b, double *x,
   const int64_t nchunk = std::max<int64_t>(cdiv(N, TS_CHUNK), cdiv(N, 4096));
   GTRY(alloc(&pPart, size_t(nchunk) * TS_MAXA * TS_MAXS * 8));
   double *Q = (double *)pQ, *Z = (double *)pZ, *Rv = (double *)pR, *part = (double *)pPart;
+  if (hipMemsetAsync(Z, 0, size_t(N) * 8, stream) != hipSuccess) GTRY(SPAND_EHIP);
+  GTRY(autotune_spmv(A, Z, Rv, stream));     // lanes per row, once per block size
   KrylovDev *Kd = (KrylovDev *)pK;
   const int ld = KRY_MMAX;
   PhaseTimer tm;
@@ -339,7 +343,6 @@ int sstep_solve(const spand_bsr_t &A0, Factor *M, const double *b, double *x,
     relres = 0.0;
   }
   const double tol = rtol * bnorm;
-  bool first = true;
   while (!converged) {
     // r = b - A x, beta = ||r||
     if (hipMemcpyAsync(Rv, b, size_t(N) * 8, hipMemcpyDeviceToDevice, stream) != hipSuccess)
@@ -361,7 +364,7 @@ int sstep_solve(const spand_bsr_t &A0, Factor *M, const double *b, double *x,
     GTRY(kry_init_cycle(Kd, m, stream));
     int k = 0, j = 0;
     bool done = false;
-    if (first && slots.empty()) {
+    if (slots.empty()) {
       for (int jj = 0; jj < s; ++jj) {
         double *w = Q + (jj + 1) * N;
         GTRY(Ahat(Q + jj * N, w, nullptr, 0.0, nullptr, 0.0));
@@ -387,11 +390,18 @@ int sstep_solve(const spand_bsr_t &A0, Factor *M, const double *b, double *x,
           break;
         }
       }
-      if (!done) {
-        std::vector<double> Hh(size_t(s) * s);
-        for (int i = 0; i < s; ++i) GTRY(d2h(&Hh[size_t(i) * s], Kd->H + i * ld, size_t(s) * 8));
-        std::vector<std::complex<double>> ev;
-        if (!hessenberg_eigs(Hh, s, ev)) ev.assign(s, 0.0);
+      // Shifts are fixed here even when the cycle already ended inside these
+      // steps (then all zero, a monomial basis): a later cycle whose true
+      // residual is still above the tolerance goes straight to the blocks.
+      {
+        std::vector<std::complex<double>> ev(s, 0.0);
+        if (!done) {
+          std::vector<double> Hh(size_t(s) * s);
+          for (int i = 0; i < s; ++i) GTRY(d2h(&Hh[size_t(i) * s], Kd->H + i * ld, size_t(s) * 8));
+          if (!hessenberg_eigs(Hh, s, ev)) ev.assign(s, 0.0);
+        }
+        for (auto &z : ev)
+          if (!std::isfinite(z.real()) || !std::isfinite(z.imag())) z = 0.0;
         slots = leja_slots(ev, s);
         while (int(slots.size()) < s) slots.push_back({0, 0.0, 0.0});
         std::vector<double> Bb(size_t(s + 1) * s, 0.0);
@@ -410,7 +420,6 @@ int sstep_solve(const spand_bsr_t &A0, Factor *M, const double *b, double *x,
       }
       j = s;
     }
-    first = false;
     while (!done && j < m) {
       for (int q = 1; q <= s; ++q) {
         const Slot &sl = slots[q - 1];

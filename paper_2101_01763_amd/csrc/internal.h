@@ -41,6 +41,16 @@ struct Status {
     if (r_ < 0) return r_;                                                  \
   } while (0)
 
+// ----------------------------------------------------------------- device memory
+// Cached device blocks (pool.hip).  pool_alloc rounds the size up and
+// reports the block's real size in *got; pool_release takes that size back.
+// Release a block only after the work that used it has completed.
+int pool_alloc(void **p, size_t bytes, size_t *got);
+void pool_release(void *p, size_t bytes);
+void pool_trim();
+size_t pool_cached_bytes();
+double pool_driver_ms();   // calling thread's cumulative hipMalloc/hipFree time
+
 // ----------------------------------------------------------------- ND
 struct NDCluster {
   int32_t node, box;

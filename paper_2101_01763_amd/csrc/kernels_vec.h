@@ -12,6 +12,11 @@ constexpr int TS_MAXA = 160;      // largest restart + s + 1
 
 int launch_pull2(FType t, const PullGroup *d_groups, int ngroups, const PullItem *d_items,
                  const double *in, double *out, double alpha, double beta, hipStream_t st);
+int launch_spmv_g(const spand_bsr_t &A, int G, double alpha, const double *x, double beta,
+                  double *y, const double *z, double gz, const double *w, double gw,
+                  hipStream_t st);
+void set_spmv_lanes(int bs, int G);
+int get_spmv_lanes(int bs);
 int launch_bsr_transpose(const spand_bsr_t &A, double *outv, int *d_flag, hipStream_t st);
 int launch_pattern_outer(const spand_bsr_t &P, const double *u, const double *v, double alpha,
                          double *out, hipStream_t st);

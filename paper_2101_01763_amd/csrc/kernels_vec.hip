@@ -21,6 +21,12 @@ __device__ inline T wsum(T v) {
 // One workgroup per band of output rows (GemvChunk).  The input is staged
 // in LDS.  Bands of one item may run concurrently, so in == out is not
 // allowed (in-place sweeps write a scratch vector and copy back).
+// Products accumulate in float64 for either factor precision: a float32
+// factor stays one fixed linear operator (rounding the vector to float32 in
+// every sweep would make M^-1 differ between applications, which
+// right-preconditioned GMRES does not tolerate: the update M^-1 Q y would no
+// longer match the basis and the true residual would stall above the
+// estimate).
 template <typename T>
 struct Vec16;
 template <>
@@ -56,19 +62,19 @@ __global__ __launch_bounds__(256) void k_gemv(const GemvDesc *__restrict__ items
     for (int rr = wid; rr < ch.nrows; rr += 4) {
       const int r = ch.row0 + rr;
       const T *row = A + (int64_t)r * d.lda;
-      T acc = T(0);
+      double acc = 0.0;
       for (int c = lane * VN; c < cv; c += 64 * VN) {
         const typename VW::V v = *reinterpret_cast<const typename VW::V *>(row + c);
         T e[VN];
         VW::get(v, e);
 #pragma unroll
-        for (int q = 0; q < VN; ++q) acc += e[q] * T(xs[c + q]);
+        for (int q = 0; q < VN; ++q) acc += double(e[q]) * xs[c + q];
       }
-      for (int c = cv + lane; c < d.cols; c += 64) acc += row[c] * T(xs[c]);
+      for (int c = cv + lane; c < d.cols; c += 64) acc += double(row[c]) * xs[c];
       acc = wsum(acc);
       if (lane == 0) {
         const int o = d.oslot[r];
-        double v = alpha * double(acc);
+        double v = alpha * acc;
         if (beta != 0.0) v += beta * out[o];
         out[o] = v;
       }
@@ -76,10 +82,10 @@ __global__ __launch_bounds__(256) void k_gemv(const GemvDesc *__restrict__ items
   } else {
     const int r = ch.row0 + tid;
     if (tid < ch.nrows) {
-      T acc = T(0);
-      for (int c = 0; c < d.cols; ++c) acc += A[(int64_t)c * d.lda + r] * T(xs[c]);
+      double acc = 0.0;
+      for (int c = 0; c < d.cols; ++c) acc += double(A[(int64_t)c * d.lda + r]) * xs[c];
       const int o = d.oslot[r];
-      double v = alpha * double(acc);
+      double v = alpha * acc;
       if (beta != 0.0) v += beta * out[o];
       out[o] = v;
     }
@@ -140,16 +146,16 @@ __global__ __launch_bounds__(256) void k_pull(const PullGroup *__restrict__ grou
     if (!p.trans) {
       for (int r = wid; r < p.rows; r += 4) {
         const T *row = B + (int64_t)r * p.ldb;
-        T a = T(0);
-        for (int c = lane; c < p.cols; c += 64) a += row[c] * T(xs[c]);
+        double a = 0.0;
+        for (int c = lane; c < p.cols; c += 64) a += double(row[c]) * xs[c];
         a = wsum(a);
-        if (lane == 0) acc[r] += double(a);
+        if (lane == 0) acc[r] += a;
       }
     } else {
       for (int r = tid; r < p.rows; r += 256) {
-        T a = T(0);
-        for (int c = 0; c < p.cols; ++c) a += B[(int64_t)c * p.ldb + r] * T(xs[c]);
-        acc[r] += double(a);
+        double a = 0.0;
+        for (int c = 0; c < p.cols; ++c) a += double(B[(int64_t)c * p.ldb + r]) * xs[c];
+        acc[r] += a;
       }
     }
   }
@@ -182,8 +188,10 @@ int launch_pull(FType t, const PullGroup *d_groups, int ngroups, const PullItem 
 
 // ------------------------------------------------------------------ SpMV
 // y = alpha*A x + beta*y + gz*z + gw*w  (row-major b x b BSR blocks).
-// 8 lanes per scalar row, 16-byte loads: one instruction of a lane group
-// reads 128 contiguous bytes of the row segment.
+// G lanes per scalar row, 16-byte loads: one instruction of a lane group
+// reads 16*G contiguous bytes of the row segment.  G is picked per block
+// size by the autotuner (4, 8 or 16).
+template <int G>
 __global__ __launch_bounds__(256) void k_spmv(int n_brows, int bs, const int32_t *__restrict__ rowptr,
                                               const int32_t *__restrict__ colind,
                                               const double *__restrict__ val,
@@ -191,9 +199,10 @@ __global__ __launch_bounds__(256) void k_spmv(int n_brows, int bs, const int32_t
                                               double beta, double *__restrict__ y,
                                               const double *__restrict__ z, double gz,
                                               const double *__restrict__ w, double gw) {
+  constexpr int RPB = 256 / G;
   const int64_t N = (int64_t)n_brows * bs;
-  const int64_t R = (int64_t)blockIdx.x * 32 + (threadIdx.x >> 3);
-  const int sub = threadIdx.x & 7;
+  const int64_t R = (int64_t)blockIdx.x * RPB + (threadIdx.x / G);
+  const int sub = threadIdx.x % G;
   double acc = 0.0;
   if (R < N) {
     const int I = int(R / bs), r = int(R % bs);
@@ -201,15 +210,14 @@ __global__ __launch_bounds__(256) void k_spmv(int n_brows, int bs, const int32_t
     for (int t = rowptr[I]; t < rowptr[I + 1]; ++t) {
       const double *rowv = val + (int64_t)t * b2 + (int64_t)r * bs;
       const double *xv = x + (int64_t)colind[t] * bs;
-      for (int c = sub * 2; c < bs; c += 16) {
+      for (int c = sub * 2; c < bs; c += 2 * G) {
         const double2 a = *reinterpret_cast<const double2 *>(rowv + c);
         acc += a.x * xv[c] + a.y * xv[c + 1];
       }
     }
   }
-  acc += __shfl_xor(acc, 4, 64);
-  acc += __shfl_xor(acc, 2, 64);
-  acc += __shfl_xor(acc, 1, 64);
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
   if (R < N && sub == 0) {
     double v = alpha * acc;
     if (beta != 0.0) v += beta * y[R];
@@ -219,17 +227,40 @@ __global__ __launch_bounds__(256) void k_spmv(int n_brows, int bs, const int32_t
   }
 }
 
+static int g_spmv_lanes[65] = {0};   // per block size; 0 = not tuned (default 8)
+
+void set_spmv_lanes(int bs, int G) {
+  if (bs >= 0 && bs <= 64) g_spmv_lanes[bs] = G;
+}
+int get_spmv_lanes(int bs) {
+  const int g = (bs >= 0 && bs <= 64) ? g_spmv_lanes[bs] : 0;
+  return g ? g : 8;
+}
+
+int launch_spmv_g(const spand_bsr_t &A, int G, double alpha, const double *x, double beta,
+                  double *y, const double *z, double gz, const double *w, double gw,
+                  hipStream_t st) {
+  const int64_t N = (int64_t)A.n_brows * A.bs;
+  if (N == 0) return SPAND_OK;
+  const unsigned nb = (unsigned)cdiv(N, 256 / G);
+  if (G == 4)
+    hipLaunchKernelGGL(k_spmv<4>, dim3(nb), dim3(256), 0, st, A.n_brows, A.bs, A.d_rowptr,
+                       A.d_colind, A.d_val, x, alpha, beta, y, z, gz, w, gw);
+  else if (G == 16)
+    hipLaunchKernelGGL(k_spmv<16>, dim3(nb), dim3(256), 0, st, A.n_brows, A.bs, A.d_rowptr,
+                       A.d_colind, A.d_val, x, alpha, beta, y, z, gz, w, gw);
+  else
+    hipLaunchKernelGGL(k_spmv<8>, dim3(nb), dim3(256), 0, st, A.n_brows, A.bs, A.d_rowptr,
+                       A.d_colind, A.d_val, x, alpha, beta, y, z, gz, w, gw);
+  SP_HIP(hipGetLastError());
+  return SPAND_OK;
+}
+
 int launch_spmv(const spand_bsr_t &A, int transpose, double alpha, const double *x, double beta,
                 double *y, const double *z, double gz, const double *w, double gw,
                 hipStream_t st) {
   (void)transpose;  // transposed products use an explicitly transposed copy
-  const int64_t N = (int64_t)A.n_brows * A.bs;
-  if (N == 0) return SPAND_OK;
-  const int64_t nb = cdiv(N, 32);
-  hipLaunchKernelGGL(k_spmv, dim3((unsigned)nb), dim3(256), 0, st, A.n_brows, A.bs, A.d_rowptr,
-                     A.d_colind, A.d_val, x, alpha, beta, y, z, gz, w, gw);
-  SP_HIP(hipGetLastError());
-  return SPAND_OK;
+  return launch_spmv_g(A, get_spmv_lanes(A.bs), alpha, x, beta, y, z, gz, w, gw, st);
 }
 
 // transposed copy: block t = (I, J) goes to the position of (J, I),

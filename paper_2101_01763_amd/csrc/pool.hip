@@ -1,0 +1,131 @@
+// Process-wide cache of device memory blocks, per device.
+//
+// A factorization allocates and releases scratch level by level (hundreds of
+// 256 MiB chunks for a 4M-unknown problem) and a solve allocates its Krylov
+// basis every call.  Going to hipMalloc/hipFree for each costs host time,
+// makes every release synchronise the device, and makes the driver clear
+// fresh pages.  Released blocks are kept here instead and handed out again
+// to a request of the same rounded size (best fit, at most twice the size
+// asked for).  Sizes are rounded up to 2 MiB.  The cache holds at most
+// SPAND_POOL_MB MiB (default 65536) per process; beyond that blocks go back
+// to the driver.  spand_pool_trim() returns every cached block.
+//
+// A block may be released only once no queued work uses it: every caller
+// synchronises the stream that used the block before releasing it.
+#include <algorithm>
+#include <chrono>
+#include <cstdlib>
+#include <map>
+#include <mutex>
+
+#include "internal.h"
+
+namespace spand {
+
+namespace {
+struct Pool {
+  std::mutex mu;
+  std::map<int, std::multimap<size_t, void *>> free;   // device -> size -> block
+  size_t cached = 0;
+};
+Pool &pool() {
+  static Pool *p = new Pool();    // never destroyed: usable from other static destructors
+  return *p;
+}
+size_t pool_cap() {
+  static const size_t cap = [] {
+    const char *e = std::getenv("SPAND_POOL_MB");
+    const long long mb = e ? std::atoll(e) : 65536;
+    return size_t(mb < 0 ? 0 : mb) << 20;
+  }();
+  return cap;
+}
+constexpr size_t kRound = size_t(2) << 20;
+thread_local double t_driver_ms = 0.0;     // this thread's time in hipMalloc/hipFree
+struct DriverTimer {
+  std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
+  ~DriverTimer() {
+    t_driver_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  }
+};
+}  // namespace
+
+double pool_driver_ms() { return t_driver_ms; }
+
+size_t pool_round(size_t bytes) { return (std::max<size_t>(bytes, 1) + kRound - 1) / kRound * kRound; }
+
+int pool_alloc(void **p, size_t bytes, size_t *got) {
+  const size_t sz = pool_round(bytes);
+  int dev = 0;
+  SP_HIP(hipGetDevice(&dev));
+  {
+    Pool &P = pool();
+    std::lock_guard<std::mutex> lk(P.mu);
+    auto &fl = P.free[dev];
+    auto it = fl.lower_bound(sz);
+    if (it != fl.end() && it->first <= 2 * sz) {
+      *p = it->second;
+      *got = it->first;
+      P.cached -= it->first;
+      fl.erase(it);
+      return SPAND_OK;
+    }
+  }
+  DriverTimer tm;
+  hipError_t e = hipMalloc(p, sz);
+  if (e != hipSuccess) {
+    // give the cache back to the driver and try once more
+    pool_trim();
+    e = hipMalloc(p, sz);
+  }
+  if (e != hipSuccess) {
+    *p = nullptr;
+    set_error("hipMalloc(%zu bytes) failed: %s", sz, hipGetErrorString(e));
+    return SPAND_ENOMEM;
+  }
+  *got = sz;
+  return SPAND_OK;
+}
+
+// `bytes` is the size pool_alloc reported in *got.
+void pool_release(void *p, size_t bytes) {
+  if (!p) return;
+  const size_t sz = bytes;
+  int dev = 0;
+  hipPointerAttribute_t at;
+  if (hipPointerGetAttributes(&at, p) == hipSuccess) dev = at.device;
+  else (void)hipGetDevice(&dev);
+  Pool &P = pool();
+  {
+    std::lock_guard<std::mutex> lk(P.mu);
+    if (P.cached + sz <= pool_cap()) {
+      P.free[dev].emplace(sz, p);
+      P.cached += sz;
+      return;
+    }
+  }
+  DriverTimer tm;
+  (void)hipFree(p);
+}
+
+void pool_trim() {
+  Pool &P = pool();
+  std::lock_guard<std::mutex> lk(P.mu);
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  for (auto &d : P.free) {
+    (void)hipSetDevice(d.first);
+    for (auto &b : d.second) (void)hipFree(b.second);
+    d.second.clear();
+  }
+  (void)hipSetDevice(cur);
+  P.cached = 0;
+}
+
+size_t pool_cached_bytes() {
+  Pool &P = pool();
+  std::lock_guard<std::mutex> lk(P.mu);
+  return P.cached;
+}
+
+}  // namespace spand

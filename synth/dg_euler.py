@@ -463,3 +463,18 @@ def modal_to_vector(uh: np.ndarray) -> np.ndarray:
 
 def vector_to_modal(cfg: DGConfig, x: np.ndarray) -> np.ndarray:
     return x.reshape(cfg.K, (cfg.p + 1) ** 2, 4)
+
+
+def batch_configs(n_systems: int = 64, seed: int = 0, nmin: int = 32, nmax: int = 96):
+    """Uneven batch: grids n ~ U{nmin..nmax} (square), p ~ U{1,2,3},
+    M ~ U[0.3, 0.7], alpha ~ U[-4, 4] degrees, drawn from default_rng(seed);
+    system i uses seed + i for its own phases and x*."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n_systems):
+        n = int(rng.integers(nmin, nmax + 1))
+        p = int(rng.integers(1, 4))
+        mach = float(rng.uniform(0.3, 0.7))
+        alpha = float(rng.uniform(-4.0, 4.0))
+        out.append(DGConfig(n=n, p=p, mach=mach, alpha_deg=alpha, seed=seed + i))
+    return out

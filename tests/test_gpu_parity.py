@@ -118,6 +118,24 @@ def test_sstep_unpreconditioned():
     assert np.max(np.abs(h - ho) / ho) <= 1e-6
 
 
+def test_sstep_restart_after_early_convergence():
+    """With an exact (single-level FP64) factor the Givens estimate can meet
+    a tolerance near rounding level inside the first s (MGS) steps while the
+    true residual does not, so another cycle starts.  As in the oracle the
+    shifts are then all zero (monomial basis) and that cycle runs its blocks.
+    Over a few tolerances at least one must take this path; none may fail."""
+    cfg, A, As, xs, b, dA = _problem(8, 1)
+    F = sp.factor(dA, 8, 8, True, False, eps=0.0, nlevels=1, dtype="f64")
+    took = 0
+    for rtol in (1e-14, 1e-15, 3e-16, 1e-16):
+        x, info = sp.solve(dA, _dev(b), F, s=5, restart=60, rtol=rtol, maxit=40)
+        assert info.relres <= 1e-13, rtol
+        assert np.linalg.norm(_host(x) - xs) <= 1e-10 * np.linalg.norm(xs)
+        if info.restarts >= 2 and all(z == 0 for z in info.shifts):
+            took += 1
+    assert took >= 1
+
+
 @pytest.mark.parametrize("s,eps", [(4, 1e-2), (5, 1e-1), (1, 1e-1), (2, 1e-2)])
 def test_sstep_parity_fp64(s, eps):
     n, p, L = 16, 1, 4
@@ -162,3 +180,40 @@ def test_adjoint_gradient_dense():
     _, lam, gb, gv = adjoint.dense_gradient(As, A.rowptr, A.colind, A.bs, b, g)
     assert np.linalg.norm(_host(bt.grad) - gb) <= 1e-10 * np.linalg.norm(gb)
     assert np.linalg.norm(_host(vals.grad) - gv) <= 1e-10 * np.linalg.norm(gv)
+
+
+def test_graph_replay_matches_eager():
+    """Captured sweeps replayed many times, with eager work and syncs between
+    replays, give exactly the eager results (apply and apply_T)."""
+    cfg, A, As, xs, b, dA = _problem(16, 2)
+    Fg = sp.factor(dA, 16, 16, True, False, eps=1e-2, nlevels=4, dtype="f32", graphs=True)
+    Fe = sp.factor(dA, 16, 16, True, False, eps=1e-2, nlevels=4, dtype="f32", graphs=False)
+    rng = np.random.default_rng(12)
+    for rep in range(5):
+        r = _dev(rng.standard_normal(cfg.N))
+        ye = _host(Fe.apply(r))
+        _ = sp.spmv(dA, r)                       # unrelated eager work in between
+        torch.cuda.synchronize()
+        yg = _host(Fg.apply(r))
+        assert np.array_equal(ye, yg), rep
+        assert np.array_equal(_host(Fe.apply_T(r)), _host(Fg.apply_T(r))), rep
+
+
+def test_batched_matches_individual():
+    from synth.dg_euler import batch_configs
+    cfgs = batch_configs(6, seed=3, nmin=8, nmax=14)
+    systems, rhs, sols = [], [], []
+    for c in cfgs:
+        A, xs, b, _ = make_problem(c)
+        systems.append((sp.BSRMatrix.from_numpy(A.rowptr, A.colind, A.val), c.n, c.n, True, False))
+        rhs.append(_dev(b))
+        sols.append(xs)
+    Ls = [sp.levels_for(c.N) for c in cfgs]
+    Fs = sp.factor_batched(systems, eps=1e-2, nlevels=Ls, dtype="f32")
+    xs_b, infos = sp.solve_batched([s[0] for s in systems], rhs, Fs, s=5, restart=60, rtol=1e-8)
+    for i, (sysd, b, xstar) in enumerate(zip(systems, rhs, sols)):
+        F = sp.factor(sysd[0], sysd[1], sysd[2], True, False, eps=1e-2, nlevels=Ls[i], dtype="f32")
+        x1, i1 = sp.solve(sysd[0], b, F, s=5, restart=60, rtol=1e-8)
+        assert infos[i].converged and i1.converged
+        assert infos[i].iters == i1.iters
+        assert np.array_equal(_host(x1), _host(xs_b[i])), i
