@@ -1048,7 +1048,7 @@ int Factor::sparsify(int l, const NDResult &nd, LevelState &S, LevelState &Nx) {
       mq = std::max(mq, Qd.m);
       mg = std::max(mg, Qd.ldw / 2);     // column groups of 2 (FP64) or 4 (FP32)
     }
-    const size_t lds = size_t(6) * mq * 8 + size_t(mg) * 4;
+    const size_t lds = qrcp_lds_bytes(mq, mg);
     if (lds > 64 * 1024) {
       set_error("RRQR problem too large for one workgroup (m=%d, %d column groups)", mq, mg);
       return SPAND_EINVAL;

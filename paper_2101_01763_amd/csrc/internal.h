@@ -170,8 +170,8 @@ struct SchurGroup {
 struct QrcpDesc {
   const void *W;       // m x ncols row-major
   void *Q;             // m x m row-major output
-  void *V;             // m x m workspace (reflectors, column t contiguous: V[t*m + r])
-  double *tau;         // [m]
+  void *V;             // m x m workspace: kept vectors q_t = V[t*m ..], then completion terms
+  double *tau;         // [m] completion signs
   double *vn1;         // [ncols]
   double *vn2;         // [ncols]
   int32_t *sel;        // [ncols] selected flags
@@ -213,6 +213,7 @@ struct RowGatherDesc {
 int launch_row_gather(FType t, const RowGatherDesc *d_items, int n, int max_rows, hipStream_t st);
 int launch_schur_elem(FType t, int bs, const double *bsr_val, const SchurGroup *d_groups,
                       int ngroups, const SchurItem *d_items, hipStream_t st);
+size_t qrcp_lds_bytes(int maxm, int maxgrp);   // dynamic LDS of one QRCP workgroup
 int launch_qrcp(FType t, const QrcpDesc *d_items, int n, double eps, int force_full, int maxm,
                 int maxgrp, hipStream_t st);
 // dst rows/cols scaling: dst[r, c] *= rs[r] * cs[c] (either may be null)

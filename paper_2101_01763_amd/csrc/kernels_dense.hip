@@ -625,13 +625,75 @@ int launch_schur_elem(FType t, int bs, const double *bsr_val, const SchurGroup *
 }
 
 // ------------------------------------------------------------------ QRCP
+// Workgroup GEMM used by the QRCP completion: for i < M, n < N,
+// epi(i, n, sum_l A(i, l) B(l, n)), 64 x 64 output tiles, K in chunks of 16,
+// 4 x 4 outputs per thread, float64 accumulation.  As/Bs: 1024 doubles each
+// in LDS.  BK: load the B tile with l fastest (B(l, n) contiguous in l).
+template <bool BK, typename FA, typename FB, typename FE>
+__device__ inline void wg_gemm(int M, int N, int K, FA A, FB B, FE epi, double *As, double *Bs) {
+  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+  for (int i0 = 0; i0 < M; i0 += 64)
+    for (int n0 = 0; n0 < N; n0 += 64) {
+      double acc[4][4];
+#pragma unroll
+      for (int p = 0; p < 4; ++p)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[p][q] = 0.0;
+      for (int l0 = 0; l0 < K; l0 += 16) {
+        __syncthreads();
+        for (int e = tid; e < 1024; e += 256) {
+          const int i = e & 63, l = e >> 6;
+          As[l * 64 + i] = (i0 + i < M && l0 + l < K) ? A(i0 + i, l0 + l) : 0.0;
+        }
+        for (int e = tid; e < 1024; e += 256) {
+          const int n = BK ? (e >> 4) : (e & 63), l = BK ? (e & 15) : (e >> 6);
+          Bs[l * 64 + n] = (n0 + n < N && l0 + l < K) ? B(l0 + l, n0 + n) : 0.0;
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int l = 0; l < 16; ++l) {
+          double a[4], b[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            a[q] = As[l * 64 + ty * 4 + q];
+            b[q] = Bs[l * 64 + tx * 4 + q];
+          }
+#pragma unroll
+          for (int p = 0; p < 4; ++p)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[p][q] += a[p] * b[q];
+        }
+      }
+#pragma unroll
+      for (int p = 0; p < 4; ++p)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int i = i0 + ty * 4 + p, n = n0 + tx * 4 + q;
+          if (i < M && n < N) epi(i, n, acc[p][q]);
+        }
+    }
+  __syncthreads();
+}
+
 // Rank-revealing QR with column pivoting of W (m x nc, row-major), one
-// workgroup per interface.  Pivoted Gram-Schmidt with re-orthogonalisation
-// (equal in exact arithmetic to Householder QRCP: same pivots, same |R_ii|,
-// same leading columns of Q up to sign); column norms are downdated with the
-// LAPACK-style safeguard and recomputed when cancellation is detected.
-// Stops at the first |R_ii| <= eps |R_00|.  The kept orthonormal columns are
-// then completed to a full orthogonal Q by Householder QR of themselves.
+// workgroup per interface (Eq. 12).
+//  1. Column norms of W.
+//  2. Pivoted Gram-Schmidt with re-orthogonalisation (equal in exact
+//     arithmetic to Householder QRCP: same pivots, same |R_ii|, same leading
+//     columns of Q up to sign).  Column norms are downdated with the
+//     LAPACK-style safeguard and recomputed when cancellation is detected.
+//     Residual norms never grow, so a column already at or below the
+//     stopping threshold eps |R_00| can never be a pivot: it leaves every
+//     later pass.  Stops at the first |R_ii| <= eps |R_00| (or at the
+//     numerical rank, |R_ii| <= 1e-12 |R_00|, whatever eps).  The kept
+//     vectors are rows of V (q_t = V[t m .. t m + m)).
+//  3. Completion to an orthogonal Q by Householder reconstruction (Ballard
+//     et al., "Reconstructing Householder vectors from tall-skinny QR",
+//     IPDPS 2014): with Q_c = [q_0 .. q_{k-1}] = [Q1; Q2] (Q1 k x k) and
+//     signs S fixed while inverting Q1 - S (every pivot gets modulus >= 1),
+//     H = I + (Q_c S - E) [I, G2^T] with G2 = Q2 (Q1 - S)^-1, E = [I_k; 0],
+//     is orthogonal and H E = Q_c S.  Output Q = [Q_c | H(:, k:m)].
+//     Rows k.. of V receive G2 S; tau receives S.
 template <typename T>
 __global__ __launch_bounds__(256) void k_qrcp(const QrcpDesc *__restrict__ items, double eps,
                                               int force_full, int MS, int GS) {
@@ -643,22 +705,63 @@ __global__ __launch_bounds__(256) void k_qrcp(const QrcpDesc *__restrict__ items
   const int ngrp = (nc + VN - 1) / VN;
   const T *W = (const T *)d.W;
   T *Q = (T *)d.Q;
-  T *V = (T *)d.V;
+  T *Qt = (T *)d.V;
   double *vn1 = d.vn1, *vn2 = d.vn2;
   int *sel = d.sel;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-  // dynamic LDS: u[MS], cbuf[MS], cw[4][MS] (MS = largest m of the launch),
-  // then the list of active column groups (GS = largest group count)
+  // dynamic LDS: u[MS], cbuf[MS] (or the two GEMM tiles), then two lists of
+  // active column groups (GS entries each)
   extern __shared__ double qsm[];
+  const int ldsd = max(2 * MS, 2048);
   double *u = qsm, *cbuf = qsm + MS;
-  auto cw = [&](int w, int t) -> double & { return qsm[(2 + w) * MS + t]; };
-  int *act = reinterpret_cast<int *>(qsm + 6 * MS);
-  __shared__ int s_nact;
+  int *act = reinterpret_cast<int *>(qsm + ldsd), *act2 = act + GS;
+  __shared__ int s_nact, s_n2, s_j, s_nflag, s_nf;
+  __shared__ int s_fl[64];
   __shared__ double red[16];
-  __shared__ int s_j;
-  __shared__ int s_nflag;
+  __shared__ double s_piv;
   const double tol3z = 1.4901161193847656e-08;  // sqrt(2^-52)
-  // column norms, VN adjacent columns per thread with 16-byte loads
+
+  // c[t] = q_t . x for t < n (one wave per 4 consecutive t)
+  auto qdots = [&](const double *x, int n, double *c) {
+    for (int t0 = wid * 4; t0 < n; t0 += 16) {
+      const T *q0 = Qt + (int64_t)t0 * m;
+      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+      for (int r = lane; r < m; r += 64) {
+        const double xr = x[r];
+        a0 += double(q0[r]) * xr;
+        if (t0 + 1 < n) a1 += double(q0[m + r]) * xr;
+        if (t0 + 2 < n) a2 += double(q0[2 * m + r]) * xr;
+        if (t0 + 3 < n) a3 += double(q0[3 * m + r]) * xr;
+      }
+      a0 = wave_sum(a0);
+      a1 = wave_sum(a1);
+      a2 = wave_sum(a2);
+      a3 = wave_sum(a3);
+      if (lane == 0) {
+        c[t0] = a0;
+        if (t0 + 1 < n) c[t0 + 1] = a1;
+        if (t0 + 2 < n) c[t0 + 2] = a2;
+        if (t0 + 3 < n) c[t0 + 3] = a3;
+      }
+    }
+    __syncthreads();
+  };
+  // x -= sum_{t<n} c[t] q_t
+  auto qsub = [&](double *x, int n, const double *c) {
+    for (int r = tid; r < m; r += 256) {
+      double s0 = 0.0, s1 = 0.0;
+      int t = 0;
+      for (; t + 2 <= n; t += 2) {
+        s0 += double(Qt[(int64_t)t * m + r]) * c[t];
+        s1 += double(Qt[(int64_t)(t + 1) * m + r]) * c[t + 1];
+      }
+      if (t < n) s0 += double(Qt[(int64_t)t * m + r]) * c[t];
+      x[r] -= s0 + s1;
+    }
+    __syncthreads();
+  };
+
+  // ---- 1. column norms, VN adjacent columns per thread with 16-byte loads
   for (int g = tid; g < ngrp; g += 256) {
     double acc[VN];
 #pragma unroll
@@ -693,10 +796,6 @@ __global__ __launch_bounds__(256) void k_qrcp(const QrcpDesc *__restrict__ items
     }
   }
   __syncthreads();
-  // Pruning: residual column norms never grow, so a column whose norm is
-  // already <= eps*|R_00| (= eps * largest column norm) can never be chosen
-  // before the rank test stops the factorisation.  Such columns leave every
-  // later pass (the pivots, ranks and Q are unchanged).
   double cmax = 0.0;
   for (int j = tid; j < nc; j += 256) cmax = fmax(cmax, vn1[j]);
 #pragma unroll
@@ -704,30 +803,33 @@ __global__ __launch_bounds__(256) void k_qrcp(const QrcpDesc *__restrict__ items
   if (lane == 0) red[wid] = cmax;
   __syncthreads();
   cmax = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+  // |R_00| is the largest column norm; the 1e-4 margin keeps a column whose
+  // norm ties the threshold up to rounding
   const double thr = force_full ? 0.0 : eps * cmax * (1.0 - 1e-4);
-  auto rebuild = [&]() {
-    if (tid == 0) s_nact = 0;
-    __syncthreads();
-    for (int g = tid; g < ngrp; g += 256) {
-      bool a = false;
+  auto live_group = [&](int g) {
+    bool a = false;
 #pragma unroll
-      for (int q = 0; q < VN; ++q) {
-        const int j = g * VN + q;
-        if (j < nc && !sel[j] && vn1[j] > thr) a = true;
-      }
-      if (a) act[atomicAdd(&s_nact, 1)] = g;
+    for (int q = 0; q < VN; ++q) {
+      const int j = g * VN + q;
+      if (j < nc && !sel[j] && vn1[j] > thr) a = true;
     }
-    __syncthreads();
+    return a;
   };
-  rebuild();
+  if (tid == 0) s_nact = 0;
+  __syncthreads();
+  for (int g = tid; g < ngrp; g += 256)
+    if (live_group(g)) act[atomicAdd(&s_nact, 1)] = g;
+  __syncthreads();
+
+  // ---- 2. pivoted Gram-Schmidt
   double R00 = 0.0;
   int k = 0;
   const int imax = min(m, nc);
   for (int i = 0; i < imax; ++i) {
-    // ---- pivot: largest remaining column norm, ties -> smallest index
+    // pivot: largest remaining column norm, ties -> smallest index
+    const int nact = s_nact;
     double bv = -1.0;
     int bi = INT_MAX;
-    const int nact = s_nact;
     for (int qa = tid; qa < nact; qa += 256) {
       const int g = act[qa];
 #pragma unroll
@@ -740,8 +842,8 @@ __global__ __launch_bounds__(256) void k_qrcp(const QrcpDesc *__restrict__ items
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
-      double ov = __shfl_xor(bv, o, 64);
-      int oi = __shfl_xor(bi, o, 64);
+      const double ov = __shfl_xor(bv, o, 64);
+      const int oi = __shfl_xor(bi, o, 64);
       if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
     }
     __shared__ double rv[4];
@@ -760,156 +862,214 @@ __global__ __launch_bounds__(256) void k_qrcp(const QrcpDesc *__restrict__ items
     if (js == INT_MAX) break;
     for (int r = tid; r < m; r += 256) u[r] = double(W[(int64_t)r * ldw + js]);
     __syncthreads();
-    // ---- two classical Gram-Schmidt passes against q_0..q_{i-1}
+    // two classical Gram-Schmidt passes against q_0..q_{i-1}
     for (int pass = 0; pass < 2 && i > 0; ++pass) {
-      for (int tq = tid; tq < i; tq += 256) {
-        double s = 0.0;
-        for (int r = 0; r < m; ++r) s += double(Q[(int64_t)r * m + tq]) * u[r];
-        cbuf[tq] = s;
-      }
-      __syncthreads();
-      for (int r = tid; r < m; r += 256) {
-        double s = 0.0;
-        for (int tq = 0; tq < i; ++tq) s += double(Q[(int64_t)r * m + tq]) * cbuf[tq];
-        u[r] -= s;
-      }
-      __syncthreads();
+      qdots(u, i, cbuf);
+      qsub(u, i, cbuf);
     }
     double ss = 0.0;
     for (int r = tid; r < m; r += 256) ss += u[r] * u[r];
     const double nrm = sqrt(block_sum(ss, red));
     if (i == 0) R00 = nrm;
-    const bool stop = force_full ? (nrm == 0.0) : (nrm == 0.0 || nrm <= eps * R00);
+    // below 1e-12 |R_00| the residual is rounding noise and Gram-Schmidt
+    // could no longer make it orthogonal: the completion supplies the rest
+    const bool stop = nrm == 0.0 || nrm <= fmax(force_full ? 0.0 : eps, 1e-12) * R00;
     if (stop) break;
     const double inv = 1.0 / nrm;
     __syncthreads();
     for (int r = tid; r < m; r += 256) {
       u[r] *= inv;
-      Q[(int64_t)r * m + i] = T(u[r]);
+      Qt[(int64_t)i * m + r] = T(u[r]);
     }
     if (tid == 0) {
       sel[js] = 1;
       s_nflag = 0;
     }
     __syncthreads();
-    // ---- row i of R for all remaining active columns; downdate their norms
-    for (int qa = tid; qa < nact; qa += 256) {
-      const int g = act[qa];
-      double acc[VN];
+    // row i of R for the active columns and downdate of their norms.  With
+    // few active groups, RS adjacent lanes split the rows of one group (in
+    // blocks of 4) and combine their sums by shuffles.
+    {
+      int RS = 1;
+      while (RS < 8 && nact * RS * 2 <= 256) RS *= 2;
+      const int sl = tid % RS, ga = tid / RS, gpp = 256 / RS;
+      const int m4 = m & ~3;
+      for (int qa0 = 0; qa0 < nact; qa0 += gpp) {
+        const int qa = qa0 + ga;
+        const bool live = qa < nact;
+        const int g = live ? act[qa] : 0;
+        double acc[VN];
 #pragma unroll
-      for (int q = 0; q < VN; ++q) acc[q] = 0.0;
-      const T *base = W + (int64_t)g * VN;
-      int r = 0;
-      for (; r + 4 <= m; r += 4) {
-        VT v[4];
+        for (int q = 0; q < VN; ++q) acc[q] = 0.0;
+        if (live) {
+          const T *base = W + (int64_t)g * VN;
+#pragma unroll 2
+          for (int r = sl * 4; r < m4; r += 4 * RS) {
+            VT v[4];
 #pragma unroll
-        for (int u4 = 0; u4 < 4; ++u4) v[u4] = *reinterpret_cast<const VT *>(base + (int64_t)(r + u4) * ldw);
+            for (int u4 = 0; u4 < 4; ++u4) v[u4] = *reinterpret_cast<const VT *>(base + (int64_t)(r + u4) * ldw);
 #pragma unroll
-        for (int u4 = 0; u4 < 4; ++u4) {
-          const T *e = reinterpret_cast<const T *>(&v[u4]);
-          const double ur = u[r + u4];
+            for (int u4 = 0; u4 < 4; ++u4) {
+              const T *e = reinterpret_cast<const T *>(&v[u4]);
+              const double ur = u[r + u4];
 #pragma unroll
-          for (int q = 0; q < VN; ++q) acc[q] += ur * double(e[q]);
+              for (int q = 0; q < VN; ++q) acc[q] += ur * double(e[q]);
+            }
+          }
+          if (sl == 0)
+            for (int r = m4; r < m; ++r) {
+              const VT v = *reinterpret_cast<const VT *>(base + (int64_t)r * ldw);
+              const T *e = reinterpret_cast<const T *>(&v);
+#pragma unroll
+              for (int q = 0; q < VN; ++q) acc[q] += u[r] * double(e[q]);
+            }
         }
-      }
-      for (; r < m; ++r) {
-        const VT v = *reinterpret_cast<const VT *>(base + (int64_t)r * ldw);
-        const T *e = reinterpret_cast<const T *>(&v);
+        for (int o = 1; o < RS; o <<= 1)
 #pragma unroll
-        for (int q = 0; q < VN; ++q) acc[q] += u[r] * double(e[q]);
-      }
+          for (int q = 0; q < VN; ++q) acc[q] += __shfl_xor(acc[q], o, 64);
+        if (live && sl == 0) {
 #pragma unroll
-      for (int q = 0; q < VN; ++q) {
-        const int j = g * VN + q;
-        if (j >= nc || sel[j]) continue;
-        const double a = vn1[j];
-        if (a != 0.0) {
-          double temp = fabs(acc[q]) / a;
-          temp = fmax(0.0, (1.0 + temp) * (1.0 - temp));
-          const double t2 = temp * (a / vn2[j]) * (a / vn2[j]);
-          if (t2 <= tol3z) {
-            vn1[j] = -1.0;          // recompute below
-            atomicAdd(&s_nflag, 1);
-          } else {
-            vn1[j] = a * sqrt(temp);
+          for (int q = 0; q < VN; ++q) {
+            const int j = g * VN + q;
+            if (j >= nc || sel[j]) continue;
+            const double a = vn1[j];
+            if (a != 0.0) {
+              double temp = fabs(acc[q]) / a;
+              temp = fmax(0.0, (1.0 + temp) * (1.0 - temp));
+              const double t2 = temp * (a / vn2[j]) * (a / vn2[j]);
+              if (t2 <= tol3z) {
+                vn1[j] = -1.0;          // recomputed below
+                atomicAdd(&s_nflag, 1);
+              } else {
+                vn1[j] = a * sqrt(temp);
+              }
+            }
           }
         }
       }
     }
     __syncthreads();
     if (s_nflag > 0) {
-      // exact residual norm of flagged columns against q_0..q_i (one wave each)
-      for (int j = wid; j < nc; j += 4) {
-        if (sel[j] || vn1[j] >= 0.0) continue;
-        for (int tq = lane; tq <= i; tq += 64) {
-          double s = 0.0;
-          for (int r = 0; r < m; ++r) s += double(Q[(int64_t)r * m + tq]) * double(W[(int64_t)r * ldw + j]);
-          cw(wid, tq) = s;
+      // exact residual norms of the flagged columns against q_0..q_i
+      for (;;) {
+        if (tid == 0) s_nf = 0;
+        __syncthreads();
+        for (int qa = tid; qa < nact; qa += 256) {
+          const int g = act[qa];
+#pragma unroll
+          for (int q = 0; q < VN; ++q) {
+            const int j = g * VN + q;
+            if (j < nc && !sel[j] && vn1[j] < 0.0) {
+              const int p = atomicAdd(&s_nf, 1);
+              if (p < 64) s_fl[p] = j;
+            }
+          }
         }
-        double acc = 0.0;
-        for (int r = lane; r < m; r += 64) {
-          double s = double(W[(int64_t)r * ldw + j]);
-          for (int tq = 0; tq <= i; ++tq) s -= double(Q[(int64_t)r * m + tq]) * cw(wid, tq);
-          acc += s * s;
-        }
-        acc = wave_sum(acc);
-        if (lane == 0) {
-          vn1[j] = sqrt(acc);
-          vn2[j] = vn1[j];
+        __syncthreads();
+        const int nf = min(s_nf, 64);
+        if (nf == 0) break;
+        for (int f = 0; f < nf; ++f) {
+          const int j = s_fl[f];
+          for (int r = tid; r < m; r += 256) u[r] = double(W[(int64_t)r * ldw + j]);
+          __syncthreads();
+          qdots(u, i + 1, cbuf);
+          qsub(u, i + 1, cbuf);
+          double s2 = 0.0;
+          for (int r = tid; r < m; r += 256) s2 += u[r] * u[r];
+          s2 = block_sum(s2, red);
+          if (tid == 0) {
+            vn1[j] = sqrt(s2);
+            vn2[j] = vn1[j];
+          }
+          __syncthreads();
         }
       }
-      __syncthreads();
     }
     k = i + 1;
-    rebuild();
-  }
-  __syncthreads();
-  // ---- complete Q: Householder QR of Q[:, 0:k] -> reflectors V, tau
-  for (int t = 0; t < k; ++t) {
-    double ss2 = 0.0;
-    for (int r = t + tid; r < m; r += 256) {
-      const double v = double(Q[(int64_t)r * m + t]);
-      ss2 += v * v;
-    }
-    const double sig = sqrt(block_sum(ss2, red));
-    const double alpha = double(Q[(int64_t)t * m + t]);
-    double tau = 0.0, scal = 0.0;
-    if (sig > 0.0) {
-      const double beta = alpha >= 0.0 ? -sig : sig;
-      tau = (beta - alpha) / beta;
-      scal = 1.0 / (alpha - beta);
+    // keep the groups that can still hold a pivot
+    if (tid == 0) s_n2 = 0;
+    __syncthreads();
+    for (int qa = tid; qa < nact; qa += 256) {
+      const int g = act[qa];
+      if (live_group(g)) act2[atomicAdd(&s_n2, 1)] = g;
     }
     __syncthreads();
-    for (int r = t + tid; r < m; r += 256) {
-      const double v = (r == t) ? 1.0 : double(Q[(int64_t)r * m + t]) * scal;
-      V[(int64_t)t * m + r] = T(v);
-    }
-    if (tid == 0) d.tau[t] = tau;
-    __syncthreads();
-    // apply H_t to columns t+1..k-1 (threads over columns)
-    for (int c = t + 1 + tid; c < k; c += 256) {
-      double s = 0.0;
-      for (int r = t; r < m; ++r) s += double(V[(int64_t)t * m + r]) * double(Q[(int64_t)r * m + c]);
-      s *= tau;
-      for (int r = t; r < m; ++r) Q[(int64_t)r * m + c] = T(double(Q[(int64_t)r * m + c]) - s * double(V[(int64_t)t * m + r]));
+    if (tid == 0) s_nact = s_n2;
+    {
+      int *t = act;
+      act = act2;
+      act2 = t;
     }
     __syncthreads();
   }
-  // ---- Q = H_0 H_1 ... H_{k-1} (applied to I from the last reflector)
-  for (int idx = tid; idx < m * m; idx += 256) Q[idx] = T((idx / m) == (idx % m) ? 1.0 : 0.0);
   __syncthreads();
-  for (int t = k - 1; t >= 0; --t) {
-    const double tau = d.tau[t];
-    for (int c = tid; c < m; c += 256) {
-      double s = 0.0;
-      for (int r = t; r < m; ++r) s += double(V[(int64_t)t * m + r]) * double(Q[(int64_t)r * m + c]);
-      s *= tau;
-      if (s != 0.0)
-        for (int r = t; r < m; ++r) Q[(int64_t)r * m + c] = T(double(Q[(int64_t)r * m + c]) - s * double(V[(int64_t)t * m + r]));
+
+  // ---- 3. complete Q
+  double *As = qsm, *Bs = qsm + 1024;
+  if (k == 0) {
+    for (int i2 = tid >> 4; i2 < m; i2 += 16)
+      for (int c = tid & 15; c < m; c += 16) Q[(int64_t)i2 * m + c] = T(i2 == c ? 1.0 : 0.0);
+  } else {
+    if (k < m) {
+      // Q1 into the top-left k x k of Q, then its in-place Gauss-Jordan
+      // inversion with the diagonal shifted by -s_j when column j pivots
+      for (int i2 = tid >> 4; i2 < k; i2 += 16)
+        for (int c = tid & 15; c < k; c += 16) Q[(int64_t)i2 * m + c] = Qt[(int64_t)c * m + i2];
+      __syncthreads();
+      double *rowj = u, *colj = cbuf;
+      for (int j = 0; j < k; ++j) {
+        if (tid == 0) {
+          const double a = double(Q[(int64_t)j * m + j]);
+          const double s = a >= 0.0 ? -1.0 : 1.0;
+          s_piv = 1.0 / (a - s);
+          d.tau[j] = s;
+        }
+        __syncthreads();
+        const double p = s_piv;
+        for (int c = tid; c < k; c += 256) {
+          rowj[c] = (c == j ? 1.0 : double(Q[(int64_t)j * m + c])) * p;
+          colj[c] = c == j ? 0.0 : double(Q[(int64_t)c * m + j]);
+        }
+        __syncthreads();
+        for (int i2 = tid >> 4; i2 < k; i2 += 16)
+          for (int c = tid & 15; c < k; c += 16) {
+            double v;
+            if (i2 == j) v = rowj[c];
+            else v = (c == j ? 0.0 : double(Q[(int64_t)i2 * m + c])) - colj[i2] * rowj[c];
+            Q[(int64_t)i2 * m + c] = T(v);
+          }
+        __syncthreads();
+      }
+      // G2 S = Q2 (Q1 - S)^-1 S into rows k.. of V
+      const double *sg = d.tau;
+      wg_gemm<false>(
+          m - k, k, k,
+          [&](int i2, int l) { return double(Qt[(int64_t)l * m + k + i2]); },
+          [&](int l, int t) { return double(Q[(int64_t)l * m + t]); },
+          [&](int i2, int t, double v) { Qt[(int64_t)(k + i2) * m + t] = T(v * sg[t]); }, As, Bs);
+      // H(:, k:m) = E_c + Q_c (G2 S)^T - [r < k] s_r G2(c, r)
+      wg_gemm<true>(
+          m, m - k, k,
+          [&](int r, int t) { return double(Qt[(int64_t)t * m + r]); },
+          [&](int t, int n) { return double(Qt[(int64_t)(k + n) * m + t]); },
+          [&](int r, int n, double v) {
+            const int c = k + n;
+            if (r == c) v += 1.0;
+            if (r < k) v -= sg[r] * double(Qt[(int64_t)c * m + r]);
+            Q[(int64_t)r * m + c] = T(v);
+          },
+          As, Bs);
     }
-    __syncthreads();
+    // Q(:, 0:k) = Q_c
+    for (int r = tid >> 4; r < m; r += 16)
+      for (int t = tid & 15; t < k; t += 16) Q[(int64_t)r * m + t] = Qt[(int64_t)t * m + r];
   }
   if (tid == 0) *d.k_out = force_full ? m : k;
+}
+
+size_t qrcp_lds_bytes(int maxm, int maxgrp) {
+  const size_t MS = size_t(std::max(maxm, 1)), GS = size_t(std::max(maxgrp, 1));
+  return std::max<size_t>(2 * MS, 2048) * sizeof(double) + 2 * GS * sizeof(int);
 }
 
 int launch_qrcp(FType t, const QrcpDesc *d_items, int n, double eps, int force_full, int maxm,
@@ -917,7 +1077,7 @@ int launch_qrcp(FType t, const QrcpDesc *d_items, int n, double eps, int force_f
   if (n <= 0) return SPAND_OK;
   const int MS = std::max(maxm, 1);
   const int GS = std::max(maxgrp, 1);
-  const size_t lds = size_t(6) * MS * sizeof(double) + size_t(GS) * sizeof(int);
+  const size_t lds = qrcp_lds_bytes(MS, GS);
   if (t == FType::F64)
     hipLaunchKernelGGL(k_qrcp<double>, dim3(n), dim3(256), lds, st, d_items, eps, force_full, MS, GS);
   else
