@@ -24,6 +24,7 @@
 // with the elimination written as L' = [[I,0],[-A_ns A_ss^-1, I]],
 // R' = [[A_ss^-1, -A_ss^-1 A_sn],[0, I]]  (L' A R' = diag(I, Schur)).
 #include <algorithm>
+#include <climits>
 #include <chrono>
 #include <mutex>
 #include <cmath>
@@ -131,16 +132,29 @@ int Factor::upload_level_slots(LevelState &S) {
 // ------------------------------------------------------------------ batched helpers
 int Factor::gemm_batch(const std::vector<GemmDesc> &items) {
   if (items.empty()) return SPAND_OK;
-  std::vector<int32_t> ts(items.size() + 1, 0);
-  for (size_t i = 0; i < items.size(); ++i) {
-    const auto &d = items[i];
-    ts[i + 1] = ts[i] + int32_t(cdiv(d.M, 64) * cdiv(d.N, 64));
+  // one launch per transpose mode (the FP32 kernel is specialised on it)
+  std::vector<GemmDesc> ord;
+  std::vector<int32_t> ts(1, 0);
+  int start[5] = {0, 0, 0, 0, 0};
+  for (int tm = 0; tm < 4; ++tm) {
+    start[tm] = int(ord.size());
+    for (const auto &d : items)
+      if (2 * (d.transA != 0) + (d.transB != 0) == tm) {
+        ord.push_back(d);
+        ts.push_back(ts.back() + int32_t(cdiv(d.M, 64) * cdiv(d.N, 64)));
+      }
   }
+  start[4] = int(ord.size());
   GemmDesc *d_items;
   int32_t *d_ts;
-  SP_TRY(upload(items, &d_items, false));
+  SP_TRY(upload(ord, &d_items, false));
   SP_TRY(upload(ts, &d_ts, false));
-  return launch_gemm(ft, d_items, d_ts, int(items.size()), ts.back(), stream);
+  for (int tm = 0; tm < 4; ++tm) {
+    const int a = start[tm], b = start[tm + 1];
+    if (b > a)
+      SP_TRY(launch_gemm(ft, d_items + a, d_ts + a, b - a, ts[b] - ts[a], stream, ts[a], tm));
+  }
+  return SPAND_OK;
 }
 
 int Factor::copy_batch(const std::vector<CopyDesc> &items, int src_is_factor) {
@@ -178,37 +192,100 @@ int Factor::elim_batch(std::vector<ElimDesc> &items, int mode) {
   std::sort(items.begin(), items.end(), [](const ElimDesc &a, const ElimDesc &b) {
     return a.n > b.n;
   });
-  size_t nP = 0, nT = 0, nI = 0;
+  // Gauss-Jordan with pivoting is blocked: panels of 16 columns update only
+  // their block of ELIM_BLK columns; the rest of the matrix receives each
+  // block at once as one rank-ELIM_BLK product on the matrix cores.
+  const bool blocked = mode == 0;
+  size_t nP = 0, nT = 0, nI = 0, nB = 0;
   for (auto &d : items) {
     nP += size_t(d.n) * ELIM_NB;
     nT += size_t(ELIM_NB) * d.ld;
     nI += size_t(d.n);
+    if (blocked) nB += size_t(ELIM_BLK) * d.ld;
   }
-  void *P, *T, *piv, *used;
+  void *P, *T, *piv, *used, *TB = nullptr;
   SP_TRY(dalloc(&P, nP * fsize(ft), false));
   SP_TRY(dalloc(&T, nT * fsize(ft), false));
   SP_TRY(dalloc(&piv, nI * 4, false));
   SP_TRY(dalloc(&used, nI * 4, false));
+  if (blocked) SP_TRY(dalloc(&TB, nB * fsize(ft), false));
   SP_HIP(hipMemsetAsync(used, 0, nI * 4, stream));
-  size_t oP = 0, oT = 0, oI = 0;
+  size_t oP = 0, oT = 0, oI = 0, oB = 0;
   for (auto &d : items) {
     d.P = (char *)P + oP * fsize(ft);
     d.T = (char *)T + oT * fsize(ft);
     d.piv = (int32_t *)piv + oI;
     d.used = (int32_t *)used + oI;
+    d.TB = blocked ? (char *)TB + oB * fsize(ft) : nullptr;
     oP += size_t(d.n) * ELIM_NB;
     oT += size_t(ELIM_NB) * d.ld;
     oI += size_t(d.n);
+    if (blocked) oB += size_t(ELIM_BLK) * d.ld;
   }
   ElimDesc *d_items;
   SP_TRY(upload(items, &d_items, false));
   const int nmax = items[0].n;
-  for (int k = 0; k < nmax; k += ELIM_NB) {
-    int nactive = 0;
-    while (nactive < int(items.size()) && items[nactive].n > k) ++nactive;
-    const int c0 = mode == 1 ? k : 0;
-    const int max_tiles = int(cdiv(nmax, 64) * cdiv(items[0].ncols - c0, 64));
-    SP_TRY(launch_elim_step(ft, d_items, nactive, k, mode, max_tiles, d_flag, stream));
+  auto nactive_at = [&](int k) {
+    int na = 0;
+    while (na < int(items.size()) && items[na].n > k) ++na;
+    return na;
+  };
+  if (!blocked) {
+    for (int k = 0; k < nmax; k += ELIM_NB) {
+      const int nactive = nactive_at(k);
+      const int c0 = mode == 1 ? k : 0;
+      const int max_tiles = int(cdiv(nmax, 64) * cdiv(items[0].ncols - c0, 64));
+      SP_TRY(launch_elim_step(ft, d_items, nactive, k, mode, max_tiles, d_flag, 0, INT_MAX, stream));
+    }
+    return SPAND_OK;
+  }
+  // trailing products of every block: columns [0, k0) and [k0 + ELIM_BLK, ncols)
+  const size_t tsz = fsize(ft);
+  std::vector<GemmDesc> gd;
+  std::vector<int32_t> ts(1, 0);
+  std::vector<size_t> bstart;
+  for (int k0 = 0; k0 < nmax; k0 += ELIM_BLK) {
+    bstart.push_back(gd.size());
+    for (auto &d : items) {
+      if (d.n <= k0) break;
+      const int wb = std::min(ELIM_BLK, d.n - k0);
+      auto add = [&](int c_off, int width) {
+        if (width <= 0) return;
+        GemmDesc g{};
+        g.A = (char *)d.A + size_t(k0) * tsz;
+        g.B = (char *)d.TB + size_t(c_off) * tsz;
+        g.C = (char *)d.A + size_t(c_off) * tsz;
+        g.M = d.n;
+        g.N = width;
+        g.K = wb;
+        g.lda = g.ldb = g.ldc = d.ld;
+        g.alpha = 1.0;
+        g.beta = 1.0;
+        gd.push_back(g);
+        ts.push_back(ts.back() + int32_t(cdiv(g.M, 64) * cdiv(g.N, 64)));
+      };
+      add(0, k0);
+      add(k0 + ELIM_BLK, d.ncols - k0 - ELIM_BLK);
+    }
+  }
+  bstart.push_back(gd.size());
+  GemmDesc *d_gd = nullptr;
+  int32_t *d_ts = nullptr;
+  SP_TRY(upload(gd, &d_gd, false));
+  SP_TRY(upload(ts, &d_ts, false));
+  for (int b = 0, k0 = 0; k0 < nmax; ++b, k0 += ELIM_BLK) {
+    for (int k = k0; k < std::min(nmax, k0 + ELIM_BLK); k += ELIM_NB) {
+      const int nactive = nactive_at(k);
+      const int max_tiles = int(cdiv(nmax, 64));     // one 64-wide column tile: the block
+      SP_TRY(launch_elim_step(ft, d_items, nactive, k, mode, max_tiles, d_flag, k0,
+                              k0 + ELIM_BLK, stream));
+    }
+    SP_TRY(launch_elim_extract(ft, d_items, nactive_at(k0), k0, stream));
+    const size_t g0 = bstart[b], g1 = bstart[b + 1];
+    if (g1 > g0) {
+      // this block's descriptors; their tile numbers start at ts[g0]
+      SP_TRY(launch_gemm(ft, d_gd + g0, d_ts + g0, int(g1 - g0), ts[g1] - ts[g0], stream, ts[g0], 0));
+    }
   }
   return SPAND_OK;
 }

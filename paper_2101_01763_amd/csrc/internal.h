@@ -119,6 +119,7 @@ struct ElimDesc {
   int32_t ncols;    // total columns (n or 2n)
   int32_t ld;
   int32_t pad;
+  void *TB;         // workspace ELIM_BLK x ld (blocked Gauss-Jordan: pivot rows of a block)
 };
 
 // Dense GEMV with gather/scatter through slot lists:
@@ -185,13 +186,16 @@ struct QrcpDesc {
 // Implemented in the .hip files.  Descriptor arrays are device pointers.
 // Every wrapper returns SPAND_OK or SPAND_EHIP (launch error).
 constexpr int ELIM_NB = 16;        // panel width of the elimination kernels
+constexpr int ELIM_BLK = 64;       // block width of the blocked Gauss-Jordan (4 panels)
 constexpr int ELIM_NT = 512;       // threads of a panel workgroup
 constexpr int ELIM_RPT = 4;        // rows held per thread -> n <= 2048
 constexpr int ELIM_MAXN = ELIM_NT * ELIM_RPT;
 constexpr int QRCP_MAXM = 1024;    // largest interface handled by the QRCP kernel
 
+// tmode = 2 * transA + transB, shared by every descriptor of the launch
+// (the FP64 kernel reads the flags per descriptor and ignores it)
 int launch_gemm(FType t, const GemmDesc *d_items, const int32_t *d_tile_start, int nitems,
-                int total_tiles, hipStream_t st);
+                int total_tiles, hipStream_t st, int tile_base, int tmode);
 // src double -> dst factor type (src_is_factor = 0) or factor -> factor (1)
 int launch_copy(FType t, int src_is_factor, const CopyDesc *d_items, int n, int64_t max_elems,
                 hipStream_t st);
@@ -202,7 +206,8 @@ int launch_copy_t(FType t, int src_is_factor, const CopyDesc *d_items, int n, in
 // pivoting; 2: Gauss-Jordan without pivoting.  Items sorted by n descending,
 // the first nactive have n > k.
 int launch_elim_step(FType t, const ElimDesc *d_items, int nactive, int k, int mode,
-                     int max_tiles, int *d_flag, hipStream_t st);
+                     int max_tiles, int *d_flag, int cw0, int cw1, hipStream_t st);
+int launch_elim_extract(FType t, const ElimDesc *d_items, int nactive, int k0, hipStream_t st);
 // out[j, c] = src[piv[j], colperm ? pinv[c] : c + col_off]
 struct RowGatherDesc {
   const void *src;

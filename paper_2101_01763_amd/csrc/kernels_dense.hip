@@ -45,8 +45,8 @@ __device__ inline double block_sum(double v, double *red) {
 template <typename T>
 __global__ __launch_bounds__(256) void k_gemm(const GemmDesc *__restrict__ items,
                                               const int32_t *__restrict__ tile_start,
-                                              int nitems) {
-  const int tile = blockIdx.x;
+                                              int nitems, int tile_base) {
+  const int tile = tile_base + int(blockIdx.x);
   int lo = 0, hi = nitems;
   while (hi - lo > 1) {
     int mid = (lo + hi) >> 1;
@@ -120,15 +120,129 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmDesc *__restrict__ items
   }
 }
 
+// FP32 version on the matrix cores: the same 64x64 tiles, each of the four
+// waves owns a 32x32 quarter and accumulates it with v_mfma_f32_32x32x2f32
+// (lane l holds A(l%32, k + l/32) and B(k + l/32, l%32); result register r
+// of lane l is row 8(r/4) + 4(l/32) + r%4, column l%32 of the quarter).
+// K advances in chunks of 32 staged through LDS; the next chunk is fetched
+// into registers while the current one is multiplied.  With alpha = 1 the
+// accumulators start from beta*C, loaded before the first product.
+// Workgroups are dealt round-robin to the 8 XCDs; each XCD is given one
+// contiguous range of tiles so that the tiles of a matrix share its L2.
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+constexpr int GK = 32;
+
+__device__ inline int xcd_tile(int b, int nb) {
+  const int q = nb >> 3, r = nb & 7, x = b & 7, j = b >> 3;
+  return x * q + min(x, r) + j;
+}
+
+template <int TA, int TB>
+__global__ __launch_bounds__(256) void k_gemm_f32_mfma(const GemmDesc *__restrict__ items,
+                                                       const int32_t *__restrict__ tile_start,
+                                                       int nitems, int tile_base) {
+  const int tile = tile_base + xcd_tile(int(blockIdx.x), int(gridDim.x));
+  int lo = 0, hi = nitems;
+  while (hi - lo > 1) {
+    int mid = (lo + hi) >> 1;
+    if (tile_start[mid] <= tile) lo = mid; else hi = mid;
+  }
+  const GemmDesc d = items[lo];
+  const int t = tile - tile_start[lo];
+  const int ntn = (d.N + 63) >> 6;
+  const int m0 = (t / ntn) * 64, n0 = (t % ntn) * 64;
+  __shared__ float As[64 * (GK + 1)];   // As[m * (GK + 1) + k]
+  __shared__ float Bs[GK * 68];         // Bs[k * 68 + n]
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int wr = wid >> 1, wc = wid & 1;
+  const float *A = (const float *)d.A;
+  const float *B = (const float *)d.B;
+  float ra[8], rb[8];
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int idx = tid + q * 256;
+      int mm, kk;
+      if (!TA) { mm = idx >> 5; kk = idx & 31; }
+      else { kk = idx >> 6; mm = idx & 63; }
+      const int gm = m0 + mm, gk = k0 + kk;
+      ra[q] = (gm < d.M && gk < d.K)
+                  ? (TA ? A[(int64_t)gk * d.lda + gm] : A[(int64_t)gm * d.lda + gk])
+                  : 0.f;
+      int nn;
+      if (!TB) { kk = idx >> 6; nn = idx & 63; }
+      else { nn = idx >> 5; kk = idx & 31; }
+      const int gn = n0 + nn, gk2 = k0 + kk;
+      rb[q] = (gn < d.N && gk2 < d.K)
+                  ? (TB ? B[(int64_t)gn * d.ldb + gk2] : B[(int64_t)gk2 * d.ldb + gn])
+                  : 0.f;
+    }
+  };
+  auto sstore = [&]() {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int idx = tid + q * 256;
+      int mm, kk;
+      if (!TA) { mm = idx >> 5; kk = idx & 31; }
+      else { kk = idx >> 6; mm = idx & 63; }
+      As[mm * (GK + 1) + kk] = ra[q];
+      int nn;
+      if (!TB) { kk = idx >> 6; nn = idx & 63; }
+      else { nn = idx >> 5; kk = idx & 31; }
+      Bs[kk * 68 + nn] = rb[q];
+    }
+  };
+  gload(0);
+  float *C = (float *)d.C;
+  const int gn = n0 + wc * 32 + (lane & 31);
+  const bool cin = d.alpha == 1.0 && d.beta != 0.0;
+  const float al = float(d.alpha), be = float(d.beta);
+  f32x16 acc;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int gm = m0 + wr * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+    acc[r] = (cin && gm < d.M && gn < d.N) ? be * C[(int64_t)gm * d.ldc + gn] : 0.f;
+  }
+  const float *ap = As + (wr * 32 + (lane & 31)) * (GK + 1) + (lane >> 5);
+  const float *bp = Bs + (lane >> 5) * 68 + wc * 32 + (lane & 31);
+  for (int k0 = 0; k0 < d.K; k0 += GK) {
+    sstore();
+    __syncthreads();
+    if (k0 + GK < d.K) gload(k0 + GK);
+#pragma unroll
+    for (int kk = 0; kk < GK; kk += 2)
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(ap[kk], bp[kk * 68], acc, 0, 0, 0);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int gm = m0 + wr * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+    if (gm < d.M && gn < d.N) {
+      float *c = C + (int64_t)gm * d.ldc + gn;
+      float v = acc[r];
+      if (!cin) {
+        v *= al;
+        if (d.beta != 0.0) v += be * (*c);
+      }
+      *c = v;
+    }
+  }
+}
+
 int launch_gemm(FType t, const GemmDesc *d_items, const int32_t *d_tile_start, int nitems,
-                int total_tiles, hipStream_t st) {
+                int total_tiles, hipStream_t st, int tile_base, int tmode) {
   if (nitems <= 0 || total_tiles <= 0) return SPAND_OK;
+  const dim3 g(total_tiles), b(256);
   if (t == FType::F64)
-    hipLaunchKernelGGL(k_gemm<double>, dim3(total_tiles), dim3(256), 0, st, d_items,
-                       d_tile_start, nitems);
+    hipLaunchKernelGGL(k_gemm<double>, g, b, 0, st, d_items, d_tile_start, nitems, tile_base);
+  else if (tmode == 0)
+    hipLaunchKernelGGL((k_gemm_f32_mfma<0, 0>), g, b, 0, st, d_items, d_tile_start, nitems, tile_base);
+  else if (tmode == 1)
+    hipLaunchKernelGGL((k_gemm_f32_mfma<0, 1>), g, b, 0, st, d_items, d_tile_start, nitems, tile_base);
+  else if (tmode == 2)
+    hipLaunchKernelGGL((k_gemm_f32_mfma<1, 0>), g, b, 0, st, d_items, d_tile_start, nitems, tile_base);
   else
-    hipLaunchKernelGGL(k_gemm<float>, dim3(total_tiles), dim3(256), 0, st, d_items,
-                       d_tile_start, nitems);
+    hipLaunchKernelGGL((k_gemm_f32_mfma<1, 1>), g, b, 0, st, d_items, d_tile_start, nitems, tile_base);
   SP_HIP(hipGetLastError());
   return SPAND_OK;
 }
@@ -274,7 +388,7 @@ int launch_eye(FType t, const EyeDesc *d_items, int n, int max_n, hipStream_t st
 // for Gauss-Jordan P is the final panel itself, for LU it is tracked in Y.
 template <typename T, int MODE>
 __global__ __launch_bounds__(ELIM_NT) void k_elim_panel(const ElimDesc *__restrict__ items, int k,
-                                                        int *__restrict__ flag) {
+                                                        int *__restrict__ flag, int cw0, int cw1) {
   constexpr int NT = ELIM_NT, RPT = ELIM_RPT, NB = ELIM_NB;
   const ElimDesc d = items[blockIdx.x];
   const int n = d.n;
@@ -410,8 +524,10 @@ __global__ __launch_bounds__(ELIM_NT) void k_elim_panel(const ElimDesc *__restri
   if (tid < w) d.piv[k + tid] = s_piv[tid];
   // pivot rows of the non-panel columns -> T, then zero them in A.  The
   // panel columns of T are zero so the update leaves the panel unchanged.
-  const int c0 = (MODE == 1) ? k : 0;
-  const int ncol = d.ncols - c0;
+  // Only the column window [cw0, cw1) is touched (a blocked elimination
+  // applies the panels of a block to the columns outside it at once).
+  const int c0 = max((MODE == 1) ? k : 0, cw0);
+  const int ncol = min(d.ncols, cw1) - c0;
   for (int idx = tid; idx < w * ncol; idx += NT) {
     const int cq = idx / ncol;
     const int col = c0 + idx % ncol;
@@ -428,13 +544,15 @@ __global__ __launch_bounds__(ELIM_NT) void k_elim_panel(const ElimDesc *__restri
 // A[:, c0:ncols] += P[:, 0:w] * T[0:w, c0:ncols]
 template <typename T>
 __global__ __launch_bounds__(256) void k_elim_update(const ElimDesc *__restrict__ items, int k,
-                                                     int lu_mode) {
+                                                     int lu_mode, int cw0, int cw1) {
   const ElimDesc d = items[blockIdx.x];
   const int n = d.n;
   if (k >= n) return;
   const int w = min(ELIM_NB, n - k);
-  const int c0 = lu_mode ? k : 0;
-  const int ncol = d.ncols - c0;
+  const int c0 = max(lu_mode ? k : 0, cw0);
+  const int cend = min(d.ncols, cw1);
+  const int ncol = cend - c0;
+  if (ncol <= 0) return;
   const int ntn = (ncol + 63) >> 6, ntm = (n + 63) >> 6;
   const int t = blockIdx.y;
   if (t >= ntm * ntn) return;
@@ -450,7 +568,7 @@ __global__ __launch_bounds__(256) void k_elim_update(const ElimDesc *__restrict_
     const int mm = idx / ELIM_NB, kk = idx % ELIM_NB;
     Ps[kk][mm] = (kk < w && m0 + mm < n) ? P[(int64_t)(m0 + mm) * ELIM_NB + kk] : T(0);
     const int kk2 = idx / 64, nn = idx % 64;
-    Ts[kk2][nn] = (kk2 < w && n0 + nn < d.ncols) ? Tb[(int64_t)kk2 * ld + n0 + nn] : T(0);
+    Ts[kk2][nn] = (kk2 < w && n0 + nn < cend) ? Tb[(int64_t)kk2 * ld + n0 + nn] : T(0);
   }
   __syncthreads();
   const int tm = tid >> 4, tn = tid & 15;
@@ -478,35 +596,72 @@ __global__ __launch_bounds__(256) void k_elim_update(const ElimDesc *__restrict_
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int gn = n0 + tn + 16 * j;
-      if (gn >= d.ncols) continue;
+      if (gn >= cend) continue;
       A[(int64_t)gm * ld + gn] += acc[i][j];
     }
   }
 }
 
 int launch_elim_step(FType t, const ElimDesc *d_items, int nactive, int k, int mode,
-                     int max_tiles, int *d_flag, hipStream_t st) {
+                     int max_tiles, int *d_flag, int cw0, int cw1, hipStream_t st) {
   if (nactive <= 0) return SPAND_OK;
   const int lu = mode == 1;
   if (t == FType::F64) {
     if (mode == 0)
-      hipLaunchKernelGGL((k_elim_panel<double, 0>), dim3(nactive), dim3(ELIM_NT), 0, st, d_items, k, d_flag);
+      hipLaunchKernelGGL((k_elim_panel<double, 0>), dim3(nactive), dim3(ELIM_NT), 0, st, d_items, k, d_flag, cw0, cw1);
     else if (mode == 1)
-      hipLaunchKernelGGL((k_elim_panel<double, 1>), dim3(nactive), dim3(ELIM_NT), 0, st, d_items, k, d_flag);
+      hipLaunchKernelGGL((k_elim_panel<double, 1>), dim3(nactive), dim3(ELIM_NT), 0, st, d_items, k, d_flag, cw0, cw1);
     else
-      hipLaunchKernelGGL((k_elim_panel<double, 2>), dim3(nactive), dim3(ELIM_NT), 0, st, d_items, k, d_flag);
+      hipLaunchKernelGGL((k_elim_panel<double, 2>), dim3(nactive), dim3(ELIM_NT), 0, st, d_items, k, d_flag, cw0, cw1);
     SP_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_elim_update<double>, dim3(nactive, max_tiles), dim3(256), 0, st, d_items, k, lu);
+    hipLaunchKernelGGL(k_elim_update<double>, dim3(nactive, max_tiles), dim3(256), 0, st, d_items, k, lu, cw0, cw1);
   } else {
     if (mode == 0)
-      hipLaunchKernelGGL((k_elim_panel<float, 0>), dim3(nactive), dim3(ELIM_NT), 0, st, d_items, k, d_flag);
+      hipLaunchKernelGGL((k_elim_panel<float, 0>), dim3(nactive), dim3(ELIM_NT), 0, st, d_items, k, d_flag, cw0, cw1);
     else if (mode == 1)
-      hipLaunchKernelGGL((k_elim_panel<float, 1>), dim3(nactive), dim3(ELIM_NT), 0, st, d_items, k, d_flag);
+      hipLaunchKernelGGL((k_elim_panel<float, 1>), dim3(nactive), dim3(ELIM_NT), 0, st, d_items, k, d_flag, cw0, cw1);
     else
-      hipLaunchKernelGGL((k_elim_panel<float, 2>), dim3(nactive), dim3(ELIM_NT), 0, st, d_items, k, d_flag);
+      hipLaunchKernelGGL((k_elim_panel<float, 2>), dim3(nactive), dim3(ELIM_NT), 0, st, d_items, k, d_flag, cw0, cw1);
     SP_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_elim_update<float>, dim3(nactive, max_tiles), dim3(256), 0, st, d_items, k, lu);
+    hipLaunchKernelGGL(k_elim_update<float>, dim3(nactive, max_tiles), dim3(256), 0, st, d_items, k, lu, cw0, cw1);
   }
+  SP_HIP(hipGetLastError());
+  return SPAND_OK;
+}
+
+// Blocked Gauss-Jordan (mode 0): after the panels of the block
+// [k0, k0 + wb) have been applied to the block's own columns, the pivot rows
+// of every other column move to TB (wb x ld) and are zeroed in A, so that
+// A[:, outside] += A[:, k0:k0+wb] TB is the whole block's effect there.
+template <typename T>
+__global__ __launch_bounds__(256) void k_elim_extract(const ElimDesc *__restrict__ items, int k0) {
+  const ElimDesc d = items[blockIdx.x];
+  if (k0 >= d.n) return;
+  const int wb = min(ELIM_BLK, d.n - k0);
+  const int cw1 = k0 + ELIM_BLK;
+  T *A = (T *)d.A;
+  T *TB = (T *)d.TB;
+  const int64_t ld = d.ld;
+  for (int q = blockIdx.y; q < wb; q += gridDim.y) {
+    const int64_t src = (int64_t)d.piv[k0 + q] * ld;
+    for (int c = threadIdx.x; c < d.ncols; c += 256) {
+      if (c >= k0 && c < cw1) {
+        TB[(int64_t)q * ld + c] = T(0);
+      } else {
+        TB[(int64_t)q * ld + c] = A[src + c];
+        A[src + c] = T(0);
+      }
+    }
+  }
+}
+
+int launch_elim_extract(FType t, const ElimDesc *d_items, int nactive, int k0, hipStream_t st) {
+  if (nactive <= 0) return SPAND_OK;
+  const dim3 grid(nactive, 16);
+  if (t == FType::F64)
+    hipLaunchKernelGGL(k_elim_extract<double>, grid, dim3(256), 0, st, d_items, k0);
+  else
+    hipLaunchKernelGGL(k_elim_extract<float>, grid, dim3(256), 0, st, d_items, k0);
   SP_HIP(hipGetLastError());
   return SPAND_OK;
 }
