@@ -231,7 +231,8 @@ def main():
             f"relres {info.relres:.2e} | lu {st['t_lu_ms']:.0f} schur {st['t_schur_ms']:.0f} "
             f"scale {st['t_scale_ms']:.0f} rrqr {st['t_rrqr_ms']:.0f} (qrcp {st['t_qrcp_ms']:.0f}) "
             f"compress {st['t_compress_ms']:.0f} host {st['t_host_ms']:.0f} "
-            f"alloc {st['t_alloc_ms']:.0f} ms, resident {st['resident_bytes'] / 2**30:.1f} GiB")
+            f"alloc {st['t_alloc_ms']:.0f} ms, resident {st['resident_bytes'] / 2**30:.1f} GiB | "
+            f"host plan ms " + " ".join(f"{v:.0f}" for v in st['t_plan_ms']))
         del F
     torch.cuda.synchronize()
     t_total = time.perf_counter() - t_start

@@ -124,6 +124,10 @@ typedef struct {
   double t_alloc_ms;                      /* host time in hipMalloc/hipFree
                                              (blocks not found in the cache) */
   int64_t resident_bytes;                 /* device memory the factor keeps  */
+  /* host time (planning and launches) spent in each phase: gather, LU,
+     Schur, scale, RRQR, compress; the device waits when it exceeds the
+     phase's device time */
+  double t_plan_ms[6];
 } spand_factor_stats_t;
 
 typedef struct spand_factor_s *spand_factor_t;

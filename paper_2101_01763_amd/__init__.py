@@ -75,7 +75,7 @@ class spand_factor_stats_t(C.Structure):
                 ("t_compress_ms", C.c_double), ("t_qrcp_ms", C.c_double),
                 ("n_qrcp", C.c_int32), ("pad0", C.c_int32), ("qrcp_bytes", C.c_double),
                 ("qrcp_flops", C.c_double), ("t_alloc_ms", C.c_double),
-                ("resident_bytes", C.c_int64)]
+                ("resident_bytes", C.c_int64), ("t_plan_ms", C.c_double * 6)]
 
 
 EXPORTS = ["spand_factor", "spand_apply", "spand_apply_T", "sstep_gmres_solve",
@@ -230,6 +230,7 @@ class Factor:
             "t_qrcp_ms": st.t_qrcp_ms, "n_qrcp": st.n_qrcp, "qrcp_bytes": st.qrcp_bytes,
             "qrcp_flops": st.qrcp_flops,
             "t_alloc_ms": st.t_alloc_ms, "resident_bytes": st.resident_bytes,
+            "t_plan_ms": list(st.t_plan_ms),
         }
 
 

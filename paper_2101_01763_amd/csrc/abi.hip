@@ -121,7 +121,22 @@ static int factor_one(const spand_bsr_t *A, const spand_grid_t *grid, const span
     return SPAND_EINVAL;
   }
   auto h = std::make_unique<spand_factor_s>();
-  h->F.stream = (hipStream_t)stream;
+  // The build runs on a private non-blocking stream ordered after the
+  // caller's: its descriptor uploads (synchronous copies on the null
+  // stream) then never wait for the factorization's own kernels, so the
+  // host plans the next kernels while the device runs the queued ones.
+  hipStream_t ps = nullptr;
+  hipEvent_t ready = nullptr;
+  SP_HIP(hipStreamCreateWithFlags(&ps, hipStreamNonBlocking));
+  if (hipEventCreateWithFlags(&ready, hipEventDisableTiming) != hipSuccess ||
+      hipEventRecord(ready, (hipStream_t)stream) != hipSuccess ||
+      hipStreamWaitEvent(ps, ready, 0) != hipSuccess) {
+    if (ready) (void)hipEventDestroy(ready);
+    (void)hipStreamDestroy(ps);
+    set_error("could not order the factorization after the caller's stream");
+    return SPAND_EHIP;
+  }
+  h->F.stream = ps;
   h->F.timing = true;
   (void)hipGetDevice(&h->F.device);
   int r;
@@ -131,8 +146,11 @@ static int factor_one(const spand_bsr_t *A, const spand_grid_t *grid, const span
     set_error("factorization failed: %s", ex.what());
     r = SPAND_EINVAL;
   }
+  (void)hipStreamSynchronize(ps);
+  (void)hipEventDestroy(ready);
+  (void)hipStreamDestroy(ps);
+  h->F.stream = nullptr;
   if (r != SPAND_OK) return r;
-  h->F.stream = nullptr;     // the build stream may be a worker's, destroyed later
   if (graphs) SP_TRY(h->F.capture_graphs());
   *out = h.release();
   return SPAND_OK;

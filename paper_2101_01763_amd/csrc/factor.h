@@ -1,5 +1,7 @@
 // spaND factor object (host side) and its per-level apply plan.
 #pragma once
+
+#include <chrono>
 #include <functional>
 #include <map>
 #include <vector>
@@ -78,6 +80,7 @@ struct Bump {
   size_t bytes = 0;
   int alloc(void **p, size_t n, size_t chunk);
   void release();
+  void absorb(Bump &o);      // take over o's chunks (o becomes empty)
 };
 
 struct Factor {
@@ -90,6 +93,7 @@ struct Factor {
   std::vector<int32_t> h_rowptr, h_colind;
   std::vector<ApplyLevel> lv;
   Bump keep, temp, next_temp;   // next_temp: next level's trailing blocks
+  Bump retired;                 // scratch of finished levels, released at the next sync
   size_t keep_bytes = 0;
   int32_t *d_iota = nullptr;
   double *d_tbuf = nullptr;
@@ -99,6 +103,9 @@ struct Factor {
   int top_size = 0;
   double apply_bytes = 0.0, flops = 0.0, t_host_ms = 0.0;
   double ph_ms[PH_COUNT] = {0};
+  double ph_host_ms[PH_COUNT] = {0};   // host time (planning + launches) per phase
+  int host_phase = -1;
+  std::chrono::steady_clock::time_point host_t;
   bool timing = false;
   std::vector<std::pair<int, hipEvent_t>> events;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> qrcp_events;
@@ -117,6 +124,7 @@ struct Factor {
   int dalloc(void **p, size_t bytes, bool keep);
   int dalloc_next(void **p, size_t bytes);
   void free_temp();
+  void release_retired();
   template <typename D>
   int upload(const std::vector<D> &v, D **out, bool keep);
   int upload_slots(const std::vector<int32_t> &v, int32_t **out);

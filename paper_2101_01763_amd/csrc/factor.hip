@@ -81,12 +81,25 @@ int Factor::dalloc_next(void **p, size_t bytes) {
   return next_temp.alloc(p, bytes, size_t(256) << 20);
 }
 
-// end of a level: this level's scratch goes, the next level's trailing
-// blocks become the current scratch
+void Bump::absorb(Bump &o) {
+  chunks.insert(chunks.end(), o.chunks.begin(), o.chunks.end());
+  bytes += o.bytes;
+  o.chunks.clear();
+  o.used = 0;
+  o.bytes = 0;
+}
+
+// End of a level: its scratch retires (kernels may still be reading it;
+// it returns to the block cache at the next stream synchronisation), and
+// the next level's trailing blocks become the current scratch.
 void Factor::free_temp() {
-  temp.release();
+  retired.absorb(temp);
   std::swap(temp, next_temp);
 }
+
+// Called right after a stream synchronisation: nothing queued uses the
+// retired scratch any more.
+void Factor::release_retired() { retired.release(); }
 
 Factor::~Factor() {
   // a build that failed may have left work queued on its chunks
@@ -95,6 +108,7 @@ Factor::~Factor() {
     if (g) (void)hipGraphExecDestroy(g);
   temp.release();
   next_temp.release();
+  retired.release();
   keep.release();
 }
 
@@ -292,6 +306,11 @@ int Factor::elim_batch(std::vector<ElimDesc> &items, int mode) {
 
 // ------------------------------------------------------------------ timing
 void Factor::mark(int phase) {
+  const auto now = std::chrono::steady_clock::now();
+  if (host_phase >= 0)
+    ph_host_ms[host_phase] += std::chrono::duration<double, std::milli>(now - host_t).count();
+  host_phase = phase;
+  host_t = now;
   if (!timing) return;
   hipEvent_t e;
   if (hipEventCreate(&e) != hipSuccess) return;
@@ -325,13 +344,14 @@ int Factor::level0(const spand_bsr_t &A, const NDResult &nd, LevelState &S) {
   const size_t tsz = fsize(ft);
   const int64_t b2 = int64_t(b) * b;
   // ---- interface-pair blocks: adjacency among separator elements + fill
-  std::set<std::pair<int, int>> pairs;
+  // (cluster pairs as sorted unique keys ce * ncl + cf)
+  std::vector<int64_t> pairs;
   std::vector<std::vector<int>> leaf_nbr(ncl);
   for (int e = 0; e < K; ++e) {
     for (int t = h_rowptr[e]; t < h_rowptr[e + 1]; ++t) {
       const int f = h_colind[t];
       const int ce = ecl[e], cf = ecl[f];
-      if (!S.interior[ce] && !S.interior[cf]) pairs.insert({ce, cf});
+      if (!S.interior[ce] && !S.interior[cf]) pairs.push_back(int64_t(ce) * ncl + cf);
       if (S.interior[ce] && !S.interior[cf]) leaf_nbr[ce].push_back(cf);
       if (S.interior[ce] && S.interior[cf] && ce != cf) {
         set_error("block (%d,%d) couples two different leaves: the matrix pattern does not "
@@ -345,20 +365,26 @@ int Factor::level0(const spand_bsr_t &A, const NDResult &nd, LevelState &S) {
     std::sort(v.begin(), v.end());
     v.erase(std::unique(v.begin(), v.end()), v.end());
     for (int n : v)
-      for (int m : v) pairs.insert({n, m});
+      for (int m : v) pairs.push_back(int64_t(n) * ncl + m);
   }
   for (int c = 0; c < ncl; ++c)
-    if (!S.interior[c]) pairs.insert({c, c});
+    if (!S.interior[c]) pairs.push_back(int64_t(c) * ncl + c);
+  std::sort(pairs.begin(), pairs.end());
+  pairs.erase(std::unique(pairs.begin(), pairs.end()), pairs.end());
   {
     PlanArena pa;
-    std::vector<std::pair<std::pair<int, int>, size_t>> offs;
-    for (auto &pr : pairs)
-      offs.push_back({pr, pa.add(size_t(S.size[pr.first]) * S.size[pr.second] * tsz)});
+    std::vector<size_t> offs;
+    offs.reserve(pairs.size());
+    for (int64_t key : pairs)
+      offs.push_back(pa.add(size_t(S.size[key / ncl]) * S.size[key % ncl] * tsz));
     void *base;
     SP_TRY(dalloc(&base, pa.total, false));
     SP_HIP(hipMemsetAsync(base, 0, pa.total, stream));
-    for (auto &o : offs)
-      S.blocks[o.first] = Blk{(char *)base + o.second, S.size[o.first.first], S.size[o.first.second]};
+    for (size_t q = 0; q < pairs.size(); ++q) {
+      const int i = int(pairs[q] / ncl), j = int(pairs[q] % ncl);
+      S.blocks.emplace_hint(S.blocks.end(), std::make_pair(i, j),
+                            Blk{(char *)base + offs[q], S.size[i], S.size[j]});
+    }
   }
   // ---- leaves: gather A_ss, invert
   std::vector<int> leaves;
@@ -423,6 +449,7 @@ int Factor::level0(const spand_bsr_t &A, const NDResult &nd, LevelState &S) {
       d.n = S.size[s];
       d.ncols = d.n;
       d.ld = d.n;
+      d.pad = s;                 // owner leaf (elim_batch reorders the items)
       items.push_back(d);
     }
     SP_TRY(elim_batch(items, 0));
@@ -438,8 +465,7 @@ int Factor::level0(const spand_bsr_t &A, const NDResult &nd, LevelState &S) {
       g.ldd = d.n;
       g.colperm = 1;
       g.ldd = ld4(d.n);
-      for (int s : leaves)
-        if (Ass[s] == d.A) g.dst = Ainv[s];
+      g.dst = Ainv[d.pad];
       rg.push_back(g);
     }
     RowGatherDesc *d_rg;
@@ -473,33 +499,70 @@ int Factor::level0(const spand_bsr_t &A, const NDResult &nd, LevelState &S) {
     }
   }
   {
-    // Schur targets keyed by (e_a, e_c), items ordered by (leaf, a, c)
-    std::map<std::pair<int, int>, std::vector<SchurItem>> tg;
+    // Schur targets (e_a, e_c); the items of a target stay in (leaf, a, c)
+    // order.  Targets get ids through short per-element lists, then a
+    // counting sort places the items (no ordered map on this hot path).
+    std::vector<std::vector<std::pair<int, int>>> tl(K);     // e_a -> (e_c, id)
+    std::vector<std::pair<int, int>> tkey;                    // id -> (e_a, e_c)
+    std::vector<int> cnt;
+    size_t nitems = 0;
+    for (int s : leaves) nitems += coup[s].size() * coup[s].size();
+    std::vector<int> item_tid;
+    item_tid.reserve(nitems);
     for (int s : leaves) {
       const auto &C = coup[s];
-      const int n = S.size[s];
-      for (const auto &ca : C)
+      for (const auto &ca : C) {
+        auto &v = tl[ca.e];
         for (const auto &cc : C) {
-          SchurItem it{};
-          it.a1 = ca.t_ef;      // A[e_a, f_a]
-          it.a2 = cc.t_fe;      // A[f_c, e_c]
-          it.Y = (char *)Ainv[s] + (size_t(epos[ca.f]) * b * ld4(n) + size_t(epos[cc.f]) * b) * tsz;
-          it.ldy = ld4(n);
-          tg[{ca.e, cc.e}].push_back(it);
+          int id = -1;
+          for (const auto &p : v)
+            if (p.first == cc.e) { id = p.second; break; }
+          if (id < 0) {
+            id = int(tkey.size());
+            v.push_back({cc.e, id});
+            tkey.push_back({ca.e, cc.e});
+            cnt.push_back(0);
+          }
+          ++cnt[id];
+          item_tid.push_back(id);
         }
+      }
     }
-    std::vector<SchurGroup> groups;
-    std::vector<SchurItem> items;
-    for (auto &kv : tg) {
-      const int ea = kv.first.first, ec = kv.first.second;
-      const Blk &B = S.blocks.at({ecl[ea], ecl[ec]});
-      SchurGroup g{};
-      g.target = (char *)B.p + (size_t(epos[ea]) * b * B.cols + size_t(epos[ec]) * b) * tsz;
-      g.ldt = B.cols;
-      g.item_begin = int(items.size());
-      items.insert(items.end(), kv.second.begin(), kv.second.end());
-      g.item_end = int(items.size());
-      groups.push_back(g);
+    std::vector<SchurGroup> groups(tkey.size());
+    std::vector<SchurItem> items(nitems);
+    {
+      int off = 0;
+      std::map<std::pair<int, int>, const Blk *> bcache;
+      for (size_t id = 0; id < tkey.size(); ++id) {
+        const int ea = tkey[id].first, ec = tkey[id].second;
+        const auto ck = std::make_pair(ecl[ea], ecl[ec]);
+        auto it = bcache.find(ck);
+        if (it == bcache.end()) it = bcache.emplace(ck, &S.blocks.at(ck)).first;
+        const Blk &B = *it->second;
+        SchurGroup &g = groups[id];
+        g.target = (char *)B.p + (size_t(epos[ea]) * b * B.cols + size_t(epos[ec]) * b) * tsz;
+        g.ldt = B.cols;
+        g.item_begin = off;
+        off += cnt[id];
+        g.item_end = g.item_begin;      // advanced while filling
+      }
+    }
+    {
+      size_t q = 0;
+      for (int s : leaves) {
+        const auto &C = coup[s];
+        const int n = S.size[s];
+        for (const auto &ca : C)
+          for (const auto &cc : C) {
+            SchurItem it{};
+            it.a1 = ca.t_ef;      // A[e_a, f_a]
+            it.a2 = cc.t_fe;      // A[f_c, e_c]
+            it.Y = (char *)Ainv[s] + (size_t(epos[ca.f]) * b * ld4(n) + size_t(epos[cc.f]) * b) * tsz;
+            it.ldy = ld4(n);
+            SchurGroup &g = groups[item_tid[q++]];
+            items[g.item_end++] = it;
+          }
+      }
     }
     SchurGroup *d_g;
     SchurItem *d_i;
@@ -517,8 +580,9 @@ int Factor::level0(const spand_bsr_t &A, const NDResult &nd, LevelState &S) {
     if (ncp) SP_TRY(dalloc(&cb, ncp * 2 * b2 * tsz, true));
     std::vector<CopyDesc> cc;
     // element -> list of (partner element, block ptr)
-    std::map<int, std::vector<std::pair<int, void *>>> fw_ns, fw_sn;  // keyed by sep elem e
-    std::map<int, std::vector<std::pair<int, void *>>> bw_sn, bw_ns;  // keyed by leaf elem f
+    using PairList = std::vector<std::vector<std::pair<int, void *>>>;
+    PairList fw_ns(K), fw_sn(K);   // indexed by separator element e
+    PairList bw_sn(K), bw_ns(K);   // indexed by leaf element f
     size_t q = 0;
     for (int s : leaves)
       for (const auto &c : coup[s]) {
@@ -541,32 +605,31 @@ int Factor::level0(const spand_bsr_t &A, const NDResult &nd, LevelState &S) {
         bw_ns[c.f].push_back({c.e, pns});
       }
     SP_TRY(copy_batch(cc, 0));
-    auto build = [&](std::map<int, std::vector<std::pair<int, void *>>> &m, int trans,
-                     std::vector<PullGroup> &G, std::vector<PullItem> &I, bool all_leaf) {
+    auto build = [&](PairList &m, int trans, std::vector<PullGroup> &G, std::vector<PullItem> &I,
+                     bool all_leaf) {
       std::vector<int> keys;
       if (all_leaf) {
         for (int s : leaves)
           for (int f : cl[s].elems) keys.push_back(f);
         std::sort(keys.begin(), keys.end());
       } else {
-        for (auto &kv : m) keys.push_back(kv.first);
+        for (int e = 0; e < K; ++e)
+          if (!m[e].empty()) keys.push_back(e);
       }
       for (int key : keys) {
         PullGroup g{};
         g.oslot = d_iota + int64_t(key) * b;
         g.rows = b;
         g.item_begin = int(I.size());
-        auto it = m.find(key);
-        if (it != m.end())
-          for (auto &pp : it->second) {
-            PullItem p{};
-            p.B = pp.second;
-            p.islot = d_iota + int64_t(pp.first) * b;
-            p.rows = p.cols = b;
-            p.ldb = b;
-            p.trans = trans;
-            I.push_back(p);
-          }
+        for (auto &pp : m[key]) {
+          PullItem p{};
+          p.B = pp.second;
+          p.islot = d_iota + int64_t(pp.first) * b;
+          p.rows = p.cols = b;
+          p.ldb = b;
+          p.trans = trans;
+          I.push_back(p);
+        }
         g.item_end = int(I.size());
         G.push_back(g);
       }
@@ -672,6 +735,7 @@ int Factor::eliminate_dense(int l, LevelState &S) {
     d.n = n;
     d.ncols = n;
     d.ld = n;
+    d.pad = s;                   // owner cluster (elim_batch reorders the items)
     items.push_back(d);
     flops += 2.0 * double(n) * n * n;
     apply_bytes += double(n) * n * tsz * 2;
@@ -688,8 +752,7 @@ int Factor::eliminate_dense(int l, LevelState &S) {
       g.lds = d.n;
       g.ldd = ld4(d.n);
       g.colperm = 1;
-      for (int s : ints)
-        if (S.blocks.at({s, s}).p == d.A) g.dst = Ainv[s];
+      g.dst = Ainv[d.pad];
       rg.push_back(g);
       mr = std::max(mr, d.n);
     }
@@ -940,6 +1003,7 @@ int Factor::sparsify(int l, const NDResult &nd, LevelState &S, LevelState &Nx) {
     el.n = m;
     el.ncols = 2 * m;
     el.ld = 2 * m;
+    el.pad = s;                  // owner interface (elim_batch reorders the items)
     items.push_back(el);
     flops += 4.0 * double(m) * m * m;
   }
@@ -953,9 +1017,7 @@ int Factor::sparsify(int l, const NDResult &nd, LevelState &S, LevelState &Nx) {
   {
     std::vector<RowGatherDesc> rg;
     for (auto &d : items) {
-      int s = -1;
-      for (int c : ifs)
-        if (Aug[c] == d.A) s = c;
+      const int s = d.pad;
       RowGatherDesc g{};
       g.src = d.A;
       g.piv = d.piv;
@@ -1057,9 +1119,10 @@ int Factor::sparsify(int l, const NDResult &nd, LevelState &S, LevelState &Nx) {
       ncols[s] = nc;
       wo[s] = pw.add(size_t(S.size[s]) * ld4(std::max(nc, 1)) * tsz);
     }
-    void *wbase = nullptr;
+    void *wbase = nullptr, *wbase2 = nullptr;
     if (!ifs.empty()) {
       SP_TRY(dalloc(&wbase, pw.total, false));
+      SP_TRY(dalloc(&wbase2, pw.total, false));     // compaction target of the kernel
       SP_HIP(hipMemsetAsync(wbase, 0, pw.total, stream));
     }
     std::vector<CopyDesc> wc;
@@ -1073,9 +1136,9 @@ int Factor::sparsify(int l, const NDResult &nd, LevelState &S, LevelState &Nx) {
       SP_TRY(dalloc(&Vm[s], size_t(m) * m * tsz, false));
       void *tau, *vn1, *vn2, *sel;
       SP_TRY(dalloc(&tau, size_t(m) * 8, false));
-      SP_TRY(dalloc(&vn1, size_t(std::max(nc, 1)) * 8, false));
-      SP_TRY(dalloc(&vn2, size_t(std::max(nc, 1)) * 8, false));
-      SP_TRY(dalloc(&sel, size_t(std::max(nc, 1)) * 4, false));
+      SP_TRY(dalloc(&vn1, size_t(ldw) * 8, false));
+      SP_TRY(dalloc(&vn2, size_t(ldw) * 8, false));
+      SP_TRY(dalloc(&sel, size_t(ldw) * 4, false));
       int off = 0;
       for (int n : nb[s]) {
         const Blk &B = S.blocks.at({s, n});
@@ -1106,6 +1169,7 @@ int Factor::sparsify(int l, const NDResult &nd, LevelState &S, LevelState &Nx) {
       }
       QrcpDesc Qd{};
       Qd.W = Wm[s];
+      Qd.W2 = (char *)wbase2 + wo[s];
       Qd.Q = Qm[s];
       Qd.V = Vm[s];
       Qd.tau = (double *)tau;
@@ -1148,6 +1212,7 @@ int Factor::sparsify(int l, const NDResult &nd, LevelState &S, LevelState &Nx) {
   if (!ifs.empty())
     SP_HIP(hipMemcpyAsync(ks.data(), kout, ifs.size() * 4, hipMemcpyDeviceToHost, stream));
   SP_HIP(hipStreamSynchronize(stream));
+  release_retired();
   std::vector<int> kk(ncl, 0);
   {
     RankStat rs;
@@ -1376,7 +1441,6 @@ int Factor::build(const spand_bsr_t &A, const spand_grid_t &g, const spand_opts_
     if (l == L - 1) break;
     LevelState Nx;
     SP_TRY(sparsify(l, nd, S, Nx));
-    SP_HIP(hipStreamSynchronize(stream));
     free_temp();
     S = std::move(Nx);
   }
@@ -1387,6 +1451,7 @@ int Factor::build(const spand_bsr_t &A, const spand_grid_t &g, const spand_opts_
   SP_HIP(hipStreamSynchronize(stream));
   temp.release();
   next_temp.release();
+  retired.release();
   alloc_ms = pool_driver_ms() - drv0;
   int flag = 0;
   SP_HIP(hipMemcpy(&flag, d_flag, 4, hipMemcpyDeviceToHost));
@@ -1524,6 +1589,7 @@ void Factor::fill_stats(spand_factor_stats_t *st) const {
   st->qrcp_bytes = qrcp_bytes;
   st->qrcp_flops = qrcp_flops;
   st->t_alloc_ms = alloc_ms;
+  for (int p = 0; p < 6; ++p) st->t_plan_ms[p] = ph_host_ms[p];
   st->resident_bytes = int64_t(keep.bytes);
 }
 

@@ -169,13 +169,14 @@ struct SchurGroup {
 
 // QRCP problem (rank-revealing QR of a row-major m x ncols matrix W)
 struct QrcpDesc {
-  const void *W;       // m x ncols row-major
+  const void *W;       // m x ncols row-major (padding columns up to ldw are zero)
+  void *W2;            // m x ldw workspace: W with its live column groups packed left
   void *Q;             // m x m row-major output
   void *V;             // m x m workspace: kept vectors q_t = V[t*m ..], then completion terms
   double *tau;         // [m] completion signs
-  double *vn1;         // [ncols]
-  double *vn2;         // [ncols]
-  int32_t *sel;        // [ncols] selected flags
+  double *vn1;         // [ldw]
+  double *vn2;         // [ldw]
+  int32_t *sel;        // [ldw] selected (or padding) flags
   int32_t *k_out;      // rank
   int32_t m, ncols;
   int32_t ldw;         // leading dimension of W (multiple of 4, padding zero)

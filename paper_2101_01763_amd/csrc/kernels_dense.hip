@@ -850,7 +850,7 @@ __device__ inline void wg_gemm(int M, int N, int K, FA A, FB B, FE epi, double *
 //     is orthogonal and H E = Q_c S.  Output Q = [Q_c | H(:, k:m)].
 //     Rows k.. of V receive G2 S; tau receives S.
 template <typename T>
-__global__ __launch_bounds__(256) void k_qrcp(const QrcpDesc *__restrict__ items, double eps,
+__global__ __launch_bounds__(256, 4) void k_qrcp(const QrcpDesc *__restrict__ items, double eps,
                                               int force_full, int MS, int GS) {
   const QrcpDesc d = items[blockIdx.x];
   const int m = d.m, nc = d.ncols;
@@ -858,7 +858,8 @@ __global__ __launch_bounds__(256) void k_qrcp(const QrcpDesc *__restrict__ items
   constexpr int VN = 16 / sizeof(T);            // columns per 16-byte load
   using VT = typename std::conditional<sizeof(T) == 4, float4, double2>::type;
   const int ngrp = (nc + VN - 1) / VN;
-  const T *W = (const T *)d.W;
+  const T *W = (const T *)d.W;      // current layout (packed copies alternate with W2)
+  T *Wother = (T *)d.W2;
   T *Q = (T *)d.Q;
   T *Qt = (T *)d.V;
   double *vn1 = d.vn1, *vn2 = d.vn2;
@@ -870,7 +871,8 @@ __global__ __launch_bounds__(256) void k_qrcp(const QrcpDesc *__restrict__ items
   const int ldsd = max(2 * MS, 2048);
   double *u = qsm, *cbuf = qsm + MS;
   int *act = reinterpret_cast<int *>(qsm + ldsd), *act2 = act + GS;
-  __shared__ int s_nact, s_n2, s_j, s_nflag, s_nf;
+  __shared__ int s_j, s_nflag, s_nf;
+  __shared__ int wtot[4];
   __shared__ int s_fl[64];
   __shared__ double red[16];
   __shared__ double s_piv;
@@ -881,6 +883,7 @@ __global__ __launch_bounds__(256) void k_qrcp(const QrcpDesc *__restrict__ items
     for (int t0 = wid * 4; t0 < n; t0 += 16) {
       const T *q0 = Qt + (int64_t)t0 * m;
       double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+#pragma unroll 4
       for (int r = lane; r < m; r += 64) {
         const double xr = x[r];
         a0 += double(q0[r]) * xr;
@@ -901,17 +904,20 @@ __global__ __launch_bounds__(256) void k_qrcp(const QrcpDesc *__restrict__ items
     }
     __syncthreads();
   };
-  // x -= sum_{t<n} c[t] q_t
+  // x -= sum_{t<n} c[t] q_t (eight independent sums keep eight loads in flight)
   auto qsub = [&](double *x, int n, const double *c) {
     for (int r = tid; r < m; r += 256) {
-      double s0 = 0.0, s1 = 0.0;
+      double sv[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) sv[q] = 0.0;
+      const T *qr = Qt + r;
       int t = 0;
-      for (; t + 2 <= n; t += 2) {
-        s0 += double(Qt[(int64_t)t * m + r]) * c[t];
-        s1 += double(Qt[(int64_t)(t + 1) * m + r]) * c[t + 1];
+      for (; t + 8 <= n; t += 8) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) sv[q] += double(qr[(int64_t)(t + q) * m]) * c[t + q];
       }
-      if (t < n) s0 += double(Qt[(int64_t)t * m + r]) * c[t];
-      x[r] -= s0 + s1;
+      for (; t < n; ++t) sv[0] += double(qr[(int64_t)t * m]) * c[t];
+      x[r] -= ((sv[0] + sv[1]) + (sv[2] + sv[3])) + ((sv[4] + sv[5]) + (sv[6] + sv[7]));
     }
     __syncthreads();
   };
@@ -943,11 +949,9 @@ __global__ __launch_bounds__(256) void k_qrcp(const QrcpDesc *__restrict__ items
 #pragma unroll
     for (int q = 0; q < VN; ++q) {
       const int j = g * VN + q;
-      if (j < nc) {
-        vn1[j] = sqrt(acc[q]);
-        vn2[j] = vn1[j];
-        sel[j] = 0;
-      }
+      vn1[j] = j < nc ? sqrt(acc[q]) : 0.0;
+      vn2[j] = vn1[j];
+      sel[j] = j < nc ? 0 : 1;      // padding columns never take part
     }
   }
   __syncthreads();
@@ -966,23 +970,40 @@ __global__ __launch_bounds__(256) void k_qrcp(const QrcpDesc *__restrict__ items
 #pragma unroll
     for (int q = 0; q < VN; ++q) {
       const int j = g * VN + q;
-      if (j < nc && !sel[j] && vn1[j] > thr) a = true;
+      if (!sel[j] && vn1[j] > thr) a = true;
     }
     return a;
   };
-  if (tid == 0) s_nact = 0;
-  __syncthreads();
-  for (int g = tid; g < ngrp; g += 256)
-    if (live_group(g)) act[atomicAdd(&s_nact, 1)] = g;
-  __syncthreads();
+  // Order-preserving filter of a list of groups (src == nullptr: all groups
+  // 0..n-1) into dst; returns the new length (the same on every thread).
+  auto filter = [&](const int *src, int n, int *dst) {
+    int base = 0;
+    for (int q0 = 0; q0 < n; q0 += 256) {
+      const int qa = q0 + tid;
+      const int g = qa < n ? (src ? src[qa] : qa) : 0;
+      const bool keep = qa < n && live_group(g);
+      const unsigned long long bal = __ballot(keep);
+      if (lane == 0) wtot[wid] = __popcll(bal);
+      __syncthreads();
+      int off = base;
+      for (int w = 0; w < wid; ++w) off += wtot[w];
+      if (keep) dst[off + __popcll(bal & ((1ull << lane) - 1ull))] = g;
+      base += wtot[0] + wtot[1] + wtot[2] + wtot[3];
+      __syncthreads();
+    }
+    return base;
+  };
+  int nact_cur = filter(nullptr, ngrp, act);   // same value on every thread
+  int cur_ngrp = ngrp;                         // groups of the current layout
 
   // ---- 2. pivoted Gram-Schmidt
   double R00 = 0.0;
   int k = 0;
   const int imax = min(m, nc);
   for (int i = 0; i < imax; ++i) {
-    // pivot: largest remaining column norm, ties -> smallest index
-    const int nact = s_nact;
+    // pivot: largest remaining column norm, ties -> smallest index (the
+    // packed layouts keep the original column order)
+    const int nact = nact_cur;
     double bv = -1.0;
     int bi = INT_MAX;
     for (int qa = tid; qa < nact; qa += 256) {
@@ -990,7 +1011,7 @@ __global__ __launch_bounds__(256) void k_qrcp(const QrcpDesc *__restrict__ items
 #pragma unroll
       for (int q = 0; q < VN; ++q) {
         const int j = g * VN + q;
-        if (j >= nc || sel[j]) continue;
+        if (sel[j]) continue;
         const double v = vn1[j];
         if (v > bv || (v == bv && j < bi)) { bv = v; bi = j; }
       }
@@ -1058,7 +1079,7 @@ __global__ __launch_bounds__(256) void k_qrcp(const QrcpDesc *__restrict__ items
         for (int q = 0; q < VN; ++q) acc[q] = 0.0;
         if (live) {
           const T *base = W + (int64_t)g * VN;
-#pragma unroll 2
+#pragma unroll 4
           for (int r = sl * 4; r < m4; r += 4 * RS) {
             VT v[4];
 #pragma unroll
@@ -1086,7 +1107,7 @@ __global__ __launch_bounds__(256) void k_qrcp(const QrcpDesc *__restrict__ items
 #pragma unroll
           for (int q = 0; q < VN; ++q) {
             const int j = g * VN + q;
-            if (j >= nc || sel[j]) continue;
+            if (sel[j]) continue;
             const double a = vn1[j];
             if (a != 0.0) {
               double temp = fabs(acc[q]) / a;
@@ -1114,7 +1135,7 @@ __global__ __launch_bounds__(256) void k_qrcp(const QrcpDesc *__restrict__ items
 #pragma unroll
           for (int q = 0; q < VN; ++q) {
             const int j = g * VN + q;
-            if (j < nc && !sel[j] && vn1[j] < 0.0) {
+            if (!sel[j] && vn1[j] < 0.0) {
               const int p = atomicAdd(&s_nf, 1);
               if (p < 64) s_fl[p] = j;
             }
@@ -1142,18 +1163,47 @@ __global__ __launch_bounds__(256) void k_qrcp(const QrcpDesc *__restrict__ items
     }
     k = i + 1;
     // keep the groups that can still hold a pivot
-    if (tid == 0) s_n2 = 0;
-    __syncthreads();
-    for (int qa = tid; qa < nact; qa += 256) {
-      const int g = act[qa];
-      if (live_group(g)) act2[atomicAdd(&s_n2, 1)] = g;
-    }
-    __syncthreads();
-    if (tid == 0) s_nact = s_n2;
+    nact_cur = filter(act, nact, act2);
     {
       int *t = act;
       act = act2;
       act2 = t;
+    }
+    // Once at most half of the groups of the layout are live, pack the live
+    // groups to the left of the other buffer (rows keep their stride), so
+    // that every later pass reads whole contiguous rows.  The norms and
+    // flags move with their columns; the order of columns is kept.
+    if (2 * nact_cur <= cur_ngrp && i + 1 < imax) {
+      const int na = nact_cur;
+      T *dst = Wother;
+      for (int r = wid; r < m; r += 4)
+        for (int p = lane; p < na; p += 64)
+          *reinterpret_cast<VT *>(dst + (int64_t)r * ldw + p * VN) =
+              *reinterpret_cast<const VT *>(W + (int64_t)r * ldw + act[p] * VN);
+      // norms and flags, in rounds: a source position is never below its
+      // destination, so reading a round completely before writing it is safe
+      for (int p0 = 0; p0 < na * VN; p0 += 256) {
+        const int pos = p0 + tid;
+        double a1 = 0.0, a2 = 0.0;
+        int sf = 1;
+        if (pos < na * VN) {
+          const int src = act[pos / VN] * VN + pos % VN;
+          a1 = vn1[src];
+          a2 = vn2[src];
+          sf = sel[src];
+        }
+        __syncthreads();
+        if (pos < na * VN) {
+          vn1[pos] = a1;
+          vn2[pos] = a2;
+          sel[pos] = sf;
+        }
+        __syncthreads();
+      }
+      for (int p = tid; p < na; p += 256) act[p] = p;
+      Wother = const_cast<T *>(W);
+      W = dst;
+      cur_ngrp = na;
     }
     __syncthreads();
   }

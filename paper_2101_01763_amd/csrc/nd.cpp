@@ -129,10 +129,12 @@ NDResult nested_dissection(int nx, int ny, bool px, bool py, int L) {
     for (int v : sep) insep[v] = 0;
     boxes[2 * k] = lbox;
     boxes[2 * k + 1] = rbox;
-    for (int e = 0; e < K; ++e) {
-      if (box_at[d][e] != k) continue;
-      box_at[d + 1][e] = coord[e] < mid ? 2 * k : 2 * k + 1;
-    }
+    // the depth-d boxes tile the grid: box k is exactly its rectangle
+    for (int y = y0; y < y1; ++y)
+      for (int x = x0; x < x1; ++x) {
+        const int e = y * nx + x;
+        box_at[d + 1][e] = coord[e] < mid ? 2 * k : 2 * k + 1;
+      }
     work.push_back(std::move(wl));
     work.push_back(std::move(wr));
   }
@@ -141,22 +143,41 @@ NDResult nested_dissection(int nx, int ny, bool px, bool py, int L) {
   for (int e = 0; e < K; ++e) lvl[e] = R.node_level[node_of[e]];
   R.levels.resize(L);
   R.children.resize(L);
+  // clusters of level l: live elements grouped by (node, depth-(L-1-l) box),
+  // keys ascending, elements ascending; one sort per level of (node, box,
+  // element) triples, packed into one word when they fit (node and box ids
+  // are below 2^L <= 2K)
+  const int ebits = [&] { int b = 1; while ((int64_t(1) << b) < K) ++b; return b; }();
+  const int kbits = ebits + 1;
+  const bool packed = 2 * kbits + ebits <= 64;
   std::map<std::pair<int64_t, int64_t>, int> prev_index;
+  std::vector<std::array<int64_t, 3>> kt;
   for (int l = 0; l < L; ++l) {
-    std::map<std::pair<int64_t, int64_t>, std::vector<int32_t>> keys;
-    for (int e = 0; e < K; ++e) {
-      if (lvl[e] < l) continue;
-      keys[{int64_t(node_of[e]), box_at[L - 1 - l][e]}].push_back(e);
+    kt.clear();
+    const auto &bl = box_at[L - 1 - l];
+    for (int e = 0; e < K; ++e)
+      if (lvl[e] >= l) kt.push_back({int64_t(node_of[e]), bl[e], int64_t(e)});
+    if (packed) {
+      std::vector<uint64_t> kw(kt.size());
+      for (size_t q = 0; q < kt.size(); ++q)
+        kw[q] = (((uint64_t(kt[q][0]) << kbits) | uint64_t(kt[q][1])) << ebits) | uint64_t(kt[q][2]);
+      std::sort(kw.begin(), kw.end());
+      const uint64_t emask = (uint64_t(1) << ebits) - 1, bmask = (uint64_t(1) << kbits) - 1;
+      for (size_t q = 0; q < kw.size(); ++q)
+        kt[q] = {int64_t(kw[q] >> (ebits + kbits)), int64_t((kw[q] >> ebits) & bmask),
+                 int64_t(kw[q] & emask)};
+    } else {
+      std::sort(kt.begin(), kt.end());
     }
     std::vector<NDCluster> cl;
     std::map<std::pair<int64_t, int64_t>, int> index;
-    for (auto &kv : keys) {
+    for (size_t q = 0; q < kt.size();) {
       NDCluster c;
-      c.node = int32_t(kv.first.first);
-      c.box = int32_t(kv.first.second);
-      c.elems = kv.second;  // inserted in ascending e
+      c.node = int32_t(kt[q][0]);
+      c.box = int32_t(kt[q][1]);
+      while (q < kt.size() && kt[q][0] == c.node && kt[q][1] == c.box) c.elems.push_back(int32_t(kt[q++][2]));
       c.interior = R.node_level[c.node] == l;
-      index[kv.first] = int(cl.size());
+      index[{int64_t(c.node), int64_t(c.box)}] = int(cl.size());
       cl.push_back(std::move(c));
     }
     if (l >= 1) {
