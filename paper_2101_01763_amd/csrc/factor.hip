@@ -657,7 +657,7 @@ int Factor::level0(const spand_bsr_t &A, const NDResult &nd, LevelState &S) {
       d.lda = ld4(S.size[s]);
       gv.push_back(d);
       os.push_back(&S.slots[s]);
-      apply_bytes += double(S.size[s]) * S.size[s] * tsz * 2;
+      apply_bytes += double(S.size[s]) * S.size[s] * tsz * 2;   // A_ss^-1: both sweeps
     }
     // band height of the sweep GEMVs: autotuned once per (precision, b)
     {
@@ -669,7 +669,7 @@ int Factor::level0(const spand_bsr_t &A, const NDResult &nd, LevelState &S) {
     }
     SP_TRY(AL.inv.set(*this, gv, os, 0));
     SP_TRY(AL.invT.set(*this, gv, os, 1));
-    apply_bytes += double(ncp) * 2 * b2 * tsz * 2;
+    apply_bytes += double(ncp) * 2 * b2 * tsz;   // A_ns forward, A_sn backward
     for (int s : leaves) flops += 2.0 * double(S.size[s]) * S.size[s] * S.size[s];
   }
   for (int s : leaves) S.size[s] = 0;   // eliminated
@@ -738,7 +738,7 @@ int Factor::eliminate_dense(int l, LevelState &S) {
     d.pad = s;                   // owner cluster (elim_batch reorders the items)
     items.push_back(d);
     flops += 2.0 * double(n) * n * n;
-    apply_bytes += double(n) * n * tsz * 2;
+    apply_bytes += double(n) * n * tsz * 2;   // A_ss^-1: both sweeps
   }
   SP_TRY(elim_batch(items, 0));
   {
@@ -873,7 +873,7 @@ int Factor::eliminate_dense(int l, LevelState &S) {
       q.ldb = Asn.cols;
       q.trans = 1;
       tfw[n].push_back(q);
-      apply_bytes += double(Ans.rows) * Ans.cols * tsz * 2 + double(Asn.rows) * Asn.cols * tsz * 2;
+      apply_bytes += double(Ans.rows) * Ans.cols * tsz + double(Asn.rows) * Asn.cols * tsz;
       if (S.size[n] > PULL_MAXR || S.size[s] > GEMV_MAXC) {
         set_error("coupling block %dx%d exceeds the sweep kernel limit", S.size[n], S.size[s]);
         return SPAND_EINVAL;
@@ -1264,7 +1264,7 @@ int Factor::sparsify(int l, const NDResult &nd, LevelState &S, LevelState &Nx) {
       d.A = Bp;
       gb.push_back(d);
       os.push_back(&S.slots[s]);
-      apply_bytes += 4.0 * double(m) * m * tsz;
+      apply_bytes += 2.0 * double(m) * m * tsz;   // F_s forward, B_s backward
       flops += 4.0 * double(m) * m * m;
     }
     SP_TRY(gemm_batch(gm));
