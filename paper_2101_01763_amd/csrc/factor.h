@@ -30,8 +30,11 @@ struct Factor;
 struct PullSet {
   PullGroup *d_groups = nullptr;
   PullItem *d_items = nullptr;
-  int n = 0;
-  int set(Factor &F, const std::vector<PullGroup> &G, const std::vector<PullItem> &I);
+  PullChunk *d_chunks = nullptr;
+  int n = 0;          // groups
+  int nchunks = 0;
+  int trans = 0;      // every item of a set has the same orientation
+  int set(Factor &F, std::vector<PullGroup> G, const std::vector<PullItem> &I);
 };
 
 // batched GEMVs of one sweep step, split into bands of output rows; for

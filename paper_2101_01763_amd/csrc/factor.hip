@@ -676,10 +676,36 @@ int Factor::level0(const spand_bsr_t &A, const NDResult &nd, LevelState &S) {
   return SPAND_OK;
 }
 
-int PullSet::set(Factor &F, const std::vector<PullGroup> &G, const std::vector<PullItem> &I) {
+int PullSet::set(Factor &F, std::vector<PullGroup> G, const std::vector<PullItem> &I) {
   n = int(G.size());
+  if (!n) return SPAND_OK;
+  trans = -1;
+  std::vector<PullChunk> ch;
+  for (size_t gi = 0; gi < G.size(); ++gi) {
+    PullGroup &g = G[gi];
+    bool vec = true;
+    for (int it = g.item_begin; it < g.item_end; ++it) {
+      const PullItem &p = I[it];
+      if (trans < 0) trans = p.trans;
+      if (p.trans != trans) {
+        set_error("a pull set mixes transposed and plain blocks");
+        return SPAND_EINVAL;
+      }
+      if (p.cols > GEMV_MAXC) {
+        set_error("coupling block with %d columns exceeds the sweep kernel limit %d", p.cols, GEMV_MAXC);
+        return SPAND_EINVAL;
+      }
+      if (p.ldb % 4 != 0 || reinterpret_cast<uintptr_t>(p.B) % 16 != 0) vec = false;
+    }
+    g.pad = vec ? 1 : 0;
+    for (int r0 = 0; r0 < g.rows; r0 += PULL_ROWS)
+      ch.push_back(PullChunk{int32_t(gi), r0, std::min(PULL_ROWS, g.rows - r0), 0});
+  }
+  if (trans < 0) trans = 0;
+  nchunks = int(ch.size());
   SP_TRY(F.upload(G, &d_groups, true));
   SP_TRY(F.upload(I, &d_items, true));
+  SP_TRY(F.upload(ch, &d_chunks, true));
   return SPAND_OK;
 }
 
@@ -1478,28 +1504,28 @@ int Factor::sweeps(double *x, int transpose, hipStream_t st) {
       const ApplyLevel &A = lv[l];
       if (A.fw.n) {
         SP_TRY(launch_gemv(ft, A.inv.d_items, A.inv.d_chunks, A.inv.nchunks, x, d_tbuf, 1.0, 0.0, st));
-        SP_TRY(launch_pull2(ft, A.fw.d_groups, A.fw.n, A.fw.d_items, d_tbuf, x, -1.0, 1.0, st));
+        SP_TRY(launch_pull2(ft, A.fw.d_groups, A.fw.d_items, A.fw.d_chunks, A.fw.nchunks, A.fw.trans, d_tbuf, x, -1.0, 1.0, st));
       }
       SP_TRY(inplace(A.F));
     }
     for (int l = L - 1; l >= 0; --l) {
       const ApplyLevel &A = lv[l];
       SP_TRY(inplace(A.B));
-      if (A.bw.n) SP_TRY(launch_pull2(ft, A.bw.d_groups, A.bw.n, A.bw.d_items, x, x, -1.0, 1.0, st));
+      if (A.bw.n) SP_TRY(launch_pull2(ft, A.bw.d_groups, A.bw.d_items, A.bw.d_chunks, A.bw.nchunks, A.bw.trans, x, x, -1.0, 1.0, st));
       SP_TRY(inplace(A.inv));
     }
   } else {
     for (int l = 0; l < L; ++l) {
       const ApplyLevel &A = lv[l];
       SP_TRY(inplace(A.invT));
-      if (A.tfw.n) SP_TRY(launch_pull2(ft, A.tfw.d_groups, A.tfw.n, A.tfw.d_items, x, x, -1.0, 1.0, st));
+      if (A.tfw.n) SP_TRY(launch_pull2(ft, A.tfw.d_groups, A.tfw.d_items, A.tfw.d_chunks, A.tfw.nchunks, A.tfw.trans, x, x, -1.0, 1.0, st));
       SP_TRY(inplace(A.BT));
     }
     for (int l = L - 1; l >= 0; --l) {
       const ApplyLevel &A = lv[l];
       SP_TRY(inplace(A.FT));
       if (A.tbw.n && A.invT.n) {
-        SP_TRY(launch_pull2(ft, A.tbw.d_groups, A.tbw.n, A.tbw.d_items, x, d_tbuf, 1.0, 0.0, st));
+        SP_TRY(launch_pull2(ft, A.tbw.d_groups, A.tbw.d_items, A.tbw.d_chunks, A.tbw.nchunks, A.tbw.trans, x, d_tbuf, 1.0, 0.0, st));
         SP_TRY(launch_gemv(ft, A.invT.d_items, A.invT.d_chunks, A.invT.nchunks, d_tbuf, x, -1.0, 1.0, st));
       }
     }

@@ -149,7 +149,10 @@ struct PullGroup {
   const int32_t *oslot;
   int32_t rows;
   int32_t item_begin, item_end;
-  int32_t pad;
+  int32_t pad;              // bit 0: every block allows 16-byte row loads (set by the host)
+};
+struct PullChunk {          // up to PULL_ROWS output rows of one group
+  int32_t group, row0, nrows, pad;
 };
 
 // Level-0 element Schur update: target -= A1 * Y * A2 (b x b blocks)
@@ -240,8 +243,7 @@ int launch_gemv(FType t, const GemvDesc *d_items, const GemvChunk *d_chunks, int
                 const double *in, double *out, double alpha, double beta, hipStream_t st);
 int launch_slot_copy(const int32_t *slots, int64_t n, const double *src, double *dst,
                      hipStream_t st);
-int launch_pull(FType t, const PullGroup *d_groups, int ngroups, const PullItem *d_items,
-                const double *in, double *out, double alpha, hipStream_t st);
+
 int launch_spmv(const spand_bsr_t &A, int transpose, double alpha, const double *x,
                 double beta, double *y, const double *z, double gz, const double *w,
                 double gw, hipStream_t st);

@@ -10,8 +10,10 @@ constexpr int TS_CHUNK = 512;     // rows per partial Gram block
 constexpr int TS_MAXS = 8;        // largest s
 constexpr int TS_MAXA = 160;      // largest restart + s + 1
 
-int launch_pull2(FType t, const PullGroup *d_groups, int ngroups, const PullItem *d_items,
-                 const double *in, double *out, double alpha, double beta, hipStream_t st);
+constexpr int PULL_ROWS = 64;     // output rows per pull workgroup
+int launch_pull2(FType t, const PullGroup *d_groups, const PullItem *d_items,
+                 const PullChunk *d_chunks, int nchunks, int trans, const double *in,
+                 double *out, double alpha, double beta, hipStream_t st);
 int launch_spmv_g(const spand_bsr_t &A, int G, double alpha, const double *x, double beta,
                   double *y, const double *z, double gz, const double *w, double gw,
                   hipStream_t st);

@@ -125,65 +125,125 @@ int launch_slot_copy(const int32_t *slots, int64_t n, const double *src, double 
 
 // ------------------------------------------------------------------ pull
 // out[oslot[r]] = beta*out[oslot[r]] + alpha * sum_items op(B_i) in[islot_i]
-// One workgroup per group (output cluster), items accumulated in order.
-template <typename T>
+// One workgroup per chunk of at most 64 output rows of a group; the items of
+// the group are accumulated in order, in registers (a row is always owned by
+// the same lanes).  Per item the input segment is staged in LDS.
+//  * op(B) = B: Q lanes per row.  Q = 4 with 16-byte loads when the group's
+//    blocks allow it (flag bit 0 of the group: leading dimensions multiple of
+//    4, 16-byte aligned rows), else Q = 16 with scalar loads; the Q partial
+//    sums combine by shuffles.
+//  * op(B) = B^T (B stored cols x rows): one lane per output row, four
+//    slices of the columns, combined through LDS at the end.
+template <typename T, int TRANS>
 __global__ __launch_bounds__(256) void k_pull(const PullGroup *__restrict__ groups,
                                               const PullItem *__restrict__ items,
+                                              const PullChunk *__restrict__ chunks,
                                               const double *__restrict__ in,
                                               double *__restrict__ out, double alpha,
                                               double beta) {
-  const PullGroup g = groups[blockIdx.x];
-  __shared__ double acc[PULL_MAXR];
+  using VW = Vec16<T>;
+  constexpr int VN = VW::N;
+  const PullChunk ch = chunks[blockIdx.x];
+  const PullGroup g = groups[ch.group];
   __shared__ double xs[GEMV_MAXC];
-  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-  for (int r = tid; r < g.rows; r += 256) acc[r] = 0.0;
+  __shared__ double part[256];
+  const int tid = threadIdx.x;
+  const bool vec = (g.pad & 1) != 0;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
   for (int it = g.item_begin; it < g.item_end; ++it) {
     const PullItem p = items[it];
     __syncthreads();
     for (int c = tid; c < p.cols; c += 256) xs[c] = in[p.islot[c]];
     __syncthreads();
     const T *B = (const T *)p.B;
-    if (!p.trans) {
-      for (int r = wid; r < p.rows; r += 4) {
-        const T *row = B + (int64_t)r * p.ldb;
+    if (!TRANS) {
+      if (vec) {
+        const int rr = tid >> 2, q = tid & 3;
         double a = 0.0;
-        for (int c = lane; c < p.cols; c += 64) a += double(row[c]) * xs[c];
-        a = wsum(a);
-        if (lane == 0) acc[r] += a;
+        if (rr < ch.nrows) {
+          const T *row = B + (int64_t)(ch.row0 + rr) * p.ldb;
+          const int cv = p.cols / VN * VN;
+#pragma unroll 4
+          for (int c = q * VN; c < cv; c += 4 * VN) {
+            const typename VW::V v = *reinterpret_cast<const typename VW::V *>(row + c);
+            T e[VN];
+            VW::get(v, e);
+#pragma unroll
+            for (int u = 0; u < VN; ++u) a += double(e[u]) * xs[c + u];
+          }
+          for (int c = cv + q; c < p.cols; c += 4) a += double(row[c]) * xs[c];
+        }
+        a += __shfl_xor(a, 1, 64);
+        a += __shfl_xor(a, 2, 64);
+        acc[0] += a;
+      } else {
+        const int rr = tid >> 4, q = tid & 15;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int r = rr + 16 * t;
+          double a = 0.0;
+          if (r < ch.nrows) {
+            const T *row = B + (int64_t)(ch.row0 + r) * p.ldb;
+            for (int c = q; c < p.cols; c += 16) a += double(row[c]) * xs[c];
+          }
+#pragma unroll
+          for (int o = 1; o < 16; o <<= 1) a += __shfl_xor(a, o, 64);
+          acc[t] += a;
+        }
       }
     } else {
-      for (int r = tid; r < p.rows; r += 256) {
-        double a = 0.0;
-        for (int c = 0; c < p.cols; ++c) a += double(B[(int64_t)c * p.ldb + r]) * xs[c];
-        acc[r] += a;
+      const int rr = tid & 63, cs = tid >> 6;
+      if (rr < ch.nrows) {
+        const T *col = B + ch.row0 + rr;
+        double a0 = 0.0, a1 = 0.0;
+        int c = cs;
+        for (; c + 4 < p.cols; c += 8) {
+          a0 += double(col[(int64_t)c * p.ldb]) * xs[c];
+          a1 += double(col[(int64_t)(c + 4) * p.ldb]) * xs[c + 4];
+        }
+        if (c < p.cols) a0 += double(col[(int64_t)c * p.ldb]) * xs[c];
+        acc[0] += a0 + a1;
       }
     }
   }
-  __syncthreads();
-  for (int r = tid; r < g.rows; r += 256) {
-    const int o = g.oslot[r];
-    double v = alpha * acc[r];
+  auto put = [&](int r, double v) {
+    const int o = g.oslot[ch.row0 + r];
+    v *= alpha;
     if (beta != 0.0) v += beta * out[o];
     out[o] = v;
+  };
+  if (!TRANS) {
+    if (vec) {
+      const int rr = tid >> 2;
+      if ((tid & 3) == 0 && rr < ch.nrows) put(rr, acc[0]);
+    } else {
+      const int rr = tid >> 4;
+      if ((tid & 15) == 0)
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+          if (rr + 16 * t < ch.nrows) put(rr + 16 * t, acc[t]);
+    }
+  } else {
+    part[tid] = acc[0];
+    __syncthreads();
+    if (tid < ch.nrows) put(tid, (part[tid] + part[tid + 64]) + (part[tid + 128] + part[tid + 192]));
   }
 }
 
-int launch_pull2(FType t, const PullGroup *d_groups, int ngroups, const PullItem *d_items,
-                 const double *in, double *out, double alpha, double beta, hipStream_t st) {
-  if (ngroups <= 0) return SPAND_OK;
-  if (t == FType::F64)
-    hipLaunchKernelGGL(k_pull<double>, dim3(ngroups), dim3(256), 0, st, d_groups, d_items, in,
-                       out, alpha, beta);
-  else
-    hipLaunchKernelGGL(k_pull<float>, dim3(ngroups), dim3(256), 0, st, d_groups, d_items, in,
-                       out, alpha, beta);
+int launch_pull2(FType t, const PullGroup *d_groups, const PullItem *d_items,
+                 const PullChunk *d_chunks, int nchunks, int trans, const double *in,
+                 double *out, double alpha, double beta, hipStream_t st) {
+  if (nchunks <= 0) return SPAND_OK;
+  const dim3 g(nchunks), b(256);
+  if (t == FType::F64) {
+    if (trans) hipLaunchKernelGGL((k_pull<double, 1>), g, b, 0, st, d_groups, d_items, d_chunks, in, out, alpha, beta);
+    else hipLaunchKernelGGL((k_pull<double, 0>), g, b, 0, st, d_groups, d_items, d_chunks, in, out, alpha, beta);
+  } else {
+    if (trans) hipLaunchKernelGGL((k_pull<float, 1>), g, b, 0, st, d_groups, d_items, d_chunks, in, out, alpha, beta);
+    else hipLaunchKernelGGL((k_pull<float, 0>), g, b, 0, st, d_groups, d_items, d_chunks, in, out, alpha, beta);
+  }
   SP_HIP(hipGetLastError());
   return SPAND_OK;
-}
-
-int launch_pull(FType t, const PullGroup *d_groups, int ngroups, const PullItem *d_items,
-                const double *in, double *out, double alpha, hipStream_t st) {
-  return launch_pull2(t, d_groups, ngroups, d_items, in, out, alpha, 1.0, st);
 }
 
 // ------------------------------------------------------------------ SpMV
