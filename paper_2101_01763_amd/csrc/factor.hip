@@ -206,35 +206,41 @@ int Factor::elim_batch(std::vector<ElimDesc> &items, int mode) {
   std::sort(items.begin(), items.end(), [](const ElimDesc &a, const ElimDesc &b) {
     return a.n > b.n;
   });
-  // Gauss-Jordan with pivoting is blocked: panels of 16 columns update only
-  // their block of ELIM_BLK columns; the rest of the matrix receives each
-  // block at once as one rank-ELIM_BLK product on the matrix cores.
-  const bool blocked = mode == 0;
-  size_t nP = 0, nT = 0, nI = 0, nB = 0;
+  // The eliminations are blocked: panels of 16 columns update only their
+  // block of ELIM_BLK columns; the rest of the matrix receives each block at
+  // once as one rank-ELIM_BLK product on the matrix cores.  In-place
+  // Gauss-Jordan (modes 0, 2) leaves the block's multipliers in the block
+  // columns themselves; LU (mode 1) accumulates them in PB.
+  const bool lu = mode == 1;
+  size_t nP = 0, nT = 0, nI = 0, nB = 0, nPB = 0;
   for (auto &d : items) {
     nP += size_t(d.n) * ELIM_NB;
     nT += size_t(ELIM_NB) * d.ld;
     nI += size_t(d.n);
-    if (blocked) nB += size_t(ELIM_BLK) * d.ld;
+    nB += size_t(ELIM_BLK) * d.ld;
+    if (lu) nPB += size_t(d.n) * ELIM_BLK;
   }
-  void *P, *T, *piv, *used, *TB = nullptr;
+  void *P, *T, *piv, *used, *TB = nullptr, *PB = nullptr;
   SP_TRY(dalloc(&P, nP * fsize(ft), false));
   SP_TRY(dalloc(&T, nT * fsize(ft), false));
   SP_TRY(dalloc(&piv, nI * 4, false));
   SP_TRY(dalloc(&used, nI * 4, false));
-  if (blocked) SP_TRY(dalloc(&TB, nB * fsize(ft), false));
+  SP_TRY(dalloc(&TB, nB * fsize(ft), false));
+  if (lu) SP_TRY(dalloc(&PB, nPB * fsize(ft), false));
   SP_HIP(hipMemsetAsync(used, 0, nI * 4, stream));
-  size_t oP = 0, oT = 0, oI = 0, oB = 0;
+  size_t oP = 0, oT = 0, oI = 0, oB = 0, oPB = 0;
   for (auto &d : items) {
     d.P = (char *)P + oP * fsize(ft);
     d.T = (char *)T + oT * fsize(ft);
     d.piv = (int32_t *)piv + oI;
     d.used = (int32_t *)used + oI;
-    d.TB = blocked ? (char *)TB + oB * fsize(ft) : nullptr;
+    d.TB = (char *)TB + oB * fsize(ft);
+    d.PB = lu ? (char *)PB + oPB * fsize(ft) : nullptr;
     oP += size_t(d.n) * ELIM_NB;
     oT += size_t(ELIM_NB) * d.ld;
     oI += size_t(d.n);
-    if (blocked) oB += size_t(ELIM_BLK) * d.ld;
+    oB += size_t(ELIM_BLK) * d.ld;
+    if (lu) oPB += size_t(d.n) * ELIM_BLK;
   }
   ElimDesc *d_items;
   SP_TRY(upload(items, &d_items, false));
@@ -244,16 +250,8 @@ int Factor::elim_batch(std::vector<ElimDesc> &items, int mode) {
     while (na < int(items.size()) && items[na].n > k) ++na;
     return na;
   };
-  if (!blocked) {
-    for (int k = 0; k < nmax; k += ELIM_NB) {
-      const int nactive = nactive_at(k);
-      const int c0 = mode == 1 ? k : 0;
-      const int max_tiles = int(cdiv(nmax, 64) * cdiv(items[0].ncols - c0, 64));
-      SP_TRY(launch_elim_step(ft, d_items, nactive, k, mode, max_tiles, d_flag, 0, INT_MAX, stream));
-    }
-    return SPAND_OK;
-  }
-  // trailing products of every block: columns [0, k0) and [k0 + ELIM_BLK, ncols)
+  // trailing products of every block: columns [k0 + ELIM_BLK, ncols), and for
+  // Gauss-Jordan also [0, k0)
   const size_t tsz = fsize(ft);
   std::vector<GemmDesc> gd;
   std::vector<int32_t> ts(1, 0);
@@ -266,19 +264,20 @@ int Factor::elim_batch(std::vector<ElimDesc> &items, int mode) {
       auto add = [&](int c_off, int width) {
         if (width <= 0) return;
         GemmDesc g{};
-        g.A = (char *)d.A + size_t(k0) * tsz;
+        g.A = lu ? d.PB : (char *)d.A + size_t(k0) * tsz;
+        g.lda = lu ? ELIM_BLK : d.ld;
         g.B = (char *)d.TB + size_t(c_off) * tsz;
         g.C = (char *)d.A + size_t(c_off) * tsz;
         g.M = d.n;
         g.N = width;
         g.K = wb;
-        g.lda = g.ldb = g.ldc = d.ld;
+        g.ldb = g.ldc = d.ld;
         g.alpha = 1.0;
         g.beta = 1.0;
         gd.push_back(g);
         ts.push_back(ts.back() + int32_t(cdiv(g.M, 64) * cdiv(g.N, 64)));
       };
-      add(0, k0);
+      if (!lu) add(0, k0);
       add(k0 + ELIM_BLK, d.ncols - k0 - ELIM_BLK);
     }
   }
@@ -293,8 +292,9 @@ int Factor::elim_batch(std::vector<ElimDesc> &items, int mode) {
       const int max_tiles = int(cdiv(nmax, 64));     // one 64-wide column tile: the block
       SP_TRY(launch_elim_step(ft, d_items, nactive, k, mode, max_tiles, d_flag, k0,
                               k0 + ELIM_BLK, stream));
+      if (lu) SP_TRY(launch_elim_pb(ft, d_items, nactive, k, k0, stream));
     }
-    SP_TRY(launch_elim_extract(ft, d_items, nactive_at(k0), k0, stream));
+    SP_TRY(launch_elim_extract(ft, d_items, nactive_at(k0), k0, lu ? 1 : 0, stream));
     const size_t g0 = bstart[b], g1 = bstart[b + 1];
     if (g1 > g0) {
       // this block's descriptors; their tile numbers start at ts[g0]

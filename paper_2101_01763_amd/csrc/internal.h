@@ -119,7 +119,8 @@ struct ElimDesc {
   int32_t ncols;    // total columns (n or 2n)
   int32_t ld;
   int32_t pad;
-  void *TB;         // workspace ELIM_BLK x ld (blocked Gauss-Jordan: pivot rows of a block)
+  void *TB;         // workspace ELIM_BLK x ld (blocked elimination: pivot rows of a block)
+  void *PB;         // workspace n x ELIM_BLK (blocked LU: multipliers of a block)
 };
 
 // Dense GEMV with gather/scatter through slot lists:
@@ -211,7 +212,8 @@ int launch_copy_t(FType t, int src_is_factor, const CopyDesc *d_items, int n, in
 // the first nactive have n > k.
 int launch_elim_step(FType t, const ElimDesc *d_items, int nactive, int k, int mode,
                      int max_tiles, int *d_flag, int cw0, int cw1, hipStream_t st);
-int launch_elim_extract(FType t, const ElimDesc *d_items, int nactive, int k0, hipStream_t st);
+int launch_elim_extract(FType t, const ElimDesc *d_items, int nactive, int k0, int lu, hipStream_t st);
+int launch_elim_pb(FType t, const ElimDesc *d_items, int nactive, int k, int k0, hipStream_t st);
 // out[j, c] = src[piv[j], colperm ? pinv[c] : c + col_off]
 struct RowGatherDesc {
   const void *src;

@@ -629,12 +629,15 @@ int launch_elim_step(FType t, const ElimDesc *d_items, int nactive, int k, int m
   return SPAND_OK;
 }
 
-// Blocked Gauss-Jordan (mode 0): after the panels of the block
-// [k0, k0 + wb) have been applied to the block's own columns, the pivot rows
-// of every other column move to TB (wb x ld) and are zeroed in A, so that
-// A[:, outside] += A[:, k0:k0+wb] TB is the whole block's effect there.
+// Blocked elimination: after the panels of the block [k0, k0 + wb) have been
+// applied to the block's own columns, the pivot rows of the columns the block
+// has not touched yet move to TB (wb x ld) and are zeroed in A, so that
+// A[:, rest] += P_B TB is the whole block's effect there (P_B = the block
+// columns for Gauss-Jordan, the tracked multipliers PB for LU).  Gauss-Jordan
+// updates every column outside the block; LU only the columns after it.
 template <typename T>
-__global__ __launch_bounds__(256) void k_elim_extract(const ElimDesc *__restrict__ items, int k0) {
+__global__ __launch_bounds__(256) void k_elim_extract(const ElimDesc *__restrict__ items, int k0,
+                                                      int lu) {
   const ElimDesc d = items[blockIdx.x];
   if (k0 >= d.n) return;
   const int wb = min(ELIM_BLK, d.n - k0);
@@ -645,7 +648,7 @@ __global__ __launch_bounds__(256) void k_elim_extract(const ElimDesc *__restrict
   for (int q = blockIdx.y; q < wb; q += gridDim.y) {
     const int64_t src = (int64_t)d.piv[k0 + q] * ld;
     for (int c = threadIdx.x; c < d.ncols; c += 256) {
-      if (c >= k0 && c < cw1) {
+      if (c < cw1 && (lu || c >= k0)) {
         TB[(int64_t)q * ld + c] = T(0);
       } else {
         TB[(int64_t)q * ld + c] = A[src + c];
@@ -655,13 +658,63 @@ __global__ __launch_bounds__(256) void k_elim_extract(const ElimDesc *__restrict
   }
 }
 
-int launch_elim_extract(FType t, const ElimDesc *d_items, int nactive, int k0, hipStream_t st) {
+int launch_elim_extract(FType t, const ElimDesc *d_items, int nactive, int k0, int lu,
+                        hipStream_t st) {
   if (nactive <= 0) return SPAND_OK;
   const dim3 grid(nactive, 16);
   if (t == FType::F64)
-    hipLaunchKernelGGL(k_elim_extract<double>, grid, dim3(256), 0, st, d_items, k0);
+    hipLaunchKernelGGL(k_elim_extract<double>, grid, dim3(256), 0, st, d_items, k0, lu);
   else
-    hipLaunchKernelGGL(k_elim_extract<float>, grid, dim3(256), 0, st, d_items, k0);
+    hipLaunchKernelGGL(k_elim_extract<float>, grid, dim3(256), 0, st, d_items, k0, lu);
+  SP_HIP(hipGetLastError());
+  return SPAND_OK;
+}
+
+// Blocked LU: fold panel k (multipliers Y = d.P, n x w, pivots piv[k..k+w))
+// into the block's multiplier matrix PB (n x ELIM_BLK) of block k0: the
+// earlier panels' columns 0..c1 receive this panel's effect (their pivot
+// rows of this panel are moved out and zeroed, then PB += Y * those rows),
+// and Y becomes columns c1..c1+w.  One workgroup per item.
+template <typename T>
+__global__ __launch_bounds__(256) void k_elim_pb(const ElimDesc *__restrict__ items, int k, int k0) {
+  const ElimDesc d = items[blockIdx.x];
+  if (k >= d.n) return;
+  const int w = min(ELIM_NB, d.n - k);
+  const int c1 = k - k0;                   // columns of earlier panels in PB
+  const T *Y = (const T *)d.P;
+  T *PB = (T *)d.PB;
+  __shared__ double ts[ELIM_NB * ELIM_BLK];
+  const int tid = threadIdx.x;
+  if (c1 > 0) {
+    for (int idx = tid; idx < w * c1; idx += 256) {
+      const int t = idx / c1, c = idx % c1;
+      ts[idx] = double(PB[(int64_t)d.piv[k + t] * ELIM_BLK + c]);
+    }
+    __syncthreads();
+    for (int idx = tid; idx < w * c1; idx += 256) {
+      const int t = idx / c1, c = idx % c1;
+      PB[(int64_t)d.piv[k + t] * ELIM_BLK + c] = T(0);
+    }
+    __syncthreads();
+    for (int idx = tid; idx < d.n * c1; idx += 256) {
+      const int i = idx / c1, c = idx % c1;
+      double v = double(PB[(int64_t)i * ELIM_BLK + c]);
+      for (int t = 0; t < w; ++t) v += double(Y[(int64_t)i * ELIM_NB + t]) * ts[t * c1 + c];
+      PB[(int64_t)i * ELIM_BLK + c] = T(v);
+    }
+  }
+  for (int idx = tid; idx < d.n * w; idx += 256) {
+    const int i = idx / w, t = idx % w;
+    PB[(int64_t)i * ELIM_BLK + c1 + t] = Y[(int64_t)i * ELIM_NB + t];
+  }
+}
+
+int launch_elim_pb(FType t, const ElimDesc *d_items, int nactive, int k, int k0, hipStream_t st) {
+  if (nactive <= 0) return SPAND_OK;
+  if (t == FType::F64)
+    hipLaunchKernelGGL(k_elim_pb<double>, dim3(nactive), dim3(256), 0, st, d_items, k, k0);
+  else
+    hipLaunchKernelGGL(k_elim_pb<float>, dim3(nactive), dim3(256), 0, st, d_items, k, k0);
   SP_HIP(hipGetLastError());
   return SPAND_OK;
 }
