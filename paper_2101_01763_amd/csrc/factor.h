@@ -108,6 +108,8 @@ struct Factor {
   double ph_ms[PH_COUNT] = {0};
   double ph_host_ms[PH_COUNT] = {0};   // host time (planning + launches) per phase
   int host_phase = -1;
+  std::chrono::steady_clock::time_point trace_t = std::chrono::steady_clock::now();
+  void trace(const char *what, int l);
   std::chrono::steady_clock::time_point host_t;
   bool timing = false;
   std::vector<std::pair<int, hipEvent_t>> events;

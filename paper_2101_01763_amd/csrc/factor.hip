@@ -165,8 +165,12 @@ int Factor::gemm_batch(const std::vector<GemmDesc> &items) {
   SP_TRY(upload(ts, &d_ts, false));
   for (int tm = 0; tm < 4; ++tm) {
     const int a = start[tm], b = start[tm + 1];
-    if (b > a)
-      SP_TRY(launch_gemm(ft, d_items + a, d_ts + a, b - a, ts[b] - ts[a], stream, ts[a], tm));
+    if (b > a) {
+      int uniform = ts[a + 1] - ts[a];
+      for (int q = a; q < b && uniform > 0; ++q)
+        if (ts[q + 1] - ts[q] != uniform) uniform = 0;
+      SP_TRY(launch_gemm(ft, d_items + a, d_ts + a, b - a, ts[b] - ts[a], stream, ts[a], tm, uniform));
+    }
   }
   return SPAND_OK;
 }
@@ -289,7 +293,7 @@ int Factor::elim_batch(std::vector<ElimDesc> &items, int mode) {
   for (int b = 0, k0 = 0; k0 < nmax; ++b, k0 += ELIM_BLK) {
     for (int k = k0; k < std::min(nmax, k0 + ELIM_BLK); k += ELIM_NB) {
       const int nactive = nactive_at(k);
-      const int max_tiles = int(cdiv(nmax, 64));     // one 64-wide column tile: the block
+      const int max_tiles = int(cdiv(nmax, 64) * cdiv(ELIM_BLK, 64));   // the block's columns
       SP_TRY(launch_elim_step(ft, d_items, nactive, k, mode, max_tiles, d_flag, k0,
                               k0 + ELIM_BLK, stream));
       if (lu) SP_TRY(launch_elim_pb(ft, d_items, nactive, k, k0, stream));
@@ -298,7 +302,11 @@ int Factor::elim_batch(std::vector<ElimDesc> &items, int mode) {
     const size_t g0 = bstart[b], g1 = bstart[b + 1];
     if (g1 > g0) {
       // this block's descriptors; their tile numbers start at ts[g0]
-      SP_TRY(launch_gemm(ft, d_gd + g0, d_ts + g0, int(g1 - g0), ts[g1] - ts[g0], stream, ts[g0], 0));
+      int uniform = ts[g0 + 1] - ts[g0];
+      for (size_t q = g0; q < g1 && uniform > 0; ++q)
+        if (ts[q + 1] - ts[q] != uniform) uniform = 0;
+      SP_TRY(launch_gemm(ft, d_gd + g0, d_ts + g0, int(g1 - g0), ts[g1] - ts[g0], stream, ts[g0], 0,
+                         uniform));
     }
   }
   return SPAND_OK;
@@ -316,6 +324,21 @@ void Factor::mark(int phase) {
   if (hipEventCreate(&e) != hipSuccess) return;
   (void)hipEventRecord(e, stream);
   events.push_back({phase, e});
+}
+
+// ------------------------------------------------------------------ host trace
+// SPAND_HOST_TRACE set: every planning step prints its host time to stderr
+// (diagnostics of the host/device overlap; no effect otherwise).
+static bool host_trace_on() {
+  static const bool on = std::getenv("SPAND_HOST_TRACE") != nullptr;
+  return on;
+}
+void Factor::trace(const char *what, int l) {
+  if (!host_trace_on()) return;
+  const auto now = std::chrono::steady_clock::now();
+  std::fprintf(stderr, "[spand host] L%-2d %-26s %8.2f ms\n", l, what,
+               std::chrono::duration<double, std::milli>(now - trace_t).count());
+  trace_t = now;
 }
 
 // ------------------------------------------------------------------ level 0
@@ -341,6 +364,7 @@ int Factor::level0(const spand_bsr_t &A, const NDResult &nd, LevelState &S) {
       for (int q = 0; q < b; ++q) sl.push_back(e * b + q);
   }
   SP_TRY(upload_level_slots(S));
+  trace("L0 slots", 0);
   const size_t tsz = fsize(ft);
   const int64_t b2 = int64_t(b) * b;
   // ---- interface-pair blocks: adjacency among separator elements + fill
@@ -371,6 +395,7 @@ int Factor::level0(const spand_bsr_t &A, const NDResult &nd, LevelState &S) {
     if (!S.interior[c]) pairs.push_back(int64_t(c) * ncl + c);
   std::sort(pairs.begin(), pairs.end());
   pairs.erase(std::unique(pairs.begin(), pairs.end()), pairs.end());
+  std::vector<Blk> pblk(pairs.size());
   {
     PlanArena pa;
     std::vector<size_t> offs;
@@ -382,10 +407,14 @@ int Factor::level0(const spand_bsr_t &A, const NDResult &nd, LevelState &S) {
     SP_HIP(hipMemsetAsync(base, 0, pa.total, stream));
     for (size_t q = 0; q < pairs.size(); ++q) {
       const int i = int(pairs[q] / ncl), j = int(pairs[q] % ncl);
-      S.blocks.emplace_hint(S.blocks.end(), std::make_pair(i, j),
-                            Blk{(char *)base + offs[q], S.size[i], S.size[j]});
+      pblk[q] = Blk{(char *)base + offs[q], S.size[i], S.size[j]};
+      S.blocks.emplace_hint(S.blocks.end(), std::make_pair(i, j), pblk[q]);
     }
   }
+  auto pair_blk = [&](int i, int j) -> const Blk & {
+    const int64_t key = int64_t(i) * ncl + j;
+    return pblk[size_t(std::lower_bound(pairs.begin(), pairs.end(), key) - pairs.begin())];
+  };
   // ---- leaves: gather A_ss, invert
   std::vector<int> leaves;
   for (int c = 0; c < ncl; ++c)
@@ -431,7 +460,7 @@ int Factor::level0(const spand_bsr_t &A, const NDResult &nd, LevelState &S) {
         d.ldd = n;
         cps.push_back(d);
       } else if (!S.interior[ce] && !S.interior[cf]) {
-        const Blk &B = S.blocks.at({ce, cf});
+        const Blk &B = pair_blk(ce, cf);
         d.dst = (char *)B.p + (size_t(epos[e]) * b * B.cols + size_t(epos[f]) * b) * tsz;
         d.ldd = B.cols;
         cps.push_back(d);
@@ -440,6 +469,7 @@ int Factor::level0(const spand_bsr_t &A, const NDResult &nd, LevelState &S) {
   }
   mark(PH_GATHER);
   SP_TRY(copy_batch(cps, 0));
+  trace("gather copies", 0);
   mark(PH_LU);
   {
     std::vector<ElimDesc> items;
@@ -453,6 +483,7 @@ int Factor::level0(const spand_bsr_t &A, const NDResult &nd, LevelState &S) {
       items.push_back(d);
     }
     SP_TRY(elim_batch(items, 0));
+    trace("elim enqueue", 0);
     std::vector<RowGatherDesc> rg;
     for (auto &d : items) {
       // find the leaf whose A_ss this is
@@ -569,6 +600,7 @@ int Factor::level0(const spand_bsr_t &A, const NDResult &nd, LevelState &S) {
     SP_TRY(upload(groups, &d_g, false));
     SP_TRY(upload(items, &d_i, false));
     SP_TRY(launch_schur_elem(ft, b, A.d_val, d_g, int(groups.size()), d_i, stream));
+    trace("schur plan+launch", 0);
     flops += double(items.size()) * 4.0 * b * b * b;
   }
   // ---- stored couplings and apply descriptors of level 0
@@ -605,6 +637,7 @@ int Factor::level0(const spand_bsr_t &A, const NDResult &nd, LevelState &S) {
         bw_ns[c.f].push_back({c.e, pns});
       }
     SP_TRY(copy_batch(cc, 0));
+    trace("coupling copies", 0);
     auto build = [&](PairList &m, int trans, std::vector<PullGroup> &G, std::vector<PullItem> &I,
                      bool all_leaf) {
       std::vector<int> keys;
@@ -647,6 +680,7 @@ int Factor::level0(const spand_bsr_t &A, const NDResult &nd, LevelState &S) {
     G.clear(); I.clear();
     build(bw_ns, 1, G, I, true);
     SP_TRY(AL.tbw.set(*this, G, I));
+    trace("pull sets", 0);
     std::vector<GemvDesc> gv;
     std::vector<const std::vector<int32_t> *> os;
     for (int s : leaves) {
@@ -669,6 +703,7 @@ int Factor::level0(const spand_bsr_t &A, const NDResult &nd, LevelState &S) {
     }
     SP_TRY(AL.inv.set(*this, gv, os, 0));
     SP_TRY(AL.invT.set(*this, gv, os, 1));
+    trace("inverse sweep sets", 0);
     apply_bytes += double(ncp) * 2 * b2 * tsz;   // A_ns forward, A_sn backward
     for (int s : leaves) flops += 2.0 * double(S.size[s]) * S.size[s] * S.size[s];
   }
@@ -767,6 +802,7 @@ int Factor::eliminate_dense(int l, LevelState &S) {
     apply_bytes += double(n) * n * tsz * 2;   // A_ss^-1: both sweeps
   }
   SP_TRY(elim_batch(items, 0));
+  trace("elim enqueue", l);
   {
     std::vector<RowGatherDesc> rg;
     int mr = 0;
@@ -813,6 +849,7 @@ int Factor::eliminate_dense(int l, LevelState &S) {
         flops += 2.0 * double(B.rows) * B.rows * B.cols;
       }
     SP_TRY(gemm_batch(gm));
+    trace("gemm", l);
   }
   // fill blocks and deterministic rounds of A_nm -= A_ns X_sm
   std::map<std::pair<int, int>, std::vector<int>> contrib;
@@ -859,6 +896,7 @@ int Factor::eliminate_dense(int l, LevelState &S) {
       flops += 2.0 * double(T.rows) * T.cols * Ans.cols;
     }
     SP_TRY(gemm_batch(gm));
+    trace("gemm", l);
   }
   // apply descriptors
   std::vector<GemvDesc> gv;
@@ -961,6 +999,7 @@ int Factor::eliminate_dense(int l, LevelState &S) {
     G2.push_back(g2);
   }
   SP_TRY(AL.bw.set(*this, G, I));
+  trace("sweep sets", l);
   SP_TRY(AL.tbw.set(*this, G2, I2));
   // eliminated clusters leave the trailing matrix
   for (int s : ints) {
@@ -1040,6 +1079,7 @@ int Factor::sparsify(int l, const NDResult &nd, LevelState &S, LevelState &Nx) {
     SP_TRY(launch_eye(ft, d_e, int(eyes.size()), maxm, stream));
   }
   SP_TRY(elim_batch(items, 1));
+  trace("scale LU enqueue", l);
   {
     std::vector<RowGatherDesc> rg;
     for (auto &d : items) {
@@ -1086,6 +1126,7 @@ int Factor::sparsify(int l, const NDResult &nd, LevelState &S, LevelState &Nx) {
     ScaleDesc *d_sc;
     SP_TRY(upload(sc, &d_sc, false));
     SP_TRY(launch_scale(ft, d_sc, int(sc.size()), stream));
+    trace("scale done", l);
   }
   // scaled blocks A'_ij = Lh_i^-1 P_i^T A_ij Uh_j^-1 (i != j)
   {
@@ -1127,6 +1168,7 @@ int Factor::sparsify(int l, const NDResult &nd, LevelState &S, LevelState &Nx) {
     }
     SP_TRY(gemm_batch(g1));
     SP_TRY(gemm_batch(g2));
+    trace("gemm pair", l);
   }
   // ---- RRQR of W = [A'_sn ... | A'_ns^T ...]
   mark(PH_RRQR);
@@ -1229,6 +1271,7 @@ int Factor::sparsify(int l, const NDResult &nd, LevelState &S, LevelState &Nx) {
       (void)hipEventRecord(qe0, stream);
     }
     SP_TRY(launch_qrcp(ft, d_q, int(qd.size()), eps, eps == 0.0 ? 1 : 0, mq, mg, stream));
+    trace("qrcp plan+launch", l);
     if (timing) {
       (void)hipEventRecord(qe1, stream);
       qrcp_events.push_back({qe0, qe1});
@@ -1238,6 +1281,7 @@ int Factor::sparsify(int l, const NDResult &nd, LevelState &S, LevelState &Nx) {
   if (!ifs.empty())
     SP_HIP(hipMemcpyAsync(ks.data(), kout, ifs.size() * 4, hipMemcpyDeviceToHost, stream));
   SP_HIP(hipStreamSynchronize(stream));
+  trace("sync", -1);
   release_retired();
   std::vector<int> kk(ncl, 0);
   {
@@ -1294,10 +1338,12 @@ int Factor::sparsify(int l, const NDResult &nd, LevelState &S, LevelState &Nx) {
       flops += 4.0 * double(m) * m * m;
     }
     SP_TRY(gemm_batch(gm));
+    trace("gemm", l);
     SP_TRY(AL.F.set(*this, gf, os, 0));
     SP_TRY(AL.B.set(*this, gb, os, 0));
     SP_TRY(AL.FT.set(*this, gf, os, 1));
     SP_TRY(AL.BT.set(*this, gb, os, 1));
+    trace("compress F/B sets", l);
   }
   // ---- merge: next-level clusters from the coarse parts
   const auto &cl1 = nd.levels[l + 1];
@@ -1318,21 +1364,26 @@ int Factor::sparsify(int l, const NDResult &nd, LevelState &S, LevelState &Nx) {
     }
     Nx.size[I] = o;
   }
-  // parent blocks
-  std::set<std::pair<int, int>> pp;
+  // parent blocks (sorted unique keys parent_i * ncl1 + parent_j)
+  std::vector<int64_t> pkeys;
+  pkeys.reserve(S.blocks.size());
   for (auto &kv : S.blocks) {
     const int i = kv.first.first, j = kv.first.second;
     if (S.size[i] == 0 || S.size[j] == 0 || kk[i] == 0 || kk[j] == 0) continue;
     if (parent[i] < 0 || parent[j] < 0) continue;
-    pp.insert({parent[i], parent[j]});
+    pkeys.push_back(int64_t(parent[i]) * ncl1 + parent[j]);
   }
+  std::sort(pkeys.begin(), pkeys.end());
+  pkeys.erase(std::unique(pkeys.begin(), pkeys.end()), pkeys.end());
+  std::vector<Blk> pblk(pkeys.size());
   {
     PlanArena pk, pt;
-    std::vector<std::tuple<std::pair<int, int>, size_t, bool>> offs;
-    for (auto &pr : pp) {
-      const bool keep = Nx.interior[pr.first] || Nx.interior[pr.second];
-      const size_t bytes = size_t(Nx.size[pr.first]) * Nx.size[pr.second] * tsz;
-      offs.push_back({pr, keep ? pk.add(bytes) : pt.add(bytes), keep});
+    std::vector<std::pair<size_t, bool>> offs(pkeys.size());
+    for (size_t q = 0; q < pkeys.size(); ++q) {
+      const int i = int(pkeys[q] / ncl1), j = int(pkeys[q] % ncl1);
+      const bool keep = Nx.interior[i] || Nx.interior[j];
+      const size_t bytes = size_t(Nx.size[i]) * Nx.size[j] * tsz;
+      offs[q] = {keep ? pk.add(bytes) : pt.add(bytes), keep};
     }
     void *bk = nullptr, *bt = nullptr;
     if (pk.total) {
@@ -1344,12 +1395,17 @@ int Factor::sparsify(int l, const NDResult &nd, LevelState &S, LevelState &Nx) {
       SP_HIP(hipMemsetAsync(bt, 0, pt.total, stream));
     }
     Nx.blocks.clear();
-    for (auto &o : offs) {
-      auto pr = std::get<0>(o);
-      char *base = (char *)(std::get<2>(o) ? bk : bt);
-      Nx.blocks[pr] = Blk{base + std::get<1>(o), Nx.size[pr.first], Nx.size[pr.second]};
+    for (size_t q = 0; q < pkeys.size(); ++q) {
+      const int i = int(pkeys[q] / ncl1), j = int(pkeys[q] % ncl1);
+      char *base = (char *)(offs[q].second ? bk : bt);
+      pblk[q] = Blk{base + offs[q].first, Nx.size[i], Nx.size[j]};
+      Nx.blocks.emplace_hint(Nx.blocks.end(), std::make_pair(i, j), pblk[q]);
     }
   }
+  auto parent_blk = [&](int i, int j) -> const Blk & {
+    const int64_t key = int64_t(i) * ncl1 + j;
+    return pblk[size_t(std::lower_bound(pkeys.begin(), pkeys.end(), key) - pkeys.begin())];
+  };
   // compression A_ij <- Q_ic^T A'_ij Q_jc into the parent block; diagonals -> I_k
   {
     std::vector<GemmDesc> g1, g2;
@@ -1358,7 +1414,7 @@ int Factor::sparsify(int l, const NDResult &nd, LevelState &S, LevelState &Nx) {
     for (auto &kv : S.blocks) {
       const int i = kv.first.first, j = kv.first.second;
       if (S.size[i] == 0 || S.size[j] == 0 || kk[i] == 0 || kk[j] == 0) continue;
-      const Blk &P = Nx.blocks.at({parent[i], parent[j]});
+      const Blk &P = parent_blk(parent[i], parent[j]);
       if (i == j) {
         EyeDesc e{};
         e.A = (char *)P.p + (size_t(poff[i]) * P.cols + poff[i]) * tsz;
@@ -1400,17 +1456,20 @@ int Factor::sparsify(int l, const NDResult &nd, LevelState &S, LevelState &Nx) {
     }
     SP_TRY(gemm_batch(g1));
     SP_TRY(gemm_batch(g2));
+    trace("gemm pair", l);
     EyeDesc *d_e;
     SP_TRY(upload(ey, &d_e, false));
     SP_TRY(launch_eye(ft, d_e, int(ey.size()), maxk, stream));
   }
   SP_TRY(upload_level_slots(Nx));
+  trace("merge plan", l);
   return SPAND_OK;
 }
 
 // ------------------------------------------------------------------ driver
 int Factor::build(const spand_bsr_t &A, const spand_grid_t &g, const spand_opts_t &o) {
   auto t0 = std::chrono::steady_clock::now();
+  trace_t = t0;
   const double drv0 = pool_driver_ms();
   bs = A.bs;
   K = A.n_brows;
@@ -1423,6 +1482,7 @@ int Factor::build(const spand_bsr_t &A, const spand_grid_t &g, const spand_opts_
   SP_HIP(hipMemcpyAsync(h_rowptr.data(), A.d_rowptr, (K + 1) * 4, hipMemcpyDeviceToHost, stream));
   SP_HIP(hipMemcpyAsync(h_colind.data(), A.d_colind, A.nnzb * 4, hipMemcpyDeviceToHost, stream));
   SP_HIP(hipStreamSynchronize(stream));
+  trace("sync", -1);
   if (h_rowptr[0] != 0 || h_rowptr[K] != A.nnzb) {
     set_error("rowptr[0] must be 0 and rowptr[n_brows] must equal nnzb");
     return SPAND_EINVAL;
@@ -1439,7 +1499,9 @@ int Factor::build(const spand_bsr_t &A, const spand_grid_t &g, const spand_opts_
       }
     }
   }
+  trace("read pattern + validate", -1);
   NDResult nd = nested_dissection(g.nx, g.ny, g.periodic_x != 0, g.periodic_y != 0, L);
+  trace("nested dissection", -1);
   void *p;
   SP_TRY(dalloc(&p, size_t(N) * 4, true));
   d_iota = (int32_t *)p;
@@ -1475,6 +1537,7 @@ int Factor::build(const spand_bsr_t &A, const spand_grid_t &g, const spand_opts_
   top_size = tops;
   mark(PH_END);
   SP_HIP(hipStreamSynchronize(stream));
+  trace("sync", -1);
   temp.release();
   next_temp.release();
   retired.release();

@@ -191,7 +191,7 @@ struct QrcpDesc {
 // Implemented in the .hip files.  Descriptor arrays are device pointers.
 // Every wrapper returns SPAND_OK or SPAND_EHIP (launch error).
 constexpr int ELIM_NB = 16;        // panel width of the elimination kernels
-constexpr int ELIM_BLK = 64;       // block width of the blocked Gauss-Jordan (4 panels)
+constexpr int ELIM_BLK = 64;       // block width of the blocked eliminations (4 panels)
 constexpr int ELIM_NT = 512;       // threads of a panel workgroup
 constexpr int ELIM_RPT = 4;        // rows held per thread -> n <= 2048
 constexpr int ELIM_MAXN = ELIM_NT * ELIM_RPT;
@@ -199,8 +199,10 @@ constexpr int QRCP_MAXM = 1024;    // largest interface handled by the QRCP kern
 
 // tmode = 2 * transA + transB, shared by every descriptor of the launch
 // (the FP64 kernel reads the flags per descriptor and ignores it)
+// uniform > 0: every descriptor of the launch has that many tiles (the item
+// of a tile is found by division instead of a search of tile_start)
 int launch_gemm(FType t, const GemmDesc *d_items, const int32_t *d_tile_start, int nitems,
-                int total_tiles, hipStream_t st, int tile_base, int tmode);
+                int total_tiles, hipStream_t st, int tile_base, int tmode, int uniform = 0);
 // src double -> dst factor type (src_is_factor = 0) or factor -> factor (1)
 int launch_copy(FType t, int src_is_factor, const CopyDesc *d_items, int n, int64_t max_elems,
                 hipStream_t st);

@@ -140,12 +140,16 @@ __device__ inline int xcd_tile(int b, int nb) {
 template <int TA, int TB>
 __global__ __launch_bounds__(256) void k_gemm_f32_mfma(const GemmDesc *__restrict__ items,
                                                        const int32_t *__restrict__ tile_start,
-                                                       int nitems, int tile_base) {
+                                                       int nitems, int tile_base, int uniform) {
   const int tile = tile_base + xcd_tile(int(blockIdx.x), int(gridDim.x));
   int lo = 0, hi = nitems;
-  while (hi - lo > 1) {
-    int mid = (lo + hi) >> 1;
-    if (tile_start[mid] <= tile) lo = mid; else hi = mid;
+  if (uniform > 0) {
+    lo = (tile - tile_base) / uniform;
+  } else {
+    while (hi - lo > 1) {
+      int mid = (lo + hi) >> 1;
+      if (tile_start[mid] <= tile) lo = mid; else hi = mid;
+    }
   }
   const GemmDesc d = items[lo];
   const int t = tile - tile_start[lo];
@@ -230,19 +234,20 @@ __global__ __launch_bounds__(256) void k_gemm_f32_mfma(const GemmDesc *__restric
 }
 
 int launch_gemm(FType t, const GemmDesc *d_items, const int32_t *d_tile_start, int nitems,
-                int total_tiles, hipStream_t st, int tile_base, int tmode) {
+                int total_tiles, hipStream_t st, int tile_base, int tmode, int uniform) {
   if (nitems <= 0 || total_tiles <= 0) return SPAND_OK;
   const dim3 g(total_tiles), b(256);
+  const int u = uniform;
   if (t == FType::F64)
     hipLaunchKernelGGL(k_gemm<double>, g, b, 0, st, d_items, d_tile_start, nitems, tile_base);
   else if (tmode == 0)
-    hipLaunchKernelGGL((k_gemm_f32_mfma<0, 0>), g, b, 0, st, d_items, d_tile_start, nitems, tile_base);
+    hipLaunchKernelGGL((k_gemm_f32_mfma<0, 0>), g, b, 0, st, d_items, d_tile_start, nitems, tile_base, u);
   else if (tmode == 1)
-    hipLaunchKernelGGL((k_gemm_f32_mfma<0, 1>), g, b, 0, st, d_items, d_tile_start, nitems, tile_base);
+    hipLaunchKernelGGL((k_gemm_f32_mfma<0, 1>), g, b, 0, st, d_items, d_tile_start, nitems, tile_base, u);
   else if (tmode == 2)
-    hipLaunchKernelGGL((k_gemm_f32_mfma<1, 0>), g, b, 0, st, d_items, d_tile_start, nitems, tile_base);
+    hipLaunchKernelGGL((k_gemm_f32_mfma<1, 0>), g, b, 0, st, d_items, d_tile_start, nitems, tile_base, u);
   else
-    hipLaunchKernelGGL((k_gemm_f32_mfma<1, 1>), g, b, 0, st, d_items, d_tile_start, nitems, tile_base);
+    hipLaunchKernelGGL((k_gemm_f32_mfma<1, 1>), g, b, 0, st, d_items, d_tile_start, nitems, tile_base, u);
   SP_HIP(hipGetLastError());
   return SPAND_OK;
 }

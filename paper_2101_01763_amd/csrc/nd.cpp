@@ -30,17 +30,16 @@ int default_levels(int64_t K) {
   return L < 1 ? 1 : L;
 }
 
-static void grid_neighbours(int nx, int ny, bool px, bool py, int e, int out[4], int &cnt) {
-  int i = e % nx, j = e / nx;
+static void grid_neighbours(int nx, int ny, bool px, bool py, int i, int j, int out[4], int &cnt) {
   static const int di[4] = {1, -1, 0, 0}, dj[4] = {0, 0, 1, -1};
   cnt = 0;
   for (int t = 0; t < 4; ++t) {
     int ii = i + di[t], jj = j + dj[t];
-    if (px) ii = ((ii % nx) + nx) % nx;
-    if (py) jj = ((jj % ny) + ny) % ny;
+    if (px) ii = ii < 0 ? ii + nx : (ii >= nx ? ii - nx : ii);
+    if (py) jj = jj < 0 ? jj + ny : (jj >= ny ? jj - ny : jj);
     if (ii < 0 || ii >= nx || jj < 0 || jj >= ny) continue;
     int f = jj * nx + ii;
-    if (f == e) continue;
+    if (ii == i && jj == j) continue;   // a one-wide periodic direction wraps onto itself
     bool dup = false;
     for (int q = 0; q < cnt; ++q) dup |= (out[q] == f);
     if (!dup) out[cnt++] = f;
@@ -104,7 +103,7 @@ NDResult nested_dissection(int nx, int ny, bool px, bool py, int L) {
     for (int v : w.V) {
       if (coord[v] < mid) continue;
       int nb[4], cnt;
-      grid_neighbours(nx, ny, px, py, v, nb, cnt);
+      grid_neighbours(nx, ny, px, py, ex[v], ey[v], nb, cnt);
       for (int q = 0; q < cnt; ++q) {
         int u = nb[q];
         if (inV[u] && coord[u] < mid) {
@@ -139,8 +138,11 @@ NDResult nested_dissection(int nx, int ny, bool px, bool py, int L) {
     work.push_back(std::move(wr));
   }
   R.node_of_elem = node_of;
+  // node ids are below 2^L <= 2K: dense tables instead of map lookups
+  std::vector<int> node_lv(size_t(1) << L, -1);
+  for (auto &kv : R.node_level) node_lv[size_t(kv.first)] = kv.second;
   std::vector<int> lvl(K);
-  for (int e = 0; e < K; ++e) lvl[e] = R.node_level[node_of[e]];
+  for (int e = 0; e < K; ++e) lvl[e] = node_lv[size_t(node_of[e])];
   R.levels.resize(L);
   R.children.resize(L);
   // clusters of level l: live elements grouped by (node, depth-(L-1-l) box),
@@ -152,21 +154,24 @@ NDResult nested_dissection(int nx, int ny, bool px, bool py, int L) {
   const bool packed = 2 * kbits + ebits <= 64;
   std::map<std::pair<int64_t, int64_t>, int> prev_index;
   std::vector<std::array<int64_t, 3>> kt;
+  std::vector<uint64_t> kw;
   for (int l = 0; l < L; ++l) {
     kt.clear();
     const auto &bl = box_at[L - 1 - l];
-    for (int e = 0; e < K; ++e)
-      if (lvl[e] >= l) kt.push_back({int64_t(node_of[e]), bl[e], int64_t(e)});
     if (packed) {
-      std::vector<uint64_t> kw(kt.size());
-      for (size_t q = 0; q < kt.size(); ++q)
-        kw[q] = (((uint64_t(kt[q][0]) << kbits) | uint64_t(kt[q][1])) << ebits) | uint64_t(kt[q][2]);
+      kw.clear();
+      for (int e = 0; e < K; ++e)
+        if (lvl[e] >= l)
+          kw.push_back((((uint64_t(node_of[e]) << kbits) | uint64_t(bl[e])) << ebits) | uint64_t(e));
       std::sort(kw.begin(), kw.end());
       const uint64_t emask = (uint64_t(1) << ebits) - 1, bmask = (uint64_t(1) << kbits) - 1;
+      kt.resize(kw.size());
       for (size_t q = 0; q < kw.size(); ++q)
         kt[q] = {int64_t(kw[q] >> (ebits + kbits)), int64_t((kw[q] >> ebits) & bmask),
                  int64_t(kw[q] & emask)};
     } else {
+      for (int e = 0; e < K; ++e)
+        if (lvl[e] >= l) kt.push_back({int64_t(node_of[e]), bl[e], int64_t(e)});
       std::sort(kt.begin(), kt.end());
     }
     std::vector<NDCluster> cl;
@@ -176,7 +181,7 @@ NDResult nested_dissection(int nx, int ny, bool px, bool py, int L) {
       c.node = int32_t(kt[q][0]);
       c.box = int32_t(kt[q][1]);
       while (q < kt.size() && kt[q][0] == c.node && kt[q][1] == c.box) c.elems.push_back(int32_t(kt[q++][2]));
-      c.interior = R.node_level[c.node] == l;
+      c.interior = node_lv[size_t(c.node)] == l;
       index[{int64_t(c.node), int64_t(c.box)}] = int(cl.size());
       cl.push_back(std::move(c));
     }
@@ -192,12 +197,22 @@ NDResult nested_dissection(int nx, int ny, bool px, bool py, int L) {
     R.levels[l] = std::move(cl);
     prev_index = std::move(index);
   }
-  std::vector<int> order(K);
-  for (int e = 0; e < K; ++e) order[e] = e;
-  std::sort(order.begin(), order.end(), [&](int a, int b) {
-    return std::make_tuple(lvl[a], node_of[a], a) < std::make_tuple(lvl[b], node_of[b], b);
-  });
-  R.perm.assign(order.begin(), order.end());
+  // elimination order: elements by (level of node, node, element); nodes
+  // sorted once, elements bucketed per node in ascending order
+  std::vector<std::pair<int, int64_t>> nodes;
+  nodes.reserve(R.node_level.size());
+  for (auto &kv : R.node_level) nodes.push_back({kv.second, kv.first});
+  std::sort(nodes.begin(), nodes.end());
+  std::vector<int> nidx(size_t(1) << L, -1);
+  for (size_t q = 0; q < nodes.size(); ++q) nidx[size_t(nodes[q].second)] = int(q);
+  std::vector<int> ncount(nodes.size() + 1, 0), enode(K);
+  for (int e = 0; e < K; ++e) {
+    enode[e] = nidx[size_t(node_of[e])];
+    ++ncount[enode[e] + 1];
+  }
+  for (size_t q = 0; q < nodes.size(); ++q) ncount[q + 1] += ncount[q];
+  R.perm.assign(K, 0);
+  for (int e = 0; e < K; ++e) R.perm[ncount[enode[e]]++] = e;
   return R;
 }
 
