@@ -58,34 +58,58 @@ __global__ __launch_bounds__(256) void k_gemv(const GemvDesc *__restrict__ items
   __syncthreads();
   const T *A = (const T *)d.A;
   if (!d.trans) {
+    // each wave works on four rows at once (independent sums keep four
+    // rows' loads in flight); rows past the band re-read the band's last
+    // row and are discarded
     const int cv = d.cols / VN * VN;     // vectorised part (lda is a multiple of 4)
-    for (int rr = wid; rr < ch.nrows; rr += 4) {
-      const int r = ch.row0 + rr;
-      const T *row = A + (int64_t)r * d.lda;
-      double acc = 0.0;
-      for (int c = lane * VN; c < cv; c += 64 * VN) {
-        const typename VW::V v = *reinterpret_cast<const typename VW::V *>(row + c);
-        T e[VN];
-        VW::get(v, e);
+    for (int rr0 = wid * 4; rr0 < ch.nrows; rr0 += 16) {
+      const T *row[4];
 #pragma unroll
-        for (int q = 0; q < VN; ++q) acc += double(e[q]) * xs[c + q];
+      for (int q = 0; q < 4; ++q)
+        row[q] = A + (int64_t)(ch.row0 + min(rr0 + q, ch.nrows - 1)) * d.lda;
+      double acc[4] = {0.0, 0.0, 0.0, 0.0};
+      for (int c = lane * VN; c < cv; c += 64 * VN) {
+        typename VW::V v[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[q] = *reinterpret_cast<const typename VW::V *>(row[q] + c);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          T e[VN];
+          VW::get(v[q], e);
+#pragma unroll
+          for (int u = 0; u < VN; ++u) acc[q] += double(e[u]) * xs[c + u];
+        }
       }
-      for (int c = cv + lane; c < d.cols; c += 64) acc += double(row[c]) * xs[c];
-      acc = wsum(acc);
-      if (lane == 0) {
-        const int o = d.oslot[r];
-        double v = alpha * acc;
-        if (beta != 0.0) v += beta * out[o];
-        out[o] = v;
-      }
+      for (int c = cv + lane; c < d.cols; c += 64)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[q] += double(row[q][c]) * xs[c];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[q] = wsum(acc[q]);
+      if (lane == 0)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          if (rr0 + q >= ch.nrows) break;
+          const int o = d.oslot[ch.row0 + rr0 + q];
+          double v = alpha * acc[q];
+          if (beta != 0.0) v += beta * out[o];
+          out[o] = v;
+        }
     }
   } else {
     const int r = ch.row0 + tid;
     if (tid < ch.nrows) {
-      double acc = 0.0;
-      for (int c = 0; c < d.cols; ++c) acc += double(A[(int64_t)c * d.lda + r]) * xs[c];
+      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+      const T *col = A + r;
+      int c = 0;
+      for (; c + 4 <= d.cols; c += 4) {
+        a0 += double(col[(int64_t)c * d.lda]) * xs[c];
+        a1 += double(col[(int64_t)(c + 1) * d.lda]) * xs[c + 1];
+        a2 += double(col[(int64_t)(c + 2) * d.lda]) * xs[c + 2];
+        a3 += double(col[(int64_t)(c + 3) * d.lda]) * xs[c + 3];
+      }
+      for (; c < d.cols; ++c) a0 += double(col[(int64_t)c * d.lda]) * xs[c];
       const int o = d.oslot[r];
-      double v = alpha * acc;
+      double v = alpha * ((a0 + a1) + (a2 + a3));
       if (beta != 0.0) v += beta * out[o];
       out[o] = v;
     }
