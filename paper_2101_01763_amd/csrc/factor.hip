@@ -215,18 +215,25 @@ int Factor::elim_batch(std::vector<ElimDesc> &items, int mode) {
   // once as one rank-ELIM_BLK product on the matrix cores.  In-place
   // Gauss-Jordan (modes 0, 2) leaves the block's multipliers in the block
   // columns themselves; LU (mode 1) accumulates them in PB.
+  // Matrices of up to elim_block_max_n rows take each block in one fused
+  // launch (one row per thread); larger ones go panel by panel.
   const bool lu = mode == 1;
+  const bool fused = items[0].n <= elim_block_max_n(ft);
   size_t nP = 0, nT = 0, nI = 0, nB = 0, nPB = 0;
   for (auto &d : items) {
-    nP += size_t(d.n) * ELIM_NB;
-    nT += size_t(ELIM_NB) * d.ld;
+    if (!fused) {
+      nP += size_t(d.n) * ELIM_NB;
+      nT += size_t(ELIM_NB) * d.ld;
+    }
     nI += size_t(d.n);
     nB += size_t(ELIM_BLK) * d.ld;
     if (lu) nPB += size_t(d.n) * ELIM_BLK;
   }
-  void *P, *T, *piv, *used, *TB = nullptr, *PB = nullptr;
-  SP_TRY(dalloc(&P, nP * fsize(ft), false));
-  SP_TRY(dalloc(&T, nT * fsize(ft), false));
+  void *P = nullptr, *T = nullptr, *piv, *used, *TB = nullptr, *PB = nullptr;
+  if (!fused) {
+    SP_TRY(dalloc(&P, nP * fsize(ft), false));
+    SP_TRY(dalloc(&T, nT * fsize(ft), false));
+  }
   SP_TRY(dalloc(&piv, nI * 4, false));
   SP_TRY(dalloc(&used, nI * 4, false));
   SP_TRY(dalloc(&TB, nB * fsize(ft), false));
@@ -234,14 +241,16 @@ int Factor::elim_batch(std::vector<ElimDesc> &items, int mode) {
   SP_HIP(hipMemsetAsync(used, 0, nI * 4, stream));
   size_t oP = 0, oT = 0, oI = 0, oB = 0, oPB = 0;
   for (auto &d : items) {
-    d.P = (char *)P + oP * fsize(ft);
-    d.T = (char *)T + oT * fsize(ft);
+    d.P = fused ? nullptr : (char *)P + oP * fsize(ft);
+    d.T = fused ? nullptr : (char *)T + oT * fsize(ft);
     d.piv = (int32_t *)piv + oI;
     d.used = (int32_t *)used + oI;
     d.TB = (char *)TB + oB * fsize(ft);
     d.PB = lu ? (char *)PB + oPB * fsize(ft) : nullptr;
-    oP += size_t(d.n) * ELIM_NB;
-    oT += size_t(ELIM_NB) * d.ld;
+    if (!fused) {
+      oP += size_t(d.n) * ELIM_NB;
+      oT += size_t(ELIM_NB) * d.ld;
+    }
     oI += size_t(d.n);
     oB += size_t(ELIM_BLK) * d.ld;
     if (lu) oPB += size_t(d.n) * ELIM_BLK;
@@ -291,12 +300,24 @@ int Factor::elim_batch(std::vector<ElimDesc> &items, int mode) {
   SP_TRY(upload(gd, &d_gd, false));
   SP_TRY(upload(ts, &d_ts, false));
   for (int b = 0, k0 = 0; k0 < nmax; ++b, k0 += ELIM_BLK) {
-    for (int k = k0; k < std::min(nmax, k0 + ELIM_BLK); k += ELIM_NB) {
-      const int nactive = nactive_at(k);
-      const int max_tiles = int(cdiv(nmax, 64) * cdiv(ELIM_BLK, 64));   // the block's columns
-      SP_TRY(launch_elim_step(ft, d_items, nactive, k, mode, max_tiles, d_flag, k0,
-                              k0 + ELIM_BLK, stream));
-      if (lu) SP_TRY(launch_elim_pb(ft, d_items, nactive, k, k0, stream));
+    if (fused) {
+      // one launch per 64-row size class (items are sorted by n, descending),
+      // so that no workgroup carries waves without rows
+      const int na = nactive_at(k0);
+      for (int a = 0; a < na;) {
+        int b = a + 1;
+        while (b < na && cdiv(items[b].n, 64) == cdiv(items[a].n, 64)) ++b;
+        SP_TRY(launch_elim_block(ft, d_items + a, b - a, k0, mode, items[a].n, d_flag, stream));
+        a = b;
+      }
+    } else {
+      for (int k = k0; k < std::min(nmax, k0 + ELIM_BLK); k += ELIM_NB) {
+        const int nactive = nactive_at(k);
+        const int max_tiles = int(cdiv(nmax, 64) * cdiv(ELIM_BLK, 64));   // the block's columns
+        SP_TRY(launch_elim_step(ft, d_items, nactive, k, mode, max_tiles, d_flag, k0,
+                                k0 + ELIM_BLK, stream));
+        if (lu) SP_TRY(launch_elim_pb(ft, d_items, nactive, k, k0, stream));
+      }
     }
     SP_TRY(launch_elim_extract(ft, d_items, nactive_at(k0), k0, lu ? 1 : 0, stream));
     const size_t g0 = bstart[b], g1 = bstart[b + 1];

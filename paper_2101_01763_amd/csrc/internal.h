@@ -216,6 +216,13 @@ int launch_elim_step(FType t, const ElimDesc *d_items, int nactive, int k, int m
                      int max_tiles, int *d_flag, int cw0, int cw1, hipStream_t st);
 int launch_elim_extract(FType t, const ElimDesc *d_items, int nactive, int k0, int lu, hipStream_t st);
 int launch_elim_pb(FType t, const ElimDesc *d_items, int nactive, int k, int k0, hipStream_t st);
+// Whole block [k0, k0 + ELIM_BLK) in one launch, one row per thread: needs
+// nmax <= elim_block_max_n(t).  Writes the block columns, piv, used, and for
+// LU (mode 1) the multipliers PB; the pivot rows' other columns are moved by
+// launch_elim_extract as for the panel path.
+int elim_block_max_n(FType t);
+int launch_elim_block(FType t, const ElimDesc *d_items, int nactive, int k0, int mode, int nmax,
+                      int *d_flag, hipStream_t st);
 // out[j, c] = src[piv[j], colperm ? pinv[c] : c + col_off]
 struct RowGatherDesc {
   const void *src;

@@ -634,6 +634,318 @@ int launch_elim_step(FType t, const ElimDesc *d_items, int nactive, int k, int m
   return SPAND_OK;
 }
 
+// Largest of v over the 64 lanes of a wave (every lane active), in every
+// lane: DPP max within each row of 16 (quad xor 1, quad xor 2, half-row
+// mirror, row mirror), then the four row results through readlane.
+__device__ inline uint32_t wave_max_u32(uint32_t v) {
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false));
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false));
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xF, 0xF, false));
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xF, 0xF, false));
+  const uint32_t a = __builtin_amdgcn_readlane((int)v, 0), b = __builtin_amdgcn_readlane((int)v, 16);
+  const uint32_t c = __builtin_amdgcn_readlane((int)v, 32), d = __builtin_amdgcn_readlane((int)v, 48);
+  return max(max(a, b), max(c, d));
+}
+
+// Pivot key of a value: the bit pattern of |x| orders like |x| (NaN counts
+// as zero, so it still names a valid row).
+__device__ inline uint64_t pivot_key(float x) {
+  const float a = fabsf(x);
+  return a == a ? uint64_t(__float_as_uint(a)) : 0;
+}
+__device__ inline uint64_t pivot_key(double x) {
+  const double a = fabs(x);
+  return a == a ? uint64_t(__double_as_longlong(a)) : 0;
+}
+
+// Lane of the largest key among the lanes with can set, lowest lane on
+// ties; -1 if no lane may pivot.  *kmax receives that key.
+template <typename T>
+__device__ inline int wave_argmax_key(uint64_t key, bool can, uint64_t *kmax) {
+  uint64_t b;
+  if (sizeof(T) == 4) {
+    const uint32_t m = wave_max_u32(can ? uint32_t(key) : 0u);
+    b = __ballot(can && uint32_t(key) == m);
+    *kmax = m;
+  } else {
+    const uint32_t hi = uint32_t(key >> 32), lo = uint32_t(key);
+    const uint32_t mh = wave_max_u32(can ? hi : 0u);
+    const bool c2 = can && hi == mh;
+    const uint32_t ml = wave_max_u32(c2 ? lo : 0u);
+    b = __ballot(c2 && lo == ml);
+    *kmax = (uint64_t(mh) << 32) | ml;
+  }
+  return b ? int(__builtin_ctzll(b)) : -1;
+}
+
+// ------------------------------------------------------------------ fused block elimination
+// One workgroup eliminates the block columns [k0, k0 + wb), wb <= ELIM_BLK,
+// of one matrix and applies them to the whole column window
+// [k0, k0 + ELIM_BLK) (columns past n exist for LU on [A | I]), one row per thread (blockDim.x >= n), the block part of the
+// row in registers.  The slots of a row are kept rotated: at the step of
+// block column c, slot i holds column (c + i) mod ELIM_BLK, so the column
+// being eliminated is always slot 0.  Every register index is then a
+// compile-time constant while the column loop stays rolled; one fused
+// multiply-add per slot both applies a step and rotates the row.
+// Per step: argmax of |slot 0| over the rows that may still pivot (a
+// butterfly per wave; each wave posts its candidate's whole row to LDS, and
+// after one barrier every thread takes the best of the waves' candidates;
+// ties go to the lowest row, as in the panel kernel).
+//   MODE 0/2: Gauss-Jordan; every row changes, the pivot row is scaled; on
+//             exit the block columns are the block's P_B.
+//   MODE 1:   LU; only rows not yet used as pivots change.  A changed row
+//             keeps its multipliers (the block's elimination matrix taken at
+//             the pivot rows) in the slots of the columns already
+//             eliminated, so PB (n x ELIM_BLK) is written out on exit with
+//             no second array: row r of PB is those slots, then 1 at the
+//             row's own pivot column for rows pivoted in this block.
+template <typename T, int MODE, int MAXT>
+__global__ __launch_bounds__(MAXT) void k_elim_block(const ElimDesc *__restrict__ items, int k0,
+                                                     int *__restrict__ flag) {
+  constexpr int BW = ELIM_BLK, NWMAX = MAXT / 64, V = 16 / sizeof(T);
+  static_assert(BW == 64, "slot rotation assumes 64 block columns");
+  const ElimDesc d = items[blockIdx.x];
+  const int n = d.n;
+  if (k0 >= n) return;
+  const int wb = min(BW, n - k0);          // columns eliminated
+  const int wc = min(BW, d.ncols - k0);    // columns of the window carried along
+  const int tid = threadIdx.x, wv = tid >> 6, nw = blockDim.x >> 6;
+  T *A = (T *)d.A;
+  const int64_t ld = d.ld;
+  __shared__ __align__(16) T cand[2][NWMAX][BW];
+  __shared__ uint64_t cval[2][NWMAX];
+  __shared__ int cidx[2][NWMAX];
+  __shared__ unsigned long long ckey[3];   // FP32: (|pivot| bits << 32) | ~row, max over waves
+  __shared__ int s_piv[BW];
+  const bool live = tid < n;
+  // 16-byte row chunks when every row start is aligned and the block is whole
+  const bool vec = wb == BW && (ld % V) == 0 && ((uintptr_t)A % 16) == 0;
+  T s[BW];
+  bool used = false;
+  int pc = -1;     // block column this row pivoted at; -2: pivot of an earlier block
+#pragma unroll
+  for (int i = 0; i < BW; ++i) s[i] = T(0);
+  if (live) {
+    const T *src = A + (int64_t)tid * ld + k0;
+    if (vec) {
+#pragma unroll
+      for (int i = 0; i < BW; i += V) {
+        T tmp[V];
+        *(uint4 *)tmp = *(const uint4 *)(src + i);
+#pragma unroll
+        for (int v = 0; v < V; ++v) s[i + v] = tmp[v];
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < BW; ++i)
+        if (i < wc) s[i] = src[i];
+    }
+    if (MODE != 2 && d.used[tid] != 0) {
+      used = true;
+      pc = -2;
+    }
+  }
+  constexpr bool KEYED = sizeof(T) == 4 && MODE != 2;
+  if (KEYED) {
+    if (tid < 3) ckey[tid] = 0;
+    __syncthreads();
+  }
+  // One step per block column.  The steps run in groups of 4: at the start
+  // of a group slot i holds block column (c0 + i) mod BW, step k of the
+  // group eliminates slot k (a compile-time index), and the slots rotate by
+  // 4 between groups.  Inside a group every slot stays in its register, so
+  // the candidate rows go to LDS and come back as aligned 16-byte vectors.
+  auto step = [&](const int c, const int k) {
+    if (c >= wb) return;
+    const int buf = c & 1;
+    int prow, ws = 0, bi = -1;
+    uint64_t kmax = 0;
+    if (MODE == 2) {
+      prow = k0 + c;
+      if (tid == prow) {
+#pragma unroll
+        for (int i = 0; i < BW; i += V) *(uint4 *)&cand[buf][0][i] = *(const uint4 *)&s[i];
+      }
+      __syncthreads();
+    } else {
+      const bool can = live && !used;
+      const int wl = wave_argmax_key<T>(pivot_key(s[k]), can, &kmax);
+      bi = wl < 0 ? -1 : (wv << 6) + wl;
+      if (tid == bi) {
+#pragma unroll
+        for (int i = 0; i < BW; i += V) *(uint4 *)&cand[buf][wv][i] = *(const uint4 *)&s[i];
+      }
+      // kmax and bi are uniform over the wave
+      if (KEYED && bi >= 0 && (tid & 63) == 0)
+        atomicMax(&ckey[c % 3], (unsigned long long)((kmax << 32) | uint32_t(~bi)));
+    }
+    if (KEYED) {
+      // the key of step c - 1 is no longer read by anyone: clear it for step c + 2
+      __syncthreads();
+      if (tid == 0) ckey[(c + 2) % 3] = 0;
+      const unsigned long long key = ckey[c % 3];
+      prow = key ? int(~uint32_t(key)) : -1;
+      ws = prow >> 6;
+      if (prow < 0 || prow >= n) {
+        if (tid == 0) atomicOr(flag, 1);   // reported as a failed factorization
+        prow = k0 + c;
+        ws = 0;
+      }
+    } else if (MODE != 2) {
+      if ((tid & 63) == 0) {
+        cval[buf][wv] = kmax;
+        cidx[buf][wv] = bi;
+      }
+      __syncthreads();
+      // best candidate over the waves; on equal keys the lower wave holds
+      // the lower row.  Some row may always pivot (n - k0 - c unused rows),
+      // the fallback only keeps a bad key from naming a row out of range.
+      uint64_t best = 0;
+      ws = -1;
+      for (int q = 0; q < nw; ++q) {
+        const uint64_t kq = cval[buf][q];
+        if (cidx[buf][q] >= 0 && (ws < 0 || kq > best)) { best = kq; ws = q; }
+      }
+      prow = ws < 0 ? -1 : cidx[buf][ws];
+      if (prow < 0 || prow >= n) {
+        if (tid == 0) atomicOr(flag, 1);   // reported as a failed factorization
+        prow = k0 + c;
+        ws = 0;
+      }
+    }
+    const uint4 *pr = (const uint4 *)&cand[buf][ws][0];
+    if (tid == 0) s_piv[c] = prow;
+    T pq[V];
+    *(uint4 *)pq = pr[k / V];
+    T p = pq[k % V];
+    if (p == T(0)) {
+      if (tid == 0) atomicOr(flag, 1);
+      p = T(1);
+    }
+    const T ip = T(1) / p;
+    const bool is_piv = tid == prow;
+    T h, z;
+    if (MODE == 1) {
+      const bool upd = live && !used && !is_piv;
+      h = upd ? -s[k] * ip : T(0);
+      z = upd ? h : s[k];
+      if (is_piv) {
+        used = true;
+        pc = c;
+      }
+    } else {
+      if (is_piv) {
+#pragma unroll
+        for (int i = 0; i < BW; ++i) s[i] *= ip;
+        h = T(0);
+        z = ip;
+        used = true;
+      } else {
+        h = -s[k] * ip;
+        z = h;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < BW; i += V) {
+      T pv[V];
+      *(uint4 *)pv = pr[i / V];
+#pragma unroll
+      for (int v = 0; v < V; ++v)
+        if (i + v != k) s[i + v] = fma(h, pv[v], s[i + v]);
+    }
+    s[k] = z;
+  };
+  const int nsteps = (wb + 3) & ~3;
+  for (int c = 0; c < nsteps; c += 4) {
+    step(c, 0);
+    step(c + 1, 1);
+    step(c + 2, 2);
+    step(c + 3, 3);
+    T t[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) t[i] = s[i];
+#pragma unroll
+    for (int i = 0; i < BW - 4; ++i) s[i] = s[i + 4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) s[BW - 4 + i] = t[i];
+  }
+  __syncthreads();
+  // slot i now holds block column (nsteps + i) mod BW
+  if (live) {
+    T *dst = A + (int64_t)tid * ld + k0;
+    if (MODE == 1) {
+      T *pb = (T *)d.PB + (int64_t)tid * BW;
+#pragma unroll
+      for (int i = 0; i < BW; ++i) {
+        const int col = (nsteps + i) & (BW - 1);
+        if (col >= wc) continue;
+        if (col >= wb) {            // window column past the last pivot column
+          dst[col] = s[i];
+          continue;
+        }
+        T a, y;
+        if (pc == -2) {
+          a = s[i];
+          y = T(0);
+        } else if (pc == -1) {
+          a = T(0);
+          y = s[i];
+        } else {
+          a = col >= pc ? s[i] : T(0);
+          y = col < pc ? s[i] : (col == pc ? T(1) : T(0));
+        }
+        dst[col] = a;
+        pb[col] = y;
+      }
+    } else if (vec) {
+#pragma unroll
+      for (int i = 0; i < BW; i += V) {
+        T tmp[V];
+#pragma unroll
+        for (int v = 0; v < V; ++v) tmp[v] = s[i + v];
+        *(uint4 *)(dst + i) = *(uint4 *)tmp;
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < BW; ++i) {
+        const int col = (nsteps + i) & (BW - 1);
+        if (col < wc) dst[col] = s[i];
+      }
+    }
+    if (MODE != 2) d.used[tid] = used ? 1 : 0;
+  }
+  if (tid < wb) d.piv[k0 + tid] = s_piv[tid];
+}
+
+int elim_block_max_n(FType t) { return t == FType::F64 ? 512 : 1024; }
+
+int launch_elim_block(FType t, const ElimDesc *d_items, int nactive, int k0, int mode, int nmax,
+                      int *d_flag, hipStream_t st) {
+  if (nactive <= 0) return SPAND_OK;
+  if (nmax > elim_block_max_n(t)) {
+    set_error("fused block elimination: n = %d exceeds %d", nmax, elim_block_max_n(t));
+    return SPAND_EINVAL;
+  }
+  const dim3 block(unsigned(cdiv(nmax, 64) * 64));
+  if (t == FType::F64) {
+    if (mode == 0)
+      hipLaunchKernelGGL((k_elim_block<double, 0, 512>), dim3(nactive), block, 0, st, d_items, k0, d_flag);
+    else if (mode == 1)
+      hipLaunchKernelGGL((k_elim_block<double, 1, 512>), dim3(nactive), block, 0, st, d_items, k0, d_flag);
+    else
+      hipLaunchKernelGGL((k_elim_block<double, 2, 512>), dim3(nactive), block, 0, st, d_items, k0, d_flag);
+  } else {
+    if (mode == 0)
+      hipLaunchKernelGGL((k_elim_block<float, 0, 1024>), dim3(nactive), block, 0, st, d_items, k0, d_flag);
+    else if (mode == 1)
+      hipLaunchKernelGGL((k_elim_block<float, 1, 1024>), dim3(nactive), block, 0, st, d_items, k0, d_flag);
+    else
+      hipLaunchKernelGGL((k_elim_block<float, 2, 1024>), dim3(nactive), block, 0, st, d_items, k0, d_flag);
+  }
+  SP_HIP(hipGetLastError());
+  return SPAND_OK;
+}
+
 // Blocked elimination: after the panels of the block [k0, k0 + wb) have been
 // applied to the block's own columns, the pivot rows of the columns the block
 // has not touched yet move to TB (wb x ld) and are zeroed in A, so that
