@@ -1214,6 +1214,17 @@ int Factor::sparsify(int l, const NDResult &nd, LevelState &S, LevelState &Nx) {
       SP_TRY(dalloc(&wbase2, pw.total, false));     // compaction target of the kernel
       SP_HIP(hipMemsetAsync(wbase, 0, pw.total, stream));
     }
+    int mq = 1, mg = 1;
+    for (int s : ifs) {
+      mq = std::max(mq, S.size[s]);
+      // column groups of 16 bytes: 2 columns (FP64) or 4 (FP32)
+      mg = std::max(mg, ld4(std::max(ncols[s], 1)) / (ft == FType::F64 ? 2 : 4));
+    }
+    const int bq = qrcp_block_width(mq, mg);
+    if (bq == 0) {
+      set_error("RRQR problem too large for one workgroup (m=%d, %d column groups)", mq, mg);
+      return SPAND_EINVAL;
+    }
     std::vector<CopyDesc> wc;
     for (size_t q = 0; q < ifs.size(); ++q) {
       const int s = ifs[q];
@@ -1223,7 +1234,8 @@ int Factor::sparsify(int l, const NDResult &nd, LevelState &S, LevelState &Nx) {
       Wm[s] = (char *)wbase + wo[s];
       SP_TRY(dalloc(&Qm[s], size_t(m) * m * tsz, false));
       SP_TRY(dalloc(&Vm[s], size_t(m) * m * tsz, false));
-      void *tau, *vn1, *vn2, *sel;
+      void *tau, *vn1, *vn2, *sel, *hq;
+      SP_TRY(dalloc(&hq, size_t(ldw) * bq * 8, false));
       SP_TRY(dalloc(&tau, size_t(m) * 8, false));
       SP_TRY(dalloc(&vn1, size_t(ldw) * 8, false));
       SP_TRY(dalloc(&vn2, size_t(ldw) * 8, false));
@@ -1265,6 +1277,7 @@ int Factor::sparsify(int l, const NDResult &nd, LevelState &S, LevelState &Nx) {
       Qd.vn1 = (double *)vn1;
       Qd.vn2 = (double *)vn2;
       Qd.sel = (int32_t *)sel;
+      Qd.H = (double *)hq;
       Qd.k_out = (int32_t *)kout + q;
       Qd.m = m;
       Qd.ncols = nc;
@@ -1273,16 +1286,6 @@ int Factor::sparsify(int l, const NDResult &nd, LevelState &S, LevelState &Nx) {
       flops += 4.0 * double(m) * nc * std::min(m, nc);
     }
     SP_TRY(copy_batch(wc, 1));
-    int mq = 1, mg = 1;
-    for (auto &Qd : qd) {
-      mq = std::max(mq, Qd.m);
-      mg = std::max(mg, Qd.ldw / 2);     // column groups of 2 (FP64) or 4 (FP32)
-    }
-    const size_t lds = qrcp_lds_bytes(mq, mg);
-    if (lds > 64 * 1024) {
-      set_error("RRQR problem too large for one workgroup (m=%d, %d column groups)", mq, mg);
-      return SPAND_EINVAL;
-    }
     QrcpDesc *d_q;
     SP_TRY(upload(qd, &d_q, false));
     hipEvent_t qe0 = nullptr, qe1 = nullptr;
@@ -1291,7 +1294,7 @@ int Factor::sparsify(int l, const NDResult &nd, LevelState &S, LevelState &Nx) {
       (void)hipEventCreate(&qe1);
       (void)hipEventRecord(qe0, stream);
     }
-    SP_TRY(launch_qrcp(ft, d_q, int(qd.size()), eps, eps == 0.0 ? 1 : 0, mq, mg, stream));
+    SP_TRY(launch_qrcp(ft, d_q, int(qd.size()), eps, eps == 0.0 ? 1 : 0, mq, mg, bq, stream));
     trace("qrcp plan+launch", l);
     if (timing) {
       (void)hipEventRecord(qe1, stream);

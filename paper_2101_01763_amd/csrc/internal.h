@@ -181,6 +181,7 @@ struct QrcpDesc {
   double *vn1;         // [ldw]
   double *vn2;         // [ldw]
   int32_t *sel;        // [ldw] selected (or padding) flags
+  double *H;           // [ldw x block width] candidate-basis coordinates of the columns
   int32_t *k_out;      // rank
   int32_t m, ncols;
   int32_t ldw;         // leading dimension of W (multiple of 4, padding zero)
@@ -233,9 +234,14 @@ struct RowGatherDesc {
 int launch_row_gather(FType t, const RowGatherDesc *d_items, int n, int max_rows, hipStream_t st);
 int launch_schur_elem(FType t, int bs, const double *bsr_val, const SchurGroup *d_groups,
                       int ngroups, const SchurItem *d_items, hipStream_t st);
-size_t qrcp_lds_bytes(int maxm, int maxgrp);   // dynamic LDS of one QRCP workgroup
+// dynamic LDS of one QRCP workgroup with candidate blocks of width bq
+size_t qrcp_lds_bytes(int maxm, int maxgrp, int bq);
+constexpr size_t QRCP_MAX_LDS = 64 * 1024;
+// widest candidate block (8, 4 or 2) whose LDS fits, 0 if none does
+int qrcp_block_width(int maxm, int maxgrp);
+// every item's H holds ldw x bq doubles
 int launch_qrcp(FType t, const QrcpDesc *d_items, int n, double eps, int force_full, int maxm,
-                int maxgrp, hipStream_t st);
+                int maxgrp, int bq, hipStream_t st);
 // dst rows/cols scaling: dst[r, c] *= rs[r] * cs[c] (either may be null)
 struct ScaleDesc {
   void *A;

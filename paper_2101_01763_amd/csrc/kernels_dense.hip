@@ -1212,6 +1212,15 @@ __device__ inline void wg_gemm(int M, int N, int K, FA A, FB B, FE epi, double *
 //     later pass.  Stops at the first |R_ii| <= eps |R_00| (or at the
 //     numerical rank, |R_ii| <= 1e-12 |R_00|, whatever eps).  The kept
 //     vectors are rows of V (q_t = V[t m .. t m + m)).
+//     The steps run in blocks.  A block takes the BQ unselected columns of
+//     largest norm as candidates, orthonormalises their residuals into a
+//     basis B (BQ x m) and reads W once to form H = B W (BQ values per
+//     column, FP64).  While the pivot chosen over all columns is a
+//     candidate, its residual and hence q_k lie in span(B), q_k = c^T B,
+//     and row k of R is c^T H: the norms of all columns are downdated
+//     from H alone.  A pivot outside the candidates ends the block.  The
+//     pivots are exactly those of the unblocked method; W is read once per
+//     block instead of once per step.
 //  3. Completion to an orthogonal Q by Householder reconstruction (Ballard
 //     et al., "Reconstructing Householder vectors from tall-skinny QR",
 //     IPDPS 2014): with Q_c = [q_0 .. q_{k-1}] = [Q1; Q2] (Q1 k x k) and
@@ -1219,9 +1228,10 @@ __device__ inline void wg_gemm(int M, int N, int K, FA A, FB B, FE epi, double *
 //     H = I + (Q_c S - E) [I, G2^T] with G2 = Q2 (Q1 - S)^-1, E = [I_k; 0],
 //     is orthogonal and H E = Q_c S.  Output Q = [Q_c | H(:, k:m)].
 //     Rows k.. of V receive G2 S; tau receives S.
-template <typename T>
-__global__ __launch_bounds__(256, 4) void k_qrcp(const QrcpDesc *__restrict__ items, double eps,
+template <typename T, int BQ>
+__global__ __launch_bounds__(256, 3) void k_qrcp(const QrcpDesc *__restrict__ items, double eps,
                                               int force_full, int MS, int GS) {
+  static_assert(BQ % 2 == 0, "H is read in pairs");
   const QrcpDesc d = items[blockIdx.x];
   const int m = d.m, nc = d.ncols;
   const int64_t ldw = d.ldw;
@@ -1235,13 +1245,21 @@ __global__ __launch_bounds__(256, 4) void k_qrcp(const QrcpDesc *__restrict__ it
   double *vn1 = d.vn1, *vn2 = d.vn2;
   int *sel = d.sel;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-  // dynamic LDS: u[MS], cbuf[MS] (or the two GEMM tiles), then two lists of
-  // active column groups (GS entries each)
+  // dynamic LDS: u[MS], cbuf[MS] (or the two GEMM tiles, or the
+  // candidates' coefficients P[MS][BQ]), the candidate
+  // basis Bm[BQ][MS], the block's coordinates Cc[BQ][BQ] and av[BQ], then
+  // two lists of active column groups (GS entries each) and the candidates
   extern __shared__ double qsm[];
-  const int ldsd = max(2 * MS, 2048);
+  const int ldsd = max(max(2 * MS, 2048), BQ * MS);
   double *u = qsm, *cbuf = qsm + MS;
-  int *act = reinterpret_cast<int *>(qsm + ldsd), *act2 = act + GS;
-  __shared__ int s_j, s_nflag, s_nf;
+  double *Bm = qsm + ldsd, *Cc = Bm + BQ * MS, *av = Cc + BQ * BQ;
+  int *act = reinterpret_cast<int *>(av + BQ), *act2 = act + GS;
+  int *sidx = act2 + GS;
+  double *H = d.H;                  // ldw x BQ: column j of B W at H + j BQ
+  __shared__ int s_j, s_nflag, s_nf, s_in;
+  __shared__ double rv[4];
+  __shared__ int ri[4];
+  __shared__ double cnw[BQ];
   __shared__ int wtot[4];
   __shared__ int s_fl[64];
   __shared__ double red[16];
@@ -1366,14 +1384,15 @@ __global__ __launch_bounds__(256, 4) void k_qrcp(const QrcpDesc *__restrict__ it
   int nact_cur = filter(nullptr, ngrp, act);   // same value on every thread
   int cur_ngrp = ngrp;                         // groups of the current layout
 
-  // ---- 2. pivoted Gram-Schmidt
+  // ---- 2. pivoted Gram-Schmidt, in blocks of candidate columns
   double R00 = 0.0;
   int k = 0;
   const int imax = min(m, nc);
-  for (int i = 0; i < imax; ++i) {
-    // pivot: largest remaining column norm, ties -> smallest index (the
-    // packed layouts keep the original column order)
-    const int nact = nact_cur;
+  const double stop_rel = fmax(force_full ? 0.0 : eps, 1e-12);
+  // largest vn1 over the unselected columns of the live groups, ties ->
+  // smallest index (the packed layouts keep the column order)
+  int ncand_in = 0;               // candidates the pivot search checks against
+  auto argmax_col = [&](int nact) {
     double bv = -1.0;
     int bi = INT_MAX;
     for (int qa = tid; qa < nact; qa += 256) {
@@ -1392,8 +1411,6 @@ __global__ __launch_bounds__(256, 4) void k_qrcp(const QrcpDesc *__restrict__ it
       const int oi = __shfl_xor(bi, o, 64);
       if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
     }
-    __shared__ double rv[4];
-    __shared__ int ri[4];
     if (lane == 0) { rv[wid] = bv; ri[wid] = bi; }
     __syncthreads();
     if (tid == 0) {
@@ -1402,148 +1419,47 @@ __global__ __launch_bounds__(256, 4) void k_qrcp(const QrcpDesc *__restrict__ it
       for (int q = 1; q < 4; ++q)
         if (rv[q] > v || (rv[q] == v && ri[q] < ii)) { v = rv[q]; ii = ri[q]; }
       s_j = ii;
+      int f = 0;                  // is it one of the block's candidates?
+      for (int cq = 0; cq < ncand_in; ++cq) f |= sidx[cq] == ii;
+      s_in = f;
     }
     __syncthreads();
-    const int js = s_j;
-    if (js == INT_MAX) break;
-    for (int r = tid; r < m; r += 256) u[r] = double(W[(int64_t)r * ldw + js]);
-    __syncthreads();
-    // two classical Gram-Schmidt passes against q_0..q_{i-1}
-    for (int pass = 0; pass < 2 && i > 0; ++pass) {
-      qdots(u, i, cbuf);
-      qsub(u, i, cbuf);
+    return s_j;
+  };
+  // c[l] = b_l . x and x -= sum_l c[l] b_l for the basis rows of Bm
+  auto bdots = [&](const double *x, int n, double *c) {
+    for (int l = wid; l < n; l += 4) {
+      double a = 0.0;
+      for (int r = lane; r < m; r += 64) a += Bm[l * MS + r] * x[r];
+      a = wave_sum(a);
+      if (lane == 0) c[l] = a;
     }
-    double ss = 0.0;
-    for (int r = tid; r < m; r += 256) ss += u[r] * u[r];
-    const double nrm = sqrt(block_sum(ss, red));
-    if (i == 0) R00 = nrm;
-    // below 1e-12 |R_00| the residual is rounding noise and Gram-Schmidt
-    // could no longer make it orthogonal: the completion supplies the rest
-    const bool stop = nrm == 0.0 || nrm <= fmax(force_full ? 0.0 : eps, 1e-12) * R00;
-    if (stop) break;
-    const double inv = 1.0 / nrm;
     __syncthreads();
+  };
+  auto bsub = [&](double *x, int n, const double *c) {
     for (int r = tid; r < m; r += 256) {
-      u[r] *= inv;
-      Qt[(int64_t)i * m + r] = T(u[r]);
-    }
-    if (tid == 0) {
-      sel[js] = 1;
-      s_nflag = 0;
+      double sv = 0.0;
+      for (int l = 0; l < n; ++l) sv += Bm[l * MS + r] * c[l];
+      x[r] -= sv;
     }
     __syncthreads();
-    // row i of R for the active columns and downdate of their norms.  With
-    // few active groups, RS adjacent lanes split the rows of one group (in
-    // blocks of 4) and combine their sums by shuffles.
-    {
-      int RS = 1;
-      while (RS < 8 && nact * RS * 2 <= 256) RS *= 2;
-      const int sl = tid % RS, ga = tid / RS, gpp = 256 / RS;
-      const int m4 = m & ~3;
-      for (int qa0 = 0; qa0 < nact; qa0 += gpp) {
-        const int qa = qa0 + ga;
-        const bool live = qa < nact;
-        const int g = live ? act[qa] : 0;
-        double acc[VN];
-#pragma unroll
-        for (int q = 0; q < VN; ++q) acc[q] = 0.0;
-        if (live) {
-          const T *base = W + (int64_t)g * VN;
-#pragma unroll 4
-          for (int r = sl * 4; r < m4; r += 4 * RS) {
-            VT v[4];
-#pragma unroll
-            for (int u4 = 0; u4 < 4; ++u4) v[u4] = *reinterpret_cast<const VT *>(base + (int64_t)(r + u4) * ldw);
-#pragma unroll
-            for (int u4 = 0; u4 < 4; ++u4) {
-              const T *e = reinterpret_cast<const T *>(&v[u4]);
-              const double ur = u[r + u4];
-#pragma unroll
-              for (int q = 0; q < VN; ++q) acc[q] += ur * double(e[q]);
-            }
-          }
-          if (sl == 0)
-            for (int r = m4; r < m; ++r) {
-              const VT v = *reinterpret_cast<const VT *>(base + (int64_t)r * ldw);
-              const T *e = reinterpret_cast<const T *>(&v);
-#pragma unroll
-              for (int q = 0; q < VN; ++q) acc[q] += u[r] * double(e[q]);
-            }
-        }
-        for (int o = 1; o < RS; o <<= 1)
-#pragma unroll
-          for (int q = 0; q < VN; ++q) acc[q] += __shfl_xor(acc[q], o, 64);
-        if (live && sl == 0) {
-#pragma unroll
-          for (int q = 0; q < VN; ++q) {
-            const int j = g * VN + q;
-            if (sel[j]) continue;
-            const double a = vn1[j];
-            if (a != 0.0) {
-              double temp = fabs(acc[q]) / a;
-              temp = fmax(0.0, (1.0 + temp) * (1.0 - temp));
-              const double t2 = temp * (a / vn2[j]) * (a / vn2[j]);
-              if (t2 <= tol3z) {
-                vn1[j] = -1.0;          // recomputed below
-                atomicAdd(&s_nflag, 1);
-              } else {
-                vn1[j] = a * sqrt(temp);
-              }
-            }
-          }
-        }
-      }
-    }
-    __syncthreads();
-    if (s_nflag > 0) {
-      // exact residual norms of the flagged columns against q_0..q_i
-      for (;;) {
-        if (tid == 0) s_nf = 0;
-        __syncthreads();
-        for (int qa = tid; qa < nact; qa += 256) {
-          const int g = act[qa];
-#pragma unroll
-          for (int q = 0; q < VN; ++q) {
-            const int j = g * VN + q;
-            if (!sel[j] && vn1[j] < 0.0) {
-              const int p = atomicAdd(&s_nf, 1);
-              if (p < 64) s_fl[p] = j;
-            }
-          }
-        }
-        __syncthreads();
-        const int nf = min(s_nf, 64);
-        if (nf == 0) break;
-        for (int f = 0; f < nf; ++f) {
-          const int j = s_fl[f];
-          for (int r = tid; r < m; r += 256) u[r] = double(W[(int64_t)r * ldw + j]);
-          __syncthreads();
-          qdots(u, i + 1, cbuf);
-          qsub(u, i + 1, cbuf);
-          double s2 = 0.0;
-          for (int r = tid; r < m; r += 256) s2 += u[r] * u[r];
-          s2 = block_sum(s2, red);
-          if (tid == 0) {
-            vn1[j] = sqrt(s2);
-            vn2[j] = vn1[j];
-          }
-          __syncthreads();
-        }
-      }
-    }
-    k = i + 1;
-    // keep the groups that can still hold a pivot
-    nact_cur = filter(act, nact, act2);
-    {
+  };
+  bool done = false;
+  while (!done && k < imax) {
+    // keep the groups that can still hold a pivot (pruning never changes a
+    // pivot: the largest norm is above the threshold whenever any is)
+    if (k > 0) {
+      nact_cur = filter(act, nact_cur, act2);
       int *t = act;
       act = act2;
       act2 = t;
+      __syncthreads();
     }
     // Once at most half of the groups of the layout are live, pack the live
     // groups to the left of the other buffer (rows keep their stride), so
     // that every later pass reads whole contiguous rows.  The norms and
     // flags move with their columns; the order of columns is kept.
-    if (2 * nact_cur <= cur_ngrp && i + 1 < imax) {
+    if (2 * nact_cur <= cur_ngrp) {
       const int na = nact_cur;
       T *dst = Wother;
       for (int r = wid; r < m; r += 4)
@@ -1574,8 +1490,301 @@ __global__ __launch_bounds__(256, 4) void k_qrcp(const QrcpDesc *__restrict__ it
       Wother = const_cast<T *>(W);
       W = dst;
       cur_ngrp = na;
+      __syncthreads();
+    }
+    // (a) candidates: the BQ unselected columns of largest norm
+    ncand_in = 0;
+    int ncand = 0;
+    for (int cq = 0; cq < BQ; ++cq) {
+      const int j = argmax_col(nact_cur);
+      if (j == INT_MAX) break;
+      if (tid == 0) {
+        sidx[cq] = j;
+        sel[j] = 2;          // excluded from the next search only
+      }
+      __syncthreads();
+      ++ncand;
+    }
+    if (ncand == 0) break;
+    if (tid < ncand) sel[sidx[tid]] = 0;
+    __syncthreads();
+    // (b) their residuals against q_0..q_{k-1} (two block Gram-Schmidt
+    // passes over the candidates at once; the k x BQ coefficients go
+    // through H, which is free until the pass below), orthonormalised in
+    // turn into the rows of Bm.  The first candidate (the next pivot)
+    // always enters, like the pivot of the unblocked method.  Another
+    // enters only while its row stays well conditioned: a residual above
+    // 1e-4 of its column's norm (two passes leave it orthogonal to the q's
+    // to ~1e-12) and above 1e-2 of it left after the earlier rows.  The
+    // candidates that do not enter are dropped from the block (compacted
+    // out of sidx): if one of them becomes the pivot, the block ends and
+    // the next one starts with it.
+    for (int e = tid; e < ncand * m; e += 256) {
+      const int cq = e / m, r = e - cq * m;
+      Bm[cq * MS + r] = double(W[(int64_t)r * ldw + sidx[cq]]);
+    }
+    for (int e = ncand * MS + tid; e < BQ * MS; e += 256) Bm[e] = 0.0;
+    __syncthreads();
+    for (int cq = wid; cq < ncand; cq += 4) {
+      double a2 = 0.0;
+      for (int r = lane; r < m; r += 64) a2 += Bm[cq * MS + r] * Bm[cq * MS + r];
+      a2 = wave_sum(a2);
+      if (lane == 0) cnw[cq] = sqrt(a2);
+    }
+    // P = Q_k^T U (k x BQ, in the u/cbuf area): lane (tl, rq) of a wave
+    // takes row t = 16 tile + tl of Qt and the rows r = rq (mod 4); the four
+    // partial sums meet by shuffles.  Then U -= Q_k P, one thread per row.
+    double *P = qsm;
+    for (int pass = 0; pass < 2 && k > 0; ++pass) {
+      {
+        const int tl = lane & 15, rq = lane >> 4;
+        for (int t0 = wid * 16; t0 < k; t0 += 64) {
+          const int t = t0 + tl;
+          double a[BQ];
+#pragma unroll
+          for (int cq = 0; cq < BQ; ++cq) a[cq] = 0.0;
+          if (t < k) {
+            const T *qt = Qt + (int64_t)t * m;
+#pragma unroll 4
+            for (int r = rq; r < m; r += 4) {
+              const double qv = double(qt[r]);
+#pragma unroll
+              for (int cq = 0; cq < BQ; ++cq) a[cq] += qv * Bm[cq * MS + r];
+            }
+          }
+#pragma unroll
+          for (int cq = 0; cq < BQ; ++cq) {
+            a[cq] += __shfl_xor(a[cq], 16, 64);
+            a[cq] += __shfl_xor(a[cq], 32, 64);
+          }
+          if (rq == 0 && t < k)
+#pragma unroll
+            for (int cq = 0; cq < BQ; ++cq) P[t * BQ + cq] = a[cq];
+        }
+      }
+      __syncthreads();
+      for (int r = tid; r < m; r += 256) {
+        double sv[BQ];
+#pragma unroll
+        for (int cq = 0; cq < BQ; ++cq) sv[cq] = 0.0;
+#pragma unroll 4
+        for (int t = 0; t < k; ++t) {
+          const double qv = double(Qt[(int64_t)t * m + r]);
+#pragma unroll
+          for (int cq = 0; cq < BQ; ++cq) sv[cq] += P[t * BQ + cq] * qv;
+        }
+#pragma unroll
+        for (int cq = 0; cq < BQ; ++cq) Bm[cq * MS + r] -= sv[cq];
+      }
+      __syncthreads();
+    }
+    int nb = 0;
+    for (int cq = 0; cq < ncand; ++cq) {
+      double *x = Bm + cq * MS;
+      double s0 = 0.0;
+      for (int r = tid; r < m; r += 256) s0 += x[r] * x[r];
+      const double n0 = sqrt(block_sum(s0, red));
+      for (int pass = 0; pass < 2 && nb > 0; ++pass) {
+        bdots(x, nb, cbuf);
+        bsub(x, nb, cbuf);
+      }
+      double s1 = 0.0;
+      for (int r = tid; r < m; r += 256) s1 += x[r] * x[r];
+      const double n1 = sqrt(block_sum(s1, red));
+      if (n1 > 0.0 && (cq == 0 || (n1 > 1e-2 * n0 && n0 > 1e-4 * cnw[cq]))) {
+        const double inv = 1.0 / n1;
+        // row cq moves to row nb <= cq (each thread moves its own entries)
+        for (int r = tid; r < m; r += 256) Bm[nb * MS + r] = x[r] * inv;
+        if (tid == 0) sidx[nb] = sidx[cq];
+        ++nb;
+      }
+      __syncthreads();
+    }
+    ncand = nb;
+    ncand_in = nb;
+    // the next pivot itself has no residual left: the unblocked method stops there
+    if (nb == 0) break;
+    for (int e = nb * MS + tid; e < BQ * MS; e += 256) Bm[e] = 0.0;
+    __syncthreads();
+    // (c) H = Bm W for the live columns: one pass over W.  With few active
+    // groups, RS adjacent lanes split the rows of one group (in blocks of 4)
+    // and combine their sums by shuffles.
+    {
+      int RS = 1;
+      while (RS < 8 && nact_cur * RS * 2 <= 256) RS *= 2;
+      const int sl = tid % RS, ga = tid / RS, gpp = 256 / RS;
+      const int m4 = m & ~3;
+      for (int qa0 = 0; qa0 < nact_cur; qa0 += gpp) {
+        const int qa = qa0 + ga;
+        const bool live = qa < nact_cur;
+        const int g = live ? act[qa] : 0;
+        double acc[VN][BQ];
+#pragma unroll
+        for (int q = 0; q < VN; ++q)
+#pragma unroll
+          for (int l = 0; l < BQ; ++l) acc[q][l] = 0.0;
+        if (live) {
+          const T *base = W + (int64_t)g * VN;
+          for (int r = sl * 4; r < m4; r += 4 * RS) {
+            VT v[4];
+#pragma unroll
+            for (int u4 = 0; u4 < 4; ++u4) v[u4] = *reinterpret_cast<const VT *>(base + (int64_t)(r + u4) * ldw);
+#pragma unroll
+            for (int u4 = 0; u4 < 4; ++u4) {
+              const T *e = reinterpret_cast<const T *>(&v[u4]);
+#pragma unroll
+              for (int l = 0; l < BQ; ++l) {
+                const double bl = Bm[l * MS + r + u4];
+#pragma unroll
+                for (int q = 0; q < VN; ++q) acc[q][l] += bl * double(e[q]);
+              }
+            }
+          }
+          if (sl == 0)
+            for (int r = m4; r < m; ++r) {
+              const VT v = *reinterpret_cast<const VT *>(base + (int64_t)r * ldw);
+              const T *e = reinterpret_cast<const T *>(&v);
+#pragma unroll
+              for (int l = 0; l < BQ; ++l) {
+                const double bl = Bm[l * MS + r];
+#pragma unroll
+                for (int q = 0; q < VN; ++q) acc[q][l] += bl * double(e[q]);
+              }
+            }
+        }
+        for (int o = 1; o < RS; o <<= 1)
+#pragma unroll
+          for (int q = 0; q < VN; ++q)
+#pragma unroll
+            for (int l = 0; l < BQ; ++l) acc[q][l] += __shfl_xor(acc[q][l], o, 64);
+        if (live && sl == 0) {
+          double *hg = H + (int64_t)g * VN * BQ;
+#pragma unroll
+          for (int q = 0; q < VN; ++q)
+#pragma unroll
+            for (int l = 0; l < BQ; l += 2)
+              *reinterpret_cast<double2 *>(hg + q * BQ + l) = make_double2(acc[q][l], acc[q][l + 1]);
+        }
+      }
     }
     __syncthreads();
+    // (d) steps: while the next pivot is a candidate, its residual lies in
+    // the span of Bm and so does q_k; row k of R is then c . H for every
+    // column, which downdates all norms without reading W
+    int nst = 0;
+    for (;;) {
+      if (k >= imax) { done = true; break; }
+      const int js = argmax_col(nact_cur);
+      if (js == INT_MAX) { done = true; break; }
+      if (!s_in) break;                 // next block, with new candidates
+      // coordinates of the pivot's residual against q_0..q_{k-1}, then
+      // against the block's earlier q's (two passes): lane (t, l) of wave 0
+      // holds c_t[l] and coordinate l; the dots reduce over l, the
+      // corrections over t.  Its norm is |R_kk|.
+      double *ck = Cc + nst * BQ;
+      if (wid == 0) {
+        const int t = lane / BQ, l = lane % BQ;
+        double v = H[(int64_t)js * BQ + l];
+        for (int pass = 0; pass < 2 && nst > 0; ++pass) {
+          const double ct = t < nst ? Cc[t * BQ + l] : 0.0;
+          double dt = ct * v;
+#pragma unroll
+          for (int o = 1; o < BQ; o <<= 1) dt += __shfl_xor(dt, o, 64);
+          double w = dt * ct;
+#pragma unroll
+          for (int o = BQ; o < 64; o <<= 1) w += __shfl_xor(w, o, 64);
+          v -= w;
+        }
+        const double nrm = sqrt(wave_sum(lane < BQ ? v * v : 0.0));
+        if (lane < BQ) ck[lane] = nrm > 0.0 ? v / nrm : 0.0;
+        if (lane == 0) s_piv = nrm;
+      }
+      __syncthreads();
+      const double nrm = s_piv;
+      if (k == 0) R00 = nrm;
+      // below 1e-12 |R_00| the residual is rounding noise and Gram-Schmidt
+      // could no longer make it orthogonal: the completion supplies the rest
+      if (nrm == 0.0 || nrm <= stop_rel * R00) { done = true; break; }
+      for (int r = tid; r < m; r += 256) {
+        double sv = 0.0;
+#pragma unroll
+        for (int l = 0; l < BQ; ++l) sv += Bm[l * MS + r] * ck[l];
+        Qt[(int64_t)k * m + r] = T(sv);
+      }
+      if (tid == 0) {
+        sel[js] = 1;
+        s_nflag = 0;
+      }
+      __syncthreads();
+      // row k of R and downdate of the norms (LAPACK's safeguard: a norm
+      // that lost too much to cancellation is recomputed below)
+      for (int qa = tid; qa < nact_cur; qa += 256) {
+        const int g = act[qa];
+        const double *hg = H + (int64_t)g * VN * BQ;
+#pragma unroll
+        for (int q = 0; q < VN; ++q) {
+          const int j = g * VN + q;
+          if (sel[j]) continue;
+          double rk = 0.0;
+#pragma unroll
+          for (int l = 0; l < BQ; l += 2) {
+            const double2 h2 = *reinterpret_cast<const double2 *>(hg + q * BQ + l);
+            rk += ck[l] * h2.x + ck[l + 1] * h2.y;
+          }
+          const double a = vn1[j];
+          if (a != 0.0) {
+            double temp = fabs(rk) / a;
+            temp = fmax(0.0, (1.0 + temp) * (1.0 - temp));
+            const double t2 = temp * (a / vn2[j]) * (a / vn2[j]);
+            if (t2 <= tol3z) {
+              vn1[j] = -1.0;          // recomputed below
+              atomicAdd(&s_nflag, 1);
+            } else {
+              vn1[j] = a * sqrt(temp);
+            }
+          }
+        }
+      }
+      __syncthreads();
+      if (s_nflag > 0) {
+        // exact residual norms of the flagged columns against q_0..q_k
+        for (;;) {
+          if (tid == 0) s_nf = 0;
+          __syncthreads();
+          for (int qa = tid; qa < nact_cur; qa += 256) {
+            const int g = act[qa];
+#pragma unroll
+            for (int q = 0; q < VN; ++q) {
+              const int j = g * VN + q;
+              if (!sel[j] && vn1[j] < 0.0) {
+                const int p = atomicAdd(&s_nf, 1);
+                if (p < 64) s_fl[p] = j;
+              }
+            }
+          }
+          __syncthreads();
+          const int nf = min(s_nf, 64);
+          if (nf == 0) break;
+          for (int f = 0; f < nf; ++f) {
+            const int j = s_fl[f];
+            for (int r = tid; r < m; r += 256) u[r] = double(W[(int64_t)r * ldw + j]);
+            __syncthreads();
+            qdots(u, k + 1, cbuf);
+            qsub(u, k + 1, cbuf);
+            double s2 = 0.0;
+            for (int r = tid; r < m; r += 256) s2 += u[r] * u[r];
+            s2 = block_sum(s2, red);
+            if (tid == 0) {
+              vn1[j] = sqrt(s2);
+              vn2[j] = vn1[j];
+            }
+            __syncthreads();
+          }
+        }
+      }
+      ++nst;
+      ++k;
+    }
   }
   __syncthreads();
 
@@ -1642,21 +1851,43 @@ __global__ __launch_bounds__(256, 4) void k_qrcp(const QrcpDesc *__restrict__ it
   if (tid == 0) *d.k_out = force_full ? m : k;
 }
 
-size_t qrcp_lds_bytes(int maxm, int maxgrp) {
-  const size_t MS = size_t(std::max(maxm, 1)), GS = size_t(std::max(maxgrp, 1));
-  return std::max<size_t>(2 * MS, 2048) * sizeof(double) + 2 * GS * sizeof(int);
+size_t qrcp_lds_bytes(int maxm, int maxgrp, int bq) {
+  const size_t MS = size_t(std::max(maxm, 1)), GS = size_t(std::max(maxgrp, 1)), B = size_t(bq);
+  return (std::max(std::max<size_t>(2 * MS, 2048), B * MS) + B * MS + B * B + B) * sizeof(double) +
+         (2 * GS + B) * sizeof(int);
+}
+
+int qrcp_block_width(int maxm, int maxgrp) {
+  for (int bq : {8, 4, 2})
+    if (qrcp_lds_bytes(maxm, maxgrp, bq) <= QRCP_MAX_LDS) return bq;
+  return 0;
 }
 
 int launch_qrcp(FType t, const QrcpDesc *d_items, int n, double eps, int force_full, int maxm,
-                int maxgrp, hipStream_t st) {
+                int maxgrp, int bq, hipStream_t st) {
   if (n <= 0) return SPAND_OK;
   const int MS = std::max(maxm, 1);
   const int GS = std::max(maxgrp, 1);
-  const size_t lds = qrcp_lds_bytes(MS, GS);
-  if (t == FType::F64)
-    hipLaunchKernelGGL(k_qrcp<double>, dim3(n), dim3(256), lds, st, d_items, eps, force_full, MS, GS);
-  else
-    hipLaunchKernelGGL(k_qrcp<float>, dim3(n), dim3(256), lds, st, d_items, eps, force_full, MS, GS);
+  const size_t lds = qrcp_lds_bytes(MS, GS, bq);
+  if ((bq != 8 && bq != 4 && bq != 2) || lds > QRCP_MAX_LDS) {
+    set_error("RRQR launch: block width %d, %zu bytes of LDS", bq, lds);
+    return SPAND_EINVAL;
+  }
+  if (t == FType::F64) {
+    if (bq == 8)
+      hipLaunchKernelGGL((k_qrcp<double, 8>), dim3(n), dim3(256), lds, st, d_items, eps, force_full, MS, GS);
+    else if (bq == 4)
+      hipLaunchKernelGGL((k_qrcp<double, 4>), dim3(n), dim3(256), lds, st, d_items, eps, force_full, MS, GS);
+    else
+      hipLaunchKernelGGL((k_qrcp<double, 2>), dim3(n), dim3(256), lds, st, d_items, eps, force_full, MS, GS);
+  } else {
+    if (bq == 8)
+      hipLaunchKernelGGL((k_qrcp<float, 8>), dim3(n), dim3(256), lds, st, d_items, eps, force_full, MS, GS);
+    else if (bq == 4)
+      hipLaunchKernelGGL((k_qrcp<float, 4>), dim3(n), dim3(256), lds, st, d_items, eps, force_full, MS, GS);
+    else
+      hipLaunchKernelGGL((k_qrcp<float, 2>), dim3(n), dim3(256), lds, st, d_items, eps, force_full, MS, GS);
+  }
   SP_HIP(hipGetLastError());
   return SPAND_OK;
 }
