@@ -550,6 +550,39 @@ int Factor::level0(const spand_bsr_t &A, const NDResult &nd, LevelState &S) {
       coup[cf].push_back({e, f, tm, t});
     }
   }
+  // the coupling blocks in factor precision, leaf by leaf (A[e, f] then
+  // A[f, e] for each coupling): operands of the Schur products below and
+  // stored for the sweeps
+  std::vector<size_t> cpl0(ncl, 0);
+  void *cb = nullptr;
+  size_t ncp = 0;
+  {
+    for (int s : leaves) {
+      cpl0[s] = ncp;
+      ncp += coup[s].size();
+    }
+    if (ncp) SP_TRY(dalloc(&cb, ncp * 2 * b2 * tsz, true));
+    std::vector<CopyDesc> cc;
+    for (int s : leaves)
+      for (size_t i = 0; i < coup[s].size(); ++i) {
+        const auto &c = coup[s][i];
+        const size_t q = cpl0[s] + i;
+        CopyDesc d{};
+        d.rows = d.cols = b;
+        d.lds = d.ldd = b;
+        d.scale = 1.0;
+        d.src = A.d_val + c.t_ef * b2;
+        d.dst = (char *)cb + (2 * q) * b2 * tsz;
+        cc.push_back(d);
+        d.src = A.d_val + c.t_fe * b2;
+        d.dst = (char *)cb + (2 * q + 1) * b2 * tsz;
+        cc.push_back(d);
+      }
+    SP_TRY(copy_batch(cc, 0));
+    trace("coupling copies", 0);
+  }
+  auto cpl_ns = [&](int s, size_t i) { return (void *)((char *)cb + (2 * (cpl0[s] + i)) * b2 * tsz); };
+  auto cpl_sn = [&](int s, size_t i) { return (void *)((char *)cb + (2 * (cpl0[s] + i) + 1) * b2 * tsz); };
   {
     // Schur targets (e_a, e_c); the items of a target stay in (leaf, a, c)
     // order.  Targets get ids through short per-element lists, then a
@@ -604,11 +637,12 @@ int Factor::level0(const spand_bsr_t &A, const NDResult &nd, LevelState &S) {
       for (int s : leaves) {
         const auto &C = coup[s];
         const int n = S.size[s];
-        for (const auto &ca : C)
-          for (const auto &cc : C) {
+        for (size_t ia = 0; ia < C.size(); ++ia)
+          for (size_t ic = 0; ic < C.size(); ++ic) {
+            const auto &ca = C[ia], &cc = C[ic];
             SchurItem it{};
-            it.a1 = ca.t_ef;      // A[e_a, f_a]
-            it.a2 = cc.t_fe;      // A[f_c, e_c]
+            it.A1 = cpl_ns(s, ia);     // A[e_a, f_a]
+            it.A2 = cpl_sn(s, ic);     // A[f_c, e_c]
             it.Y = (char *)Ainv[s] + (size_t(epos[ca.f]) * b * ld4(n) + size_t(epos[cc.f]) * b) * tsz;
             it.ldy = ld4(n);
             SchurGroup &g = groups[item_tid[q++]];
@@ -620,45 +654,26 @@ int Factor::level0(const spand_bsr_t &A, const NDResult &nd, LevelState &S) {
     SchurItem *d_i;
     SP_TRY(upload(groups, &d_g, false));
     SP_TRY(upload(items, &d_i, false));
-    SP_TRY(launch_schur_elem(ft, b, A.d_val, d_g, int(groups.size()), d_i, stream));
+    SP_TRY(launch_schur_elem(ft, b, d_g, int(groups.size()), d_i, stream));
     trace("schur plan+launch", 0);
     flops += double(items.size()) * 4.0 * b * b * b;
   }
   // ---- stored couplings and apply descriptors of level 0
   ApplyLevel &AL = lv[0];
   {
-    size_t ncp = 0;
-    for (int s : leaves) ncp += coup[s].size();
-    void *cb = nullptr;
-    if (ncp) SP_TRY(dalloc(&cb, ncp * 2 * b2 * tsz, true));
-    std::vector<CopyDesc> cc;
     // element -> list of (partner element, block ptr)
     using PairList = std::vector<std::vector<std::pair<int, void *>>>;
     PairList fw_ns(K), fw_sn(K);   // indexed by separator element e
     PairList bw_sn(K), bw_ns(K);   // indexed by leaf element f
-    size_t q = 0;
     for (int s : leaves)
-      for (const auto &c : coup[s]) {
-        void *pns = (char *)cb + (2 * q) * b2 * tsz;
-        void *psn = (char *)cb + (2 * q + 1) * b2 * tsz;
-        ++q;
-        CopyDesc d{};
-        d.rows = d.cols = b;
-        d.lds = d.ldd = b;
-        d.scale = 1.0;
-        d.src = A.d_val + c.t_ef * b2;
-        d.dst = pns;
-        cc.push_back(d);
-        d.src = A.d_val + c.t_fe * b2;
-        d.dst = psn;
-        cc.push_back(d);
+      for (size_t i = 0; i < coup[s].size(); ++i) {
+        const auto &c = coup[s][i];
+        void *pns = cpl_ns(s, i), *psn = cpl_sn(s, i);
         fw_ns[c.e].push_back({c.f, pns});
         fw_sn[c.e].push_back({c.f, psn});
         bw_sn[c.f].push_back({c.e, psn});
         bw_ns[c.f].push_back({c.e, pns});
       }
-    SP_TRY(copy_batch(cc, 0));
-    trace("coupling copies", 0);
     auto build = [&](PairList &m, int trans, std::vector<PullGroup> &G, std::vector<PullItem> &I,
                      bool all_leaf) {
       std::vector<int> keys;

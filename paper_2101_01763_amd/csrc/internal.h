@@ -158,9 +158,9 @@ struct PullChunk {          // up to PULL_ROWS output rows of one group
 
 // Level-0 element Schur update: target -= A1 * Y * A2 (b x b blocks)
 struct SchurItem {
-  int64_t a1;          // BSR block index (row sep elem, col leaf elem)
+  const void *A1;      // b x b copy of A[sep elem, leaf elem] (factor precision, ld b)
   const void *Y;       // pointer to the b x b block inside Ainv (ld = ldy)
-  int64_t a2;          // BSR block index (row leaf elem, col sep elem)
+  const void *A2;      // b x b copy of A[leaf elem, sep elem]
   int32_t ldy;
   int32_t pad;
 };
@@ -232,8 +232,8 @@ struct RowGatherDesc {
   int32_t n, cols, lds, ldd, col_off, colperm;
 };
 int launch_row_gather(FType t, const RowGatherDesc *d_items, int n, int max_rows, hipStream_t st);
-int launch_schur_elem(FType t, int bs, const double *bsr_val, const SchurGroup *d_groups,
-                      int ngroups, const SchurItem *d_items, hipStream_t st);
+int launch_schur_elem(FType t, int bs, const SchurGroup *d_groups, int ngroups,
+                      const SchurItem *d_items, hipStream_t st);
 // dynamic LDS of one QRCP workgroup with candidate blocks of width bq
 size_t qrcp_lds_bytes(int maxm, int maxgrp, int bq);
 constexpr size_t QRCP_MAX_LDS = 64 * 1024;

@@ -1070,9 +1070,10 @@ int launch_row_gather(FType t, const RowGatherDesc *d_items, int n, int max_rows
 
 // ------------------------------------------------------------------ level-0 Schur
 // target(b x b) -= A1 * Y * A2 for every item of a group, items in order.
+// A1, A2: b x b copies of the coupling blocks (factor precision, ld b);
+// Y: b x b block of an interior inverse (ld ldy).
 template <typename T>
-__global__ __launch_bounds__(256) void k_schur_elem(int bs, const double *__restrict__ bsr_val,
-                                                    const SchurGroup *__restrict__ groups,
+__global__ __launch_bounds__(256) void k_schur_elem(int bs, const SchurGroup *__restrict__ groups,
                                                     const SchurItem *__restrict__ items) {
   const SchurGroup g = groups[blockIdx.x];
   __shared__ T Xs[64][65];
@@ -1086,15 +1087,14 @@ __global__ __launch_bounds__(256) void k_schur_elem(int bs, const double *__rest
     const int idx = tid + q * 256;
     acc[q] = (q < nq && idx < bs * bs) ? tg[(int64_t)(idx / bs) * g.ldt + idx % bs] : T(0);
   }
-  const int64_t b2 = (int64_t)bs * bs;
   for (int it = g.item_begin; it < g.item_end; ++it) {
     const SchurItem s = items[it];
-    const double *a1 = bsr_val + s.a1 * b2;
-    const double *a2 = bsr_val + s.a2 * b2;
+    const T *a1 = (const T *)s.A1;
+    const T *a2 = (const T *)s.A2;
     const T *Y = (const T *)s.Y;
     for (int idx = tid; idx < bs * bs; idx += 256) {
       const int r = idx / bs, c = idx % bs;
-      Xs[r][c] = T(a1[idx]);
+      Xs[r][c] = a1[idx];
       Ys[r][c] = Y[(int64_t)r * s.ldy + c];
     }
     __syncthreads();
@@ -1115,7 +1115,7 @@ __global__ __launch_bounds__(256) void k_schur_elem(int bs, const double *__rest
       const int idx = tid + q * 256;
       if (q < nq && idx < bs * bs) Xs[idx / bs][idx % bs] = t1[q];
     }
-    for (int idx = tid; idx < bs * bs; idx += 256) Ys[idx / bs][idx % bs] = T(a2[idx]);
+    for (int idx = tid; idx < bs * bs; idx += 256) Ys[idx / bs][idx % bs] = a2[idx];
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
@@ -1136,15 +1136,85 @@ __global__ __launch_bounds__(256) void k_schur_elem(int bs, const double *__rest
   }
 }
 
-int launch_schur_elem(FType t, int bs, const double *bsr_val, const SchurGroup *d_groups,
-                      int ngroups, const SchurItem *d_items, hipStream_t st) {
+// FP32 on the matrix cores: the target (zero-padded to 64 x 64) stays in
+// the accumulators of the four waves (a 32 x 32 quarter each, the lane
+// layout of k_gemm_f32_mfma) for all its items.  Per item: T1 = A1 Y
+// (64^3 on v_mfma_f32_32x32x2f32 from LDS), -T1 back to LDS over A1, A2
+// over Y, then acc += (-T1) A2.
+__global__ __launch_bounds__(256) void k_schur_elem_mfma(int bs, const SchurGroup *__restrict__ groups,
+                                                         const SchurItem *__restrict__ items) {
+  constexpr int LS = 65;
+  const SchurGroup g = groups[blockIdx.x];
+  __shared__ float L0[64 * LS];     // A1 (row-major), then -T1
+  __shared__ float L1[64 * LS];     // Y, then A2 (both [k][n])
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int wr = wid >> 1, wc = wid & 1;
+  const int kmax = (bs + 1) & ~1;
+  float *tg = (float *)g.target;
+  const int col = wc * 32 + (lane & 31);
+  f32x16 acc;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int row = wr * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+    acc[r] = (row < bs && col < bs) ? tg[(int64_t)row * g.ldt + col] : 0.f;
+  }
+  // zero padding rows/columns stay zero in both tiles
+  for (int e = tid; e < 64 * LS; e += 256) {
+    L0[e] = 0.f;
+    L1[e] = 0.f;
+  }
+  __syncthreads();
+  const float *ap = L0 + (wr * 32 + (lane & 31)) * LS + (lane >> 5);
+  const float *bp = L1 + (lane >> 5) * LS + wc * 32 + (lane & 31);
+  for (int it = g.item_begin; it < g.item_end; ++it) {
+    const SchurItem s = items[it];
+    const float *a1 = (const float *)s.A1;
+    const float *a2 = (const float *)s.A2;
+    const float *Y = (const float *)s.Y;
+    for (int idx = tid; idx < bs * bs; idx += 256) {
+      const int r = idx / bs, c = idx - r * bs;
+      L0[r * LS + c] = a1[idx];
+      L1[r * LS + c] = Y[(int64_t)r * s.ldy + c];
+    }
+    __syncthreads();
+    f32x16 t1;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) t1[r] = 0.f;
+    for (int kk = 0; kk < kmax; kk += 2)
+      t1 = __builtin_amdgcn_mfma_f32_32x32x2f32(ap[kk], bp[kk * LS], t1, 0, 0, 0);
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int row = wr * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+      L0[row * LS + col] = (row < bs && col < bs) ? -t1[r] : 0.f;
+    }
+    for (int idx = tid; idx < bs * bs; idx += 256) {
+      const int r = idx / bs, c = idx - r * bs;
+      L1[r * LS + c] = a2[idx];
+    }
+    __syncthreads();
+    for (int kk = 0; kk < kmax; kk += 2)
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(ap[kk], bp[kk * LS], acc, 0, 0, 0);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int row = wr * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+    if (row < bs && col < bs) tg[(int64_t)row * g.ldt + col] = acc[r];
+  }
+}
+
+int launch_schur_elem(FType t, int bs, const SchurGroup *d_groups, int ngroups,
+                      const SchurItem *d_items, hipStream_t st) {
   if (ngroups <= 0) return SPAND_OK;
+  if (bs > 64) {
+    set_error("level-0 Schur: element block %d exceeds 64", bs);
+    return SPAND_EINVAL;
+  }
   if (t == FType::F64)
-    hipLaunchKernelGGL(k_schur_elem<double>, dim3(ngroups), dim3(256), 0, st, bs, bsr_val,
-                       d_groups, d_items);
+    hipLaunchKernelGGL(k_schur_elem<double>, dim3(ngroups), dim3(256), 0, st, bs, d_groups, d_items);
   else
-    hipLaunchKernelGGL(k_schur_elem<float>, dim3(ngroups), dim3(256), 0, st, bs, bsr_val,
-                       d_groups, d_items);
+    hipLaunchKernelGGL(k_schur_elem_mfma, dim3(ngroups), dim3(256), 0, st, bs, d_groups, d_items);
   SP_HIP(hipGetLastError());
   return SPAND_OK;
 }
