@@ -136,6 +136,9 @@ struct Factor {
   int upload_level_slots(LevelState &S);
   int gemm_batch(const std::vector<GemmDesc> &items);
   int copy_batch(const std::vector<CopyDesc> &items, int src_is_factor);
+  int complete_q(const LevelState &S, const std::vector<int> &ifs,
+                 const std::vector<int32_t> &kg, const std::vector<void *> &Qm,
+                 const std::vector<void *> &Vm);
   int elim_batch(std::vector<ElimDesc> &items, int mode);
   void mark(int phase);
   void collect_events();

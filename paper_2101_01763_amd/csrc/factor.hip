@@ -219,6 +219,10 @@ int Factor::elim_batch(std::vector<ElimDesc> &items, int mode) {
   // launch (one row per thread); larger ones go panel by panel.
   const bool lu = mode == 1;
   const bool fused = items[0].n <= elim_block_max_n(ft);
+  if (mode == 3 && !fused) {
+    set_error("shifted Gauss-Jordan: n = %d exceeds the fused limit %d", items[0].n, elim_block_max_n(ft));
+    return SPAND_EINVAL;
+  }
   size_t nP = 0, nT = 0, nI = 0, nB = 0, nPB = 0;
   for (auto &d : items) {
     if (!fused) {
@@ -330,6 +334,126 @@ int Factor::elim_batch(std::vector<ElimDesc> &items, int mode) {
                          uniform));
     }
   }
+  return SPAND_OK;
+}
+
+// Completion of the RRQR's orthogonal factors from their kept vectors, by
+// Householder reconstruction (Ballard et al., IPDPS 2014), batched over the
+// interfaces of a level.  With Q_c = [q_0 .. q_{k-1}] = [Q1; Q2] (Q1 k x k),
+// V rows 0..k-1 holding the q_t:
+//   M = Q1 - S, S = diag(s_j) chosen during the inversion (|pivot| >= 1);
+//   G2' = Q2 M^-1 S, written to V rows k..m-1;
+//   Q = [Q_c | E_c + Q_c G2'^T - [S G2'^T; 0]]   (E_c = columns k..m-1 of I;
+//   S G2'^T = G2^T with G2 = Q2 M^-1, the rows of the reflector block).
+// The right block is orthogonal to Q_c and completes it; with k = 0 Q = I.
+int Factor::complete_q(const LevelState &S, const std::vector<int> &ifs,
+                       const std::vector<int32_t> &kg, const std::vector<void *> &Qm,
+                       const std::vector<void *> &Vm) {
+  const size_t tsz = fsize(ft);
+  size_t nm = 0, ns = 0;
+  for (size_t q = 0; q < ifs.size(); ++q) {
+    const int m = S.size[ifs[q]], k = kg[q];
+    if (k > 0 && k < m) {
+      nm += size_t(k) * ld4(k);
+      ns += size_t(k);
+    }
+  }
+  void *Mb = nullptr, *Sg = nullptr;
+  if (nm) {
+    SP_TRY(dalloc(&Mb, nm * tsz, false));
+    SP_TRY(dalloc(&Sg, ns * tsz, false));
+  }
+  std::vector<CopyDesc> c1, c2;
+  std::vector<ElimDesc> gj;
+  std::vector<ScaleDesc> sc, sc2;
+  std::vector<GemmDesc> g1, g2;
+  std::vector<EyeDesc> ey;
+  size_t om = 0, os = 0;
+  int maxe = 1;
+  auto at = [&](void *p, size_t elems) { return (void *)((char *)p + elems * tsz); };
+  for (size_t q = 0; q < ifs.size(); ++q) {
+    const int s = ifs[q];
+    const int m = S.size[s], k = kg[q];
+    void *Qt = Vm[s], *Q = Qm[s];
+    if (k < 0 || k > m) {
+      set_error("RRQR returned %d kept vectors for an interface of size %d", k, m);
+      return SPAND_EHIP;
+    }
+    if (k == 0) {
+      ey.push_back(EyeDesc{Q, m, m});
+      maxe = std::max(maxe, m);
+      continue;
+    }
+    // Q(:, 0:k) = Q_c
+    c2.push_back(CopyDesc{Qt, Q, m, k, m, m, 1, 0, 1.0});
+    if (k == m) continue;
+    const int ldm = ld4(k);
+    void *M = at(Mb, om), *sg = at(Sg, os);
+    om += size_t(k) * ldm;
+    os += size_t(k);
+    c1.push_back(CopyDesc{Qt, M, k, k, m, ldm, 1, 0, 1.0});     // M(i, c) = q_c[i]
+    ElimDesc e{};
+    e.A = M;
+    e.n = e.ncols = k;
+    e.ld = ldm;
+    e.sg = sg;
+    gj.push_back(e);
+    sc.push_back(ScaleDesc{M, nullptr, sg, k, k, ldm, 0});     // M^-1 S
+    GemmDesc a{};
+    a.A = at(Qt, k);            // Q2(i, t) = q_t[k + i]
+    a.transA = 1;
+    a.lda = m;
+    a.B = M;
+    a.ldb = ldm;
+    a.C = at(Qt, size_t(k) * m);
+    a.ldc = m;
+    a.M = m - k;
+    a.N = k;
+    a.K = k;
+    a.alpha = 1.0;
+    g1.push_back(a);
+    // Q(0:k, k:m) = -S G2'^T ; Q(k:m, k:m) = I ; then Q(:, k:m) += Q_c G2'^T
+    c2.push_back(CopyDesc{at(Qt, size_t(k) * m), at(Q, k), k, m - k, m, m, 1, 0, -1.0});
+    sc2.push_back(ScaleDesc{at(Q, k), sg, nullptr, k, m - k, m, 0});
+    ey.push_back(EyeDesc{at(Q, size_t(k) * m + k), m - k, m});
+    maxe = std::max(maxe, m - k);
+    GemmDesc b{};
+    b.A = Qt;
+    b.transA = 1;
+    b.lda = m;
+    b.B = at(Qt, size_t(k) * m);
+    b.transB = 1;
+    b.ldb = m;
+    b.C = at(Q, k);
+    b.ldc = m;
+    b.M = m;
+    b.N = m - k;
+    b.K = k;
+    b.alpha = 1.0;
+    b.beta = 1.0;
+    g2.push_back(b);
+    flops += 2.0 * k * k * k + 2.0 * (m - k) * k * k + 2.0 * m * (m - k) * k;
+  }
+  SP_TRY(copy_batch(c1, 1));
+  if (!gj.empty()) SP_TRY(elim_batch(gj, 3));
+  if (!sc.empty()) {
+    ScaleDesc *d_sc;
+    SP_TRY(upload(sc, &d_sc, false));
+    SP_TRY(launch_scale(ft, d_sc, int(sc.size()), stream));
+  }
+  SP_TRY(gemm_batch(g1));
+  SP_TRY(copy_batch(c2, 1));
+  if (!sc2.empty()) {
+    ScaleDesc *d_sc;
+    SP_TRY(upload(sc2, &d_sc, false));
+    SP_TRY(launch_scale(ft, d_sc, int(sc2.size()), stream));
+  }
+  if (!ey.empty()) {
+    EyeDesc *d_e;
+    SP_TRY(upload(ey, &d_e, false));
+    SP_TRY(launch_eye(ft, d_e, int(ey.size()), maxe, stream));
+  }
+  SP_TRY(gemm_batch(g2));
   return SPAND_OK;
 }
 
@@ -1211,8 +1335,14 @@ int Factor::sparsify(int l, const NDResult &nd, LevelState &S, LevelState &Nx) {
   std::vector<void *> Qm(ncl), Vm(ncl), Wm(ncl);
   std::vector<int> ncols(ncl, 0);
   std::vector<QrcpDesc> qd;
-  void *kout;
+  void *kout, *kgs;
   SP_TRY(dalloc(&kout, std::max<size_t>(1, ifs.size()) * 4, false));
+  SP_TRY(dalloc(&kgs, std::max<size_t>(1, ifs.size()) * 4, false));
+  // Q is completed by batched launches (sign-shifted Gauss-Jordan on the
+  // fused path, products on the matrix cores) when every interface fits the
+  // fused elimination; otherwise inside the QRCP kernel
+  bool batched_cq = true;
+  for (int s : ifs) batched_cq = batched_cq && S.size[s] <= elim_block_max_n(ft);
   {
     // all W in one zeroed region (padding columns must read as zero)
     PlanArena pw;
@@ -1294,6 +1424,7 @@ int Factor::sparsify(int l, const NDResult &nd, LevelState &S, LevelState &Nx) {
       Qd.sel = (int32_t *)sel;
       Qd.H = (double *)hq;
       Qd.k_out = (int32_t *)kout + q;
+      Qd.k_gs = (int32_t *)kgs + q;
       Qd.m = m;
       Qd.ncols = nc;
       Qd.ldw = ldw;
@@ -1309,19 +1440,27 @@ int Factor::sparsify(int l, const NDResult &nd, LevelState &S, LevelState &Nx) {
       (void)hipEventCreate(&qe1);
       (void)hipEventRecord(qe0, stream);
     }
-    SP_TRY(launch_qrcp(ft, d_q, int(qd.size()), eps, eps == 0.0 ? 1 : 0, mq, mg, bq, stream));
+    SP_TRY(launch_qrcp(ft, d_q, int(qd.size()), eps, eps == 0.0 ? 1 : 0, mq, mg, bq,
+                       batched_cq ? 0 : 1, stream));
     trace("qrcp plan+launch", l);
     if (timing) {
       (void)hipEventRecord(qe1, stream);
       qrcp_events.push_back({qe0, qe1});
     }
   }
-  std::vector<int32_t> ks(ifs.size(), 0);
-  if (!ifs.empty())
+  std::vector<int32_t> ks(ifs.size(), 0), kg(ifs.size(), 0);
+  if (!ifs.empty()) {
     SP_HIP(hipMemcpyAsync(ks.data(), kout, ifs.size() * 4, hipMemcpyDeviceToHost, stream));
+    if (batched_cq)
+      SP_HIP(hipMemcpyAsync(kg.data(), kgs, ifs.size() * 4, hipMemcpyDeviceToHost, stream));
+  }
   SP_HIP(hipStreamSynchronize(stream));
   trace("sync", -1);
   release_retired();
+  if (batched_cq && !ifs.empty()) {
+    SP_TRY(complete_q(S, ifs, kg, Qm, Vm));
+    trace("qrcp completion", l);
+  }
   std::vector<int> kk(ncl, 0);
   {
     RankStat rs;

@@ -121,6 +121,7 @@ struct ElimDesc {
   int32_t pad;
   void *TB;         // workspace ELIM_BLK x ld (blocked elimination: pivot rows of a block)
   void *PB;         // workspace n x ELIM_BLK (blocked LU: multipliers of a block)
+  void *sg;         // [n] factor precision: diagonal shifts of mode 3
 };
 
 // Dense GEMV with gather/scatter through slot lists:
@@ -183,6 +184,7 @@ struct QrcpDesc {
   int32_t *sel;        // [ldw] selected (or padding) flags
   double *H;           // [ldw x block width] candidate-basis coordinates of the columns
   int32_t *k_out;      // rank
+  int32_t *k_gs;       // kept Gram-Schmidt vectors (V rows 0..k_gs-1)
   int32_t m, ncols;
   int32_t ldw;         // leading dimension of W (multiple of 4, padding zero)
   int32_t pad;         // LDS stride (largest m of the launch), set by the host
@@ -211,7 +213,8 @@ int launch_copy(FType t, int src_is_factor, const CopyDesc *d_items, int n, int6
 int launch_copy_t(FType t, int src_is_factor, const CopyDesc *d_items, int n, int max_rows,
                   int max_cols, hipStream_t st);
 // mode 0: Gauss-Jordan, partial pivoting; 1: LU (augmented), partial
-// pivoting; 2: Gauss-Jordan without pivoting.  Items sorted by n descending,
+// pivoting; 2: Gauss-Jordan without pivoting; 3: as 2 on A - S with the
+// signs S chosen on the way (fused block path only, signs to ElimDesc::sg).  Items sorted by n descending,
 // the first nactive have n > k.
 int launch_elim_step(FType t, const ElimDesc *d_items, int nactive, int k, int mode,
                      int max_tiles, int *d_flag, int cw0, int cw1, hipStream_t st);
@@ -239,9 +242,10 @@ size_t qrcp_lds_bytes(int maxm, int maxgrp, int bq);
 constexpr size_t QRCP_MAX_LDS = 64 * 1024;
 // widest candidate block (8, 4 or 2) whose LDS fits, 0 if none does
 int qrcp_block_width(int maxm, int maxgrp);
-// every item's H holds ldw x bq doubles
+// every item's H holds ldw x bq doubles.  complete = 0: Q is left to the
+// caller (V rows 0..k_gs-1 hold the kept vectors, nothing else is written)
 int launch_qrcp(FType t, const QrcpDesc *d_items, int n, double eps, int force_full, int maxm,
-                int maxgrp, int bq, hipStream_t st);
+                int maxgrp, int bq, int complete, hipStream_t st);
 // dst rows/cols scaling: dst[r, c] *= rs[r] * cs[c] (either may be null)
 struct ScaleDesc {
   void *A;

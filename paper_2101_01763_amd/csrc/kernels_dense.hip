@@ -681,18 +681,21 @@ __device__ inline int wave_argmax_key(uint64_t key, bool can, uint64_t *kmax) {
 // ------------------------------------------------------------------ fused block elimination
 // One workgroup eliminates the block columns [k0, k0 + wb), wb <= ELIM_BLK,
 // of one matrix and applies them to the whole column window
-// [k0, k0 + ELIM_BLK) (columns past n exist for LU on [A | I]), one row per thread (blockDim.x >= n), the block part of the
-// row in registers.  The slots of a row are kept rotated: at the step of
-// block column c, slot i holds column (c + i) mod ELIM_BLK, so the column
-// being eliminated is always slot 0.  Every register index is then a
-// compile-time constant while the column loop stays rolled; one fused
-// multiply-add per slot both applies a step and rotates the row.
-// Per step: argmax of |slot 0| over the rows that may still pivot (a
-// butterfly per wave; each wave posts its candidate's whole row to LDS, and
-// after one barrier every thread takes the best of the waves' candidates;
-// ties go to the lowest row, as in the panel kernel).
-//   MODE 0/2: Gauss-Jordan; every row changes, the pivot row is scaled; on
-//             exit the block columns are the block's P_B.
+// [k0, k0 + ELIM_BLK) (columns past n exist for LU on [A | I]); one row per
+// thread (blockDim.x >= n), the window part of the row in registers.  The
+// steps run in groups of 4 columns with the slots fixed inside a group, so
+// every register index is a compile-time constant while the group loop
+// stays rolled (see the step below).
+// Per step: argmax of |a_rc| over the rows that may still pivot (DPP wave
+// maximum and ballot, ties to the lowest row; each wave posts its
+// candidate's whole row to LDS and one barrier later every thread takes
+// the best), then one fused multiply-add per slot.
+//   MODE 0/2: Gauss-Jordan (with / without pivoting); every row changes,
+//             the pivot row is scaled; on exit the block columns are the
+//             block's P_B.
+//   MODE 3:   Gauss-Jordan without pivoting on A - S, S = diag(s_c) chosen
+//             as each column is reached: s_c = -sign of the current a_cc,
+//             so every pivot has modulus >= 1 (the signs go to d.sg).
 //   MODE 1:   LU; only rows not yet used as pivots change.  A changed row
 //             keeps its multipliers (the block's elimination matrix taken at
 //             the pivot rows) in the slots of the columns already
@@ -703,6 +706,7 @@ template <typename T, int MODE, int MAXT>
 __global__ __launch_bounds__(MAXT) void k_elim_block(const ElimDesc *__restrict__ items, int k0,
                                                      int *__restrict__ flag) {
   constexpr int BW = ELIM_BLK, NWMAX = MAXT / 64, V = 16 / sizeof(T);
+  constexpr bool NOPIV = MODE >= 2;        // pivot of block column c is row k0 + c
   static_assert(BW == 64, "slot rotation assumes 64 block columns");
   const ElimDesc d = items[blockIdx.x];
   const int n = d.n;
@@ -740,12 +744,12 @@ __global__ __launch_bounds__(MAXT) void k_elim_block(const ElimDesc *__restrict_
       for (int i = 0; i < BW; ++i)
         if (i < wc) s[i] = src[i];
     }
-    if (MODE != 2 && d.used[tid] != 0) {
+    if (!NOPIV && d.used[tid] != 0) {
       used = true;
       pc = -2;
     }
   }
-  constexpr bool KEYED = sizeof(T) == 4 && MODE != 2;
+  constexpr bool KEYED = sizeof(T) == 4 && !NOPIV;
   if (KEYED) {
     if (tid < 3) ckey[tid] = 0;
     __syncthreads();
@@ -760,7 +764,7 @@ __global__ __launch_bounds__(MAXT) void k_elim_block(const ElimDesc *__restrict_
     const int buf = c & 1;
     int prow, ws = 0, bi = -1;
     uint64_t kmax = 0;
-    if (MODE == 2) {
+    if (NOPIV) {
       prow = k0 + c;
       if (tid == prow) {
 #pragma unroll
@@ -791,7 +795,7 @@ __global__ __launch_bounds__(MAXT) void k_elim_block(const ElimDesc *__restrict_
         prow = k0 + c;
         ws = 0;
       }
-    } else if (MODE != 2) {
+    } else if (!NOPIV) {
       if ((tid & 63) == 0) {
         cval[buf][wv] = kmax;
         cidx[buf][wv] = bi;
@@ -818,7 +822,12 @@ __global__ __launch_bounds__(MAXT) void k_elim_block(const ElimDesc *__restrict_
     T pq[V];
     *(uint4 *)pq = pr[k / V];
     T p = pq[k % V];
-    if (p == T(0)) {
+    if (MODE == 3) {
+      // shifted pivot a_cc - s_c with s_c = -sign(a_cc): modulus >= 1
+      const T sgn = p >= T(0) ? T(-1) : T(1);
+      if (tid == 0) ((T *)d.sg)[k0 + c] = sgn;
+      p -= sgn;
+    } else if (p == T(0)) {
       if (tid == 0) atomicOr(flag, 1);
       p = T(1);
     }
@@ -912,7 +921,7 @@ __global__ __launch_bounds__(MAXT) void k_elim_block(const ElimDesc *__restrict_
         if (col < wc) dst[col] = s[i];
       }
     }
-    if (MODE != 2) d.used[tid] = used ? 1 : 0;
+    if (!NOPIV) d.used[tid] = used ? 1 : 0;
   }
   if (tid < wb) d.piv[k0 + tid] = s_piv[tid];
 }
@@ -932,15 +941,19 @@ int launch_elim_block(FType t, const ElimDesc *d_items, int nactive, int k0, int
       hipLaunchKernelGGL((k_elim_block<double, 0, 512>), dim3(nactive), block, 0, st, d_items, k0, d_flag);
     else if (mode == 1)
       hipLaunchKernelGGL((k_elim_block<double, 1, 512>), dim3(nactive), block, 0, st, d_items, k0, d_flag);
-    else
+    else if (mode == 2)
       hipLaunchKernelGGL((k_elim_block<double, 2, 512>), dim3(nactive), block, 0, st, d_items, k0, d_flag);
+    else
+      hipLaunchKernelGGL((k_elim_block<double, 3, 512>), dim3(nactive), block, 0, st, d_items, k0, d_flag);
   } else {
     if (mode == 0)
       hipLaunchKernelGGL((k_elim_block<float, 0, 1024>), dim3(nactive), block, 0, st, d_items, k0, d_flag);
     else if (mode == 1)
       hipLaunchKernelGGL((k_elim_block<float, 1, 1024>), dim3(nactive), block, 0, st, d_items, k0, d_flag);
-    else
+    else if (mode == 2)
       hipLaunchKernelGGL((k_elim_block<float, 2, 1024>), dim3(nactive), block, 0, st, d_items, k0, d_flag);
+    else
+      hipLaunchKernelGGL((k_elim_block<float, 3, 1024>), dim3(nactive), block, 0, st, d_items, k0, d_flag);
   }
   SP_HIP(hipGetLastError());
   return SPAND_OK;
@@ -1300,7 +1313,7 @@ __device__ inline void wg_gemm(int M, int N, int K, FA A, FB B, FE epi, double *
 //     Rows k.. of V receive G2 S; tau receives S.
 template <typename T, int BQ>
 __global__ __launch_bounds__(256, 3) void k_qrcp(const QrcpDesc *__restrict__ items, double eps,
-                                              int force_full, int MS, int GS) {
+                                              int force_full, int MS, int GS, int complete) {
   static_assert(BQ % 2 == 0, "H is read in pairs");
   const QrcpDesc d = items[blockIdx.x];
   const int m = d.m, nc = d.ncols;
@@ -1858,12 +1871,14 @@ __global__ __launch_bounds__(256, 3) void k_qrcp(const QrcpDesc *__restrict__ it
   }
   __syncthreads();
 
-  // ---- 3. complete Q
+  // ---- 3. complete Q (unless the caller completes it in batched launches
+  // from the k_gs kept vectors)
+  if (tid == 0) *d.k_gs = k;
   double *As = qsm, *Bs = qsm + 1024;
-  if (k == 0) {
+  if (complete && k == 0) {
     for (int i2 = tid >> 4; i2 < m; i2 += 16)
       for (int c = tid & 15; c < m; c += 16) Q[(int64_t)i2 * m + c] = T(i2 == c ? 1.0 : 0.0);
-  } else {
+  } else if (complete) {
     if (k < m) {
       // Q1 into the top-left k x k of Q, then its in-place Gauss-Jordan
       // inversion with the diagonal shifted by -s_j when column j pivots
@@ -1934,7 +1949,7 @@ int qrcp_block_width(int maxm, int maxgrp) {
 }
 
 int launch_qrcp(FType t, const QrcpDesc *d_items, int n, double eps, int force_full, int maxm,
-                int maxgrp, int bq, hipStream_t st) {
+                int maxgrp, int bq, int complete, hipStream_t st) {
   if (n <= 0) return SPAND_OK;
   const int MS = std::max(maxm, 1);
   const int GS = std::max(maxgrp, 1);
@@ -1945,18 +1960,18 @@ int launch_qrcp(FType t, const QrcpDesc *d_items, int n, double eps, int force_f
   }
   if (t == FType::F64) {
     if (bq == 8)
-      hipLaunchKernelGGL((k_qrcp<double, 8>), dim3(n), dim3(256), lds, st, d_items, eps, force_full, MS, GS);
+      hipLaunchKernelGGL((k_qrcp<double, 8>), dim3(n), dim3(256), lds, st, d_items, eps, force_full, MS, GS, complete);
     else if (bq == 4)
-      hipLaunchKernelGGL((k_qrcp<double, 4>), dim3(n), dim3(256), lds, st, d_items, eps, force_full, MS, GS);
+      hipLaunchKernelGGL((k_qrcp<double, 4>), dim3(n), dim3(256), lds, st, d_items, eps, force_full, MS, GS, complete);
     else
-      hipLaunchKernelGGL((k_qrcp<double, 2>), dim3(n), dim3(256), lds, st, d_items, eps, force_full, MS, GS);
+      hipLaunchKernelGGL((k_qrcp<double, 2>), dim3(n), dim3(256), lds, st, d_items, eps, force_full, MS, GS, complete);
   } else {
     if (bq == 8)
-      hipLaunchKernelGGL((k_qrcp<float, 8>), dim3(n), dim3(256), lds, st, d_items, eps, force_full, MS, GS);
+      hipLaunchKernelGGL((k_qrcp<float, 8>), dim3(n), dim3(256), lds, st, d_items, eps, force_full, MS, GS, complete);
     else if (bq == 4)
-      hipLaunchKernelGGL((k_qrcp<float, 4>), dim3(n), dim3(256), lds, st, d_items, eps, force_full, MS, GS);
+      hipLaunchKernelGGL((k_qrcp<float, 4>), dim3(n), dim3(256), lds, st, d_items, eps, force_full, MS, GS, complete);
     else
-      hipLaunchKernelGGL((k_qrcp<float, 2>), dim3(n), dim3(256), lds, st, d_items, eps, force_full, MS, GS);
+      hipLaunchKernelGGL((k_qrcp<float, 2>), dim3(n), dim3(256), lds, st, d_items, eps, force_full, MS, GS, complete);
   }
   SP_HIP(hipGetLastError());
   return SPAND_OK;
