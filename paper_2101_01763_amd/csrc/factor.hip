@@ -1357,7 +1357,22 @@ int Factor::sparsify(int l, const NDResult &nd, LevelState &S, LevelState &Nx) {
     if (!ifs.empty()) {
       SP_TRY(dalloc(&wbase, pw.total, false));
       SP_TRY(dalloc(&wbase2, pw.total, false));     // compaction target of the kernel
-      SP_HIP(hipMemsetAsync(wbase, 0, pw.total, stream));
+      // the copies below write every column but the padding up to ldw,
+      // which must read as zero
+      std::vector<ZeroDesc> zd;
+      int64_t mz = 1;
+      for (int s : ifs) {
+        const int nc = ncols[s], ldw = ld4(std::max(nc, 1));
+        if (ldw > nc) {
+          zd.push_back(ZeroDesc{(char *)wbase + wo[s] + size_t(nc) * tsz, S.size[s], ldw - nc, ldw, 0});
+          mz = std::max<int64_t>(mz, int64_t(S.size[s]) * (ldw - nc));
+        }
+      }
+      if (!zd.empty()) {
+        ZeroDesc *d_zd;
+        SP_TRY(upload(zd, &d_zd, false));
+        SP_TRY(launch_zero(ft, d_zd, int(zd.size()), mz, stream));
+      }
     }
     int mq = 1, mg = 1;
     for (int s : ifs) {

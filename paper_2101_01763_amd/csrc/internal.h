@@ -260,6 +260,12 @@ struct EyeDesc {
   int32_t n, ld;
 };
 int launch_eye(FType t, const EyeDesc *d_items, int n, int max_n, hipStream_t st);
+// A = 0 (rows x cols sub-block with leading dimension ld)
+struct ZeroDesc {
+  void *A;
+  int32_t rows, cols, ld, pad;
+};
+int launch_zero(FType t, const ZeroDesc *d_items, int n, int64_t max_elems, hipStream_t st);
 int launch_gemv(FType t, const GemvDesc *d_items, const GemvChunk *d_chunks, int nchunks,
                 const double *in, double *out, double alpha, double beta, hipStream_t st);
 int launch_slot_copy(const int32_t *slots, int64_t n, const double *src, double *dst,
