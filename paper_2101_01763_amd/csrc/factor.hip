@@ -143,6 +143,14 @@ int Factor::upload_level_slots(LevelState &S) {
   return SPAND_OK;
 }
 
+// ------------------------------------------------------------------ host trace
+// SPAND_HOST_TRACE set: every planning step prints its host time to stderr
+// (diagnostics of the host/device overlap; no effect otherwise).
+static bool host_trace_on() {
+  static const bool on = std::getenv("SPAND_HOST_TRACE") != nullptr;
+  return on;
+}
+
 // ------------------------------------------------------------------ batched helpers
 int Factor::gemm_batch(const std::vector<GemmDesc> &items) {
   if (items.empty()) return SPAND_OK;
@@ -471,13 +479,6 @@ void Factor::mark(int phase) {
   events.push_back({phase, e});
 }
 
-// ------------------------------------------------------------------ host trace
-// SPAND_HOST_TRACE set: every planning step prints its host time to stderr
-// (diagnostics of the host/device overlap; no effect otherwise).
-static bool host_trace_on() {
-  static const bool on = std::getenv("SPAND_HOST_TRACE") != nullptr;
-  return on;
-}
 void Factor::trace(const char *what, int l) {
   if (!host_trace_on()) return;
   const auto now = std::chrono::steady_clock::now();
@@ -898,6 +899,16 @@ int PullSet::set(Factor &F, std::vector<PullGroup> G, const std::vector<PullItem
   }
   if (trans < 0) trans = 0;
   nchunks = int(ch.size());
+  if (host_trace_on()) {
+    double bytes = 0.0;
+    int maxc = 0;
+    for (const auto &p : I) {
+      bytes += double(p.rows) * p.cols * fsize(F.ft);
+      maxc = std::max(maxc, p.cols);
+    }
+    std::fprintf(stderr, "[spand host] pull set: %zu groups %d chunks %zu items %.3f GB, max cols %d, trans %d\n",
+                 G.size(), nchunks, I.size(), bytes * 1e-9, maxc, trans);
+  }
   SP_TRY(F.upload(G, &d_groups, true));
   SP_TRY(F.upload(I, &d_items, true));
   SP_TRY(F.upload(ch, &d_chunks, true));

@@ -152,10 +152,9 @@ int launch_slot_copy(const int32_t *slots, int64_t n, const double *src, double 
 // One workgroup per chunk of at most 64 output rows of a group; the items of
 // the group are accumulated in order, in registers (a row is always owned by
 // the same lanes).  Per item the input segment is staged in LDS.
-//  * op(B) = B: Q lanes per row.  Q = 4 with 16-byte loads when the group's
-//    blocks allow it (flag bit 0 of the group: leading dimensions multiple of
-//    4, 16-byte aligned rows), else Q = 16 with scalar loads; the Q partial
-//    sums combine by shuffles.
+//  * op(B) = B: 4 lanes per row with 16-byte loads from each row's first
+//    16-byte boundary on (scalar head and tail); the partial sums combine
+//    by shuffles.
 //  * op(B) = B^T (B stored cols x rows): one lane per output row, four
 //    slices of the columns, combined through LDS at the end.
 template <typename T, int TRANS>
@@ -172,7 +171,6 @@ __global__ __launch_bounds__(256) void k_pull(const PullGroup *__restrict__ grou
   __shared__ double xs[GEMV_MAXC];
   __shared__ double part[256];
   const int tid = threadIdx.x;
-  const bool vec = (g.pad & 1) != 0;
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   for (int it = g.item_begin; it < g.item_end; ++it) {
     const PullItem p = items[it];
@@ -181,40 +179,30 @@ __global__ __launch_bounds__(256) void k_pull(const PullGroup *__restrict__ grou
     __syncthreads();
     const T *B = (const T *)p.B;
     if (!TRANS) {
-      if (vec) {
-        const int rr = tid >> 2, q = tid & 3;
-        double a = 0.0;
-        if (rr < ch.nrows) {
-          const T *row = B + (int64_t)(ch.row0 + rr) * p.ldb;
-          const int cv = p.cols / VN * VN;
+      // 4 lanes per row, 16-byte loads from the row's first 16-byte
+      // boundary on (a row of any leading dimension: the few elements
+      // before the boundary and after the last full vector are scalar)
+      const int rr = tid >> 2, q = tid & 3;
+      double a = 0.0;
+      if (rr < ch.nrows) {
+        const T *row = B + (int64_t)(ch.row0 + rr) * p.ldb;
+        const int mis = int((reinterpret_cast<uintptr_t>(row) / sizeof(T)) % VN);
+        const int h = min(mis ? VN - mis : 0, p.cols);
+        if (q < h) a += double(row[q]) * xs[q];
+        const int cv = h + (p.cols - h) / VN * VN;
 #pragma unroll 4
-          for (int c = q * VN; c < cv; c += 4 * VN) {
-            const typename VW::V v = *reinterpret_cast<const typename VW::V *>(row + c);
-            T e[VN];
-            VW::get(v, e);
+        for (int c = h + q * VN; c < cv; c += 4 * VN) {
+          const typename VW::V v = *reinterpret_cast<const typename VW::V *>(row + c);
+          T e[VN];
+          VW::get(v, e);
 #pragma unroll
-            for (int u = 0; u < VN; ++u) a += double(e[u]) * xs[c + u];
-          }
-          for (int c = cv + q; c < p.cols; c += 4) a += double(row[c]) * xs[c];
+          for (int u = 0; u < VN; ++u) a += double(e[u]) * xs[c + u];
         }
-        a += __shfl_xor(a, 1, 64);
-        a += __shfl_xor(a, 2, 64);
-        acc[0] += a;
-      } else {
-        const int rr = tid >> 4, q = tid & 15;
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          const int r = rr + 16 * t;
-          double a = 0.0;
-          if (r < ch.nrows) {
-            const T *row = B + (int64_t)(ch.row0 + r) * p.ldb;
-            for (int c = q; c < p.cols; c += 16) a += double(row[c]) * xs[c];
-          }
-#pragma unroll
-          for (int o = 1; o < 16; o <<= 1) a += __shfl_xor(a, o, 64);
-          acc[t] += a;
-        }
+        for (int c = cv + q; c < p.cols; c += 4) a += double(row[c]) * xs[c];
       }
+      a += __shfl_xor(a, 1, 64);
+      a += __shfl_xor(a, 2, 64);
+      acc[0] += a;
     } else {
       const int rr = tid & 63, cs = tid >> 6;
       if (rr < ch.nrows) {
@@ -237,16 +225,8 @@ __global__ __launch_bounds__(256) void k_pull(const PullGroup *__restrict__ grou
     out[o] = v;
   };
   if (!TRANS) {
-    if (vec) {
-      const int rr = tid >> 2;
-      if ((tid & 3) == 0 && rr < ch.nrows) put(rr, acc[0]);
-    } else {
-      const int rr = tid >> 4;
-      if ((tid & 15) == 0)
-#pragma unroll
-        for (int t = 0; t < 4; ++t)
-          if (rr + 16 * t < ch.nrows) put(rr + 16 * t, acc[t]);
-    }
+    const int rr = tid >> 2;
+    if ((tid & 3) == 0 && rr < ch.nrows) put(rr, acc[0]);
   } else {
     part[tid] = acc[0];
     __syncthreads();
