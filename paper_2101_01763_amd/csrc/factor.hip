@@ -152,8 +152,36 @@ static bool host_trace_on() {
 }
 
 // ------------------------------------------------------------------ batched helpers
+void gemm_coarse(const std::vector<int32_t> &ts, size_t a, size_t b, std::vector<int32_t> &out) {
+  const int64_t ntiles = ts[b] - ts[a];
+  const int64_t nc = ntiles / 64 + 1;
+  size_t d = a;
+  for (int64_t c = 0; c <= nc; ++c) {
+    const int64_t t = ts[a] + std::min<int64_t>(c * 64, ntiles - 1);
+    while (d + 1 < b && ts[d + 1] <= t) ++d;
+    out.push_back(int32_t(d - a));
+  }
+}
+
 int Factor::gemm_batch(const std::vector<GemmDesc> &items) {
   if (items.empty()) return SPAND_OK;
+  if (host_trace_on()) {
+    double fl = 0.0, by = 0.0;
+    int64_t tiles = 0;
+    for (const auto &d : items) {
+      fl += 2.0 * d.M * d.N * d.K;
+      by += (double(d.M) * d.K + double(d.K) * d.N + double(d.M) * d.N * (d.beta != 0.0 ? 2 : 1)) * fsize(ft);
+      tiles += cdiv(d.M, 64) * cdiv(d.N, 64);
+    }
+    int modes = 0;
+    for (int tm = 0; tm < 4; ++tm) {
+      bool any = false;
+      for (const auto &d : items) any = any || 2 * (d.transA != 0) + (d.transB != 0) == tm;
+      modes += any;
+    }
+    std::fprintf(stderr, "[spand host] gemm batch: %zu items %lld tiles %.3f TFLOP %.3f GB (operands once), %d launches\n",
+                 items.size(), (long long)tiles, fl * 1e-12, by * 1e-9, modes);
+  }
   // one launch per transpose mode (the FP32 kernel is specialised on it)
   std::vector<GemmDesc> ord;
   std::vector<int32_t> ts(1, 0);
@@ -171,14 +199,27 @@ int Factor::gemm_batch(const std::vector<GemmDesc> &items) {
   int32_t *d_ts;
   SP_TRY(upload(ord, &d_items, false));
   SP_TRY(upload(ts, &d_ts, false));
+  int uni[4] = {0, 0, 0, 0};
+  size_t coff[5] = {0, 0, 0, 0, 0};
+  std::vector<int32_t> coarse;
   for (int tm = 0; tm < 4; ++tm) {
     const int a = start[tm], b = start[tm + 1];
+    coff[tm] = coarse.size();
     if (b > a) {
       int uniform = ts[a + 1] - ts[a];
       for (int q = a; q < b && uniform > 0; ++q)
         if (ts[q + 1] - ts[q] != uniform) uniform = 0;
-      SP_TRY(launch_gemm(ft, d_items + a, d_ts + a, b - a, ts[b] - ts[a], stream, ts[a], tm, uniform));
+      uni[tm] = uniform;
+      if (!uniform) gemm_coarse(ts, size_t(a), size_t(b), coarse);
     }
+  }
+  int32_t *d_coarse = nullptr;
+  if (!coarse.empty()) SP_TRY(upload(coarse, &d_coarse, false));
+  for (int tm = 0; tm < 4; ++tm) {
+    const int a = start[tm], b = start[tm + 1];
+    if (b > a)
+      SP_TRY(launch_gemm(ft, d_items + a, d_ts + a, b - a, ts[b] - ts[a], stream, ts[a], tm, uni[tm],
+                         uni[tm] ? nullptr : d_coarse + coff[tm]));
   }
   return SPAND_OK;
 }
@@ -307,10 +348,37 @@ int Factor::elim_batch(std::vector<ElimDesc> &items, int mode) {
     }
   }
   bstart.push_back(gd.size());
+  if (host_trace_on()) {
+    double fl = 0.0, by = 0.0;
+    for (const auto &d : gd) {
+      fl += 2.0 * d.M * d.N * d.K;
+      by += (double(d.M) * d.K + double(d.K) * d.N + 2.0 * d.M * d.N) * fsize(ft);
+    }
+    int nl = 0;
+    for (size_t b = 0; b + 1 < bstart.size(); ++b) nl += bstart[b + 1] > bstart[b];
+    std::fprintf(stderr, "[spand host] elim batch mode %d: %zu items nmax %d, %zu block products %.3f TFLOP %.3f GB, %d launches\n",
+                 mode, items.size(), nmax, gd.size(), fl * 1e-12, by * 1e-9, nl);
+  }
   GemmDesc *d_gd = nullptr;
   int32_t *d_ts = nullptr;
   SP_TRY(upload(gd, &d_gd, false));
   SP_TRY(upload(ts, &d_ts, false));
+  // per block: uniform tile count, or the offset of its coarse index
+  std::vector<int> buni(bstart.size(), 0);
+  std::vector<size_t> boff(bstart.size(), 0);
+  std::vector<int32_t> coarse;
+  for (size_t b = 0; b + 1 < bstart.size(); ++b) {
+    const size_t g0 = bstart[b], g1 = bstart[b + 1];
+    if (g1 <= g0) continue;
+    int uniform = ts[g0 + 1] - ts[g0];
+    for (size_t q = g0; q < g1 && uniform > 0; ++q)
+      if (ts[q + 1] - ts[q] != uniform) uniform = 0;
+    buni[b] = uniform;
+    boff[b] = coarse.size();
+    if (!uniform) gemm_coarse(ts, g0, g1, coarse);
+  }
+  int32_t *d_coarse = nullptr;
+  if (!coarse.empty()) SP_TRY(upload(coarse, &d_coarse, false));
   for (int b = 0, k0 = 0; k0 < nmax; ++b, k0 += ELIM_BLK) {
     if (fused) {
       // one launch per 64-row size class (items are sorted by n, descending),
@@ -333,14 +401,9 @@ int Factor::elim_batch(std::vector<ElimDesc> &items, int mode) {
     }
     SP_TRY(launch_elim_extract(ft, d_items, nactive_at(k0), k0, lu ? 1 : 0, stream));
     const size_t g0 = bstart[b], g1 = bstart[b + 1];
-    if (g1 > g0) {
-      // this block's descriptors; their tile numbers start at ts[g0]
-      int uniform = ts[g0 + 1] - ts[g0];
-      for (size_t q = g0; q < g1 && uniform > 0; ++q)
-        if (ts[q + 1] - ts[q] != uniform) uniform = 0;
+    if (g1 > g0)     // this block's descriptors; their tile numbers start at ts[g0]
       SP_TRY(launch_gemm(ft, d_gd + g0, d_ts + g0, int(g1 - g0), ts[g1] - ts[g0], stream, ts[g0], 0,
-                         uniform));
-    }
+                         buni[b], buni[b] ? nullptr : d_coarse + boff[b]));
   }
   return SPAND_OK;
 }

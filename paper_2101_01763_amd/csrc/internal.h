@@ -204,8 +204,14 @@ constexpr int QRCP_MAXM = 1024;    // largest interface handled by the QRCP kern
 // (the FP64 kernel reads the flags per descriptor and ignores it)
 // uniform > 0: every descriptor of the launch has that many tiles (the item
 // of a tile is found by division instead of a search of tile_start)
+// d_coarse (may be null): for c = 0 .. ceil(total_tiles / 64), the item (of
+// this launch) holding tile tile_base + 64 c, the last entry nitems - 1; it
+// narrows each workgroup's search of d_tile_start to a few items.
 int launch_gemm(FType t, const GemmDesc *d_items, const int32_t *d_tile_start, int nitems,
-                int total_tiles, hipStream_t st, int tile_base, int tmode, int uniform = 0);
+                int total_tiles, hipStream_t st, int tile_base, int tmode, int uniform = 0,
+                const int32_t *d_coarse = nullptr);
+// host: the coarse index of items [a, b) of a tile_start array (ts[a..b])
+void gemm_coarse(const std::vector<int32_t> &ts, size_t a, size_t b, std::vector<int32_t> &out);
 // src double -> dst factor type (src_is_factor = 0) or factor -> factor (1)
 int launch_copy(FType t, int src_is_factor, const CopyDesc *d_items, int n, int64_t max_elems,
                 hipStream_t st);

@@ -42,16 +42,31 @@ __device__ inline double block_sum(double v, double *red) {
 
 // ------------------------------------------------------------------ GEMM
 // 64x64 output tile per 256-thread workgroup, K step 16, 4x4 per thread.
+// Item of a tile: binary search of tile_start (absolute tile numbers),
+// narrowed first by the coarse index when there is one (coarse[c] = item of
+// tile tile_base + 64 c, c <= ntiles / 64, relative to this launch's items).
+__device__ inline int gemm_item(int tile, int tile_base, const int32_t *__restrict__ tile_start,
+                                const int32_t *__restrict__ coarse, int nitems) {
+  int lo = 0, hi = nitems;
+  if (coarse) {
+    const int c = (tile - tile_base) >> 6;
+    lo = coarse[c];
+    hi = min(nitems, coarse[c + 1] + 1);
+  }
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (tile_start[mid] <= tile) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_gemm(const GemmDesc *__restrict__ items,
                                               const int32_t *__restrict__ tile_start,
+                                              const int32_t *__restrict__ coarse,
                                               int nitems, int tile_base) {
   const int tile = tile_base + int(blockIdx.x);
-  int lo = 0, hi = nitems;
-  while (hi - lo > 1) {
-    int mid = (lo + hi) >> 1;
-    if (tile_start[mid] <= tile) lo = mid; else hi = mid;
-  }
+  const int lo = gemm_item(tile, tile_base, tile_start, coarse, nitems);
   const GemmDesc d = items[lo];
   const int t = tile - tile_start[lo];
   const int ntn = (d.N + 63) >> 6;
@@ -129,7 +144,10 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmDesc *__restrict__ items
 // accumulators start from beta*C, loaded before the first product.
 // Workgroups are dealt round-robin to the 8 XCDs; each XCD is given one
 // contiguous range of tiles so that the tiles of a matrix share its L2.
+// The register budget is set for 5 waves per SIMD: the K = 64 block updates
+// are latency-bound and gain from the extra workgroup per CU (6 spills).
 typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float __attribute__((address_space(1))) gfloat;   // global memory
 constexpr int GK = 32;
 
 __device__ inline int xcd_tile(int b, int nb) {
@@ -138,19 +156,13 @@ __device__ inline int xcd_tile(int b, int nb) {
 }
 
 template <int TA, int TB>
-__global__ __launch_bounds__(256) void k_gemm_f32_mfma(const GemmDesc *__restrict__ items,
+__global__ __launch_bounds__(256, 5) void k_gemm_f32_mfma(const GemmDesc *__restrict__ items,
                                                        const int32_t *__restrict__ tile_start,
+                                                       const int32_t *__restrict__ coarse,
                                                        int nitems, int tile_base, int uniform) {
   const int tile = tile_base + xcd_tile(int(blockIdx.x), int(gridDim.x));
-  int lo = 0, hi = nitems;
-  if (uniform > 0) {
-    lo = (tile - tile_base) / uniform;
-  } else {
-    while (hi - lo > 1) {
-      int mid = (lo + hi) >> 1;
-      if (tile_start[mid] <= tile) lo = mid; else hi = mid;
-    }
-  }
+  const int lo = uniform > 0 ? (tile - tile_base) / uniform
+                             : gemm_item(tile, tile_base, tile_start, coarse, nitems);
   const GemmDesc d = items[lo];
   const int t = tile - tile_start[lo];
   const int ntn = (d.N + 63) >> 6;
@@ -159,8 +171,10 @@ __global__ __launch_bounds__(256) void k_gemm_f32_mfma(const GemmDesc *__restric
   __shared__ float Bs[GK * 68];         // Bs[k * 68 + n]
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int wr = wid >> 1, wc = wid & 1;
-  const float *A = (const float *)d.A;
-  const float *B = (const float *)d.B;
+  // global address space and 32-bit element offsets (every operand has
+  // fewer than 2^31 elements): a scalar base and one offset register per load
+  const gfloat *A = (const gfloat *)d.A;
+  const gfloat *B = (const gfloat *)d.B;
   float ra[8], rb[8];
   auto gload = [&](int k0) {
 #pragma unroll
@@ -170,16 +184,12 @@ __global__ __launch_bounds__(256) void k_gemm_f32_mfma(const GemmDesc *__restric
       if (!TA) { mm = idx >> 5; kk = idx & 31; }
       else { kk = idx >> 6; mm = idx & 63; }
       const int gm = m0 + mm, gk = k0 + kk;
-      ra[q] = (gm < d.M && gk < d.K)
-                  ? (TA ? A[(int64_t)gk * d.lda + gm] : A[(int64_t)gm * d.lda + gk])
-                  : 0.f;
+      ra[q] = (gm < d.M && gk < d.K) ? A[TA ? gk * d.lda + gm : gm * d.lda + gk] : 0.f;
       int nn;
       if (!TB) { kk = idx >> 6; nn = idx & 63; }
       else { nn = idx >> 5; kk = idx & 31; }
       const int gn = n0 + nn, gk2 = k0 + kk;
-      rb[q] = (gn < d.N && gk2 < d.K)
-                  ? (TB ? B[(int64_t)gn * d.ldb + gk2] : B[(int64_t)gk2 * d.ldb + gn])
-                  : 0.f;
+      rb[q] = (gn < d.N && gk2 < d.K) ? B[TB ? gn * d.ldb + gk2 : gk2 * d.ldb + gn] : 0.f;
     }
   };
   auto sstore = [&]() {
@@ -197,7 +207,7 @@ __global__ __launch_bounds__(256) void k_gemm_f32_mfma(const GemmDesc *__restric
     }
   };
   gload(0);
-  float *C = (float *)d.C;
+  gfloat *C = (gfloat *)d.C;
   const int gn = n0 + wc * 32 + (lane & 31);
   const bool cin = d.alpha == 1.0 && d.beta != 0.0;
   const float al = float(d.alpha), be = float(d.beta);
@@ -205,7 +215,7 @@ __global__ __launch_bounds__(256) void k_gemm_f32_mfma(const GemmDesc *__restric
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
     const int gm = m0 + wr * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-    acc[r] = (cin && gm < d.M && gn < d.N) ? be * C[(int64_t)gm * d.ldc + gn] : 0.f;
+    acc[r] = (cin && gm < d.M && gn < d.N) ? be * C[gm * d.ldc + gn] : 0.f;
   }
   const float *ap = As + (wr * 32 + (lane & 31)) * (GK + 1) + (lane >> 5);
   const float *bp = Bs + (lane >> 5) * 68 + wc * 32 + (lane & 31);
@@ -222,7 +232,7 @@ __global__ __launch_bounds__(256) void k_gemm_f32_mfma(const GemmDesc *__restric
   for (int r = 0; r < 16; ++r) {
     const int gm = m0 + wr * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
     if (gm < d.M && gn < d.N) {
-      float *c = C + (int64_t)gm * d.ldc + gn;
+      gfloat *c = C + gm * d.ldc + gn;
       float v = acc[r];
       if (!cin) {
         v *= al;
@@ -234,20 +244,22 @@ __global__ __launch_bounds__(256) void k_gemm_f32_mfma(const GemmDesc *__restric
 }
 
 int launch_gemm(FType t, const GemmDesc *d_items, const int32_t *d_tile_start, int nitems,
-                int total_tiles, hipStream_t st, int tile_base, int tmode, int uniform) {
+                int total_tiles, hipStream_t st, int tile_base, int tmode, int uniform,
+                const int32_t *d_coarse) {
   if (nitems <= 0 || total_tiles <= 0) return SPAND_OK;
   const dim3 g(total_tiles), b(256);
   const int u = uniform;
+  const int32_t *cs = d_coarse;
   if (t == FType::F64)
-    hipLaunchKernelGGL(k_gemm<double>, g, b, 0, st, d_items, d_tile_start, nitems, tile_base);
+    hipLaunchKernelGGL(k_gemm<double>, g, b, 0, st, d_items, d_tile_start, cs, nitems, tile_base);
   else if (tmode == 0)
-    hipLaunchKernelGGL((k_gemm_f32_mfma<0, 0>), g, b, 0, st, d_items, d_tile_start, nitems, tile_base, u);
+    hipLaunchKernelGGL((k_gemm_f32_mfma<0, 0>), g, b, 0, st, d_items, d_tile_start, cs, nitems, tile_base, u);
   else if (tmode == 1)
-    hipLaunchKernelGGL((k_gemm_f32_mfma<0, 1>), g, b, 0, st, d_items, d_tile_start, nitems, tile_base, u);
+    hipLaunchKernelGGL((k_gemm_f32_mfma<0, 1>), g, b, 0, st, d_items, d_tile_start, cs, nitems, tile_base, u);
   else if (tmode == 2)
-    hipLaunchKernelGGL((k_gemm_f32_mfma<1, 0>), g, b, 0, st, d_items, d_tile_start, nitems, tile_base, u);
+    hipLaunchKernelGGL((k_gemm_f32_mfma<1, 0>), g, b, 0, st, d_items, d_tile_start, cs, nitems, tile_base, u);
   else
-    hipLaunchKernelGGL((k_gemm_f32_mfma<1, 1>), g, b, 0, st, d_items, d_tile_start, nitems, tile_base, u);
+    hipLaunchKernelGGL((k_gemm_f32_mfma<1, 1>), g, b, 0, st, d_items, d_tile_start, cs, nitems, tile_base, u);
   SP_HIP(hipGetLastError());
   return SPAND_OK;
 }
