@@ -576,6 +576,89 @@ int Factor::level0(const spand_bsr_t &A, const NDResult &nd, LevelState &S) {
   trace("L0 slots", 0);
   const size_t tsz = fsize(ft);
   const int64_t b2 = int64_t(b) * b;
+  // ---- leaves: gather A_ss, invert
+  std::vector<int> leaves;
+  for (int c = 0; c < ncl; ++c)
+    if (S.interior[c]) leaves.push_back(c);
+  std::vector<void *> Ass(ncl, nullptr), Ainv(ncl, nullptr);
+  {
+    PlanArena pt, pk;
+    std::vector<size_t> ot(ncl), ok(ncl);
+    for (int s : leaves) {
+      const int n = S.size[s];
+      if (n > ELIM_MAXN || n > GEMV_MAXC) {
+        set_error("leaf cluster of %d unknowns exceeds the kernel limit %d; use more levels", n,
+                  ELIM_MAXN);
+        return SPAND_EINVAL;
+      }
+      ot[s] = pt.add(size_t(n) * n * tsz);
+      ok[s] = pk.add(size_t(n) * ld4(n) * tsz);
+    }
+    if (!leaves.empty()) {
+      void *bt, *bk;
+      SP_TRY(dalloc(&bt, pt.total, false));
+      SP_TRY(dalloc(&bk, pk.total, true));
+      SP_HIP(hipMemsetAsync(bt, 0, pt.total, stream));
+      for (int s : leaves) {
+        Ass[s] = (char *)bt + ot[s];
+        Ainv[s] = (char *)bk + ok[s];
+      }
+    }
+  }
+  {
+    // leaf blocks first: the leaf eliminations start while the interface
+    // blocks are planned
+    std::vector<GatherItem> gi;
+    for (int s : leaves) {
+      const int n = S.size[s];
+      for (int e : cl[s].elems)
+        for (int t = h_rowptr[e]; t < h_rowptr[e + 1]; ++t) {
+          const int f = h_colind[t];
+          if (ecl[f] == s)
+            gi.push_back({(char *)Ass[s] + (size_t(epos[e]) * b * n + size_t(epos[f]) * b) * tsz, t, n});
+        }
+    }
+    mark(PH_GATHER);
+    GatherItem *d_gi;
+    SP_TRY(upload(gi, &d_gi, false));
+    SP_TRY(launch_bsr_gather(ft, A.d_val, d_gi, int(gi.size()), b, stream));
+    trace("leaf gather", 0);
+  }
+  mark(PH_LU);
+  {
+    std::vector<ElimDesc> items;
+    for (int s : leaves) {
+      ElimDesc d{};
+      d.A = Ass[s];
+      d.n = S.size[s];
+      d.ncols = d.n;
+      d.ld = d.n;
+      d.pad = s;                 // owner leaf (elim_batch reorders the items)
+      items.push_back(d);
+    }
+    SP_TRY(elim_batch(items, 0));
+    trace("elim enqueue", 0);
+    std::vector<RowGatherDesc> rg;
+    for (auto &d : items) {
+      // find the leaf whose A_ss this is
+      RowGatherDesc g{};
+      g.src = d.A;
+      g.piv = d.piv;
+      g.n = d.n;
+      g.cols = d.n;
+      g.lds = d.ld;
+      g.ldd = d.n;
+      g.colperm = 1;
+      g.ldd = ld4(d.n);
+      g.dst = Ainv[d.pad];
+      rg.push_back(g);
+    }
+    RowGatherDesc *d_rg;
+    SP_TRY(upload(rg, &d_rg, false));
+    int mr = 0;
+    for (auto &g : rg) mr = std::max(mr, g.n);
+    SP_TRY(launch_row_gather(ft, d_rg, int(rg.size()), mr, stream));
+  }
   // ---- interface-pair blocks: adjacency among separator elements + fill
   // (cluster pairs as sorted unique keys ce * ncl + cf)
   std::vector<int64_t> pairs;
@@ -624,95 +707,25 @@ int Factor::level0(const spand_bsr_t &A, const NDResult &nd, LevelState &S) {
     const int64_t key = int64_t(i) * ncl + j;
     return pblk[size_t(std::lower_bound(pairs.begin(), pairs.end(), key) - pairs.begin())];
   };
-  // ---- leaves: gather A_ss, invert
-  std::vector<int> leaves;
-  for (int c = 0; c < ncl; ++c)
-    if (S.interior[c]) leaves.push_back(c);
-  std::vector<void *> Ass(ncl, nullptr), Ainv(ncl, nullptr);
   {
-    PlanArena pt, pk;
-    std::vector<size_t> ot(ncl), ok(ncl);
-    for (int s : leaves) {
-      const int n = S.size[s];
-      if (n > ELIM_MAXN || n > GEMV_MAXC) {
-        set_error("leaf cluster of %d unknowns exceeds the kernel limit %d; use more levels", n,
-                  ELIM_MAXN);
-        return SPAND_EINVAL;
-      }
-      ot[s] = pt.add(size_t(n) * n * tsz);
-      ok[s] = pk.add(size_t(n) * ld4(n) * tsz);
-    }
-    if (!leaves.empty()) {
-      void *bt, *bk;
-      SP_TRY(dalloc(&bt, pt.total, false));
-      SP_TRY(dalloc(&bk, pk.total, true));
-      SP_HIP(hipMemsetAsync(bt, 0, pt.total, stream));
-      for (int s : leaves) {
-        Ass[s] = (char *)bt + ot[s];
-        Ainv[s] = (char *)bk + ok[s];
-      }
-    }
-  }
-  std::vector<CopyDesc> cps;
-  for (int e = 0; e < K; ++e) {
-    for (int t = h_rowptr[e]; t < h_rowptr[e + 1]; ++t) {
-      const int f = h_colind[t];
-      const int ce = ecl[e], cf = ecl[f];
-      CopyDesc d{};
-      d.src = A.d_val + t * b2;
-      d.rows = d.cols = b;
-      d.lds = b;
-      d.scale = 1.0;
-      if (ce == cf && S.interior[ce]) {
-        const int n = S.size[ce];
-        d.dst = (char *)Ass[ce] + (size_t(epos[e]) * b * n + size_t(epos[f]) * b) * tsz;
-        d.ldd = n;
-        cps.push_back(d);
-      } else if (!S.interior[ce] && !S.interior[cf]) {
+    std::vector<GatherItem> gi;
+    for (int e = 0; e < K; ++e) {
+      const int ce = ecl[e];
+      if (S.interior[ce]) continue;
+      for (int t = h_rowptr[e]; t < h_rowptr[e + 1]; ++t) {
+        const int f = h_colind[t];
+        const int cf = ecl[f];
+        if (S.interior[cf]) continue;
         const Blk &B = pair_blk(ce, cf);
-        d.dst = (char *)B.p + (size_t(epos[e]) * b * B.cols + size_t(epos[f]) * b) * tsz;
-        d.ldd = B.cols;
-        cps.push_back(d);
+        gi.push_back({(char *)B.p + (size_t(epos[e]) * b * B.cols + size_t(epos[f]) * b) * tsz, t,
+                      B.cols});
       }
     }
-  }
-  mark(PH_GATHER);
-  SP_TRY(copy_batch(cps, 0));
-  trace("gather copies", 0);
-  mark(PH_LU);
-  {
-    std::vector<ElimDesc> items;
-    for (int s : leaves) {
-      ElimDesc d{};
-      d.A = Ass[s];
-      d.n = S.size[s];
-      d.ncols = d.n;
-      d.ld = d.n;
-      d.pad = s;                 // owner leaf (elim_batch reorders the items)
-      items.push_back(d);
-    }
-    SP_TRY(elim_batch(items, 0));
-    trace("elim enqueue", 0);
-    std::vector<RowGatherDesc> rg;
-    for (auto &d : items) {
-      // find the leaf whose A_ss this is
-      RowGatherDesc g{};
-      g.src = d.A;
-      g.piv = d.piv;
-      g.n = d.n;
-      g.cols = d.n;
-      g.lds = d.ld;
-      g.ldd = d.n;
-      g.colperm = 1;
-      g.ldd = ld4(d.n);
-      g.dst = Ainv[d.pad];
-      rg.push_back(g);
-    }
-    RowGatherDesc *d_rg;
-    SP_TRY(upload(rg, &d_rg, false));
-    int mr = 0;
-    for (auto &g : rg) mr = std::max(mr, g.n);
-    SP_TRY(launch_row_gather(ft, d_rg, int(rg.size()), mr, stream));
+    mark(PH_GATHER);
+    GatherItem *d_gi;
+    SP_TRY(upload(gi, &d_gi, false));
+    SP_TRY(launch_bsr_gather(ft, A.d_val, d_gi, int(gi.size()), b, stream));
+    trace("interface gather", 0);
   }
   mark(PH_SCHUR);
   // ---- couplings (separator element e, leaf element f) per leaf
@@ -750,23 +763,20 @@ int Factor::level0(const spand_bsr_t &A, const NDResult &nd, LevelState &S) {
       ncp += coup[s].size();
     }
     if (ncp) SP_TRY(dalloc(&cb, ncp * 2 * b2 * tsz, true));
-    std::vector<CopyDesc> cc;
+    std::vector<GatherItem> cc;
+    cc.reserve(2 * ncp);
     for (int s : leaves)
       for (size_t i = 0; i < coup[s].size(); ++i) {
         const auto &c = coup[s][i];
         const size_t q = cpl0[s] + i;
-        CopyDesc d{};
-        d.rows = d.cols = b;
-        d.lds = d.ldd = b;
-        d.scale = 1.0;
-        d.src = A.d_val + c.t_ef * b2;
-        d.dst = (char *)cb + (2 * q) * b2 * tsz;
-        cc.push_back(d);
-        d.src = A.d_val + c.t_fe * b2;
-        d.dst = (char *)cb + (2 * q + 1) * b2 * tsz;
-        cc.push_back(d);
+        cc.push_back({(char *)cb + (2 * q) * b2 * tsz, int32_t(c.t_ef), b});
+        cc.push_back({(char *)cb + (2 * q + 1) * b2 * tsz, int32_t(c.t_fe), b});
       }
-    SP_TRY(copy_batch(cc, 0));
+    if (!cc.empty()) {
+      GatherItem *d_cc;
+      SP_TRY(upload(cc, &d_cc, false));
+      SP_TRY(launch_bsr_gather(ft, A.d_val, d_cc, int(cc.size()), b, stream));
+    }
     trace("coupling copies", 0);
   }
   auto cpl_ns = [&](int s, size_t i) { return (void *)((char *)cb + (2 * (cpl0[s] + i)) * b2 * tsz); };

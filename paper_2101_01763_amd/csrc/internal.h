@@ -108,6 +108,14 @@ struct CopyDesc {
   double scale;
 };
 
+// One b x b block of the BSR value array copied to dst (leading dimension
+// ldd, factor precision).
+struct GatherItem {
+  void *dst;
+  int32_t blk;
+  int32_t ldd;
+};
+
 // Panel factorisation problem (GJE / LU on an augmented row-major matrix).
 struct ElimDesc {
   void *A;          // n x ld row-major (ld >= ncols)
@@ -213,6 +221,8 @@ int launch_gemm(FType t, const GemmDesc *d_items, const int32_t *d_tile_start, i
 // host: the coarse index of items [a, b) of a tile_start array (ts[a..b])
 void gemm_coarse(const std::vector<int32_t> &ts, size_t a, size_t b, std::vector<int32_t> &out);
 // src double -> dst factor type (src_is_factor = 0) or factor -> factor (1)
+int launch_bsr_gather(FType t, const double *d_val, const GatherItem *d_items, int n, int b,
+                      hipStream_t st);
 int launch_copy(FType t, int src_is_factor, const CopyDesc *d_items, int n, int64_t max_elems,
                 hipStream_t st);
 // transposed copies (trans = 1), 32 x 32 tiles through LDS

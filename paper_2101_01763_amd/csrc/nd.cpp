@@ -17,8 +17,6 @@
 #include <algorithm>
 #include <array>
 #include <cmath>
-#include <deque>
-#include <tuple>
 
 #include "internal.h"
 
@@ -57,145 +55,124 @@ NDResult nested_dissection(int nx, int ny, bool px, bool py, int L) {
     ex[e] = e % nx;
     ey[e] = e / nx;
   }
-  std::vector<int32_t> node_of(K, -1);
-  std::vector<std::vector<int64_t>> box_at(L, std::vector<int64_t>(K, 0));
-  for (int e = 0; e < K; ++e) box_at[0][e] = 1;
-  std::map<int64_t, std::array<int, 4>> boxes;
-  boxes[1] = {0, nx, 0, ny};
-  struct Work {
-    int64_t k;
-    int d;
-    std::vector<int> V;
-  };
-  std::deque<Work> work;
-  {
-    Work w{1, 0, std::vector<int>(K)};
-    for (int e = 0; e < K; ++e) w.V[e] = e;
-    work.push_back(std::move(w));
+  // grid neighbours of every element, once (-1 = none)
+  std::vector<std::array<int, 4>> nbr(K);
+  for (int e = 0; e < K; ++e) {
+    int tmp[4], cnt;
+    grid_neighbours(nx, ny, px, py, ex[e], ey[e], tmp, cnt);
+    nbr[e] = {-1, -1, -1, -1};
+    for (int q = 0; q < cnt; ++q) nbr[e][q] = tmp[q];
   }
-  std::vector<char> inV(K, 0), insep(K, 0);
-  while (!work.empty()) {
-    Work w = std::move(work.front());
-    work.pop_front();
-    const int64_t k = w.k;
-    const int d = w.d;
-    R.node_level[k] = L - 1 - d;
-    auto bx = boxes[k];
-    int x0 = bx[0], x1 = bx[1], y0 = bx[2], y1 = bx[3];
-    if (d == L - 1) {
-      for (int v : w.V) node_of[v] = int32_t(k);
-      continue;
-    }
-    bool xsplit = (x1 - x0) >= (y1 - y0);
-    int lo = xsplit ? x0 : y0, hi = xsplit ? x1 : y1;
-    const std::vector<int> &coord = xsplit ? ex : ey;
-    int mid = lo + (hi - lo) / 2;
-    std::array<int, 4> lbox, rbox;
-    if (xsplit) {
-      lbox = {x0, mid, y0, y1};
-      rbox = {mid, x1, y0, y1};
-    } else {
-      lbox = {x0, x1, y0, mid};
-      rbox = {x0, x1, mid, y1};
-    }
-    for (int v : w.V) inV[v] = 1;
-    std::vector<int> sep;
-    for (int v : w.V) {
-      if (coord[v] < mid) continue;
-      int nb[4], cnt;
-      grid_neighbours(nx, ny, px, py, ex[v], ey[v], nb, cnt);
-      for (int q = 0; q < cnt; ++q) {
-        int u = nb[q];
-        if (inV[u] && coord[u] < mid) {
-          sep.push_back(v);
-          break;
+  // node ids are below 2^L <= 2K: dense tables indexed by node id
+  const size_t nnode = size_t(1) << L;
+  std::vector<int32_t> node_of(K, -1);
+  std::vector<int> node_lv(nnode, -1);
+  std::vector<std::array<int, 4>> boxes(nnode);
+  std::vector<std::vector<int32_t>> box_at(L, std::vector<int32_t>(K, 0));
+  for (int e = 0; e < K; ++e) box_at[0][e] = 1;
+  boxes[1] = {0, nx, 0, ny};
+  // Breadth-first over the tree.  The live set of node k is its box minus
+  // the separators of its ancestors, i.e. the elements of the box that no
+  // node has claimed yet; scanning the box row by row visits them in
+  // ascending order.
+  std::vector<int> sep;
+  for (int d = 0; d < L; ++d) {
+    const int64_t k0 = int64_t(1) << d;
+    for (int64_t k = k0; k < 2 * k0; ++k) {
+      node_lv[size_t(k)] = L - 1 - d;
+      R.node_level.emplace_hint(R.node_level.end(), k, L - 1 - d);
+      const auto bx = boxes[size_t(k)];
+      const int x0 = bx[0], x1 = bx[1], y0 = bx[2], y1 = bx[3];
+      if (d == L - 1) {
+        for (int y = y0; y < y1; ++y)
+          for (int x = x0; x < x1; ++x)
+            if (node_of[y * nx + x] < 0) node_of[y * nx + x] = int32_t(k);
+        continue;
+      }
+      const bool xsplit = (x1 - x0) >= (y1 - y0);
+      const int lo = xsplit ? x0 : y0, hi = xsplit ? x1 : y1;
+      const int mid = lo + (hi - lo) / 2;
+      auto live = [&](int f) {
+        return ex[f] >= x0 && ex[f] < x1 && ey[f] >= y0 && ey[f] < y1 && node_of[f] < 0;
+      };
+      sep.clear();
+      for (int y = y0; y < y1; ++y)
+        for (int x = x0; x < x1; ++x) {
+          const int v = y * nx + x;
+          if ((xsplit ? x : y) < mid || node_of[v] >= 0) continue;
+          for (int u : nbr[v]) {
+            if (u >= 0 && (xsplit ? ex[u] : ey[u]) < mid && live(u)) {
+              sep.push_back(v);
+              break;
+            }
+          }
         }
+      for (int v : sep) node_of[v] = int32_t(k);
+      if (xsplit) {
+        boxes[size_t(2 * k)] = {x0, mid, y0, y1};
+        boxes[size_t(2 * k + 1)] = {mid, x1, y0, y1};
+      } else {
+        boxes[size_t(2 * k)] = {x0, x1, y0, mid};
+        boxes[size_t(2 * k + 1)] = {x0, x1, mid, y1};
       }
+      // the depth-d boxes tile the grid: box k is exactly its rectangle
+      auto &bn = box_at[d + 1];
+      for (int y = y0; y < y1; ++y)
+        for (int x = x0; x < x1; ++x)
+          bn[y * nx + x] = int32_t((xsplit ? x : y) < mid ? 2 * k : 2 * k + 1);
     }
-    std::sort(sep.begin(), sep.end());
-    for (int v : sep) {
-      node_of[v] = int32_t(k);
-      insep[v] = 1;
-    }
-    Work wl{2 * k, d + 1, {}}, wr{2 * k + 1, d + 1, {}};
-    for (int v : w.V) {
-      if (coord[v] < mid)
-        wl.V.push_back(v);
-      else if (!insep[v])
-        wr.V.push_back(v);
-    }
-    for (int v : w.V) inV[v] = 0;
-    for (int v : sep) insep[v] = 0;
-    boxes[2 * k] = lbox;
-    boxes[2 * k + 1] = rbox;
-    // the depth-d boxes tile the grid: box k is exactly its rectangle
-    for (int y = y0; y < y1; ++y)
-      for (int x = x0; x < x1; ++x) {
-        const int e = y * nx + x;
-        box_at[d + 1][e] = coord[e] < mid ? 2 * k : 2 * k + 1;
-      }
-    work.push_back(std::move(wl));
-    work.push_back(std::move(wr));
   }
   R.node_of_elem = node_of;
-  // node ids are below 2^L <= 2K: dense tables instead of map lookups
-  std::vector<int> node_lv(size_t(1) << L, -1);
-  for (auto &kv : R.node_level) node_lv[size_t(kv.first)] = kv.second;
   std::vector<int> lvl(K);
   for (int e = 0; e < K; ++e) lvl[e] = node_lv[size_t(node_of[e])];
   R.levels.resize(L);
   R.children.resize(L);
   // clusters of level l: live elements grouped by (node, depth-(L-1-l) box),
-  // keys ascending, elements ascending; one sort per level of (node, box,
-  // element) triples, packed into one word when they fit (node and box ids
-  // are below 2^L <= 2K)
-  const int ebits = [&] { int b = 1; while ((int64_t(1) << b) < K) ++b; return b; }();
-  const int kbits = ebits + 1;
-  const bool packed = 2 * kbits + ebits <= 64;
-  std::map<std::pair<int64_t, int64_t>, int> prev_index;
-  std::vector<std::array<int64_t, 3>> kt;
-  std::vector<uint64_t> kw;
+  // keys ascending, elements ascending.  Two stable counting sorts over the
+  // ascending live elements (by box, then by node) give exactly that order.
+  std::vector<int32_t> cnt(nnode + 1), byb, ord;
+  std::vector<int64_t> prev_keys, keys;   // sorted cluster keys node * 2^L + box
   for (int l = 0; l < L; ++l) {
-    kt.clear();
     const auto &bl = box_at[L - 1 - l];
-    if (packed) {
-      kw.clear();
-      for (int e = 0; e < K; ++e)
-        if (lvl[e] >= l)
-          kw.push_back((((uint64_t(node_of[e]) << kbits) | uint64_t(bl[e])) << ebits) | uint64_t(e));
-      std::sort(kw.begin(), kw.end());
-      const uint64_t emask = (uint64_t(1) << ebits) - 1, bmask = (uint64_t(1) << kbits) - 1;
-      kt.resize(kw.size());
-      for (size_t q = 0; q < kw.size(); ++q)
-        kt[q] = {int64_t(kw[q] >> (ebits + kbits)), int64_t((kw[q] >> ebits) & bmask),
-                 int64_t(kw[q] & emask)};
-    } else {
-      for (int e = 0; e < K; ++e)
-        if (lvl[e] >= l) kt.push_back({int64_t(node_of[e]), bl[e], int64_t(e)});
-      std::sort(kt.begin(), kt.end());
-    }
+    byb.clear();
+    std::fill(cnt.begin(), cnt.end(), 0);
+    for (int e = 0; e < K; ++e)
+      if (lvl[e] >= l) ++cnt[size_t(bl[e]) + 1];
+    for (size_t q = 0; q < nnode; ++q) cnt[q + 1] += cnt[q];
+    byb.resize(size_t(cnt[nnode]));
+    for (int e = 0; e < K; ++e)
+      if (lvl[e] >= l) byb[size_t(cnt[size_t(bl[e])]++)] = e;
+    std::fill(cnt.begin(), cnt.end(), 0);
+    for (int e : byb) ++cnt[size_t(node_of[e]) + 1];
+    for (size_t q = 0; q < nnode; ++q) cnt[q + 1] += cnt[q];
+    ord.resize(byb.size());
+    for (int e : byb) ord[size_t(cnt[size_t(node_of[e])]++)] = e;
     std::vector<NDCluster> cl;
-    std::map<std::pair<int64_t, int64_t>, int> index;
-    for (size_t q = 0; q < kt.size();) {
+    keys.clear();
+    for (size_t q = 0; q < ord.size();) {
       NDCluster c;
-      c.node = int32_t(kt[q][0]);
-      c.box = int32_t(kt[q][1]);
-      while (q < kt.size() && kt[q][0] == c.node && kt[q][1] == c.box) c.elems.push_back(int32_t(kt[q++][2]));
+      c.node = node_of[ord[q]];
+      c.box = bl[ord[q]];
+      size_t r = q + 1;
+      while (r < ord.size() && node_of[ord[r]] == c.node && bl[ord[r]] == c.box) ++r;
+      c.elems.assign(ord.begin() + q, ord.begin() + r);
+      q = r;
       c.interior = node_lv[size_t(c.node)] == l;
-      index[{int64_t(c.node), int64_t(c.box)}] = int(cl.size());
+      keys.push_back(int64_t(c.node) * int64_t(nnode) + c.box);
       cl.push_back(std::move(c));
     }
     if (l >= 1) {
       R.children[l].resize(cl.size());
       for (size_t i = 0; i < cl.size(); ++i) {
         for (int64_t cb : {2 * int64_t(cl[i].box), 2 * int64_t(cl[i].box) + 1}) {
-          auto it = prev_index.find({int64_t(cl[i].node), cb});
-          if (it != prev_index.end()) R.children[l][i].push_back(it->second);
+          const int64_t key = int64_t(cl[i].node) * int64_t(nnode) + cb;
+          auto it = std::lower_bound(prev_keys.begin(), prev_keys.end(), key);
+          if (it != prev_keys.end() && *it == key) R.children[l][i].push_back(int(it - prev_keys.begin()));
         }
       }
     }
     R.levels[l] = std::move(cl);
-    prev_index = std::move(index);
+    prev_keys.swap(keys);
   }
   // elimination order: elements by (level of node, node, element); nodes
   // sorted once, elements bucketed per node in ascending order
@@ -203,7 +180,7 @@ NDResult nested_dissection(int nx, int ny, bool px, bool py, int L) {
   nodes.reserve(R.node_level.size());
   for (auto &kv : R.node_level) nodes.push_back({kv.second, kv.first});
   std::sort(nodes.begin(), nodes.end());
-  std::vector<int> nidx(size_t(1) << L, -1);
+  std::vector<int> nidx(nnode, -1);
   for (size_t q = 0; q < nodes.size(); ++q) nidx[size_t(nodes[q].second)] = int(q);
   std::vector<int> ncount(nodes.size() + 1, 0), enode(K);
   for (int e = 0; e < K; ++e) {
