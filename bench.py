@@ -7,10 +7,10 @@ GMRES solve (FP64 SpMV / Gram / CholQR / Hessenberg) to rtol 1e-8.
 value = N / (t_factor + t_solve) in DOF/s, inputs resident in HBM.
 
 Prints ONE JSON line.  Extra fields: the roofline of the dominant kernel
-(the rank-revealing QR: algorithmic bytes per launch from the factor's
-counters, duration from HIP events around every launch in the timed region;
-HBM traffic from the committed PMC measurement while its kernel source is
-unchanged), the SpMV roofline, a one-step comparison with the other factor
+(the rank-revealing QR, ALU-bound: algorithmic flops and bytes per launch from
+the factor's counters, duration from HIP events around every launch in the
+timed region; HBM traffic from the committed PMC measurement while its kernel
+source is unchanged), the SpMV roofline, a one-step comparison with the other factor
 precision, and the CPU oracle timed on a bounded sample of the same operator
 family.
 """
@@ -37,6 +37,9 @@ WORKLOADS = {
     "c5": (192, 2, 1e-2, 11, 5, 60),
 }
 HBM_PEAK_GBS = 8000.0
+# FP32 vector peak: 256 CUs x 4 SIMDs x 16 lanes x 2 (dual issue) x 2 (FMA)
+# x 2.4 GHz = 157.3 TFLOP/s
+ALU_F32_PEAK_TFS = 157.3
 
 
 def log(*a):
@@ -251,6 +254,8 @@ def main():
     q_avg_ms = qrcp_ms / max(qrcp_n, 1)
     q_bytes_launch = qrcp_bytes / max(qrcp_n, 1)
     q_ach = q_bytes_launch / (q_avg_ms * 1e-3) / 1e9 if qrcp_n else 0.0
+    q_flops_launch = qrcp_flops / max(qrcp_n, 1)
+    q_tfs = q_flops_launch / (q_avg_ms * 1e-3) / 1e12 if qrcp_n else 0.0
     traffic = pmc_traffic("k_qrcp")
     out = {
         "metric": "spaND factor+s-step GMRES time to rtol 1e-8, FP32- vs FP64-spaND; DOF/s",
@@ -280,15 +285,20 @@ def main():
                          ("top_size", "factor_bytes", "factor_flops", "rank_avg", "rank_max")},
         "solve_phases_ms": {"spmv": infos[-1].t_spmv_ms, "apply": infos[-1].t_apply_ms,
                             "orth": infos[-1].t_orth_ms, "other": infos[-1].t_other_ms},
+        # Arithmetic intensity of the QR (algorithmic flops over algorithmic
+        # bytes, about 60 flop/B) is above the FP32 ridge point (157.3 / 8 =
+        # 20 flop/B): the binding roof is the vector ALU, not HBM.
         "roofline": {"kernel": "k_qrcp (column-pivoted QR of [A_sn A_ns^T], all interfaces "
-                               "of one level per launch)", "bound": "hbm",
-                     "achieved": q_ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": q_ach / HBM_PEAK_GBS, "traffic": traffic,
-                     "bytes_per_launch": q_bytes_launch, "avg_launch_ms": q_avg_ms,
+                               "of one level per launch)", "bound": "alu",
+                     "achieved": q_tfs, "peak": ALU_F32_PEAK_TFS, "unit": "TFLOP/s",
+                     "frac": q_tfs / ALU_F32_PEAK_TFS, "traffic": traffic,
+                     "flops_per_launch": q_flops_launch, "avg_launch_ms": q_avg_ms,
                      "launches": qrcp_n,
+                     "algorithmic_flops": "sum over interfaces of 4mck - 2k^2(m+c) + 4k^3/3 "
+                                          "(k Householder-equivalent steps on m x c)",
+                     "bytes_per_launch": q_bytes_launch, "hbm_achieved_GBs": q_ach,
                      "algorithmic_bytes": "each W (m x ncols) read once + each Q (m x m) "
-                                          "written once, factor precision",
-                     "flops_per_launch": qrcp_flops / max(qrcp_n, 1)},
+                                          "written once, factor precision"},
         "roofline_spmv": {"kernel": "k_spmv (BSR SpMV, FP64)", "bound": "hbm",
                           "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                           "frac": achieved / HBM_PEAK_GBS, "bytes_per_launch": spmv_bytes,

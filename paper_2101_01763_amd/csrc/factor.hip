@@ -131,6 +131,9 @@ int Factor::upload_slots(const std::vector<int32_t> &v, int32_t **out) {
 int Factor::upload_level_slots(LevelState &S) {
   std::vector<int32_t> all;
   std::vector<size_t> off(S.slots.size());
+  size_t tot = 0;
+  for (const auto &v : S.slots) tot += v.size();
+  all.reserve(tot);
   for (size_t c = 0; c < S.slots.size(); ++c) {
     off[c] = all.size();
     all.insert(all.end(), S.slots[c].begin(), S.slots[c].end());
@@ -563,17 +566,10 @@ int Factor::level0(const spand_bsr_t &A, const NDResult &nd, LevelState &S) {
     }
   S.size.assign(ncl, 0);
   S.interior.assign(ncl, 0);
-  S.slots.assign(ncl, {});
   for (int c = 0; c < ncl; ++c) {
     S.interior[c] = cl[c].interior;
     S.size[c] = int(cl[c].elems.size()) * b;
-    auto &sl = S.slots[c];
-    sl.reserve(S.size[c]);
-    for (int e : cl[c].elems)
-      for (int q = 0; q < b; ++q) sl.push_back(e * b + q);
   }
-  SP_TRY(upload_level_slots(S));
-  trace("L0 slots", 0);
   const size_t tsz = fsize(ft);
   const int64_t b2 = int64_t(b) * b;
   // ---- leaves: gather A_ss, invert
@@ -659,6 +655,17 @@ int Factor::level0(const spand_bsr_t &A, const NDResult &nd, LevelState &S) {
     for (auto &g : rg) mr = std::max(mr, g.n);
     SP_TRY(launch_row_gather(ft, d_rg, int(rg.size()), mr, stream));
   }
+  // slot lists (the apply's sweeps), built while the leaves are eliminated
+  S.slots.assign(ncl, {});
+  for (int c = 0; c < ncl; ++c) {
+    auto &sl = S.slots[c];
+    sl.resize(size_t(S.size[c]));
+    size_t o = 0;
+    for (int e : cl[c].elems)
+      for (int q = 0; q < b; ++q) sl[o++] = e * b + q;
+  }
+  SP_TRY(upload_level_slots(S));
+  trace("L0 slots", 0);
   // ---- interface-pair blocks: adjacency among separator elements + fill
   // (cluster pairs as sorted unique keys ce * ncl + cf)
   std::vector<int64_t> pairs;
@@ -687,6 +694,7 @@ int Factor::level0(const spand_bsr_t &A, const NDResult &nd, LevelState &S) {
     if (!S.interior[c]) pairs.push_back(int64_t(c) * ncl + c);
   std::sort(pairs.begin(), pairs.end());
   pairs.erase(std::unique(pairs.begin(), pairs.end()), pairs.end());
+  trace("pair keys", 0);
   std::vector<Blk> pblk(pairs.size());
   {
     PlanArena pa;
@@ -703,6 +711,7 @@ int Factor::level0(const spand_bsr_t &A, const NDResult &nd, LevelState &S) {
       S.blocks.emplace_hint(S.blocks.end(), std::make_pair(i, j), pblk[q]);
     }
   }
+  trace("pair blocks", 0);
   auto pair_blk = [&](int i, int j) -> const Blk & {
     const int64_t key = int64_t(i) * ncl + j;
     return pblk[size_t(std::lower_bound(pairs.begin(), pairs.end(), key) - pairs.begin())];
@@ -811,17 +820,14 @@ int Factor::level0(const spand_bsr_t &A, const NDResult &nd, LevelState &S) {
         }
       }
     }
+    trace("schur target ids", 0);
     std::vector<SchurGroup> groups(tkey.size());
     std::vector<SchurItem> items(nitems);
     {
       int off = 0;
-      std::map<std::pair<int, int>, const Blk *> bcache;
       for (size_t id = 0; id < tkey.size(); ++id) {
         const int ea = tkey[id].first, ec = tkey[id].second;
-        const auto ck = std::make_pair(ecl[ea], ecl[ec]);
-        auto it = bcache.find(ck);
-        if (it == bcache.end()) it = bcache.emplace(ck, &S.blocks.at(ck)).first;
-        const Blk &B = *it->second;
+        const Blk &B = pair_blk(ecl[ea], ecl[ec]);
         SchurGroup &g = groups[id];
         g.target = (char *)B.p + (size_t(epos[ea]) * b * B.cols + size_t(epos[ec]) * b) * tsz;
         g.ldt = B.cols;
@@ -830,6 +836,7 @@ int Factor::level0(const spand_bsr_t &A, const NDResult &nd, LevelState &S) {
         g.item_end = g.item_begin;      // advanced while filling
       }
     }
+    trace("schur groups", 0);
     {
       size_t q = 0;
       for (int s : leaves) {
@@ -848,6 +855,7 @@ int Factor::level0(const spand_bsr_t &A, const NDResult &nd, LevelState &S) {
           }
       }
     }
+    trace("schur items", 0);
     SchurGroup *d_g;
     SchurItem *d_i;
     SP_TRY(upload(groups, &d_g, false));
