@@ -7,8 +7,9 @@
 // fresh pages.  Released blocks are kept here instead and handed out again
 // to a request of the same rounded size (best fit, at most twice the size
 // asked for).  Sizes are rounded up to 2 MiB.  The cache holds at most
-// SPAND_POOL_MB MiB (default 65536) per process; beyond that blocks go back
-// to the driver.  spand_pool_trim() returns every cached block.
+// SPAND_POOL_MB MiB per process (default: half of the first device's
+// memory); beyond that blocks go back to the driver.  spand_pool_trim()
+// returns every cached block.
 //
 // A block may be released only once no queued work uses it: every caller
 // synchronises the stream that used the block before releasing it.
@@ -35,8 +36,15 @@ Pool &pool() {
 size_t pool_cap() {
   static const size_t cap = [] {
     const char *e = std::getenv("SPAND_POOL_MB");
-    const long long mb = e ? std::atoll(e) : 65536;
-    return size_t(mb < 0 ? 0 : mb) << 20;
+    if (e) {
+      const long long mb = std::atoll(e);
+      return size_t(mb < 0 ? 0 : mb) << 20;
+    }
+    // half of the device memory: a factorization's transient scratch plus
+    // its stored factor stay cached across repeated factorizations
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) != hipSuccess || tot == 0) return size_t(65536) << 20;
+    return tot / 2;
   }();
   return cap;
 }
