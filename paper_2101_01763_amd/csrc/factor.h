@@ -134,6 +134,12 @@ struct Factor {
   int upload(const std::vector<D> &v, D **out, bool keep);
   int upload_slots(const std::vector<int32_t> &v, int32_t **out);
   int upload_level_slots(LevelState &S);
+  // Host work that only the apply needs (sweep descriptor sets): queued
+  // while the device is busy and run while the host would otherwise wait
+  // (before a rank read-back, at the end of a level and of the build).
+  std::vector<std::function<int()>> deferred;
+  void defer(std::function<int()> f) { deferred.push_back(std::move(f)); }
+  int flush_deferred();
   int gemm_batch(const std::vector<GemmDesc> &items);
   int copy_batch(const std::vector<CopyDesc> &items, int src_is_factor);
   int complete_q(const LevelState &S, const std::vector<int> &ifs,

@@ -146,6 +146,13 @@ int Factor::upload_level_slots(LevelState &S) {
   return SPAND_OK;
 }
 
+int Factor::flush_deferred() {
+  std::vector<std::function<int()>> q;
+  q.swap(deferred);
+  for (auto &f : q) SP_TRY(f());
+  return SPAND_OK;
+}
+
 // ------------------------------------------------------------------ host trace
 // SPAND_HOST_TRACE set: every planning step prints its host time to stderr
 // (diagnostics of the host/device overlap; no effect otherwise).
@@ -198,10 +205,12 @@ int Factor::gemm_batch(const std::vector<GemmDesc> &items) {
       }
   }
   start[4] = int(ord.size());
+  trace("  gemm plan", -2);
   GemmDesc *d_items;
   int32_t *d_ts;
   SP_TRY(upload(ord, &d_items, false));
   SP_TRY(upload(ts, &d_ts, false));
+  trace("  gemm upload", -2);
   int uni[4] = {0, 0, 0, 0};
   size_t coff[5] = {0, 0, 0, 0, 0};
   std::vector<int32_t> coarse;
@@ -912,16 +921,16 @@ int Factor::level0(const spand_bsr_t &A, const NDResult &nd, LevelState &S) {
     std::vector<PullGroup> G;
     std::vector<PullItem> I;
     build(fw_ns, 0, G, I, false);
-    SP_TRY(AL.fw.set(*this, G, I));
+    defer([this, &AL, G, I]() { return AL.fw.set(*this, G, I); });
     G.clear(); I.clear();
     build(bw_sn, 0, G, I, false);
-    SP_TRY(AL.bw.set(*this, G, I));
+    defer([this, &AL, G, I]() { return AL.bw.set(*this, G, I); });
     G.clear(); I.clear();
     build(fw_sn, 1, G, I, false);
-    SP_TRY(AL.tfw.set(*this, G, I));
+    defer([this, &AL, G, I]() { return AL.tfw.set(*this, G, I); });
     G.clear(); I.clear();
     build(bw_ns, 1, G, I, true);
-    SP_TRY(AL.tbw.set(*this, G, I));
+    defer([this, &AL, G, I]() { return AL.tbw.set(*this, G, I); });
     trace("pull sets", 0);
     std::vector<GemvDesc> gv;
     std::vector<const std::vector<int32_t> *> os;
@@ -936,15 +945,15 @@ int Factor::level0(const spand_bsr_t &A, const NDResult &nd, LevelState &S) {
       apply_bytes += double(S.size[s]) * S.size[s] * tsz * 2;   // A_ss^-1: both sweeps
     }
     // band height of the sweep GEMVs: autotuned once per (precision, b)
-    {
+    defer([this, &AL, gv, os]() -> int {
       void *tin;
       SP_TRY(dalloc(&tin, size_t(N) * 8, false));
       SP_HIP(hipMemsetAsync(tin, 0, size_t(N) * 8, stream));
       auto build_set = [&](int R, GemvSet &g) { return g.set(*this, gv, os, 0, R); };
       SP_TRY(autotune_gemv(ft, bs, build_set, (double *)tin, d_tbuf, stream, &gemv_rows));
-    }
-    SP_TRY(AL.inv.set(*this, gv, os, 0));
-    SP_TRY(AL.invT.set(*this, gv, os, 1));
+      SP_TRY(AL.inv.set(*this, gv, os, 0));
+      return AL.invT.set(*this, gv, os, 1);
+    });
     trace("inverse sweep sets", 0);
     apply_bytes += double(ncp) * 2 * b2 * tsz;   // A_ns forward, A_sn backward
     for (int s : leaves) flops += 2.0 * double(S.size[s]) * S.size[s] * S.size[s];
@@ -1162,8 +1171,8 @@ int Factor::eliminate_dense(int l, LevelState &S) {
     gv.push_back(d);
     os.push_back(&S.slots[s]);
   }
-  SP_TRY(AL.inv.set(*this, gv, os, 0));
-  SP_TRY(AL.invT.set(*this, gv, os, 1));
+  defer([this, &AL, gv, os]() { return AL.inv.set(*this, gv, os, 0); });
+  defer([this, &AL, gv, os]() { return AL.invT.set(*this, gv, os, 1); });
   std::map<int, std::vector<PullItem>> fw, tfw;
   std::vector<PullGroup> G;
   std::vector<PullItem> I;
@@ -1204,7 +1213,7 @@ int Factor::eliminate_dense(int l, LevelState &S) {
     g.item_end = int(I.size());
     G.push_back(g);
   }
-  SP_TRY(AL.fw.set(*this, G, I));
+  defer([this, &AL, G, I]() { return AL.fw.set(*this, G, I); });
   G.clear();
   I.clear();
   for (auto &kv : tfw) {
@@ -1216,7 +1225,7 @@ int Factor::eliminate_dense(int l, LevelState &S) {
     g.item_end = int(I.size());
     G.push_back(g);
   }
-  SP_TRY(AL.tfw.set(*this, G, I));
+  defer([this, &AL, G, I]() { return AL.tfw.set(*this, G, I); });
   G.clear();
   I.clear();
   for (int s : ints) {
@@ -1250,9 +1259,9 @@ int Factor::eliminate_dense(int l, LevelState &S) {
     if (g.item_end > g.item_begin) G.push_back(g);
     G2.push_back(g2);
   }
-  SP_TRY(AL.bw.set(*this, G, I));
+  defer([this, &AL, G, I]() { return AL.bw.set(*this, G, I); });
   trace("sweep sets", l);
-  SP_TRY(AL.tbw.set(*this, G2, I2));
+  defer([this, &AL, G2, I2]() { return AL.tbw.set(*this, G2, I2); });
   // eliminated clusters leave the trailing matrix
   for (int s : ints) {
     for (int n : nb[s]) {
@@ -1555,6 +1564,8 @@ int Factor::sparsify(int l, const NDResult &nd, LevelState &S, LevelState &Nx) {
       qrcp_events.push_back({qe0, qe1});
     }
   }
+  SP_TRY(flush_deferred());
+  trace("deferred sets", l);
   std::vector<int32_t> ks(ifs.size(), 0), kg(ifs.size(), 0);
   if (!ifs.empty()) {
     SP_HIP(hipMemcpyAsync(ks.data(), kout, ifs.size() * 4, hipMemcpyDeviceToHost, stream));
@@ -1624,10 +1635,10 @@ int Factor::sparsify(int l, const NDResult &nd, LevelState &S, LevelState &Nx) {
     }
     SP_TRY(gemm_batch(gm));
     trace("gemm", l);
-    SP_TRY(AL.F.set(*this, gf, os, 0));
-    SP_TRY(AL.B.set(*this, gb, os, 0));
-    SP_TRY(AL.FT.set(*this, gf, os, 1));
-    SP_TRY(AL.BT.set(*this, gb, os, 1));
+    defer([this, &AL, gf, os]() { return AL.F.set(*this, gf, os, 0); });
+    defer([this, &AL, gb, os]() { return AL.B.set(*this, gb, os, 0); });
+    defer([this, &AL, gf, os]() { return AL.FT.set(*this, gf, os, 1); });
+    defer([this, &AL, gb, os]() { return AL.BT.set(*this, gb, os, 1); });
     trace("compress F/B sets", l);
   }
   // ---- merge: next-level clusters from the coarse parts
@@ -1660,6 +1671,7 @@ int Factor::sparsify(int l, const NDResult &nd, LevelState &S, LevelState &Nx) {
   }
   std::sort(pkeys.begin(), pkeys.end());
   pkeys.erase(std::unique(pkeys.begin(), pkeys.end()), pkeys.end());
+  trace("parent keys", l);
   std::vector<Blk> pblk(pkeys.size());
   {
     PlanArena pk, pt;
@@ -1687,6 +1699,7 @@ int Factor::sparsify(int l, const NDResult &nd, LevelState &S, LevelState &Nx) {
       Nx.blocks.emplace_hint(Nx.blocks.end(), std::make_pair(i, j), pblk[q]);
     }
   }
+  trace("parent blocks", l);
   auto parent_blk = [&](int i, int j) -> const Blk & {
     const int64_t key = int64_t(i) * ncl1 + j;
     return pblk[size_t(std::lower_bound(pkeys.begin(), pkeys.end(), key) - pkeys.begin())];
@@ -1739,6 +1752,7 @@ int Factor::sparsify(int l, const NDResult &nd, LevelState &S, LevelState &Nx) {
       g2.push_back(h);
       flops += 2.0 * double(kk[i]) * B.cols * (B.rows + kk[j]);
     }
+    trace("pair descriptors", l);
     SP_TRY(gemm_batch(g1));
     SP_TRY(gemm_batch(g2));
     trace("gemm pair", l);
@@ -1748,6 +1762,8 @@ int Factor::sparsify(int l, const NDResult &nd, LevelState &S, LevelState &Nx) {
   }
   SP_TRY(upload_level_slots(Nx));
   trace("merge plan", l);
+  SP_TRY(flush_deferred());
+  trace("deferred sets", l);
   return SPAND_OK;
 }
 
@@ -1820,6 +1836,7 @@ int Factor::build(const spand_bsr_t &A, const spand_grid_t &g, const spand_opts_
   int tops = 0;
   for (int c = 0; c < int(S.size.size()); ++c) tops += S.size[c];
   top_size = tops;
+  SP_TRY(flush_deferred());
   mark(PH_END);
   SP_HIP(hipStreamSynchronize(stream));
   trace("sync", -1);
