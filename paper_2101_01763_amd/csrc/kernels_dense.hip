@@ -1394,13 +1394,13 @@ __global__ __launch_bounds__(256, 3) void k_qrcp(const QrcpDesc *__restrict__ it
   // dynamic LDS: u[MS], cbuf[MS] (or the two GEMM tiles, or the
   // candidates' coefficients P[MS][BQ]), the candidate
   // basis Bm[BQ][MS], the block's coordinates Cc[BQ][BQ] and av[BQ], then
-  // two lists of active column groups (GS entries each) and the candidates
+  // the list of active column groups (GS entries) and the candidates
   extern __shared__ double qsm[];
   const int ldsd = max(max(2 * MS, 2048), BQ * MS);
   double *u = qsm, *cbuf = qsm + MS;
   double *Bm = qsm + ldsd, *Cc = Bm + BQ * MS, *av = Cc + BQ * BQ;
-  int *act = reinterpret_cast<int *>(av + BQ), *act2 = act + GS;
-  int *sidx = act2 + GS;
+  int *act = reinterpret_cast<int *>(av + BQ);
+  int *sidx = act + GS;
   double *H = d.H;                  // ldw x BQ: column j of B W at H + j BQ
   __shared__ int s_j, s_nflag, s_nf, s_in;
   __shared__ double rv[4];
@@ -1510,6 +1510,9 @@ __global__ __launch_bounds__(256, 3) void k_qrcp(const QrcpDesc *__restrict__ it
   };
   // Order-preserving filter of a list of groups (src == nullptr: all groups
   // 0..n-1) into dst; returns the new length (the same on every thread).
+  // Stable compaction of the live groups; dst may be src: every thread reads
+  // its entry of a round before the round's first barrier and entries are
+  // only written at or below the position they are read from.
   auto filter = [&](const int *src, int n, int *dst) {
     int base = 0;
     for (int q0 = 0; q0 < n; q0 += 256) {
@@ -1595,10 +1598,7 @@ __global__ __launch_bounds__(256, 3) void k_qrcp(const QrcpDesc *__restrict__ it
     // keep the groups that can still hold a pivot (pruning never changes a
     // pivot: the largest norm is above the threshold whenever any is)
     if (k > 0) {
-      nact_cur = filter(act, nact_cur, act2);
-      int *t = act;
-      act = act2;
-      act2 = t;
+      nact_cur = filter(act, nact_cur, act);
       __syncthreads();
     }
     // Once at most half of the groups of the layout are live, pack the live
@@ -2011,7 +2011,7 @@ __global__ __launch_bounds__(256, 3) void k_qrcp(const QrcpDesc *__restrict__ it
 size_t qrcp_lds_bytes(int maxm, int maxgrp, int bq) {
   const size_t MS = size_t(std::max(maxm, 1)), GS = size_t(std::max(maxgrp, 1)), B = size_t(bq);
   return (std::max(std::max<size_t>(2 * MS, 2048), B * MS) + B * MS + B * B + B) * sizeof(double) +
-         (2 * GS + B) * sizeof(int);
+         (GS + B) * sizeof(int);
 }
 
 int qrcp_block_width(int maxm, int maxgrp) {
