@@ -1541,19 +1541,9 @@ __global__ __launch_bounds__(256, 3) void k_qrcp(const QrcpDesc *__restrict__ it
   // largest vn1 over the unselected columns of the live groups, ties ->
   // smallest index (the packed layouts keep the column order)
   int ncand_in = 0;               // candidates the pivot search checks against
-  auto argmax_col = [&](int nact) {
-    double bv = -1.0;
-    int bi = INT_MAX;
-    for (int qa = tid; qa < nact; qa += 256) {
-      const int g = act[qa];
-#pragma unroll
-      for (int q = 0; q < VN; ++q) {
-        const int j = g * VN + q;
-        if (sel[j]) continue;
-        const double v = vn1[j];
-        if (v > bv || (v == bv && j < bi)) { bv = v; bi = j; }
-      }
-    }
+  // block-wide maximum of the threads' (value, index) pairs: s_j, and s_in
+  // = whether it is one of the block's candidates
+  auto finish_argmax = [&](double bv, int bi) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
       const double ov = __shfl_xor(bv, o, 64);
@@ -1574,6 +1564,21 @@ __global__ __launch_bounds__(256, 3) void k_qrcp(const QrcpDesc *__restrict__ it
     }
     __syncthreads();
     return s_j;
+  };
+  auto argmax_col = [&](int nact) {
+    double bv = -1.0;
+    int bi = INT_MAX;
+    for (int qa = tid; qa < nact; qa += 256) {
+      const int g = act[qa];
+#pragma unroll
+      for (int q = 0; q < VN; ++q) {
+        const int j = g * VN + q;
+        if (sel[j]) continue;
+        const double v = vn1[j];
+        if (v > bv || (v == bv && j < bi)) { bv = v; bi = j; }
+      }
+    }
+    return finish_argmax(bv, bi);
   };
   // c[l] = b_l . x and x -= sum_l c[l] b_l for the basis rows of Bm
   auto bdots = [&](const double *x, int n, double *c) {
@@ -1818,9 +1823,10 @@ __global__ __launch_bounds__(256, 3) void k_qrcp(const QrcpDesc *__restrict__ it
     // the span of Bm and so does q_k; row k of R is then c . H for every
     // column, which downdates all norms without reading W
     int nst = 0;
+    int js_next = -1;                   // pivot found by the previous downdate
     for (;;) {
       if (k >= imax) { done = true; break; }
-      const int js = argmax_col(nact_cur);
+      const int js = js_next >= 0 ? js_next : argmax_col(nact_cur);
       if (js == INT_MAX) { done = true; break; }
       if (!s_in) break;                 // next block, with new candidates
       // coordinates of the pivot's residual against q_0..q_{k-1}, then
@@ -1863,7 +1869,10 @@ __global__ __launch_bounds__(256, 3) void k_qrcp(const QrcpDesc *__restrict__ it
       }
       __syncthreads();
       // row k of R and downdate of the norms (LAPACK's safeguard: a norm
-      // that lost too much to cancellation is recomputed below)
+      // that lost too much to cancellation is recomputed below); the next
+      // pivot search rides along on the new norms
+      double nbv = -1.0;
+      int nbi = INT_MAX;
       for (int qa = tid; qa < nact_cur; qa += 256) {
         const int g = act[qa];
         const double *hg = H + (int64_t)g * VN * BQ;
@@ -1898,9 +1907,14 @@ __global__ __launch_bounds__(256, 3) void k_qrcp(const QrcpDesc *__restrict__ it
               vn1[j] = a * sqrt(temp);
             }
           }
+          const double v = vn1[j];
+          if (v > nbv || (v == nbv && j < nbi)) { nbv = v; nbi = j; }
         }
       }
       __syncthreads();
+      // without recomputed norms the search is complete; otherwise it is
+      // repeated after the recomputation
+      js_next = s_nflag > 0 ? -1 : finish_argmax(nbv, nbi);
       if (s_nflag > 0) {
         // exact residual norms of the flagged columns against q_0..q_k
         for (;;) {
