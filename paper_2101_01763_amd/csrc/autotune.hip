@@ -1,7 +1,7 @@
 // Autotuner for the two tile-shape knobs of the hot memory-bound kernels:
 //   * BSR SpMV: lanes per scalar row (4, 8 or 16), per block size b;
-//   * preconditioner sweeps: rows per workgroup band of the GEMV (32, 64,
-//     128), per factor precision and block size.
+//   * preconditioner sweeps: rows per workgroup band of the GEMV (32 or
+//     64), per factor precision and block size.
 // Each candidate is timed with HIP events on the caller's stream on the real
 // operands (median of 3), once per key and process.  Results are kept in a
 // process-wide table and, when SPAND_AUTOTUNE_CACHE names a file, appended to
@@ -126,9 +126,12 @@ int autotune_gemv(FType t, int bs, const std::function<int(int, GemvSet &)> &bui
       return SPAND_OK;
     }
   }
+  // 128-row bands can win on the level-0 matrices timed here by a hair
+  // but lose more on the smaller matrices of the upper levels (measured at
+  // 4M unknowns: 148 ms of sweeps per solve against 140-141 for 32 or 64)
   int best = 64;
   float bt = 1e30f;
-  for (int R : {32, 64, 128}) {
+  for (int R : {32, 64}) {
     GemvSet g;
     SP_TRY(build(R, g));
     const float tm = time_median(st, [&]() {
