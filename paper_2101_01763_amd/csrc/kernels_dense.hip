@@ -1643,21 +1643,51 @@ __global__ __launch_bounds__(256, 3) void k_qrcp(const QrcpDesc *__restrict__ it
       cur_ngrp = na;
       __syncthreads();
     }
-    // (a) candidates: the BQ unselected columns of largest norm
+    // (a) candidates: the BQ unselected columns of largest norm (ties to
+    // the smaller index), in that order.  One pass keeps each thread's
+    // best BQ sorted in registers; BQ block-wide maxima over the threads'
+    // heads then pop them in order.
     ncand_in = 0;
     int ncand = 0;
-    for (int cq = 0; cq < BQ; ++cq) {
-      const int j = argmax_col(nact_cur);
-      if (j == INT_MAX) break;
-      if (tid == 0) {
-        sidx[cq] = j;
-        sel[j] = 2;          // excluded from the next search only
+    {
+      double tv[BQ];
+      int ti[BQ];
+#pragma unroll
+      for (int c = 0; c < BQ; ++c) { tv[c] = -1.0; ti[c] = INT_MAX; }
+      auto better = [](double v, int j, double w, int i) { return v > w || (v == w && j < i); };
+      for (int qa = tid; qa < nact_cur; qa += 256) {
+        const int g = act[qa];
+#pragma unroll 1
+        for (int q = 0; q < VN; ++q) {
+          const int j = g * VN + q;
+          if (sel[j]) continue;
+          const double v = vn1[j];
+          if (better(v, j, tv[BQ - 1], ti[BQ - 1])) {
+            tv[BQ - 1] = v;
+            ti[BQ - 1] = j;
+#pragma unroll
+            for (int c = BQ - 1; c > 0; --c)
+              if (better(tv[c], ti[c], tv[c - 1], ti[c - 1])) {
+                const double x = tv[c]; tv[c] = tv[c - 1]; tv[c - 1] = x;
+                const int y = ti[c]; ti[c] = ti[c - 1]; ti[c - 1] = y;
+              }
+          }
+        }
       }
-      __syncthreads();
-      ++ncand;
+      for (int cq = 0; cq < BQ; ++cq) {
+        const int j = finish_argmax(tv[0], ti[0]);
+        if (j == INT_MAX) break;
+        if (tid == 0) sidx[cq] = j;
+        if (ti[0] == j) {
+#pragma unroll
+          for (int c = 0; c + 1 < BQ; ++c) { tv[c] = tv[c + 1]; ti[c] = ti[c + 1]; }
+          tv[BQ - 1] = -1.0;
+          ti[BQ - 1] = INT_MAX;
+        }
+        ++ncand;
+      }
     }
     if (ncand == 0) break;
-    if (tid < ncand) sel[sidx[tid]] = 0;
     __syncthreads();
     // (b) their residuals against q_0..q_{k-1} (two block Gram-Schmidt
     // passes over the candidates at once; the k x BQ coefficients go
