@@ -1424,6 +1424,7 @@ int Factor::sparsify(int l, const NDResult &nd, LevelState &S, LevelState &Nx) {
       h.ldc = B.cols;
       h.alpha = 1.0;
       h.beta = 0.0;
+      h.tri = GEMM_TRI_B_UPPER;   // Uh_j^-1 is upper triangular
       g2.push_back(h);
       flops += 2.0 * double(B.rows) * B.cols * (B.rows + B.cols);
     }
@@ -1620,6 +1621,7 @@ int Factor::sparsify(int l, const NDResult &nd, LevelState &S, LevelState &Nx) {
       h.lda = h.ldb = m;
       h.ldc = ld4(m);
       h.alpha = 1.0;
+      h.tri = GEMM_TRI_A_UPPER;   // Uh^-1 is upper triangular
       gm.push_back(h);
       GemvDesc d{};
       d.islot = d.oslot = S.d_slots[s];

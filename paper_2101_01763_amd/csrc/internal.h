@@ -86,6 +86,11 @@ inline size_t fsize(FType t) { return t == FType::F64 ? 8 : 4; }
 // they are built and bounds-checked on the host, then uploaded.
 
 // C = alpha * op(A) op(B) + beta * C  (row-major, per item sizes)
+// tri: structural zeros of the operands as used in the product, which the
+// kernels skip (exactly: the skipped terms are products with zeros)
+//   GEMM_TRI_B_UPPER  op(B)(k, j) = 0 for k > j
+//   GEMM_TRI_A_UPPER  op(A)(i, k) = 0 for k < i
+constexpr int GEMM_TRI_B_UPPER = 1, GEMM_TRI_A_UPPER = 2;
 struct GemmDesc {
   const void *A;
   const void *B;
@@ -94,6 +99,7 @@ struct GemmDesc {
   int32_t lda, ldb, ldc;
   int32_t transA, transB;
   double alpha, beta;
+  int32_t tri, pad;
 };
 
 // Copy of a rows x cols sub-matrix, optional transpose, from src (type Ts)

@@ -81,7 +81,9 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmDesc *__restrict__ items
     for (int j = 0; j < 4; ++j) acc[i][j] = T(0);
   const T *A = (const T *)d.A;
   const T *B = (const T *)d.B;
-  for (int k0 = 0; k0 < d.K; k0 += 16) {
+  const int kb = (d.tri & GEMM_TRI_A_UPPER) ? min(m0, d.K) : 0;
+  const int ke = (d.tri & GEMM_TRI_B_UPPER) ? min(d.K, n0 + 64) : d.K;
+  for (int k0 = kb; k0 < ke; k0 += 16) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int idx = tid + q * 256;
@@ -206,7 +208,11 @@ __global__ __launch_bounds__(256, 5) void k_gemm_f32_mfma(const GemmDesc *__rest
       Bs[kk * 68 + nn] = rb[q];
     }
   };
-  gload(0);
+  // K range of this tile: triangular operands contribute nothing outside
+  // it (m0, n0 are multiples of 64, so the range stays in whole chunks)
+  const int kb = (d.tri & GEMM_TRI_A_UPPER) ? min(m0, d.K) : 0;
+  const int ke = (d.tri & GEMM_TRI_B_UPPER) ? min(d.K, n0 + 64) : d.K;
+  if (kb < ke) gload(kb);
   gfloat *C = (gfloat *)d.C;
   const int gn = n0 + wc * 32 + (lane & 31);
   const bool cin = d.alpha == 1.0 && d.beta != 0.0;
@@ -219,10 +225,10 @@ __global__ __launch_bounds__(256, 5) void k_gemm_f32_mfma(const GemmDesc *__rest
   }
   const float *ap = As + (wr * 32 + (lane & 31)) * (GK + 1) + (lane >> 5);
   const float *bp = Bs + (lane >> 5) * 68 + wc * 32 + (lane & 31);
-  for (int k0 = 0; k0 < d.K; k0 += GK) {
+  for (int k0 = kb; k0 < ke; k0 += GK) {
     sstore();
     __syncthreads();
-    if (k0 + GK < d.K) gload(k0 + GK);
+    if (k0 + GK < ke) gload(k0 + GK);
 #pragma unroll
     for (int kk = 0; kk < GK; kk += 2)
       acc = __builtin_amdgcn_mfma_f32_32x32x2f32(ap[kk], bp[kk * 68], acc, 0, 0, 0);
