@@ -8,8 +8,9 @@
 // to a request of the same rounded size (best fit, at most twice the size
 // asked for).  Sizes are rounded up to 2 MiB.  The cache holds at most
 // SPAND_POOL_MB MiB per process (default: half of the first device's
-// memory); beyond that blocks go back to the driver.  spand_pool_trim()
-// returns every cached block.
+// memory); beyond that blocks go back to the driver, and so does the whole
+// cache before a new block would leave less than 8 GiB of the device free.
+// spand_pool_trim() returns every cached block.
 //
 // A block may be released only once no queued work uses it: every caller
 // synchronises the stream that used the block before releasing it.
@@ -49,6 +50,7 @@ size_t pool_cap() {
   return cap;
 }
 constexpr size_t kRound = size_t(2) << 20;
+constexpr size_t kHeadroom = size_t(8) << 30;
 thread_local double t_driver_ms = 0.0;     // this thread's time in hipMalloc/hipFree
 struct DriverTimer {
   std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
@@ -80,6 +82,15 @@ int pool_alloc(void **p, size_t bytes, size_t *got) {
     }
   }
   DriverTimer tm;
+  // keep headroom on the device for allocations the library does not see
+  // (the runtime's own buffers, the caller's tensors): when a new block would
+  // leave less than kHeadroom free, the cached blocks go back to the driver
+  // first (they may be of sizes the current work never asks for)
+  {
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) == hipSuccess && fr < sz + kHeadroom && pool_cached_bytes() > 0)
+      pool_trim();
+  }
   hipError_t e = hipMalloc(p, sz);
   if (e != hipSuccess) {
     // give the cache back to the driver and try once more
