@@ -151,7 +151,9 @@ static int factor_one(const spand_bsr_t *A, const spand_grid_t *grid, const span
   (void)hipStreamDestroy(ps);
   h->F.stream = nullptr;
   if (r != SPAND_OK) return r;
-  if (graphs) SP_TRY(h->F.capture_graphs());
+  h->F.trace("build end", -1);
+  if (graphs) SP_TRY(h->F.capture_graphs(1));
+  h->F.trace("graph capture", -1);
   *out = h.release();
   return SPAND_OK;
 }
@@ -177,6 +179,7 @@ int spand_apply_T(spand_factor_t F, const double *d_in, double *d_out, void *str
     set_error("NULL argument");
     return SPAND_EINVAL;
   }
+  SP_TRY(F->F.capture_graphs(2));
   return F->F.apply(d_in, d_out, 1, (hipStream_t)stream);
 }
 
@@ -206,6 +209,7 @@ int sstep_gmres_solve(const spand_bsr_t *A, spand_factor_t M, const double *d_b,
     return SPAND_EINVAL;
   }
   if (st) std::memset(st, 0, sizeof(*st));
+  if (M && opts->transpose) SP_TRY(M->F.capture_graphs(2));
   try {
     return sstep_solve(*A, M ? &M->F : nullptr, d_b, d_x, *opts, st, (hipStream_t)stream);
   } catch (const std::exception &ex) {
@@ -356,6 +360,9 @@ int sstep_gmres_solve_batched(int32_t n, const spand_bsr_t *A, const spand_facto
     set_error("bad batched arguments");
     return SPAND_EINVAL;
   }
+  // transposed sweeps are captured here, before any worker thread exists
+  for (int i = 0; i < n; ++i)
+    if (M && M[i] && opts[i].transpose) SP_TRY(M[i]->F.capture_graphs(2));
   std::vector<int> st;
   SP_TRY(run_batched(n, (hipStream_t)stream, [&](int i, hipStream_t s) {
     return sstep_gmres_solve(&A[i], M ? M[i] : nullptr, d_b[i], d_x[i], &opts[i],

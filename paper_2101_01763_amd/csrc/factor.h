@@ -125,7 +125,7 @@ struct Factor {
   ~Factor();
   int sweeps(double *x, int transpose, hipStream_t st);
   int capture(int transpose);
-  int capture_graphs();
+  int capture_graphs(int which = 3);
   int dalloc(void **p, size_t bytes, bool keep);
   int dalloc_next(void **p, size_t bytes);
   void free_temp();

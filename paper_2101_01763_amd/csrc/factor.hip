@@ -1848,7 +1848,9 @@ int Factor::build(const spand_bsr_t &A, const spand_grid_t &g, const spand_opts_
   alloc_ms = pool_driver_ms() - drv0;
   int flag = 0;
   SP_HIP(hipMemcpy(&flag, d_flag, 4, hipMemcpyDeviceToHost));
+  trace("release + flag", -1);
   collect_events();
+  trace("timing events", -1);
   if (flag) {
     set_error("zero pivot met during the factorization");
     return SPAND_ESINGULAR;
@@ -1929,17 +1931,19 @@ int Factor::capture(int transpose) {
   return r;
 }
 
-// Both sweeps are captured once, right after the factorization, by the thread
-// that asked for it and with no worker thread of this library alive: a
-// capture never overlaps another thread's hipMalloc/hipFree/stream creation
-// issued from here.  The mutex keeps captures of concurrent host callers apart.
+// Sweeps are captured once, by a thread of the caller and with no worker
+// thread of this library alive: a capture never overlaps another thread's
+// hipMalloc/hipFree/stream creation issued from here.  The M^-1 sweep right
+// after the factorization, the M^-T sweep at the first public call that needs
+// it (batched factorizations capture both at once).  The mutex keeps
+// captures of concurrent host callers apart.  `which`: bit 0 M^-1, bit 1 M^-T.
 static std::mutex g_capture_mu;
 
-int Factor::capture_graphs() {
+int Factor::capture_graphs(int which) {
   if (!use_graphs) return SPAND_OK;
   std::lock_guard<std::mutex> lk(g_capture_mu);
   for (int t = 0; t < 2; ++t)
-    if (!gexec[t]) SP_TRY(capture(t));
+    if ((which >> t & 1) && !gexec[t]) SP_TRY(capture(t));
   return SPAND_OK;
 }
 
