@@ -251,7 +251,7 @@ int spand_nd(const spand_grid_t *grid, int32_t L, int32_t *L_out,
  * spand_pool_trim - return every device block the library keeps cached.
  * Factorizations and solves take their device memory from a per-process
  * cache of blocks (sizes rounded up to 2 MiB, at most SPAND_POOL_MB MiB
- * cached, default half of the device memory) so that repeated builds and
+ * cached, default 3/4 of the device memory) so that repeated builds and
  * solves neither call hipMalloc/hipFree again nor synchronise the device
  * for each release.
  * Blocks held by live factors are not affected.  Call with no library call

@@ -7,9 +7,9 @@
 // fresh pages.  Released blocks are kept here instead and handed out again
 // to a request of the same rounded size (best fit, at most twice the size
 // asked for).  Sizes are rounded up to 2 MiB.  The cache holds at most
-// SPAND_POOL_MB MiB per process (default: half of the first device's
-// memory); beyond that blocks go back to the driver, and so does the whole
-// cache before a new block would leave less than 8 GiB of the device free.
+// SPAND_POOL_MB MiB per process (default: three quarters of the first
+// device's memory); beyond that blocks go back to the driver, and so does the whole
+// cache before a new block would leave less than 8 GiB free.
 // spand_pool_trim() returns every cached block.
 //
 // A block may be released only once no queued work uses it: every caller
@@ -41,11 +41,13 @@ size_t pool_cap() {
       const long long mb = std::atoll(e);
       return size_t(mb < 0 ? 0 : mb) << 20;
     }
-    // half of the device memory: a factorization's transient scratch plus
-    // its stored factor stay cached across repeated factorizations
+    // three quarters of the device memory: a factorization's transient
+    // scratch plus its stored factor stay cached across repeated
+    // factorizations (FP64 at 4M unknowns peaks near 150 GB); the headroom
+    // rule below hands the cache back when others need the memory
     size_t fr = 0, tot = 0;
     if (hipMemGetInfo(&fr, &tot) != hipSuccess || tot == 0) return size_t(65536) << 20;
-    return tot / 2;
+    return tot / 4 * 3;
   }();
   return cap;
 }
@@ -85,7 +87,8 @@ int pool_alloc(void **p, size_t bytes, size_t *got) {
   // keep headroom on the device for allocations the library does not see
   // (the runtime's own buffers, the caller's tensors): when a new block would
   // leave less than kHeadroom free, the cached blocks go back to the driver
-  // first (they may be of sizes the current work never asks for)
+  // first, all at once (the first release waits for the device; the others
+  // then cost nothing more)
   {
     size_t fr = 0, tot = 0;
     if (hipMemGetInfo(&fr, &tot) == hipSuccess && fr < sz + kHeadroom && pool_cached_bytes() > 0)
