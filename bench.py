@@ -147,6 +147,58 @@ def bench_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_sweep(args):
+    """FP32-spaND + s-step GMRES (s = 5, m = 60, rtol 1e-8) on the 256x256
+    grid over one parameter; per case one untimed and one timed build."""
+    import torch
+    import paper_2101_01763_amd as sp
+    from synth.dg_euler import DGConfig, make_problem
+
+    n = 256
+    # leaves of about 600 unknowns: L = 11, 12, 13 at p = 1, 2, 3
+    lp = {1: 11, 2: 12, 3: 13}
+    if args.sweep == "eps":
+        cases = [(3, e, 13) for e in (1e-1, 1e-2, 1e-3, 1e-4)]
+    elif args.sweep == "levels":
+        cases = [(3, 1e-2, L) for L in (12, 13, 14)]   # L = 11: 4096-unknown leaves
+    else:
+        cases = [(p, 1e-2, lp[p]) for p in (1, 2, 3)]
+    probs = {}
+    for p, eps, L in cases:
+        if p not in probs:
+            cfg = DGConfig(n=n, p=p)
+            A, xs, b, _ = make_problem(cfg)
+            probs[p] = (cfg, sp.BSRMatrix.from_numpy(A.rowptr, A.colind, A.val),
+                        torch.as_tensor(b, device="cuda"), torch.as_tensor(xs, device="cuda"))
+            del A
+            log(f"generated p={p}: N={cfg.N}")
+        cfg, dA, db, dxs = probs[p]
+        try:
+            F = sp.factor(dA, n, n, True, False, eps=eps, nlevels=L, dtype="f32")
+        except sp.SpandError as ex:      # e.g. a cluster beyond the kernel limits
+            print(json.dumps({"sweep": args.sweep, "p": p, "eps": eps, "levels": L,
+                              "error": str(ex)}), flush=True)
+            continue
+        del F
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        F = sp.factor(dA, n, n, True, False, eps=eps, nlevels=L, dtype="f32")
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        x, info = sp.solve(dA, db, F, s=5, restart=60, rtol=1e-8)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        st = F.stats()
+        print(json.dumps({
+            "sweep": args.sweep, "p": p, "N": cfg.N, "eps": eps, "levels": L,
+            "t_factor_ms": 1e3 * (t1 - t0), "t_solve_ms": 1e3 * (t2 - t1),
+            "dof_per_s": cfg.N / (t2 - t0), "iters": info.iters, "relres": info.relres,
+            "rel_err_vs_xstar": float(torch.linalg.norm(x - dxs) / torch.linalg.norm(dxs)),
+            "resident_GiB": st["resident_bytes"] / 2**30, "factor_GB": st["factor_bytes"] / 1e9,
+            "rank_avg": st["rank_avg"], "rank_max": st["rank_max"]}), flush=True)
+        del F, x
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -161,6 +213,9 @@ def main():
                     help="skip the one-step FP64-factor comparison run")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (PMC byte-counter calibration)")
+    ap.add_argument("--sweep", choices=["eps", "levels", "p"], default=None,
+                    help="256x256 grid: ranks, iterations, times and memory over eps "
+                         "(1e-1..1e-4), the number of levels, or p = 1..3 (one JSON line each)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -182,6 +237,8 @@ def main():
     import paper_2101_01763_amd as sp
     from synth.dg_euler import DGConfig, make_problem
 
+    if args.sweep:
+        return bench_sweep(args)
     if args.workload == "c4":
         return bench_batch(args)
     n, p, eps, L, s, m = WORKLOADS[args.workload]
