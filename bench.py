@@ -147,6 +147,44 @@ def bench_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_basis_study(args):
+    """Stability of the s-step basis (the paper's CAGMRES study): FP32-spaND
+    preconditioned s-step GMRES (s = 5, m = 60, rtol 1e-8) on the 128x128,
+    p = 2 operator with {Newton, monomial} basis x {1, 2} passes of block CGS
+    + CholQR; ||Q^T Q - I||_F after every block, iterations and times."""
+    import torch
+    import paper_2101_01763_amd as sp
+    from synth.dg_euler import DGConfig, make_problem
+
+    n, p, eps, L, s, m = WORKLOADS["c2"]
+    cfg = DGConfig(n=n, p=p)
+    A, xs, b, _ = make_problem(cfg)
+    dA = sp.BSRMatrix.from_numpy(A.rowptr, A.colind, A.val)
+    db = torch.as_tensor(b, device="cuda")
+    dxs = torch.as_tensor(xs, device="cuda")
+    F = sp.factor(dA, n, n, True, False, eps=eps, nlevels=L, dtype="f32")
+    for monomial in (False, True):
+        for passes in (2, 1):
+            sp.solve(dA, db, F, s=s, restart=m, rtol=1e-8, monomial=monomial, passes=passes)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            x, info = sp.solve(dA, db, F, s=s, restart=m, rtol=1e-8, monomial=monomial,
+                               passes=passes)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            # the losses from a separate run (the Gram matrices are diagnostics)
+            _, info2 = sp.solve(dA, db, F, s=s, restart=m, rtol=1e-8, monomial=monomial,
+                                passes=passes, orth_loss=True)
+            print(json.dumps({
+                "sweep": "basis", "N": cfg.N, "p": p, "eps": eps, "levels": L, "s": s,
+                "restart": m, "basis": "monomial" if monomial else "newton",
+                "passes": passes, "iters": info.iters, "converged": info.converged,
+                "relres": info.relres, "t_solve_ms": 1e3 * (t1 - t0),
+                "t_orth_ms": info.t_orth_ms,
+                "rel_err_vs_xstar": float(torch.linalg.norm(x - dxs) / torch.linalg.norm(dxs)),
+                "orth_loss": info2.orth_loss}), flush=True)
+
+
 def bench_sweep(args):
     """FP32-spaND + s-step GMRES (s = 5, m = 60, rtol 1e-8) on the 256x256
     grid over one parameter; per case one untimed and one timed build."""
@@ -154,6 +192,8 @@ def bench_sweep(args):
     import paper_2101_01763_amd as sp
     from synth.dg_euler import DGConfig, make_problem
 
+    if args.sweep == "basis":
+        return bench_basis_study(args)
     n = 256
     # leaves of about 600 unknowns: L = 11, 12, 13 at p = 1, 2, 3
     lp = {1: 11, 2: 12, 3: 13}
@@ -213,9 +253,11 @@ def main():
                     help="skip the one-step FP64-factor comparison run")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (PMC byte-counter calibration)")
-    ap.add_argument("--sweep", choices=["eps", "levels", "p"], default=None,
+    ap.add_argument("--sweep", choices=["eps", "levels", "p", "basis"], default=None,
                     help="256x256 grid: ranks, iterations, times and memory over eps "
-                         "(1e-1..1e-4), the number of levels, or p = 1..3 (one JSON line each)")
+                         "(1e-1..1e-4), the number of levels, or p = 1..3; 'basis': the "
+                         "128x128 p=2 operator, Newton/monomial basis x 1/2 orthogonalisation "
+                         "passes with the loss of orthogonality per block (one JSON line each)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "

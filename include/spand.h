@@ -74,12 +74,25 @@ typedef struct {
   int32_t flags;            /* SPAND_FLAG_* bits, 0 by default               */
 } spand_opts_t;
 
+/* sstep_opts_t.flags (0: Newton basis on Leja-ordered Ritz values, two
+ * block CGS + CholQR passes, no diagnostics - the method of Sec. CAGMRES).
+ * For the stability study of the basis and the orthogonalisation (Fig. 6):
+ *   SSTEP_FLAG_MONOMIAL  all shifts zero, no Ritz steps: the monomial basis
+ *   SSTEP_FLAG_ONE_PASS  one block CGS + CholQR pass per block instead of two
+ *   SSTEP_FLAG_ORTH_LOSS record ||Q^T Q - I||_F of the basis after every block
+ *                        (a diagnostic: one Gram matrix of the whole basis per
+ *                        block, inside the timed phases as "other")          */
+#define SSTEP_FLAG_MONOMIAL 1
+#define SSTEP_FLAG_ONE_PASS 2
+#define SSTEP_FLAG_ORTH_LOSS 4
 typedef struct {
   int32_t s;                /* block size of the s-step method (1..8)        */
   int32_t restart;          /* restart length m, a multiple of s              */
   int32_t maxit;            /* maximum number of Krylov vectors              */
   int32_t transpose;        /* 1: solve A^T x = b, preconditioned by M^-T    */
   double rtol;              /* stop when ||b - A x|| <= rtol ||b||            */
+  int32_t flags;            /* SSTEP_FLAG_* bits                             */
+  int32_t pad;
 } sstep_opts_t;
 
 #define SSTEP_MAX_HIST 1024
@@ -97,6 +110,11 @@ typedef struct {
   double t_total_ms, t_spmv_ms, t_apply_ms, t_orth_ms, t_other_ms;
   int32_t n_spmv;           /* SpMV launches (t_spmv_ms covers exactly these) */
   int32_t n_apply;          /* preconditioner applications                  */
+  int32_t n_orth;           /* entries in orth_loss (SSTEP_FLAG_ORTH_LOSS)   */
+  int32_t pad;
+  double orth_loss[SSTEP_MAX_HIST]; /* ||Q^T Q - I||_F after each block, with
+                               the basis size j + s + 1 in orth_cols       */
+  int32_t orth_cols[SSTEP_MAX_HIST];
 } sstep_stats_t;
 
 #define SPAND_MAX_LEVELS 32

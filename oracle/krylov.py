@@ -261,6 +261,19 @@ def bcgs2_cholqr2(Q, W):
     return W2, R1 + R2 @ T1, T2 @ T1
 
 
+def bcgs_cholqr(Q, W):
+    """One pass of block CGS + CholQR (the single-pass variant of the
+    stability study).  Returns (Wnew, R_a, R_b) with W = Q R_a + Wnew R_b, or
+    None on breakdown."""
+    R1 = Q.T @ W
+    W1 = W - Q @ R1
+    T1 = _chol_upper(W1.T @ W1)
+    if T1 is None:
+        return None
+    W1 = np.linalg.solve(T1.T, W1.T).T
+    return W1, R1, T1
+
+
 def hessenberg_block(H, j, s, Ra, Rb, Bb):
     """Columns j..j+s-1 of the Hessenberg matrix of A_hat in the basis Q."""
     nr = j + 1 + s
@@ -276,9 +289,13 @@ def hessenberg_block(H, j, s, Ra, Rb, Bb):
 
 
 def sstep_gmres(A, b, M=None, x0=None, s=4, rtol=1e-8, restart=40, maxit=1000,
-                shifts=None, record_Q=False):
-    """s-step GMRES, right preconditioned; restart must be a multiple of s."""
+                shifts=None, record_Q=False, passes=2):
+    """s-step GMRES, right preconditioned; restart must be a multiple of s.
+    shifts = zeros gives the monomial basis; passes = 1 orthogonalises each
+    block once (block CGS + CholQR) instead of twice; record_Q keeps
+    ||Q^T Q - I||_F of the basis after every block in info.orth_err."""
     assert restart % s == 0 and restart >= s
+    assert passes in (1, 2)
     Mf = M if M is not None else (lambda v: v)
     Ahat = lambda v: A(Mf(v))
     n = b.shape[0]
@@ -336,7 +353,7 @@ def sstep_gmres(A, b, M=None, x0=None, s=4, rtol=1e-8, restart=40, maxit=1000,
         first = False
         while not done and j < m:
             W, Bb = newton_basis(Ahat, Q[:, j], slots)
-            res = bcgs2_cholqr2(Q[:, :j + 1], W)
+            res = (bcgs2_cholqr2 if passes == 2 else bcgs_cholqr)(Q[:, :j + 1], W)
             if res is None:
                 info.breakdown = True
                 done = True

@@ -47,9 +47,13 @@ class spand_opts_t(C.Structure):
                 ("flags", C.c_int32)]
 
 
+SSTEP_FLAG_MONOMIAL, SSTEP_FLAG_ONE_PASS, SSTEP_FLAG_ORTH_LOSS = 1, 2, 4
+
+
 class sstep_opts_t(C.Structure):
     _fields_ = [("s", C.c_int32), ("restart", C.c_int32), ("maxit", C.c_int32),
-                ("transpose", C.c_int32), ("rtol", C.c_double)]
+                ("transpose", C.c_int32), ("rtol", C.c_double), ("flags", C.c_int32),
+                ("pad", C.c_int32)]
 
 
 class sstep_stats_t(C.Structure):
@@ -59,7 +63,10 @@ class sstep_stats_t(C.Structure):
                 ("shift_re", C.c_double * 8), ("shift_im", C.c_double * 8),
                 ("t_total_ms", C.c_double), ("t_spmv_ms", C.c_double),
                 ("t_apply_ms", C.c_double), ("t_orth_ms", C.c_double),
-                ("t_other_ms", C.c_double), ("n_spmv", C.c_int32), ("n_apply", C.c_int32)]
+                ("t_other_ms", C.c_double), ("n_spmv", C.c_int32), ("n_apply", C.c_int32),
+                ("n_orth", C.c_int32), ("pad", C.c_int32),
+                ("orth_loss", C.c_double * SSTEP_MAX_HIST),
+                ("orth_cols", C.c_int32 * SSTEP_MAX_HIST)]
 
 
 class spand_factor_stats_t(C.Structure):
@@ -261,14 +268,21 @@ class SolveInfo:
     t_other_ms: float
     n_spmv: int
     n_apply: int
+    orth_loss: list = None      # [(basis columns, ||Q^T Q - I||_F)] with orth_loss=True
 
 
 def solve(A: BSRMatrix, b, M: Factor | None = None, s=5, restart=60, rtol=1e-8, maxit=1000,
-          transpose=False, x0=None, val=None):
-    """s-step GMRES; returns (x, SolveInfo).  ENOTCONV/EBREAKDOWN do not raise."""
+          transpose=False, x0=None, val=None, monomial=False, passes=2, orth_loss=False):
+    """s-step GMRES; returns (x, SolveInfo).  ENOTCONV/EBREAKDOWN do not raise.
+    monomial / passes=1 / orth_loss: the basis and orthogonalisation variants
+    of the stability study (SSTEP_FLAG_*)."""
     import torch
+    if passes not in (1, 2):
+        raise ValueError("passes must be 1 or 2")
     x = torch.zeros_like(b) if x0 is None else x0.clone()
-    o = sstep_opts_t(int(s), int(restart), int(maxit), int(bool(transpose)), float(rtol))
+    flags = ((SSTEP_FLAG_MONOMIAL if monomial else 0) | (SSTEP_FLAG_ONE_PASS if passes == 1 else 0)
+             | (SSTEP_FLAG_ORTH_LOSS if orth_loss else 0))
+    o = sstep_opts_t(int(s), int(restart), int(maxit), int(bool(transpose)), float(rtol), flags, 0)
     st = sstep_stats_t()
     Ac = A.c(val)
     code = lib().sstep_gmres_solve(C.byref(Ac), M._h if M is not None else None, _ptr(b),
@@ -278,7 +292,8 @@ def solve(A: BSRMatrix, b, M: Factor | None = None, s=5, restart=60, rtol=1e-8, 
                      list(st.hist[:st.n_hist]),
                      [complex(st.shift_re[i], st.shift_im[i]) for i in range(st.n_shifts)],
                      st.t_total_ms, st.t_spmv_ms, st.t_apply_ms, st.t_orth_ms, st.t_other_ms,
-                     st.n_spmv, st.n_apply)
+                     st.n_spmv, st.n_apply,
+                     [(st.orth_cols[i], st.orth_loss[i]) for i in range(st.n_orth)])
     return x, info
 
 
@@ -323,7 +338,7 @@ def solve_batched(As, bs, Ms=None, s=5, restart=60, rtol=1e-8, maxit=1000):
     Mh = (C.c_void_p * n)(*[(m._h.value if m is not None else None) for m in (Ms or [None] * n)])
     pb = (C.c_void_p * n)(*[b.data_ptr() for b in bs])
     px = (C.c_void_p * n)(*[x.data_ptr() for x in xs])
-    o = (sstep_opts_t * n)(*[sstep_opts_t(int(s), int(restart), int(maxit), 0, float(rtol))
+    o = (sstep_opts_t * n)(*[sstep_opts_t(int(s), int(restart), int(maxit), 0, float(rtol), 0, 0)
                              for _ in range(n)])
     st = (sstep_stats_t * n)()
     code = lib().sstep_gmres_solve_batched(n, Ac, Mh, pb, px, o, st, _stream())

@@ -245,6 +245,13 @@ int sstep_solve(const spand_bsr_t &A0, Factor *M, const double *b, double *x,
   const double rtol = o.rtol;
   const int maxit = o.maxit;
   const int tr = o.transpose != 0;
+  // stability-study variants (Sec. CAGMRES, Fig. 6): monomial basis, one
+  // orthogonalisation pass, loss of orthogonality after every block
+  const bool monomial = (o.flags & SSTEP_FLAG_MONOMIAL) != 0;
+  const int passes = (o.flags & SSTEP_FLAG_ONE_PASS) ? 1 : 2;
+  const bool orth_log = (o.flags & SSTEP_FLAG_ORTH_LOSS) != 0;
+  std::vector<double> orth_loss;
+  std::vector<int> orth_cols;
   std::vector<std::pair<void *, size_t>> allocs;
   auto cleanup = [&]() {
     (void)hipStreamSynchronize(stream);     // nothing queued may still use them
@@ -290,6 +297,31 @@ int sstep_solve(const spand_bsr_t &A0, Factor *M, const double *b, double *x,
   const int64_t nchunk = std::max<int64_t>(cdiv(N, TS_CHUNK), cdiv(N, 4096));
   GTRY(alloc(&pPart, size_t(nchunk) * TS_MAXA * TS_MAXS * 8));
   double *Q = (double *)pQ, *Z = (double *)pZ, *Rv = (double *)pR, *part = (double *)pPart;
+  double *Gq = nullptr;      // Gram matrix of the basis (diagnostic)
+  if (orth_log) {
+    void *pG;
+    GTRY(alloc(&pG, size_t(m + 1) * (m + 1) * 8));
+    Gq = (double *)pG;
+  }
+  // ||Q^T Q - I||_F of the first nc basis vectors: Gram matrix in column
+  // chunks of the block kernels' width, then on the host
+  auto record_orth = [&](int nc) -> int {
+    for (int c0 = 0; c0 < nc; c0 += TS_MAXS)
+      SP_TRY(launch_gram(N, Q, N, nc, Q + int64_t(c0) * N, N, std::min(TS_MAXS, nc - c0), part,
+                         Gq + c0, nc, stream));
+    std::vector<double> G(size_t(nc) * nc);
+    SP_HIP(hipMemcpyAsync(G.data(), Gq, G.size() * 8, hipMemcpyDeviceToHost, stream));
+    SP_HIP(hipStreamSynchronize(stream));
+    double f = 0.0;
+    for (int r = 0; r < nc; ++r)
+      for (int c = 0; c < nc; ++c) {
+        const double d = G[size_t(r) * nc + c] - (r == c ? 1.0 : 0.0);
+        f += d * d;
+      }
+    orth_loss.push_back(std::sqrt(f));
+    orth_cols.push_back(nc);
+    return SPAND_OK;
+  };
   if (hipMemsetAsync(Z, 0, size_t(N) * 8, stream) != hipSuccess) GTRY(SPAND_EHIP);
   GTRY(autotune_spmv(A, Z, Rv, stream));     // lanes per row, once per block size
   KrylovDev *Kd = (KrylovDev *)pK;
@@ -364,6 +396,16 @@ int sstep_solve(const spand_bsr_t &A0, Factor *M, const double *b, double *x,
     GTRY(kry_init_cycle(Kd, m, stream));
     int k = 0, j = 0;
     bool done = false;
+    if (slots.empty() && monomial) {
+      // all shifts zero: W = [A q, A^2 q, ...] from the first column on
+      slots.assign(size_t(s), Slot{0, 0.0, 0.0});
+      std::vector<double> Bb(size_t(s + 1) * s, 0.0);
+      for (int q = 1; q <= s; ++q) Bb[size_t(q) * s + q - 1] = 1.0;
+      if (hipMemcpyAsync(Kd->Bb, Bb.data(), Bb.size() * 8, hipMemcpyHostToDevice, stream) !=
+          hipSuccess)
+        GTRY(SPAND_EHIP);
+      if (hipStreamSynchronize(stream) != hipSuccess) GTRY(SPAND_EHIP);
+    }
     if (slots.empty()) {
       for (int jj = 0; jj < s; ++jj) {
         double *w = Q + (jj + 1) * N;
@@ -435,15 +477,16 @@ int sstep_solve(const spand_bsr_t &A0, Factor *M, const double *b, double *x,
       const int a = j + 1;
       double *Rp[2] = {Kd->R1, Kd->R2};
       double *Tp[2] = {Kd->T1, Kd->T2};
-      for (int pass = 0; pass < 2; ++pass) {
+      for (int pass = 0; pass < passes; ++pass) {
         GTRY(launch_gram(N, Q, N, a, W, N, s, part, Rp[pass], s, stream));
         GTRY(launch_ts_update(N, Q, N, a, Rp[pass], s, W, N, s, stream));
         GTRY(launch_gram(N, W, N, s, W, N, s, part, Kd->G, s, stream));
         GTRY(kry_chol(Kd, s, Kd->G, Tp[pass], stream));
         GTRY(launch_ts_trsm(N, W, N, s, Tp[pass], &Kd->bad, stream));
       }
-      GTRY(kry_block_finish(Kd, j, s, stream));
+      GTRY(kry_block_finish(Kd, j, s, passes, stream));
       tm.mark(T_OTHER);
+      if (orth_log) GTRY(record_orth(j + s + 1));
       std::vector<double> est(s);
       int bad = 0;
       GTRY(d2h(est.data(), Kd->est + j, size_t(s) * 8));
@@ -498,6 +541,11 @@ int sstep_solve(const spand_bsr_t &A0, Factor *M, const double *b, double *x,
     st->relres = relres;
     st->n_hist = int(std::min<size_t>(hist.size(), SSTEP_MAX_HIST));
     for (int i = 0; i < st->n_hist; ++i) st->hist[i] = hist[i];
+    st->n_orth = int(std::min<size_t>(orth_loss.size(), SSTEP_MAX_HIST));
+    for (int i = 0; i < st->n_orth; ++i) {
+      st->orth_loss[i] = orth_loss[i];
+      st->orth_cols[i] = orth_cols[i];
+    }
     st->n_shifts = int(std::min<size_t>(slots.size(), 8));
     for (int i = 0; i < st->n_shifts; ++i) {
       st->shift_re[i] = slots[i].a;

@@ -137,7 +137,9 @@ int kry_givens_col(KrylovDev *K, int j, hipStream_t st) {
 // R_a = R1 + R2 T1, R_b = T2 T1;  H[:, j:j+s] = (Rhat Bbar - [H Ctop; 0]) T^{-1}
 // with Rhat = [[e_j, R_a], [0, R_b]], Ctop = Rhat[0:j, 0:s], T = Rhat[j:j+s, 0:s];
 // then Givens rotations of the new columns.
-__global__ __launch_bounds__(256) void k_block_finish(KrylovDev *K, int j, int s) {
+// passes = 2: W = Q Ra + Wnew Rb with Ra = R1 + R2 T1, Rb = T2 T1 (block
+// CGS2 + CholQR2); passes = 1: Ra = R1, Rb = T1.
+__global__ __launch_bounds__(256) void k_block_finish(KrylovDev *K, int j, int s, int passes) {
   __shared__ double Ra[TS_MAXA * TS_MAXS];
   __shared__ double Rb[TS_MAXS * TS_MAXS];
   __shared__ double Rhat[TS_MAXA * (TS_MAXS + 1)];
@@ -147,13 +149,17 @@ __global__ __launch_bounds__(256) void k_block_finish(KrylovDev *K, int j, int s
   for (int idx = tid; idx < a * s; idx += blockDim.x) {
     const int r = idx / s, c = idx % s;
     double v = K->R1[r * s + c];
-    for (int q = 0; q <= c; ++q) v += K->R2[r * s + q] * K->T1[q * s + c];
+    if (passes == 2)
+      for (int q = 0; q <= c; ++q) v += K->R2[r * s + q] * K->T1[q * s + c];
     Ra[idx] = v;
   }
   for (int idx = tid; idx < s * s; idx += blockDim.x) {
     const int r = idx / s, c = idx % s;
     double v = 0.0;
-    for (int q = r; q <= c; ++q) v += K->T2[r * s + q] * K->T1[q * s + c];
+    if (passes == 2)
+      for (int q = r; q <= c; ++q) v += K->T2[r * s + q] * K->T1[q * s + c];
+    else
+      v = K->T1[r * s + c];
     Rb[idx] = (c >= r) ? v : 0.0;
   }
   __syncthreads();
@@ -189,8 +195,8 @@ __global__ __launch_bounds__(256) void k_block_finish(KrylovDev *K, int j, int s
     for (int c = j; c < j + s; ++c) givens_column(K, c);
 }
 
-int kry_block_finish(KrylovDev *K, int j, int s, hipStream_t st) {
-  hipLaunchKernelGGL(k_block_finish, dim3(1), dim3(256), 0, st, K, j, s);
+int kry_block_finish(KrylovDev *K, int j, int s, int passes, hipStream_t st) {
+  hipLaunchKernelGGL(k_block_finish, dim3(1), dim3(256), 0, st, K, j, s, passes);
   SP_HIP(hipGetLastError());
   return SPAND_OK;
 }

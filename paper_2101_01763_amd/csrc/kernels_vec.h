@@ -53,7 +53,7 @@ struct KrylovDev {
 
 int kry_init_cycle(KrylovDev *K, int m, hipStream_t st);                  // g = beta e0 (beta in scal[0])
 int kry_chol(KrylovDev *K, int s, double *G, double *T, hipStream_t st);  // T = chol(G)
-int kry_block_finish(KrylovDev *K, int j, int s, hipStream_t st);         // R, Hessenberg, Givens
+int kry_block_finish(KrylovDev *K, int j, int s, int passes, hipStream_t st);         // R, Hessenberg, Givens
 int kry_givens_col(KrylovDev *K, int j, hipStream_t st);                  // column j (MGS steps)
 int kry_lsq(KrylovDev *K, int k, hipStream_t st);                         // y from Rm, g
 int launch_dot(int64_t N, const double *x, const double *y, double *part, double *out,

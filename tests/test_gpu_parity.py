@@ -217,3 +217,34 @@ def test_batched_matches_individual():
         assert infos[i].converged and i1.converged
         assert infos[i].iters == i1.iters
         assert np.array_equal(_host(x1), _host(xs_b[i])), i
+
+
+@pytest.mark.parametrize("monomial,passes", [(True, 1), (True, 2), (False, 1), (False, 2)])
+def test_sstep_stability_variants(monomial, passes):
+    """Basis (Newton / monomial) x orthogonalisation passes (1 / 2) with the
+    loss of orthogonality recorded after every block, against the oracle:
+    same iterations, residual histories to 1e-6 (1e-2 with one pass, whose
+    basis is only orthogonal to the recorded loss), losses within a factor
+    of 10 where they are above rounding level."""
+    n, p, L, eps, s = 16, 1, 4, 1e-1, 5
+    cfg, A, As, xs, b, dA = _problem(n, p)
+    F = sp.factor(dA, n, n, True, False, eps=eps, nlevels=L, dtype="f64")
+    x, info = sp.solve(dA, _dev(b), F, s=s, restart=40, rtol=1e-8, monomial=monomial,
+                       passes=passes, orth_loss=True)
+    Fo = spand.factor(As, nested_dissection(n, n, True, False, L), cfg.b, eps)
+    xo, io = krylov.sstep_gmres(lambda v: As @ v, b, lambda v: spand.apply(Fo, v), s=s,
+                                rtol=1e-8, restart=40, shifts=[0.0] * s if monomial else None,
+                                record_Q=True, passes=passes)
+    assert info.converged and io.converged and info.relres <= 1e-8
+    assert info.iters == io.iters
+    np.testing.assert_allclose(info.history, io.history, rtol=1e-6 if passes == 2 else 1e-2)
+    if monomial:
+        assert all(z == 0 for z in info.shifts)
+    cols = [c for c, _ in info.orth_loss]
+    g = np.array([v for _, v in info.orth_loss])
+    o = np.array(io.orth_err)
+    assert len(g) == len(o) > 0
+    assert cols == sorted(cols) and all((c - 1) % s == 0 for c in cols)
+    big = o > 1e-10
+    assert np.all(np.abs(np.log10(g[big] / o[big])) <= 1.0)
+    assert np.all(g[~big] <= 1e-10)

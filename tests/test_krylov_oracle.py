@@ -133,3 +133,35 @@ def test_sstep_restarts_unpreconditioned():
     x, info = krylov.sstep_gmres(lambda v: As @ v, b, None, s=4, rtol=1e-8, restart=40)
     assert info.converged and info.restarts > 1
     assert np.linalg.norm(b - As @ x) <= 1e-8 * np.linalg.norm(b)
+
+
+# ---- stability-study variants (monomial basis, one orthogonalisation pass)
+
+def test_one_pass_decomposition_identity():
+    """One block CGS + CholQR pass: W = Q R_a + Wnew R_b exactly (up to
+    rounding), Wnew orthonormal, R_b upper triangular."""
+    rng = np.random.default_rng(3)
+    Q, _ = np.linalg.qr(rng.standard_normal((200, 7)))
+    W = rng.standard_normal((200, 4))
+    Wn, Ra, Rb = krylov.bcgs_cholqr(Q, W)
+    assert np.linalg.norm(Q @ Ra + Wn @ Rb - W) <= 1e-12 * np.linalg.norm(W)
+    assert np.linalg.norm(Wn.T @ Wn - np.eye(4)) <= 1e-12
+    assert np.allclose(Rb, np.triu(Rb))
+
+
+def test_two_passes_keep_orthogonality_one_pass_loses_it():
+    """The study's claim in small: on an ill-conditioned monomial basis one
+    CGS + CholQR pass leaves orders of magnitude more loss of orthogonality
+    than two; both still converge on this well-conditioned system."""
+    As, xs, b, F = _dg_problem(1e-1)
+    Af = lambda v: As @ v
+    Mf = lambda v: spand.apply(F, v)
+    zs = [0.0] * 5
+    x2, i2 = krylov.sstep_gmres(Af, b, Mf, s=5, rtol=1e-8, restart=40, shifts=zs, record_Q=True)
+    x1, i1 = krylov.sstep_gmres(Af, b, Mf, s=5, rtol=1e-8, restart=40, shifts=zs, record_Q=True,
+                                passes=1)
+    assert i2.converged and i1.converged
+    assert max(i2.orth_err) <= 1e-12
+    assert max(i1.orth_err) >= 100 * max(i2.orth_err)
+    for x in (x1, x2):
+        assert np.linalg.norm(b - As @ x) <= 1e-8 * np.linalg.norm(b)
