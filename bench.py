@@ -148,41 +148,51 @@ def bench_batch(args):
 
 
 def bench_basis_study(args):
-    """Stability of the s-step basis (the paper's CAGMRES study): FP32-spaND
-    preconditioned s-step GMRES (s = 5, m = 60, rtol 1e-8) on the 128x128,
-    p = 2 operator with {Newton, monomial} basis x {1, 2} passes of block CGS
-    + CholQR; ||Q^T Q - I||_F after every block, iterations and times."""
+    """Stability of the s-step basis (the paper's CAGMRES study) and the
+    classical-GMRES baseline: FP32-spaND preconditioned GMRES (rtol 1e-8) on
+    the 128x128, p = 2 operator with s = 5, m = 60 and {Newton, monomial}
+    basis x {1, 2} passes of block CGS + CholQR (||Q^T Q - I||_F after every
+    block), then s-step against classical GMRES (modified Gram-Schmidt) with
+    the phase times on that operator and on the 256x256, p = 3 one."""
     import torch
     import paper_2101_01763_amd as sp
     from synth.dg_euler import DGConfig, make_problem
 
-    n, p, eps, L, s, m = WORKLOADS["c2"]
-    cfg = DGConfig(n=n, p=p)
-    A, xs, b, _ = make_problem(cfg)
-    dA = sp.BSRMatrix.from_numpy(A.rowptr, A.colind, A.val)
-    db = torch.as_tensor(b, device="cuda")
-    dxs = torch.as_tensor(xs, device="cuda")
-    F = sp.factor(dA, n, n, True, False, eps=eps, nlevels=L, dtype="f32")
-    for monomial in (False, True):
-        for passes in (2, 1):
-            sp.solve(dA, db, F, s=s, restart=m, rtol=1e-8, monomial=monomial, passes=passes)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            x, info = sp.solve(dA, db, F, s=s, restart=m, rtol=1e-8, monomial=monomial,
-                               passes=passes)
-            torch.cuda.synchronize()
-            t1 = time.perf_counter()
+    def run(name, cfg, dA, db, dxs, F, s, m, **kw):
+        sp.solve(dA, db, F, s=s, restart=m, rtol=1e-8, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, info = sp.solve(dA, db, F, s=s, restart=m, rtol=1e-8, **kw)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        rec = {"sweep": "basis", "workload": name, "N": cfg.N, "s": s, "restart": m,
+               "variant": kw, "iters": info.iters, "converged": info.converged,
+               "relres": info.relres, "t_solve_ms": 1e3 * (t1 - t0),
+               "phases_ms": {"spmv": info.t_spmv_ms, "apply": info.t_apply_ms,
+                             "orth": info.t_orth_ms, "other": info.t_other_ms},
+               "rel_err_vs_xstar": float(torch.linalg.norm(x - dxs) / torch.linalg.norm(dxs))}
+        if not kw.get("classical"):
             # the losses from a separate run (the Gram matrices are diagnostics)
-            _, info2 = sp.solve(dA, db, F, s=s, restart=m, rtol=1e-8, monomial=monomial,
-                                passes=passes, orth_loss=True)
-            print(json.dumps({
-                "sweep": "basis", "N": cfg.N, "p": p, "eps": eps, "levels": L, "s": s,
-                "restart": m, "basis": "monomial" if monomial else "newton",
-                "passes": passes, "iters": info.iters, "converged": info.converged,
-                "relres": info.relres, "t_solve_ms": 1e3 * (t1 - t0),
-                "t_orth_ms": info.t_orth_ms,
-                "rel_err_vs_xstar": float(torch.linalg.norm(x - dxs) / torch.linalg.norm(dxs)),
-                "orth_loss": info2.orth_loss}), flush=True)
+            _, info2 = sp.solve(dA, db, F, s=s, restart=m, rtol=1e-8, orth_loss=True, **kw)
+            rec["orth_loss"] = info2.orth_loss
+        print(json.dumps(rec), flush=True)
+
+    for name in ("c2", "c3"):
+        n, p, eps, L, s, m = WORKLOADS[name]
+        cfg = DGConfig(n=n, p=p)
+        A, xs, b, _ = make_problem(cfg)
+        dA = sp.BSRMatrix.from_numpy(A.rowptr, A.colind, A.val)
+        del A
+        db = torch.as_tensor(b, device="cuda")
+        dxs = torch.as_tensor(xs, device="cuda")
+        F = sp.factor(dA, n, n, True, False, eps=eps, nlevels=L, dtype="f32")
+        variants = [{}, {"classical": True}]
+        if name == "c2":
+            variants = [{}, {"passes": 1}, {"monomial": True}, {"monomial": True, "passes": 1},
+                        {"classical": True}]
+        for kw in variants:
+            run(name, cfg, dA, db, dxs, F, s, m, **kw)
+        del F, dA
 
 
 def bench_sweep(args):

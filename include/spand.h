@@ -85,6 +85,10 @@ typedef struct {
 #define SSTEP_FLAG_MONOMIAL 1
 #define SSTEP_FLAG_ONE_PASS 2
 #define SSTEP_FLAG_ORTH_LOSS 4
+/*   SSTEP_FLAG_CLASSICAL classical GMRES (Algorithm 1): every column by an
+ *                        Arnoldi step with modified Gram-Schmidt, the baseline
+ *                        the s-step method is compared with (Fig. 7)         */
+#define SSTEP_FLAG_CLASSICAL 8
 typedef struct {
   int32_t s;                /* block size of the s-step method (1..8)        */
   int32_t restart;          /* restart length m, a multiple of s              */

@@ -47,7 +47,7 @@ class spand_opts_t(C.Structure):
                 ("flags", C.c_int32)]
 
 
-SSTEP_FLAG_MONOMIAL, SSTEP_FLAG_ONE_PASS, SSTEP_FLAG_ORTH_LOSS = 1, 2, 4
+SSTEP_FLAG_MONOMIAL, SSTEP_FLAG_ONE_PASS, SSTEP_FLAG_ORTH_LOSS, SSTEP_FLAG_CLASSICAL = 1, 2, 4, 8
 
 
 class sstep_opts_t(C.Structure):
@@ -272,16 +272,18 @@ class SolveInfo:
 
 
 def solve(A: BSRMatrix, b, M: Factor | None = None, s=5, restart=60, rtol=1e-8, maxit=1000,
-          transpose=False, x0=None, val=None, monomial=False, passes=2, orth_loss=False):
+          transpose=False, x0=None, val=None, monomial=False, passes=2, orth_loss=False,
+          classical=False):
     """s-step GMRES; returns (x, SolveInfo).  ENOTCONV/EBREAKDOWN do not raise.
     monomial / passes=1 / orth_loss: the basis and orthogonalisation variants
-    of the stability study (SSTEP_FLAG_*)."""
+    of the stability study; classical: GMRES with modified Gram-Schmidt
+    Arnoldi steps (the baseline; s is then unused) (SSTEP_FLAG_*)."""
     import torch
     if passes not in (1, 2):
         raise ValueError("passes must be 1 or 2")
     x = torch.zeros_like(b) if x0 is None else x0.clone()
     flags = ((SSTEP_FLAG_MONOMIAL if monomial else 0) | (SSTEP_FLAG_ONE_PASS if passes == 1 else 0)
-             | (SSTEP_FLAG_ORTH_LOSS if orth_loss else 0))
+             | (SSTEP_FLAG_ORTH_LOSS if orth_loss else 0) | (SSTEP_FLAG_CLASSICAL if classical else 0))
     o = sstep_opts_t(int(s), int(restart), int(maxit), int(bool(transpose)), float(rtol), flags, 0)
     st = sstep_stats_t()
     Ac = A.c(val)

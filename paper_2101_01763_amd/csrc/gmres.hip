@@ -250,6 +250,9 @@ int sstep_solve(const spand_bsr_t &A0, Factor *M, const double *b, double *x,
   const bool monomial = (o.flags & SSTEP_FLAG_MONOMIAL) != 0;
   const int passes = (o.flags & SSTEP_FLAG_ONE_PASS) ? 1 : 2;
   const bool orth_log = (o.flags & SSTEP_FLAG_ORTH_LOSS) != 0;
+  // classical GMRES (Algorithm 1): every column by the Arnoldi step with
+  // modified Gram-Schmidt, no blocks
+  const bool classical = (o.flags & SSTEP_FLAG_CLASSICAL) != 0;
   std::vector<double> orth_loss;
   std::vector<int> orth_cols;
   std::vector<std::pair<void *, size_t>> allocs;
@@ -396,7 +399,7 @@ int sstep_solve(const spand_bsr_t &A0, Factor *M, const double *b, double *x,
     GTRY(kry_init_cycle(Kd, m, stream));
     int k = 0, j = 0;
     bool done = false;
-    if (slots.empty() && monomial) {
+    if (slots.empty() && monomial && !classical) {
       // all shifts zero: W = [A q, A^2 q, ...] from the first column on
       slots.assign(size_t(s), Slot{0, 0.0, 0.0});
       std::vector<double> Bb(size_t(s + 1) * s, 0.0);
@@ -407,7 +410,8 @@ int sstep_solve(const spand_bsr_t &A0, Factor *M, const double *b, double *x,
       if (hipStreamSynchronize(stream) != hipSuccess) GTRY(SPAND_EHIP);
     }
     if (slots.empty()) {
-      for (int jj = 0; jj < s; ++jj) {
+      const int nsteps = classical ? m : s;
+      for (int jj = 0; jj < nsteps; ++jj) {
         double *w = Q + (jj + 1) * N;
         GTRY(Ahat(Q + jj * N, w, nullptr, 0.0, nullptr, 0.0));
         tm.mark(T_ORTH);
@@ -435,7 +439,9 @@ int sstep_solve(const spand_bsr_t &A0, Factor *M, const double *b, double *x,
       // Shifts are fixed here even when the cycle already ended inside these
       // steps (then all zero, a monomial basis): a later cycle whose true
       // residual is still above the tolerance goes straight to the blocks.
-      {
+      if (classical) {
+        done = true;            // the cycle's m columns are all Arnoldi steps
+      } else {
         std::vector<std::complex<double>> ev(s, 0.0);
         if (!done) {
           std::vector<double> Hh(size_t(s) * s);

@@ -248,3 +248,21 @@ def test_sstep_stability_variants(monomial, passes):
     big = o > 1e-10
     assert np.all(np.abs(np.log10(g[big] / o[big])) <= 1.0)
     assert np.all(g[~big] <= 1e-10)
+
+
+def test_classical_gmres_parity():
+    """SSTEP_FLAG_CLASSICAL (every column an Arnoldi step with modified
+    Gram-Schmidt) against the oracle's classical GMRES (Algorithm 1), with
+    and without restarts: same iterations, histories to 1e-6, x to 1e-10."""
+    n, p, L, eps = 16, 1, 4, 1e-1
+    cfg, A, As, xs, b, dA = _problem(n, p)
+    F = sp.factor(dA, n, n, True, False, eps=eps, nlevels=L, dtype="f64")
+    Fo = spand.factor(As, nested_dissection(n, n, True, False, L), cfg.b, eps)
+    for m in (40, 10):
+        x, info = sp.solve(dA, _dev(b), F, s=5, restart=m, rtol=1e-8, classical=True)
+        xo, io = krylov.gmres(lambda v: As @ v, b, lambda v: spand.apply(Fo, v), rtol=1e-8,
+                              restart=m)
+        assert info.converged and io.converged and info.relres <= 1e-8
+        assert info.iters == io.iters, m
+        np.testing.assert_allclose(info.history, io.history, rtol=1e-6)
+        assert np.linalg.norm(_host(x) - xo) <= 1e-10 * np.linalg.norm(xo)
