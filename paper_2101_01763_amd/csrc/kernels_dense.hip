@@ -41,8 +41,8 @@ __device__ inline double block_sum(double v, double *red) {
 }
 
 // ------------------------------------------------------------------ GEMM
-// 64x64 output tile per 256-thread workgroup, K step 16, 4x4 per thread.
-// Item of a tile: binary search of tile_start (absolute tile numbers),
+// Batched GEMMs: 64x64 output tiles, one 256-thread workgroup each (the
+// kernels below).  Item of a tile: binary search of tile_start (absolute tile numbers),
 // narrowed first by the coarse index when there is one (coarse[c] = item of
 // tile tile_base + 64 c, c <= ntiles / 64, relative to this launch's items).
 __device__ inline int gemm_item(int tile, int tile_base, const int32_t *__restrict__ tile_start,
@@ -58,83 +58,6 @@ __device__ inline int gemm_item(int tile, int tile_base, const int32_t *__restri
     if (tile_start[mid] <= tile) lo = mid; else hi = mid;
   }
   return lo;
-}
-
-template <typename T>
-__global__ __launch_bounds__(256) void k_gemm(const GemmDesc *__restrict__ items,
-                                              const int32_t *__restrict__ tile_start,
-                                              const int32_t *__restrict__ coarse,
-                                              int nitems, int tile_base) {
-  const int tile = tile_base + int(blockIdx.x);
-  const int lo = gemm_item(tile, tile_base, tile_start, coarse, nitems);
-  const GemmDesc d = items[lo];
-  const int t = tile - tile_start[lo];
-  const int ntn = (d.N + 63) >> 6;
-  const int m0 = (t / ntn) * 64, n0 = (t % ntn) * 64;
-  __shared__ T As[16][65];
-  __shared__ T Bs[16][65];
-  const int tid = threadIdx.x, tm = tid >> 4, tn = tid & 15;
-  T acc[4][4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = T(0);
-  const T *A = (const T *)d.A;
-  const T *B = (const T *)d.B;
-  const int kb = (d.tri & GEMM_TRI_A_UPPER) ? min(m0, d.K) : 0;
-  const int ke = (d.tri & GEMM_TRI_B_UPPER) ? min(d.K, n0 + 64) : d.K;
-  for (int k0 = kb; k0 < ke; k0 += 16) {
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int idx = tid + q * 256;
-      int mm, kk;
-      if (!d.transA) { mm = idx >> 4; kk = idx & 15; }
-      else { kk = idx >> 6; mm = idx & 63; }
-      const int gm = m0 + mm, gk = k0 + kk;
-      T v = T(0);
-      if (gm < d.M && gk < d.K)
-        v = d.transA ? A[(int64_t)gk * d.lda + gm] : A[(int64_t)gm * d.lda + gk];
-      As[kk][mm] = v;
-      int nn;
-      if (!d.transB) { kk = idx >> 6; nn = idx & 63; }
-      else { nn = idx >> 4; kk = idx & 15; }
-      const int gn = n0 + nn, gk2 = k0 + kk;
-      T w = T(0);
-      if (gn < d.N && gk2 < d.K)
-        w = d.transB ? B[(int64_t)gn * d.ldb + gk2] : B[(int64_t)gk2 * d.ldb + gn];
-      Bs[kk][nn] = w;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < 16; ++kk) {
-      T a[4], b[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] = As[kk][tm + 16 * i];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) b[j] = Bs[kk][tn + 16 * j];
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] += a[i] * b[j];
-    }
-    __syncthreads();
-  }
-  T *C = (T *)d.C;
-  const T al = T(d.alpha), be = T(d.beta);
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int gm = m0 + tm + 16 * i;
-    if (gm >= d.M) continue;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int gn = n0 + tn + 16 * j;
-      if (gn >= d.N) continue;
-      T *c = C + (int64_t)gm * d.ldc + gn;
-      T v = al * acc[i][j];
-      if (d.beta != 0.0) v += be * (*c);
-      *c = v;
-    }
-  }
 }
 
 // FP32 version on the matrix cores: the same 64x64 tiles, each of the four
@@ -249,6 +172,109 @@ __global__ __launch_bounds__(256, 5) void k_gemm_f32_mfma(const GemmDesc *__rest
   }
 }
 
+// FP64 version on the matrix cores: 64x64 tiles, each wave a 32x32 quarter
+// as 2x2 blocks of v_mfma_f64_16x16x4f64 (lane l holds A(l%16, k + l/16)
+// and B(k + l/16, l%16); result register r of lane l is row l/16 + 4r,
+// column l%16 of the block, checked on gfx950).  K advances in chunks of
+// 16 through LDS with register prefetch, as in the FP32 kernel.
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef double __attribute__((address_space(1))) gdouble;
+
+template <int TA, int TB>
+__global__ __launch_bounds__(256, 4) void k_gemm_f64_mfma(const GemmDesc *__restrict__ items,
+                                                       const int32_t *__restrict__ tile_start,
+                                                       const int32_t *__restrict__ coarse,
+                                                       int nitems, int tile_base, int uniform) {
+  constexpr int DK = 16, LA = DK + 1, LB = 68;
+  const int tile = tile_base + xcd_tile(int(blockIdx.x), int(gridDim.x));
+  const int lo = uniform > 0 ? (tile - tile_base) / uniform
+                             : gemm_item(tile, tile_base, tile_start, coarse, nitems);
+  const GemmDesc d = items[lo];
+  const int t = tile - tile_start[lo];
+  const int ntn = (d.N + 63) >> 6;
+  const int m0 = (t / ntn) * 64, n0 = (t % ntn) * 64;
+  __shared__ double As[64 * LA];   // As[m * LA + k]
+  __shared__ double Bs[DK * LB];   // Bs[k * LB + n]
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int wr = wid >> 1, wc = wid & 1;
+  const gdouble *A = (const gdouble *)d.A;
+  const gdouble *B = (const gdouble *)d.B;
+  double ra[4], rb[4];
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int idx = tid + q * 256;
+      int mm, kk;
+      if (!TA) { mm = idx >> 4; kk = idx & 15; }
+      else { kk = idx >> 6; mm = idx & 63; }
+      const int gm = m0 + mm, gk = k0 + kk;
+      ra[q] = (gm < d.M && gk < d.K) ? A[TA ? gk * d.lda + gm : gm * d.lda + gk] : 0.0;
+      int nn;
+      if (!TB) { kk = idx >> 6; nn = idx & 63; }
+      else { nn = idx >> 4; kk = idx & 15; }
+      const int gn = n0 + nn, gk2 = k0 + kk;
+      rb[q] = (gn < d.N && gk2 < d.K) ? B[TB ? gn * d.ldb + gk2 : gk2 * d.ldb + gn] : 0.0;
+    }
+  };
+  auto sstore = [&]() {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int idx = tid + q * 256;
+      int mm, kk;
+      if (!TA) { mm = idx >> 4; kk = idx & 15; }
+      else { kk = idx >> 6; mm = idx & 63; }
+      As[mm * LA + kk] = ra[q];
+      int nn;
+      if (!TB) { kk = idx >> 6; nn = idx & 63; }
+      else { nn = idx >> 4; kk = idx & 15; }
+      Bs[kk * LB + nn] = rb[q];
+    }
+  };
+  const int kb = (d.tri & GEMM_TRI_A_UPPER) ? min(m0, d.K) : 0;
+  const int ke = (d.tri & GEMM_TRI_B_UPPER) ? min(d.K, n0 + 64) : d.K;
+  if (kb < ke) gload(kb);
+  f64x4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
+  const double *ap = As + (wr * 32 + (lane & 15)) * LA + (lane >> 4);
+  const double *bp = Bs + (lane >> 4) * LB + wc * 32 + (lane & 15);
+  for (int k0 = kb; k0 < ke; k0 += DK) {
+    sstore();
+    __syncthreads();
+    if (k0 + DK < ke) gload(k0 + DK);
+#pragma unroll
+    for (int kk = 0; kk < DK; kk += 4) {
+      const double a0 = ap[kk], a1 = ap[16 * LA + kk];
+      const double b0 = bp[kk * LB], b1 = bp[kk * LB + 16];
+      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  gdouble *C = (gdouble *)d.C;
+  const double al = d.alpha, be = d.beta;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int gn = n0 + wc * 32 + j * 16 + (lane & 15);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gm = m0 + wr * 32 + i * 16 + (lane >> 4) + 4 * r;
+        if (gm < d.M && gn < d.N) {
+          gdouble *c = C + gm * d.ldc + gn;
+          double v = al * acc[i][j][r];
+          if (be != 0.0) v += be * (*c);
+          *c = v;
+        }
+      }
+    }
+}
+
 int launch_gemm(FType t, const GemmDesc *d_items, const int32_t *d_tile_start, int nitems,
                 int total_tiles, hipStream_t st, int tile_base, int tmode, int uniform,
                 const int32_t *d_coarse) {
@@ -256,8 +282,14 @@ int launch_gemm(FType t, const GemmDesc *d_items, const int32_t *d_tile_start, i
   const dim3 g(total_tiles), b(256);
   const int u = uniform;
   const int32_t *cs = d_coarse;
-  if (t == FType::F64)
-    hipLaunchKernelGGL(k_gemm<double>, g, b, 0, st, d_items, d_tile_start, cs, nitems, tile_base);
+  if (t == FType::F64 && tmode == 0)
+    hipLaunchKernelGGL((k_gemm_f64_mfma<0, 0>), g, b, 0, st, d_items, d_tile_start, cs, nitems, tile_base, u);
+  else if (t == FType::F64 && tmode == 1)
+    hipLaunchKernelGGL((k_gemm_f64_mfma<0, 1>), g, b, 0, st, d_items, d_tile_start, cs, nitems, tile_base, u);
+  else if (t == FType::F64 && tmode == 2)
+    hipLaunchKernelGGL((k_gemm_f64_mfma<1, 0>), g, b, 0, st, d_items, d_tile_start, cs, nitems, tile_base, u);
+  else if (t == FType::F64)
+    hipLaunchKernelGGL((k_gemm_f64_mfma<1, 1>), g, b, 0, st, d_items, d_tile_start, cs, nitems, tile_base, u);
   else if (tmode == 0)
     hipLaunchKernelGGL((k_gemm_f32_mfma<0, 0>), g, b, 0, st, d_items, d_tile_start, cs, nitems, tile_base, u);
   else if (tmode == 1)
