@@ -1186,75 +1186,6 @@ int launch_row_gather(FType t, const RowGatherDesc *d_items, int n, int max_rows
 // target(b x b) -= A1 * Y * A2 for every item of a group, items in order.
 // A1, A2: b x b copies of the coupling blocks (factor precision, ld b);
 // Y: b x b block of an interior inverse (ld ldy).
-template <typename T>
-__global__ __launch_bounds__(256) void k_schur_elem(int bs, const SchurGroup *__restrict__ groups,
-                                                    const SchurItem *__restrict__ items) {
-  const SchurGroup g = groups[blockIdx.x];
-  __shared__ T Xs[64][65];
-  __shared__ T Ys[64][65];
-  const int tid = threadIdx.x;
-  const int nq = (bs * bs + 255) / 256;
-  T *tg = (T *)g.target;
-  T acc[16];
-#pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    const int idx = tid + q * 256;
-    acc[q] = (q < nq && idx < bs * bs) ? tg[(int64_t)(idx / bs) * g.ldt + idx % bs] : T(0);
-  }
-  for (int it = g.item_begin; it < g.item_end; ++it) {
-    const SchurItem s = items[it];
-    const T *a1 = (const T *)s.A1;
-    const T *a2 = (const T *)s.A2;
-    const T *Y = (const T *)s.Y;
-    for (int idx = tid; idx < bs * bs; idx += 256) {
-      const int r = idx / bs, c = idx % bs;
-      Xs[r][c] = a1[idx];
-      Ys[r][c] = Y[(int64_t)r * s.ldy + c];
-    }
-    __syncthreads();
-    T t1[16];
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int idx = tid + q * 256;
-      T v = T(0);
-      if (q < nq && idx < bs * bs) {
-        const int r = idx / bs, c = idx % bs;
-        for (int kk = 0; kk < bs; ++kk) v += Xs[r][kk] * Ys[kk][c];
-      }
-      t1[q] = v;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int idx = tid + q * 256;
-      if (q < nq && idx < bs * bs) Xs[idx / bs][idx % bs] = t1[q];
-    }
-    for (int idx = tid; idx < bs * bs; idx += 256) Ys[idx / bs][idx % bs] = a2[idx];
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int idx = tid + q * 256;
-      if (q < nq && idx < bs * bs) {
-        const int r = idx / bs, c = idx % bs;
-        T v = T(0);
-        for (int kk = 0; kk < bs; ++kk) v += Xs[r][kk] * Ys[kk][c];
-        acc[q] -= v;
-      }
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    const int idx = tid + q * 256;
-    if (q < nq && idx < bs * bs) tg[(int64_t)(idx / bs) * g.ldt + idx % bs] = acc[q];
-  }
-}
-
-// FP32 on the matrix cores: the target (zero-padded to 64 x 64) stays in
-// the accumulators of the four waves (a 32 x 32 quarter each, the lane
-// layout of k_gemm_f32_mfma) for all its items.  Per item: T1 = A1 Y
-// (64^3 on v_mfma_f32_32x32x2f32 from LDS), -T1 back to LDS over A1, A2
-// over Y, then acc += (-T1) A2.
 __global__ __launch_bounds__(256) void k_schur_elem_mfma(int bs, const SchurGroup *__restrict__ groups,
                                                          const SchurItem *__restrict__ items) {
   constexpr int LS = 65;
@@ -1318,6 +1249,100 @@ __global__ __launch_bounds__(256) void k_schur_elem_mfma(int bs, const SchurGrou
   }
 }
 
+// FP64 version on the matrix cores: the same two products per coupling pair
+// with v_mfma_f64_16x16x4f64, each wave a 32x32 quarter as 2x2 blocks of
+// 16x16 (layout as in k_gemm_f64_mfma); the target stays in the
+// accumulators for all its pairs.
+__global__ __launch_bounds__(256) void k_schur_elem_mfma64(int bs, const SchurGroup *__restrict__ groups,
+                                                           const SchurItem *__restrict__ items) {
+  constexpr int LS = 65;
+  const SchurGroup g = groups[blockIdx.x];
+  __shared__ double L0[64 * LS];     // A1 (row-major), then -T1
+  __shared__ double L1[64 * LS];     // Y, then A2 (both [k][n])
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int wr = wid >> 1, wc = wid & 1;
+  const int kmax = (bs + 3) & ~3;
+  double *tg = (double *)g.target;
+  f64x4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int col = wc * 32 + j * 16 + (lane & 15);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = wr * 32 + i * 16 + (lane >> 4) + 4 * r;
+        acc[i][j][r] = (row < bs && col < bs) ? tg[(int64_t)row * g.ldt + col] : 0.0;
+      }
+    }
+  // zero padding rows/columns stay zero in both tiles
+  for (int e = tid; e < 64 * LS; e += 256) {
+    L0[e] = 0.0;
+    L1[e] = 0.0;
+  }
+  __syncthreads();
+  const double *ap = L0 + (wr * 32 + (lane & 15)) * LS + (lane >> 4);
+  const double *bp = L1 + (lane >> 4) * LS + wc * 32 + (lane & 15);
+  auto product = [&](f64x4 (&c)[2][2]) {
+    for (int kk = 0; kk < kmax; kk += 4) {
+      const double a0 = ap[kk], a1 = ap[16 * LS + kk];
+      const double b0 = bp[kk * LS], b1 = bp[kk * LS + 16];
+      c[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, c[0][0], 0, 0, 0);
+      c[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, c[0][1], 0, 0, 0);
+      c[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, c[1][0], 0, 0, 0);
+      c[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, c[1][1], 0, 0, 0);
+    }
+  };
+  for (int it = g.item_begin; it < g.item_end; ++it) {
+    const SchurItem s = items[it];
+    const double *a1 = (const double *)s.A1;
+    const double *a2 = (const double *)s.A2;
+    const double *Y = (const double *)s.Y;
+    for (int idx = tid; idx < bs * bs; idx += 256) {
+      const int r = idx / bs, c = idx - r * bs;
+      L0[r * LS + c] = a1[idx];
+      L1[r * LS + c] = Y[(int64_t)r * s.ldy + c];
+    }
+    __syncthreads();
+    f64x4 t1[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) t1[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
+    product(t1);
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int col = wc * 32 + j * 16 + (lane & 15);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = wr * 32 + i * 16 + (lane >> 4) + 4 * r;
+          L0[row * LS + col] = (row < bs && col < bs) ? -t1[i][j][r] : 0.0;
+        }
+      }
+    for (int idx = tid; idx < bs * bs; idx += 256) {
+      const int r = idx / bs, c = idx - r * bs;
+      L1[r * LS + c] = a2[idx];
+    }
+    __syncthreads();
+    product(acc);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int col = wc * 32 + j * 16 + (lane & 15);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = wr * 32 + i * 16 + (lane >> 4) + 4 * r;
+        if (row < bs && col < bs) tg[(int64_t)row * g.ldt + col] = acc[i][j][r];
+      }
+    }
+}
+
 int launch_schur_elem(FType t, int bs, const SchurGroup *d_groups, int ngroups,
                       const SchurItem *d_items, hipStream_t st) {
   if (ngroups <= 0) return SPAND_OK;
@@ -1326,7 +1351,7 @@ int launch_schur_elem(FType t, int bs, const SchurGroup *d_groups, int ngroups,
     return SPAND_EINVAL;
   }
   if (t == FType::F64)
-    hipLaunchKernelGGL(k_schur_elem<double>, dim3(ngroups), dim3(256), 0, st, bs, d_groups, d_items);
+    hipLaunchKernelGGL(k_schur_elem_mfma64, dim3(ngroups), dim3(256), 0, st, bs, d_groups, d_items);
   else
     hipLaunchKernelGGL(k_schur_elem_mfma, dim3(ngroups), dim3(256), 0, st, bs, d_groups, d_items);
   SP_HIP(hipGetLastError());
