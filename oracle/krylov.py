@@ -26,11 +26,24 @@ Readings where the paper is silent:
     log-distances to the chosen values; ties -> larger real part, then
     larger imaginary part; a value with Im > 0 is followed by its
     conjugate; if the last slot would split a pair its real part is used;
-  * the two passes are not lagged (block CGS2 + CholQR2); the Hessenberg
-    columns of a block are recovered from the change-of-basis matrix and
-    the orthogonalisation coefficients:
+  * by default the two passes are not lagged (block CGS2 + CholQR2); the
+    Hessenberg columns of a block are recovered from the change-of-basis
+    matrix and the orthogonalisation coefficients:
       H[:, j:j+s] = (Rhat Bbar - [H[0:j+1, 0:j] Rhat[0:j, 0:s]; 0]) T^{-1},
-    Rhat = [[e_j, R_a], [0, R_b]], T = Rhat[j:j+s, 0:s].
+    Rhat = [[rho, R_a], [0, R_b]], T = Rhat[j:j+s, 0:s], where rho holds
+    the coefficients of the block's starting vector on Q[:, 0:j+1] (e_j
+    when it is the final basis vector q_j);
+  * lagged=True is Algorithm 2's single-reduce schedule: the operator
+    applications of a block start from the last vector of the previous
+    block after its first pass only; one Gram matrix
+    Q[:, 0:j+s+1]^T [P, W] then gives the second pass of the previous block
+    P (re-orthogonalisation and re-normalisation), its Hessenberg columns,
+    the Givens rotations and the convergence check, and the first pass of
+    the new block W against the re-orthogonalised basis (the coefficients
+    on the new P are T^{-T}(P^T W - R_1^T Q_old^T W), its Gram matrix
+    W^T W - C^T C); the last block of a cycle gets its second pass from a
+    reduction of its own.  In exact arithmetic the basis, the Hessenberg
+    matrix and the residual history are those of the non-lagged schedule.
 """
 from __future__ import annotations
 
@@ -274,11 +287,16 @@ def bcgs_cholqr(Q, W):
     return W1, R1, T1
 
 
-def hessenberg_block(H, j, s, Ra, Rb, Bb):
-    """Columns j..j+s-1 of the Hessenberg matrix of A_hat in the basis Q."""
+def hessenberg_block(H, j, s, Ra, Rb, Bb, rho=None):
+    """Columns j..j+s-1 of the Hessenberg matrix of A_hat in the basis Q.
+    rho: coefficients of the block's starting vector on Q[:, 0:j+1]
+    (default e_j, the starting vector is q_j itself)."""
     nr = j + 1 + s
     Rhat = np.zeros((nr, s + 1))
-    Rhat[j, 0] = 1.0
+    if rho is None:
+        Rhat[j, 0] = 1.0
+    else:
+        Rhat[:j + 1, 0] = rho
     Rhat[:j + 1, 1:] = Ra
     Rhat[j + 1:, 1:] = Rb
     RB = Rhat @ Bb
@@ -288,14 +306,60 @@ def hessenberg_block(H, j, s, Ra, Rb, Bb):
     return np.linalg.solve(T.T, RB.T).T          # RB T^{-1}
 
 
+class LagStep:
+    """Coefficients of one single-reduce step: P = Q_old R1 + Phat T (second
+    pass of the previous block) and W = Q[:, 0:a+sp] C + What RV (first pass
+    of the new block).  Any of them is None when absent or on breakdown."""
+
+    def __init__(self):
+        self.R1 = self.T = self.C = self.RV = None
+
+
+def lagged_reduce_step(Q, a, sp, sw):
+    """One step of Algorithm 2's single-reduce orthogonalisation, in place.
+
+    Q[:, 0:a] is final and orthonormal, Q[:, a:a+sp] the previous block after
+    its first pass (sp = 0 in the first block of a cycle) and Q[:, a+sp:a+sp+sw]
+    the new block from the operator applications (sw = 0 for the second pass
+    of the last block of a cycle).  The only inner products taken are the
+    single Gram matrix G = Q[:, 0:a+sp+sw]^T Q[:, a:a+sp+sw]; everything else
+    follows from it.  Breakdown (a Gram matrix that is not positive definite)
+    leaves the corresponding coefficients None."""
+    st = LagStep()
+    G = Q[:, :a + sp + sw].T @ Q[:, a:a + sp + sw]          # the single reduction
+    if sp:
+        R1 = G[:a, :sp]
+        T = _chol_upper(G[a:a + sp, :sp] - R1.T @ R1)       # Gram of P - Q_old R1
+        if T is None:
+            return st
+        st.R1, st.T = R1, T
+        P1 = Q[:, a:a + sp] - Q[:, :a] @ R1                 # re-orthogonalise
+        Q[:, a:a + sp] = np.linalg.solve(T.T, P1.T).T       # re-normalise
+    if sw:
+        C = G[:a, sp:]
+        if sp:
+            # coefficients on the re-orthogonalised P from the same Gram matrix
+            CP = np.linalg.solve(st.T.T, G[a:a + sp, sp:] - st.R1.T @ C)
+            C = np.vstack([C, CP])
+        RV = _chol_upper(G[a + sp:, sp:] - C.T @ C)
+        if RV is None:
+            return st
+        st.C, st.RV = C, RV
+        W1 = Q[:, a + sp:a + sp + sw] - Q[:, :a + sp] @ C   # orthogonalise (one pass)
+        Q[:, a + sp:a + sp + sw] = np.linalg.solve(RV.T, W1.T).T
+    return st
+
+
 def sstep_gmres(A, b, M=None, x0=None, s=4, rtol=1e-8, restart=40, maxit=1000,
-                shifts=None, record_Q=False, passes=2):
+                shifts=None, record_Q=False, passes=2, lagged=False):
     """s-step GMRES, right preconditioned; restart must be a multiple of s.
     shifts = zeros gives the monomial basis; passes = 1 orthogonalises each
-    block once (block CGS + CholQR) instead of twice; record_Q keeps
-    ||Q^T Q - I||_F of the basis after every block in info.orth_err."""
+    block once (block CGS + CholQR) instead of twice; lagged = True uses the
+    single-reduce schedule (second pass lagged by one block); record_Q keeps
+    ||Q^T Q - I||_F of the final basis after every block in info.orth_err."""
     assert restart % s == 0 and restart >= s
     assert passes in (1, 2)
+    assert not (lagged and passes == 1)
     Mf = M if M is not None else (lambda v: v)
     Ahat = lambda v: A(Mf(v))
     n = b.shape[0]
@@ -351,7 +415,49 @@ def sstep_gmres(A, b, M=None, x0=None, s=4, rtol=1e-8, restart=40, maxit=1000,
             slots = shift_slots(shifts)
             j = s
         first = False
-        while not done and j < m:
+        pend = None      # (j0, R_a, R_b, rho) of the block in Q[:, j0+1:j0+s+1]
+        while lagged and not done:
+            sw = s if j < m else 0
+            if pend is None and sw == 0:
+                break
+            if sw:
+                W, Bb = newton_basis(Ahat, Q[:, j], slots)
+                Q[:, j + 1:j + s + 1] = W
+            sp = s if pend is not None else 0
+            st = lagged_reduce_step(Q, j + 1 - sp, sp, sw)
+            if sp:
+                if st.T is None:
+                    info.breakdown = True
+                    k = pend[0]
+                    break
+                j0, Ra0, Rb0, rho0 = pend
+                H[:j0 + s + 1, j0:j0 + s] = hessenberg_block(
+                    H, j0, s, Ra0 + st.R1 @ Rb0, st.T @ Rb0, Bb, rho0)
+                if record_Q:
+                    nq = j0 + s + 1
+                    orth_err.append(np.linalg.norm(Q[:, :nq].T @ Q[:, :nq] - np.eye(nq)))
+                for c in range(j0, j0 + s):
+                    info.iters += 1
+                    est = lsq.add_column(c, H[:c + 2, c])
+                    info.history.append(est)
+                    k = c + 1
+                    if est <= tol or info.iters >= maxit:
+                        done = True
+                        break
+            if done or not sw:
+                pend = None
+                continue
+            if st.RV is None:
+                info.breakdown = True
+                break
+            if sp:
+                rho = np.concatenate([st.R1[:, -1], st.T[:, -1]])
+            else:
+                rho = np.zeros(j + 1)
+                rho[j] = 1.0
+            pend = (j, st.C, st.RV, rho)
+            j += s
+        while not lagged and not done and j < m:
             W, Bb = newton_basis(Ahat, Q[:, j], slots)
             res = (bcgs2_cholqr2 if passes == 2 else bcgs_cholqr)(Q[:, :j + 1], W)
             if res is None:

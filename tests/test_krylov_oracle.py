@@ -165,3 +165,75 @@ def test_two_passes_keep_orthogonality_one_pass_loses_it():
     assert max(i1.orth_err) >= 100 * max(i2.orth_err)
     for x in (x1, x2):
         assert np.linalg.norm(b - As @ x) <= 1e-8 * np.linalg.norm(b)
+
+
+# ---- single-reduce schedule (Algorithm 2, second pass lagged by one block)
+
+def test_lagged_step_identities():
+    """One single-reduce step, checked by rebuilding its inputs from its
+    outputs: P = Q_old R1 + Phat T, W = [Q_old, Phat] C + What RV, the whole
+    basis orthonormal, T and RV upper triangular."""
+    rng = np.random.default_rng(11)
+    n, a, s = 300, 9, 4
+    Qo, _ = np.linalg.qr(rng.standard_normal((n, a)))
+    # a previous block after one pass: orthonormal, slightly off Q_old
+    P, _ = np.linalg.qr(rng.standard_normal((n, s)) - Qo @ (Qo.T @ rng.standard_normal((n, s))))
+    P = P + 1e-6 * Qo @ rng.standard_normal((a, s))
+    W = rng.standard_normal((n, s))
+    Q = np.hstack([Qo, P, W])
+    P0, W0 = P.copy(), W.copy()
+    st = krylov.lagged_reduce_step(Q, a, s, s)
+    assert st.T is not None and st.RV is not None
+    assert np.linalg.norm(Qo @ st.R1 + Q[:, a:a + s] @ st.T - P0) <= 1e-13 * np.linalg.norm(P0)
+    assert np.linalg.norm(Q[:, :a + s] @ st.C + Q[:, a + s:] @ st.RV - W0) \
+        <= 1e-12 * np.linalg.norm(W0)
+    assert np.linalg.norm(Q.T @ Q - np.eye(a + 2 * s)) <= 1e-12
+    assert np.allclose(st.T, np.triu(st.T)) and np.allclose(st.RV, np.triu(st.RV))
+    # the end-of-cycle step (no new block) and the first step (no previous one)
+    Q2 = np.hstack([Qo, P0])
+    st2 = krylov.lagged_reduce_step(Q2, a, s, 0)
+    assert st2.C is None and np.allclose(st2.T, st.T, rtol=1e-12, atol=1e-14)
+    Q3 = np.hstack([Qo, W0])
+    st3 = krylov.lagged_reduce_step(Q3, a, 0, s)
+    assert np.linalg.norm(Qo @ st3.C + Q3[:, a:] @ st3.RV - W0) <= 1e-12 * np.linalg.norm(W0)
+    assert np.linalg.norm(Q3.T @ Q3 - np.eye(a + s)) <= 1e-12
+
+
+@pytest.mark.parametrize("s", [2, 4, 5])
+def test_lagged_history_matches_two_pass_and_classical(s):
+    """In exact arithmetic the lagged schedule yields the basis, Hessenberg
+    matrix and residual history of the non-lagged one, and s-step GMRES
+    those of classical GMRES."""
+    As, xs, b, F = _dg_problem(1e-1)
+    Af = lambda v: As @ v
+    Mf = lambda v: spand.apply(F, v)
+    _, i1 = krylov.gmres(Af, b, Mf, rtol=1e-8, restart=40)
+    _, i2 = krylov.sstep_gmres(Af, b, Mf, s=s, rtol=1e-8, restart=40)
+    x3, i3 = krylov.sstep_gmres(Af, b, Mf, s=s, rtol=1e-8, restart=40, lagged=True,
+                                record_Q=True)
+    assert i3.converged and i3.iters == i2.iters and abs(i3.iters - i1.iters) <= 1
+    h1, h2, h3 = (np.array(i.history) for i in (i1, i2, i3))
+    nn = min(len(h1), len(h3))
+    assert np.max(np.abs(h3 - h2) / h2) <= 1e-7
+    assert np.max(np.abs(h3[:nn] - h1[:nn]) / h1[:nn]) <= 1e-6
+    assert max(i3.orth_err) <= 1e-12
+    assert np.linalg.norm(b - As @ x3) <= 1e-8 * np.linalg.norm(b)
+
+
+def test_lagged_restarts_and_monomial():
+    """Restarted cycles (the last block of each gets its own second pass) and
+    the monomial basis under the lagged schedule."""
+    As, xs, b, F = _dg_problem()
+    x, info = krylov.sstep_gmres(lambda v: As @ v, b, None, s=4, rtol=1e-8, restart=40,
+                                 lagged=True)
+    _, ref = krylov.sstep_gmres(lambda v: As @ v, b, None, s=4, rtol=1e-8, restart=40)
+    assert info.converged and info.restarts > 1 and info.restarts == ref.restarts
+    assert abs(info.iters - ref.iters) <= 1
+    assert np.linalg.norm(b - As @ x) <= 1e-8 * np.linalg.norm(b)
+    As2, xs2, b2, F2 = _dg_problem(1e-1)
+    Mf = lambda v: spand.apply(F2, v)
+    zs = [0.0] * 5
+    x2, i2 = krylov.sstep_gmres(lambda v: As2 @ v, b2, Mf, s=5, rtol=1e-8, restart=40,
+                                shifts=zs, lagged=True, record_Q=True)
+    assert i2.converged and max(i2.orth_err) <= 1e-12
+    assert np.linalg.norm(b2 - As2 @ x2) <= 1e-8 * np.linalg.norm(b2)
