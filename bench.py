@@ -167,6 +167,7 @@ def bench_basis_study(args):
         t1 = time.perf_counter()
         rec = {"sweep": "basis", "workload": name, "N": cfg.N, "s": s, "restart": m,
                "variant": kw, "iters": info.iters, "converged": info.converged,
+               "n_reduce": info.n_reduce,
                "relres": info.relres, "t_solve_ms": 1e3 * (t1 - t0),
                "phases_ms": {"spmv": info.t_spmv_ms, "apply": info.t_apply_ms,
                              "orth": info.t_orth_ms, "other": info.t_other_ms},
@@ -186,10 +187,10 @@ def bench_basis_study(args):
         db = torch.as_tensor(b, device="cuda")
         dxs = torch.as_tensor(xs, device="cuda")
         F = sp.factor(dA, n, n, True, False, eps=eps, nlevels=L, dtype="f32")
-        variants = [{}, {"classical": True}]
+        variants = [{}, {"lagged": True}, {"classical": True}]
         if name == "c2":
             variants = [{}, {"passes": 1}, {"monomial": True}, {"monomial": True, "passes": 1},
-                        {"classical": True}]
+                        {"lagged": True}, {"monomial": True, "lagged": True}, {"classical": True}]
         for kw in variants:
             run(name, cfg, dA, db, dxs, F, s, m, **kw)
         del F, dA
@@ -258,6 +259,9 @@ def main():
     ap.add_argument("--dtype", default="f32", choices=["f32", "f64"])
     ap.add_argument("--levels", type=int, default=0)
     ap.add_argument("--eps", type=float, default=None)
+    ap.add_argument("--schedule", default="two-pass", choices=["two-pass", "lagged"],
+                    help="s-step orthogonalisation: two passes per block, or the "
+                         "single-reduce schedule with the second pass lagged")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the one-step FP64-factor comparison run")
@@ -313,7 +317,8 @@ def main():
         F = sp.factor(dA, n, n, True, False, eps=eps, nlevels=L, dtype=args.dtype)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        x, info = sp.solve(dA, db, F, s=s, restart=m, rtol=1e-8)
+        x, info = sp.solve(dA, db, F, s=s, restart=m, rtol=1e-8,
+                           lagged=args.schedule == "lagged")
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         return F, x, info, t1 - t0, t2 - t1
@@ -381,9 +386,10 @@ def main():
         "data": "synthetic (seeded DG-Euler Jacobian, x* ~ N(0,1), b = A x*)",
         "config": {
             "workload": f"DG-Euler {n}x{n} p={p} (b={bsz}, N={cfg.N}, nnzb={nnzb}); "
-                        f"spaND eps={eps} L={L} {args.dtype}; s-step GMRES s={s} m={m} rtol=1e-8",
+                        f"spaND eps={eps} L={L} {args.dtype}; s-step GMRES s={s} m={m} rtol=1e-8"
+                        f" ({args.schedule})",
             "n": n, "p": p, "N": cfg.N, "eps": eps, "levels": L, "s": s, "restart": m,
-            "factor_dtype": args.dtype,
+            "factor_dtype": args.dtype, "schedule": args.schedule,
         },
         "t_factor_ms": 1e3 * float(np.median(tfs)),
         "t_solve_ms": 1e3 * float(np.median(tss)),
@@ -394,6 +400,7 @@ def main():
                          ("top_size", "factor_bytes", "factor_flops", "rank_avg", "rank_max")},
         "solve_phases_ms": {"spmv": infos[-1].t_spmv_ms, "apply": infos[-1].t_apply_ms,
                             "orth": infos[-1].t_orth_ms, "other": infos[-1].t_other_ms},
+        "solve_reductions": infos[-1].n_reduce,
         # Arithmetic intensity of the QR (algorithmic flops over algorithmic
         # bytes, about 60 flop/B) is above the FP32 ridge point (157.3 / 8 =
         # 20 flop/B): the binding roof is the vector ALU, not HBM.
@@ -424,7 +431,8 @@ def main():
         torch.cuda.empty_cache()
         cmd = [sys.executable, os.path.abspath(__file__), "--workload", args.workload,
                "--dtype", other, "--steps", "1", "--warmup", "1", "--no-compare",
-               "--no-cpu-baseline", "--levels", str(L), "--eps", str(eps)]
+               "--no-cpu-baseline", "--levels", str(L), "--eps", str(eps),
+               "--schedule", args.schedule]
         log(f"comparison: {other} factor in a child process")
         try:
             r = subprocess.run(cmd, capture_output=True, text=True, timeout=600)

@@ -89,6 +89,16 @@ typedef struct {
  *                        Arnoldi step with modified Gram-Schmidt, the baseline
  *                        the s-step method is compared with (Fig. 7)         */
 #define SSTEP_FLAG_CLASSICAL 8
+/*   SSTEP_FLAG_LAGGED    the single-reduce schedule of Algorithm 2: the
+ *                        operator applications of a block start from the
+ *                        previous block after its first pass; one Gram matrix
+ *                        per block gives that block's second pass (its
+ *                        Hessenberg columns and convergence check) and the new
+ *                        block's first pass.  Same basis, Hessenberg matrix and
+ *                        residual history as the default schedule in exact
+ *                        arithmetic, one reduction per block instead of four.
+ *                        Not with SSTEP_FLAG_ONE_PASS (SPAND_EINVAL).        */
+#define SSTEP_FLAG_LAGGED 16
 typedef struct {
   int32_t s;                /* block size of the s-step method (1..8)        */
   int32_t restart;          /* restart length m, a multiple of s              */
@@ -115,7 +125,8 @@ typedef struct {
   int32_t n_spmv;           /* SpMV launches (t_spmv_ms covers exactly these) */
   int32_t n_apply;          /* preconditioner applications                  */
   int32_t n_orth;           /* entries in orth_loss (SSTEP_FLAG_ORTH_LOSS)   */
-  int32_t pad;
+  int32_t n_reduce;         /* inner-product reductions over the vectors
+                               (dot products and Gram matrices)             */
   double orth_loss[SSTEP_MAX_HIST]; /* ||Q^T Q - I||_F after each block, with
                                the basis size j + s + 1 in orth_cols       */
   int32_t orth_cols[SSTEP_MAX_HIST];

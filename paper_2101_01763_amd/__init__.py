@@ -48,6 +48,7 @@ class spand_opts_t(C.Structure):
 
 
 SSTEP_FLAG_MONOMIAL, SSTEP_FLAG_ONE_PASS, SSTEP_FLAG_ORTH_LOSS, SSTEP_FLAG_CLASSICAL = 1, 2, 4, 8
+SSTEP_FLAG_LAGGED = 16
 
 
 class sstep_opts_t(C.Structure):
@@ -64,7 +65,7 @@ class sstep_stats_t(C.Structure):
                 ("t_total_ms", C.c_double), ("t_spmv_ms", C.c_double),
                 ("t_apply_ms", C.c_double), ("t_orth_ms", C.c_double),
                 ("t_other_ms", C.c_double), ("n_spmv", C.c_int32), ("n_apply", C.c_int32),
-                ("n_orth", C.c_int32), ("pad", C.c_int32),
+                ("n_orth", C.c_int32), ("n_reduce", C.c_int32),
                 ("orth_loss", C.c_double * SSTEP_MAX_HIST),
                 ("orth_cols", C.c_int32 * SSTEP_MAX_HIST)]
 
@@ -269,21 +270,24 @@ class SolveInfo:
     n_spmv: int
     n_apply: int
     orth_loss: list = None      # [(basis columns, ||Q^T Q - I||_F)] with orth_loss=True
+    n_reduce: int = 0           # inner-product reductions (dots and Gram matrices)
 
 
 def solve(A: BSRMatrix, b, M: Factor | None = None, s=5, restart=60, rtol=1e-8, maxit=1000,
           transpose=False, x0=None, val=None, monomial=False, passes=2, orth_loss=False,
-          classical=False):
+          classical=False, lagged=False):
     """s-step GMRES; returns (x, SolveInfo).  ENOTCONV/EBREAKDOWN do not raise.
     monomial / passes=1 / orth_loss: the basis and orthogonalisation variants
     of the stability study; classical: GMRES with modified Gram-Schmidt
-    Arnoldi steps (the baseline; s is then unused) (SSTEP_FLAG_*)."""
+    Arnoldi steps (the baseline; s is then unused); lagged: the single-reduce
+    schedule of Algorithm 2 (SSTEP_FLAG_*)."""
     import torch
     if passes not in (1, 2):
         raise ValueError("passes must be 1 or 2")
     x = torch.zeros_like(b) if x0 is None else x0.clone()
     flags = ((SSTEP_FLAG_MONOMIAL if monomial else 0) | (SSTEP_FLAG_ONE_PASS if passes == 1 else 0)
-             | (SSTEP_FLAG_ORTH_LOSS if orth_loss else 0) | (SSTEP_FLAG_CLASSICAL if classical else 0))
+             | (SSTEP_FLAG_ORTH_LOSS if orth_loss else 0) | (SSTEP_FLAG_CLASSICAL if classical else 0)
+             | (SSTEP_FLAG_LAGGED if lagged else 0))
     o = sstep_opts_t(int(s), int(restart), int(maxit), int(bool(transpose)), float(rtol), flags, 0)
     st = sstep_stats_t()
     Ac = A.c(val)
@@ -295,7 +299,8 @@ def solve(A: BSRMatrix, b, M: Factor | None = None, s=5, restart=60, rtol=1e-8, 
                      [complex(st.shift_re[i], st.shift_im[i]) for i in range(st.n_shifts)],
                      st.t_total_ms, st.t_spmv_ms, st.t_apply_ms, st.t_orth_ms, st.t_other_ms,
                      st.n_spmv, st.n_apply,
-                     [(st.orth_cols[i], st.orth_loss[i]) for i in range(st.n_orth)])
+                     [(st.orth_cols[i], st.orth_loss[i]) for i in range(st.n_orth)],
+                     st.n_reduce)
     return x, info
 
 

@@ -238,6 +238,12 @@ struct PhaseTimer {
 enum { T_SPMV = 0, T_APPLY, T_ORTH, T_OTHER, T_N };
 
 // ------------------------------------------------------------------ solver
+// Single-reduce schedule: a pending block whose one-pass residual estimate is
+// within this factor of the tolerance gets its second pass at once instead of
+// starting the next block's operator applications (which would be wasted if
+// the block converges).  Only the work changes; the results are the same.
+constexpr double kEagerFinish = 4.0;
+
 int sstep_solve(const spand_bsr_t &A0, Factor *M, const double *b, double *x,
                 const sstep_opts_t &o, sstep_stats_t *st, hipStream_t stream) {
   const int64_t N = int64_t(A0.n_brows) * A0.bs;
@@ -253,6 +259,13 @@ int sstep_solve(const spand_bsr_t &A0, Factor *M, const double *b, double *x,
   // classical GMRES (Algorithm 1): every column by the Arnoldi step with
   // modified Gram-Schmidt, no blocks
   const bool classical = (o.flags & SSTEP_FLAG_CLASSICAL) != 0;
+  // single-reduce schedule (Algorithm 2): the second pass of a block lagged
+  // into the one Gram matrix of the next block
+  const bool lagged = (o.flags & SSTEP_FLAG_LAGGED) != 0 && !classical;
+  if (lagged && passes == 1) {
+    set_error("the single-reduce schedule needs two passes");
+    return SPAND_EINVAL;
+  }
   std::vector<double> orth_loss;
   std::vector<int> orth_cols;
   std::vector<std::pair<void *, size_t>> allocs;
@@ -298,7 +311,9 @@ int sstep_solve(const spand_bsr_t &A0, Factor *M, const double *b, double *x,
   GTRY(alloc(&pR, size_t(N) * 8));
   GTRY(alloc(&pK, sizeof(KrylovDev)));
   const int64_t nchunk = std::max<int64_t>(cdiv(N, TS_CHUNK), cdiv(N, 4096));
-  GTRY(alloc(&pPart, size_t(nchunk) * TS_MAXA * TS_MAXS * 8));
+  int64_t npart = nchunk * TS_MAXA * TS_MAXS;
+  if (lagged) npart = std::max(npart, gram_wide_part_elems(N, m + 1, 2 * s));
+  GTRY(alloc(&pPart, size_t(npart) * 8));
   double *Q = (double *)pQ, *Z = (double *)pZ, *Rv = (double *)pR, *part = (double *)pPart;
   double *Gq = nullptr;      // Gram matrix of the basis (diagnostic)
   if (orth_log) {
@@ -339,7 +354,7 @@ int sstep_solve(const spand_bsr_t &A0, Factor *M, const double *b, double *x,
     (void)hipEventCreate(&e1);
     (void)hipEventRecord(e0, stream);
   }
-  int n_spmv = 0, n_apply = 0;
+  int n_spmv = 0, n_apply = 0, n_reduce = 0;   // n_reduce: inner-product reductions
   auto Minv = [&](const double *in, double *out) -> int {
     ++n_apply;
     if (M) return M->apply(in, out, tr, stream);
@@ -369,6 +384,7 @@ int sstep_solve(const spand_bsr_t &A0, Factor *M, const double *b, double *x,
   std::vector<Slot> slots;
   tm.mark(T_OTHER);
   // ||b||
+  ++n_reduce;
   GTRY(launch_dot(N, b, b, part, Kd->scal + 1, 1, stream));
   double bnorm = 0.0;
   GTRY(d2h(&bnorm, Kd->scal + 1, 8));
@@ -386,6 +402,7 @@ int sstep_solve(const spand_bsr_t &A0, Factor *M, const double *b, double *x,
     ++n_spmv;
     GTRY(launch_spmv(A, 0, -1.0, x, 1.0, Rv, nullptr, 0.0, nullptr, 0.0, stream));
     tm.mark(T_OTHER);
+    ++n_reduce;
     GTRY(launch_dot(N, Rv, Rv, part, Kd->scal, 1, stream));
     double beta = 0.0;
     GTRY(d2h(&beta, Kd->scal, 8));
@@ -417,11 +434,13 @@ int sstep_solve(const spand_bsr_t &A0, Factor *M, const double *b, double *x,
         tm.mark(T_ORTH);
         for (int i = 0; i <= jj; ++i) {
           double *hij = Kd->H + i * ld + jj;
-          GTRY(launch_dot(N, w, Q + i * N, part, hij, 0, stream));
+          ++n_reduce;
+    GTRY(launch_dot(N, w, Q + i * N, part, hij, 0, stream));
           GTRY(vec_axpby(N, Q + i * N, w, -1.0, hij, 0, 1.0, stream));
         }
         double *hn = Kd->H + (jj + 1) * ld + jj;
-        GTRY(launch_dot(N, w, w, part, hn, 1, stream));
+        ++n_reduce;
+    GTRY(launch_dot(N, w, w, part, hn, 1, stream));
         GTRY(vec_axpby(N, w, w, 1.0, hn, 1, 0.0, stream));
         GTRY(kry_givens_col(Kd, jj, stream));
         tm.mark(T_OTHER);
@@ -468,7 +487,73 @@ int sstep_solve(const spand_bsr_t &A0, Factor *M, const double *b, double *x,
       }
       j = s;
     }
-    while (!done && j < m) {
+    // Single-reduce schedule.  j: last basis column (start of the next
+    // operator applications); with a pending block P = Q[:, j-s+1:j+1] (one
+    // pass, Hessenberg columns j0..j0+s-1 not yet assembled).  Each step: s
+    // applications from q_j, one Gram matrix, the dense step, one pass over
+    // the rows.  The last block of a cycle is finished by a step with no new
+    // block; so is a block whose one-pass residual estimate already meets the
+    // tolerance (then no applications are spent past convergence).
+    bool pend = false, finish_now = false;
+    int j0 = 0;
+    while (lagged && !done) {
+      const int sw = (j < m && !(pend && finish_now)) ? s : 0;
+      if (!pend && sw == 0) break;
+      for (int q = 1; q <= sw; ++q) {
+        const Slot &sl = slots[q - 1];
+        double *prev = Q + (j + q - 1) * N;
+        double *out = Q + (j + q) * N;
+        if (sl.kind == 2)
+          GTRY(Ahat(prev, out, prev, -sl.a, Q + (j + q - 2) * N, sl.b * sl.b));
+        else
+          GTRY(Ahat(prev, out, prev, -sl.a, nullptr, 0.0));
+      }
+      tm.mark(T_ORTH);
+      const int sp = pend ? s : 0, a = j + 1 - sp;
+      ++n_reduce;
+      GTRY(launch_gram_wide(N, Q, N, a + sp + sw, Q + int64_t(a) * N, N, sp + sw, part, Kd->LG,
+                            sp + sw, stream));
+      GTRY(kry_lag_block(Kd, a, sp, sw, s, stream));
+      GTRY(launch_ts_lag_update(N, Q, N, a, sp, sw, s, Kd, stream));
+      tm.mark(T_OTHER);
+      int bad = 0;
+      GTRY(d2h(&bad, &Kd->bad, 4));
+      if (sp) {
+        if (bad == 1) {
+          breakdown = 1;
+          k = j0;      // keep the columns before the pending block
+          break;
+        }
+        if (orth_log) GTRY(record_orth(j0 + s + 1));
+        std::vector<double> est(s);
+        GTRY(d2h(est.data(), Kd->est + j0, size_t(s) * 8));
+        for (int c = j0; c < j0 + s; ++c) {
+          ++iters;
+          hist.push_back(est[c - j0]);
+          k = c + 1;
+          if (est[c - j0] <= tol || iters >= maxit) {
+            done = true;
+            break;
+          }
+        }
+      }
+      if (done || !sw) {
+        pend = false;
+        continue;
+      }
+      if (bad == 2) {
+        breakdown = 1;
+        break;
+      }
+      std::vector<double> et(s);
+      GTRY(d2h(et.data(), Kd->est_t, size_t(s) * 8));
+      pend = true;
+      j0 = j;
+      j += s;
+      const double emin = *std::min_element(et.begin(), et.end());
+      finish_now = emin <= kEagerFinish * tol || j >= m || iters + s >= maxit;
+    }
+    while (!lagged && !done && j < m) {
       for (int q = 1; q <= s; ++q) {
         const Slot &sl = slots[q - 1];
         double *prev = Q + (j + q - 1) * N;
@@ -484,8 +569,10 @@ int sstep_solve(const spand_bsr_t &A0, Factor *M, const double *b, double *x,
       double *Rp[2] = {Kd->R1, Kd->R2};
       double *Tp[2] = {Kd->T1, Kd->T2};
       for (int pass = 0; pass < passes; ++pass) {
+        ++n_reduce;
         GTRY(launch_gram(N, Q, N, a, W, N, s, part, Rp[pass], s, stream));
         GTRY(launch_ts_update(N, Q, N, a, Rp[pass], s, W, N, s, stream));
+        ++n_reduce;
         GTRY(launch_gram(N, W, N, s, W, N, s, part, Kd->G, s, stream));
         GTRY(kry_chol(Kd, s, Kd->G, Tp[pass], stream));
         GTRY(launch_ts_trsm(N, W, N, s, Tp[pass], &Kd->bad, stream));
@@ -547,6 +634,7 @@ int sstep_solve(const spand_bsr_t &A0, Factor *M, const double *b, double *x,
     st->relres = relres;
     st->n_hist = int(std::min<size_t>(hist.size(), SSTEP_MAX_HIST));
     for (int i = 0; i < st->n_hist; ++i) st->hist[i] = hist[i];
+    st->n_reduce = n_reduce;
     st->n_orth = int(std::min<size_t>(orth_loss.size(), SSTEP_MAX_HIST));
     for (int i = 0; i < st->n_orth; ++i) {
       st->orth_loss[i] = orth_loss[i];

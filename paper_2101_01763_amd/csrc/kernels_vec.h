@@ -34,6 +34,10 @@ int launch_ts_trsm(int64_t N, double *W, int64_t ldw, int s, const double *T, co
                    hipStream_t st);
 int launch_ts_gemv(int64_t N, const double *X, int64_t ldx, int k, const double *c, double *y,
                    hipStream_t st);
+// Gram matrix with up to 2 * TS_MAXS columns (single-reduce step)
+int launch_gram_wide(int64_t N, const double *X, int64_t ldx, int a, const double *W,
+                     int64_t ldw, int s, double *part, double *out, int ldo, hipStream_t st);
+int64_t gram_wide_part_elems(int64_t N, int a, int s);   // size of its partial buffer
 
 // ---- small dense state of the s-step method (device, one workgroup)
 constexpr int KRY_MMAX = 128;     // largest restart length
@@ -47,8 +51,16 @@ struct KrylovDev {
   double G[TS_MAXS * TS_MAXS], T1[TS_MAXS * TS_MAXS], T2[TS_MAXS * TS_MAXS];
   double Bb[(TS_MAXS + 1) * TS_MAXS];
   double scal[8];                        // [0] beta / norms
-  int bad;                               // CholQR breakdown flag
+  int bad;                               // CholQR breakdown flag (lagged: 1 = P, 2 = W)
   int pad;
+  // single-reduce schedule (second pass lagged by one block)
+  double LG[TS_MAXA * 2 * TS_MAXS];      // Q[:, 0:a+sp+sw]^T Q[:, a:a+sp+sw], ld sp+sw
+  double Lr1[TS_MAXA * TS_MAXS];         // R1 = Q_old^T P (a x s, ld s)
+  double Lt[TS_MAXS * TS_MAXS];          // T = chol(P^T P - R1^T R1)
+  double Pra[TS_MAXA * TS_MAXS];         // pending block: W = Q[:, 0:a2] Pra + What Prb
+  double Prb[TS_MAXS * TS_MAXS];
+  double Prho[TS_MAXA];                  // its starting vector on Q[:, 0:a2]
+  double est_t[TS_MAXS];                 // residual estimates from its first pass
 };
 
 int kry_init_cycle(KrylovDev *K, int m, hipStream_t st);                  // g = beta e0 (beta in scal[0])
@@ -56,6 +68,9 @@ int kry_chol(KrylovDev *K, int s, double *G, double *T, hipStream_t st);  // T =
 int kry_block_finish(KrylovDev *K, int j, int s, int passes, hipStream_t st);         // R, Hessenberg, Givens
 int kry_givens_col(KrylovDev *K, int j, hipStream_t st);                  // column j (MGS steps)
 int kry_lsq(KrylovDev *K, int k, hipStream_t st);                         // y from Rm, g
+int kry_lag_block(KrylovDev *K, int a, int sp, int sw, int s, hipStream_t st);  // from K->LG
+int launch_ts_lag_update(int64_t N, double *Q, int64_t ldq, int a, int sp, int sw, int s,
+                         const KrylovDev *K, hipStream_t st);
 int launch_dot(int64_t N, const double *x, const double *y, double *part, double *out,
                int take_sqrt, hipStream_t st);
 

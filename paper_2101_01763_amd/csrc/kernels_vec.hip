@@ -500,6 +500,223 @@ __global__ __launch_bounds__(256) void k_gram_reduce(const double *__restrict__ 
   if (threadIdx.x == 0) out[(idx / s) * ldo + idx % s] = red[0];
 }
 
+// Wide variant for the single-reduce step (up to 2 * TS_MAXS columns) on the
+// FP64 matrix cores: each wave owns TS_WCHUNK rows and accumulates the
+// a x s partial Gram matrix as ceil(a/16) tiles of v_mfma_f64_16x16x4f64
+// (lane l supplies X(row k + l/16, column l%16) as A and W(row k + l/16,
+// column l%16) as B; result register q of lane l is tile row l/16 + 4q,
+// column l%16), so the sum over rows needs no cross-lane reduction.  The
+// per-wave partials are summed in two deterministic stages (fixed partition
+// and order).
+constexpr int TS_WCHUNK = 256;     // rows per wave
+constexpr int TS_WMAXS = 2 * TS_MAXS;
+constexpr int TS_WSPLIT = 64;      // first-stage splits of the partial sums
+typedef double gram_f64x4 __attribute__((ext_vector_type(4)));
+
+template <int NT>
+__global__ __launch_bounds__(256) void k_gram_part_wide(int64_t N, const double *__restrict__ X,
+                                                        int64_t ldx, int a,
+                                                        const double *__restrict__ W,
+                                                        int64_t ldw, int s, int64_t nchunk,
+                                                        double *__restrict__ part) {
+  const int lane = threadIdx.x & 63, m = lane & 15, g = lane >> 4;
+  const int64_t chunk = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (chunk >= nchunk) return;        // whole wave; no barriers below
+  const int64_t rb = chunk * TS_WCHUNK + g;
+  gram_f64x4 acc[NT];
+  const double *xc[NT];
+  bool xok[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    acc[t] = gram_f64x4{0.0, 0.0, 0.0, 0.0};
+    const int col = t * 16 + m;
+    xok[t] = col < a;
+    xc[t] = X + (int64_t)(xok[t] ? col : 0) * ldx;
+  }
+  const bool wok = m < s;
+  const double *wc = W + (int64_t)(wok ? m : 0) * ldw;
+#pragma unroll 4
+  for (int k = 0; k < TS_WCHUNK / 4; ++k) {
+    const int64_t r = rb + 4 * k;
+    const bool in = r < N;
+    const double bw = (in && wok) ? wc[r] : 0.0;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const double ax = (in && xok[t]) ? xc[t][r] : 0.0;
+      acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(ax, bw, acc[t], 0, 0, 0);
+    }
+  }
+  double *outp = part + chunk * a * s;
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = t * 16 + g + 4 * q;
+      if (i < a && wok) outp[(int64_t)i * s + m] = acc[t][q];
+    }
+}
+
+// Stage 1: workgroup (x, y) sums chunks [y*nchunk/S, (y+1)*nchunk/S) of the
+// 64 outputs from x*64 (one wave per quarter of the range, then in order).
+__global__ __launch_bounds__(256) void k_gram_reduce_s1(const double *__restrict__ part,
+                                                        int64_t nchunk, int n,
+                                                        double *__restrict__ part2) {
+  __shared__ double red[4][64];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int idx = blockIdx.x * 64 + lane;
+  const int64_t c0 = nchunk * blockIdx.y / gridDim.y, c1 = nchunk * (blockIdx.y + 1) / gridDim.y;
+  const int64_t q0 = c0 + (c1 - c0) * wid / 4, q1 = c0 + (c1 - c0) * (wid + 1) / 4;
+  double v = 0.0;
+  if (idx < n)
+    for (int64_t c = q0; c < q1; ++c) v += part[c * n + idx];
+  red[wid][lane] = v;
+  __syncthreads();
+  if (wid == 0 && idx < n)
+    part2[(int64_t)blockIdx.y * n + idx] = (red[0][lane] + red[1][lane]) +
+                                           (red[2][lane] + red[3][lane]);
+}
+
+// Stage 2: out = sum over the splits, in order.
+__global__ __launch_bounds__(64) void k_gram_reduce_s2(const double *__restrict__ part2,
+                                                       int nsplit, int n, int s,
+                                                       double *__restrict__ out, int ldo) {
+  const int idx = blockIdx.x * 64 + threadIdx.x;
+  if (idx >= n) return;
+  double v = 0.0;
+  for (int y = 0; y < nsplit; ++y) v += part2[(int64_t)y * n + idx];
+  out[(idx / s) * ldo + idx % s] = v;
+}
+
+int64_t gram_wide_part_elems(int64_t N, int a, int s) {
+  return (cdiv(N, TS_WCHUNK) + TS_WSPLIT) * a * s;
+}
+
+int launch_gram_wide(int64_t N, const double *X, int64_t ldx, int a, const double *W,
+                     int64_t ldw, int s, double *part, double *out, int ldo, hipStream_t st) {
+  if (a <= 0 || s <= 0 || N <= 0) return SPAND_OK;
+  if (s > TS_WMAXS || a > TS_MAXA) {
+    set_error("wide Gram matrix: %d x %d exceeds %d x %d", a, s, TS_MAXA, TS_WMAXS);
+    return SPAND_EINVAL;
+  }
+  const int64_t nchunk = cdiv(N, TS_WCHUNK);
+  const dim3 g1((unsigned)cdiv(nchunk, 4));
+  switch (int(cdiv(a, 16))) {
+#define GRAM_NT(nt)                                                                          \
+  case nt:                                                                                   \
+    hipLaunchKernelGGL(k_gram_part_wide<nt>, g1, dim3(256), 0, st, N, X, ldx, a, W, ldw, s, \
+                       nchunk, part);                                                        \
+    break;
+    GRAM_NT(1) GRAM_NT(2) GRAM_NT(3) GRAM_NT(4) GRAM_NT(5)
+    GRAM_NT(6) GRAM_NT(7) GRAM_NT(8) GRAM_NT(9) GRAM_NT(10)
+#undef GRAM_NT
+    default:
+      set_error("wide Gram matrix: %d rows", a);
+      return SPAND_EINVAL;
+  }
+  SP_HIP(hipGetLastError());
+  const int n = a * s;
+  double *part2 = part + nchunk * n;
+  const int nsplit = int(std::min<int64_t>(TS_WSPLIT, nchunk));
+  hipLaunchKernelGGL(k_gram_reduce_s1, dim3(unsigned(cdiv(n, 64)), unsigned(nsplit)), dim3(256),
+                     0, st, part, nchunk, n, part2);
+  SP_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_gram_reduce_s2, dim3(unsigned(cdiv(n, 64))), dim3(64), 0, st, part2,
+                     nsplit, n, s, out, ldo);
+  SP_HIP(hipGetLastError());
+  return SPAND_OK;
+}
+
+// One pass over the rows for a single-reduce step, Q_old = Q[:, 0:a] read
+// once per row: the pending block P = Q[:, a:a+sp] <- (P - Q_old R1) T^{-1}
+// (its second pass) and the new block W = Q[:, a+sp:a+sp+sw] <-
+// (W - Q_old C_old - Phat C_P) RV^{-1} (its first pass), coefficients from
+// the single-reduce kernel.  bad = 1: nothing; bad = 2: P only.
+__global__ __launch_bounds__(256) void k_ts_lag_update(int64_t N, double *__restrict__ Q,
+                                                       int64_t ldq, int a, int sp, int sw, int s,
+                                                       const KrylovDev *__restrict__ K) {
+  __shared__ double RP[TS_MAXA * TS_MAXS];    // R1, ld TS_MAXS
+  __shared__ double RW[TS_MAXA * TS_MAXS];    // C_old, ld TS_MAXS
+  __shared__ double Ts[TS_MAXS * TS_MAXS], CP[TS_MAXS * TS_MAXS], RV[TS_MAXS * TS_MAXS];
+  const int bad = K->bad;
+  if (bad == 1) return;
+  const int ww = (bad == 0) ? sw : 0;
+  if (sp + ww == 0) return;
+  for (int idx = threadIdx.x; idx < a * TS_MAXS; idx += 256) {
+    const int i = idx / TS_MAXS, c = idx % TS_MAXS;
+    RP[idx] = c < sp ? K->Lr1[i * s + c] : 0.0;
+    RW[idx] = c < ww ? K->Pra[i * s + c] : 0.0;
+  }
+  for (int idx = threadIdx.x; idx < TS_MAXS * TS_MAXS; idx += 256) {
+    const int r = idx / TS_MAXS, c = idx % TS_MAXS;
+    const bool in = r < s && c < s;
+    Ts[idx] = in && sp ? K->Lt[r * s + c] : 0.0;
+    CP[idx] = in && sp && ww ? K->Pra[(a + r) * s + c] : 0.0;
+    RV[idx] = in && ww ? K->Prb[r * s + c] : 0.0;
+  }
+  __syncthreads();
+  // one row per thread (a grid-stride loop would let the compiler keep the
+  // triangular factors in registers and spill)
+  const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (r < N) {
+    double ap[TS_MAXS], aw[TS_MAXS];
+#pragma unroll
+    for (int c = 0; c < TS_MAXS; ++c) ap[c] = aw[c] = 0.0;
+#pragma unroll 2
+    for (int i = 0; i < a; ++i) {
+      const double xv = Q[(int64_t)i * ldq + r];
+#pragma unroll
+      for (int c = 0; c < TS_MAXS; ++c) {
+        if (c < sp) ap[c] += xv * RP[i * TS_MAXS + c];
+        if (c < ww) aw[c] += xv * RW[i * TS_MAXS + c];
+      }
+    }
+    double p[TS_MAXS];
+#pragma unroll
+    for (int c = 0; c < TS_MAXS; ++c) {
+      p[c] = 0.0;
+      if (c < sp) {
+        double v = Q[(int64_t)(a + c) * ldq + r] - ap[c];
+#pragma unroll
+        for (int q = 0; q < TS_MAXS; ++q)
+          if (q < c) v -= p[q] * Ts[q * TS_MAXS + c];
+        p[c] = v / Ts[c * TS_MAXS + c];
+        Q[(int64_t)(a + c) * ldq + r] = p[c];
+      }
+    }
+    if (ww) {
+      double w[TS_MAXS];
+#pragma unroll
+      for (int c = 0; c < TS_MAXS; ++c) {
+        w[c] = 0.0;
+        if (c < ww) {
+          double v = Q[(int64_t)(a + sp + c) * ldq + r] - aw[c];
+#pragma unroll
+          for (int q = 0; q < TS_MAXS; ++q)
+            if (q < sp) v -= p[q] * CP[q * TS_MAXS + c];
+#pragma unroll
+          for (int q = 0; q < TS_MAXS; ++q)
+            if (q < c) v -= w[q] * RV[q * TS_MAXS + c];
+          w[c] = v / RV[c * TS_MAXS + c];
+          Q[(int64_t)(a + sp + c) * ldq + r] = w[c];
+        }
+      }
+    }
+  }
+}
+
+int launch_ts_lag_update(int64_t N, double *Q, int64_t ldq, int a, int sp, int sw, int s,
+                         const KrylovDev *K, hipStream_t st) {
+  if (N <= 0 || sp + sw == 0) return SPAND_OK;
+  if (a > TS_MAXA || s > TS_MAXS || (sp && sp != s) || (sw && sw != s)) {
+    set_error("single-reduce update: a = %d, s = %d out of range", a, s);
+    return SPAND_EINVAL;
+  }
+  hipLaunchKernelGGL(k_ts_lag_update, dim3(unsigned(cdiv(N, 256))), dim3(256), 0, st, N, Q, ldq,
+                     a, sp, sw, s, K);
+  SP_HIP(hipGetLastError());
+  return SPAND_OK;
+}
+
 int launch_gram(int64_t N, const double *X, int64_t ldx, int a, const double *W, int64_t ldw,
                 int s, double *part, double *out, int ldo, hipStream_t st) {
   if (a <= 0 || s <= 0) return SPAND_OK;

@@ -266,3 +266,46 @@ def test_classical_gmres_parity():
         assert info.iters == io.iters, m
         np.testing.assert_allclose(info.history, io.history, rtol=1e-6)
         assert np.linalg.norm(_host(x) - xo) <= 1e-10 * np.linalg.norm(xo)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("n,s,m,monomial", [(16, 5, 40, False), (10, 4, 12, False),
+                                            (16, 5, 40, True), (10, 3, 9, False)])
+def test_lagged_schedule_parity(n, s, m, monomial):
+    """SSTEP_FLAG_LAGGED (Algorithm 2's single-reduce schedule) against the
+    oracle's lagged schedule and against the default two-pass schedule on
+    the GPU: same iterations, residual histories to 1e-6, x to 1e-8, the
+    final basis orthonormal after every block, and far fewer reductions.
+    n = 10 gives a row count that is not a multiple of the Gram chunk;
+    m = 12 and 9 restart, so each cycle's last block gets a step of its own."""
+    p, L, eps = 1, 4, 1e-1
+    cfg, A, As, xs, b, dA = _problem(n, p)
+    F = sp.factor(dA, n, n, True, False, eps=eps, nlevels=L, dtype="f64")
+    x, info = sp.solve(dA, _dev(b), F, s=s, restart=m, rtol=1e-8, monomial=monomial,
+                       lagged=True, orth_loss=True)
+    x2, info2 = sp.solve(dA, _dev(b), F, s=s, restart=m, rtol=1e-8, monomial=monomial)
+    Fo = spand.factor(As, nested_dissection(n, n, True, False, L), cfg.b, eps)
+    xo, io = krylov.sstep_gmres(lambda v: As @ v, b, lambda v: spand.apply(Fo, v), s=s,
+                                rtol=1e-8, restart=m, shifts=[0.0] * s if monomial else None,
+                                lagged=True, record_Q=True)
+    assert info.converged and io.converged and info.relres <= 1e-8
+    assert info.iters == io.iters == info2.iters
+    assert info.restarts == io.restarts
+    np.testing.assert_allclose(info.history, io.history, rtol=1e-6)
+    np.testing.assert_allclose(info.history, info2.history, rtol=1e-6)
+    assert np.linalg.norm(_host(x) - xo) <= 1e-8 * np.linalg.norm(xo)
+    g = np.array([v for _, v in info.orth_loss])
+    assert len(g) > 0 and np.all(g <= 1e-10)
+    assert all((c - 1) % s == 0 for c, _ in info.orth_loss)
+    # four Gram matrices per block against one per step (the dot products of
+    # the first cycle's Ritz steps are common to both)
+    assert info.n_reduce < info2.n_reduce
+    if info.restarts == 1 and not monomial:
+        assert info2.n_reduce - info.n_reduce >= 2 * ((io.iters - s) // s)
+
+
+@pytest.mark.gpu
+def test_lagged_rejects_one_pass():
+    cfg, A, As, xs, b, dA = _problem(8, 1)
+    with pytest.raises(RuntimeError):
+        sp.solve(dA, _dev(b), None, s=4, restart=8, rtol=1e-8, lagged=True, passes=1)
