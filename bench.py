@@ -259,7 +259,7 @@ def main():
     ap.add_argument("--dtype", default="f32", choices=["f32", "f64"])
     ap.add_argument("--levels", type=int, default=0)
     ap.add_argument("--eps", type=float, default=None)
-    ap.add_argument("--schedule", default="two-pass", choices=["two-pass", "lagged"],
+    ap.add_argument("--schedule", default="lagged", choices=["two-pass", "lagged"],
                     help="s-step orthogonalisation: two passes per block, or the "
                          "single-reduce schedule with the second pass lagged")
     ap.add_argument("--no-cpu-baseline", action="store_true")
