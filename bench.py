@@ -116,7 +116,8 @@ def bench_batch(args):
         Fs = sp.factor_batched(systems, eps=1e-2, nlevels=Ls, dtype="f32")
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        xs, infos = sp.solve_batched([q[0] for q in systems], rhs, Fs, s=5, restart=60, rtol=1e-8)
+        xs, infos = sp.solve_batched([q[0] for q in systems], rhs, Fs, s=5, restart=60, rtol=1e-8,
+                                     lagged=args.schedule == "lagged")
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         for F in Fs:
@@ -137,7 +138,8 @@ def bench_batch(args):
         "scaling": "weak", "vs_baseline": None, "dtype": "f32 (spaND) + f64 (Krylov)",
         "data": "synthetic (64 seeded DG-Euler systems)",
         "config": {"workload": f"C4 batch: 64 systems, {ntot} DOF total, n in 32..96, p in 1..3, "
-                               f"FP32 spaND eps=1e-2, s=5, m=60, rtol=1e-8, 8 streams"},
+                               f"FP32 spaND eps=1e-2, s=5, m=60, rtol=1e-8 ({args.schedule}), "
+                               f"8 streams", "schedule": args.schedule},
         "t_factor_ms": 1e3 * tf, "t_solve_ms": 1e3 * ts,
         "all_converged": all(i.converged for i in infos),
         "iters_min_max": [min(i.iters for i in infos), max(i.iters for i in infos)],

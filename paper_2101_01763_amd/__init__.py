@@ -336,8 +336,9 @@ def factor_batched(systems, eps=1e-2, nlevels=0, dtype="f32", graphs=True):
     return fs
 
 
-def solve_batched(As, bs, Ms=None, s=5, restart=60, rtol=1e-8, maxit=1000):
-    """Concurrent s-step GMRES solves; returns (list of x, list of SolveInfo)."""
+def solve_batched(As, bs, Ms=None, s=5, restart=60, rtol=1e-8, maxit=1000, lagged=False):
+    """Concurrent s-step GMRES solves; returns (list of x, list of SolveInfo).
+    lagged: the single-reduce schedule of Algorithm 2 for every system."""
     import torch
     n = len(As)
     xs = [torch.zeros_like(b) for b in bs]
@@ -345,7 +346,8 @@ def solve_batched(As, bs, Ms=None, s=5, restart=60, rtol=1e-8, maxit=1000):
     Mh = (C.c_void_p * n)(*[(m._h.value if m is not None else None) for m in (Ms or [None] * n)])
     pb = (C.c_void_p * n)(*[b.data_ptr() for b in bs])
     px = (C.c_void_p * n)(*[x.data_ptr() for x in xs])
-    o = (sstep_opts_t * n)(*[sstep_opts_t(int(s), int(restart), int(maxit), 0, float(rtol), 0, 0)
+    fl = SSTEP_FLAG_LAGGED if lagged else 0
+    o = (sstep_opts_t * n)(*[sstep_opts_t(int(s), int(restart), int(maxit), 0, float(rtol), fl, 0)
                              for _ in range(n)])
     st = (sstep_stats_t * n)()
     code = lib().sstep_gmres_solve_batched(n, Ac, Mh, pb, px, o, st, _stream())

@@ -199,7 +199,8 @@ def test_graph_replay_matches_eager():
         assert np.array_equal(_host(Fe.apply_T(r)), _host(Fg.apply_T(r))), rep
 
 
-def test_batched_matches_individual():
+@pytest.mark.parametrize("lagged", [False, True])
+def test_batched_matches_individual(lagged):
     from synth.dg_euler import batch_configs
     cfgs = batch_configs(6, seed=3, nmin=8, nmax=14)
     systems, rhs, sols = [], [], []
@@ -210,10 +211,11 @@ def test_batched_matches_individual():
         sols.append(xs)
     Ls = [sp.levels_for(c.N) for c in cfgs]
     Fs = sp.factor_batched(systems, eps=1e-2, nlevels=Ls, dtype="f32")
-    xs_b, infos = sp.solve_batched([s[0] for s in systems], rhs, Fs, s=5, restart=60, rtol=1e-8)
+    xs_b, infos = sp.solve_batched([s[0] for s in systems], rhs, Fs, s=5, restart=60, rtol=1e-8,
+                                   lagged=lagged)
     for i, (sysd, b, xstar) in enumerate(zip(systems, rhs, sols)):
         F = sp.factor(sysd[0], sysd[1], sysd[2], True, False, eps=1e-2, nlevels=Ls[i], dtype="f32")
-        x1, i1 = sp.solve(sysd[0], b, F, s=5, restart=60, rtol=1e-8)
+        x1, i1 = sp.solve(sysd[0], b, F, s=5, restart=60, rtol=1e-8, lagged=lagged)
         assert infos[i].converged and i1.converged
         assert infos[i].iters == i1.iters
         assert np.array_equal(_host(x1), _host(xs_b[i])), i
@@ -302,6 +304,23 @@ def test_lagged_schedule_parity(n, s, m, monomial):
     assert info.n_reduce < info2.n_reduce
     if info.restarts == 1 and not monomial:
         assert info2.n_reduce - info.n_reduce >= 2 * ((io.iters - s) // s)
+
+
+@pytest.mark.gpu
+def test_lagged_transpose_solve():
+    """The single-reduce schedule on the adjoint system A^T x = b (M^-T):
+    same iterations and histories as the two-pass schedule, x to 1e-8, and
+    A^T x = b to the tolerance."""
+    n, p, L, eps = 12, 1, 4, 1e-1
+    cfg, A, As, xs, b, dA = _problem(n, p)
+    F = sp.factor(dA, n, n, True, False, eps=eps, nlevels=L, dtype="f64")
+    x1, i1 = sp.solve(dA, _dev(b), F, s=5, restart=40, rtol=1e-8, transpose=True, lagged=True)
+    x2, i2 = sp.solve(dA, _dev(b), F, s=5, restart=40, rtol=1e-8, transpose=True)
+    assert i1.converged and i2.converged and i1.iters == i2.iters
+    np.testing.assert_allclose(i1.history, i2.history, rtol=1e-6)
+    xa, xb = _host(x1), _host(x2)
+    assert np.linalg.norm(xa - xb) <= 1e-8 * np.linalg.norm(xb)
+    assert np.linalg.norm(As.T @ xa - b) <= 1e-8 * np.linalg.norm(b)
 
 
 @pytest.mark.gpu
