@@ -518,7 +518,7 @@ __global__ __launch_bounds__(256) void k_gram_part_wide(int64_t N, const double 
                                                         int64_t ldx, int a,
                                                         const double *__restrict__ W,
                                                         int64_t ldw, int s, int64_t nchunk,
-                                                        double *__restrict__ part) {
+                                                        int vec4, double *__restrict__ part) {
   const int lane = threadIdx.x & 63, m = lane & 15, g = lane >> 4;
   const int64_t chunk = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (chunk >= nchunk) return;        // whole wave; no barriers below
@@ -535,15 +535,36 @@ __global__ __launch_bounds__(256) void k_gram_part_wide(int64_t N, const double 
   }
   const bool wok = m < s;
   const double *wc = W + (int64_t)(wok ? m : 0) * ldw;
-#pragma unroll 4
-  for (int k = 0; k < TS_WCHUNK / 4; ++k) {
-    const int64_t r = rb + 4 * k;
-    const bool in = r < N;
-    const double bw = (in && wok) ? wc[r] : 0.0;
+  if (vec4 && (chunk + 1) * TS_WCHUNK <= N) {
+    // full chunk, 32-byte aligned columns: lane group g loads rows
+    // 16kk + 4g .. 16kk + 4g + 3 at once and feeds them to four products
+    // (k-slot g of product q is row 16kk + 4g + q)
+    const int64_t rv = chunk * TS_WCHUNK + 4 * g;
+    const gram_f64x4 z4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 2
+    for (int kk = 0; kk < TS_WCHUNK / 16; ++kk) {
+      const int64_t r = rv + 16 * kk;
+      const gram_f64x4 bw = wok ? *(const gram_f64x4 *)(wc + r) : z4;
 #pragma unroll
-    for (int t = 0; t < NT; ++t) {
-      const double ax = (in && xok[t]) ? xc[t][r] : 0.0;
-      acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(ax, bw, acc[t], 0, 0, 0);
+      for (int t = 0; t < NT; ++t) {
+        const gram_f64x4 ax = xok[t] ? *(const gram_f64x4 *)(xc[t] + r) : z4;
+        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(ax[0], bw[0], acc[t], 0, 0, 0);
+        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(ax[1], bw[1], acc[t], 0, 0, 0);
+        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(ax[2], bw[2], acc[t], 0, 0, 0);
+        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(ax[3], bw[3], acc[t], 0, 0, 0);
+      }
+    }
+  } else {
+#pragma unroll 4
+    for (int k = 0; k < TS_WCHUNK / 4; ++k) {
+      const int64_t r = rb + 4 * k;
+      const bool in = r < N;
+      const double bw = (in && wok) ? wc[r] : 0.0;
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const double ax = (in && xok[t]) ? xc[t][r] : 0.0;
+        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(ax, bw, acc[t], 0, 0, 0);
+      }
     }
   }
   double *outp = part + chunk * a * s;
@@ -600,11 +621,14 @@ int launch_gram_wide(int64_t N, const double *X, int64_t ldx, int a, const doubl
   }
   const int64_t nchunk = cdiv(N, TS_WCHUNK);
   const dim3 g1((unsigned)cdiv(nchunk, 4));
+  // every column start 32-byte aligned: four-row vector loads
+  const int vec4 = (ldx % 4 == 0) && (ldw % 4 == 0) && (uintptr_t(X) % 32 == 0) &&
+                   (uintptr_t(W) % 32 == 0);
   switch (int(cdiv(a, 16))) {
 #define GRAM_NT(nt)                                                                          \
   case nt:                                                                                   \
     hipLaunchKernelGGL(k_gram_part_wide<nt>, g1, dim3(256), 0, st, N, X, ldx, a, W, ldw, s, \
-                       nchunk, part);                                                        \
+                       nchunk, vec4, part);                                                  \
     break;
     GRAM_NT(1) GRAM_NT(2) GRAM_NT(3) GRAM_NT(4) GRAM_NT(5)
     GRAM_NT(6) GRAM_NT(7) GRAM_NT(8) GRAM_NT(9) GRAM_NT(10)
