@@ -100,14 +100,17 @@ int kry_chol(KrylovDev *K, int s, double *G, double *T, hipStream_t st) {
 // ---------------------------------------------------------------- Givens
 __device__ void givens_column(KrylovDev *K, int c) {
   // rotate column c of H into Rm using the previous rotations (in place)
+  // the rotated entry of row i + 1 is carried in a register (no read back of
+  // what was just stored); every other load is of H, cs or sn
   const int ld = KRY_MMAX;
-  for (int i = 0; i <= c + 1; ++i) K->Rm[i * ld + c] = K->H[i * ld + c];
+  double hi = K->H[c];
   for (int i = 0; i < c; ++i) {
-    const double hi = K->Rm[i * ld + c], hn = K->Rm[(i + 1) * ld + c];
-    K->Rm[i * ld + c] = K->cs[i] * hi + K->sn[i] * hn;
-    K->Rm[(i + 1) * ld + c] = -K->sn[i] * hi + K->cs[i] * hn;
+    const double hn = K->H[(i + 1) * ld + c];
+    const double ci = K->cs[i], si = K->sn[i];
+    K->Rm[i * ld + c] = ci * hi + si * hn;
+    hi = -si * hi + ci * hn;
   }
-  const double a = K->Rm[c * ld + c], b = K->Rm[(c + 1) * ld + c];
+  const double a = hi, b = K->H[(c + 1) * ld + c];
   double cc = 1.0, ss = 0.0, r = a;
   if (b != 0.0) {
     r = hypot(a, b);
