@@ -328,3 +328,45 @@ def test_lagged_rejects_one_pass():
     cfg, A, As, xs, b, dA = _problem(8, 1)
     with pytest.raises(RuntimeError):
         sp.solve(dA, _dev(b), None, s=4, restart=8, rtol=1e-8, lagged=True, passes=1)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("case", ["restart_eq_s", "maxit", "widest"])
+def test_lagged_edge_cases(case):
+    """Edge cases of the single-reduce schedule against the oracle's and the
+    two-pass schedule: restart = s (every block is the last of its cycle),
+    maxit ending a cycle early (not converged, the pending block finished
+    before the budget), and the largest shape, s = 8 and m = 128 without a
+    preconditioner (Gram matrices of 16 columns over up to 129 basis
+    vectors)."""
+    n, p, L, eps = 10, 1, 4, 1e-1
+    cfg, A, As, xs, b, dA = _problem(n, p)
+    kw = dict(s=5, restart=40, rtol=1e-8, maxit=1000)
+    F, Mo = None, None
+    if case != "widest":
+        F = sp.factor(dA, n, n, True, False, eps=eps, nlevels=L, dtype="f64")
+        Fo = spand.factor(As, nested_dissection(n, n, True, False, L), cfg.b, eps)
+        Mo = lambda v: spand.apply(Fo, v)
+    if case == "restart_eq_s":
+        kw.update(s=4, restart=4)
+    elif case == "maxit":
+        kw.update(maxit=13)
+    else:
+        kw.update(s=8, restart=128, rtol=1e-10, maxit=400)
+    x, info = sp.solve(dA, _dev(b), F, lagged=True, **kw)
+    x2, info2 = sp.solve(dA, _dev(b), F, **kw)
+    xo, io = krylov.sstep_gmres(lambda v: As @ v, b, Mo, s=kw["s"], rtol=kw["rtol"],
+                                restart=kw["restart"], maxit=kw["maxit"], lagged=True)
+    assert info.iters == info2.iters == io.iters
+    assert info.converged == info2.converged == io.converged
+    assert info.restarts == io.restarts
+    rt = 1e-6 if case != "widest" else 1e-4
+    np.testing.assert_allclose(info.history, io.history, rtol=rt)
+    np.testing.assert_allclose(info.history, info2.history, rtol=rt)
+    if case == "maxit":
+        assert info.iters == 13 and not info.converged
+        assert info.status == sp.SPAND_ENOTCONV
+    else:
+        assert info.converged and info.relres <= kw["rtol"]
+    if case == "widest":
+        assert info.iters > 128        # a full cycle: the 129-column basis was reached
