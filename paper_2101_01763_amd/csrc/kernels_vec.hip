@@ -255,6 +255,7 @@ int launch_pull2(FType t, const PullGroup *d_groups, const PullItem *d_items,
 // G lanes per scalar row, 16-byte loads: one instruction of a lane group
 // reads 16*G contiguous bytes of the row segment.  G is picked per block
 // size by the autotuner (4, 8 or 16).
+typedef double spmv_f64x2 __attribute__((ext_vector_type(2)));
 template <int G>
 __global__ __launch_bounds__(256) void k_spmv(int n_brows, int bs, const int32_t *__restrict__ rowptr,
                                               const int32_t *__restrict__ colind,
@@ -275,8 +276,10 @@ __global__ __launch_bounds__(256) void k_spmv(int n_brows, int bs, const int32_t
       const double *rowv = val + (int64_t)t * b2 + (int64_t)r * bs;
       const double *xv = x + (int64_t)colind[t] * bs;
       for (int c = sub * 2; c < bs; c += 2 * G) {
-        const double2 a = *reinterpret_cast<const double2 *>(rowv + c);
-        acc += a.x * xv[c] + a.y * xv[c + 1];
+        // the matrix is streamed once per product: non-temporal, so that
+        // the vector's blocks stay in the caches
+        const spmv_f64x2 a = __builtin_nontemporal_load(reinterpret_cast<const spmv_f64x2 *>(rowv + c));
+        acc += a[0] * xv[c] + a[1] * xv[c + 1];
       }
     }
   }
