@@ -310,6 +310,18 @@ __global__ __launch_bounds__(256) void k_copy(const CopyDesc *__restrict__ items
   Td *dst = (Td *)d.dst;
   const int64_t total = (int64_t)d.rows * d.cols;
   const Ts sc = Ts(d.scale);
+  if (total <= INT_MAX) {
+    // 32-bit index arithmetic (a 64-bit division per element costs more
+    // than the element's memory traffic)
+    const int tot = int(total), cols = d.cols;
+    for (int idx = blockIdx.y * blockDim.x + threadIdx.x; idx < tot;
+         idx += gridDim.y * blockDim.x) {
+      const int r = idx / cols, c = idx - r * cols;
+      const Ts v = d.trans ? src[(int64_t)c * d.lds + r] : src[(int64_t)r * d.lds + c];
+      dst[(int64_t)r * d.ldd + c] = Td(v * sc);
+    }
+    return;
+  }
   for (int64_t idx = (int64_t)blockIdx.y * blockDim.x + threadIdx.x; idx < total;
        idx += (int64_t)gridDim.y * blockDim.x) {
     const int r = int(idx / d.cols), c = int(idx % d.cols);
