@@ -310,9 +310,10 @@ __global__ __launch_bounds__(256) void k_copy(const CopyDesc *__restrict__ items
   Td *dst = (Td *)d.dst;
   const int64_t total = (int64_t)d.rows * d.cols;
   const Ts sc = Ts(d.scale);
-  if (total <= INT_MAX) {
+  if (total + int64_t(gridDim.y) * blockDim.x <= INT_MAX) {
     // 32-bit index arithmetic (a 64-bit division per element costs more
-    // than the element's memory traffic)
+    // than the element's memory traffic); the bound keeps the last
+    // idx + stride within int
     const int tot = int(total), cols = d.cols;
     for (int idx = blockIdx.y * blockDim.x + threadIdx.x; idx < tot;
          idx += gridDim.y * blockDim.x) {
@@ -1431,7 +1432,8 @@ __device__ inline void wg_gemm(int M, int N, int K, FA A, FB B, FE epi, double *
 //     Residual norms never grow, so a column already at or below the
 //     stopping threshold eps |R_00| can never be a pivot: it leaves every
 //     later pass.  Stops at the first |R_ii| <= eps |R_00| (or at the
-//     numerical rank, |R_ii| <= 1e-12 |R_00|, whatever eps).  The kept
+//     numerical rank of the stored q's, |R_ii| <= 1e-12 |R_00| in FP64 and
+//     1e-4 |R_00| in FP32, whatever eps).  The kept
 //     vectors are rows of V (q_t = V[t m .. t m + m)).
 //     The steps run in blocks.  A block takes the BQ unselected columns of
 //     largest norm as candidates, orthonormalises their residuals into a
@@ -1612,7 +1614,16 @@ __global__ __launch_bounds__(256, 3) void k_qrcp(const QrcpDesc *__restrict__ it
   double R00 = 0.0;
   int k = 0;
   const int imax = min(m, nc);
-  const double stop_rel = fmax(force_full ? 0.0 : eps, 1e-12);
+  // Numerical rank floor of the stored kept vectors: Gram-Schmidt against q's
+  // whose orthogonality is delta (~sqrt(k) u, u the unit roundoff of T)
+  // leaves a new residual x with projections ~delta^2 |w| on them, so q_k =
+  // x / |x| is orthogonal only to delta^2 |w| / |x|.  Below 1e-12 |R_00|
+  // (FP64) or 1e-4 |R_00| (FP32: delta^2 ~ 4e-12 at k = 1024) the residual
+  // is rounding noise that cannot be made orthogonal; the completion of Q
+  // supplies the remaining orthonormal columns.  Only eps below the floor is
+  // affected (eps = 0 still keeps every unknown).
+  const double floor_rel = sizeof(T) == 4 ? 1e-4 : 1e-12;
+  const double stop_rel = fmax(force_full ? 0.0 : eps, floor_rel);
   // largest vn1 over the unselected columns of the live groups, ties ->
   // smallest index (the packed layouts keep the column order)
   int ncand_in = 0;               // candidates the pivot search checks against
@@ -1959,7 +1970,7 @@ __global__ __launch_bounds__(256, 3) void k_qrcp(const QrcpDesc *__restrict__ it
       __syncthreads();
       const double nrm = s_piv;
       if (k == 0) R00 = nrm;
-      // below 1e-12 |R_00| the residual is rounding noise and Gram-Schmidt
+      // below the floor the residual is rounding noise and Gram-Schmidt
       // could no longer make it orthogonal: the completion supplies the rest
       if (nrm == 0.0 || nrm <= stop_rel * R00) { done = true; break; }
       for (int r = tid; r < m; r += 256) {
