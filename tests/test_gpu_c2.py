@@ -1,0 +1,72 @@
+"""The plain method on the GPU in FP64 at full size, against the oracle's
+stored result (tests/golden/c2_fp64.json, written by make_c2_fixture.py,
+which calls only oracle/): 128 x 128 grid, p = 2, N = 589,824; spaND
+eps = 1e-2 with 10 levels (Eqs. (10)-(13)); s-step GMRES s = 5, restart 60,
+rtol 1e-8 (Algorithm 2).
+
+  * per level: number of interfaces, smallest and largest rank, kept and
+    total unknowns, all equal (integers decided in FP64 on both sides; the
+    fixture records that no |R_kk| lies within 7e-6 relative of the
+    threshold, far above FP64 rounding);
+  * iteration count equal, residual estimates after every column to 1e-6
+    relative, true relative residual below 1e-8;
+  * x on 4096 seeded indices and |x| within 1e-10 relative of the oracle's.
+The single-reduce schedule (equal to the two-pass one in exact arithmetic)
+is held to the same history and solution bounds.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_2101_01763_amd as sp  # noqa: E402
+from synth.dg_euler import DGConfig, make_problem  # noqa: E402
+
+FIX = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c2_fp64.json")
+
+
+@pytest.fixture(scope="module")
+def c2():
+    ref = json.load(open(FIX))
+    cfg = DGConfig(n=ref["n"], p=ref["p"])
+    A, xs, b, _ = make_problem(cfg)
+    dA = sp.BSRMatrix.from_numpy(A.rowptr, A.colind, A.val)
+    db = torch.as_tensor(b, device="cuda")
+    F = sp.factor(dA, ref["n"], ref["n"], True, False, eps=ref["eps"], nlevels=ref["levels"],
+                  dtype="f64")
+    yield ref, dA, db, F
+    F.destroy()
+
+
+def test_c2_ranks(c2):
+    ref, dA, db, F = c2
+    st = F.stats()
+    got = [{"interfaces": st["n_clusters"][l], "rank_min": st["rank_min"][l],
+            "rank_max": st["rank_max"][l], "kept": int(st["size_after"][l]),
+            "size": int(st["size_before"][l])} for l in range(st["nlevels"] - 1)]
+    assert got == ref["rank_levels"]
+    assert ref["min_threshold_margin"] > 1e-8
+
+
+@pytest.mark.parametrize("lagged", [False, True])
+def test_c2_solve(c2, lagged):
+    ref, dA, db, F = c2
+    x, info = sp.solve(dA, db, F, s=ref["s"], restart=ref["restart"], rtol=ref["rtol"],
+                       lagged=lagged)
+    torch.cuda.synchronize()
+    assert info.converged and info.relres <= ref["rtol"]
+    assert info.iters == ref["iters"] and info.restarts == ref["restarts"]
+    np.testing.assert_allclose(info.history, ref["history"], rtol=1e-6)
+    xh = x.cpu().numpy()
+    idx = np.asarray(ref["sample_idx"])
+    xo = np.asarray(ref["sample_x"])
+    err = np.linalg.norm(xh[idx] - xo) / np.linalg.norm(xo)
+    nerr = abs(np.linalg.norm(xh) - ref["x_norm"]) / ref["x_norm"]
+    print(f"C2 FP64 lagged={lagged}: iters {info.iters}, relres {info.relres:.3e}, "
+          f"sampled |x - x_oracle|/|x_oracle| = {err:.3e}, norm difference {nerr:.3e}")
+    assert err <= 1e-10
+    assert nerr <= 1e-10
