@@ -149,7 +149,25 @@ def _stream():
     return C.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
-def _ptr(t):
+def _vec(t, n, name, dtype=None, shape=None, check_device=True):
+    """Device pointer of a tensor the kernels read or write, after checking
+    that it is a contiguous float64 (or `dtype`) CUDA tensor of n elements
+    (or of `shape`): a wrong dtype, size or device would make the kernels
+    read or write out of bounds, so it is rejected before any launch."""
+    import torch
+    dtype = torch.float64 if dtype is None else dtype
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{name}: expected a torch.Tensor, got {type(t).__name__}")
+    if t.dtype != dtype:
+        raise ValueError(f"{name}: dtype {t.dtype}, expected {dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name}: shape {tuple(t.shape)}, expected {tuple(shape)}")
+    if t.numel() != n:
+        raise ValueError(f"{name}: {t.numel()} elements, expected {n}")
+    if check_device and not t.is_cuda:
+        raise ValueError(f"{name}: must be a CUDA (HIP) device tensor")
     return C.c_void_p(t.data_ptr())
 
 
@@ -173,9 +191,18 @@ class BSRMatrix:
         return self.n_brows * self.bs
 
     def c(self, val=None):
+        import torch
         v = self.val if val is None else val
-        return spand_bsr_t(self.n_brows, self.bs, int(self.colind.numel()), self.rowptr.data_ptr(),
-                           self.colind.data_ptr(), v.data_ptr())
+        nb, bs = self.n_brows, self.bs
+        nnzb = int(self.colind.numel())
+        _vec(self.rowptr, nb + 1, "rowptr", dtype=torch.int32, check_device=False)
+        _vec(self.colind, nnzb, "colind", dtype=torch.int32, check_device=False)
+        _vec(v, nnzb * bs * bs, "val", shape=(nnzb, bs, bs), check_device=False)
+        for name, t in (("rowptr", self.rowptr), ("colind", self.colind), ("val", v)):
+            if not t.is_cuda:
+                raise ValueError(f"{name}: must be a CUDA (HIP) device tensor")
+        return spand_bsr_t(nb, bs, nnzb, self.rowptr.data_ptr(), self.colind.data_ptr(),
+                           v.data_ptr())
 
     @staticmethod
     def from_numpy(rowptr, colind, val, device="cuda"):
@@ -207,14 +234,16 @@ class Factor:
 
     def apply(self, r, out=None):
         import torch
+        pr = _vec(r, self.N, "r")
         out = torch.empty_like(r) if out is None else out
-        _check(lib().spand_apply(self._h, _ptr(r), _ptr(out), _stream()))
+        _check(lib().spand_apply(self._h, pr, _vec(out, self.N, "out"), _stream()))
         return out
 
     def apply_T(self, r, out=None):
         import torch
+        pr = _vec(r, self.N, "r")
         out = torch.empty_like(r) if out is None else out
-        _check(lib().spand_apply_T(self._h, _ptr(r), _ptr(out), _stream()))
+        _check(lib().spand_apply_T(self._h, pr, _vec(out, self.N, "out"), _stream()))
         return out
 
     def stats(self):
@@ -284,15 +313,20 @@ def solve(A: BSRMatrix, b, M: Factor | None = None, s=5, restart=60, rtol=1e-8, 
     import torch
     if passes not in (1, 2):
         raise ValueError("passes must be 1 or 2")
-    x = torch.zeros_like(b) if x0 is None else x0.clone()
+    Ac = A.c(val)
+    pb = _vec(b, A.N, "b")
+    if x0 is not None:
+        _vec(x0, A.N, "x0")
+    x = torch.zeros_like(b) if x0 is None else x0.clone(memory_format=torch.contiguous_format)
     flags = ((SSTEP_FLAG_MONOMIAL if monomial else 0) | (SSTEP_FLAG_ONE_PASS if passes == 1 else 0)
              | (SSTEP_FLAG_ORTH_LOSS if orth_loss else 0) | (SSTEP_FLAG_CLASSICAL if classical else 0)
              | (SSTEP_FLAG_LAGGED if lagged else 0))
     o = sstep_opts_t(int(s), int(restart), int(maxit), int(bool(transpose)), float(rtol), flags, 0)
     st = sstep_stats_t()
-    Ac = A.c(val)
-    code = lib().sstep_gmres_solve(C.byref(Ac), M._h if M is not None else None, _ptr(b),
-                                   _ptr(x), C.byref(o), C.byref(st), _stream())
+    if M is not None and M.N != A.N:
+        raise ValueError(f"M: factor of {M.N} unknowns for a system of {A.N}")
+    code = lib().sstep_gmres_solve(C.byref(Ac), M._h if M is not None else None, pb,
+                                   _vec(x, A.N, "x"), C.byref(o), C.byref(st), _stream())
     _check(code, allow=(SPAND_OK, SPAND_ENOTCONV, SPAND_EBREAKDOWN))
     info = SolveInfo(code, st.iters, st.restarts, bool(st.converged), st.relres,
                      list(st.hist[:st.n_hist]),
@@ -341,10 +375,16 @@ def solve_batched(As, bs, Ms=None, s=5, restart=60, rtol=1e-8, maxit=1000, lagge
     lagged: the single-reduce schedule of Algorithm 2 for every system."""
     import torch
     n = len(As)
-    xs = [torch.zeros_like(b) for b in bs]
+    if len(bs) != n or (Ms is not None and len(Ms) != n):
+        raise ValueError("As, bs and Ms must have the same length")
     Ac = (spand_bsr_t * n)(*[A.c() for A in As])
+    pbl = [_vec(b, A.N, f"bs[{i}]") for i, (A, b) in enumerate(zip(As, bs))]
+    for i, m in enumerate(Ms or []):
+        if m is not None and m.N != As[i].N:
+            raise ValueError(f"Ms[{i}]: factor of {m.N} unknowns for a system of {As[i].N}")
+    xs = [torch.zeros_like(b) for b in bs]
     Mh = (C.c_void_p * n)(*[(m._h.value if m is not None else None) for m in (Ms or [None] * n)])
-    pb = (C.c_void_p * n)(*[b.data_ptr() for b in bs])
+    pb = (C.c_void_p * n)(*[p.value for p in pbl])
     px = (C.c_void_p * n)(*[x.data_ptr() for x in xs])
     fl = SSTEP_FLAG_LAGGED if lagged else 0
     o = (sstep_opts_t * n)(*[sstep_opts_t(int(s), int(restart), int(maxit), 0, float(rtol), fl, 0)
@@ -362,19 +402,21 @@ def pool_trim():
 
 def spmv(A: BSRMatrix, x, transpose=False, alpha=1.0, beta=0.0, y=None, val=None):
     import torch
-    y = torch.zeros_like(x) if y is None else y
     Ac = A.c(val)
-    _check(lib().spand_bsr_spmv(C.byref(Ac), int(bool(transpose)), float(alpha), _ptr(x),
-                                float(beta), _ptr(y), _stream()))
+    px = _vec(x, A.N, "x")
+    y = torch.zeros_like(x) if y is None else y
+    _check(lib().spand_bsr_spmv(C.byref(Ac), int(bool(transpose)), float(alpha), px,
+                                float(beta), _vec(y, A.N, "y"), _stream()))
     return y
 
 
 def pattern_outer(A: BSRMatrix, u, v, alpha=1.0):
     import torch
-    out = torch.empty_like(A.val)
     Ac = A.c()
-    _check(lib().spand_bsr_pattern_outer(C.byref(Ac), _ptr(u), _ptr(v), float(alpha),
-                                         _ptr(out), _stream()))
+    pu, pv = _vec(u, A.N, "u"), _vec(v, A.N, "v")
+    out = torch.empty_like(A.val)
+    _check(lib().spand_bsr_pattern_outer(C.byref(Ac), pu, pv, float(alpha),
+                                         _vec(out, out.numel(), "out"), _stream()))
     return out
 
 
