@@ -242,7 +242,10 @@ int spand_factor_batched(int32_t n, const spand_bsr_t *A, const spand_grid_t *gr
 
 /*
  * sstep_gmres_solve_batched - n independent s-step GMRES solves, concurrent
- * like spand_factor_batched.  M[i] may be NULL; d_b[i], d_x[i] device
+ * like spand_factor_batched.  M[i] may be NULL; one handle may appear at
+ * several M[i] (one operator, many right-hand sides): the systems that share
+ * a handle are solved one after the other, in index order, on one worker
+ * stream, since they share its scratch vectors.  d_b[i], d_x[i] device
  * float64 vectors (x0 in, solution out); opts[i]; st may be NULL or an
  * array of n stats.  Returns SPAND_OK if every system converged, otherwise
  * the most severe status (negative errors first, then SPAND_EBREAKDOWN,

@@ -8,6 +8,7 @@
 #include <atomic>
 #include <cstdlib>
 #include <thread>
+#include <unordered_map>
 #include <vector>
 
 #include <functional>
@@ -269,15 +270,40 @@ int spand_bsr_pattern_outer(const spand_bsr_t *P, const double *d_u, const doubl
 
 // Run job(i, stream) for i < n on a pool of worker threads, each with its own
 // non-blocking stream (default priority) ordered after `stream`; `stream`
-// then waits for every worker stream.  Returns the per-item statuses.
+// then waits for every worker stream.  Items of one group (group[i], equal
+// values) run in index order on one worker, so that items sharing state (a
+// factor handle and its scratch vectors) never run on two streams at once;
+// group == nullptr makes every item its own group.  Returns the per-item
+// statuses.
 static int run_batched(int n, hipStream_t stream, const std::function<int(int, hipStream_t)> &job,
-                       std::vector<int> &status) {
+                       std::vector<int> &status, const std::vector<int> *group = nullptr) {
   status.assign(n, SPAND_OK);
+  // work units: lists of items, in order of their first item
+  std::vector<std::vector<int>> units;
+  {
+    std::unordered_map<int, size_t> at;
+    for (int i = 0; i < n; ++i) {
+      const int g = group ? (*group)[i] : -1;
+      if (g < 0) {
+        units.push_back({i});
+        continue;
+      }
+      auto it = at.find(g);
+      if (it == at.end()) {
+        at.emplace(g, units.size());
+        units.push_back({i});
+      } else {
+        units[it->second].push_back(i);
+      }
+    }
+  }
+  const int nu = int(units.size());
   int dev = 0;
   SP_HIP(hipGetDevice(&dev));
   int nw = 8;
   if (const char *e = std::getenv("SPAND_BATCH_STREAMS")) nw = std::max(1, std::atoi(e));
-  nw = std::min(nw, n);
+  nw = std::min(nw, nu);
+  if (nw <= 0) return SPAND_OK;
   hipEvent_t start;
   SP_HIP(hipEventCreateWithFlags(&start, hipEventDisableTiming));
   SP_HIP(hipEventRecord(start, stream));
@@ -291,17 +317,19 @@ static int run_batched(int n, hipStream_t stream, const std::function<int(int, h
   auto worker = [&](int w) {
     (void)hipSetDevice(dev);
     for (;;) {
-      const int i = next.fetch_add(1);
-      if (i >= n) break;
-      int r;
-      try {
-        r = job(i, ss[w]);
-      } catch (const std::exception &ex) {
-        set_error("system %d: %s", i, ex.what());
-        r = SPAND_EINVAL;
+      const int u = next.fetch_add(1);
+      if (u >= nu) break;
+      for (const int i : units[u]) {
+        int r;
+        try {
+          r = job(i, ss[w]);
+        } catch (const std::exception &ex) {
+          set_error("system %d: %s", i, ex.what());
+          r = SPAND_EINVAL;
+        }
+        status[i] = r;
+        if (r != SPAND_OK) errs[i] = last_error();
       }
-      status[i] = r;
-      if (r != SPAND_OK) errs[i] = last_error();
     }
   };
   std::vector<std::thread> th;
@@ -363,11 +391,19 @@ int sstep_gmres_solve_batched(int32_t n, const spand_bsr_t *A, const spand_facto
   // transposed sweeps are captured here, before any worker thread exists
   for (int i = 0; i < n; ++i)
     if (M && M[i] && opts[i].transpose) SP_TRY(M[i]->F.capture_graphs(2));
+  // systems that share a factor handle share its scratch vectors: they run
+  // one after the other on one worker stream
+  std::vector<int> group(n, -1);
+  {
+    std::unordered_map<const void *, int> id;
+    for (int i = 0; i < n; ++i)
+      if (M && M[i]) group[i] = id.emplace((const void *)M[i], int(id.size())).first->second;
+  }
   std::vector<int> st;
   SP_TRY(run_batched(n, (hipStream_t)stream, [&](int i, hipStream_t s) {
     return sstep_gmres_solve(&A[i], M ? M[i] : nullptr, d_b[i], d_x[i], &opts[i],
                              stv ? &stv[i] : nullptr, (void *)s);
-  }, st));
+  }, st, &group));
   int worst = SPAND_OK;
   for (int i = 0; i < n; ++i) {
     if (st[i] < 0) return st[i];
