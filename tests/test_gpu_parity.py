@@ -83,7 +83,14 @@ def test_apply_parity_fp64(n, p, L, eps):
     ranks_ora = [(r[4], r[3]) for r in ro]
     r = np.random.default_rng(7).standard_normal(cfg.N)
     if ranks_gpu != ranks_ora:
-        pytest.skip(f"rank tie at the threshold: gpu {ranks_gpu} oracle {ranks_ora}")
+        # one interface whose |R_kk| ties the threshold to rounding changes
+        # one level's kept count by one (and the later levels' sizes by it);
+        # anything else is a failure, not a tie
+        diff = [(g, o) for g, o in zip(ranks_gpu, ranks_ora) if g != o]
+        first = diff[0]
+        assert len(ranks_gpu) == len(ranks_ora)
+        assert first[0][0] == first[1][0] and abs(first[0][1] - first[1][1]) == 1, diff
+        pytest.skip(f"one rank tie at the threshold: gpu {ranks_gpu} oracle {ranks_ora}")
     y = _host(F.apply(_dev(r)))
     yo = spand.apply(Fo, r)
     assert np.linalg.norm(y - yo) <= 1e-10 * np.linalg.norm(yo)

@@ -141,3 +141,22 @@ def test_rank_statistics_shape():
     assert len(st) == 3
     for (mn, av, mx, kept, tot) in st:
         assert 0 <= mn <= av <= mx and kept <= tot
+
+
+def test_rank_statistics_values():
+    """rank_stats fields, hand-computed: per level (min k, mean k, max k,
+    sum k, sum |s|) over the interfaces' (|s|, k) pairs."""
+    F = spand.Factor(0, [], [[(32, 5), (16, 9)], [(8, 0)], []], 1e-2, 4)
+    assert spand.rank_stats(F) == [(5, 7.0, 9, 14, 48), (0, 0.0, 0, 0, 8), (0, 0.0, 0, 0, 0)]
+
+
+def test_rank_statistics_eps0_sizes():
+    """At eps = 0 every unknown is kept: k = |s| for each interface, and the
+    level-0 total is the level-0 interface elements of the ND times b."""
+    cfg, As, xs, b, nd = _setup(8, 1, 3)
+    F = spand.factor(As, nd, cfg.b, 0.0)
+    st = spand.rank_stats(F)
+    ifs0 = [len(c.elems) * cfg.b for c in nd.levels[0] if not c.interior]
+    assert st[0] == (min(ifs0), float(np.mean(ifs0)), max(ifs0), sum(ifs0), sum(ifs0))
+    for lv in st:
+        assert lv[3] == lv[4]
