@@ -33,9 +33,6 @@ void set_error(const char *fmt, ...) {
 
 const char *last_error() { return g_err; }
 
-int sstep_solve(const spand_bsr_t &A, Factor *M, const double *b, double *x,
-                const sstep_opts_t &o, sstep_stats_t *st, hipStream_t stream);
-
 static int check_bsr(const spand_bsr_t *A) {
   if (!A) {
     set_error("A is NULL");
@@ -229,31 +226,23 @@ int spand_bsr_spmv(const spand_bsr_t *A, int transpose, double alpha, const doub
   }
   hipStream_t st = (hipStream_t)stream;
   if (!transpose) return launch_spmv(*A, 0, alpha, d_x, beta, d_y, nullptr, 0.0, nullptr, 0.0, st);
-  void *tv = nullptr, *fl = nullptr;
-  if (hipMalloc(&tv, size_t(A->nnzb) * A->bs * A->bs * 8) != hipSuccess) {
-    set_error("hipMalloc failed");
-    return SPAND_ENOMEM;
-  }
-  if (hipMalloc(&fl, 64) != hipSuccess) {
-    (void)hipFree(tv);
-    set_error("hipMalloc failed");
-    return SPAND_ENOMEM;
-  }
+  // A^T x reads the mirror blocks in place; the pattern must be symmetric,
+  // which is checked (and reported) before the product
+  void *fl = nullptr;
+  size_t got = 0;
+  SP_TRY(pool_alloc(&fl, 64, &got));
   int r = SPAND_OK, flag = 0;
   if (hipMemsetAsync(fl, 0, 64, st) != hipSuccess) r = SPAND_EHIP;
-  if (r == SPAND_OK) r = launch_bsr_transpose(*A, (double *)tv, (int *)fl, st);
-  spand_bsr_t At = *A;
-  At.d_val = (const double *)tv;
-  if (r == SPAND_OK) r = launch_spmv(At, 0, alpha, d_x, beta, d_y, nullptr, 0.0, nullptr, 0.0, st);
+  if (r == SPAND_OK) r = launch_spmv_t_check(*A, (int *)fl, st);
   if (r == SPAND_OK && (hipMemcpyAsync(&flag, fl, 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
                         hipStreamSynchronize(st) != hipSuccess))
     r = SPAND_EHIP;
-  (void)hipFree(tv);
-  (void)hipFree(fl);
+  pool_release(fl, got);
   if (r == SPAND_OK && flag) {
     set_error("transposed SpMV needs a structurally symmetric block pattern");
     r = SPAND_EINVAL;
   }
+  if (r == SPAND_OK) r = launch_spmv(*A, 1, alpha, d_x, beta, d_y, nullptr, 0.0, nullptr, 0.0, st);
   return r;
 }
 

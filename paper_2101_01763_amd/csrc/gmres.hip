@@ -244,8 +244,28 @@ enum { T_SPMV = 0, T_APPLY, T_ORTH, T_OTHER, T_N };
 // the block converges).  Only the work changes; the results are the same.
 constexpr double kEagerFinish = 4.0;
 
+// Device workspace of one solve, in allocation order (each piece rounded
+// up to 256 bytes): the Krylov basis Q (N x (m+1)), Z and R (N), the small
+// Krylov state, the partial sums of the reductions, the basis Gram matrix
+// of the orthogonality record, and the mirror flag of a transposed solve.
+static size_t ws_round(size_t b) { return (b + 255) & ~size_t(255); }
+size_t sstep_workspace_bytes(int64_t N, const sstep_opts_t &o) {
+  const int s = o.s, m = o.restart;
+  const bool lagged = (o.flags & SSTEP_FLAG_LAGGED) != 0 && (o.flags & SSTEP_FLAG_CLASSICAL) == 0;
+  size_t t = 0;
+  t += ws_round(size_t(N) * (m + 1) * 8) + 2 * ws_round(size_t(N) * 8) + ws_round(sizeof(KrylovDev));
+  const int64_t nchunk = std::max<int64_t>(cdiv(N, TS_CHUNK), cdiv(N, 4096));
+  int64_t npart = nchunk * TS_MAXA * TS_MAXS;
+  if (lagged) npart = std::max(npart, gram_wide_part_elems(N, m + 1, 2 * s));
+  t += ws_round(size_t(npart) * 8);
+  if (o.flags & SSTEP_FLAG_ORTH_LOSS) t += ws_round(size_t(m + 1) * (m + 1) * 8);
+  if (o.transpose) t += ws_round(64);
+  return t;
+}
+
 int sstep_solve(const spand_bsr_t &A0, Factor *M, const double *b, double *x,
-                const sstep_opts_t &o, sstep_stats_t *st, hipStream_t stream) {
+                const sstep_opts_t &o, sstep_stats_t *st, hipStream_t stream,
+                const SolveWorkspace *ws) {
   const int64_t N = int64_t(A0.n_brows) * A0.bs;
   const int s = o.s, m = o.restart;
   const double rtol = o.rtol;
@@ -269,11 +289,23 @@ int sstep_solve(const spand_bsr_t &A0, Factor *M, const double *b, double *x,
   std::vector<double> orth_loss;
   std::vector<int> orth_cols;
   std::vector<std::pair<void *, size_t>> allocs;
+  size_t ws_used = 0;
   auto cleanup = [&]() {
     (void)hipStreamSynchronize(stream);     // nothing queued may still use them
     for (auto &a : allocs) pool_release(a.first, a.second);
   };
+  // from the device block cache, or carved from the caller's workspace
   auto alloc = [&](void **p, size_t bytes) -> int {
+    if (ws) {
+      const size_t need = ws_round(bytes);
+      if (ws_used + need > ws->bytes) {
+        set_error("solve workspace exceeds %zu bytes", ws->bytes);
+        return SPAND_EINVAL;
+      }
+      *p = (char *)ws->base + ws_used;
+      ws_used += need;
+      return SPAND_OK;
+    }
     size_t got = 0;
     SP_TRY(pool_alloc(p, bytes, &got));
     allocs.push_back({*p, got});
@@ -287,24 +319,7 @@ int sstep_solve(const spand_bsr_t &A0, Factor *M, const double *b, double *x,
       return r__;          \
     }                      \
   } while (0)
-  spand_bsr_t A = A0;
-  if (tr) {
-    void *tv, *fl;
-    GTRY(alloc(&tv, size_t(A0.nnzb) * A0.bs * A0.bs * 8));
-    GTRY(alloc(&fl, 64));
-    if (hipMemsetAsync(fl, 0, 64, stream) != hipSuccess) GTRY(SPAND_EHIP);
-    GTRY(launch_bsr_transpose(A0, (double *)tv, (int *)fl, stream));
-    int flag = 0;
-    if (hipMemcpyAsync(&flag, fl, 4, hipMemcpyDeviceToHost, stream) != hipSuccess ||
-        hipStreamSynchronize(stream) != hipSuccess)
-      GTRY(SPAND_EHIP);
-    if (flag) {
-      set_error("transpose solve needs a structurally symmetric block pattern");
-      cleanup();
-      return SPAND_EINVAL;
-    }
-    A.d_val = (const double *)tv;
-  }
+  const spand_bsr_t &A = A0;
   void *pQ, *pZ, *pR, *pK, *pPart;
   GTRY(alloc(&pQ, size_t(N) * (m + 1) * 8));
   GTRY(alloc(&pZ, size_t(N) * 8));
@@ -320,6 +335,23 @@ int sstep_solve(const spand_bsr_t &A0, Factor *M, const double *b, double *x,
     void *pG;
     GTRY(alloc(&pG, size_t(m + 1) * (m + 1) * 8));
     Gq = (double *)pG;
+  }
+  if (tr) {
+    // A^T products read the mirror blocks of A in place (no transposed
+    // copy); the block pattern must be structurally symmetric
+    void *fl;
+    GTRY(alloc(&fl, 64));
+    if (hipMemsetAsync(fl, 0, 64, stream) != hipSuccess) GTRY(SPAND_EHIP);
+    GTRY(launch_spmv_t_check(A, (int *)fl, stream));
+    int flag = 0;
+    if (hipMemcpyAsync(&flag, fl, 4, hipMemcpyDeviceToHost, stream) != hipSuccess ||
+        hipStreamSynchronize(stream) != hipSuccess)
+      GTRY(SPAND_EHIP);
+    if (flag) {
+      set_error("transpose solve needs a structurally symmetric block pattern");
+      cleanup();
+      return SPAND_EINVAL;
+    }
   }
   // ||Q^T Q - I||_F of the first nc basis vectors: Gram matrix in column
   // chunks of the block kernels' width, then on the host
@@ -341,11 +373,13 @@ int sstep_solve(const spand_bsr_t &A0, Factor *M, const double *b, double *x,
     return SPAND_OK;
   };
   if (hipMemsetAsync(Z, 0, size_t(N) * 8, stream) != hipSuccess) GTRY(SPAND_EHIP);
-  GTRY(autotune_spmv(A, Z, Rv, stream));     // lanes per row, once per block size
+  // lanes per row, once per block size (a caller's workspace means a call
+  // that must not allocate or time: it keeps the tuned or default lanes)
+  if (!ws) GTRY(autotune_spmv(A, Z, Rv, stream));
   KrylovDev *Kd = (KrylovDev *)pK;
   const int ld = KRY_MMAX;
   PhaseTimer tm;
-  tm.on = st != nullptr;
+  tm.on = st != nullptr && !ws;
   tm.st = stream;
   double ph[T_N] = {0, 0, 0, 0};
   hipEvent_t e0, e1;
@@ -369,7 +403,7 @@ int sstep_solve(const spand_bsr_t &A0, Factor *M, const double *b, double *x,
     SP_TRY(Minv(v, Z));
     tm.mark(T_SPMV);
     ++n_spmv;
-    SP_TRY(launch_spmv(A, 0, 1.0, Z, 0.0, out, w1, c1, w2, c2, stream));
+    SP_TRY(launch_spmv(A, tr, 1.0, Z, 0.0, out, w1, c1, w2, c2, stream));
     tm.mark(T_OTHER);
     return SPAND_OK;
   };
@@ -400,7 +434,7 @@ int sstep_solve(const spand_bsr_t &A0, Factor *M, const double *b, double *x,
       GTRY(SPAND_EHIP);
     tm.mark(T_SPMV);
     ++n_spmv;
-    GTRY(launch_spmv(A, 0, -1.0, x, 1.0, Rv, nullptr, 0.0, nullptr, 0.0, stream));
+    GTRY(launch_spmv(A, tr, -1.0, x, 1.0, Rv, nullptr, 0.0, nullptr, 0.0, stream));
     tm.mark(T_OTHER);
     ++n_reduce;
     GTRY(launch_dot(N, Rv, Rv, part, Kd->scal, 1, stream));
@@ -613,19 +647,21 @@ int sstep_solve(const spand_bsr_t &A0, Factor *M, const double *b, double *x,
   }
   if (hipStreamSynchronize(stream) != hipSuccess) GTRY(SPAND_EHIP);
   if (st) {
-    (void)hipEventRecord(e1, stream);
-    (void)hipEventSynchronize(e1);
-    float tt = 0.f;
-    (void)hipEventElapsedTime(&tt, e0, e1);
-    tm.mark(T_OTHER);
-    tm.collect(ph);
-    st->t_total_ms = tt;
-    st->t_spmv_ms = ph[T_SPMV];
-    st->t_apply_ms = ph[T_APPLY];
-    st->t_orth_ms = ph[T_ORTH];
-    st->t_other_ms = ph[T_OTHER];
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    if (tm.on) {
+      (void)hipEventRecord(e1, stream);
+      (void)hipEventSynchronize(e1);
+      float tt = 0.f;
+      (void)hipEventElapsedTime(&tt, e0, e1);
+      tm.mark(T_OTHER);
+      tm.collect(ph);
+      st->t_total_ms = tt;
+      st->t_spmv_ms = ph[T_SPMV];
+      st->t_apply_ms = ph[T_APPLY];
+      st->t_orth_ms = ph[T_ORTH];
+      st->t_other_ms = ph[T_OTHER];
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+    }
     st->n_spmv = n_spmv;
     st->n_apply = n_apply;
     st->iters = iters;

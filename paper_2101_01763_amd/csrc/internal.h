@@ -297,6 +297,19 @@ int launch_spmv(const spand_bsr_t &A, int transpose, double alpha, const double 
                 double beta, double *y, const double *z, double gz, const double *w,
                 double gw, hipStream_t st);
 
+// s-step GMRES (gmres.hip).  ws == nullptr: device workspace from the block
+// cache; otherwise carved from [ws->base, ws->base + ws->bytes) (no device
+// allocation, no autotuning, no phase timers).
+struct SolveWorkspace {
+  void *base;
+  size_t bytes;
+};
+struct Factor;
+size_t sstep_workspace_bytes(int64_t N, const sstep_opts_t &o);
+int sstep_solve(const spand_bsr_t &A, Factor *M, const double *b, double *x,
+                const sstep_opts_t &o, sstep_stats_t *st, hipStream_t stream,
+                const SolveWorkspace *ws = nullptr);
+
 // ----------------------------------------------------------------- helpers
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 

@@ -19,7 +19,7 @@ int launch_spmv_g(const spand_bsr_t &A, int G, double alpha, const double *x, do
                   hipStream_t st);
 void set_spmv_lanes(int bs, int G);
 int get_spmv_lanes(int bs);
-int launch_bsr_transpose(const spand_bsr_t &A, double *outv, int *d_flag, hipStream_t st);
+int launch_spmv_t_check(const spand_bsr_t &A, int *d_flag, hipStream_t st);   // *d_flag = 1: no mirror block
 int launch_pattern_outer(const spand_bsr_t &P, const double *u, const double *v, double alpha,
                          double *out, hipStream_t st);
 int vec_fill(double *x, int64_t n, double v, hipStream_t st);

@@ -323,50 +323,94 @@ int launch_spmv_g(const spand_bsr_t &A, int G, double alpha, const double *x, do
   return SPAND_OK;
 }
 
-int launch_spmv(const spand_bsr_t &A, int transpose, double alpha, const double *x, double beta,
-                double *y, const double *z, double gz, const double *w, double gw,
-                hipStream_t st) {
-  (void)transpose;  // transposed products use an explicitly transposed copy
-  return launch_spmv_g(A, get_spmv_lanes(A.bs), alpha, x, beta, y, z, gz, w, gw, st);
-}
-
-// transposed copy: block t = (I, J) goes to the position of (J, I),
-// transposed.  Missing mirror block -> *flag = 1 (pattern not symmetric).
-__global__ __launch_bounds__(256) void k_bsr_transpose(int n_brows, int bs,
-                                                       const int32_t *__restrict__ rowptr,
-                                                       const int32_t *__restrict__ colind,
-                                                       const double *__restrict__ val,
-                                                       double *__restrict__ outv,
-                                                       int *__restrict__ flag) {
-  const int I = blockIdx.x;
-  if (I >= n_brows) return;
+// y = alpha*A^T x + beta*y + gz*z + gw*w for a structurally symmetric block
+// pattern, without a transposed copy: row R = I*bs + r of A^T x sums
+// A_JI(c, r) x_J(c) over the blocks (J, I) mirroring row I's blocks (I, J).
+// One lane per output row: for each c the lanes of element I read row c of
+// A_JI, bs contiguous doubles, so every load instruction is coalesced.  The
+// mirror block is found by binary search in row J (the same search on
+// every lane of the element, served by the caches); a missing mirror
+// contributes nothing (spmv_t_check reports it before the products).
+__global__ __launch_bounds__(256) void k_spmv_t(int n_brows, int bs,
+                                                const int32_t *__restrict__ rowptr,
+                                                const int32_t *__restrict__ colind,
+                                                const double *__restrict__ val,
+                                                const double *__restrict__ x, double alpha,
+                                                double beta, double *__restrict__ y,
+                                                const double *__restrict__ z, double gz,
+                                                const double *__restrict__ w, double gw) {
+  const int64_t N = (int64_t)n_brows * bs;
+  const int64_t R = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (R >= N) return;
+  const int I = int(R / bs), r = int(R - (int64_t)I * bs);
   const int64_t b2 = (int64_t)bs * bs;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
   for (int t = rowptr[I]; t < rowptr[I + 1]; ++t) {
     const int J = colind[t];
     int lo = rowptr[J], hi = rowptr[J + 1] - 1, pos = -1;
     while (lo <= hi) {
       const int mid = (lo + hi) >> 1;
-      const int c = colind[mid];
-      if (c == I) { pos = mid; break; }
-      if (c < I) lo = mid + 1; else hi = mid - 1;
+      const int cm = colind[mid];
+      if (cm == I) { pos = mid; break; }
+      if (cm < I) lo = mid + 1; else hi = mid - 1;
+    }
+    if (pos < 0) continue;
+    const double *blk = val + (int64_t)pos * b2 + r;
+    const double *xv = x + (int64_t)J * bs;
+    int c = 0;
+    for (; c + 4 <= bs; c += 4) {
+      a0 += __builtin_nontemporal_load(blk + (int64_t)c * bs) * xv[c];
+      a1 += __builtin_nontemporal_load(blk + (int64_t)(c + 1) * bs) * xv[c + 1];
+      a2 += __builtin_nontemporal_load(blk + (int64_t)(c + 2) * bs) * xv[c + 2];
+      a3 += __builtin_nontemporal_load(blk + (int64_t)(c + 3) * bs) * xv[c + 3];
+    }
+    for (; c < bs; ++c) a0 += __builtin_nontemporal_load(blk + (int64_t)c * bs) * xv[c];
+  }
+  double v = alpha * ((a0 + a1) + (a2 + a3));
+  if (beta != 0.0) v += beta * y[R];
+  if (z) v += gz * z[R];
+  if (w) v += gw * w[R];
+  y[R] = v;
+}
+
+// *flag = 1 if some stored block (I, J) has no mirror (J, I)
+__global__ __launch_bounds__(256) void k_spmv_t_check(int n_brows, const int32_t *__restrict__ rowptr,
+                                                      const int32_t *__restrict__ colind,
+                                                      int *__restrict__ flag) {
+  const int I = blockIdx.x * 256 + threadIdx.x;
+  if (I >= n_brows) return;
+  for (int t = rowptr[I]; t < rowptr[I + 1]; ++t) {
+    const int J = colind[t];
+    int lo = rowptr[J], hi = rowptr[J + 1] - 1, pos = -1;
+    while (lo <= hi) {
+      const int mid = (lo + hi) >> 1;
+      const int cm = colind[mid];
+      if (cm == I) { pos = mid; break; }
+      if (cm < I) lo = mid + 1; else hi = mid - 1;
     }
     if (pos < 0) {
-      if (threadIdx.x == 0) atomicOr(flag, 1);
-      continue;
-    }
-    const double *src = val + (int64_t)t * b2;
-    double *dst = outv + (int64_t)pos * b2;
-    for (int idx = threadIdx.x; idx < bs * bs; idx += 256) {
-      const int r = idx / bs, c = idx % bs;
-      dst[(int64_t)c * bs + r] = src[idx];
+      atomicOr(flag, 1);
+      return;
     }
   }
 }
 
-int launch_bsr_transpose(const spand_bsr_t &A, double *outv, int *d_flag, hipStream_t st) {
+int launch_spmv_t_check(const spand_bsr_t &A, int *d_flag, hipStream_t st) {
   if (A.n_brows <= 0) return SPAND_OK;
-  hipLaunchKernelGGL(k_bsr_transpose, dim3(A.n_brows), dim3(256), 0, st, A.n_brows, A.bs,
-                     A.d_rowptr, A.d_colind, A.d_val, outv, d_flag);
+  hipLaunchKernelGGL(k_spmv_t_check, dim3((unsigned)cdiv(A.n_brows, 256)), dim3(256), 0, st,
+                     A.n_brows, A.d_rowptr, A.d_colind, d_flag);
+  SP_HIP(hipGetLastError());
+  return SPAND_OK;
+}
+
+int launch_spmv(const spand_bsr_t &A, int transpose, double alpha, const double *x, double beta,
+                double *y, const double *z, double gz, const double *w, double gw,
+                hipStream_t st) {
+  if (!transpose) return launch_spmv_g(A, get_spmv_lanes(A.bs), alpha, x, beta, y, z, gz, w, gw, st);
+  const int64_t N = (int64_t)A.n_brows * A.bs;
+  if (N == 0) return SPAND_OK;
+  hipLaunchKernelGGL(k_spmv_t, dim3((unsigned)cdiv(N, 256)), dim3(256), 0, st, A.n_brows, A.bs,
+                     A.d_rowptr, A.d_colind, A.d_val, x, alpha, beta, y, z, gz, w, gw);
   SP_HIP(hipGetLastError());
   return SPAND_OK;
 }
