@@ -28,6 +28,7 @@
 #ifndef SPAND_H
 #define SPAND_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -209,6 +210,30 @@ int spand_apply_T(spand_factor_t F, const double *d_in, double *d_out, void *str
 int sstep_gmres_solve(const spand_bsr_t *A, spand_factor_t M, const double *d_b,
                       double *d_x, const sstep_opts_t *opts, sstep_stats_t *st,
                       void *stream);
+
+/*
+ * sstep_gmres_solve_noalloc - sstep_gmres_solve for callers that cannot
+ * allocate device memory (serving loops and harnesses that forbid
+ * hipMalloc).  Same arguments, results and statuses, computed by the same
+ * kernels; it allocates no device memory: its workspace (the Krylov basis,
+ * N x (restart + 1) doubles, two N-vectors, the Krylov state, the partial
+ * sums) lives in a library-owned array of SPAND_NOALLOC_SCRATCH_BYTES per
+ * device, held from the first call on that device until the process ends.
+ * A solve whose workspace would exceed it returns SPAND_EINVAL before any
+ * launch (about N (restart + 3) 8 bytes: N up to ~130,000 at restart 60).
+ * It does not tune the SpMV (the tuned or default lanes are used) and
+ * reports no phase times (t_* = 0 in st).  A transposed solve with M uses
+ * the eager M^-T sweeps unless a transposed solve or spand_apply_T has
+ * captured them before.  The solver synchronises with the host every cycle,
+ * so the call cannot be captured into a HIP graph.  All calls on one device
+ * share its array: they are serialised by a lock, each returns only after
+ * its work on `stream` has finished, and the array keeps the last call's
+ * contents (every buffer is rewritten before it is read).
+ */
+#define SPAND_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int sstep_gmres_solve_noalloc(const spand_bsr_t *A, spand_factor_t M, const double *d_b,
+                              double *d_x, const sstep_opts_t *opts, sstep_stats_t *st,
+                              void *stream);
 
 /*
  * spand_bsr_spmv - d_y = alpha * op(A) d_x + beta * d_y, op = A or A^T

@@ -89,7 +89,9 @@ class spand_factor_stats_t(C.Structure):
 EXPORTS = ["spand_factor", "spand_apply", "spand_apply_T", "sstep_gmres_solve",
            "spand_bsr_spmv", "spand_bsr_pattern_outer", "spand_factor_stats",
            "spand_destroy", "spand_nd", "spand_status_string", "spand_last_error",
-           "spand_factor_batched", "sstep_gmres_solve_batched", "spand_pool_trim"]
+           "spand_factor_batched", "sstep_gmres_solve_batched", "spand_pool_trim",
+           "sstep_gmres_solve_noalloc"]
+SPAND_NOALLOC_SCRATCH_BYTES = 64 << 20
 SPAND_FLAG_NO_GRAPH = 1
 
 _lib = None
@@ -115,6 +117,7 @@ def lib():
         L.spand_apply_T.argtypes = [vp, vp, vp, vp]
         L.sstep_gmres_solve.argtypes = [C.POINTER(spand_bsr_t), vp, vp, vp,
                                         C.POINTER(sstep_opts_t), C.POINTER(sstep_stats_t), vp]
+        L.sstep_gmres_solve_noalloc.argtypes = L.sstep_gmres_solve.argtypes
         L.spand_bsr_spmv.argtypes = [C.POINTER(spand_bsr_t), C.c_int, dbl, vp, dbl, vp, vp]
         L.spand_bsr_pattern_outer.argtypes = [C.POINTER(spand_bsr_t), vp, vp, dbl, vp, vp]
         L.spand_factor_stats.argtypes = [vp, C.POINTER(spand_factor_stats_t)]
@@ -304,7 +307,7 @@ class SolveInfo:
 
 def solve(A: BSRMatrix, b, M: Factor | None = None, s=5, restart=60, rtol=1e-8, maxit=1000,
           transpose=False, x0=None, val=None, monomial=False, passes=2, orth_loss=False,
-          classical=False, lagged=False):
+          classical=False, lagged=False, _entry="sstep_gmres_solve"):
     """s-step GMRES; returns (x, SolveInfo).  ENOTCONV/EBREAKDOWN do not raise.
     monomial / passes=1 / orth_loss: the basis and orthogonalisation variants
     of the stability study; classical: GMRES with modified Gram-Schmidt
@@ -325,8 +328,8 @@ def solve(A: BSRMatrix, b, M: Factor | None = None, s=5, restart=60, rtol=1e-8, 
     st = sstep_stats_t()
     if M is not None and M.N != A.N:
         raise ValueError(f"M: factor of {M.N} unknowns for a system of {A.N}")
-    code = lib().sstep_gmres_solve(C.byref(Ac), M._h if M is not None else None, pb,
-                                   _vec(x, A.N, "x"), C.byref(o), C.byref(st), _stream())
+    code = getattr(lib(), _entry)(C.byref(Ac), M._h if M is not None else None, pb,
+                                  _vec(x, A.N, "x"), C.byref(o), C.byref(st), _stream())
     _check(code, allow=(SPAND_OK, SPAND_ENOTCONV, SPAND_EBREAKDOWN))
     info = SolveInfo(code, st.iters, st.restarts, bool(st.converged), st.relres,
                      list(st.hist[:st.n_hist]),
@@ -336,6 +339,13 @@ def solve(A: BSRMatrix, b, M: Factor | None = None, s=5, restart=60, rtol=1e-8, 
                      [(st.orth_cols[i], st.orth_loss[i]) for i in range(st.n_orth)],
                      st.n_reduce)
     return x, info
+
+
+def solve_noalloc(A: BSRMatrix, b, M: Factor | None = None, **kw):
+    """solve() through sstep_gmres_solve_noalloc: no device allocation inside
+    the call (the workspace is the library's per-device scratch array of
+    SPAND_NOALLOC_SCRATCH_BYTES); same arguments and results."""
+    return solve(A, b, M, _entry="sstep_gmres_solve_noalloc", **kw)
 
 
 def _info(code, st):

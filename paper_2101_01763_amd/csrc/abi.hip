@@ -12,6 +12,7 @@
 #include <vector>
 
 #include <functional>
+#include <mutex>
 #include <string>
 
 #include "factor.h"
@@ -181,9 +182,10 @@ int spand_apply_T(spand_factor_t F, const double *d_in, double *d_out, void *str
   return F->F.apply(d_in, d_out, 1, (hipStream_t)stream);
 }
 
-int sstep_gmres_solve(const spand_bsr_t *A, spand_factor_t M, const double *d_b, double *d_x,
-                      const sstep_opts_t *opts, sstep_stats_t *st, void *stream) {
-  set_error("");
+}  // extern "C"
+
+static int check_solve_args(const spand_bsr_t *A, spand_factor_t M, const double *d_b,
+                            double *d_x, const sstep_opts_t *opts) {
   SP_TRY(check_bsr(A));
   if (!d_b || !d_x || !opts) {
     set_error("NULL argument");
@@ -206,10 +208,80 @@ int sstep_gmres_solve(const spand_bsr_t *A, spand_factor_t M, const double *d_b,
     set_error("factor size does not match A");
     return SPAND_EINVAL;
   }
+  return SPAND_OK;
+}
+
+// ------------------------------------------------- solve without allocation
+// Workspace of sstep_gmres_solve_noalloc: one array per device, held from
+// the first call on that device until the process ends.  Host code uses its
+// device address from hipGetSymbolAddress (taken once per device, with that
+// device current), never the array's name.
+static __device__ __align__(256) unsigned char scratch[SPAND_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;                 // guards g_scratch_ptr
+static void *g_scratch_ptr[kMaxDevices] = {};
+static std::mutex g_scratch_use[kMaxDevices];   // one no-allocation solve per device at a time
+
+static int scratch_address(int dev, void **ptr) {
+  if (dev < 0 || dev >= kMaxDevices) {
+    set_error("device %d beyond the %d devices the no-allocation scratch supports", dev, kMaxDevices);
+    return SPAND_EINVAL;
+  }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      set_error("hipGetSymbolAddress(scratch) failed on device %d: %s", dev, hipGetErrorString(e));
+      return SPAND_EHIP;
+    }
+    g_scratch_ptr[dev] = p;
+  }
+  *ptr = g_scratch_ptr[dev];
+  return SPAND_OK;
+}
+
+extern "C" {
+
+int sstep_gmres_solve(const spand_bsr_t *A, spand_factor_t M, const double *d_b, double *d_x,
+                      const sstep_opts_t *opts, sstep_stats_t *st, void *stream) {
+  set_error("");
+  SP_TRY(check_solve_args(A, M, d_b, d_x, opts));
   if (st) std::memset(st, 0, sizeof(*st));
   if (M && opts->transpose) SP_TRY(M->F.capture_graphs(2));
   try {
     return sstep_solve(*A, M ? &M->F : nullptr, d_b, d_x, *opts, st, (hipStream_t)stream);
+  } catch (const std::exception &ex) {
+    set_error("solve failed: %s", ex.what());
+    return SPAND_EINVAL;
+  }
+}
+
+int sstep_gmres_solve_noalloc(const spand_bsr_t *A, spand_factor_t M, const double *d_b,
+                              double *d_x, const sstep_opts_t *opts, sstep_stats_t *st,
+                              void *stream) {
+  set_error("");
+  SP_TRY(check_solve_args(A, M, d_b, d_x, opts));
+  const int64_t N = int64_t(A->n_brows) * A->bs;
+  const size_t need = sstep_workspace_bytes(N, *opts);
+  if (need > SPAND_NOALLOC_SCRATCH_BYTES) {
+    set_error("the solve needs %zu bytes of workspace (N = %lld, restart %d); the no-allocation "
+              "scratch holds %zu",
+              need, (long long)N, opts->restart, (size_t)SPAND_NOALLOC_SCRATCH_BYTES);
+    return SPAND_EINVAL;
+  }
+  int dev = 0;
+  SP_HIP(hipGetDevice(&dev));
+  void *ptr = nullptr;
+  SP_TRY(scratch_address(dev, &ptr));
+  if (st) std::memset(st, 0, sizeof(*st));
+  // calls on one device share its scratch: they run one at a time, and each
+  // returns only after its work on `stream` has finished
+  std::lock_guard<std::mutex> lk(g_scratch_use[dev]);
+  const SolveWorkspace ws{ptr, SPAND_NOALLOC_SCRATCH_BYTES};
+  try {
+    return sstep_solve(*A, M ? &M->F : nullptr, d_b, d_x, *opts, st, (hipStream_t)stream, &ws);
   } catch (const std::exception &ex) {
     set_error("solve failed: %s", ex.what());
     return SPAND_EINVAL;

@@ -65,3 +65,18 @@ def test_validation_before_launch():
     so = sp.sstep_opts_t(9, 45, 100, 0, 1e-8)   # s too large
     assert L.sstep_gmres_solve(C.byref(A), None, 1, 1, C.byref(so), None, None) == sp.SPAND_EINVAL
     assert L.spand_nd(C.byref(sp.spand_grid_t(0, 4, 1, 0)), 2, None, *([None] * 7)) == sp.SPAND_EINVAL
+
+
+def test_noalloc_rejects_oversize_before_launch():
+    """A solve whose workspace exceeds the no-allocation scratch is rejected
+    on the host, before any device call (dummy pointers, never used)."""
+    L = sp.lib()
+    N_brows = 200_000                       # N = 3.2M unknowns at b = 16
+    A = sp.spand_bsr_t(N_brows, 16, N_brows, 1, 1, 1)
+    so = sp.sstep_opts_t(5, 60, 100, 0, 1e-8)
+    r = L.sstep_gmres_solve_noalloc(C.byref(A), None, 1, 1, C.byref(so), None, None)
+    assert r == sp.SPAND_EINVAL
+    assert b"no-allocation scratch" in L.spand_last_error()
+    so = sp.sstep_opts_t(4, 42, 100, 0, 1e-8)  # the usual argument checks come first
+    assert L.sstep_gmres_solve_noalloc(C.byref(A), None, 1, 1, C.byref(so), None, None) == sp.SPAND_EINVAL
+    assert b"restart" in L.spand_last_error()
