@@ -10,9 +10,12 @@ Prints ONE JSON line.  Extra fields: the roofline of the dominant kernel
 (the rank-revealing QR, ALU-bound: algorithmic flops and bytes per launch from
 the factor's counters, duration from HIP events around every launch in the
 timed region; HBM traffic from the committed PMC measurement while its kernel
-source is unchanged), the SpMV roofline, a one-step comparison with the other factor
-precision, and the CPU oracle timed on a bounded sample of the same operator
-family.
+source is unchanged), the HBM rooflines of the SpMV and of the preconditioner
+apply, the matrix-core roofline of the factorization's products, the
+achievable copy and matrix-core ceilings measured on the device, the
+survey's other C3 points (L = 12; eps = 0.1), the other factor precision
+(median of three steps in a child process), and the CPU oracle timed on a
+bounded sample of the same operator family.
 """
 from __future__ import annotations
 
@@ -40,34 +43,65 @@ HBM_PEAK_GBS = 8000.0
 # FP32 vector peak: 256 CUs x 4 SIMDs x 16 lanes x 2 (dual issue) x 2 (FMA)
 # x 2.4 GHz = 157.3 TFLOP/s
 ALU_F32_PEAK_TFS = 157.3
+MFMA_F32_PEAK_TFS = 157.3   # dense FP32 matrix
+MFMA_F64_PEAK_TFS = 78.6    # dense FP64 matrix
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def host_cores():
+    """(logical CPUs this process may run on, physical cores behind them)."""
+    try:
+        cpus = sorted(os.sched_getaffinity(0))
+    except AttributeError:
+        cpus = list(range(os.cpu_count() or 1))
+    phys = set()
+    try:
+        core, pkg, cur = {}, {}, None
+        for line in open("/proc/cpuinfo"):
+            k, _, v = line.partition(":")
+            k, v = k.strip(), v.strip()
+            if k == "processor":
+                cur = int(v)
+            elif k == "core id" and cur is not None:
+                core[cur] = v
+            elif k == "physical id" and cur is not None:
+                pkg[cur] = v
+        phys = {(pkg.get(c), core.get(c)) for c in cpus if c in core}
+    except OSError:
+        pass
+    return len(cpus), (len(phys) if phys else None)
+
+
 def cpu_baseline(p, eps, s, restart, budget_s=30.0):
     """Oracle (plain FP64 numpy/scipy) on a bounded sample: a smaller grid of
-    the same operator family (same p, eps, s, restart), factor + solve."""
-    from threadpoolctl import threadpool_info
+    the same operator family (same p, eps, s, restart, leaves of about 1024
+    unknowns as on the GPU), factor + solve, BLAS threads on every physical
+    core."""
+    from threadpoolctl import threadpool_info, threadpool_limits
 
     from oracle import krylov, spand
-    from oracle.nd import default_levels, nested_dissection
+    from oracle.nd import nested_dissection
     from synth.dg_euler import DGConfig, make_problem
+    import paper_2101_01763_amd as sp
     n = 32 if p >= 3 else 48
     cfg = DGConfig(n=n, p=p)
     A, xs, b, _ = make_problem(cfg)
     As = A.to_scipy().tocsr()
-    L = default_levels(cfg.K)
-    t0 = time.perf_counter()
-    F = spand.factor(As, nested_dissection(n, n, True, False, L), cfg.b, eps)
-    t1 = time.perf_counter()
-    x, info = krylov.sstep_gmres(lambda v: As @ v, b, lambda v: spand.apply(F, v), s=s,
-                                 rtol=1e-8, restart=restart)
-    t2 = time.perf_counter()
-    threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+    L = sp.levels_for(cfg.N)
+    nproc, nphys = host_cores()
+    with threadpool_limits(limits=nphys or nproc):
+        t0 = time.perf_counter()
+        F = spand.factor(As, nested_dissection(n, n, True, False, L), cfg.b, eps)
+        t1 = time.perf_counter()
+        x, info = krylov.sstep_gmres(lambda v: As @ v, b, lambda v: spand.apply(F, v), s=s,
+                                     rtol=1e-8, restart=restart)
+        t2 = time.perf_counter()
+        threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
     return {"value": cfg.N / (t2 - t0), "unit": "DOF/s", "cores": int(threads),
-            "kind": "oracle",
+            "kind": "oracle", "nproc": nproc, "physical_cores": nphys,
             "sample": f"{n}x{n} grid, p={p} (N={cfg.N}), eps={eps}, L={L}, s={s}, m={restart}: "
                       f"factor {t1 - t0:.2f} s + solve {t2 - t1:.2f} s, {info.iters} iterations",
             "t_factor_s": t1 - t0, "t_solve_s": t2 - t1}
@@ -266,7 +300,11 @@ def main():
                          "single-reduce schedule with the second pass lagged")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true",
-                    help="skip the one-step FP64-factor comparison run")
+                    help="skip the FP64-factor comparison run (child process)")
+    ap.add_argument("--no-secondary", action="store_true",
+                    help="skip the secondary C3 points (L = 12; eps = 0.1)")
+    ap.add_argument("--no-ceilings", action="store_true",
+                    help="skip the measured copy / matrix-core ceilings")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (PMC byte-counter calibration)")
     ap.add_argument("--sweep", choices=["eps", "levels", "p", "basis"], default=None,
@@ -313,74 +351,32 @@ def main():
     dxs = torch.as_tensor(xs, device="cuda")
     del A
     torch.cuda.synchronize()
-
-    def step():
-        t0 = time.perf_counter()
-        F = sp.factor(dA, n, n, True, False, eps=eps, nlevels=L, dtype=args.dtype)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        x, info = sp.solve(dA, db, F, s=s, restart=m, rtol=1e-8,
-                           lagged=args.schedule == "lagged")
-        torch.cuda.synchronize()
-        t2 = time.perf_counter()
-        return F, x, info, t1 - t0, t2 - t1
-
-    for w in range(args.warmup):
-        F, x, info, tf, ts = step()
-        log(f"warmup {w}: factor {tf * 1e3:.1f} ms solve {ts * 1e3:.1f} ms iters {info.iters}")
-        del F
-    torch.cuda.synchronize()
-    tfs, tss, infos = [], [], []
-    spmv_ms, spmv_n = 0.0, 0
-    qrcp_ms, qrcp_n, qrcp_bytes, qrcp_flops = 0.0, 0, 0.0, 0.0
-    t_start = time.perf_counter()
-    for k in range(args.steps):
-        F, x, info, tf, ts = step()
-        tfs.append(tf)
-        tss.append(ts)
-        infos.append(info)
-        spmv_ms += info.t_spmv_ms
-        spmv_n += info.n_spmv
-        st = F.stats()
-        qrcp_ms += st["t_qrcp_ms"]
-        qrcp_n += st["n_qrcp"]
-        qrcp_bytes += st["qrcp_bytes"]
-        qrcp_flops += st["qrcp_flops"]
-        log(f"step {k}: factor {tf * 1e3:.1f} ms solve {ts * 1e3:.1f} ms iters {info.iters} "
-            f"relres {info.relres:.2e} | lu {st['t_lu_ms']:.0f} schur {st['t_schur_ms']:.0f} "
-            f"scale {st['t_scale_ms']:.0f} rrqr {st['t_rrqr_ms']:.0f} (qrcp {st['t_qrcp_ms']:.0f}) "
-            f"compress {st['t_compress_ms']:.0f} host {st['t_host_ms']:.0f} "
-            f"alloc {st['t_alloc_ms']:.0f} ms, resident {st['resident_bytes'] / 2**30:.1f} GiB | "
-            f"host plan ms " + " ".join(f"{v:.0f}" for v in st['t_plan_ms']))
-        del F
-    torch.cuda.synchronize()
-    t_total = time.perf_counter() - t_start
-    err = float(torch.linalg.norm(x - dxs) / torch.linalg.norm(dxs))
-    ms_per_step = 1e3 * t_total / args.steps
-    value = cfg.N * args.steps / t_total
     nnzb = int(dA.colind.numel())
     bsz = cfg.b
-    # SpMV algorithmic bytes per launch: values, indices, x read once, y written;
-    # the fused Newton terms read up to two more vectors (counted as 8N each when used:
-    # here we count the base contract 16N for x and y).
-    spmv_bytes = 8 * nnzb * bsz * bsz + 4 * nnzb + 4 * (cfg.K + 1) + 16 * cfg.N
-    spmv_avg_ms = spmv_ms / max(spmv_n, 1)
-    achieved = spmv_bytes / (spmv_avg_ms * 1e-3) / 1e9 if spmv_n else 0.0
-    # dominant kernel of the step: the rank-revealing QR (one launch per level)
-    q_avg_ms = qrcp_ms / max(qrcp_n, 1)
-    q_bytes_launch = qrcp_bytes / max(qrcp_n, 1)
-    q_ach = q_bytes_launch / (q_avg_ms * 1e-3) / 1e9 if qrcp_n else 0.0
-    q_flops_launch = qrcp_flops / max(qrcp_n, 1)
-    q_tfs = q_flops_launch / (q_avg_ms * 1e-3) / 1e12 if qrcp_n else 0.0
-    traffic = pmc_traffic("k_qrcp")
+    ceil = None
+    if not args.no_ceilings:
+        # achievable ceilings of this device, measured by the library's own
+        # kernels before the timed region
+        ceil = {"copy_GBs": sp.measure_bandwidth("copy", 4 << 30, 5),
+                "read_GBs": sp.measure_bandwidth("read", 4 << 30, 5),
+                "mfma_f32_TFs": sp.measure_mfma("f32", 5), "mfma_f64_TFs": sp.measure_mfma("f64", 5),
+                "kernels": "streaming copy and streaming read of 4 GiB (16-byte non-temporal "
+                           "loads/stores); loops of independent v_mfma_f32_32x32x2f32 / "
+                           "v_mfma_f64_16x16x4f64 on every CU"}
+        log(f"ceilings: copy {ceil['copy_GBs']:.0f} GB/s, read {ceil['read_GBs']:.0f} GB/s, FP32 "
+            f"MFMA {ceil['mfma_f32_TFs']:.1f} TFLOP/s, FP64 MFMA {ceil['mfma_f64_TFs']:.1f} TFLOP/s")
+
+    r = run_steps(sp, torch, dA, db, dxs, cfg, eps, L, args.dtype, s, m, args.schedule,
+                  args.steps, args.warmup, label="")
+    mfma_peak = MFMA_F32_PEAK_TFS if args.dtype == "f32" else MFMA_F64_PEAK_TFS
     out = {
         "metric": "spaND factor+s-step GMRES time to rtol 1e-8, FP32- vs FP64-spaND; DOF/s",
-        "value": value,
+        "value": r["value"],
         "unit": "DOF/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": r["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -393,37 +389,75 @@ def main():
             "n": n, "p": p, "N": cfg.N, "eps": eps, "levels": L, "s": s, "restart": m,
             "factor_dtype": args.dtype, "schedule": args.schedule,
         },
-        "t_factor_ms": 1e3 * float(np.median(tfs)),
-        "t_solve_ms": 1e3 * float(np.median(tss)),
-        "iters": infos[-1].iters,
-        "relres": infos[-1].relres,
-        "rel_err_vs_xstar": err,
-        "factor_stats": {k: v for k, v in st.items() if k.startswith("t_") or k in
-                         ("top_size", "factor_bytes", "factor_flops", "rank_avg", "rank_max")},
-        "solve_phases_ms": {"spmv": infos[-1].t_spmv_ms, "apply": infos[-1].t_apply_ms,
-                            "orth": infos[-1].t_orth_ms, "other": infos[-1].t_other_ms},
-        "solve_reductions": infos[-1].n_reduce,
-        # Arithmetic intensity of the QR (algorithmic flops over algorithmic
-        # bytes, about 60 flop/B) is above the FP32 ridge point (157.3 / 8 =
-        # 20 flop/B): the binding roof is the vector ALU, not HBM.
-        "roofline": {"kernel": "k_qrcp (column-pivoted QR of [A_sn A_ns^T], all interfaces "
-                               "of one level per launch)", "bound": "alu",
-                     "achieved": q_tfs, "peak": ALU_F32_PEAK_TFS, "unit": "TFLOP/s",
-                     "frac": q_tfs / ALU_F32_PEAK_TFS, "traffic": traffic,
-                     "flops_per_launch": q_flops_launch, "avg_launch_ms": q_avg_ms,
-                     "launches": qrcp_n,
-                     "algorithmic_flops": "sum over interfaces of 4mck - 2k^2(m+c) + 4k^3/3 "
-                                          "(k Householder-equivalent steps on m x c)",
-                     "bytes_per_launch": q_bytes_launch, "hbm_achieved_GBs": q_ach,
-                     "algorithmic_bytes": "each W (m x ncols) read once + each Q (m x m) "
-                                          "written once, factor precision"},
-        "roofline_spmv": {"kernel": "k_spmv (BSR SpMV, FP64)", "bound": "hbm",
-                          "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                          "frac": achieved / HBM_PEAK_GBS, "bytes_per_launch": spmv_bytes,
-                          "avg_launch_ms": spmv_avg_ms, "launches": spmv_n},
     }
+    out.update(r["summary"])
+    # dominant factorization kernel: the rank-revealing QR (one launch per
+    # level).  Its arithmetic intensity (algorithmic flops over algorithmic
+    # bytes, about 60 flop/B) is above the FP32 ridge point (157.3 / 8 = 20
+    # flop/B): the binding roof is the vector ALU, not HBM.
+    q = r["qrcp"]
+    out["roofline"] = {
+        "kernel": "k_qrcp (column-pivoted QR of [A_sn A_ns^T], all interfaces of one level per "
+                  "launch)", "bound": "alu",
+        "achieved": q["tflops"], "peak": ALU_F32_PEAK_TFS, "unit": "TFLOP/s",
+        "frac": q["tflops"] / ALU_F32_PEAK_TFS, "traffic": pmc_traffic("k_qrcp"),
+        "flops_per_launch": q["flops_per_launch"], "avg_launch_ms": q["avg_ms"],
+        "launches": q["launches"],
+        "algorithmic_flops": "sum over interfaces of 4mck - 2k^2(m+c) + 4k^3/3 "
+                             "(k Householder-equivalent steps on m x c)",
+        "bytes_per_launch": q["bytes_per_launch"], "hbm_achieved_GBs": q["GBs"],
+        "algorithmic_bytes": "each W (m x ncols) read once + each Q (m x m) written once, "
+                             "factor precision"}
+    sv = r["spmv"]
+    out["roofline_spmv"] = {
+        "kernel": "k_spmv (BSR SpMV, FP64)", "bound": "hbm", "achieved": sv["GBs"],
+        "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": sv["GBs"] / HBM_PEAK_GBS,
+        "bytes_per_launch": sv["bytes"], "avg_launch_ms": sv["avg_ms"], "launches": sv["launches"],
+        "algorithmic_bytes": "8 nnzb b^2 + 4 nnzb + 4 (K+1) + 16 N"}
+    ap_ = r["apply"]
+    out["roofline_apply"] = {
+        "kernel": "M^-1 r sweeps (k_gemv, k_pull, k_slot_copy replayed from a hipGraph)",
+        "bound": "hbm", "achieved": ap_["GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": ap_["GBs"] / HBM_PEAK_GBS, "bytes_per_apply": ap_["bytes"],
+        "avg_apply_ms": ap_["avg_ms"], "applies": ap_["n"],
+        "algorithmic_bytes": "every stored factor entry once per apply (A_ss^-1 in both sweeps) "
+                             "in factor precision + 16 N for the FP64 vector in and out"}
+    g = r["mfma"]
+    out["roofline_factor_mfma"] = {
+        "kernel": "factorization products on the matrix cores (k_gemm_f32_mfma / "
+                  "k_gemm_f64_mfma batched GEMMs, k_schur_elem_mfma level-0 Schur)",
+        "bound": "mfma", "achieved": g["tflops"], "peak": mfma_peak, "unit": "TFLOP/s",
+        "frac": g["tflops"] / mfma_peak, "flops_per_step": g["flops"], "ms_per_step": g["ms"],
+        "launches_per_step": g["launches"], "hbm_GBs": g["GBs"],
+        "gemm": g["gemm"], "schur_elem": g["schur"],
+        "algorithmic_flops": "2MNK per product (zero half of triangular operands excluded), "
+                             "4 b^3 per level-0 Schur coupling pair"}
+    if ceil:
+        out["ceilings_measured"] = ceil
+        out["roofline"]["frac_of_measured"] = None          # ALU roof: no matrix-core loop
+        # the SpMV and the sweeps read almost all of their bytes: against the
+        # measured streaming-read bandwidth
+        out["roofline_spmv"]["frac_of_measured"] = sv["GBs"] / ceil["read_GBs"]
+        out["roofline_apply"]["frac_of_measured"] = ap_["GBs"] / ceil["read_GBs"]
+        out["roofline_factor_mfma"]["frac_of_measured"] = g["tflops"] / (
+            ceil["mfma_f32_TFs"] if args.dtype == "f32" else ceil["mfma_f64_TFs"])
+    if not args.no_secondary and args.workload == "c3":
+        # the survey's other C3 points, same process and precision: the
+        # element rule's L = 12, and the paper's other tolerance eps = 0.1
+        sec = []
+        for e2, L2 in ((eps, 12), (1e-1, L)):
+            if (e2, L2) == (eps, L):
+                continue
+            r2 = run_steps(sp, torch, dA, db, dxs, cfg, e2, L2, args.dtype, s, m, args.schedule,
+                           3, 1, label=f"eps={e2} L={L2} ")
+            d = {"eps": e2, "levels": L2, "dof_per_s": r2["value"],
+                 "ms_per_step": r2["ms_per_step"], "steps": 3, "warmup": 1}
+            d.update(r2["summary"])
+            d["roofline_apply_GBs"] = r2["apply"]["GBs"]
+            sec.append(d)
+        out["secondary"] = sec
     if not args.no_compare:
-        # The other precision, one warm-up and one timed step, in a child
+        # The other precision, one warm-up and three timed steps, in a child
         # process: a fresh device allocator, as in a run of its own (in this
         # process the block cache and the driver hold the first precision's
         # blocks, whose sizes the other precision never asks for).
@@ -432,21 +466,25 @@ def main():
         sp.pool_trim()
         torch.cuda.empty_cache()
         cmd = [sys.executable, os.path.abspath(__file__), "--workload", args.workload,
-               "--dtype", other, "--steps", "1", "--warmup", "1", "--no-compare",
-               "--no-cpu-baseline", "--levels", str(L), "--eps", str(eps),
-               "--schedule", args.schedule]
+               "--dtype", other, "--steps", "3", "--warmup", "1", "--no-compare",
+               "--no-cpu-baseline", "--no-secondary", "--no-ceilings", "--levels", str(L),
+               "--eps", str(eps), "--schedule", args.schedule]
         log(f"comparison: {other} factor in a child process")
         try:
-            r = subprocess.run(cmd, capture_output=True, text=True, timeout=600)
-            lines = [q for q in r.stdout.strip().splitlines() if q.startswith("{")]
-            if r.returncode != 0 or not lines:
-                raise RuntimeError(f"exit {r.returncode}: {r.stderr[-500:]}")
+            rr = subprocess.run(cmd, capture_output=True, text=True, timeout=900)
+            lines = [q_ for q_ in rr.stdout.strip().splitlines() if q_.startswith("{")]
+            if rr.returncode != 0 or not lines:
+                raise RuntimeError(f"exit {rr.returncode}: {rr.stderr[-500:]}")
             c = json.loads(lines[-1])
-            out[f"compare_{other}_factor"] = {
-                "t_factor_ms": c["t_factor_ms"], "t_solve_ms": c["t_solve_ms"],
-                "iters": c["iters"], "relres": c["relres"],
-                "rel_err_vs_xstar": c["rel_err_vs_xstar"], "dof_per_s": c["value"],
-                "run": "child process, 1 warm-up + 1 timed step"}
+            keep = ("t_factor_ms", "t_solve_ms", "iters", "relres", "rel_err_vs_xstar",
+                    "factor_phases_ms", "solve_phases_ms", "t_factor_ms_min", "t_solve_ms_min")
+            d = {k: c[k] for k in keep if k in c}
+            d["dof_per_s"] = c["value"]
+            d["roofline_apply_GBs"] = c["roofline_apply"]["achieved"]
+            d["roofline_factor_mfma"] = {k: c["roofline_factor_mfma"][k] for k in
+                                         ("achieved", "peak", "frac", "unit")}
+            d["run"] = "child process, 1 warm-up + 3 timed steps (medians)"
+            out[f"compare_{other}_factor"] = d
         except (RuntimeError, subprocess.TimeoutExpired, ValueError, KeyError) as ex:
             # the comparison is context; the measured line stands without it
             log(f"comparison run failed: {ex}")
@@ -454,6 +492,108 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, eps, s, m)
     print(json.dumps(out), flush=True)
+
+
+def run_steps(sp, torch, dA, db, dxs, cfg, eps, L, dtype, s, m, schedule, steps, warmup,
+              label=""):
+    """`warmup` untimed and `steps` timed steps of (factor, solve); returns the
+    rate, per-step medians, phase times and the per-kernel rooflines over the
+    timed steps."""
+    n = cfg.n
+
+    def step():
+        t0 = time.perf_counter()
+        F = sp.factor(dA, n, n, True, False, eps=eps, nlevels=L, dtype=dtype)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        x, info = sp.solve(dA, db, F, s=s, restart=m, rtol=1e-8, lagged=schedule == "lagged")
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        return F, x, info, t1 - t0, t2 - t1
+
+    for w in range(warmup):
+        F, x, info, tf, ts = step()
+        log(f"{label}warmup {w}: factor {tf * 1e3:.1f} ms solve {ts * 1e3:.1f} ms iters {info.iters}")
+        del F
+    torch.cuda.synchronize()
+    tfs, tss, infos, sts = [], [], [], []
+    t_start = time.perf_counter()
+    for k in range(steps):
+        F, x, info, tf, ts = step()
+        st = F.stats()
+        tfs.append(tf)
+        tss.append(ts)
+        infos.append(info)
+        sts.append(st)
+        log(f"{label}step {k}: factor {tf * 1e3:.1f} ms solve {ts * 1e3:.1f} ms iters {info.iters} "
+            f"relres {info.relres:.2e} | lu {st['t_lu_ms']:.0f} schur {st['t_schur_ms']:.0f} "
+            f"scale {st['t_scale_ms']:.0f} rrqr {st['t_rrqr_ms']:.0f} (qrcp {st['t_qrcp_ms']:.0f}) "
+            f"compress {st['t_compress_ms']:.0f} host {st['t_host_ms']:.0f} "
+            f"alloc {st['t_alloc_ms']:.0f} ms | gemm {st['t_gemm_ms']:.0f} ms "
+            f"schur-mfma {st['t_schur_elem_ms']:.0f} ms | apply {info.t_apply_ms:.0f} ms "
+            f"spmv {info.t_spmv_ms:.0f} ms")
+        del F
+    torch.cuda.synchronize()
+    t_total = time.perf_counter() - t_start
+    err = float(torch.linalg.norm(x - dxs) / torch.linalg.norm(dxs))
+    N, nnzb, bsz = cfg.N, int(dA.colind.numel()), cfg.b
+    tot = lambda key: sum(q[key] for q in sts)
+    # SpMV: values, indices, x read once, y written
+    spmv_bytes = 8 * nnzb * bsz * bsz + 4 * nnzb + 4 * (cfg.K + 1) + 16 * N
+    spmv_ms = sum(i.t_spmv_ms for i in infos)
+    spmv_n = sum(i.n_spmv for i in infos)
+    spmv_avg = spmv_ms / max(spmv_n, 1)
+    # apply: every stored factor entry once per application + FP64 vector in/out
+    app_bytes = float(sts[-1]["factor_bytes"]) + 16.0 * N
+    app_ms = sum(i.t_apply_ms for i in infos)
+    app_n = sum(i.n_apply for i in infos)
+    app_avg = app_ms / max(app_n, 1)
+    q_ms, q_n = tot("t_qrcp_ms"), tot("n_qrcp")
+    q_avg = q_ms / max(q_n, 1)
+    q_fl = tot("qrcp_flops") / max(q_n, 1)
+    q_by = tot("qrcp_bytes") / max(q_n, 1)
+    g_ms, g_fl, g_by = tot("t_gemm_ms"), tot("gemm_flops"), tot("gemm_bytes")
+    c_ms, c_fl, c_by = tot("t_schur_elem_ms"), tot("schur_elem_flops"), tot("schur_elem_bytes")
+    mf_ms = g_ms + c_ms
+    med = lambda v: float(np.median(v))
+    last = sts[-1]
+    return {
+        "value": N * steps / t_total, "ms_per_step": 1e3 * t_total / steps,
+        "summary": {
+            "t_factor_ms": 1e3 * med(tfs), "t_solve_ms": 1e3 * med(tss),
+            "t_factor_ms_min": 1e3 * min(tfs), "t_solve_ms_min": 1e3 * min(tss),
+            "iters": infos[-1].iters, "relres": infos[-1].relres, "rel_err_vs_xstar": err,
+            "factor_phases_ms": {k: med([q[k] for q in sts]) for k in
+                                 ("t_host_ms", "t_lu_ms", "t_schur_ms", "t_scale_ms", "t_rrqr_ms",
+                                  "t_compress_ms", "t_qrcp_ms", "t_gemm_ms", "t_schur_elem_ms",
+                                  "t_alloc_ms")},
+            "factor_stats": {k: last[k] for k in ("top_size", "factor_bytes", "factor_flops",
+                                                  "rank_avg", "rank_max", "resident_bytes")},
+            "solve_phases_ms": {"spmv": med([i.t_spmv_ms for i in infos]),
+                                "apply": med([i.t_apply_ms for i in infos]),
+                                "orth": med([i.t_orth_ms for i in infos]),
+                                "other": med([i.t_other_ms for i in infos])},
+            "solve_reductions": infos[-1].n_reduce,
+        },
+        "spmv": {"bytes": spmv_bytes, "avg_ms": spmv_avg, "launches": spmv_n,
+                 "GBs": spmv_bytes / (spmv_avg * 1e-3) / 1e9 if spmv_n else 0.0},
+        "apply": {"bytes": app_bytes, "avg_ms": app_avg, "n": app_n,
+                  "GBs": app_bytes / (app_avg * 1e-3) / 1e9 if app_n else 0.0},
+        "qrcp": {"avg_ms": q_avg, "launches": q_n, "flops_per_launch": q_fl,
+                 "bytes_per_launch": q_by,
+                 "tflops": q_fl / (q_avg * 1e-3) / 1e12 if q_n else 0.0,
+                 "GBs": q_by / (q_avg * 1e-3) / 1e9 if q_n else 0.0},
+        "mfma": {"flops": (g_fl + c_fl) / steps, "ms": mf_ms / steps,
+                 "launches": (tot("n_gemm") + tot("n_schur_elem")) / steps,
+                 "tflops": (g_fl + c_fl) / (mf_ms * 1e-3) / 1e12 if mf_ms else 0.0,
+                 "GBs": (g_by + c_by) / (mf_ms * 1e-3) / 1e9 if mf_ms else 0.0,
+                 "gemm": {"ms_per_step": g_ms / steps, "flops_per_step": g_fl / steps,
+                          "tflops": g_fl / (g_ms * 1e-3) / 1e12 if g_ms else 0.0,
+                          "GBs": g_by / (g_ms * 1e-3) / 1e9 if g_ms else 0.0},
+                 "schur": {"ms_per_step": c_ms / steps, "flops_per_step": c_fl / steps,
+                           "tflops": c_fl / (c_ms * 1e-3) / 1e12 if c_ms else 0.0,
+                           "GBs": c_by / (c_ms * 1e-3) / 1e9 if c_ms else 0.0}},
+    }
 
 
 if __name__ == "__main__":

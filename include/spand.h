@@ -162,6 +162,15 @@ typedef struct {
      Schur, scale, RRQR, compress; the device waits when it exceeds the
      phase's device time */
   double t_plan_ms[6];
+  /* the factorization's matrix-core products (HIP events around each
+     launch): batched GEMMs (elimination, scaling, compression, completion,
+     Schur updates of levels >= 1) and the level-0 element-block Schur
+     kernel, with their algorithmic flops (2MNK per product, the zero half
+     of a triangular operand excluded; 4 b^3 per Schur coupling pair) and
+     bytes (operands read once, C read when accumulated, C written) */
+  double t_gemm_ms, gemm_flops, gemm_bytes;
+  int32_t n_gemm, n_schur_elem;
+  double t_schur_elem_ms, schur_elem_flops, schur_elem_bytes;
 } spand_factor_stats_t;
 
 typedef struct spand_factor_s *spand_factor_t;
@@ -279,6 +288,22 @@ int spand_factor_batched(int32_t n, const spand_bsr_t *A, const spand_grid_t *gr
 int sstep_gmres_solve_batched(int32_t n, const spand_bsr_t *A, const spand_factor_t *M,
                               const double *const *d_b, double *const *d_x,
                               const sstep_opts_t *opts, sstep_stats_t *st, void *stream);
+
+/*
+ * Measurement helpers: the achievable ceilings of the device, measured by
+ * this library's own kernels (to state roofline fractions against both the
+ * published peaks and what the device delivers).
+ * spand_measure_bandwidth - mode 0: streaming copy of `bytes` (16-byte
+ *   non-temporal loads and stores, grid-stride), *gbs = 2 bytes / median
+ *   time of `reps` launches (read + write); mode 1: streaming read of
+ *   `bytes`, *gbs = bytes / median time.  GB/s.  Allocates and frees the
+ *   buffers (2 x bytes for a copy).
+ * spand_measure_mfma - loops of independent matrix-core instructions on
+ *   every CU: v_mfma_f32_32x32x2f32 (dtype SPAND_F32) or
+ *   v_mfma_f64_16x16x4f64 (SPAND_F64); *tflops = flops / median time.
+ */
+int spand_measure_bandwidth(int32_t mode, size_t bytes, int reps, void *stream, double *gbs);
+int spand_measure_mfma(int32_t dtype, int reps, void *stream, double *tflops);
 
 /* spand_factor_stats - rank statistics per level (paper Figs. 4-5 report
  * ranks per level), apply bytes and algorithmic flops.  Host struct. */

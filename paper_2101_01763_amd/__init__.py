@@ -83,14 +83,18 @@ class spand_factor_stats_t(C.Structure):
                 ("t_compress_ms", C.c_double), ("t_qrcp_ms", C.c_double),
                 ("n_qrcp", C.c_int32), ("pad0", C.c_int32), ("qrcp_bytes", C.c_double),
                 ("qrcp_flops", C.c_double), ("t_alloc_ms", C.c_double),
-                ("resident_bytes", C.c_int64), ("t_plan_ms", C.c_double * 6)]
+                ("resident_bytes", C.c_int64), ("t_plan_ms", C.c_double * 6),
+                ("t_gemm_ms", C.c_double), ("gemm_flops", C.c_double),
+                ("gemm_bytes", C.c_double), ("n_gemm", C.c_int32), ("n_schur_elem", C.c_int32),
+                ("t_schur_elem_ms", C.c_double), ("schur_elem_flops", C.c_double),
+                ("schur_elem_bytes", C.c_double)]
 
 
 EXPORTS = ["spand_factor", "spand_apply", "spand_apply_T", "sstep_gmres_solve",
            "spand_bsr_spmv", "spand_bsr_pattern_outer", "spand_factor_stats",
            "spand_destroy", "spand_nd", "spand_status_string", "spand_last_error",
            "spand_factor_batched", "sstep_gmres_solve_batched", "spand_pool_trim",
-           "sstep_gmres_solve_noalloc"]
+           "sstep_gmres_solve_noalloc", "spand_measure_bandwidth", "spand_measure_mfma"]
 SPAND_NOALLOC_SCRATCH_BYTES = 64 << 20
 SPAND_FLAG_NO_GRAPH = 1
 
@@ -118,6 +122,8 @@ def lib():
         L.sstep_gmres_solve.argtypes = [C.POINTER(spand_bsr_t), vp, vp, vp,
                                         C.POINTER(sstep_opts_t), C.POINTER(sstep_stats_t), vp]
         L.sstep_gmres_solve_noalloc.argtypes = L.sstep_gmres_solve.argtypes
+        L.spand_measure_bandwidth.argtypes = [i32, C.c_size_t, C.c_int, vp, C.POINTER(dbl)]
+        L.spand_measure_mfma.argtypes = [i32, C.c_int, vp, C.POINTER(dbl)]
         L.spand_bsr_spmv.argtypes = [C.POINTER(spand_bsr_t), C.c_int, dbl, vp, dbl, vp, vp]
         L.spand_bsr_pattern_outer.argtypes = [C.POINTER(spand_bsr_t), vp, vp, dbl, vp, vp]
         L.spand_factor_stats.argtypes = [vp, C.POINTER(spand_factor_stats_t)]
@@ -271,6 +277,10 @@ class Factor:
             "qrcp_flops": st.qrcp_flops,
             "t_alloc_ms": st.t_alloc_ms, "resident_bytes": st.resident_bytes,
             "t_plan_ms": list(st.t_plan_ms),
+            "t_gemm_ms": st.t_gemm_ms, "gemm_flops": st.gemm_flops, "gemm_bytes": st.gemm_bytes,
+            "n_gemm": st.n_gemm, "t_schur_elem_ms": st.t_schur_elem_ms,
+            "schur_elem_flops": st.schur_elem_flops, "schur_elem_bytes": st.schur_elem_bytes,
+            "n_schur_elem": st.n_schur_elem,
         }
 
 
@@ -403,6 +413,24 @@ def solve_batched(As, bs, Ms=None, s=5, restart=60, rtol=1e-8, maxit=1000, lagge
     code = lib().sstep_gmres_solve_batched(n, Ac, Mh, pb, px, o, st, _stream())
     _check(code, allow=(SPAND_OK, SPAND_ENOTCONV, SPAND_EBREAKDOWN))
     return xs, [_info(code, st[i]) for i in range(n)]
+
+
+def measure_bandwidth(mode="copy", nbytes=4 << 30, reps=5):
+    """Streaming bandwidth of the device in GB/s: "copy" (read + write bytes)
+    or "read"."""
+    v = C.c_double()
+    _check(lib().spand_measure_bandwidth(0 if mode == "copy" else 1, int(nbytes), int(reps),
+                                         _stream(), C.byref(v)))
+    return v.value
+
+
+def measure_mfma(dtype="f32", reps=5):
+    """Matrix-core throughput in TFLOP/s from loops of the factorization's
+    MFMA instructions (FP32 32x32x2 or FP64 16x16x4)."""
+    v = C.c_double()
+    _check(lib().spand_measure_mfma(SPAND_F32 if dtype == "f32" else SPAND_F64, int(reps),
+                                    _stream(), C.byref(v)))
+    return v.value
 
 
 def pool_trim():

@@ -13,7 +13,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libspand.so")
 SOURCES = ["nd.cpp", "abi.hip", "factor.hip", "gmres.hip", "kernels_dense.hip",
-           "kernels_vec.hip", "kernels_krylov.hip", "autotune.hip", "pool.hip"]
+           "kernels_vec.hip", "kernels_krylov.hip", "autotune.hip", "pool.hip",
+           "ceilings.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wno-unused-result"]

@@ -117,6 +117,17 @@ struct Factor {
   double qrcp_ms = 0.0, qrcp_bytes = 0.0, qrcp_flops = 0.0;
   double alloc_ms = 0.0;
   int n_qrcp = 0;
+  // matrix-core products: events around each launch (kind 0 GEMM, 1 the
+  // level-0 Schur kernel) with the launch's algorithmic flops and bytes
+  struct KTime {
+    int kind;
+    hipEvent_t a, b;
+    double flops, bytes;
+  };
+  std::vector<KTime> kevents;
+  double kt_ms[2] = {0, 0}, kt_flops[2] = {0, 0}, kt_bytes[2] = {0, 0};
+  int kt_n[2] = {0, 0};
+  int timed_launch(int kind, double flops, double bytes, const std::function<int()> &launch);
 
   int gemv_rows = 64;              // band height of the sweep GEMVs (autotuned)
   bool use_graphs = true;          // replay the sweeps from captured hipGraphs

@@ -104,6 +104,7 @@ void Factor::release_retired() { retired.release(); }
 Factor::~Factor() {
   // a build that failed may have left work queued on its chunks
   (void)hipDeviceSynchronize();
+  collect_events();         // events of a build that stopped early
   for (auto &g : gexec)
     if (g) (void)hipGraphExecDestroy(g);
   temp.release();
@@ -173,6 +174,36 @@ void gemm_coarse(const std::vector<int32_t> &ts, size_t a, size_t b, std::vector
   }
 }
 
+// Algorithmic work of a batch of products: 2MNK flops per item (for a
+// triangular operand only its nonzero half, which is what the tiles read),
+// operands read once, C read when accumulated and written.
+static void gemm_work(const GemmDesc *d, int n, size_t esz, double *fl, double *by) {
+  for (int i = 0; i < n; ++i) {
+    const double f = 2.0 * d[i].M * d[i].N * d[i].K;
+    *fl += d[i].tri ? 0.5 * f : f;
+    *by += (double(d[i].M) * d[i].K * (d[i].tri ? 0.5 : 1.0) + double(d[i].K) * d[i].N +
+            double(d[i].M) * d[i].N * (d[i].beta != 0.0 ? 2 : 1)) * double(esz);
+  }
+}
+
+int Factor::timed_launch(int kind, double flops, double bytes, const std::function<int()> &launch) {
+  hipEvent_t a = nullptr, b = nullptr;
+  if (timing && hipEventCreate(&a) == hipSuccess) {
+    if (hipEventCreate(&b) != hipSuccess) {
+      (void)hipEventDestroy(a);
+      a = nullptr;
+    } else {
+      (void)hipEventRecord(a, stream);
+    }
+  }
+  const int r = launch();
+  if (a) {
+    (void)hipEventRecord(b, stream);
+    kevents.push_back({kind, a, b, flops, bytes});
+  }
+  return r;
+}
+
 int Factor::gemm_batch(const std::vector<GemmDesc> &items) {
   if (items.empty()) return SPAND_OK;
   if (host_trace_on()) {
@@ -229,9 +260,14 @@ int Factor::gemm_batch(const std::vector<GemmDesc> &items) {
   if (!coarse.empty()) SP_TRY(upload(coarse, &d_coarse, false));
   for (int tm = 0; tm < 4; ++tm) {
     const int a = start[tm], b = start[tm + 1];
-    if (b > a)
-      SP_TRY(launch_gemm(ft, d_items + a, d_ts + a, b - a, ts[b] - ts[a], stream, ts[a], tm, uni[tm],
-                         uni[tm] ? nullptr : d_coarse + coff[tm]));
+    if (b > a) {
+      double fl = 0.0, by = 0.0;
+      gemm_work(ord.data() + a, b - a, fsize(ft), &fl, &by);
+      SP_TRY(timed_launch(0, fl, by, [&]() {
+        return launch_gemm(ft, d_items + a, d_ts + a, b - a, ts[b] - ts[a], stream, ts[a], tm,
+                           uni[tm], uni[tm] ? nullptr : d_coarse + coff[tm]);
+      }));
+    }
   }
   return SPAND_OK;
 }
@@ -413,9 +449,14 @@ int Factor::elim_batch(std::vector<ElimDesc> &items, int mode) {
     }
     SP_TRY(launch_elim_extract(ft, d_items, nactive_at(k0), k0, lu ? 1 : 0, stream));
     const size_t g0 = bstart[b], g1 = bstart[b + 1];
-    if (g1 > g0)     // this block's descriptors; their tile numbers start at ts[g0]
-      SP_TRY(launch_gemm(ft, d_gd + g0, d_ts + g0, int(g1 - g0), ts[g1] - ts[g0], stream, ts[g0], 0,
-                         buni[b], buni[b] ? nullptr : d_coarse + boff[b]));
+    if (g1 > g0) {   // this block's descriptors; their tile numbers start at ts[g0]
+      double fl = 0.0, by = 0.0;
+      gemm_work(gd.data() + g0, int(g1 - g0), fsize(ft), &fl, &by);
+      SP_TRY(timed_launch(0, fl, by, [&]() {
+        return launch_gemm(ft, d_gd + g0, d_ts + g0, int(g1 - g0), ts[g1] - ts[g0], stream, ts[g0],
+                           0, buni[b], buni[b] ? nullptr : d_coarse + boff[b]);
+      }));
+    }
   }
   return SPAND_OK;
 }
@@ -869,7 +910,16 @@ int Factor::level0(const spand_bsr_t &A, const NDResult &nd, LevelState &S) {
     SchurItem *d_i;
     SP_TRY(upload(groups, &d_g, false));
     SP_TRY(upload(items, &d_i, false));
-    SP_TRY(launch_schur_elem(ft, b, d_g, int(groups.size()), d_i, stream));
+    {
+      // per coupling pair: two b x b products; A1, Y, A2 read, plus every
+      // target block read and written once
+      const double fl = double(items.size()) * 4.0 * b * b * b;
+      const double by = (double(items.size()) * 3.0 + 2.0 * double(groups.size())) * double(b) * b *
+                        double(tsz);
+      SP_TRY(timed_launch(1, fl, by, [&]() {
+        return launch_schur_elem(ft, b, d_g, int(groups.size()), d_i, stream);
+      }));
+    }
     trace("schur plan+launch", 0);
     flops += double(items.size()) * 4.0 * b * b * b;
   }
@@ -1988,6 +2038,14 @@ void Factor::fill_stats(spand_factor_stats_t *st) const {
   st->t_alloc_ms = alloc_ms;
   for (int p = 0; p < 6; ++p) st->t_plan_ms[p] = ph_host_ms[p];
   st->resident_bytes = int64_t(keep.bytes);
+  st->t_gemm_ms = kt_ms[0];
+  st->gemm_flops = kt_flops[0];
+  st->gemm_bytes = kt_bytes[0];
+  st->n_gemm = kt_n[0];
+  st->t_schur_elem_ms = kt_ms[1];
+  st->schur_elem_flops = kt_flops[1];
+  st->schur_elem_bytes = kt_bytes[1];
+  st->n_schur_elem = kt_n[1];
 }
 
 void Factor::collect_events() {
@@ -2006,6 +2064,16 @@ void Factor::collect_events() {
   }
   n_qrcp += int(qrcp_events.size());
   qrcp_events.clear();
+  for (auto &e : kevents) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, e.a, e.b) == hipSuccess) kt_ms[e.kind] += ms;
+    kt_flops[e.kind] += e.flops;
+    kt_bytes[e.kind] += e.bytes;
+    ++kt_n[e.kind];
+    (void)hipEventDestroy(e.a);
+    (void)hipEventDestroy(e.b);
+  }
+  kevents.clear();
 }
 
 }  // namespace spand
