@@ -478,3 +478,90 @@ def batch_configs(n_systems: int = 64, seed: int = 0, nmin: int = 32, nmax: int 
         alpha = float(rng.uniform(-4.0, 4.0))
         out.append(DGConfig(n=n, p=p, mach=mach, alpha_deg=alpha, seed=seed + i))
     return out
+
+
+# ---------------------------------------------------------------- Jacobian at a general state
+
+def element_means(cfg: DGConfig, uhat: np.ndarray) -> np.ndarray:
+    """Element-mean conserved state [K, 4] of modal coefficients (mode 0
+    carries the mean: psi_00 = 1/2, so mean = uhat[:, 0, :] / 2)."""
+    return 0.5 * uhat.reshape(cfg.K, -1, 4)[:, 0, :]
+
+
+def local_lambda(cfg: DGConfig, U: np.ndarray) -> np.ndarray:
+    """lambda_k = (2p+1)(|v| + c)/h at the per-element states U [K, 4]
+    (the length scale the paper's Eq. (8) leaves implicit)."""
+    rho, u, v, _ = conserved_to_primitive(U)
+    return (2 * cfg.p + 1) * (np.sqrt(u * u + v * v) + sound_speed(U)) / (1.0 / cfg.n)
+
+
+def jacobian(cfg: DGConfig, uhat: np.ndarray, lam_state: np.ndarray, dtau: float | None):
+    """A = M/dtau + dR/du at the modal state ``uhat`` [K, (p+1)^2, 4]: the
+    exact derivative of ``residual`` (same quadrature, LF spectral radius
+    frozen at ``lam_state``), in the block pattern of ``assemble``.  dtau =
+    None leaves the mass term out.  Returns a BSR matrix."""
+    p = cfg.p
+    q = p + 1
+    hh = 0.5 / cfg.n
+    xg, wg = _gauss(p + 2)
+    V, D = _legendre_vals(p, xg)
+    Pp, Pm = legendre_trace(p)
+    K = cfg.K
+    bsz = cfg.b
+    uh = uhat.reshape(K, q, q, 4)
+    rowptr, colind, slots, (R_, L_, T_, B_) = _pattern(cfg)
+    val = np.zeros((colind.shape[0], bsz, bsz))
+    W = np.outer(wg, wg)
+
+    def put(slot, blk):
+        # blk [k, a, b, c, a', b', c'] -> rows 4(a q + b) + c, cols 4(a' q + b') + c'
+        val[slot] += blk.reshape(-1, bsz, bsz)
+
+    # volume: -(h/2) sum_rs W [A(U) D_a V_b + B(U) V_a D_b] V_a' V_b'
+    Uq = np.einsum("kabc,ar,bs->krsc", uh, V, V)
+    Ax, By = flux_jacobians(Uq)                         # [K, r, s, 4, 4]
+    blk = -hh * (np.einsum("rs,ar,bs,krsij,er,fs->kabiefj", W, D, V, Ax, V, V)
+                 + np.einsum("rs,ar,bs,krsij,er,fs->kabiefj", W, V, D, By, V, V))
+    put(slots[0], blk)
+    Uinf = freestream(cfg)
+    I4 = np.eye(4)
+    faces = [(R_, slots[1], 1.0, 0.0, +1, "x"), (L_, slots[2], -1.0, 0.0, -1, "x"),
+             (T_, slots[3], 0.0, 1.0, +1, "y"), (B_, slots[4], 0.0, -1.0, -1, "y")]
+    for nbr, slot, nx, ny, side, ax in faces:
+        inner = nbr >= 0
+        lamN = np.where(inner[:, None], lam_state[np.maximum(nbr, 0)], Uinf[None, :])
+        lam = face_lambda(lam_state, lamN, nx, ny)          # [K]
+        t_in = Pp if side > 0 else Pm                        # this element's trace
+        t_out = Pm if side > 0 else Pp                       # the neighbour's
+        if ax == "x":
+            UL = np.einsum("kabc,a,bs->ksc", uh, t_in, V)
+            UR = np.einsum("kabc,a,bs->ksc", uh[np.maximum(nbr, 0)], t_out, V)
+        else:
+            UL = np.einsum("kabc,b,as->ksc", uh, t_in, V)
+            UR = np.einsum("kabc,b,as->ksc", uh[np.maximum(nbr, 0)], t_out, V)
+        AL, BL = flux_jacobians(UL)
+        AR, BR = flux_jacobians(UR)
+        JL = 0.5 * (nx * AL + ny * BL + lam[:, None, None, None] * I4)   # dF*/dU_L [K, s, 4, 4]
+        JR = 0.5 * (nx * AR + ny * BR - lam[:, None, None, None] * I4)   # dF*/dU_R
+        if ax == "x":
+            # test t_in(a) V_b(s), trial t(a') V_b'(s)
+            self_blk = hh * np.einsum("s,a,bs,ksij,e,fs->kabiefj", wg, t_in, V, JL, t_in, V)
+            nb_blk = hh * np.einsum("s,a,bs,ksij,e,fs->kabiefj", wg, t_in, V, JR, t_out, V)
+        else:
+            self_blk = hh * np.einsum("s,b,as,ksij,f,es->kabiefj", wg, t_in, V, JL, t_in, V)
+            nb_blk = hh * np.einsum("s,b,as,ksij,f,es->kabiefj", wg, t_in, V, JR, t_out, V)
+        put(slots[0], self_blk)
+        if inner.any():
+            put(slot[inner], nb_blk[inner])
+    if dtau is not None:
+        idx = np.arange(bsz)
+        val[slots[0][:, None], idx[None, :], idx[None, :]] += hh * hh / dtau
+    return BSR(K, bsz, rowptr, colind.astype(np.int32), val)
+
+
+def initial_state(cfg: DGConfig) -> np.ndarray:
+    """Seeded start of the pseudo-transient loop: the smooth perturbed base
+    state of ``assemble`` (same phases), as modal coefficients."""
+    rng = np.random.default_rng(cfg.seed)
+    U = base_state(cfg, draw_phases(rng))
+    return state_to_modal(cfg, U)
