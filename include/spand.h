@@ -202,6 +202,22 @@ int spand_factor(const spand_bsr_t *A, const spand_grid_t *grid,
  */
 int spand_apply(spand_factor_t F, const double *d_in, double *d_out, void *stream);
 
+/*
+ * spand_refactor - rebuild the factorization held by F for new values of a
+ * matrix with the same block pattern and grid (the next nonlinear step of a
+ * pseudo-transient solve, paper Sec. "Flow Solver", Eqs. (5), (8), (9): the
+ * factorization is computed at every nonlinear step, the partitioning is
+ * pre-processing, Sec. "Scalability study of spaND").  Reuses F's symbolic
+ * phase (the validated block pattern and the nested dissection) with F's
+ * options; every numeric phase runs again (the ranks depend on the values).
+ * A is borrowed for the call.  Returns SPAND_EINVAL, before any launch, if
+ * A's sizes or block pattern (compared on the host) differ from F's; any
+ * other failure leaves F's previous factorization in place.  The previous
+ * factorization stays allocated until the new one is built (peak memory
+ * holds both).  Stream-ordered like spand_factor.
+ */
+int spand_refactor(spand_factor_t F, const spand_bsr_t *A, void *stream);
+
 /* spand_apply_T - d_out = M^{-T} d_in, the exact transpose of spand_apply
  * (same factors, transposed sweeps).  Same arguments and rules. */
 int spand_apply_T(spand_factor_t F, const double *d_in, double *d_out, void *stream);

@@ -94,7 +94,8 @@ EXPORTS = ["spand_factor", "spand_apply", "spand_apply_T", "sstep_gmres_solve",
            "spand_bsr_spmv", "spand_bsr_pattern_outer", "spand_factor_stats",
            "spand_destroy", "spand_nd", "spand_status_string", "spand_last_error",
            "spand_factor_batched", "sstep_gmres_solve_batched", "spand_pool_trim",
-           "sstep_gmres_solve_noalloc", "spand_measure_bandwidth", "spand_measure_mfma"]
+           "sstep_gmres_solve_noalloc", "spand_measure_bandwidth", "spand_measure_mfma",
+           "spand_refactor"]
 SPAND_NOALLOC_SCRATCH_BYTES = 64 << 20
 SPAND_FLAG_NO_GRAPH = 1
 
@@ -118,6 +119,7 @@ def lib():
         L.spand_factor.argtypes = [C.POINTER(spand_bsr_t), C.POINTER(spand_grid_t),
                                    C.POINTER(spand_opts_t), vp, C.POINTER(vp)]
         L.spand_apply.argtypes = [vp, vp, vp, vp]
+        L.spand_refactor.argtypes = [vp, C.POINTER(spand_bsr_t), vp]
         L.spand_apply_T.argtypes = [vp, vp, vp, vp]
         L.sstep_gmres_solve.argtypes = [C.POINTER(spand_bsr_t), vp, vp, vp,
                                         C.POINTER(sstep_opts_t), C.POINTER(sstep_stats_t), vp]
@@ -240,6 +242,15 @@ class Factor:
         if self._h:
             lib().spand_destroy(self._h)
             self._h = None
+
+    def refactor(self, A, val=None):
+        """Rebuild this factorization for new values of a matrix with the
+        same block pattern (reuses the nested dissection and the pattern)."""
+        Ac = A.c(val)
+        if A.N != self.N:
+            raise ValueError(f"A has {A.N} unknowns, the factor {self.N}")
+        _check(lib().spand_refactor(self._h, C.byref(Ac), _stream()))
+        return self
 
     def apply(self, r, out=None):
         import torch

@@ -18,7 +18,7 @@
 #include "factor.h"
 
 struct spand_factor_s {
-  spand::Factor F;
+  std::unique_ptr<spand::Factor> F;
 };
 
 namespace spand {
@@ -85,6 +85,12 @@ const char *spand_last_error(void) { return last_error(); }
 // Validate, build, and (when `graphs`) capture the sweep graphs.  Batched
 // callers build on worker threads with graphs=false and capture afterwards,
 // once the workers have joined.
+// Builds a factorization on a private stream ordered after `stream`; with
+// `sym` the ordering and the validated block pattern (the symbolic phase)
+// are taken from that earlier factorization of the same pattern.
+static int build_factor(const spand_bsr_t *A, const spand_grid_t *grid, const spand_opts_t *opts,
+                        void *stream, const Factor *sym, bool graphs, std::unique_ptr<Factor> &out);
+
 static int factor_one(const spand_bsr_t *A, const spand_grid_t *grid, const spand_opts_t *opts,
                       void *stream, spand_factor_t *out, bool graphs) {
   if (!out) {
@@ -120,6 +126,15 @@ static int factor_one(const spand_bsr_t *A, const spand_grid_t *grid, const span
     return SPAND_EINVAL;
   }
   auto h = std::make_unique<spand_factor_s>();
+  SP_TRY(build_factor(A, grid, opts, stream, nullptr, graphs, h->F));
+  *out = h.release();
+  return SPAND_OK;
+}
+
+static int build_factor(const spand_bsr_t *A, const spand_grid_t *grid, const spand_opts_t *opts,
+                        void *stream, const Factor *sym, bool graphs, std::unique_ptr<Factor> &out) {
+  auto h = std::make_unique<spand_factor_s>();
+  h->F = std::make_unique<Factor>();
   // The build runs on a private non-blocking stream ordered after the
   // caller's: its descriptor uploads (synchronous copies on the null
   // stream) then never wait for the factorization's own kernels, so the
@@ -135,12 +150,12 @@ static int factor_one(const spand_bsr_t *A, const spand_grid_t *grid, const span
     set_error("could not order the factorization after the caller's stream");
     return SPAND_EHIP;
   }
-  h->F.stream = ps;
-  h->F.timing = true;
-  (void)hipGetDevice(&h->F.device);
+  h->F->stream = ps;
+  h->F->timing = true;
+  (void)hipGetDevice(&h->F->device);
   int r;
   try {
-    r = h->F.build(*A, *grid, *opts);
+    r = h->F->build(*A, *grid, *opts, sym);
   } catch (const std::exception &ex) {
     set_error("factorization failed: %s", ex.what());
     r = SPAND_EINVAL;
@@ -148,12 +163,12 @@ static int factor_one(const spand_bsr_t *A, const spand_grid_t *grid, const span
   (void)hipStreamSynchronize(ps);
   (void)hipEventDestroy(ready);
   (void)hipStreamDestroy(ps);
-  h->F.stream = nullptr;
+  h->F->stream = nullptr;
   if (r != SPAND_OK) return r;
-  h->F.trace("build end", -1);
-  if (graphs) SP_TRY(h->F.capture_graphs(1));
-  h->F.trace("graph capture", -1);
-  *out = h.release();
+  h->F->trace("build end", -1);
+  if (graphs) SP_TRY(h->F->capture_graphs(1));
+  h->F->trace("graph capture", -1);
+  out = std::move(h->F);
   return SPAND_OK;
 }
 
@@ -165,12 +180,48 @@ int spand_factor(const spand_bsr_t *A, const spand_grid_t *grid, const spand_opt
   return factor_one(A, grid, opts, stream, out, true);
 }
 
+int spand_refactor(spand_factor_t F, const spand_bsr_t *A, void *stream) {
+  set_error("");
+  if (!F || !F->F) {
+    set_error("F is NULL");
+    return SPAND_EINVAL;
+  }
+  SP_TRY(check_bsr(A));
+  Factor &old = *F->F;
+  if (A->n_brows != old.K || A->bs != old.bs || A->nnzb != int64_t(old.h_colind.size())) {
+    set_error("A (n_brows %d, bs %d, nnzb %lld) does not have the factored pattern (%d, %d, %zu)",
+              A->n_brows, A->bs, (long long)A->nnzb, old.K, old.bs, old.h_colind.size());
+    return SPAND_EINVAL;
+  }
+  {
+    // the symbolic phase is only valid for the same block pattern
+    std::vector<int32_t> rp(size_t(A->n_brows) + 1), ci(size_t(A->nnzb));
+    hipStream_t st = (hipStream_t)stream;
+    SP_HIP(hipMemcpyAsync(rp.data(), A->d_rowptr, rp.size() * 4, hipMemcpyDeviceToHost, st));
+    SP_HIP(hipMemcpyAsync(ci.data(), A->d_colind, ci.size() * 4, hipMemcpyDeviceToHost, st));
+    SP_HIP(hipStreamSynchronize(st));
+    if (rp != old.h_rowptr || ci != old.h_colind) {
+      set_error("A's block pattern differs from the factored one");
+      return SPAND_EINVAL;
+    }
+  }
+  std::unique_ptr<Factor> nf;
+  try {
+    SP_TRY(build_factor(A, &old.grid, &old.opts, stream, &old, old.use_graphs, nf));
+  } catch (const std::exception &ex) {
+    set_error("refactorization failed: %s", ex.what());
+    return SPAND_EINVAL;
+  }
+  F->F = std::move(nf);        // the previous factorization is released here
+  return SPAND_OK;
+}
+
 int spand_apply(spand_factor_t F, const double *d_in, double *d_out, void *stream) {
   if (!F || !d_in || !d_out) {
     set_error("NULL argument");
     return SPAND_EINVAL;
   }
-  return F->F.apply(d_in, d_out, 0, (hipStream_t)stream);
+  return F->F->apply(d_in, d_out, 0, (hipStream_t)stream);
 }
 
 int spand_apply_T(spand_factor_t F, const double *d_in, double *d_out, void *stream) {
@@ -178,8 +229,8 @@ int spand_apply_T(spand_factor_t F, const double *d_in, double *d_out, void *str
     set_error("NULL argument");
     return SPAND_EINVAL;
   }
-  SP_TRY(F->F.capture_graphs(2));
-  return F->F.apply(d_in, d_out, 1, (hipStream_t)stream);
+  SP_TRY(F->F->capture_graphs(2));
+  return F->F->apply(d_in, d_out, 1, (hipStream_t)stream);
 }
 
 }  // extern "C"
@@ -204,7 +255,7 @@ static int check_solve_args(const spand_bsr_t *A, spand_factor_t M, const double
     set_error("maxit must be >= 1 and rtol > 0");
     return SPAND_EINVAL;
   }
-  if (M && (int64_t(M->F.N) != int64_t(A->n_brows) * A->bs)) {
+  if (M && (int64_t(M->F->N) != int64_t(A->n_brows) * A->bs)) {
     set_error("factor size does not match A");
     return SPAND_EINVAL;
   }
@@ -249,9 +300,9 @@ int sstep_gmres_solve(const spand_bsr_t *A, spand_factor_t M, const double *d_b,
   set_error("");
   SP_TRY(check_solve_args(A, M, d_b, d_x, opts));
   if (st) std::memset(st, 0, sizeof(*st));
-  if (M && opts->transpose) SP_TRY(M->F.capture_graphs(2));
+  if (M && opts->transpose) SP_TRY(M->F->capture_graphs(2));
   try {
-    return sstep_solve(*A, M ? &M->F : nullptr, d_b, d_x, *opts, st, (hipStream_t)stream);
+    return sstep_solve(*A, M ? M->F.get() : nullptr, d_b, d_x, *opts, st, (hipStream_t)stream);
   } catch (const std::exception &ex) {
     set_error("solve failed: %s", ex.what());
     return SPAND_EINVAL;
@@ -281,7 +332,7 @@ int sstep_gmres_solve_noalloc(const spand_bsr_t *A, spand_factor_t M, const doub
   std::lock_guard<std::mutex> lk(g_scratch_use[dev]);
   const SolveWorkspace ws{ptr, SPAND_NOALLOC_SCRATCH_BYTES};
   try {
-    return sstep_solve(*A, M ? &M->F : nullptr, d_b, d_x, *opts, st, (hipStream_t)stream, &ws);
+    return sstep_solve(*A, M ? M->F.get() : nullptr, d_b, d_x, *opts, st, (hipStream_t)stream, &ws);
   } catch (const std::exception &ex) {
     set_error("solve failed: %s", ex.what());
     return SPAND_EINVAL;
@@ -432,7 +483,7 @@ int spand_factor_batched(int32_t n, const spand_bsr_t *A, const spand_grid_t *gr
   for (int i = 0; i < n; ++i)
     if (st[i] < 0) return st[i];
   for (int i = 0; i < n; ++i) {
-    const int r = out[i]->F.capture_graphs();
+    const int r = out[i]->F->capture_graphs();
     if (r != SPAND_OK) {
       set_error("system %d: %s", i, std::string(last_error()).c_str());
       return r;
@@ -451,7 +502,7 @@ int sstep_gmres_solve_batched(int32_t n, const spand_bsr_t *A, const spand_facto
   }
   // transposed sweeps are captured here, before any worker thread exists
   for (int i = 0; i < n; ++i)
-    if (M && M[i] && opts[i].transpose) SP_TRY(M[i]->F.capture_graphs(2));
+    if (M && M[i] && opts[i].transpose) SP_TRY(M[i]->F->capture_graphs(2));
   // systems that share a factor handle share its scratch vectors: they run
   // one after the other on one worker stream
   std::vector<int> group(n, -1);
@@ -484,7 +535,7 @@ int spand_factor_stats(spand_factor_t F, spand_factor_stats_t *out) {
     set_error("NULL argument");
     return SPAND_EINVAL;
   }
-  F->F.fill_stats(out);
+  F->F->fill_stats(out);
   return SPAND_OK;
 }
 

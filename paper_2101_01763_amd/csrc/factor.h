@@ -4,6 +4,7 @@
 #include <chrono>
 #include <functional>
 #include <map>
+#include <memory>
 #include <vector>
 
 #include "internal.h"
@@ -94,6 +95,11 @@ struct Factor {
   int64_t N = 0;
   double eps = 0.0;
   std::vector<int32_t> h_rowptr, h_colind;
+  // symbolic phase, reused by refactorizations of the same pattern: the
+  // validated block pattern above, the nested dissection, grid and options
+  std::shared_ptr<const NDResult> nd_sym;
+  spand_grid_t grid{};
+  spand_opts_t opts{};
   std::vector<ApplyLevel> lv;
   Bump keep, temp, next_temp;   // next_temp: next level's trailing blocks
   Bump retired;                 // scratch of finished levels, released at the next sync
@@ -162,7 +168,8 @@ struct Factor {
   int level0(const spand_bsr_t &A, const NDResult &nd, LevelState &S);
   int eliminate_dense(int l, LevelState &S);
   int sparsify(int l, const NDResult &nd, LevelState &S, LevelState &Nx);
-  int build(const spand_bsr_t &A, const spand_grid_t &g, const spand_opts_t &o);
+  int build(const spand_bsr_t &A, const spand_grid_t &g, const spand_opts_t &o,
+            const Factor *sym = nullptr);
   int apply(const double *in, double *out, int transpose, hipStream_t st);
   void fill_stats(spand_factor_stats_t *st) const;
 };

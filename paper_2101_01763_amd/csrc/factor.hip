@@ -1820,7 +1820,8 @@ int Factor::sparsify(int l, const NDResult &nd, LevelState &S, LevelState &Nx) {
 }
 
 // ------------------------------------------------------------------ driver
-int Factor::build(const spand_bsr_t &A, const spand_grid_t &g, const spand_opts_t &o) {
+int Factor::build(const spand_bsr_t &A, const spand_grid_t &g, const spand_opts_t &o,
+                  const Factor *sym) {
   auto t0 = std::chrono::steady_clock::now();
   trace_t = t0;
   const double drv0 = pool_driver_ms();
@@ -1830,31 +1831,44 @@ int Factor::build(const spand_bsr_t &A, const spand_grid_t &g, const spand_opts_
   ft = o.factor_dtype == SPAND_F32 ? FType::F32 : FType::F64;
   eps = o.eps;
   L = o.nlevels > 0 ? o.nlevels : default_levels(K);
-  h_rowptr.resize(K + 1);
-  h_colind.resize(A.nnzb);
-  SP_HIP(hipMemcpyAsync(h_rowptr.data(), A.d_rowptr, (K + 1) * 4, hipMemcpyDeviceToHost, stream));
-  SP_HIP(hipMemcpyAsync(h_colind.data(), A.d_colind, A.nnzb * 4, hipMemcpyDeviceToHost, stream));
-  SP_HIP(hipStreamSynchronize(stream));
-  trace("sync", -1);
-  if (h_rowptr[0] != 0 || h_rowptr[K] != A.nnzb) {
-    set_error("rowptr[0] must be 0 and rowptr[n_brows] must equal nnzb");
-    return SPAND_EINVAL;
-  }
-  for (int e = 0; e < K; ++e) {
-    if (h_rowptr[e + 1] < h_rowptr[e]) {
-      set_error("rowptr must be non-decreasing");
+  grid = g;
+  opts = o;
+  if (sym) {
+    // refactorization: the pattern (checked by the caller) and the ordering
+    // of the earlier factorization; only the numeric phases run again
+    h_rowptr = sym->h_rowptr;
+    h_colind = sym->h_colind;
+    nd_sym = sym->nd_sym;
+    trace("symbolic phase reused", -1);
+  } else {
+    h_rowptr.resize(K + 1);
+    h_colind.resize(A.nnzb);
+    SP_HIP(hipMemcpyAsync(h_rowptr.data(), A.d_rowptr, (K + 1) * 4, hipMemcpyDeviceToHost, stream));
+    SP_HIP(hipMemcpyAsync(h_colind.data(), A.d_colind, A.nnzb * 4, hipMemcpyDeviceToHost, stream));
+    SP_HIP(hipStreamSynchronize(stream));
+    trace("sync", -1);
+    if (h_rowptr[0] != 0 || h_rowptr[K] != A.nnzb) {
+      set_error("rowptr[0] must be 0 and rowptr[n_brows] must equal nnzb");
       return SPAND_EINVAL;
     }
-    for (int t = h_rowptr[e]; t < h_rowptr[e + 1]; ++t) {
-      if (h_colind[t] < 0 || h_colind[t] >= K || (t > h_rowptr[e] && h_colind[t] <= h_colind[t - 1])) {
-        set_error("colind must be in range and strictly ascending in every block row (row %d)", e);
+    for (int e = 0; e < K; ++e) {
+      if (h_rowptr[e + 1] < h_rowptr[e]) {
+        set_error("rowptr must be non-decreasing");
         return SPAND_EINVAL;
       }
+      for (int t = h_rowptr[e]; t < h_rowptr[e + 1]; ++t) {
+        if (h_colind[t] < 0 || h_colind[t] >= K || (t > h_rowptr[e] && h_colind[t] <= h_colind[t - 1])) {
+          set_error("colind must be in range and strictly ascending in every block row (row %d)", e);
+          return SPAND_EINVAL;
+        }
+      }
     }
+    trace("read pattern + validate", -1);
+    nd_sym = std::make_shared<const NDResult>(
+        nested_dissection(g.nx, g.ny, g.periodic_x != 0, g.periodic_y != 0, L));
+    trace("nested dissection", -1);
   }
-  trace("read pattern + validate", -1);
-  NDResult nd = nested_dissection(g.nx, g.ny, g.periodic_x != 0, g.periodic_y != 0, L);
-  trace("nested dissection", -1);
+  const NDResult &nd = *nd_sym;
   void *p;
   SP_TRY(dalloc(&p, size_t(N) * 4, true));
   d_iota = (int32_t *)p;
