@@ -520,8 +520,8 @@ def jacobian(cfg: DGConfig, uhat: np.ndarray, lam_state: np.ndarray, dtau: float
     # volume: -(h/2) sum_rs W [A(U) D_a V_b + B(U) V_a D_b] V_a' V_b'
     Uq = np.einsum("kabc,ar,bs->krsc", uh, V, V)
     Ax, By = flux_jacobians(Uq)                         # [K, r, s, 4, 4]
-    blk = -hh * (np.einsum("rs,ar,bs,krsij,er,fs->kabiefj", W, D, V, Ax, V, V)
-                 + np.einsum("rs,ar,bs,krsij,er,fs->kabiefj", W, V, D, By, V, V))
+    blk = -hh * (np.einsum("rs,ar,bs,krsij,er,fs->kabiefj", W, D, V, Ax, V, V, optimize=True)
+                 + np.einsum("rs,ar,bs,krsij,er,fs->kabiefj", W, V, D, By, V, V, optimize=True))
     put(slots[0], blk)
     Uinf = freestream(cfg)
     I4 = np.eye(4)
@@ -545,11 +545,11 @@ def jacobian(cfg: DGConfig, uhat: np.ndarray, lam_state: np.ndarray, dtau: float
         JR = 0.5 * (nx * AR + ny * BR - lam[:, None, None, None] * I4)   # dF*/dU_R
         if ax == "x":
             # test t_in(a) V_b(s), trial t(a') V_b'(s)
-            self_blk = hh * np.einsum("s,a,bs,ksij,e,fs->kabiefj", wg, t_in, V, JL, t_in, V)
-            nb_blk = hh * np.einsum("s,a,bs,ksij,e,fs->kabiefj", wg, t_in, V, JR, t_out, V)
+            self_blk = hh * np.einsum("s,a,bs,ksij,e,fs->kabiefj", wg, t_in, V, JL, t_in, V, optimize=True)
+            nb_blk = hh * np.einsum("s,a,bs,ksij,e,fs->kabiefj", wg, t_in, V, JR, t_out, V, optimize=True)
         else:
-            self_blk = hh * np.einsum("s,b,as,ksij,f,es->kabiefj", wg, t_in, V, JL, t_in, V)
-            nb_blk = hh * np.einsum("s,b,as,ksij,f,es->kabiefj", wg, t_in, V, JR, t_out, V)
+            self_blk = hh * np.einsum("s,b,as,ksij,f,es->kabiefj", wg, t_in, V, JL, t_in, V, optimize=True)
+            nb_blk = hh * np.einsum("s,b,as,ksij,f,es->kabiefj", wg, t_in, V, JR, t_out, V, optimize=True)
         put(slots[0], self_blk)
         if inner.any():
             put(slot[inner], nb_blk[inner])
