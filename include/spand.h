@@ -262,7 +262,10 @@ int sstep_gmres_solve_noalloc(const spand_bsr_t *A, spand_factor_t M, const doub
 
 /*
  * spand_bsr_spmv - d_y = alpha * op(A) d_x + beta * d_y, op = A or A^T
- * (the SpMV of Algorithms 1 and 2).  float64.  d_x != d_y.
+ * (the SpMV of Algorithms 1 and 2).  float64.  d_x != d_y.  A^T reads the
+ * mirror block (J, I) of every stored (I, J) in place: the block pattern
+ * must be structurally symmetric, which is checked first (SPAND_EINVAL,
+ * after a synchronisation of `stream`, before the product).
  */
 int spand_bsr_spmv(const spand_bsr_t *A, int transpose, double alpha, const double *d_x,
                    double beta, double *d_y, void *stream);
