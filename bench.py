@@ -125,9 +125,12 @@ def bench_batch(args):
     """C4: 64 uneven seeded systems (n ~ U{32..96}, p ~ U{1,2,3},
     M ~ U[0.3,0.7], alpha ~ U[-4,4] deg), FP32 spaND eps=1e-2, s=5, m=60,
     rtol 1e-8; factored and solved concurrently (batched entry points,
-    graph-replayed sweeps, autotuned SpMV/GEMV shapes).  value = total DOF /
-    wall time of one batched factor+solve; the same batch on one stream is
-    timed beside it."""
+    graph-replayed sweeps, autotuned SpMV/GEMV shapes).  The systems of one
+    block size are factored together (one set of launches per phase for a
+    group of up to 4M unknowns); each is solved on its own worker stream.
+    value = total DOF / wall time of one batched factor+solve; the same batch
+    with every system factored on its own (8 streams, then 1) is timed
+    beside it."""
     import torch
 
     import paper_2101_01763_amd as sp
@@ -144,8 +147,11 @@ def bench_batch(args):
     log(f"generated 64 systems, {ntot} DOF in {time.time() - t:.1f} s")
     torch.cuda.synchronize()
 
-    def run(streams):
+    extra = {}
+
+    def run(streams, separate=False, probe=False):
         os.environ["SPAND_BATCH_STREAMS"] = str(streams)
+        os.environ["SPAND_BATCH_SEPARATE"] = "1" if separate else "0"
         t0 = time.perf_counter()
         Fs = sp.factor_batched(systems, eps=1e-2, nlevels=Ls, dtype="f32")
         torch.cuda.synchronize()
@@ -154,17 +160,38 @@ def bench_batch(args):
                                      lagged=args.schedule == "lagged")
         torch.cuda.synchronize()
         t2 = time.perf_counter()
+        if probe:
+            # the shared factorizations, and one apply of every system: one
+            # replay per shared sweep graph against one apply per handle
+            extra["shared_factorizations"] = int(round(sum(1.0 / F.stats()["batch_systems"]
+                                                           for F in Fs)))
+            outs = [torch.empty_like(b) for b in rhs]
+            sp.apply_batched(Fs, rhs, outs)
+            torch.cuda.synchronize()
+            tb = []
+            for _ in range(5):
+                t3 = time.perf_counter()
+                sp.apply_batched(Fs, rhs, outs)
+                torch.cuda.synchronize()
+                tb.append(time.perf_counter() - t3)
+            t3 = time.perf_counter()
+            for F, b, o in zip(Fs, rhs, outs):
+                F.apply(b, out=o)
+            torch.cuda.synchronize()
+            extra["apply_all_ms"] = {"batched_graphs": 1e3 * float(np.median(tb)),
+                                     "per_handle": 1e3 * (time.perf_counter() - t3)}
         for F in Fs:
             F.destroy()
         return t1 - t0, t2 - t1, infos
 
     for _ in range(args.warmup):
         run(8)
-    res = [run(8) for _ in range(args.steps)]
+    res = [run(8, probe=(k == 0)) for k in range(args.steps)]
     tf = float(np.median([r[0] for r in res]))
     ts = float(np.median([r[1] for r in res]))
     infos = res[-1][2]
-    seq = run(1)
+    sep = run(8, separate=True)
+    seq = run(1, separate=True)
     out = {
         "metric": "batched spaND factor + s-step GMRES (64 uneven systems); DOF/s",
         "value": ntot / (tf + ts), "unit": "DOF/s", "n_gpus": 1, "steps": args.steps,
@@ -172,11 +199,17 @@ def bench_batch(args):
         "scaling": "weak", "vs_baseline": None, "dtype": "f32 (spaND) + f64 (Krylov)",
         "data": "synthetic (64 seeded DG-Euler systems)",
         "config": {"workload": f"C4 batch: 64 systems, {ntot} DOF total, n in 32..96, p in 1..3, "
-                               f"FP32 spaND eps=1e-2, s=5, m=60, rtol=1e-8 ({args.schedule}), "
-                               f"8 streams", "schedule": args.schedule},
+                               f"FP32 spaND eps=1e-2, s=5, m=60, rtol=1e-8 ({args.schedule}); "
+                               f"systems of one block size factored together (groups of up to 4M "
+                               f"unknowns, 2 at a time), solves on 8 streams",
+                   "schedule": args.schedule},
         "t_factor_ms": 1e3 * tf, "t_solve_ms": 1e3 * ts,
         "all_converged": all(i.converged for i in infos),
         "iters_min_max": [min(i.iters for i in infos), max(i.iters for i in infos)],
+        "shared_factorizations": extra.get("shared_factorizations"),
+        "apply_all_ms": extra.get("apply_all_ms"),
+        "separate_factorizations": {"t_factor_ms": 1e3 * sep[0], "t_solve_ms": 1e3 * sep[1],
+                                    "dof_per_s": ntot / (sep[0] + sep[1])},
         "one_stream": {"t_factor_ms": 1e3 * seq[0], "t_solve_ms": 1e3 * seq[1],
                        "dof_per_s": ntot / (seq[0] + seq[1])},
     }

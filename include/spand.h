@@ -171,6 +171,14 @@ typedef struct {
   double t_gemm_ms, gemm_flops, gemm_bytes;
   int32_t n_gemm, n_schur_elem;
   double t_schur_elem_ms, schur_elem_flops, schur_elem_bytes;
+  /* systems factored together (1 unless the handle comes from
+     spand_factor_batched and shares its factorization with other systems of
+     the batch: then the ranks, top_size, factor_bytes and factor_flops
+     above are this system's own, and the times, counts and bytes of the
+     kernels, resident_bytes and t_host_ms are those of the shared
+     factorization) */
+  int32_t batch_systems;
+  int32_t pad1;
 } spand_factor_stats_t;
 
 typedef struct spand_factor_s *spand_factor_t;
@@ -282,20 +290,51 @@ int spand_bsr_pattern_outer(const spand_bsr_t *pattern, const double *d_u,
 
 /*
  * spand_factor_batched - factor n independent systems of possibly different
- * sizes (A[i], grids[i], opts[i]).  The systems run concurrently on
- * library-owned HIP streams from a pool of host workers (SPAND_BATCH_STREAMS,
- * default 8); the call waits on `stream` first and makes `stream` wait for
- * all of them at the end, so results are ordered on `stream` as usual.
- * out[i] receives each handle (NULL for a system that failed).  Returns
- * SPAND_OK, or the first negative status (out[] still holds the successful
- * handles, which the caller destroys).
+ * sizes (A[i], grids[i], opts[i]; each is checked as by spand_factor before
+ * any work).  The systems with the same block size, factor precision, eps
+ * and flags are factored together, in index order, in groups of at most
+ * SPAND_BATCH_UNION_DOF unknowns (default 4M), each group as one
+ * block-diagonal matrix: the systems' orderings are placed side by side
+ * (level l holds the level-l clusters of every one of them, a system with
+ * fewer levels finishes at its own top), and every phase of every level is
+ * one set of launches for all of them.  No launch mixes the arithmetic of
+ * two systems, and each cluster takes the kernels its own size selects, so
+ * every system's factor is the one spand_factor computes for it alone (same
+ * ranks, same values).  The groups run concurrently on library-owned HIP
+ * streams, at most SPAND_BATCH_FACTOR_STREAMS (default 2) at a time; the
+ * call waits on `stream` first and makes `stream` wait for all of them at
+ * the end.  SPAND_BATCH_SEPARATE=1 factors every system on its own instead
+ * (SPAND_BATCH_STREAMS, default 8, at a time).
+ * out[i] receives system i's handle; the handles of one group share the
+ * factorization's device memory, which is released with the last of them.
+ * Such a handle applies its own system's operators only (its own sweep
+ * graphs; apply, apply_T, solves and stats as for spand_factor), several of
+ * them may be used on different streams at once, and spand_refactor rejects
+ * it (SPAND_EINVAL).  Returns SPAND_OK, or the first negative status; then
+ * every out[i] is NULL.
  */
 int spand_factor_batched(int32_t n, const spand_bsr_t *A, const spand_grid_t *grids,
                          const spand_opts_t *opts, void *stream, spand_factor_t *out);
 
 /*
- * sstep_gmres_solve_batched - n independent s-step GMRES solves, concurrent
- * like spand_factor_batched.  M[i] may be NULL; one handle may appear at
+ * spand_apply_batched - d_out[i] = M_i^-1 d_in[i] (transpose = 0) or
+ * M_i^-T d_in[i] (1) for i < n, in stream order on `stream`.  Where the
+ * handles include every system of one factorization of
+ * spand_factor_batched, each once, those systems are applied together by one
+ * replay of that factorization's sweep graph (all its systems in each
+ * launch); other handles are applied one by one.  Vectors: device float64
+ * of each system's length; d_in[i] == d_out[i] is allowed.  Must not
+ * overlap in time with another apply or solve that uses one of these
+ * handles.
+ */
+int spand_apply_batched(int32_t n, const spand_factor_t *F, const double *const *d_in,
+                        double *const *d_out, int32_t transpose, void *stream);
+
+/*
+ * sstep_gmres_solve_batched - n independent s-step GMRES solves, run
+ * concurrently on library-owned HIP streams from a pool of host workers
+ * (SPAND_BATCH_STREAMS, default 8), ordered after `stream` and waited for
+ * on it at the end.  M[i] may be NULL; one handle may appear at
  * several M[i] (one operator, many right-hand sides): the systems that share
  * a handle are solved one after the other, in index order, on one worker
  * stream, since they share its scratch vectors.  d_b[i], d_x[i] device

@@ -87,7 +87,8 @@ class spand_factor_stats_t(C.Structure):
                 ("t_gemm_ms", C.c_double), ("gemm_flops", C.c_double),
                 ("gemm_bytes", C.c_double), ("n_gemm", C.c_int32), ("n_schur_elem", C.c_int32),
                 ("t_schur_elem_ms", C.c_double), ("schur_elem_flops", C.c_double),
-                ("schur_elem_bytes", C.c_double)]
+                ("schur_elem_bytes", C.c_double), ("batch_systems", C.c_int32),
+                ("pad1", C.c_int32)]
 
 
 EXPORTS = ["spand_factor", "spand_apply", "spand_apply_T", "sstep_gmres_solve",
@@ -95,7 +96,7 @@ EXPORTS = ["spand_factor", "spand_apply", "spand_apply_T", "sstep_gmres_solve",
            "spand_destroy", "spand_nd", "spand_status_string", "spand_last_error",
            "spand_factor_batched", "sstep_gmres_solve_batched", "spand_pool_trim",
            "sstep_gmres_solve_noalloc", "spand_measure_bandwidth", "spand_measure_mfma",
-           "spand_refactor"]
+           "spand_refactor", "spand_apply_batched"]
 SPAND_NOALLOC_SCRATCH_BYTES = 64 << 20
 SPAND_FLAG_NO_GRAPH = 1
 
@@ -136,6 +137,8 @@ def lib():
         L.sstep_gmres_solve_batched.argtypes = [i32, C.POINTER(spand_bsr_t), C.POINTER(vp),
                                                 C.POINTER(vp), C.POINTER(vp),
                                                 C.POINTER(sstep_opts_t), C.POINTER(sstep_stats_t), vp]
+        L.spand_apply_batched.argtypes = [i32, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), i32,
+                                          vp]
         L.spand_pool_trim.argtypes = []
         L.spand_status_string.restype = C.c_char_p
         L.spand_status_string.argtypes = [C.c_int]
@@ -291,7 +294,7 @@ class Factor:
             "t_gemm_ms": st.t_gemm_ms, "gemm_flops": st.gemm_flops, "gemm_bytes": st.gemm_bytes,
             "n_gemm": st.n_gemm, "t_schur_elem_ms": st.t_schur_elem_ms,
             "schur_elem_flops": st.schur_elem_flops, "schur_elem_bytes": st.schur_elem_bytes,
-            "n_schur_elem": st.n_schur_elem,
+            "n_schur_elem": st.n_schur_elem, "batch_systems": st.batch_systems,
         }
 
 
@@ -399,6 +402,24 @@ def factor_batched(systems, eps=1e-2, nlevels=0, dtype="f32", graphs=True):
     fs = [Factor(C.c_void_p(hs[i]), systems[i][0].N) if hs[i] else None for i in range(n)]
     _check(code)
     return fs
+
+
+def apply_batched(Fs, rs, outs=None, transpose=False):
+    """outs[i] = M_i^-1 rs[i] (M_i^-T with transpose) for every factor of Fs;
+    the factors of one factor_batched group are applied together by one
+    replay of their shared sweep graph."""
+    import torch
+    n = len(Fs)
+    if len(rs) != n or (outs is not None and len(outs) != n):
+        raise ValueError("Fs, rs and outs must have the same length")
+    outs = [torch.empty_like(r) for r in rs] if outs is None else outs
+    pin = [_vec(r, F.N, f"rs[{i}]") for i, (F, r) in enumerate(zip(Fs, rs))]
+    pout = [_vec(o, F.N, f"outs[{i}]") for i, (F, o) in enumerate(zip(Fs, outs))]
+    hs = (C.c_void_p * n)(*[F._h.value for F in Fs])
+    pi = (C.c_void_p * n)(*[p.value for p in pin])
+    po = (C.c_void_p * n)(*[p.value for p in pout])
+    _check(lib().spand_apply_batched(n, hs, pi, po, 1 if transpose else 0, _stream()))
+    return outs
 
 
 def solve_batched(As, bs, Ms=None, s=5, restart=60, rtol=1e-8, maxit=1000, lagged=False):

@@ -12,13 +12,19 @@
 #include <vector>
 
 #include <functional>
+#include <map>
 #include <mutex>
 #include <string>
+#include <tuple>
 
 #include "factor.h"
 
+// A handle owns a factorization, or shares one with the other systems of a
+// batch (member = its index there; -1: the factorization is its own).
 struct spand_factor_s {
-  std::unique_ptr<spand::Factor> F;
+  std::shared_ptr<spand::Factor> F;
+  int member = -1;
+  int64_t N() const { return member < 0 ? F->N : F->members[size_t(member)].N; }
 };
 
 namespace spand {
@@ -91,13 +97,9 @@ const char *spand_last_error(void) { return last_error(); }
 static int build_factor(const spand_bsr_t *A, const spand_grid_t *grid, const spand_opts_t *opts,
                         void *stream, const Factor *sym, bool graphs, std::unique_ptr<Factor> &out);
 
-static int factor_one(const spand_bsr_t *A, const spand_grid_t *grid, const spand_opts_t *opts,
-                      void *stream, spand_factor_t *out, bool graphs) {
-  if (!out) {
-    set_error("out is NULL");
-    return SPAND_EINVAL;
-  }
-  *out = nullptr;
+// Arguments of one factorization; *L_out receives the number of levels.
+static int check_factor_args(const spand_bsr_t *A, const spand_grid_t *grid,
+                             const spand_opts_t *opts, int *L_out) {
   SP_TRY(check_bsr(A));
   if (!grid || !opts) {
     set_error("grid/opts is NULL");
@@ -125,16 +127,43 @@ static int factor_one(const spand_bsr_t *A, const spand_grid_t *grid, const span
     set_error("nlevels=%d too large for %d elements", L, A->n_brows);
     return SPAND_EINVAL;
   }
+  if (L_out) *L_out = L;
+  return SPAND_OK;
+}
+
+static int factor_one(const spand_bsr_t *A, const spand_grid_t *grid, const spand_opts_t *opts,
+                      void *stream, spand_factor_t *out, bool graphs) {
+  if (!out) {
+    set_error("out is NULL");
+    return SPAND_EINVAL;
+  }
+  *out = nullptr;
+  SP_TRY(check_factor_args(A, grid, opts, nullptr));
   auto h = std::make_unique<spand_factor_s>();
-  SP_TRY(build_factor(A, grid, opts, stream, nullptr, graphs, h->F));
+  std::unique_ptr<Factor> f;
+  SP_TRY(build_factor(A, grid, opts, stream, nullptr, graphs, f));
+  h->F = std::move(f);
   *out = h.release();
   return SPAND_OK;
 }
 
+// Runs `body` on a new Factor with a private stream ordered after `stream`.
+static int run_build(void *stream, const std::function<int(Factor &)> &body,
+                     std::unique_ptr<Factor> &out);
+
 static int build_factor(const spand_bsr_t *A, const spand_grid_t *grid, const spand_opts_t *opts,
                         void *stream, const Factor *sym, bool graphs, std::unique_ptr<Factor> &out) {
-  auto h = std::make_unique<spand_factor_s>();
-  h->F = std::make_unique<Factor>();
+  std::unique_ptr<Factor> f;
+  SP_TRY(run_build(stream, [&](Factor &F) { return F.build(*A, *grid, *opts, sym); }, f));
+  if (graphs) SP_TRY(f->capture_graphs(1));
+  f->trace("graph capture", -1);
+  out = std::move(f);
+  return SPAND_OK;
+}
+
+static int run_build(void *stream, const std::function<int(Factor &)> &body,
+                     std::unique_ptr<Factor> &out) {
+  auto F = std::make_unique<Factor>();
   // The build runs on a private non-blocking stream ordered after the
   // caller's: its descriptor uploads (synchronous copies on the null
   // stream) then never wait for the factorization's own kernels, so the
@@ -150,12 +179,12 @@ static int build_factor(const spand_bsr_t *A, const spand_grid_t *grid, const sp
     set_error("could not order the factorization after the caller's stream");
     return SPAND_EHIP;
   }
-  h->F->stream = ps;
-  h->F->timing = true;
-  (void)hipGetDevice(&h->F->device);
+  F->stream = ps;
+  F->timing = true;
+  (void)hipGetDevice(&F->device);
   int r;
   try {
-    r = h->F->build(*A, *grid, *opts, sym);
+    r = body(*F);
   } catch (const std::exception &ex) {
     set_error("factorization failed: %s", ex.what());
     r = SPAND_EINVAL;
@@ -163,12 +192,10 @@ static int build_factor(const spand_bsr_t *A, const spand_grid_t *grid, const sp
   (void)hipStreamSynchronize(ps);
   (void)hipEventDestroy(ready);
   (void)hipStreamDestroy(ps);
-  h->F->stream = nullptr;
+  F->stream = nullptr;
   if (r != SPAND_OK) return r;
-  h->F->trace("build end", -1);
-  if (graphs) SP_TRY(h->F->capture_graphs(1));
-  h->F->trace("graph capture", -1);
-  out = std::move(h->F);
+  F->trace("build end", -1);
+  out = std::move(F);
   return SPAND_OK;
 }
 
@@ -184,6 +211,11 @@ int spand_refactor(spand_factor_t F, const spand_bsr_t *A, void *stream) {
   set_error("");
   if (!F || !F->F) {
     set_error("F is NULL");
+    return SPAND_EINVAL;
+  }
+  if (F->member >= 0) {
+    set_error("a handle that shares a batched factorization cannot be refactored; factor the "
+              "system with spand_factor");
     return SPAND_EINVAL;
   }
   SP_TRY(check_bsr(A));
@@ -221,7 +253,7 @@ int spand_apply(spand_factor_t F, const double *d_in, double *d_out, void *strea
     set_error("NULL argument");
     return SPAND_EINVAL;
   }
-  return F->F->apply(d_in, d_out, 0, (hipStream_t)stream);
+  return F->F->apply(d_in, d_out, 0, (hipStream_t)stream, F->member);
 }
 
 int spand_apply_T(spand_factor_t F, const double *d_in, double *d_out, void *stream) {
@@ -229,8 +261,8 @@ int spand_apply_T(spand_factor_t F, const double *d_in, double *d_out, void *str
     set_error("NULL argument");
     return SPAND_EINVAL;
   }
-  SP_TRY(F->F->capture_graphs(2));
-  return F->F->apply(d_in, d_out, 1, (hipStream_t)stream);
+  SP_TRY(F->F->capture_graphs(2, F->member));
+  return F->F->apply(d_in, d_out, 1, (hipStream_t)stream, F->member);
 }
 
 }  // extern "C"
@@ -255,7 +287,7 @@ static int check_solve_args(const spand_bsr_t *A, spand_factor_t M, const double
     set_error("maxit must be >= 1 and rtol > 0");
     return SPAND_EINVAL;
   }
-  if (M && (int64_t(M->F->N) != int64_t(A->n_brows) * A->bs)) {
+  if (M && (M->N() != int64_t(A->n_brows) * A->bs)) {
     set_error("factor size does not match A");
     return SPAND_EINVAL;
   }
@@ -300,9 +332,10 @@ int sstep_gmres_solve(const spand_bsr_t *A, spand_factor_t M, const double *d_b,
   set_error("");
   SP_TRY(check_solve_args(A, M, d_b, d_x, opts));
   if (st) std::memset(st, 0, sizeof(*st));
-  if (M && opts->transpose) SP_TRY(M->F->capture_graphs(2));
+  if (M && opts->transpose) SP_TRY(M->F->capture_graphs(2, M->member));
   try {
-    return sstep_solve(*A, M ? M->F.get() : nullptr, d_b, d_x, *opts, st, (hipStream_t)stream);
+    return sstep_solve(*A, M ? M->F.get() : nullptr, M ? M->member : -1, d_b, d_x, *opts, st,
+                       (hipStream_t)stream);
   } catch (const std::exception &ex) {
     set_error("solve failed: %s", ex.what());
     return SPAND_EINVAL;
@@ -332,7 +365,8 @@ int sstep_gmres_solve_noalloc(const spand_bsr_t *A, spand_factor_t M, const doub
   std::lock_guard<std::mutex> lk(g_scratch_use[dev]);
   const SolveWorkspace ws{ptr, SPAND_NOALLOC_SCRATCH_BYTES};
   try {
-    return sstep_solve(*A, M ? M->F.get() : nullptr, d_b, d_x, *opts, st, (hipStream_t)stream, &ws);
+    return sstep_solve(*A, M ? M->F.get() : nullptr, M ? M->member : -1, d_b, d_x, *opts, st,
+                       (hipStream_t)stream, &ws);
   } catch (const std::exception &ex) {
     set_error("solve failed: %s", ex.what());
     return SPAND_EINVAL;
@@ -388,7 +422,8 @@ int spand_bsr_pattern_outer(const spand_bsr_t *P, const double *d_u, const doubl
 // group == nullptr makes every item its own group.  Returns the per-item
 // statuses.
 static int run_batched(int n, hipStream_t stream, const std::function<int(int, hipStream_t)> &job,
-                       std::vector<int> &status, const std::vector<int> *group = nullptr) {
+                       std::vector<int> &status, const std::vector<int> *group = nullptr,
+                       int max_workers = 0) {
   status.assign(n, SPAND_OK);
   // work units: lists of items, in order of their first item
   std::vector<std::vector<int>> units;
@@ -414,6 +449,7 @@ static int run_batched(int n, hipStream_t stream, const std::function<int(int, h
   SP_HIP(hipGetDevice(&dev));
   int nw = 8;
   if (const char *e = std::getenv("SPAND_BATCH_STREAMS")) nw = std::max(1, std::atoi(e));
+  if (max_workers > 0) nw = std::min(nw, max_workers);
   nw = std::min(nw, nu);
   if (nw <= 0) return SPAND_OK;
   hipEvent_t start;
@@ -475,20 +511,130 @@ int spand_factor_batched(int32_t n, const spand_bsr_t *A, const spand_grid_t *gr
     return SPAND_EINVAL;
   }
   for (int i = 0; i < n; ++i) out[i] = nullptr;
-  std::vector<int> st;
-  SP_TRY(run_batched(n, (hipStream_t)stream, [&](int i, hipStream_t s) {
-    set_error("");
-    return factor_one(&A[i], &grids[i], &opts[i], (void *)s, &out[i], false);
-  }, st));
-  for (int i = 0; i < n; ++i)
-    if (st[i] < 0) return st[i];
+  std::vector<int> Ls(size_t(n), 0);
   for (int i = 0; i < n; ++i) {
-    const int r = out[i]->F->capture_graphs();
+    const int r = check_factor_args(&A[i], &grids[i], &opts[i], &Ls[size_t(i)]);
     if (r != SPAND_OK) {
       set_error("system %d: %s", i, std::string(last_error()).c_str());
       return r;
     }
   }
+  // Systems with the same block size, factor precision, eps and flags are
+  // factored together (one launch per phase for all of them), in index
+  // order, in groups of at most SPAND_BATCH_UNION_DOF unknowns (default 4M,
+  // the size that fills the device; a factorization's scratch peaks near
+  // 20 kB per unknown in FP32), at most SPAND_BATCH_FACTOR_STREAMS groups
+  // (default 2) at a time, each on its own worker stream.
+  // SPAND_BATCH_SEPARATE=1 factors every system on its own (for comparisons).
+  std::vector<std::vector<int>> groups;
+  {
+    const bool sep = std::getenv("SPAND_BATCH_SEPARATE") && std::atoi(std::getenv("SPAND_BATCH_SEPARATE"));
+    int64_t cap = int64_t(4) << 20;
+    if (const char *e = std::getenv("SPAND_BATCH_UNION_DOF")) cap = std::max<int64_t>(1, std::atoll(e));
+    std::map<std::tuple<int, int, uint64_t, int>, size_t> gid;   // key -> open group
+    std::vector<int64_t> gdof;
+    for (int i = 0; i < n; ++i) {
+      uint64_t eb;
+      std::memcpy(&eb, &opts[i].eps, 8);
+      const auto key = std::make_tuple(A[i].bs, opts[i].factor_dtype, eb, opts[i].flags);
+      const int64_t dof = int64_t(A[i].n_brows) * A[i].bs;
+      auto it = gid.find(key);
+      if (sep || it == gid.end() || gdof[it->second] + dof > cap) {
+        if (!sep) gid[key] = groups.size();
+        groups.push_back({i});
+        gdof.push_back(dof);
+      } else {
+        groups[it->second].push_back(i);
+        gdof[it->second] += dof;
+      }
+    }
+  }
+  int fw = 2;
+  if (const char *e = std::getenv("SPAND_BATCH_FACTOR_STREAMS")) fw = std::max(1, std::atoi(e));
+  if (std::getenv("SPAND_BATCH_SEPARATE") && std::atoi(std::getenv("SPAND_BATCH_SEPARATE"))) fw = 0;
+  std::vector<std::unique_ptr<Factor>> gf(groups.size());
+  std::vector<int> st;
+  SP_TRY(run_batched(int(groups.size()), (hipStream_t)stream, [&](int g, hipStream_t s) {
+    set_error("");
+    const auto &idx = groups[size_t(g)];
+    if (idx.size() == 1) {
+      const int i = idx[0];
+      return build_factor(&A[i], &grids[i], &opts[i], (void *)s, nullptr, false, gf[size_t(g)]);
+    }
+    std::vector<BatchSystem> sy;
+    for (int i : idx) sy.push_back(BatchSystem{A[i], grids[i], Ls[size_t(i)]});
+    return run_build((void *)s, [&](Factor &F) { return F.build_batch(sy, opts[idx[0]]); },
+                     gf[size_t(g)]);
+  }, st, nullptr, fw));
+  for (size_t g = 0; g < groups.size(); ++g)
+    if (st[g] < 0) return st[g];
+  std::vector<std::unique_ptr<spand_factor_s>> hs(static_cast<size_t>(n));
+  for (size_t g = 0; g < groups.size(); ++g) {
+    std::shared_ptr<Factor> f(std::move(gf[g]));
+    const auto &idx = groups[g];
+    for (size_t k = 0; k < idx.size(); ++k) {
+      auto h = std::make_unique<spand_factor_s>();
+      h->F = f;
+      h->member = idx.size() == 1 ? -1 : int(k);
+      hs[size_t(idx[k])] = std::move(h);
+    }
+  }
+  // graphs are captured on the calling thread, with no worker alive
+  for (int i = 0; i < n; ++i) {
+    const int r = hs[size_t(i)]->F->capture_graphs(1, hs[size_t(i)]->member);
+    if (r != SPAND_OK) {
+      set_error("system %d: %s", i, std::string(last_error()).c_str());
+      return r;
+    }
+  }
+  for (int i = 0; i < n; ++i) out[i] = hs[size_t(i)].release();
+  return SPAND_OK;
+}
+
+int spand_apply_batched(int32_t n, const spand_factor_t *F, const double *const *d_in,
+                        double *const *d_out, int32_t transpose, void *stream) {
+  set_error("");
+  if (n < 0 || (n > 0 && (!F || !d_in || !d_out)) || (transpose != 0 && transpose != 1)) {
+    set_error("bad batched arguments");
+    return SPAND_EINVAL;
+  }
+  for (int i = 0; i < n; ++i)
+    if (!F[i] || !d_in[i] || !d_out[i]) {
+      set_error("system %d: NULL argument", i);
+      return SPAND_EINVAL;
+    }
+  hipStream_t st = (hipStream_t)stream;
+  // the handles that hold every system of one shared factorization, each
+  // once, take one replay of that factorization's sweeps
+  std::map<Factor *, std::vector<int>> by;
+  for (int i = 0; i < n; ++i)
+    if (F[i]->member >= 0) by[F[i]->F.get()].push_back(i);
+  std::vector<char> done(size_t(n), 0);
+  for (auto &kv : by) {
+    Factor &f = *kv.first;
+    std::vector<int> at(f.members.size(), -1);
+    bool full = kv.second.size() == f.members.size();
+    for (int i : kv.second) {
+      int &a = at[size_t(F[i]->member)];
+      if (a >= 0) full = false;
+      a = i;
+    }
+    if (!full) continue;
+    std::vector<const double *> in;
+    std::vector<double *> out;
+    for (int i : at) {
+      in.push_back(d_in[i]);
+      out.push_back(d_out[i]);
+    }
+    SP_TRY(f.capture_graphs(1 << transpose, -1));
+    SP_TRY(f.apply_batch(in, out, transpose, st));
+    for (int i : kv.second) done[size_t(i)] = 1;
+  }
+  for (int i = 0; i < n; ++i)
+    if (!done[size_t(i)]) {
+      SP_TRY(F[i]->F->capture_graphs(1 << transpose, F[i]->member));
+      SP_TRY(F[i]->F->apply(d_in[i], d_out[i], transpose, st, F[i]->member));
+    }
   return SPAND_OK;
 }
 
@@ -502,7 +648,7 @@ int sstep_gmres_solve_batched(int32_t n, const spand_bsr_t *A, const spand_facto
   }
   // transposed sweeps are captured here, before any worker thread exists
   for (int i = 0; i < n; ++i)
-    if (M && M[i] && opts[i].transpose) SP_TRY(M[i]->F->capture_graphs(2));
+    if (M && M[i] && opts[i].transpose) SP_TRY(M[i]->F->capture_graphs(2, M[i]->member));
   // systems that share a factor handle share its scratch vectors: they run
   // one after the other on one worker stream
   std::vector<int> group(n, -1);
@@ -535,7 +681,7 @@ int spand_factor_stats(spand_factor_t F, spand_factor_stats_t *out) {
     set_error("NULL argument");
     return SPAND_EINVAL;
   }
-  F->F->fill_stats(out);
+  F->F->fill_stats(out, F->member);
   return SPAND_OK;
 }
 

@@ -77,6 +77,33 @@ struct RankStat {
 
 enum { PH_GATHER = 0, PH_LU, PH_SCHUR, PH_SCALE, PH_RRQR, PH_COMPRESS, PH_END, PH_COUNT };
 
+// One system of a batched factorization.  The systems of a batch that share
+// the block size, the factor precision, eps and the flags are factored as
+// one block-diagonal matrix: their elements are numbered one system after
+// the other, the nested dissection is the union of the systems' own
+// (clusters of one level side by side), and every phase runs one set of
+// launches for all of them.  No cluster couples two systems, so every
+// system's blocks, ranks and stored operators are those of its own
+// factorization.  A system keeps its own sweep plan (the descriptors of its
+// clusters only) and graphs, so its apply reads only its own operators.
+struct Member {
+  int K = 0, L = 0;
+  int64_t elem_off = 0, nnz_off = 0, dof_off = 0, N = 0;
+  const double *d_val = nullptr;
+  std::vector<ApplyLevel> lv;
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};
+  std::vector<RankStat> ranks;
+  int top_size = 0;
+  double apply_bytes = 0.0, flops = 0.0;
+};
+
+// input of a batched factorization: one system
+struct BatchSystem {
+  spand_bsr_t A;
+  spand_grid_t grid;
+  int L;
+};
+
 // chunked bump allocator over the device block cache
 struct Bump {
   std::vector<std::pair<char *, size_t>> chunks;
@@ -100,7 +127,15 @@ struct Factor {
   std::shared_ptr<const NDResult> nd_sym;
   spand_grid_t grid{};
   spand_opts_t opts{};
-  std::vector<ApplyLevel> lv;
+  std::vector<ApplyLevel> lv;   // sweeps of all unknowns (every system of a batch)
+  // batched factorization: its systems, and the system of every element
+  // (empty for a factorization of one system)
+  std::vector<Member> members;
+  std::vector<int32_t> esys;
+  const double *d_val = nullptr;          // values of a one-system factorization
+  const double *blk_src(int e, int64_t t) const;   // block t of the input (row element e)
+  int csys(int l, int c) const;           // system of cluster c of level l
+  void acct(int sys, double bytes, double fl);      // apply bytes and flops of a system
   Bump keep, temp, next_temp;   // next_temp: next level's trailing blocks
   Bump retired;                 // scratch of finished levels, released at the next sync
   size_t keep_bytes = 0;
@@ -117,6 +152,8 @@ struct Factor {
   std::chrono::steady_clock::time_point trace_t = std::chrono::steady_clock::now();
   void trace(const char *what, int l);
   std::chrono::steady_clock::time_point host_t;
+  std::chrono::steady_clock::time_point build_t0;
+  double build_drv0 = 0.0;
   bool timing = false;
   std::vector<std::pair<int, hipEvent_t>> events;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> qrcp_events;
@@ -140,9 +177,16 @@ struct Factor {
   hipGraphExec_t gexec[2] = {nullptr, nullptr};
   double *d_xg = nullptr;          // the graphs' fixed input/output vector
   ~Factor();
-  int sweeps(double *x, int transpose, hipStream_t st);
-  int capture(int transpose);
-  int capture_graphs(int which = 3);
+  int sweeps(const std::vector<ApplyLevel> &plan, double *x, int transpose, hipStream_t st);
+  int capture(int member, int transpose);
+  int capture_graphs(int which = 3, int member = -1);
+  // the sweep sets of every system from the sets of all unknowns (gs: the
+  // system of each group or item)
+  int member_pull(int l, PullSet ApplyLevel::*which, const std::vector<PullGroup> &G,
+                  const std::vector<PullItem> &I, const std::vector<int> &gs);
+  int member_gemv(int l, GemvSet ApplyLevel::*which, const std::vector<GemvDesc> &gv,
+                  const std::vector<const std::vector<int32_t> *> &os, const std::vector<int> &gs,
+                  int trans);
   int dalloc(void **p, size_t bytes, bool keep);
   int dalloc_next(void **p, size_t bytes);
   void free_temp();
@@ -159,19 +203,26 @@ struct Factor {
   int flush_deferred();
   int gemm_batch(const std::vector<GemmDesc> &items);
   int copy_batch(const std::vector<CopyDesc> &items, int src_is_factor);
-  int complete_q(const LevelState &S, const std::vector<int> &ifs,
+  int complete_q(int l, const LevelState &S, const std::vector<int> &ifs,
                  const std::vector<int32_t> &kg, const std::vector<void *> &Qm,
                  const std::vector<void *> &Vm);
   int elim_batch(std::vector<ElimDesc> &items, int mode);
   void mark(int phase);
   void collect_events();
-  int level0(const spand_bsr_t &A, const NDResult &nd, LevelState &S);
+  int level0(const NDResult &nd, LevelState &S);
   int eliminate_dense(int l, LevelState &S);
   int sparsify(int l, const NDResult &nd, LevelState &S, LevelState &Nx);
   int build(const spand_bsr_t &A, const spand_grid_t &g, const spand_opts_t &o,
             const Factor *sym = nullptr);
-  int apply(const double *in, double *out, int transpose, hipStream_t st);
-  void fill_stats(spand_factor_stats_t *st) const;
+  int build_batch(const std::vector<BatchSystem> &sys, const spand_opts_t &o);
+  int numeric();                // buffers, level 0, the levels, the final checks
+  // member < 0: all unknowns; otherwise the vectors are those of one system
+  int apply(const double *in, double *out, int transpose, hipStream_t st, int member = -1);
+  // every system of a batch at once (in[m], out[m]: system m's vectors), one
+  // replay of the sweeps of all unknowns
+  int apply_batch(const std::vector<const double *> &in, const std::vector<double *> &out,
+                  int transpose, hipStream_t st);
+  void fill_stats(spand_factor_stats_t *st, int member = -1) const;
 };
 
 struct DiagDesc {

@@ -107,10 +107,68 @@ Factor::~Factor() {
   collect_events();         // events of a build that stopped early
   for (auto &g : gexec)
     if (g) (void)hipGraphExecDestroy(g);
+  for (auto &m : members)
+    for (auto &g : m.gexec)
+      if (g) (void)hipGraphExecDestroy(g);
   temp.release();
   next_temp.release();
   retired.release();
   keep.release();
+}
+
+// ------------------------------------------------------------------ batch members
+const double *Factor::blk_src(int e, int64_t t) const {
+  const size_t b2 = size_t(bs) * bs;
+  if (members.empty()) return d_val + size_t(t) * b2;
+  const Member &M = members[size_t(esys[size_t(e)])];
+  return M.d_val + size_t(t - M.nnz_off) * b2;
+}
+
+int Factor::csys(int l, int c) const {
+  if (members.empty()) return 0;
+  return esys[size_t(nd_sym->levels[size_t(l)][size_t(c)].elems[0])];
+}
+
+void Factor::acct(int sys, double bytes, double fl) {
+  apply_bytes += bytes;
+  flops += fl;
+  if (!members.empty()) {
+    members[size_t(sys)].apply_bytes += bytes;
+    members[size_t(sys)].flops += fl;
+  }
+}
+
+int Factor::member_pull(int l, PullSet ApplyLevel::*which, const std::vector<PullGroup> &G,
+                        const std::vector<PullItem> &I, const std::vector<int> &gs) {
+  if (members.empty()) return SPAND_OK;
+  std::vector<std::vector<PullGroup>> Gm(members.size());
+  std::vector<std::vector<PullItem>> Im(members.size());
+  for (size_t g = 0; g < G.size(); ++g) {
+    const int m = gs[g];
+    PullGroup q = G[g];
+    q.item_begin = int(Im[size_t(m)].size());
+    Im[size_t(m)].insert(Im[size_t(m)].end(), I.begin() + G[g].item_begin, I.begin() + G[g].item_end);
+    q.item_end = int(Im[size_t(m)].size());
+    Gm[size_t(m)].push_back(q);
+  }
+  for (size_t m = 0; m < members.size(); ++m)
+    SP_TRY((members[m].lv[size_t(l)].*which).set(*this, Gm[m], Im[m]));
+  return SPAND_OK;
+}
+
+int Factor::member_gemv(int l, GemvSet ApplyLevel::*which, const std::vector<GemvDesc> &gv,
+                        const std::vector<const std::vector<int32_t> *> &os,
+                        const std::vector<int> &gs, int trans) {
+  if (members.empty()) return SPAND_OK;
+  std::vector<std::vector<GemvDesc>> gm(members.size());
+  std::vector<std::vector<const std::vector<int32_t> *>> om(members.size());
+  for (size_t i = 0; i < gv.size(); ++i) {
+    gm[size_t(gs[i])].push_back(gv[i]);
+    om[size_t(gs[i])].push_back(os[i]);
+  }
+  for (size_t m = 0; m < members.size(); ++m)
+    SP_TRY((members[m].lv[size_t(l)].*which).set(*this, gm[m], om[m], trans));
+  return SPAND_OK;
 }
 
 template <typename D>
@@ -315,6 +373,19 @@ int Factor::elim_batch(std::vector<ElimDesc> &items, int mode) {
   // Matrices of up to elim_block_max_n rows take each block in one fused
   // launch (one row per thread); larger ones go panel by panel.
   const bool lu = mode == 1;
+  // every item takes its own path: the matrices beyond the fused limit and
+  // the others go to separate calls
+  if (items[0].n > elim_block_max_n(ft) && items.back().n <= elim_block_max_n(ft)) {
+    const auto cut = std::find_if(items.begin(), items.end(), [&](const ElimDesc &d) {
+      return d.n <= elim_block_max_n(ft);
+    });
+    std::vector<ElimDesc> big(items.begin(), cut), small(cut, items.end());
+    SP_TRY(elim_batch(big, mode));
+    SP_TRY(elim_batch(small, mode));
+    std::copy(big.begin(), big.end(), items.begin());
+    std::copy(small.begin(), small.end(), items.begin() + big.size());
+    return SPAND_OK;
+  }
   const bool fused = items[0].n <= elim_block_max_n(ft);
   if (mode == 3 && !fused) {
     set_error("shifted Gauss-Jordan: n = %d exceeds the fused limit %d", items[0].n, elim_block_max_n(ft));
@@ -470,7 +541,7 @@ int Factor::elim_batch(std::vector<ElimDesc> &items, int mode) {
 //   Q = [Q_c | E_c + Q_c G2'^T - [S G2'^T; 0]]   (E_c = columns k..m-1 of I;
 //   S G2'^T = G2^T with G2 = Q2 M^-1, the rows of the reflector block).
 // The right block is orthogonal to Q_c and completes it; with k = 0 Q = I.
-int Factor::complete_q(const LevelState &S, const std::vector<int> &ifs,
+int Factor::complete_q(int l, const LevelState &S, const std::vector<int> &ifs,
                        const std::vector<int32_t> &kg, const std::vector<void *> &Qm,
                        const std::vector<void *> &Vm) {
   const size_t tsz = fsize(ft);
@@ -556,7 +627,7 @@ int Factor::complete_q(const LevelState &S, const std::vector<int> &ifs,
     b.alpha = 1.0;
     b.beta = 1.0;
     g2.push_back(b);
-    flops += 2.0 * k * k * k + 2.0 * (m - k) * k * k + 2.0 * m * (m - k) * k;
+    acct(csys(l, s), 0.0, 2.0 * k * k * k + 2.0 * (m - k) * k * k + 2.0 * m * (m - k) * k);
   }
   SP_TRY(copy_batch(c1, 1));
   if (!gj.empty()) SP_TRY(elim_batch(gj, 3));
@@ -604,7 +675,7 @@ void Factor::trace(const char *what, int l) {
 }
 
 // ------------------------------------------------------------------ level 0
-int Factor::level0(const spand_bsr_t &A, const NDResult &nd, LevelState &S) {
+int Factor::level0(const NDResult &nd, LevelState &S) {
   const int b = bs;
   const auto &cl = nd.levels[0];
   const int ncl = int(cl.size());
@@ -661,13 +732,14 @@ int Factor::level0(const spand_bsr_t &A, const NDResult &nd, LevelState &S) {
         for (int t = h_rowptr[e]; t < h_rowptr[e + 1]; ++t) {
           const int f = h_colind[t];
           if (ecl[f] == s)
-            gi.push_back({(char *)Ass[s] + (size_t(epos[e]) * b * n + size_t(epos[f]) * b) * tsz, t, n});
+            gi.push_back({(char *)Ass[s] + (size_t(epos[e]) * b * n + size_t(epos[f]) * b) * tsz,
+                          blk_src(e, t), n, 0});
         }
     }
     mark(PH_GATHER);
     GatherItem *d_gi;
     SP_TRY(upload(gi, &d_gi, false));
-    SP_TRY(launch_bsr_gather(ft, A.d_val, d_gi, int(gi.size()), b, stream));
+    SP_TRY(launch_bsr_gather(ft, d_gi, int(gi.size()), b, stream));
     trace("leaf gather", 0);
   }
   mark(PH_LU);
@@ -776,14 +848,14 @@ int Factor::level0(const spand_bsr_t &A, const NDResult &nd, LevelState &S) {
         const int cf = ecl[f];
         if (S.interior[cf]) continue;
         const Blk &B = pair_blk(ce, cf);
-        gi.push_back({(char *)B.p + (size_t(epos[e]) * b * B.cols + size_t(epos[f]) * b) * tsz, t,
-                      B.cols});
+        gi.push_back({(char *)B.p + (size_t(epos[e]) * b * B.cols + size_t(epos[f]) * b) * tsz,
+                      blk_src(e, t), B.cols, 0});
       }
     }
     mark(PH_GATHER);
     GatherItem *d_gi;
     SP_TRY(upload(gi, &d_gi, false));
-    SP_TRY(launch_bsr_gather(ft, A.d_val, d_gi, int(gi.size()), b, stream));
+    SP_TRY(launch_bsr_gather(ft, d_gi, int(gi.size()), b, stream));
     trace("interface gather", 0);
   }
   mark(PH_SCHUR);
@@ -828,13 +900,13 @@ int Factor::level0(const spand_bsr_t &A, const NDResult &nd, LevelState &S) {
       for (size_t i = 0; i < coup[s].size(); ++i) {
         const auto &c = coup[s][i];
         const size_t q = cpl0[s] + i;
-        cc.push_back({(char *)cb + (2 * q) * b2 * tsz, int32_t(c.t_ef), b});
-        cc.push_back({(char *)cb + (2 * q + 1) * b2 * tsz, int32_t(c.t_fe), b});
+        cc.push_back({(char *)cb + (2 * q) * b2 * tsz, blk_src(c.e, c.t_ef), b, 0});
+        cc.push_back({(char *)cb + (2 * q + 1) * b2 * tsz, blk_src(c.f, c.t_fe), b, 0});
       }
     if (!cc.empty()) {
       GatherItem *d_cc;
       SP_TRY(upload(cc, &d_cc, false));
-      SP_TRY(launch_bsr_gather(ft, A.d_val, d_cc, int(cc.size()), b, stream));
+      SP_TRY(launch_bsr_gather(ft, d_cc, int(cc.size()), b, stream));
     }
     trace("coupling copies", 0);
   }
@@ -921,7 +993,7 @@ int Factor::level0(const spand_bsr_t &A, const NDResult &nd, LevelState &S) {
       }));
     }
     trace("schur plan+launch", 0);
-    flops += double(items.size()) * 4.0 * b * b * b;
+    for (int s : leaves) acct(csys(0, s), 0.0, double(coup[s].size()) * coup[s].size() * 4.0 * b * b * b);
   }
   // ---- stored couplings and apply descriptors of level 0
   ApplyLevel &AL = lv[0];
@@ -940,7 +1012,7 @@ int Factor::level0(const spand_bsr_t &A, const NDResult &nd, LevelState &S) {
         bw_ns[c.f].push_back({c.e, pns});
       }
     auto build = [&](PairList &m, int trans, std::vector<PullGroup> &G, std::vector<PullItem> &I,
-                     bool all_leaf) {
+                     std::vector<int> &gs, bool all_leaf) {
       std::vector<int> keys;
       if (all_leaf) {
         for (int s : leaves)
@@ -966,24 +1038,39 @@ int Factor::level0(const spand_bsr_t &A, const NDResult &nd, LevelState &S) {
         }
         g.item_end = int(I.size());
         G.push_back(g);
+        gs.push_back(members.empty() ? 0 : esys[size_t(key)]);
       }
     };
     std::vector<PullGroup> G;
     std::vector<PullItem> I;
-    build(fw_ns, 0, G, I, false);
-    defer([this, &AL, G, I]() { return AL.fw.set(*this, G, I); });
-    G.clear(); I.clear();
-    build(bw_sn, 0, G, I, false);
-    defer([this, &AL, G, I]() { return AL.bw.set(*this, G, I); });
-    G.clear(); I.clear();
-    build(fw_sn, 1, G, I, false);
-    defer([this, &AL, G, I]() { return AL.tfw.set(*this, G, I); });
-    G.clear(); I.clear();
-    build(bw_ns, 1, G, I, true);
-    defer([this, &AL, G, I]() { return AL.tbw.set(*this, G, I); });
+    std::vector<int> gs;
+    build(fw_ns, 0, G, I, gs, false);
+    defer([this, &AL, G, I, gs]() {
+      SP_TRY(AL.fw.set(*this, G, I));
+      return member_pull(0, &ApplyLevel::fw, G, I, gs);
+    });
+    G.clear(); I.clear(); gs.clear();
+    build(bw_sn, 0, G, I, gs, false);
+    defer([this, &AL, G, I, gs]() {
+      SP_TRY(AL.bw.set(*this, G, I));
+      return member_pull(0, &ApplyLevel::bw, G, I, gs);
+    });
+    G.clear(); I.clear(); gs.clear();
+    build(fw_sn, 1, G, I, gs, false);
+    defer([this, &AL, G, I, gs]() {
+      SP_TRY(AL.tfw.set(*this, G, I));
+      return member_pull(0, &ApplyLevel::tfw, G, I, gs);
+    });
+    G.clear(); I.clear(); gs.clear();
+    build(bw_ns, 1, G, I, gs, true);
+    defer([this, &AL, G, I, gs]() {
+      SP_TRY(AL.tbw.set(*this, G, I));
+      return member_pull(0, &ApplyLevel::tbw, G, I, gs);
+    });
     trace("pull sets", 0);
     std::vector<GemvDesc> gv;
     std::vector<const std::vector<int32_t> *> os;
+    std::vector<int> vs;
     for (int s : leaves) {
       GemvDesc d{};
       d.A = Ainv[s];
@@ -992,21 +1079,25 @@ int Factor::level0(const spand_bsr_t &A, const NDResult &nd, LevelState &S) {
       d.lda = ld4(S.size[s]);
       gv.push_back(d);
       os.push_back(&S.slots[s]);
-      apply_bytes += double(S.size[s]) * S.size[s] * tsz * 2;   // A_ss^-1: both sweeps
+      vs.push_back(csys(0, s));
+      acct(csys(0, s), double(S.size[s]) * S.size[s] * tsz * 2, 0.0);   // A_ss^-1: both sweeps
     }
     // band height of the sweep GEMVs: autotuned once per (precision, b)
-    defer([this, &AL, gv, os]() -> int {
+    defer([this, &AL, gv, os, vs]() -> int {
       void *tin;
       SP_TRY(dalloc(&tin, size_t(N) * 8, false));
       SP_HIP(hipMemsetAsync(tin, 0, size_t(N) * 8, stream));
       auto build_set = [&](int R, GemvSet &g) { return g.set(*this, gv, os, 0, R); };
       SP_TRY(autotune_gemv(ft, bs, build_set, (double *)tin, d_tbuf, stream, &gemv_rows));
       SP_TRY(AL.inv.set(*this, gv, os, 0));
-      return AL.invT.set(*this, gv, os, 1);
+      SP_TRY(AL.invT.set(*this, gv, os, 1));
+      SP_TRY(member_gemv(0, &ApplyLevel::inv, gv, os, vs, 0));
+      return member_gemv(0, &ApplyLevel::invT, gv, os, vs, 1);
     });
     trace("inverse sweep sets", 0);
-    apply_bytes += double(ncp) * 2 * b2 * tsz;   // A_ns forward, A_sn backward
-    for (int s : leaves) flops += 2.0 * double(S.size[s]) * S.size[s] * S.size[s];
+    for (int s : leaves)   // A_ns forward, A_sn backward; the inversion
+      acct(csys(0, s), double(coup[s].size()) * 2 * b2 * tsz,
+           2.0 * double(S.size[s]) * S.size[s] * S.size[s]);
   }
   for (int s : leaves) S.size[s] = 0;   // eliminated
   return SPAND_OK;
@@ -1109,8 +1200,7 @@ int Factor::eliminate_dense(int l, LevelState &S) {
     d.ld = n;
     d.pad = s;                   // owner cluster (elim_batch reorders the items)
     items.push_back(d);
-    flops += 2.0 * double(n) * n * n;
-    apply_bytes += double(n) * n * tsz * 2;   // A_ss^-1: both sweeps
+    acct(csys(l, s), double(n) * n * tsz * 2, 2.0 * double(n) * n * n);   // A_ss^-1: both sweeps
   }
   SP_TRY(elim_batch(items, 0));
   trace("elim enqueue", l);
@@ -1157,7 +1247,7 @@ int Factor::eliminate_dense(int l, LevelState &S) {
         g.alpha = 1.0;
         g.beta = 0.0;
         gm.push_back(g);
-        flops += 2.0 * double(B.rows) * B.rows * B.cols;
+        acct(csys(l, s), 0.0, 2.0 * double(B.rows) * B.rows * B.cols);
       }
     SP_TRY(gemm_batch(gm));
     trace("gemm", l);
@@ -1204,7 +1294,7 @@ int Factor::eliminate_dense(int l, LevelState &S) {
       g.alpha = -1.0;
       g.beta = 1.0;
       gm.push_back(g);
-      flops += 2.0 * double(T.rows) * T.cols * Ans.cols;
+      acct(csys(l, s), 0.0, 2.0 * double(T.rows) * T.cols * Ans.cols);
     }
     SP_TRY(gemm_batch(gm));
     trace("gemm", l);
@@ -1212,6 +1302,7 @@ int Factor::eliminate_dense(int l, LevelState &S) {
   // apply descriptors
   std::vector<GemvDesc> gv;
   std::vector<const std::vector<int32_t> *> os;
+  std::vector<int> vs;
   for (int s : ints) {
     GemvDesc d{};
     d.A = Ainv[s];
@@ -1220,9 +1311,16 @@ int Factor::eliminate_dense(int l, LevelState &S) {
     d.lda = ld4(S.size[s]);
     gv.push_back(d);
     os.push_back(&S.slots[s]);
+    vs.push_back(csys(l, s));
   }
-  defer([this, &AL, gv, os]() { return AL.inv.set(*this, gv, os, 0); });
-  defer([this, &AL, gv, os]() { return AL.invT.set(*this, gv, os, 1); });
+  defer([this, &AL, gv, os, vs, l]() {
+    SP_TRY(AL.inv.set(*this, gv, os, 0));
+    return member_gemv(l, &ApplyLevel::inv, gv, os, vs, 0);
+  });
+  defer([this, &AL, gv, os, vs, l]() {
+    SP_TRY(AL.invT.set(*this, gv, os, 1));
+    return member_gemv(l, &ApplyLevel::invT, gv, os, vs, 1);
+  });
   std::map<int, std::vector<PullItem>> fw, tfw;
   std::vector<PullGroup> G;
   std::vector<PullItem> I;
@@ -1248,12 +1346,13 @@ int Factor::eliminate_dense(int l, LevelState &S) {
       q.ldb = Asn.cols;
       q.trans = 1;
       tfw[n].push_back(q);
-      apply_bytes += double(Ans.rows) * Ans.cols * tsz + double(Asn.rows) * Asn.cols * tsz;
+      acct(csys(l, s), double(Ans.rows) * Ans.cols * tsz + double(Asn.rows) * Asn.cols * tsz, 0.0);
       if (S.size[n] > PULL_MAXR || S.size[s] > GEMV_MAXC) {
         set_error("coupling block %dx%d exceeds the sweep kernel limit", S.size[n], S.size[s]);
         return SPAND_EINVAL;
       }
     }
+  std::vector<int> gs, gs2;
   for (auto &kv : fw) {
     PullGroup g{};
     g.oslot = S.d_slots[kv.first];
@@ -1262,10 +1361,15 @@ int Factor::eliminate_dense(int l, LevelState &S) {
     I.insert(I.end(), kv.second.begin(), kv.second.end());
     g.item_end = int(I.size());
     G.push_back(g);
+    gs.push_back(csys(l, kv.first));
   }
-  defer([this, &AL, G, I]() { return AL.fw.set(*this, G, I); });
+  defer([this, &AL, G, I, gs, l]() {
+    SP_TRY(AL.fw.set(*this, G, I));
+    return member_pull(l, &ApplyLevel::fw, G, I, gs);
+  });
   G.clear();
   I.clear();
+  gs.clear();
   for (auto &kv : tfw) {
     PullGroup g{};
     g.oslot = S.d_slots[kv.first];
@@ -1274,10 +1378,15 @@ int Factor::eliminate_dense(int l, LevelState &S) {
     I.insert(I.end(), kv.second.begin(), kv.second.end());
     g.item_end = int(I.size());
     G.push_back(g);
+    gs.push_back(csys(l, kv.first));
   }
-  defer([this, &AL, G, I]() { return AL.tfw.set(*this, G, I); });
+  defer([this, &AL, G, I, gs, l]() {
+    SP_TRY(AL.tfw.set(*this, G, I));
+    return member_pull(l, &ApplyLevel::tfw, G, I, gs);
+  });
   G.clear();
   I.clear();
+  gs.clear();
   for (int s : ints) {
     PullGroup g{}, g2{};
     g.oslot = g2.oslot = S.d_slots[s];
@@ -1306,12 +1415,22 @@ int Factor::eliminate_dense(int l, LevelState &S) {
     }
     g.item_end = int(I.size());
     g2.item_end = int(I2.size());
-    if (g.item_end > g.item_begin) G.push_back(g);
+    if (g.item_end > g.item_begin) {
+      G.push_back(g);
+      gs.push_back(csys(l, s));
+    }
     G2.push_back(g2);
+    gs2.push_back(csys(l, s));
   }
-  defer([this, &AL, G, I]() { return AL.bw.set(*this, G, I); });
+  defer([this, &AL, G, I, gs, l]() {
+    SP_TRY(AL.bw.set(*this, G, I));
+    return member_pull(l, &ApplyLevel::bw, G, I, gs);
+  });
   trace("sweep sets", l);
-  defer([this, &AL, G2, I2]() { return AL.tbw.set(*this, G2, I2); });
+  defer([this, &AL, G2, I2, gs2, l]() {
+    SP_TRY(AL.tbw.set(*this, G2, I2));
+    return member_pull(l, &ApplyLevel::tbw, G2, I2, gs2);
+  });
   // eliminated clusters leave the trailing matrix
   for (int s : ints) {
     for (int n : nb[s]) {
@@ -1381,7 +1500,7 @@ int Factor::sparsify(int l, const NDResult &nd, LevelState &S, LevelState &Nx) {
     el.ld = 2 * m;
     el.pad = s;                  // owner interface (elim_batch reorders the items)
     items.push_back(el);
-    flops += 4.0 * double(m) * m * m;
+    acct(csys(l, s), 0.0, 4.0 * double(m) * m * m);
   }
   SP_TRY(copy_batch(cps, 1));
   {
@@ -1425,7 +1544,7 @@ int Factor::sparsify(int l, const NDResult &nd, LevelState &S, LevelState &Nx) {
       el.A = Ust[s];
       el.n = el.ncols = el.ld = S.size[s];
       ui.push_back(el);
-      flops += 2.0 * double(S.size[s]) * S.size[s] * S.size[s];
+      acct(csys(l, s), 0.0, 2.0 * double(S.size[s]) * S.size[s] * S.size[s]);
     }
     SP_TRY(elim_batch(ui, 2));
     // Lh^-1 P^T = S^-1 (L^-1 P^T) ; Uh^-1 = U^-1 S
@@ -1476,7 +1595,7 @@ int Factor::sparsify(int l, const NDResult &nd, LevelState &S, LevelState &Nx) {
       h.beta = 0.0;
       h.tri = GEMM_TRI_B_UPPER;   // Uh_j^-1 is upper triangular
       g2.push_back(h);
-      flops += 2.0 * double(B.rows) * B.cols * (B.rows + B.cols);
+      acct(csys(l, i), 0.0, 2.0 * double(B.rows) * B.cols * (B.rows + B.cols));
     }
     SP_TRY(gemm_batch(g1));
     SP_TRY(gemm_batch(g2));
@@ -1491,10 +1610,13 @@ int Factor::sparsify(int l, const NDResult &nd, LevelState &S, LevelState &Nx) {
   SP_TRY(dalloc(&kout, std::max<size_t>(1, ifs.size()) * 4, false));
   SP_TRY(dalloc(&kgs, std::max<size_t>(1, ifs.size()) * 4, false));
   // Q is completed by batched launches (sign-shifted Gauss-Jordan on the
-  // fused path, products on the matrix cores) when every interface fits the
-  // fused elimination; otherwise inside the QRCP kernel
-  bool batched_cq = true;
-  for (int s : ifs) batched_cq = batched_cq && S.size[s] <= elim_block_max_n(ft);
+  // fused path, products on the matrix cores) for the interfaces that fit
+  // the fused elimination, inside the QRCP kernel for the others.  Each
+  // interface also takes its own candidate block width (the widest whose
+  // LDS fits it), so that its arithmetic never depends on the other
+  // interfaces of the launch.
+  std::vector<char> cq_in(ncl, 0);
+  for (int s : ifs) cq_in[s] = S.size[s] > elim_block_max_n(ft) ? 1 : 0;
   {
     // all W in one zeroed region (padding columns must read as zero)
     PlanArena pw;
@@ -1526,16 +1648,16 @@ int Factor::sparsify(int l, const NDResult &nd, LevelState &S, LevelState &Nx) {
         SP_TRY(launch_zero(ft, d_zd, int(zd.size()), mz, stream));
       }
     }
-    int mq = 1, mg = 1;
+    // column groups of 16 bytes: 2 columns (FP64) or 4 (FP32)
+    std::vector<int> grp(ncl, 1), bqs(ncl, 0);
     for (int s : ifs) {
-      mq = std::max(mq, S.size[s]);
-      // column groups of 16 bytes: 2 columns (FP64) or 4 (FP32)
-      mg = std::max(mg, ld4(std::max(ncols[s], 1)) / (ft == FType::F64 ? 2 : 4));
-    }
-    const int bq = qrcp_block_width(mq, mg);
-    if (bq == 0) {
-      set_error("RRQR problem too large for one workgroup (m=%d, %d column groups)", mq, mg);
-      return SPAND_EINVAL;
+      grp[s] = std::max(1, ld4(std::max(ncols[s], 1)) / (ft == FType::F64 ? 2 : 4));
+      bqs[s] = qrcp_block_width(S.size[s], grp[s]);
+      if (bqs[s] == 0) {
+        set_error("RRQR problem too large for one workgroup (m=%d, %d column groups)", S.size[s],
+                  grp[s]);
+        return SPAND_EINVAL;
+      }
     }
     std::vector<CopyDesc> wc;
     for (size_t q = 0; q < ifs.size(); ++q) {
@@ -1547,7 +1669,7 @@ int Factor::sparsify(int l, const NDResult &nd, LevelState &S, LevelState &Nx) {
       SP_TRY(dalloc(&Qm[s], size_t(m) * m * tsz, false));
       SP_TRY(dalloc(&Vm[s], size_t(m) * m * tsz, false));
       void *tau, *vn1, *vn2, *sel, *hq;
-      SP_TRY(dalloc(&hq, size_t(ldw) * bq * 8, false));
+      SP_TRY(dalloc(&hq, size_t(ldw) * bqs[s] * 8, false));
       SP_TRY(dalloc(&tau, size_t(m) * 8, false));
       SP_TRY(dalloc(&vn1, size_t(ldw) * 8, false));
       SP_TRY(dalloc(&vn2, size_t(ldw) * 8, false));
@@ -1596,19 +1718,33 @@ int Factor::sparsify(int l, const NDResult &nd, LevelState &S, LevelState &Nx) {
       Qd.ncols = nc;
       Qd.ldw = ldw;
       qd.push_back(Qd);
-      flops += 4.0 * double(m) * nc * std::min(m, nc);
+      acct(csys(l, s), 0.0, 4.0 * double(m) * nc * std::min(m, nc));
     }
     SP_TRY(copy_batch(wc, 1));
-    QrcpDesc *d_q;
-    SP_TRY(upload(qd, &d_q, false));
     hipEvent_t qe0 = nullptr, qe1 = nullptr;
     if (timing) {
       (void)hipEventCreate(&qe0);
       (void)hipEventCreate(&qe1);
       (void)hipEventRecord(qe0, stream);
     }
-    SP_TRY(launch_qrcp(ft, d_q, int(qd.size()), eps, eps == 0.0 ? 1 : 0, mq, mg, bq,
-                       batched_cq ? 0 : 1, stream));
+    // one launch per (block width, completion) class
+    for (const int cq : {0, 1})
+      for (const int bq : {8, 4, 2}) {
+        std::vector<QrcpDesc> qc;
+        int mq = 1, mg = 1;
+        for (size_t q = 0; q < ifs.size(); ++q) {
+          const int s = ifs[q];
+          if (cq_in[s] != cq || bqs[s] != bq) continue;
+          qc.push_back(qd[q]);
+          mq = std::max(mq, S.size[s]);
+          mg = std::max(mg, grp[s]);
+        }
+        if (qc.empty()) continue;
+        QrcpDesc *d_q;
+        SP_TRY(upload(qc, &d_q, false));
+        SP_TRY(launch_qrcp(ft, d_q, int(qc.size()), eps, eps == 0.0 ? 1 : 0, mq, mg, bq, cq,
+                           stream));
+      }
     trace("qrcp plan+launch", l);
     if (timing) {
       (void)hipEventRecord(qe1, stream);
@@ -1620,15 +1756,23 @@ int Factor::sparsify(int l, const NDResult &nd, LevelState &S, LevelState &Nx) {
   std::vector<int32_t> ks(ifs.size(), 0), kg(ifs.size(), 0);
   if (!ifs.empty()) {
     SP_HIP(hipMemcpyAsync(ks.data(), kout, ifs.size() * 4, hipMemcpyDeviceToHost, stream));
-    if (batched_cq)
-      SP_HIP(hipMemcpyAsync(kg.data(), kgs, ifs.size() * 4, hipMemcpyDeviceToHost, stream));
+    SP_HIP(hipMemcpyAsync(kg.data(), kgs, ifs.size() * 4, hipMemcpyDeviceToHost, stream));
   }
   SP_HIP(hipStreamSynchronize(stream));
   trace("sync", -1);
   release_retired();
-  if (batched_cq && !ifs.empty()) {
-    SP_TRY(complete_q(S, ifs, kg, Qm, Vm));
-    trace("qrcp completion", l);
+  {
+    std::vector<int> ib;
+    std::vector<int32_t> kb;
+    for (size_t q = 0; q < ifs.size(); ++q)
+      if (!cq_in[ifs[q]]) {
+        ib.push_back(ifs[q]);
+        kb.push_back(kg[q]);
+      }
+    if (!ib.empty()) {
+      SP_TRY(complete_q(l, S, ib, kb, Qm, Vm));
+      trace("qrcp completion", l);
+    }
   }
   std::vector<int> kk(ncl, 0);
   {
@@ -1636,6 +1780,10 @@ int Factor::sparsify(int l, const NDResult &nd, LevelState &S, LevelState &Nx) {
     for (size_t q = 0; q < ifs.size(); ++q) {
       kk[ifs[q]] = ks[q];
       rs.add(S.size[ifs[q]], ks[q]);
+      if (!members.empty()) {
+        auto &mr = members[size_t(csys(l, ifs[q]))].ranks;
+        if (size_t(l) < mr.size()) mr[size_t(l)].add(S.size[ifs[q]], ks[q]);
+      }
       const double m = S.size[ifs[q]], c = ncols[ifs[q]], k = ks[q];
       qrcp_bytes += (m * c + m * m) * double(tsz);
       qrcp_flops += 4.0 * m * c * k - 2.0 * k * k * (m + c) + 4.0 * k * k * k / 3.0;
@@ -1648,6 +1796,7 @@ int Factor::sparsify(int l, const NDResult &nd, LevelState &S, LevelState &Nx) {
     std::vector<GemmDesc> gm;
     std::vector<GemvDesc> gf, gb;
     std::vector<const std::vector<int32_t> *> os;
+    std::vector<int> vs;
     for (int s : ifs) {
       const int m = S.size[s];
       void *Fp, *Bp;
@@ -1682,15 +1831,21 @@ int Factor::sparsify(int l, const NDResult &nd, LevelState &S, LevelState &Nx) {
       d.A = Bp;
       gb.push_back(d);
       os.push_back(&S.slots[s]);
-      apply_bytes += 2.0 * double(m) * m * tsz;   // F_s forward, B_s backward
-      flops += 4.0 * double(m) * m * m;
+      vs.push_back(csys(l, s));
+      acct(csys(l, s), 2.0 * double(m) * m * tsz, 4.0 * double(m) * m * m);   // F_s forward, B_s backward
     }
     SP_TRY(gemm_batch(gm));
     trace("gemm", l);
-    defer([this, &AL, gf, os]() { return AL.F.set(*this, gf, os, 0); });
-    defer([this, &AL, gb, os]() { return AL.B.set(*this, gb, os, 0); });
-    defer([this, &AL, gf, os]() { return AL.FT.set(*this, gf, os, 1); });
-    defer([this, &AL, gb, os]() { return AL.BT.set(*this, gb, os, 1); });
+    defer([this, &AL, gf, gb, os, vs, l]() {
+      SP_TRY(AL.F.set(*this, gf, os, 0));
+      SP_TRY(AL.B.set(*this, gb, os, 0));
+      SP_TRY(AL.FT.set(*this, gf, os, 1));
+      SP_TRY(AL.BT.set(*this, gb, os, 1));
+      SP_TRY(member_gemv(l, &ApplyLevel::F, gf, os, vs, 0));
+      SP_TRY(member_gemv(l, &ApplyLevel::B, gb, os, vs, 0));
+      SP_TRY(member_gemv(l, &ApplyLevel::FT, gf, os, vs, 1));
+      return member_gemv(l, &ApplyLevel::BT, gb, os, vs, 1);
+    });
     trace("compress F/B sets", l);
   }
   // ---- merge: next-level clusters from the coarse parts
@@ -1802,7 +1957,7 @@ int Factor::sparsify(int l, const NDResult &nd, LevelState &S, LevelState &Nx) {
       h.K = B.cols;
       h.alpha = 1.0;
       g2.push_back(h);
-      flops += 2.0 * double(kk[i]) * B.cols * (B.rows + kk[j]);
+      acct(csys(l, i), 0.0, 2.0 * double(kk[i]) * B.cols * (B.rows + kk[j]));
     }
     trace("pair descriptors", l);
     SP_TRY(gemm_batch(g1));
@@ -1820,11 +1975,35 @@ int Factor::sparsify(int l, const NDResult &nd, LevelState &S, LevelState &Nx) {
 }
 
 // ------------------------------------------------------------------ driver
+// Host copy of a BSR pattern, validated (rowptr monotone from 0 to nnzb,
+// colind in range and strictly ascending in every row).
+static int check_pattern(const std::vector<int32_t> &rp, const std::vector<int32_t> &ci, int K,
+                         int64_t nnzb, const char *who) {
+  if (rp[0] != 0 || rp[size_t(K)] != nnzb) {
+    set_error("%srowptr[0] must be 0 and rowptr[n_brows] must equal nnzb", who);
+    return SPAND_EINVAL;
+  }
+  for (int e = 0; e < K; ++e) {
+    if (rp[size_t(e) + 1] < rp[size_t(e)]) {
+      set_error("%srowptr must be non-decreasing", who);
+      return SPAND_EINVAL;
+    }
+    for (int t = rp[size_t(e)]; t < rp[size_t(e) + 1]; ++t) {
+      if (ci[size_t(t)] < 0 || ci[size_t(t)] >= K || (t > rp[size_t(e)] && ci[size_t(t)] <= ci[size_t(t) - 1])) {
+        set_error("%scolind must be in range and strictly ascending in every block row (row %d)",
+                  who, e);
+        return SPAND_EINVAL;
+      }
+    }
+  }
+  return SPAND_OK;
+}
+
 int Factor::build(const spand_bsr_t &A, const spand_grid_t &g, const spand_opts_t &o,
                   const Factor *sym) {
-  auto t0 = std::chrono::steady_clock::now();
-  trace_t = t0;
-  const double drv0 = pool_driver_ms();
+  build_t0 = std::chrono::steady_clock::now();
+  trace_t = build_t0;
+  build_drv0 = pool_driver_ms();
   bs = A.bs;
   K = A.n_brows;
   N = int64_t(K) * bs;
@@ -1833,6 +2012,7 @@ int Factor::build(const spand_bsr_t &A, const spand_grid_t &g, const spand_opts_
   L = o.nlevels > 0 ? o.nlevels : default_levels(K);
   grid = g;
   opts = o;
+  d_val = A.d_val;
   if (sym) {
     // refactorization: the pattern (checked by the caller) and the ordering
     // of the earlier factorization; only the numeric phases run again
@@ -1847,27 +2027,90 @@ int Factor::build(const spand_bsr_t &A, const spand_grid_t &g, const spand_opts_
     SP_HIP(hipMemcpyAsync(h_colind.data(), A.d_colind, A.nnzb * 4, hipMemcpyDeviceToHost, stream));
     SP_HIP(hipStreamSynchronize(stream));
     trace("sync", -1);
-    if (h_rowptr[0] != 0 || h_rowptr[K] != A.nnzb) {
-      set_error("rowptr[0] must be 0 and rowptr[n_brows] must equal nnzb");
-      return SPAND_EINVAL;
-    }
-    for (int e = 0; e < K; ++e) {
-      if (h_rowptr[e + 1] < h_rowptr[e]) {
-        set_error("rowptr must be non-decreasing");
-        return SPAND_EINVAL;
-      }
-      for (int t = h_rowptr[e]; t < h_rowptr[e + 1]; ++t) {
-        if (h_colind[t] < 0 || h_colind[t] >= K || (t > h_rowptr[e] && h_colind[t] <= h_colind[t - 1])) {
-          set_error("colind must be in range and strictly ascending in every block row (row %d)", e);
-          return SPAND_EINVAL;
-        }
-      }
-    }
+    SP_TRY(check_pattern(h_rowptr, h_colind, K, A.nnzb, ""));
     trace("read pattern + validate", -1);
     nd_sym = std::make_shared<const NDResult>(
         nested_dissection(g.nx, g.ny, g.periodic_x != 0, g.periodic_y != 0, L));
     trace("nested dissection", -1);
   }
+  return numeric();
+}
+
+int Factor::build_batch(const std::vector<BatchSystem> &sy, const spand_opts_t &o) {
+  build_t0 = std::chrono::steady_clock::now();
+  trace_t = build_t0;
+  build_drv0 = pool_driver_ms();
+  const int n = int(sy.size());
+  bs = sy[0].A.bs;
+  ft = o.factor_dtype == SPAND_F32 ? FType::F32 : FType::F64;
+  eps = o.eps;
+  opts = o;
+  members.assign(size_t(n), Member{});
+  int64_t eo = 0, no = 0;
+  L = 0;
+  for (int m = 0; m < n; ++m) {
+    Member &M = members[size_t(m)];
+    M.K = sy[size_t(m)].A.n_brows;
+    M.L = sy[size_t(m)].L;
+    M.elem_off = eo;
+    M.nnz_off = no;
+    M.dof_off = eo * bs;
+    M.N = int64_t(M.K) * bs;
+    M.d_val = sy[size_t(m)].A.d_val;
+    M.ranks.assign(size_t(std::max(M.L - 1, 0)), RankStat{});
+    eo += M.K;
+    no += sy[size_t(m)].A.nnzb;
+    L = std::max(L, M.L);
+  }
+  if (eo > INT_MAX / 2 || no > INT_MAX) {
+    set_error("batched factorization of %lld elements and %lld blocks exceeds the 32-bit indices",
+              (long long)eo, (long long)no);
+    return SPAND_EINVAL;
+  }
+  K = int(eo);
+  N = eo * bs;
+  // the systems' patterns: all copies queued, then one wait
+  std::vector<std::vector<int32_t>> rps(static_cast<size_t>(n)), cis(static_cast<size_t>(n));
+  for (int m = 0; m < n; ++m) {
+    const spand_bsr_t &A = sy[size_t(m)].A;
+    rps[size_t(m)].resize(size_t(A.n_brows) + 1);
+    cis[size_t(m)].resize(size_t(A.nnzb));
+    SP_HIP(hipMemcpyAsync(rps[size_t(m)].data(), A.d_rowptr, rps[size_t(m)].size() * 4,
+                          hipMemcpyDeviceToHost, stream));
+    SP_HIP(hipMemcpyAsync(cis[size_t(m)].data(), A.d_colind, cis[size_t(m)].size() * 4,
+                          hipMemcpyDeviceToHost, stream));
+  }
+  SP_HIP(hipStreamSynchronize(stream));
+  trace("sync", -1);
+  h_rowptr.assign(size_t(K) + 1, 0);
+  h_colind.resize(size_t(no));
+  esys.resize(size_t(K));
+  std::vector<NDResult> parts(static_cast<size_t>(n));
+  std::vector<int64_t> eoffs(static_cast<size_t>(n));
+  for (int m = 0; m < n; ++m) {
+    const Member &M = members[size_t(m)];
+    char who[32];
+    std::snprintf(who, sizeof(who), "system %d: ", m);
+    SP_TRY(check_pattern(rps[size_t(m)], cis[size_t(m)], M.K, int64_t(cis[size_t(m)].size()), who));
+    for (int e = 0; e < M.K; ++e) {
+      h_rowptr[size_t(M.elem_off + e)] = int32_t(M.nnz_off + rps[size_t(m)][size_t(e)]);
+      esys[size_t(M.elem_off + e)] = m;
+    }
+    for (size_t t = 0; t < cis[size_t(m)].size(); ++t)
+      h_colind[size_t(M.nnz_off) + t] = int32_t(cis[size_t(m)][t] + M.elem_off);
+    const spand_grid_t &g = sy[size_t(m)].grid;
+    parts[size_t(m)] = nested_dissection(g.nx, g.ny, g.periodic_x != 0, g.periodic_y != 0, M.L);
+    eoffs[size_t(m)] = M.elem_off;
+  }
+  h_rowptr[size_t(K)] = int32_t(no);
+  trace("read patterns + validate + nested dissections", -1);
+  nd_sym = std::make_shared<const NDResult>(nd_union(parts, eoffs));
+  for (auto &M : members) M.lv.assign(size_t(L), ApplyLevel{});
+  trace("union ordering", -1);
+  return numeric();
+}
+
+int Factor::numeric() {
   const NDResult &nd = *nd_sym;
   void *p;
   SP_TRY(dalloc(&p, size_t(N) * 4, true));
@@ -1877,7 +2120,7 @@ int Factor::build(const spand_bsr_t &A, const spand_grid_t &g, const spand_opts_
   d_tbuf = (double *)p;
   SP_TRY(dalloc(&p, size_t(N) * 8, true));
   d_xg = (double *)p;
-  use_graphs = (o.flags & SPAND_FLAG_NO_GRAPH) == 0 && !std::getenv("SPAND_NO_GRAPH");
+  use_graphs = (opts.flags & SPAND_FLAG_NO_GRAPH) == 0 && !std::getenv("SPAND_NO_GRAPH");
   {
     const int tr = tuned_gemv_rows(ft, bs);
     if (tr > 0) gemv_rows = tr;
@@ -1887,12 +2130,17 @@ int Factor::build(const spand_bsr_t &A, const spand_grid_t &g, const spand_opts_
   SP_HIP(hipMemsetAsync(d_flag, 0, 64, stream));
   lv.assign(L, ApplyLevel{});
   auto t1 = std::chrono::steady_clock::now();
-  t_host_ms += std::chrono::duration<double, std::milli>(t1 - t0).count();
+  t_host_ms += std::chrono::duration<double, std::milli>(t1 - build_t0).count();
   mark(PH_GATHER);
   LevelState S;
-  SP_TRY(level0(A, nd, S));
+  SP_TRY(level0(nd, S));
   for (int l = 0; l < L; ++l) {
     if (l >= 1) SP_TRY(eliminate_dense(l, S));
+    // a system whose top level this is keeps what its top clusters hold
+    for (size_t m = 0; m < members.size(); ++m)
+      if (members[m].L - 1 == l)
+        for (int c = 0; c < int(S.size.size()); ++c)
+          if (csys(l, c) == int(m)) members[m].top_size += S.size[c];
     if (l == L - 1) break;
     LevelState Nx;
     SP_TRY(sparsify(l, nd, S, Nx));
@@ -1900,7 +2148,10 @@ int Factor::build(const spand_bsr_t &A, const spand_grid_t &g, const spand_opts_
     S = std::move(Nx);
   }
   int tops = 0;
-  for (int c = 0; c < int(S.size.size()); ++c) tops += S.size[c];
+  if (members.empty())
+    for (int c = 0; c < int(S.size.size()); ++c) tops += S.size[c];
+  else
+    for (const auto &M : members) tops += M.top_size;
   top_size = tops;
   SP_TRY(flush_deferred());
   mark(PH_END);
@@ -1909,7 +2160,7 @@ int Factor::build(const spand_bsr_t &A, const spand_grid_t &g, const spand_opts_
   temp.release();
   next_temp.release();
   retired.release();
-  alloc_ms = pool_driver_ms() - drv0;
+  alloc_ms = pool_driver_ms() - build_drv0;
   int flag = 0;
   SP_HIP(hipMemcpy(&flag, d_flag, 4, hipMemcpyDeviceToHost));
   trace("release + flag", -1);
@@ -1926,7 +2177,8 @@ int Factor::build(const spand_bsr_t &A, const spand_grid_t &g, const spand_opts_
 // y = M^-1 r:  forward over levels applies L' (interiors: x_n -= A_ns A_ss^-1 x_s)
 // and F_s (interfaces); backward applies B_s and R' (x_s = A_ss^-1 (x_s - A_sn x_n)).
 // y = M^-T r:  forward applies R'^T and B_s^T, backward F_s^T and L'^T.
-int Factor::sweeps(double *x, int transpose, hipStream_t st) {
+int Factor::sweeps(const std::vector<ApplyLevel> &lv, double *x, int transpose, hipStream_t st) {
+  const int L = int(lv.size());
   auto inplace = [&](const GemvSet &g) -> int {
     if (!g.n) return SPAND_OK;
     SP_TRY(launch_gemv(ft, g.d_items, g.d_chunks, g.nchunks, x, d_tbuf, 1.0, 0.0, st));
@@ -1967,7 +2219,10 @@ int Factor::sweeps(double *x, int transpose, hipStream_t st) {
 }
 
 // Capture the sweeps on the fixed vector d_xg once; replays need one launch.
-int Factor::capture(int transpose) {
+// member >= 0: the sweeps of that system of a batch (its share of d_xg).
+int Factor::capture(int member, int transpose) {
+  const std::vector<ApplyLevel> &plan = member < 0 ? lv : members[size_t(member)].lv;
+  hipGraphExec_t *ge = member < 0 ? gexec : members[size_t(member)].gexec;
   hipStream_t cs;
   SP_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
   hipGraph_t g = nullptr;
@@ -1977,7 +2232,7 @@ int Factor::capture(int transpose) {
     r = SPAND_EHIP;
   }
   if (r == SPAND_OK) {
-    const int rs = sweeps(d_xg, transpose, cs);
+    const int rs = sweeps(plan, d_xg, transpose, cs);
     const hipError_t e = hipStreamEndCapture(cs, &g);
     if (rs != SPAND_OK) r = rs;
     else if (e != hipSuccess || !g) {
@@ -1985,9 +2240,9 @@ int Factor::capture(int transpose) {
       r = SPAND_EHIP;
     }
   }
-  if (r == SPAND_OK && hipGraphInstantiate(&gexec[transpose], g, nullptr, nullptr, 0) != hipSuccess) {
+  if (r == SPAND_OK && hipGraphInstantiate(&ge[transpose], g, nullptr, nullptr, 0) != hipSuccess) {
     set_error("hipGraphInstantiate failed");
-    gexec[transpose] = nullptr;
+    ge[transpose] = nullptr;
     r = SPAND_EHIP;
   }
   if (g) (void)hipGraphDestroy(g);
@@ -2003,18 +2258,30 @@ int Factor::capture(int transpose) {
 // captures of concurrent host callers apart.  `which`: bit 0 M^-1, bit 1 M^-T.
 static std::mutex g_capture_mu;
 
-int Factor::capture_graphs(int which) {
+int Factor::capture_graphs(int which, int member) {
   if (!use_graphs) return SPAND_OK;
   std::lock_guard<std::mutex> lk(g_capture_mu);
+  const hipGraphExec_t *ge = member < 0 ? gexec : members[size_t(member)].gexec;
   for (int t = 0; t < 2; ++t)
-    if ((which >> t & 1) && !gexec[t]) SP_TRY(capture(t));
+    if ((which >> t & 1) && !ge[t]) SP_TRY(capture(member, t));
   return SPAND_OK;
 }
 
-int Factor::apply(const double *in, double *out, int transpose, hipStream_t st) {
+int Factor::apply(const double *in, double *out, int transpose, hipStream_t st, int member) {
+  if (member >= 0) {
+    // one system of a batch: its vector goes through its share of d_xg (the
+    // sweeps address the unknowns of the whole batch)
+    const Member &M = members[size_t(member)];
+    double *seg = d_xg + M.dof_off;
+    SP_HIP(hipMemcpyAsync(seg, in, size_t(M.N) * 8, hipMemcpyDeviceToDevice, st));
+    if (use_graphs && M.gexec[transpose]) SP_HIP(hipGraphLaunch(M.gexec[transpose], st));
+    else SP_TRY(sweeps(M.lv, d_xg, transpose, st));
+    SP_HIP(hipMemcpyAsync(out, seg, size_t(M.N) * 8, hipMemcpyDeviceToDevice, st));
+    return SPAND_OK;
+  }
   if (!use_graphs || !gexec[transpose]) {
     if (out != in) SP_HIP(hipMemcpyAsync(out, in, size_t(N) * 8, hipMemcpyDeviceToDevice, st));
-    return sweeps(out, transpose, st);
+    return sweeps(lv, out, transpose, st);
   }
   SP_HIP(hipMemcpyAsync(d_xg, in, size_t(N) * 8, hipMemcpyDeviceToDevice, st));
   SP_HIP(hipGraphLaunch(gexec[transpose], st));
@@ -2022,9 +2289,25 @@ int Factor::apply(const double *in, double *out, int transpose, hipStream_t st) 
   return SPAND_OK;
 }
 
-void Factor::fill_stats(spand_factor_stats_t *st) const {
+int Factor::apply_batch(const std::vector<const double *> &in, const std::vector<double *> &out,
+                        int transpose, hipStream_t st) {
+  for (size_t m = 0; m < members.size(); ++m)
+    SP_HIP(hipMemcpyAsync(d_xg + members[m].dof_off, in[m], size_t(members[m].N) * 8,
+                          hipMemcpyDeviceToDevice, st));
+  if (use_graphs && gexec[transpose]) SP_HIP(hipGraphLaunch(gexec[transpose], st));
+  else SP_TRY(sweeps(lv, d_xg, transpose, st));
+  for (size_t m = 0; m < members.size(); ++m)
+    SP_HIP(hipMemcpyAsync(out[m], d_xg + members[m].dof_off, size_t(members[m].N) * 8,
+                          hipMemcpyDeviceToDevice, st));
+  return SPAND_OK;
+}
+
+void Factor::fill_stats(spand_factor_stats_t *st, int member) const {
   std::memset(st, 0, sizeof(*st));
-  st->nlevels = L;
+  const Member *M = member >= 0 ? &members[size_t(member)] : nullptr;
+  const std::vector<RankStat> &ranks = M ? M->ranks : this->ranks;
+  st->nlevels = M ? M->L : L;
+  st->batch_systems = members.empty() ? 1 : int32_t(members.size());
   for (size_t l = 0; l < ranks.size() && l < SPAND_MAX_LEVELS; ++l) {
     const RankStat &r = ranks[l];
     st->n_clusters[l] = r.n;
@@ -2034,9 +2317,9 @@ void Factor::fill_stats(spand_factor_stats_t *st) const {
     st->size_before[l] = r.msum;
     st->size_after[l] = r.ksum;
   }
-  st->top_size = top_size;
-  st->factor_bytes = int64_t(apply_bytes);
-  st->factor_flops = flops;
+  st->top_size = M ? M->top_size : top_size;
+  st->factor_bytes = int64_t(M ? M->apply_bytes : apply_bytes);
+  st->factor_flops = M ? M->flops : flops;
   st->t_host_ms = t_host_ms;
   st->t_device_ms = ph_ms[PH_GATHER] + ph_ms[PH_LU] + ph_ms[PH_SCHUR] + ph_ms[PH_SCALE] +
                     ph_ms[PH_RRQR] + ph_ms[PH_COMPRESS];

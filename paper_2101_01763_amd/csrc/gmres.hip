@@ -263,7 +263,7 @@ size_t sstep_workspace_bytes(int64_t N, const sstep_opts_t &o) {
   return t;
 }
 
-int sstep_solve(const spand_bsr_t &A0, Factor *M, const double *b, double *x,
+int sstep_solve(const spand_bsr_t &A0, Factor *M, int member, const double *b, double *x,
                 const sstep_opts_t &o, sstep_stats_t *st, hipStream_t stream,
                 const SolveWorkspace *ws) {
   const int64_t N = int64_t(A0.n_brows) * A0.bs;
@@ -391,7 +391,7 @@ int sstep_solve(const spand_bsr_t &A0, Factor *M, const double *b, double *x,
   int n_spmv = 0, n_apply = 0, n_reduce = 0;   // n_reduce: inner-product reductions
   auto Minv = [&](const double *in, double *out) -> int {
     ++n_apply;
-    if (M) return M->apply(in, out, tr, stream);
+    if (M) return M->apply(in, out, tr, stream, member);
     if (in != out)
       SP_HIP(hipMemcpyAsync(out, in, size_t(N) * 8, hipMemcpyDeviceToDevice, stream));
     return SPAND_OK;

@@ -70,6 +70,7 @@ struct NDResult {
 
 int default_levels(int64_t K);
 NDResult nested_dissection(int nx, int ny, bool px, bool py, int L);
+NDResult nd_union(const std::vector<NDResult> &parts, const std::vector<int64_t> &elem_off);
 
 // ----------------------------------------------------------------- device memory
 // Simple owning device buffer.
@@ -119,8 +120,9 @@ struct CopyDesc {
 // ldd, factor precision).
 struct GatherItem {
   void *dst;
-  int32_t blk;
+  const double *src;   // b x b block of the input values
   int32_t ldd;
+  int32_t pad;
 };
 
 // Panel factorisation problem (GJE / LU on an augmented row-major matrix).
@@ -227,9 +229,9 @@ int launch_gemm(FType t, const GemmDesc *d_items, const int32_t *d_tile_start, i
                 const int32_t *d_coarse = nullptr);
 // host: the coarse index of items [a, b) of a tile_start array (ts[a..b])
 void gemm_coarse(const std::vector<int32_t> &ts, size_t a, size_t b, std::vector<int32_t> &out);
+// b x b blocks of BSR values (FP64) into factor-precision matrices
+int launch_bsr_gather(FType t, const GatherItem *d_items, int n, int b, hipStream_t st);
 // src double -> dst factor type (src_is_factor = 0) or factor -> factor (1)
-int launch_bsr_gather(FType t, const double *d_val, const GatherItem *d_items, int n, int b,
-                      hipStream_t st);
 int launch_copy(FType t, int src_is_factor, const CopyDesc *d_items, int n, int64_t max_elems,
                 hipStream_t st);
 // transposed copies (trans = 1), 32 x 32 tiles through LDS
@@ -307,7 +309,9 @@ struct SolveWorkspace {
 };
 struct Factor;
 size_t sstep_workspace_bytes(int64_t N, const sstep_opts_t &o);
-int sstep_solve(const spand_bsr_t &A, Factor *M, const double *b, double *x,
+// M: the preconditioner (nullptr: none); member >= 0 selects one system of
+// a batched factorization
+int sstep_solve(const spand_bsr_t &A, Factor *M, int member, const double *b, double *x,
                 const sstep_opts_t &o, sstep_stats_t *st, hipStream_t stream,
                 const SolveWorkspace *ws = nullptr);
 

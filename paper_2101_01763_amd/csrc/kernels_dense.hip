@@ -347,14 +347,14 @@ int launch_copy(FType t, int src_is_factor, const CopyDesc *d_items, int n, int6
   return SPAND_OK;
 }
 
-// Gather of whole b x b blocks of the BSR value array (FP64, row-major
-// blocks) into factor-precision matrices: one workgroup per item, source
-// read contiguously, destination rows of b at leading dimension ldd.
+// Gather of whole b x b blocks of BSR value arrays (FP64, row-major blocks;
+// each item names its source block, so one launch may read the blocks of
+// several matrices) into factor-precision matrices: one workgroup per item,
+// source read contiguously, destination rows of b at leading dimension ldd.
 template <typename Td>
-__global__ __launch_bounds__(256) void k_bsr_gather(const double *__restrict__ val,
-                                                    const GatherItem *__restrict__ items, int b) {
+__global__ __launch_bounds__(256) void k_bsr_gather(const GatherItem *__restrict__ items, int b) {
   const GatherItem it = items[blockIdx.x];
-  const double *s = val + (int64_t)it.blk * b * b;
+  const double *s = it.src;
   Td *d = (Td *)it.dst;
   const int bb = b * b;
   for (int idx = threadIdx.x; idx < bb; idx += 256) {
@@ -363,13 +363,12 @@ __global__ __launch_bounds__(256) void k_bsr_gather(const double *__restrict__ v
   }
 }
 
-int launch_bsr_gather(FType t, const double *d_val, const GatherItem *d_items, int n, int b,
-                      hipStream_t st) {
+int launch_bsr_gather(FType t, const GatherItem *d_items, int n, int b, hipStream_t st) {
   if (n <= 0) return SPAND_OK;
   if (t == FType::F64)
-    hipLaunchKernelGGL(k_bsr_gather<double>, dim3(n), dim3(256), 0, st, d_val, d_items, b);
+    hipLaunchKernelGGL(k_bsr_gather<double>, dim3(n), dim3(256), 0, st, d_items, b);
   else
-    hipLaunchKernelGGL(k_bsr_gather<float>, dim3(n), dim3(256), 0, st, d_val, d_items, b);
+    hipLaunchKernelGGL(k_bsr_gather<float>, dim3(n), dim3(256), 0, st, d_items, b);
   SP_HIP(hipGetLastError());
   return SPAND_OK;
 }

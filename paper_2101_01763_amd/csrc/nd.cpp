@@ -193,4 +193,42 @@ NDResult nested_dissection(int nx, int ny, bool px, bool py, int L) {
   return R;
 }
 
+// Disjoint union of the orderings of several grids whose elements are
+// numbered one grid after the other (grid g from elem_off[g]): level l holds
+// the level-l clusters of every grid, grid by grid, each with its own order;
+// grids with fewer levels have no clusters above their top.  Node ids are
+// shifted by 2^L per grid so that they stay distinct.
+NDResult nd_union(const std::vector<NDResult> &parts, const std::vector<int64_t> &elem_off) {
+  NDResult R;
+  for (const auto &p : parts) R.L = std::max(R.L, p.L);
+  R.levels.resize(size_t(R.L));
+  R.children.resize(size_t(R.L));
+  int64_t node_base = 0;
+  std::vector<int> cbase(size_t(R.L), 0);      // clusters of each level so far
+  for (size_t g = 0; g < parts.size(); ++g) {
+    const NDResult &p = parts[g];
+    const int32_t eo = int32_t(elem_off[g]);
+    for (int32_t v : p.node_of_elem) R.node_of_elem.push_back(int32_t(v + node_base));
+    for (int32_t v : p.perm) R.perm.push_back(v + eo);
+    for (const auto &kv : p.node_level) R.node_level.emplace(kv.first + node_base, kv.second);
+    for (int l = 0; l < p.L; ++l) {
+      if (l >= 1)
+        for (const auto &kids : p.children[size_t(l)]) {
+          std::vector<int> k2;
+          for (int c : kids) k2.push_back(c + cbase[size_t(l - 1)]);
+          R.children[size_t(l)].push_back(std::move(k2));
+        }
+      for (const auto &c : p.levels[size_t(l)]) {
+        NDCluster d = c;
+        d.node = int32_t(c.node + node_base);
+        for (auto &e : d.elems) e += eo;
+        R.levels[size_t(l)].push_back(std::move(d));
+      }
+    }
+    for (int l = 0; l < p.L; ++l) cbase[size_t(l)] += int(p.levels[size_t(l)].size());
+    node_base += int64_t(1) << p.L;
+  }
+  return R;
+}
+
 }  // namespace spand
