@@ -197,7 +197,7 @@ struct Factor {
   int upload_level_slots(LevelState &S);
   // Host work that only the apply needs (sweep descriptor sets): queued
   // while the device is busy and run while the host would otherwise wait
-  // (before a rank read-back, at the end of a level and of the build).
+  // (before a rank read-back, and at the end of the build).
   std::vector<std::function<int()>> deferred;
   void defer(std::function<int()> f) { deferred.push_back(std::move(f)); }
   int flush_deferred();

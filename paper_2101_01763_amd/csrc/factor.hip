@@ -435,6 +435,32 @@ int Factor::elim_batch(std::vector<ElimDesc> &items, int mode) {
     while (na < int(items.size()) && items[na].n > k) ++na;
     return na;
   };
+  // elimination of block [k0, k0 + ELIM_BLK) in its own columns, then its
+  // pivot rows of the other columns out to TB
+  auto eliminate_block = [&](int k0) -> int {
+    if (fused) {
+      // one launch per 64-row size class (items are sorted by n, descending),
+      // so that no workgroup carries waves without rows
+      const int na = nactive_at(k0);
+      for (int a = 0; a < na;) {
+        int b = a + 1;
+        while (b < na && cdiv(items[b].n, 64) == cdiv(items[a].n, 64)) ++b;
+        SP_TRY(launch_elim_block(ft, d_items + a, b - a, k0, mode, items[a].n, d_flag, stream));
+        a = b;
+      }
+    } else {
+      for (int k = k0; k < std::min(nmax, k0 + ELIM_BLK); k += ELIM_NB) {
+        const int nactive = nactive_at(k);
+        const int max_tiles = int(cdiv(nmax, 64) * cdiv(ELIM_BLK, 64));   // the block's columns
+        SP_TRY(launch_elim_step(ft, d_items, nactive, k, mode, max_tiles, d_flag, k0,
+                                k0 + ELIM_BLK, stream));
+        if (lu) SP_TRY(launch_elim_pb(ft, d_items, nactive, k, k0, stream));
+      }
+    }
+    return launch_elim_extract(ft, d_items, nactive_at(k0), k0, lu ? 1 : 0, stream);
+  };
+  // the first block runs while the products of all blocks are planned
+  SP_TRY(eliminate_block(0));
   // trailing products of every block: columns [k0 + ELIM_BLK, ncols), and for
   // Gauss-Jordan also [0, k0)
   const size_t tsz = fsize(ft);
@@ -499,26 +525,7 @@ int Factor::elim_batch(std::vector<ElimDesc> &items, int mode) {
   int32_t *d_coarse = nullptr;
   if (!coarse.empty()) SP_TRY(upload(coarse, &d_coarse, false));
   for (int b = 0, k0 = 0; k0 < nmax; ++b, k0 += ELIM_BLK) {
-    if (fused) {
-      // one launch per 64-row size class (items are sorted by n, descending),
-      // so that no workgroup carries waves without rows
-      const int na = nactive_at(k0);
-      for (int a = 0; a < na;) {
-        int b = a + 1;
-        while (b < na && cdiv(items[b].n, 64) == cdiv(items[a].n, 64)) ++b;
-        SP_TRY(launch_elim_block(ft, d_items + a, b - a, k0, mode, items[a].n, d_flag, stream));
-        a = b;
-      }
-    } else {
-      for (int k = k0; k < std::min(nmax, k0 + ELIM_BLK); k += ELIM_NB) {
-        const int nactive = nactive_at(k);
-        const int max_tiles = int(cdiv(nmax, 64) * cdiv(ELIM_BLK, 64));   // the block's columns
-        SP_TRY(launch_elim_step(ft, d_items, nactive, k, mode, max_tiles, d_flag, k0,
-                                k0 + ELIM_BLK, stream));
-        if (lu) SP_TRY(launch_elim_pb(ft, d_items, nactive, k, k0, stream));
-      }
-    }
-    SP_TRY(launch_elim_extract(ft, d_items, nactive_at(k0), k0, lu ? 1 : 0, stream));
+    if (b > 0) SP_TRY(eliminate_block(k0));
     const size_t g0 = bstart[b], g1 = bstart[b + 1];
     if (g1 > g0) {   // this block's descriptors; their tile numbers start at ts[g0]
       double fl = 0.0, by = 0.0;
@@ -1969,8 +1976,10 @@ int Factor::sparsify(int l, const NDResult &nd, LevelState &S, LevelState &Nx) {
   }
   SP_TRY(upload_level_slots(Nx));
   trace("merge plan", l);
-  SP_TRY(flush_deferred());
-  trace("deferred sets", l);
+  // the sweep sets queued by this level (compression) are built while the
+  // host next waits for the device, before the next level's rank read-back:
+  // the device goes on to the next level's eliminations meanwhile (the
+  // caller keeps S, whose slot lists they read, alive until then)
   return SPAND_OK;
 }
 
@@ -2132,7 +2141,7 @@ int Factor::numeric() {
   auto t1 = std::chrono::steady_clock::now();
   t_host_ms += std::chrono::duration<double, std::milli>(t1 - build_t0).count();
   mark(PH_GATHER);
-  LevelState S;
+  LevelState S, prev;   // prev: the level before, read by sweep sets not yet built
   SP_TRY(level0(nd, S));
   for (int l = 0; l < L; ++l) {
     if (l >= 1) SP_TRY(eliminate_dense(l, S));
@@ -2145,6 +2154,9 @@ int Factor::numeric() {
     LevelState Nx;
     SP_TRY(sparsify(l, nd, S, Nx));
     free_temp();
+    // every set that read the level before was built in this sparsify (at
+    // its rank read-back); the sets of this level's compression read S
+    prev = std::move(S);
     S = std::move(Nx);
   }
   int tops = 0;
