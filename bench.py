@@ -185,13 +185,14 @@ def bench_batch(args):
             F.destroy()
         return t1 - t0, t2 - t1, infos
 
+    nst = args.batch_streams
     for _ in range(args.warmup):
-        run(8)
-    res = [run(8, probe=(k == 0)) for k in range(args.steps)]
+        run(nst)
+    res = [run(nst, probe=(k == 0)) for k in range(args.steps)]
     tf = float(np.median([r[0] for r in res]))
     ts = float(np.median([r[1] for r in res]))
     infos = res[-1][2]
-    sep = run(8, separate=True)
+    sep = run(nst, separate=True)
     seq = run(1, separate=True)
     out = {
         "metric": "batched spaND factor + s-step GMRES (64 uneven systems); DOF/s",
@@ -202,7 +203,7 @@ def bench_batch(args):
         "config": {"workload": f"C4 batch: 64 systems, {ntot} DOF total, n in 32..96, p in 1..3, "
                                f"FP32 spaND eps=1e-2, s=5, m=60, rtol=1e-8 ({args.schedule}); "
                                f"systems of one block size factored together (groups of up to 4M "
-                               f"unknowns, 2 at a time), solves on 8 streams",
+                               f"unknowns, 2 at a time), solves on {nst} streams",
                    "schedule": args.schedule},
         "t_factor_ms": 1e3 * tf, "t_solve_ms": 1e3 * ts,
         "all_converged": all(i.converged for i in infos),
@@ -398,6 +399,8 @@ def main():
                     help="skip the FP64-factor comparison run (child process)")
     ap.add_argument("--no-secondary", action="store_true",
                     help="skip the secondary C3 points (L = 12; eps = 0.1)")
+    ap.add_argument("--batch-streams", type=int, default=8,
+                    help="C4: worker streams of the batched calls")
     ap.add_argument("--no-ceilings", action="store_true",
                     help="skip the measured copy / matrix-core ceilings")
     ap.add_argument("--calibrate-copy", action="store_true",

@@ -9,7 +9,9 @@ precision and eps factored together, one set of launches per phase):
     its systems) equals the per-handle applies, also for a partial set of a
     group's handles (applied one by one) and in place;
   * the handles of a group stay valid when other handles of the group are
-    destroyed; a handle that shares a factorization cannot be refactored.
+    destroyed; a handle that shares a factorization cannot be refactored;
+  * a call mixing whole groups, a partial group, an FP64 group and a factor
+    of its own; empty and one-system batches.
 """
 import numpy as np
 import pytest
@@ -92,3 +94,38 @@ def test_batched_handles_lifetime_and_refactor():
     assert torch.equal(Fs[4].apply(rs[4]), ref[4])
     x, info = sp.solve(systems[4][0], rs[4], Fs[4], s=5, restart=60, rtol=1e-8)
     assert info.converged and info.relres <= 1e-8
+
+
+def test_apply_batched_mixed_handles():
+    """A call mixing whole groups, a partial group, a factor of its own and
+    FP64 handles (a group of their own): every result equals that handle's
+    own apply; an empty call does nothing."""
+    systems, cfgs, Ls, Fs = _batch("f32")
+    sysd = systems[0]
+    F1 = sp.factor(sysd[0], sysd[1], sysd[2], True, False, eps=1e-2, nlevels=Ls[0], dtype="f32")
+    sys64 = [systems[1], systems[3]]
+    F64 = sp.factor_batched(sys64, eps=1e-2, nlevels=[Ls[1], Ls[3]], dtype="f64")
+    assert all(F.stats()["batch_systems"] == 2 for F in F64)
+    # whole groups: p = 1 (Fs[0], Fs[2]) and FP64 (F64); partial: p = 2
+    # (Fs[1], Fs[3] without Fs[4]); F1 a factor of its own
+    hs = [Fs[0], Fs[2], F1, F64[1], Fs[1], Fs[3], F64[0]]
+    ns = [cfgs[0].N, cfgs[2].N, cfgs[0].N, cfgs[3].N, cfgs[1].N, cfgs[3].N, cfgs[1].N]
+    rng = np.random.default_rng(21)
+    rs = [torch.as_tensor(rng.standard_normal(n), device="cuda") for n in ns]
+    for tr in (False, True):
+        out = sp.apply_batched(hs, rs, transpose=tr)
+        for i, (F, r) in enumerate(zip(hs, rs)):
+            ref = F.apply_T(r) if tr else F.apply(r)
+            assert torch.equal(out[i], ref), (tr, i)
+    assert sp.apply_batched([], []) == []
+    with pytest.raises(ValueError):
+        sp.apply_batched([Fs[0]], [rs[1]])          # wrong length for the handle
+
+
+def test_factor_batched_empty_and_single():
+    assert sp.factor_batched([], eps=1e-2) == []
+    systems, cfgs, Ls, Fs = _batch("f32")
+    one = sp.factor_batched([systems[2]], eps=1e-2, nlevels=[Ls[2]], dtype="f32")
+    assert one[0].stats()["batch_systems"] == 1
+    r = torch.as_tensor(np.random.default_rng(2).standard_normal(cfgs[2].N), device="cuda")
+    assert torch.equal(one[0].apply(r), Fs[2].apply(r))
