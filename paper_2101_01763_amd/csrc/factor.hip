@@ -1231,16 +1231,26 @@ int Factor::eliminate_dense(int l, LevelState &S) {
     SP_TRY(launch_row_gather(ft, d_rg, int(rg.size()), mr, stream));
   }
   mark(PH_SCHUR);
-  // X_sm = A_ss^-1 A_sm
-  std::map<std::pair<int, int>, void *> X;
+  // X_sm = A_ss^-1 A_sm.  Per interior s, its neighbours' blocks and
+  // products are kept in the order of nb[s] (map nodes do not move when
+  // blocks are added later).
+  std::vector<std::vector<void *>> X(ncl);
+  std::vector<std::vector<const Blk *>> Bns(ncl), Bsn(ncl);   // A_ns, A_sn
   {
     std::vector<GemmDesc> gm;
-    for (int s : ints)
-      for (int m : nb[s]) {
+    for (int s : ints) {
+      const size_t nn = nb[s].size();
+      X[s].resize(nn);
+      Bns[s].resize(nn);
+      Bsn[s].resize(nn);
+      for (size_t i = 0; i < nn; ++i) {
+        const int m = nb[s][i];
         const Blk &B = S.blocks.at({s, m});
+        Bsn[s][i] = &B;
+        Bns[s][i] = &S.blocks.at({m, s});
         void *x;
         SP_TRY(dalloc(&x, size_t(B.rows) * B.cols * tsz, false));
-        X[{s, m}] = x;
+        X[s][i] = x;
         GemmDesc g{};
         g.A = Ainv[s];
         g.B = B.p;
@@ -1256,20 +1266,37 @@ int Factor::eliminate_dense(int l, LevelState &S) {
         gm.push_back(g);
         acct(csys(l, s), 0.0, 2.0 * double(B.rows) * B.rows * B.cols);
       }
+    }
     SP_TRY(gemm_batch(gm));
     trace("gemm", l);
   }
-  // fill blocks and deterministic rounds of A_nm -= A_ns X_sm
-  std::map<std::pair<int, int>, std::vector<int>> contrib;
+  // fill blocks and deterministic rounds of A_nm -= A_ns X_sm: the
+  // contributions to a target (n, m) come in ascending order of s (round r
+  // takes the r-th), targets in ascending (n, m)
+  struct Contrib {
+    int64_t key;          // n * ncl + m
+    int s, in, im;        // interior, positions of n and m in nb[s]
+  };
+  std::vector<Contrib> contrib;
   for (int s : ints)
-    for (int n : nb[s])
-      for (int m : nb[s]) contrib[{n, m}].push_back(s);
+    for (int in = 0; in < int(nb[s].size()); ++in)
+      for (int im = 0; im < int(nb[s].size()); ++im)
+        contrib.push_back({int64_t(nb[s][in]) * ncl + nb[s][im], s, in, im});
+  std::stable_sort(contrib.begin(), contrib.end(),
+                   [](const Contrib &x, const Contrib &y) { return x.key < y.key; });
+  std::vector<size_t> run;          // start of every target's contributions
+  for (size_t q = 0; q < contrib.size(); ++q)
+    if (q == 0 || contrib[q].key != contrib[q - 1].key) run.push_back(q);
+  run.push_back(contrib.size());
+  const size_t ntarget = run.size() - 1;
   {
     PlanArena pa;
     std::vector<std::pair<std::pair<int, int>, size_t>> offs;
-    for (auto &kv : contrib)
-      if (!S.blocks.count(kv.first))
-        offs.push_back({kv.first, pa.add(size_t(S.size[kv.first.first]) * S.size[kv.first.second] * tsz)});
+    for (size_t t = 0; t < ntarget; ++t) {
+      const int n = int(contrib[run[t]].key / ncl), m = int(contrib[run[t]].key % ncl);
+      if (!S.blocks.count({n, m}))
+        offs.push_back({{n, m}, pa.add(size_t(S.size[n]) * S.size[m] * tsz)});
+    }
     if (!offs.empty()) {
       void *base;
       SP_TRY(dalloc(&base, pa.total, false));
@@ -1278,19 +1305,23 @@ int Factor::eliminate_dense(int l, LevelState &S) {
         S.blocks[o.first] = Blk{(char *)base + o.second, S.size[o.first.first], S.size[o.first.second]};
     }
   }
+  std::vector<const Blk *> tblk(ntarget);
   size_t rounds = 0;
-  for (auto &kv : contrib) rounds = std::max(rounds, kv.second.size());
+  for (size_t t = 0; t < ntarget; ++t) {
+    const int n = int(contrib[run[t]].key / ncl), m = int(contrib[run[t]].key % ncl);
+    tblk[t] = &S.blocks.at({n, m});
+    rounds = std::max(rounds, run[t + 1] - run[t]);
+  }
   for (size_t r = 0; r < rounds; ++r) {
     std::vector<GemmDesc> gm;
-    for (auto &kv : contrib) {
-      if (kv.second.size() <= r) continue;
-      const int s = kv.second[r];
-      const int n = kv.first.first, m = kv.first.second;
-      const Blk &Ans = S.blocks.at({n, s});
-      const Blk &T = S.blocks.at(kv.first);
+    for (size_t t = 0; t < ntarget; ++t) {
+      if (run[t + 1] - run[t] <= r) continue;
+      const Contrib &c = contrib[run[t] + r];
+      const Blk &Ans = *Bns[c.s][c.in];
+      const Blk &T = *tblk[t];
       GemmDesc g{};
       g.A = Ans.p;
-      g.B = X.at({s, m});
+      g.B = X[c.s][c.im];
       g.C = T.p;
       g.M = T.rows;
       g.N = T.cols;
@@ -1301,7 +1332,7 @@ int Factor::eliminate_dense(int l, LevelState &S) {
       g.alpha = -1.0;
       g.beta = 1.0;
       gm.push_back(g);
-      acct(csys(l, s), 0.0, 2.0 * double(T.rows) * T.cols * Ans.cols);
+      acct(csys(l, c.s), 0.0, 2.0 * double(T.rows) * T.cols * Ans.cols);
     }
     SP_TRY(gemm_batch(gm));
     trace("gemm", l);
@@ -1328,15 +1359,16 @@ int Factor::eliminate_dense(int l, LevelState &S) {
     SP_TRY(AL.invT.set(*this, gv, os, 1));
     return member_gemv(l, &ApplyLevel::invT, gv, os, vs, 1);
   });
-  std::map<int, std::vector<PullItem>> fw, tfw;
+  std::vector<std::vector<PullItem>> fw(ncl), tfw(ncl);   // by neighbour n
   std::vector<PullGroup> G;
   std::vector<PullItem> I;
   std::vector<PullGroup> G2;
   std::vector<PullItem> I2;
   for (int s : ints)
-    for (int n : nb[s]) {
-      const Blk &Ans = S.blocks.at({n, s});   // |n| x |s|
-      const Blk &Asn = S.blocks.at({s, n});   // |s| x |n|
+    for (size_t i = 0; i < nb[s].size(); ++i) {
+      const int n = nb[s][i];
+      const Blk &Ans = *Bns[s][i];   // |n| x |s|
+      const Blk &Asn = *Bsn[s][i];   // |s| x |n|
       PullItem p{};
       p.B = Ans.p;
       p.islot = S.d_slots[s];
@@ -1360,15 +1392,16 @@ int Factor::eliminate_dense(int l, LevelState &S) {
       }
     }
   std::vector<int> gs, gs2;
-  for (auto &kv : fw) {
+  for (int n = 0; n < ncl; ++n) {
+    if (fw[n].empty()) continue;
     PullGroup g{};
-    g.oslot = S.d_slots[kv.first];
-    g.rows = S.size[kv.first];
+    g.oslot = S.d_slots[n];
+    g.rows = S.size[n];
     g.item_begin = int(I.size());
-    I.insert(I.end(), kv.second.begin(), kv.second.end());
+    I.insert(I.end(), fw[n].begin(), fw[n].end());
     g.item_end = int(I.size());
     G.push_back(g);
-    gs.push_back(csys(l, kv.first));
+    gs.push_back(csys(l, n));
   }
   defer([this, &AL, G, I, gs, l]() {
     SP_TRY(AL.fw.set(*this, G, I));
@@ -1377,15 +1410,16 @@ int Factor::eliminate_dense(int l, LevelState &S) {
   G.clear();
   I.clear();
   gs.clear();
-  for (auto &kv : tfw) {
+  for (int n = 0; n < ncl; ++n) {
+    if (tfw[n].empty()) continue;
     PullGroup g{};
-    g.oslot = S.d_slots[kv.first];
-    g.rows = S.size[kv.first];
+    g.oslot = S.d_slots[n];
+    g.rows = S.size[n];
     g.item_begin = int(I.size());
-    I.insert(I.end(), kv.second.begin(), kv.second.end());
+    I.insert(I.end(), tfw[n].begin(), tfw[n].end());
     g.item_end = int(I.size());
     G.push_back(g);
-    gs.push_back(csys(l, kv.first));
+    gs.push_back(csys(l, n));
   }
   defer([this, &AL, G, I, gs, l]() {
     SP_TRY(AL.tfw.set(*this, G, I));
@@ -1400,9 +1434,10 @@ int Factor::eliminate_dense(int l, LevelState &S) {
     g.rows = g2.rows = S.size[s];
     g.item_begin = int(I.size());
     g2.item_begin = int(I2.size());
-    for (int n : nb[s]) {
-      const Blk &Asn = S.blocks.at({s, n});
-      const Blk &Ans = S.blocks.at({n, s});
+    for (size_t i = 0; i < nb[s].size(); ++i) {
+      const int n = nb[s][i];
+      const Blk &Asn = *Bsn[s][i];
+      const Blk &Ans = *Bns[s][i];
       PullItem p{};
       p.B = Asn.p;
       p.islot = S.d_slots[n];
