@@ -2051,6 +2051,10 @@ int Factor::build(const spand_bsr_t &A, const spand_grid_t &g, const spand_opts_
   bs = A.bs;
   K = A.n_brows;
   N = int64_t(K) * bs;
+  if (N > INT_MAX) {     // the sweeps address unknowns with 32-bit slots
+    set_error("%lld unknowns exceed the 32-bit indices of the factorization", (long long)N);
+    return SPAND_EINVAL;
+  }
   ft = o.factor_dtype == SPAND_F32 ? FType::F32 : FType::F64;
   eps = o.eps;
   L = o.nlevels > 0 ? o.nlevels : default_levels(K);
@@ -2106,9 +2110,9 @@ int Factor::build_batch(const std::vector<BatchSystem> &sy, const spand_opts_t &
     no += sy[size_t(m)].A.nnzb;
     L = std::max(L, M.L);
   }
-  if (eo > INT_MAX / 2 || no > INT_MAX) {
-    set_error("batched factorization of %lld elements and %lld blocks exceeds the 32-bit indices",
-              (long long)eo, (long long)no);
+  if (eo * bs > INT_MAX || no > INT_MAX) {
+    set_error("batched factorization of %lld unknowns and %lld blocks exceeds the 32-bit indices",
+              (long long)(eo * bs), (long long)no);
     return SPAND_EINVAL;
   }
   K = int(eo);
