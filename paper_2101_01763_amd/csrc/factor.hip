@@ -462,8 +462,11 @@ int Factor::elim_batch(std::vector<ElimDesc> &items, int mode) {
   // the first block runs while the products of all blocks are planned
   SP_TRY(eliminate_block(0));
   // trailing products of every block: columns [k0 + ELIM_BLK, ncols), and for
-  // Gauss-Jordan also [0, k0)
+  // Gauss-Jordan also [0, k0).  In FP32 they run as strips of STRIP_TILES
+  // tiles along N (one block of A staged once per strip).
   const size_t tsz = fsize(ft);
+  constexpr int STRIP_TILES = 8;   // 256x256 p = 3 factorization: 2 tiles 395 ms, 4 386, 8 and 16 382
+  const bool strip = ft == FType::F32;
   std::vector<GemmDesc> gd;
   std::vector<int32_t> ts(1, 0);
   std::vector<size_t> bstart;
@@ -486,7 +489,8 @@ int Factor::elim_batch(std::vector<ElimDesc> &items, int mode) {
         g.alpha = 1.0;
         g.beta = 1.0;
         gd.push_back(g);
-        ts.push_back(ts.back() + int32_t(cdiv(g.M, 64) * cdiv(g.N, 64)));
+        const int64_t ntn = cdiv(g.N, 64);
+        ts.push_back(ts.back() + int32_t(cdiv(g.M, 64) * (strip ? cdiv(ntn, STRIP_TILES) : ntn)));
       };
       if (!lu) add(0, k0);
       add(k0 + ELIM_BLK, d.ncols - k0 - ELIM_BLK);
@@ -531,6 +535,10 @@ int Factor::elim_batch(std::vector<ElimDesc> &items, int mode) {
       double fl = 0.0, by = 0.0;
       gemm_work(gd.data() + g0, int(g1 - g0), fsize(ft), &fl, &by);
       SP_TRY(timed_launch(0, fl, by, [&]() {
+        if (strip)
+          return launch_gemm_strip(d_gd + g0, d_ts + g0, int(g1 - g0), ts[g1] - ts[g0], stream,
+                                   ts[g0], buni[b], buni[b] ? nullptr : d_coarse + boff[b],
+                                   STRIP_TILES);
         return launch_gemm(ft, d_gd + g0, d_ts + g0, int(g1 - g0), ts[g1] - ts[g0], stream, ts[g0],
                            0, buni[b], buni[b] ? nullptr : d_coarse + boff[b]);
       }));

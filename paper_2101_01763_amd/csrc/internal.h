@@ -227,6 +227,12 @@ constexpr int QRCP_MAXM = 1024;    // largest interface handled by the QRCP kern
 int launch_gemm(FType t, const GemmDesc *d_items, const int32_t *d_tile_start, int nitems,
                 int total_tiles, hipStream_t st, int tile_base, int tmode, int uniform = 0,
                 const int32_t *d_coarse = nullptr);
+// FP32 C += A B with K <= 64 (alpha = 1, no transposes): work units are
+// strips of up to `tps` 64x64 tiles along N (d_unit_start / total_units count
+// strips); the same results as launch_gemm, bit for bit
+int launch_gemm_strip(const GemmDesc *d_items, const int32_t *d_unit_start, int nitems,
+                      int total_units, hipStream_t st, int unit_base, int uniform,
+                      const int32_t *d_coarse, int tps);
 // host: the coarse index of items [a, b) of a tile_start array (ts[a..b])
 void gemm_coarse(const std::vector<int32_t> &ts, size_t a, size_t b, std::vector<int32_t> &out);
 // b x b blocks of BSR values (FP64) into factor-precision matrices

@@ -172,6 +172,100 @@ __global__ __launch_bounds__(256, 5) void k_gemm_f32_mfma(const GemmDesc *__rest
   }
 }
 
+// Accumulating products with a short K (the block updates of the blocked
+// eliminations, C += A B with K <= 64, FP32): one workgroup owns a strip of
+// up to `tps` 64x64 tiles of C along N that share one 64-row block of A.
+// A is staged in LDS once; per tile, the next tile's B and C are fetched into
+// registers while the current one is multiplied.  Every output takes the same
+// instructions in the same order as in k_gemm_f32_mfma (start from beta*C, K
+// in chunks of 32 with zero padding, v_mfma_f32_32x32x2f32 on pairs of k), so
+// the results are the same bit for bit.  Items: alpha = 1, no transposes.
+constexpr int SK = 64;   // largest K of a strip product
+__global__ __launch_bounds__(256, 4) void k_gemm_f32_strip(const GemmDesc *__restrict__ items,
+                                                         const int32_t *__restrict__ unit_start,
+                                                         const int32_t *__restrict__ coarse,
+                                                         int nitems, int unit_base, int uniform,
+                                                         int tps) {
+  const int unit = unit_base + xcd_tile(int(blockIdx.x), int(gridDim.x));
+  const int lo = uniform > 0 ? (unit - unit_base) / uniform
+                             : gemm_item(unit, unit_base, unit_start, coarse, nitems);
+  const GemmDesc d = items[lo];
+  const int u = unit - unit_start[lo];
+  const int ntn = (d.N + 63) >> 6;
+  const int nstrip = (ntn + tps - 1) / tps;
+  const int m0 = (u / nstrip) * 64, t0 = (u % nstrip) * tps;
+  const int t1 = min(ntn, t0 + tps);
+  const int kc = (d.K + GK - 1) / GK * GK;         // K padded to whole chunks (<= SK)
+  __shared__ float As[64 * (SK + 1)];   // As[m * (SK + 1) + k]
+  __shared__ float Bs[SK * 68];         // Bs[k * 68 + n]
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int wr = wid >> 1, wc = wid & 1;
+  const gfloat *A = (const gfloat *)d.A;
+  const gfloat *B = (const gfloat *)d.B;
+  gfloat *C = (gfloat *)d.C;
+  const float be = float(d.beta);
+  // A block: 64 x kc
+  for (int idx = tid; idx < 64 * kc; idx += 256) {
+    const int mm = idx / kc, kk = idx - mm * kc;
+    const int gm = m0 + mm;
+    As[mm * (SK + 1) + kk] = (gm < d.M && kk < d.K) ? A[gm * d.lda + kk] : 0.f;
+  }
+  // B tile (kc x 64) and C tile of column tile t into registers: each thread
+  // holds kc/4 B values (k = idx >> 6, n = idx & 63) and its 16 C values
+  float rb[SK / 4], rc[16];
+  const int gcol = wc * 32 + (lane & 31);
+  auto fetch = [&](int t) {
+    const int n0 = t * 64;
+#pragma unroll
+    for (int q = 0; q < SK / 4; ++q) {
+      const int idx = tid + q * 256;
+      const int kk = idx >> 6, nn = idx & 63;
+      const int gn = n0 + nn;
+      rb[q] = (kk < kc && kk < d.K && gn < d.N) ? B[kk * d.ldb + gn] : 0.f;
+    }
+    const int gn = n0 + gcol;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int gm = m0 + wr * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+      rc[r] = (gm < d.M && gn < d.N) ? C[gm * d.ldc + gn] : 0.f;
+    }
+  };
+  if (t0 < t1) fetch(t0);
+  const float *ap = As + (wr * 32 + (lane & 31)) * (SK + 1) + (lane >> 5);
+  const float *bp = Bs + (lane >> 5) * 68 + wc * 32 + (lane & 31);
+  for (int t = t0; t < t1; ++t) {
+    __syncthreads();       // the previous tile's products have read Bs
+#pragma unroll
+    for (int q = 0; q < SK / 4; ++q) {
+      const int idx = tid + q * 256;
+      if ((idx >> 6) < kc) Bs[(idx >> 6) * 68 + (idx & 63)] = rb[q];
+    }
+    f32x16 acc;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[r] = be * rc[r];
+    __syncthreads();
+    if (t + 1 < t1) fetch(t + 1);
+    for (int kk = 0; kk < kc; kk += 2)
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(ap[kk], bp[kk * 68], acc, 0, 0, 0);
+    const int gn = t * 64 + gcol;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int gm = m0 + wr * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+      if (gm < d.M && gn < d.N) C[gm * d.ldc + gn] = acc[r];
+    }
+  }
+}
+
+int launch_gemm_strip(const GemmDesc *d_items, const int32_t *d_unit_start, int nitems,
+                      int total_units, hipStream_t st, int unit_base, int uniform,
+                      const int32_t *d_coarse, int tps) {
+  if (nitems <= 0 || total_units <= 0) return SPAND_OK;
+  hipLaunchKernelGGL(k_gemm_f32_strip, dim3(total_units), dim3(256), 0, st, d_items, d_unit_start,
+                     d_coarse, nitems, unit_base, uniform, tps);
+  SP_HIP(hipGetLastError());
+  return SPAND_OK;
+}
+
 // FP64 version on the matrix cores: 64x64 tiles, each wave a 32x32 quarter
 // as 2x2 blocks of v_mfma_f64_16x16x4f64 (lane l holds A(l%16, k + l/16)
 // and B(k + l/16, l%16); result register r of lane l is row l/16 + 4r,
