@@ -116,6 +116,7 @@ struct Bump {
 
 struct Factor {
   hipStream_t stream = nullptr;
+  hipStream_t side = nullptr;      // second stream of the build (forked from and joined to stream)
   int device = 0;
   FType ft = FType::F64;
   int bs = 0, K = 0, L = 0;

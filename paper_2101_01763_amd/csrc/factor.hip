@@ -114,6 +114,7 @@ Factor::~Factor() {
   next_temp.release();
   retired.release();
   keep.release();
+  if (side) (void)hipStreamDestroy(side);
 }
 
 // ------------------------------------------------------------------ batch members
@@ -365,28 +366,55 @@ int Factor::elim_batch(std::vector<ElimDesc> &items, int mode) {
   std::sort(items.begin(), items.end(), [](const ElimDesc &a, const ElimDesc &b) {
     return a.n > b.n;
   });
-  // The eliminations are blocked: panels of 16 columns update only their
-  // block of ELIM_BLK columns; the rest of the matrix receives each block at
-  // once as one rank-ELIM_BLK product on the matrix cores.  In-place
-  // Gauss-Jordan (modes 0, 2) leaves the block's multipliers in the block
-  // columns themselves; LU (mode 1) accumulates them in PB.
-  // Matrices of up to elim_block_max_n rows take each block in one fused
-  // launch (one row per thread); larger ones go panel by panel.
+  // The eliminations are blocked: each block of bw columns is eliminated in
+  // its own columns (one fused launch, one row per thread, for matrices of
+  // up to elim_block_max_n rows; panels of 16 columns for larger ones); the
+  // rest of the matrix receives each block at once as one rank-bw product
+  // on the matrix cores.  In-place Gauss-Jordan (modes 0, 2) leaves the
+  // block's multipliers in the block columns themselves; LU (mode 1)
+  // accumulates them in PB.
   const bool lu = mode == 1;
-  // every item takes its own path: the matrices beyond the fused limit and
-  // the others go to separate calls
-  if (items[0].n > elim_block_max_n(ft) && items.back().n <= elim_block_max_n(ft)) {
+  // path of a matrix: 0 panels, else the fused block width
+  auto path = [&](int n) { return n > elim_block_max_n(ft) ? 0 : elim_block_width(ft, n); };
+  // every item takes its own path: matrices of different paths go to
+  // separate calls
+  if (path(items[0].n) != path(items.back().n)) {
+    const int p0 = path(items[0].n);
     const auto cut = std::find_if(items.begin(), items.end(), [&](const ElimDesc &d) {
-      return d.n <= elim_block_max_n(ft);
+      return path(d.n) != p0;
     });
     std::vector<ElimDesc> big(items.begin(), cut), small(cut, items.end());
-    SP_TRY(elim_batch(big, mode));
-    SP_TRY(elim_batch(small, mode));
+    if (p0 == 0) {
+      // the few matrices beyond the fused limit take a long chain of
+      // one-workgroup panel launches: it runs on the side stream, beside the
+      // fused launches of the others (independent matrices and scratch)
+      if (!side) SP_HIP(hipStreamCreateWithFlags(&side, hipStreamNonBlocking));
+      hipEvent_t fork, join;
+      SP_HIP(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
+      SP_HIP(hipEventCreateWithFlags(&join, hipEventDisableTiming));
+      SP_HIP(hipEventRecord(fork, stream));
+      SP_HIP(hipStreamWaitEvent(side, fork, 0));
+      std::swap(stream, side);
+      const int rb = elim_batch(big, mode);
+      std::swap(stream, side);
+      // joined even when the side call failed, so that nothing it queued
+      // outlives the build's scratch
+      SP_HIP(hipEventRecord(join, side));
+      const int rs = rb == SPAND_OK ? elim_batch(small, mode) : rb;
+      SP_HIP(hipStreamWaitEvent(stream, join, 0));
+      (void)hipEventDestroy(fork);
+      (void)hipEventDestroy(join);
+      SP_TRY(rs);
+    } else {
+      SP_TRY(elim_batch(big, mode));
+      SP_TRY(elim_batch(small, mode));
+    }
     std::copy(big.begin(), big.end(), items.begin());
     std::copy(small.begin(), small.end(), items.begin() + big.size());
     return SPAND_OK;
   }
-  const bool fused = items[0].n <= elim_block_max_n(ft);
+  const bool fused = path(items[0].n) != 0;
+  const int bw = fused ? path(items[0].n) : ELIM_BLK;
   if (mode == 3 && !fused) {
     set_error("shifted Gauss-Jordan: n = %d exceeds the fused limit %d", items[0].n, elim_block_max_n(ft));
     return SPAND_EINVAL;
@@ -398,8 +426,8 @@ int Factor::elim_batch(std::vector<ElimDesc> &items, int mode) {
       nT += size_t(ELIM_NB) * d.ld;
     }
     nI += size_t(d.n);
-    nB += size_t(ELIM_BLK) * d.ld;
-    if (lu) nPB += size_t(d.n) * ELIM_BLK;
+    nB += size_t(bw) * d.ld;
+    if (lu) nPB += size_t(d.n) * bw;
   }
   void *P = nullptr, *T = nullptr, *piv, *used, *TB = nullptr, *PB = nullptr;
   if (!fused) {
@@ -424,8 +452,8 @@ int Factor::elim_batch(std::vector<ElimDesc> &items, int mode) {
       oT += size_t(ELIM_NB) * d.ld;
     }
     oI += size_t(d.n);
-    oB += size_t(ELIM_BLK) * d.ld;
-    if (lu) oPB += size_t(d.n) * ELIM_BLK;
+    oB += size_t(bw) * d.ld;
+    if (lu) oPB += size_t(d.n) * bw;
   }
   ElimDesc *d_items;
   SP_TRY(upload(items, &d_items, false));
@@ -435,7 +463,7 @@ int Factor::elim_batch(std::vector<ElimDesc> &items, int mode) {
     while (na < int(items.size()) && items[na].n > k) ++na;
     return na;
   };
-  // elimination of block [k0, k0 + ELIM_BLK) in its own columns, then its
+  // elimination of block [k0, k0 + bw) in its own columns, then its
   // pivot rows of the other columns out to TB
   auto eliminate_block = [&](int k0) -> int {
     if (fused) {
@@ -445,7 +473,7 @@ int Factor::elim_batch(std::vector<ElimDesc> &items, int mode) {
       for (int a = 0; a < na;) {
         int b = a + 1;
         while (b < na && cdiv(items[b].n, 64) == cdiv(items[a].n, 64)) ++b;
-        SP_TRY(launch_elim_block(ft, d_items + a, b - a, k0, mode, items[a].n, d_flag, stream));
+        SP_TRY(launch_elim_block(ft, d_items + a, b - a, k0, mode, items[a].n, bw, d_flag, stream));
         a = b;
       }
     } else {
@@ -457,11 +485,11 @@ int Factor::elim_batch(std::vector<ElimDesc> &items, int mode) {
         if (lu) SP_TRY(launch_elim_pb(ft, d_items, nactive, k, k0, stream));
       }
     }
-    return launch_elim_extract(ft, d_items, nactive_at(k0), k0, lu ? 1 : 0, stream);
+    return launch_elim_extract(ft, d_items, nactive_at(k0), k0, bw, lu ? 1 : 0, stream);
   };
   // the first block runs while the products of all blocks are planned
   SP_TRY(eliminate_block(0));
-  // trailing products of every block: columns [k0 + ELIM_BLK, ncols), and for
+  // trailing products of every block: columns [k0 + bw, ncols), and for
   // Gauss-Jordan also [0, k0).  In FP32 they run as strips of STRIP_TILES
   // tiles along N (one block of A staged once per strip).
   const size_t tsz = fsize(ft);
@@ -470,16 +498,16 @@ int Factor::elim_batch(std::vector<ElimDesc> &items, int mode) {
   std::vector<GemmDesc> gd;
   std::vector<int32_t> ts(1, 0);
   std::vector<size_t> bstart;
-  for (int k0 = 0; k0 < nmax; k0 += ELIM_BLK) {
+  for (int k0 = 0; k0 < nmax; k0 += bw) {
     bstart.push_back(gd.size());
     for (auto &d : items) {
       if (d.n <= k0) break;
-      const int wb = std::min(ELIM_BLK, d.n - k0);
+      const int wb = std::min(bw, d.n - k0);
       auto add = [&](int c_off, int width) {
         if (width <= 0) return;
         GemmDesc g{};
         g.A = lu ? d.PB : (char *)d.A + size_t(k0) * tsz;
-        g.lda = lu ? ELIM_BLK : d.ld;
+        g.lda = lu ? bw : d.ld;
         g.B = (char *)d.TB + size_t(c_off) * tsz;
         g.C = (char *)d.A + size_t(c_off) * tsz;
         g.M = d.n;
@@ -493,7 +521,7 @@ int Factor::elim_batch(std::vector<ElimDesc> &items, int mode) {
         ts.push_back(ts.back() + int32_t(cdiv(g.M, 64) * (strip ? cdiv(ntn, STRIP_TILES) : ntn)));
       };
       if (!lu) add(0, k0);
-      add(k0 + ELIM_BLK, d.ncols - k0 - ELIM_BLK);
+      add(k0 + bw, d.ncols - k0 - bw);
     }
   }
   bstart.push_back(gd.size());
@@ -528,7 +556,7 @@ int Factor::elim_batch(std::vector<ElimDesc> &items, int mode) {
   }
   int32_t *d_coarse = nullptr;
   if (!coarse.empty()) SP_TRY(upload(coarse, &d_coarse, false));
-  for (int b = 0, k0 = 0; k0 < nmax; ++b, k0 += ELIM_BLK) {
+  for (int b = 0, k0 = 0; k0 < nmax; ++b, k0 += bw) {
     if (b > 0) SP_TRY(eliminate_block(k0));
     const size_t g0 = bstart[b], g1 = bstart[b + 1];
     if (g1 > g0) {   // this block's descriptors; their tile numbers start at ts[g0]
@@ -1777,23 +1805,34 @@ int Factor::sparsify(int l, const NDResult &nd, LevelState &S, LevelState &Nx) {
       (void)hipEventCreate(&qe1);
       (void)hipEventRecord(qe0, stream);
     }
-    // one launch per (block width, completion) class
+    // one launch per (block width, completion) class; the LDS of a launch is
+    // laid out for its largest m and its largest number of column groups,
+    // which may come from different interfaces, so a class is cut into
+    // several launches where the two together would not fit
     for (const int cq : {0, 1})
       for (const int bq : {8, 4, 2}) {
         std::vector<QrcpDesc> qc;
         int mq = 1, mg = 1;
+        auto flush = [&]() -> int {
+          if (qc.empty()) return SPAND_OK;
+          QrcpDesc *d_q;
+          SP_TRY(upload(qc, &d_q, false));
+          SP_TRY(launch_qrcp(ft, d_q, int(qc.size()), eps, eps == 0.0 ? 1 : 0, mq, mg, bq, cq,
+                             stream));
+          qc.clear();
+          mq = mg = 1;
+          return SPAND_OK;
+        };
         for (size_t q = 0; q < ifs.size(); ++q) {
           const int s = ifs[q];
           if (cq_in[s] != cq || bqs[s] != bq) continue;
+          if (qrcp_lds_bytes(std::max(mq, S.size[s]), std::max(mg, grp[s]), bq) > QRCP_MAX_LDS)
+            SP_TRY(flush());
           qc.push_back(qd[q]);
           mq = std::max(mq, S.size[s]);
           mg = std::max(mg, grp[s]);
         }
-        if (qc.empty()) continue;
-        QrcpDesc *d_q;
-        SP_TRY(upload(qc, &d_q, false));
-        SP_TRY(launch_qrcp(ft, d_q, int(qc.size()), eps, eps == 0.0 ? 1 : 0, mq, mg, bq, cq,
-                           stream));
+        SP_TRY(flush());
       }
     trace("qrcp plan+launch", l);
     if (timing) {

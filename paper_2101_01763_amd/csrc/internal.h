@@ -136,8 +136,8 @@ struct ElimDesc {
   int32_t ncols;    // total columns (n or 2n)
   int32_t ld;
   int32_t pad;
-  void *TB;         // workspace ELIM_BLK x ld (blocked elimination: pivot rows of a block)
-  void *PB;         // workspace n x ELIM_BLK (blocked LU: multipliers of a block)
+  void *TB;         // workspace bw x ld (blocked elimination: pivot rows of a block)
+  void *PB;         // workspace n x bw (blocked LU: multipliers of a block)
   void *sg;         // [n] factor precision: diagonal shifts of mode 3
 };
 
@@ -249,15 +249,20 @@ int launch_copy_t(FType t, int src_is_factor, const CopyDesc *d_items, int n, in
 // the first nactive have n > k.
 int launch_elim_step(FType t, const ElimDesc *d_items, int nactive, int k, int mode,
                      int max_tiles, int *d_flag, int cw0, int cw1, hipStream_t st);
-int launch_elim_extract(FType t, const ElimDesc *d_items, int nactive, int k0, int lu, hipStream_t st);
+// block [k0, k0 + bw) (bw = ELIM_BLK on the panel path)
+int launch_elim_extract(FType t, const ElimDesc *d_items, int nactive, int k0, int bw, int lu,
+                        hipStream_t st);
 int launch_elim_pb(FType t, const ElimDesc *d_items, int nactive, int k, int k0, hipStream_t st);
-// Whole block [k0, k0 + ELIM_BLK) in one launch, one row per thread: needs
-// nmax <= elim_block_max_n(t).  Writes the block columns, piv, used, and for
-// LU (mode 1) the multipliers PB; the pivot rows' other columns are moved by
-// launch_elim_extract as for the panel path.
+// Whole block [k0, k0 + bw) in one launch, one row per thread: needs
+// nmax <= elim_block_max_n(t) and bw = elim_block_width(t, nmax) (32 for
+// FP64 matrices of more than 512 rows, else ELIM_BLK).  Writes the block
+// columns, piv, used, and for LU (mode 1) the multipliers PB (n x bw); the
+// pivot rows' other columns are moved by launch_elim_extract as for the
+// panel path.
 int elim_block_max_n(FType t);
+int elim_block_width(FType t, int n);
 int launch_elim_block(FType t, const ElimDesc *d_items, int nactive, int k0, int mode, int nmax,
-                      int *d_flag, hipStream_t st);
+                      int bw, int *d_flag, hipStream_t st);
 // out[j, c] = src[piv[j], colperm ? pinv[c] : c + col_off]
 struct RowGatherDesc {
   const void *src;

@@ -886,10 +886,13 @@ __device__ inline int wave_argmax_key(uint64_t key, bool can, uint64_t *kmax) {
 }
 
 // ------------------------------------------------------------------ fused block elimination
-// One workgroup eliminates the block columns [k0, k0 + wb), wb <= ELIM_BLK,
-// of one matrix and applies them to the whole column window
-// [k0, k0 + ELIM_BLK) (columns past n exist for LU on [A | I]); one row per
-// thread (blockDim.x >= n), the window part of the row in registers.  The
+// One workgroup eliminates the block columns [k0, k0 + wb), wb <= BW, of
+// one matrix and applies them to the whole column window [k0, k0 + BW)
+// (columns past n exist for LU on [A | I]); one row per thread
+// (blockDim.x >= n), the window part of the row in registers.  BW = 64
+// (ELIM_BLK), except for FP64 matrices of more than 512 rows: 1024 rows of
+// 64 doubles would take the whole register file of a CU, so they take
+// blocks of 32 columns.  The
 // steps run in groups of 4 columns with the slots fixed inside a group, so
 // every register index is a compile-time constant while the group loop
 // stays rolled (see the step below).
@@ -906,15 +909,15 @@ __device__ inline int wave_argmax_key(uint64_t key, bool can, uint64_t *kmax) {
 //   MODE 1:   LU; only rows not yet used as pivots change.  A changed row
 //             keeps its multipliers (the block's elimination matrix taken at
 //             the pivot rows) in the slots of the columns already
-//             eliminated, so PB (n x ELIM_BLK) is written out on exit with
+//             eliminated, so PB (n x BW) is written out on exit with
 //             no second array: row r of PB is those slots, then 1 at the
 //             row's own pivot column for rows pivoted in this block.
-template <typename T, int MODE, int MAXT>
+template <typename T, int MODE, int MAXT, int BW>
 __global__ __launch_bounds__(MAXT) void k_elim_block(const ElimDesc *__restrict__ items, int k0,
                                                      int *__restrict__ flag) {
-  constexpr int BW = ELIM_BLK, NWMAX = MAXT / 64, V = 16 / sizeof(T);
+  constexpr int NWMAX = MAXT / 64, V = 16 / sizeof(T);
   constexpr bool NOPIV = MODE >= 2;        // pivot of block column c is row k0 + c
-  static_assert(BW == 64, "slot rotation assumes 64 block columns");
+  static_assert(BW >= 8 && (BW & (BW - 1)) == 0, "slot rotation needs a power-of-two block");
   const ElimDesc d = items[blockIdx.x];
   const int n = d.n;
   if (k0 >= n) return;
@@ -1133,34 +1136,39 @@ __global__ __launch_bounds__(MAXT) void k_elim_block(const ElimDesc *__restrict_
   if (tid < wb) d.piv[k0 + tid] = s_piv[tid];
 }
 
-int elim_block_max_n(FType t) { return t == FType::F64 ? 512 : 1024; }
+int elim_block_max_n(FType) { return 1024; }
+
+int elim_block_width(FType t, int n) { return t == FType::F64 && n > 512 ? 32 : ELIM_BLK; }
+
+template <typename T, int MAXT, int BW>
+static void elim_block_modes(int mode, dim3 grid, dim3 block, hipStream_t st,
+                             const ElimDesc *d_items, int k0, int *d_flag) {
+  if (mode == 0)
+    hipLaunchKernelGGL((k_elim_block<T, 0, MAXT, BW>), grid, block, 0, st, d_items, k0, d_flag);
+  else if (mode == 1)
+    hipLaunchKernelGGL((k_elim_block<T, 1, MAXT, BW>), grid, block, 0, st, d_items, k0, d_flag);
+  else if (mode == 2)
+    hipLaunchKernelGGL((k_elim_block<T, 2, MAXT, BW>), grid, block, 0, st, d_items, k0, d_flag);
+  else
+    hipLaunchKernelGGL((k_elim_block<T, 3, MAXT, BW>), grid, block, 0, st, d_items, k0, d_flag);
+}
 
 int launch_elim_block(FType t, const ElimDesc *d_items, int nactive, int k0, int mode, int nmax,
-                      int *d_flag, hipStream_t st) {
+                      int bw, int *d_flag, hipStream_t st) {
   if (nactive <= 0) return SPAND_OK;
-  if (nmax > elim_block_max_n(t)) {
-    set_error("fused block elimination: n = %d exceeds %d", nmax, elim_block_max_n(t));
+  if (nmax > elim_block_max_n(t) || bw != elim_block_width(t, nmax)) {
+    set_error("fused block elimination: n = %d, block width %d (limit %d rows, width %d)", nmax,
+              bw, elim_block_max_n(t), elim_block_width(t, nmax));
     return SPAND_EINVAL;
   }
-  const dim3 block(unsigned(cdiv(nmax, 64) * 64));
+  const dim3 grid(nactive), block(unsigned(cdiv(nmax, 64) * 64));
   if (t == FType::F64) {
-    if (mode == 0)
-      hipLaunchKernelGGL((k_elim_block<double, 0, 512>), dim3(nactive), block, 0, st, d_items, k0, d_flag);
-    else if (mode == 1)
-      hipLaunchKernelGGL((k_elim_block<double, 1, 512>), dim3(nactive), block, 0, st, d_items, k0, d_flag);
-    else if (mode == 2)
-      hipLaunchKernelGGL((k_elim_block<double, 2, 512>), dim3(nactive), block, 0, st, d_items, k0, d_flag);
+    if (bw == 32)
+      elim_block_modes<double, 1024, 32>(mode, grid, block, st, d_items, k0, d_flag);
     else
-      hipLaunchKernelGGL((k_elim_block<double, 3, 512>), dim3(nactive), block, 0, st, d_items, k0, d_flag);
+      elim_block_modes<double, 512, ELIM_BLK>(mode, grid, block, st, d_items, k0, d_flag);
   } else {
-    if (mode == 0)
-      hipLaunchKernelGGL((k_elim_block<float, 0, 1024>), dim3(nactive), block, 0, st, d_items, k0, d_flag);
-    else if (mode == 1)
-      hipLaunchKernelGGL((k_elim_block<float, 1, 1024>), dim3(nactive), block, 0, st, d_items, k0, d_flag);
-    else if (mode == 2)
-      hipLaunchKernelGGL((k_elim_block<float, 2, 1024>), dim3(nactive), block, 0, st, d_items, k0, d_flag);
-    else
-      hipLaunchKernelGGL((k_elim_block<float, 3, 1024>), dim3(nactive), block, 0, st, d_items, k0, d_flag);
+    elim_block_modes<float, 1024, ELIM_BLK>(mode, grid, block, st, d_items, k0, d_flag);
   }
   SP_HIP(hipGetLastError());
   return SPAND_OK;
@@ -1174,11 +1182,11 @@ int launch_elim_block(FType t, const ElimDesc *d_items, int nactive, int k0, int
 // updates every column outside the block; LU only the columns after it.
 template <typename T>
 __global__ __launch_bounds__(256) void k_elim_extract(const ElimDesc *__restrict__ items, int k0,
-                                                      int lu) {
+                                                      int bw, int lu) {
   const ElimDesc d = items[blockIdx.x];
   if (k0 >= d.n) return;
-  const int wb = min(ELIM_BLK, d.n - k0);
-  const int cw1 = k0 + ELIM_BLK;
+  const int wb = min(bw, d.n - k0);
+  const int cw1 = k0 + bw;
   T *A = (T *)d.A;
   T *TB = (T *)d.TB;
   const int64_t ld = d.ld;
@@ -1195,14 +1203,14 @@ __global__ __launch_bounds__(256) void k_elim_extract(const ElimDesc *__restrict
   }
 }
 
-int launch_elim_extract(FType t, const ElimDesc *d_items, int nactive, int k0, int lu,
+int launch_elim_extract(FType t, const ElimDesc *d_items, int nactive, int k0, int bw, int lu,
                         hipStream_t st) {
   if (nactive <= 0) return SPAND_OK;
   const dim3 grid(nactive, 16);
   if (t == FType::F64)
-    hipLaunchKernelGGL(k_elim_extract<double>, grid, dim3(256), 0, st, d_items, k0, lu);
+    hipLaunchKernelGGL(k_elim_extract<double>, grid, dim3(256), 0, st, d_items, k0, bw, lu);
   else
-    hipLaunchKernelGGL(k_elim_extract<float>, grid, dim3(256), 0, st, d_items, k0, lu);
+    hipLaunchKernelGGL(k_elim_extract<float>, grid, dim3(256), 0, st, d_items, k0, bw, lu);
   SP_HIP(hipGetLastError());
   return SPAND_OK;
 }

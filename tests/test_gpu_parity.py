@@ -59,7 +59,14 @@ def test_pattern_outer():
             np.testing.assert_array_equal(got[t], -np.outer(u[I * bs:(I + 1) * bs], v[J * bs:(J + 1) * bs]))
 
 
-@pytest.mark.parametrize("n,p,L", [(16, 1, 4), (8, 2, 3), (12, 1, 5), (6, 3, 2), (8, 1, 1)])
+# FP64 matrices of 513-1024 rows take fused blocks of 32 columns: 8x8 p = 3
+# with 3 levels (leaves and the last interface of up to 1024 unknowns: the
+# Gauss-Jordan inverses and the LU scaling), 14x14 p = 2 with 4 levels
+# (leaves up to 756, interfaces up to 1008); with 3 levels its leaves span
+# 180-1764 unknowns, so one elimination splits into the 64- and 32-column
+# fused paths and the panel path (on the side stream)
+@pytest.mark.parametrize("n,p,L", [(16, 1, 4), (8, 2, 3), (12, 1, 5), (6, 3, 2), (8, 1, 1),
+                                   (8, 3, 3), (14, 2, 4), (14, 2, 3)])
 def test_eps0_direct(n, p, L):
     cfg, A, As, xs, b, dA = _problem(n, p)
     F = sp.factor(dA, n, n, True, False, eps=0.0, nlevels=L, dtype="f64")
@@ -72,7 +79,7 @@ def test_eps0_direct(n, p, L):
 
 
 @pytest.mark.parametrize("n,p,L,eps", [(16, 1, 4, 1e-2), (16, 1, 4, 1e-1), (10, 2, 3, 1e-2),
-                                       (13, 1, 4, 1e-3)])
+                                       (13, 1, 4, 1e-3), (16, 3, 5, 1e-2)])
 def test_apply_parity_fp64(n, p, L, eps):
     cfg, A, As, xs, b, dA = _problem(n, p)
     F = sp.factor(dA, n, n, True, False, eps=eps, nlevels=L, dtype="f64")
