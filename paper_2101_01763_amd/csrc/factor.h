@@ -117,6 +117,8 @@ struct Bump {
 struct Factor {
   hipStream_t stream = nullptr;
   hipStream_t side = nullptr;      // second stream of the build (forked from and joined to stream)
+  hipStream_t side2 = nullptr;     // third one (size classes of a fused elimination block)
+  hipEvent_t cls_fork = nullptr, cls_join = nullptr;
   int device = 0;
   FType ft = FType::F64;
   int bs = 0, K = 0, L = 0;

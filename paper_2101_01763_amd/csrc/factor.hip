@@ -115,6 +115,9 @@ Factor::~Factor() {
   retired.release();
   keep.release();
   if (side) (void)hipStreamDestroy(side);
+  if (side2) (void)hipStreamDestroy(side2);
+  if (cls_fork) (void)hipEventDestroy(cls_fork);
+  if (cls_join) (void)hipEventDestroy(cls_join);
 }
 
 // ------------------------------------------------------------------ batch members
@@ -468,14 +471,45 @@ int Factor::elim_batch(std::vector<ElimDesc> &items, int mode) {
   auto eliminate_block = [&](int k0) -> int {
     if (fused) {
       // one launch per 64-row size class (items are sorted by n, descending),
-      // so that no workgroup carries waves without rows
+      // so that no workgroup carries waves without rows.  The class with
+      // the most rows runs on the build stream, the others at the same time
+      // on a second one (independent matrices): a class of a few large
+      // matrices would otherwise hold the whole device for its long chain
+      // of dependent steps.
       const int na = nactive_at(k0);
+      std::vector<std::pair<int, int>> cls;
       for (int a = 0; a < na;) {
         int b = a + 1;
         while (b < na && cdiv(items[b].n, 64) == cdiv(items[a].n, 64)) ++b;
-        SP_TRY(launch_elim_block(ft, d_items + a, b - a, k0, mode, items[a].n, bw, d_flag, stream));
+        cls.push_back({a, b});
         a = b;
       }
+      if (cls.size() == 1) {
+        SP_TRY(launch_elim_block(ft, d_items, na, k0, mode, items[0].n, bw, d_flag, stream));
+        return launch_elim_extract(ft, d_items, na, k0, bw, lu ? 1 : 0, stream);
+      }
+      size_t big = 0;
+      for (size_t c = 1; c < cls.size(); ++c)
+        if (int64_t(cls[c].second - cls[c].first) * items[cls[c].first].n >
+            int64_t(cls[big].second - cls[big].first) * items[cls[big].first].n)
+          big = c;
+      if (!side2) SP_HIP(hipStreamCreateWithFlags(&side2, hipStreamNonBlocking));
+      if (!cls_fork) SP_HIP(hipEventCreateWithFlags(&cls_fork, hipEventDisableTiming));
+      if (!cls_join) SP_HIP(hipEventCreateWithFlags(&cls_join, hipEventDisableTiming));
+      SP_HIP(hipEventRecord(cls_fork, stream));
+      SP_HIP(hipStreamWaitEvent(side2, cls_fork, 0));
+      int r = SPAND_OK;
+      for (size_t c = 0; c < cls.size() && r == SPAND_OK; ++c)
+        if (c != big)
+          r = launch_elim_block(ft, d_items + cls[c].first, cls[c].second - cls[c].first, k0, mode,
+                                items[cls[c].first].n, bw, d_flag, side2);
+      if (r == SPAND_OK)
+        r = launch_elim_block(ft, d_items + cls[big].first, cls[big].second - cls[big].first, k0,
+                              mode, items[cls[big].first].n, bw, d_flag, stream);
+      // joined even after a failed launch
+      SP_HIP(hipEventRecord(cls_join, side2));
+      SP_HIP(hipStreamWaitEvent(stream, cls_join, 0));
+      SP_TRY(r);
     } else {
       for (int k = k0; k < std::min(nmax, k0 + ELIM_BLK); k += ELIM_NB) {
         const int nactive = nactive_at(k);
