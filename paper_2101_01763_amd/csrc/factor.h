@@ -5,6 +5,7 @@
 #include <functional>
 #include <map>
 #include <memory>
+#include <initializer_list>
 #include <vector>
 
 #include "internal.h"
@@ -196,6 +197,18 @@ struct Factor {
   void release_retired();
   template <typename D>
   int upload(const std::vector<D> &v, D **out, bool keep);
+  // several host arrays in one device allocation and one copy (each part
+  // 256-byte aligned; an empty part gets nullptr)
+  struct UpPart {
+    const void *src;
+    size_t bytes;
+    void **dst;
+  };
+  template <typename D>
+  static UpPart part(const std::vector<D> &v, D **out) {
+    return UpPart{v.data(), v.size() * sizeof(D), (void **)out};
+  }
+  int upload_parts(std::initializer_list<UpPart> parts, bool keep);
   int upload_slots(const std::vector<int32_t> &v, int32_t **out);
   int upload_level_slots(LevelState &S);
   // Host work that only the apply needs (sweep descriptor sets): queued

@@ -186,6 +186,26 @@ int Factor::upload(const std::vector<D> &v, D **out, bool keep) {
   return SPAND_OK;
 }
 
+int Factor::upload_parts(std::initializer_list<UpPart> parts, bool keep) {
+  size_t tot = 0;
+  for (const auto &q : parts) tot += (q.bytes + 255) & ~size_t(255);
+  for (const auto &q : parts) *q.dst = nullptr;
+  if (tot == 0) return SPAND_OK;
+  void *p;
+  SP_TRY(dalloc(&p, tot, keep));
+  std::vector<char> h(tot);
+  size_t off = 0;
+  for (const auto &q : parts) {
+    if (q.bytes) {
+      std::memcpy(h.data() + off, q.src, q.bytes);
+      *q.dst = (char *)p + off;
+    }
+    off += (q.bytes + 255) & ~size_t(255);
+  }
+  SP_HIP(hipMemcpy(p, h.data(), tot, hipMemcpyHostToDevice));
+  return SPAND_OK;
+}
+
 int Factor::upload_slots(const std::vector<int32_t> &v, int32_t **out) {
   return upload(v, out, true);
 }
@@ -250,9 +270,9 @@ static void gemm_work(const GemmDesc *d, int n, size_t esz, double *fl, double *
 
 int Factor::timed_launch(int kind, double flops, double bytes, const std::function<int()> &launch) {
   hipEvent_t a = nullptr, b = nullptr;
-  if (timing && hipEventCreate(&a) == hipSuccess) {
-    if (hipEventCreate(&b) != hipSuccess) {
-      (void)hipEventDestroy(a);
+  if (timing && event_get(&a) == SPAND_OK) {
+    if (event_get(&b) != SPAND_OK) {
+      event_put(a);
       a = nullptr;
     } else {
       (void)hipEventRecord(a, stream);
@@ -299,11 +319,6 @@ int Factor::gemm_batch(const std::vector<GemmDesc> &items) {
   }
   start[4] = int(ord.size());
   trace("  gemm plan", -2);
-  GemmDesc *d_items;
-  int32_t *d_ts;
-  SP_TRY(upload(ord, &d_items, false));
-  SP_TRY(upload(ts, &d_ts, false));
-  trace("  gemm upload", -2);
   int uni[4] = {0, 0, 0, 0};
   size_t coff[5] = {0, 0, 0, 0, 0};
   std::vector<int32_t> coarse;
@@ -318,8 +333,10 @@ int Factor::gemm_batch(const std::vector<GemmDesc> &items) {
       if (!uniform) gemm_coarse(ts, size_t(a), size_t(b), coarse);
     }
   }
-  int32_t *d_coarse = nullptr;
-  if (!coarse.empty()) SP_TRY(upload(coarse, &d_coarse, false));
+  GemmDesc *d_items;
+  int32_t *d_ts, *d_coarse;
+  SP_TRY(upload_parts({part(ord, &d_items), part(ts, &d_ts), part(coarse, &d_coarse)}, false));
+  trace("  gemm upload", -2);
   for (int tm = 0; tm < 4; ++tm) {
     const int a = start[tm], b = start[tm + 1];
     if (b > a) {
@@ -350,16 +367,11 @@ int Factor::copy_batch(const std::vector<CopyDesc> &items, int src_is_factor) {
       mx = std::max<int64_t>(mx, int64_t(d.rows) * d.cols);
     }
   }
-  if (!st.empty()) {
-    CopyDesc *d_items;
-    SP_TRY(upload(st, &d_items, false));
-    SP_TRY(launch_copy(ft, src_is_factor, d_items, int(st.size()), mx, stream));
-  }
-  if (!tr.empty()) {
-    CopyDesc *d_items;
-    SP_TRY(upload(tr, &d_items, false));
-    SP_TRY(launch_copy_t(ft, src_is_factor, d_items, int(tr.size()), mr, mc, stream));
-  }
+  CopyDesc *d_st, *d_tr;
+  SP_TRY(upload_parts({part(st, &d_st), part(tr, &d_tr)}, false));
+  if (!st.empty()) SP_TRY(launch_copy(ft, src_is_factor, d_st, int(st.size()), mx, stream));
+  if (!tr.empty())
+    SP_TRY(launch_copy_t(ft, src_is_factor, d_tr, int(tr.size()), mr, mc, stream));
   return SPAND_OK;
 }
 
@@ -570,10 +582,6 @@ int Factor::elim_batch(std::vector<ElimDesc> &items, int mode) {
     std::fprintf(stderr, "[spand host] elim batch mode %d: %zu items nmax %d, %zu block products %.3f TFLOP %.3f GB, %d launches\n",
                  mode, items.size(), nmax, gd.size(), fl * 1e-12, by * 1e-9, nl);
   }
-  GemmDesc *d_gd = nullptr;
-  int32_t *d_ts = nullptr;
-  SP_TRY(upload(gd, &d_gd, false));
-  SP_TRY(upload(ts, &d_ts, false));
   // per block: uniform tile count, or the offset of its coarse index
   std::vector<int> buni(bstart.size(), 0);
   std::vector<size_t> boff(bstart.size(), 0);
@@ -588,8 +596,9 @@ int Factor::elim_batch(std::vector<ElimDesc> &items, int mode) {
     boff[b] = coarse.size();
     if (!uniform) gemm_coarse(ts, g0, g1, coarse);
   }
-  int32_t *d_coarse = nullptr;
-  if (!coarse.empty()) SP_TRY(upload(coarse, &d_coarse, false));
+  GemmDesc *d_gd;
+  int32_t *d_ts, *d_coarse;
+  SP_TRY(upload_parts({part(gd, &d_gd), part(ts, &d_ts), part(coarse, &d_coarse)}, false));
   for (int b = 0, k0 = 0; k0 < nmax; ++b, k0 += bw) {
     if (b > 0) SP_TRY(eliminate_block(k0));
     const size_t g0 = bstart[b], g1 = bstart[b + 1];
@@ -738,7 +747,7 @@ void Factor::mark(int phase) {
   host_t = now;
   if (!timing) return;
   hipEvent_t e;
-  if (hipEventCreate(&e) != hipSuccess) return;
+  if (event_get(&e) != SPAND_OK) return;
   (void)hipEventRecord(e, stream);
   events.push_back({phase, e});
 }
@@ -1057,8 +1066,7 @@ int Factor::level0(const NDResult &nd, LevelState &S) {
     trace("schur items", 0);
     SchurGroup *d_g;
     SchurItem *d_i;
-    SP_TRY(upload(groups, &d_g, false));
-    SP_TRY(upload(items, &d_i, false));
+    SP_TRY(upload_parts({part(groups, &d_g), part(items, &d_i)}, false));
     {
       // per coupling pair: two b x b products; A1, Y, A2 read, plus every
       // target block read and written once
@@ -1217,9 +1225,9 @@ int PullSet::set(Factor &F, std::vector<PullGroup> G, const std::vector<PullItem
     std::fprintf(stderr, "[spand host] pull set: %zu groups %d chunks %zu items %.3f GB, max cols %d, trans %d\n",
                  G.size(), nchunks, I.size(), bytes * 1e-9, maxc, trans);
   }
-  SP_TRY(F.upload(G, &d_groups, true));
-  SP_TRY(F.upload(I, &d_items, true));
-  SP_TRY(F.upload(ch, &d_chunks, true));
+  SP_TRY(F.upload_parts({Factor::part(G, &d_groups), Factor::part(I, &d_items),
+                         Factor::part(ch, &d_chunks)},
+                        true));
   return SPAND_OK;
 }
 
@@ -1238,9 +1246,9 @@ int GemvSet::set(Factor &F, std::vector<GemvDesc> items,
   }
   nchunks = int(ch.size());
   nslots = int64_t(sl.size());
-  SP_TRY(F.upload(items, &d_items, true));
-  SP_TRY(F.upload(ch, &d_chunks, true));
-  SP_TRY(F.upload(sl, &d_slots, true));
+  SP_TRY(F.upload_parts({Factor::part(items, &d_items), Factor::part(ch, &d_chunks),
+                         Factor::part(sl, &d_slots)},
+                        true));
   return SPAND_OK;
 }
 
@@ -1835,9 +1843,9 @@ int Factor::sparsify(int l, const NDResult &nd, LevelState &S, LevelState &Nx) {
     SP_TRY(copy_batch(wc, 1));
     hipEvent_t qe0 = nullptr, qe1 = nullptr;
     if (timing) {
-      (void)hipEventCreate(&qe0);
-      (void)hipEventCreate(&qe1);
-      (void)hipEventRecord(qe0, stream);
+      if (event_get(&qe0) != SPAND_OK) qe0 = nullptr;
+      if (event_get(&qe1) != SPAND_OK) qe1 = nullptr;
+      if (qe0) (void)hipEventRecord(qe0, stream);
     }
     // one launch per (block width, completion) class; the LDS of a launch is
     // laid out for its largest m and its largest number of column groups,
@@ -1870,7 +1878,7 @@ int Factor::sparsify(int l, const NDResult &nd, LevelState &S, LevelState &Nx) {
       }
     trace("qrcp plan+launch", l);
     if (timing) {
-      (void)hipEventRecord(qe1, stream);
+      if (qe1) (void)hipEventRecord(qe1, stream);
       qrcp_events.push_back({qe0, qe1});
     }
   }
@@ -2483,13 +2491,14 @@ void Factor::collect_events() {
     if (hipEventElapsedTime(&ms, events[i].second, events[i + 1].second) == hipSuccess)
       ph_ms[events[i].first] += ms;
   }
-  for (auto &e : events) (void)hipEventDestroy(e.second);
+  for (auto &e : events) event_put(e.second);
   events.clear();
   for (auto &e : qrcp_events) {
     float ms = 0.f;
-    if (hipEventElapsedTime(&ms, e.first, e.second) == hipSuccess) qrcp_ms += ms;
-    (void)hipEventDestroy(e.first);
-    (void)hipEventDestroy(e.second);
+    if (e.first && e.second && hipEventElapsedTime(&ms, e.first, e.second) == hipSuccess)
+      qrcp_ms += ms;
+    event_put(e.first);
+    event_put(e.second);
   }
   n_qrcp += int(qrcp_events.size());
   qrcp_events.clear();
@@ -2499,8 +2508,8 @@ void Factor::collect_events() {
     kt_flops[e.kind] += e.flops;
     kt_bytes[e.kind] += e.bytes;
     ++kt_n[e.kind];
-    (void)hipEventDestroy(e.a);
-    (void)hipEventDestroy(e.b);
+    event_put(e.a);
+    event_put(e.b);
   }
   kevents.clear();
 }

@@ -51,6 +51,10 @@ void pool_release(void *p, size_t bytes);
 void pool_trim();
 size_t pool_cached_bytes();
 double pool_driver_ms();   // calling thread's cumulative hipMalloc/hipFree time
+// Timing events of the current device, cached (pool.hip); put an event back
+// only after its last record has completed and been read.
+int event_get(hipEvent_t *e);
+void event_put(hipEvent_t e);
 
 // ----------------------------------------------------------------- ND
 struct NDCluster {

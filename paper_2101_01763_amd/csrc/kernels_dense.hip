@@ -397,6 +397,11 @@ int launch_gemm(FType t, const GemmDesc *d_items, const int32_t *d_tile_start, i
 }
 
 // ------------------------------------------------------------------ copies
+// Each thread moves COPY_ILP elements per round, all loads issued before the
+// stores: with a few elements per thread the waves would hold too few bytes
+// in flight to cover the memory latency (3.3 TB/s measured on the W copies
+// with one element per load round).
+constexpr int COPY_ILP = 8;
 template <typename Ts, typename Td>
 __global__ __launch_bounds__(256) void k_copy(const CopyDesc *__restrict__ items) {
   const CopyDesc d = items[blockIdx.x];
@@ -404,16 +409,30 @@ __global__ __launch_bounds__(256) void k_copy(const CopyDesc *__restrict__ items
   Td *dst = (Td *)d.dst;
   const int64_t total = (int64_t)d.rows * d.cols;
   const Ts sc = Ts(d.scale);
-  if (total + int64_t(gridDim.y) * blockDim.x <= INT_MAX) {
+  constexpr int PER = 256 * COPY_ILP;
+  if (total + int64_t(gridDim.y) * PER <= INT_MAX) {
     // 32-bit index arithmetic (a 64-bit division per element costs more
     // than the element's memory traffic); the bound keeps the last
-    // idx + stride within int
+    // index of a round within int
     const int tot = int(total), cols = d.cols;
-    for (int idx = blockIdx.y * blockDim.x + threadIdx.x; idx < tot;
-         idx += gridDim.y * blockDim.x) {
-      const int r = idx / cols, c = idx - r * cols;
-      const Ts v = d.trans ? src[(int64_t)c * d.lds + r] : src[(int64_t)r * d.lds + c];
-      dst[(int64_t)r * d.ldd + c] = Td(v * sc);
+    for (int base = blockIdx.y * PER + threadIdx.x; base < tot; base += gridDim.y * PER) {
+      Ts v[COPY_ILP];
+#pragma unroll
+      for (int j = 0; j < COPY_ILP; ++j) {
+        const int idx = base + j * 256;
+        if (idx < tot) {
+          const int r = idx / cols, c = idx - r * cols;
+          v[j] = d.trans ? src[(int64_t)c * d.lds + r] : src[(int64_t)r * d.lds + c];
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < COPY_ILP; ++j) {
+        const int idx = base + j * 256;
+        if (idx < tot) {
+          const int r = idx / cols, c = idx - r * cols;
+          dst[(int64_t)r * d.ldd + c] = Td(v[j] * sc);
+        }
+      }
     }
     return;
   }
@@ -428,7 +447,7 @@ __global__ __launch_bounds__(256) void k_copy(const CopyDesc *__restrict__ items
 int launch_copy(FType t, int src_is_factor, const CopyDesc *d_items, int n, int64_t max_elems,
                 hipStream_t st) {
   if (n <= 0) return SPAND_OK;
-  int gy = int(std::min<int64_t>(64, std::max<int64_t>(1, cdiv(max_elems, 256))));
+  int gy = int(std::min<int64_t>(64, std::max<int64_t>(1, cdiv(max_elems, 256 * COPY_ILP))));
   dim3 grid(n, gy);
   if (t == FType::F64) {
     hipLaunchKernelGGL((k_copy<double, double>), grid, dim3(256), 0, st, d_items);
@@ -467,25 +486,33 @@ int launch_bsr_gather(FType t, const GatherItem *d_items, int n, int b, hipStrea
   return SPAND_OK;
 }
 
-// dst(r, c) = scale * src(c, r): tile (32 x 32) read along the source rows
-// into LDS, written along the destination rows (both coalesced).
+// dst(r, c) = scale * src(c, r): tiles of 64 x 64 read along the source rows
+// into LDS (16 loads in flight per thread), written along the destination
+// rows (both coalesced).
 template <typename Ts, typename Td>
 __global__ __launch_bounds__(256) void k_copy_t(const CopyDesc *__restrict__ items, int tiles_c) {
   const CopyDesc d = items[blockIdx.x];
   const int tr = blockIdx.y / tiles_c, tc = blockIdx.y % tiles_c;
-  const int r0 = tr * 32, c0 = tc * 32;
+  const int r0 = tr * 64, c0 = tc * 64;
   if (r0 >= d.rows || c0 >= d.cols) return;
-  __shared__ Ts tile[32][33];
+  __shared__ Ts tile[64][65];
   const Ts *src = (const Ts *)d.src;
   Td *dst = (Td *)d.dst;
-  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;    // 32 x 8
-  for (int k = ty; k < 32; k += 8) {
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;    // 64 x 4
+  Ts v[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int k = ty + 4 * q;
     const int c = c0 + k, r = r0 + tx;                      // source row c, column r
-    tile[k][tx] = (c < d.cols && r < d.rows) ? src[(int64_t)c * d.lds + r] : Ts(0);
+    v[q] = (c < d.cols && r < d.rows) ? src[(int64_t)c * d.lds + r] : Ts(0);
   }
+#pragma unroll
+  for (int q = 0; q < 16; ++q) tile[ty + 4 * q][tx] = v[q];
   __syncthreads();
   const Ts sc = Ts(d.scale);
-  for (int k = ty; k < 32; k += 8) {
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int k = ty + 4 * q;
     const int r = r0 + k, c = c0 + tx;
     if (r < d.rows && c < d.cols) dst[(int64_t)r * d.ldd + c] = Td(tile[tx][k] * sc);
   }
@@ -494,8 +521,8 @@ __global__ __launch_bounds__(256) void k_copy_t(const CopyDesc *__restrict__ ite
 int launch_copy_t(FType t, int src_is_factor, const CopyDesc *d_items, int n, int max_rows,
                   int max_cols, hipStream_t st) {
   if (n <= 0) return SPAND_OK;
-  const int tiles_c = int(cdiv(max_cols, 32));
-  dim3 grid(n, unsigned(cdiv(max_rows, 32) * tiles_c));   // tiles <= 64*64 < 65536
+  const int tiles_c = int(cdiv(max_cols, 64));
+  dim3 grid(n, unsigned(cdiv(max_rows, 64) * tiles_c));   // tiles <= 32*32 < 65536
   if (t == FType::F64)
     hipLaunchKernelGGL((k_copy_t<double, double>), grid, dim3(256), 0, st, d_items, tiles_c);
   else if (src_is_factor)

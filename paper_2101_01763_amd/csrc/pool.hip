@@ -19,6 +19,7 @@
 #include <cstdlib>
 #include <map>
 #include <mutex>
+#include <vector>
 
 #include "internal.h"
 
@@ -148,6 +149,55 @@ size_t pool_cached_bytes() {
   Pool &P = pool();
   std::lock_guard<std::mutex> lk(P.mu);
   return P.cached;
+}
+
+// ----------------------------------------------------------------- timing events
+// A factorization times its phases and kernel batches with a few hundred
+// events; creating each costs host time on the path that plans the upper
+// levels, so finished events are kept per device and handed out again.
+namespace {
+struct EventCache {
+  std::mutex mu;
+  std::map<int, std::vector<hipEvent_t>> free;
+};
+EventCache &event_cache() {
+  static EventCache *c = new EventCache();
+  return *c;
+}
+constexpr size_t kEventCap = 8192;
+}  // namespace
+
+int event_get(hipEvent_t *e) {
+  int dev = 0;
+  SP_HIP(hipGetDevice(&dev));
+  {
+    EventCache &C = event_cache();
+    std::lock_guard<std::mutex> lk(C.mu);
+    auto &v = C.free[dev];
+    if (!v.empty()) {
+      *e = v.back();
+      v.pop_back();
+      return SPAND_OK;
+    }
+  }
+  SP_HIP(hipEventCreate(e));
+  return SPAND_OK;
+}
+
+void event_put(hipEvent_t e) {
+  if (!e) return;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  EventCache &C = event_cache();
+  {
+    std::lock_guard<std::mutex> lk(C.mu);
+    auto &v = C.free[dev];
+    if (v.size() < kEventCap) {
+      v.push_back(e);
+      return;
+    }
+  }
+  (void)hipEventDestroy(e);
 }
 
 }  // namespace spand
