@@ -95,7 +95,8 @@ const char *spand_last_error(void) { return last_error(); }
 // `sym` the ordering and the validated block pattern (the symbolic phase)
 // are taken from that earlier factorization of the same pattern.
 static int build_factor(const spand_bsr_t *A, const spand_grid_t *grid, const spand_opts_t *opts,
-                        void *stream, const Factor *sym, bool graphs, std::unique_ptr<Factor> &out);
+                        void *stream, const Factor *sym, bool graphs, std::unique_ptr<Factor> &out,
+                        bool one_stream = false);
 
 // Arguments of one factorization; *L_out receives the number of levels.
 static int check_factor_args(const spand_bsr_t *A, const spand_grid_t *grid,
@@ -149,12 +150,14 @@ static int factor_one(const spand_bsr_t *A, const spand_grid_t *grid, const span
 
 // Runs `body` on a new Factor with a private stream ordered after `stream`.
 static int run_build(void *stream, const std::function<int(Factor &)> &body,
-                     std::unique_ptr<Factor> &out);
+                     std::unique_ptr<Factor> &out, bool one_stream = false);
 
 static int build_factor(const spand_bsr_t *A, const spand_grid_t *grid, const spand_opts_t *opts,
-                        void *stream, const Factor *sym, bool graphs, std::unique_ptr<Factor> &out) {
+                        void *stream, const Factor *sym, bool graphs, std::unique_ptr<Factor> &out,
+                        bool one_stream) {
   std::unique_ptr<Factor> f;
-  SP_TRY(run_build(stream, [&](Factor &F) { return F.build(*A, *grid, *opts, sym); }, f));
+  SP_TRY(run_build(stream, [&](Factor &F) { return F.build(*A, *grid, *opts, sym); }, f,
+                   one_stream));
   if (graphs) SP_TRY(f->capture_graphs(1));
   f->trace("graph capture", -1);
   out = std::move(f);
@@ -162,8 +165,9 @@ static int build_factor(const spand_bsr_t *A, const spand_grid_t *grid, const sp
 }
 
 static int run_build(void *stream, const std::function<int(Factor &)> &body,
-                     std::unique_ptr<Factor> &out) {
+                     std::unique_ptr<Factor> &out, bool one_stream) {
   auto F = std::make_unique<Factor>();
+  F->one_stream = one_stream;
   // The build runs on a private non-blocking stream ordered after the
   // caller's: its descriptor uploads (synchronous copies on the null
   // stream) then never wait for the factorization's own kernels, so the
@@ -554,17 +558,20 @@ int spand_factor_batched(int32_t n, const spand_bsr_t *A, const spand_grid_t *gr
   if (std::getenv("SPAND_BATCH_SEPARATE") && std::atoi(std::getenv("SPAND_BATCH_SEPARATE"))) fw = 0;
   std::vector<std::unique_ptr<Factor>> gf(groups.size());
   std::vector<int> st;
+  // with several builds at once each keeps to its worker stream
+  const bool conc = groups.size() > 1 && fw != 1;
   SP_TRY(run_batched(int(groups.size()), (hipStream_t)stream, [&](int g, hipStream_t s) {
     set_error("");
     const auto &idx = groups[size_t(g)];
     if (idx.size() == 1) {
       const int i = idx[0];
-      return build_factor(&A[i], &grids[i], &opts[i], (void *)s, nullptr, false, gf[size_t(g)]);
+      return build_factor(&A[i], &grids[i], &opts[i], (void *)s, nullptr, false, gf[size_t(g)],
+                          conc);
     }
     std::vector<BatchSystem> sy;
     for (int i : idx) sy.push_back(BatchSystem{A[i], grids[i], Ls[size_t(i)]});
     return run_build((void *)s, [&](Factor &F) { return F.build_batch(sy, opts[idx[0]]); },
-                     gf[size_t(g)]);
+                     gf[size_t(g)], conc);
   }, st, nullptr, fw));
   for (size_t g = 0; g < groups.size(); ++g)
     if (st[g] < 0) return st[g];

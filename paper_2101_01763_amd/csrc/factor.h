@@ -120,6 +120,10 @@ struct Factor {
   hipStream_t side = nullptr;      // second stream of the build (forked from and joined to stream)
   hipStream_t side2 = nullptr;     // third one (size classes of a fused elimination block)
   hipEvent_t cls_fork = nullptr, cls_join = nullptr;
+  // no second and third stream: set when several builds share the device at
+  // once (their extra streams would share the few hardware queues with the
+  // other builds' work)
+  bool one_stream = false;
   int device = 0;
   FType ft = FType::F64;
   int bs = 0, K = 0, L = 0;

@@ -399,7 +399,7 @@ int Factor::elim_batch(std::vector<ElimDesc> &items, int mode) {
       return path(d.n) != p0;
     });
     std::vector<ElimDesc> big(items.begin(), cut), small(cut, items.end());
-    if (p0 == 0) {
+    if (p0 == 0 && !one_stream) {
       // the few matrices beyond the fused limit take a long chain of
       // one-workgroup panel launches: it runs on the side stream, beside the
       // fused launches of the others (independent matrices and scratch)
@@ -496,8 +496,10 @@ int Factor::elim_batch(std::vector<ElimDesc> &items, int mode) {
         cls.push_back({a, b});
         a = b;
       }
-      if (cls.size() == 1) {
-        SP_TRY(launch_elim_block(ft, d_items, na, k0, mode, items[0].n, bw, d_flag, stream));
+      if (cls.size() == 1 || one_stream) {
+        for (const auto &c : cls)
+          SP_TRY(launch_elim_block(ft, d_items + c.first, c.second - c.first, k0, mode,
+                                   items[c.first].n, bw, d_flag, stream));
         return launch_elim_extract(ft, d_items, na, k0, bw, lu ? 1 : 0, stream);
       }
       size_t big = 0;
