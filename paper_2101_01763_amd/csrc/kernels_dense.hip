@@ -1327,9 +1327,9 @@ int launch_row_gather(FType t, const RowGatherDesc *d_items, int n, int max_rows
 // target(b x b) -= A1 * Y * A2 for every item of a group, items in order.
 // A1, A2: b x b copies of the coupling blocks (factor precision, ld b);
 // Y: b x b block of an interior inverse (ld ldy).
-__global__ __launch_bounds__(256) void k_schur_elem_mfma(int bs, const SchurGroup *__restrict__ groups,
-                                                         const SchurItem *__restrict__ items) {
-  constexpr int LS = 65;
+__global__ __launch_bounds__(256, 4) void k_schur_elem_mfma(int bs, const SchurGroup *__restrict__ groups,
+                                                            const SchurItem *__restrict__ items) {
+  constexpr int LS = 65, NE = 16;   // rows of a b x b block per thread (b <= 64)
   const SchurGroup g = groups[blockIdx.x];
   __shared__ float L0[64 * LS];     // A1 (row-major), then -T1
   __shared__ float L1[64 * LS];     // Y, then A2 (both [k][n])
@@ -1349,20 +1349,48 @@ __global__ __launch_bounds__(256) void k_schur_elem_mfma(int bs, const SchurGrou
     L0[e] = 0.f;
     L1[e] = 0.f;
   }
+  // element (r, c) of a block: this thread takes column c = tid % 64 of the
+  // rows r = tid / 64 + 4q; the next pair's blocks are fetched into
+  // registers while the current pair is multiplied
+  const int c0 = tid & 63, r0 = tid >> 6;
+  const bool cin = c0 < bs;
+  float ra[NE], ry[NE], r2[NE];
+  auto fetch_a1y = [&](int it) {
+    const SchurItem s = items[it];
+    const float *a1 = (const float *)s.A1 + r0 * bs + c0;
+    const float *Y = (const float *)s.Y + (int64_t)r0 * s.ldy + c0;
+    const int64_t ys = 4 * (int64_t)s.ldy;
+#pragma unroll
+    for (int q = 0; q < NE; ++q)
+      if (cin && r0 + 4 * q < bs) {
+        ra[q] = a1[q * 4 * bs];
+        ry[q] = Y[q * ys];
+      }
+  };
+  auto fetch_a2 = [&](int it) {
+    const float *a2 = (const float *)items[it].A2 + r0 * bs + c0;
+#pragma unroll
+    for (int q = 0; q < NE; ++q)
+      if (cin && r0 + 4 * q < bs) r2[q] = a2[q * 4 * bs];
+  };
+  if (g.item_begin < g.item_end) {
+    fetch_a1y(g.item_begin);
+    fetch_a2(g.item_begin);
+  }
   __syncthreads();
   const float *ap = L0 + (wr * 32 + (lane & 31)) * LS + (lane >> 5);
   const float *bp = L1 + (lane >> 5) * LS + wc * 32 + (lane & 31);
+  float *l0 = L0 + r0 * LS + c0, *l1 = L1 + r0 * LS + c0;
   for (int it = g.item_begin; it < g.item_end; ++it) {
-    const SchurItem s = items[it];
-    const float *a1 = (const float *)s.A1;
-    const float *a2 = (const float *)s.A2;
-    const float *Y = (const float *)s.Y;
-    for (int idx = tid; idx < bs * bs; idx += 256) {
-      const int r = idx / bs, c = idx - r * bs;
-      L0[r * LS + c] = a1[idx];
-      L1[r * LS + c] = Y[(int64_t)r * s.ldy + c];
-    }
+    const bool more = it + 1 < g.item_end;
+#pragma unroll
+    for (int q = 0; q < NE; ++q)
+      if (cin && r0 + 4 * q < bs) {
+        l0[q * 4 * LS] = ra[q];
+        l1[q * 4 * LS] = ry[q];
+      }
     __syncthreads();
+    if (more) fetch_a1y(it + 1);
     f32x16 t1;
 #pragma unroll
     for (int r = 0; r < 16; ++r) t1[r] = 0.f;
@@ -1374,11 +1402,11 @@ __global__ __launch_bounds__(256) void k_schur_elem_mfma(int bs, const SchurGrou
       const int row = wr * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
       L0[row * LS + col] = (row < bs && col < bs) ? -t1[r] : 0.f;
     }
-    for (int idx = tid; idx < bs * bs; idx += 256) {
-      const int r = idx / bs, c = idx - r * bs;
-      L1[r * LS + c] = a2[idx];
-    }
+#pragma unroll
+    for (int q = 0; q < NE; ++q)
+      if (cin && r0 + 4 * q < bs) l1[q * 4 * LS] = r2[q];
     __syncthreads();
+    if (more) fetch_a2(it + 1);
     for (int kk = 0; kk < kmax; kk += 2)
       acc = __builtin_amdgcn_mfma_f32_32x32x2f32(ap[kk], bp[kk * LS], acc, 0, 0, 0);
     __syncthreads();
