@@ -1422,9 +1422,9 @@ __global__ __launch_bounds__(256, 4) void k_schur_elem_mfma(int bs, const SchurG
 // with v_mfma_f64_16x16x4f64, each wave a 32x32 quarter as 2x2 blocks of
 // 16x16 (layout as in k_gemm_f64_mfma); the target stays in the
 // accumulators for all its pairs.
-__global__ __launch_bounds__(256) void k_schur_elem_mfma64(int bs, const SchurGroup *__restrict__ groups,
-                                                           const SchurItem *__restrict__ items) {
-  constexpr int LS = 65;
+__global__ __launch_bounds__(256, 2) void k_schur_elem_mfma64(int bs, const SchurGroup *__restrict__ groups,
+                                                              const SchurItem *__restrict__ items) {
+  constexpr int LS = 65, NE = 16;
   const SchurGroup g = groups[blockIdx.x];
   __shared__ double L0[64 * LS];     // A1 (row-major), then -T1
   __shared__ double L1[64 * LS];     // Y, then A2 (both [k][n])
@@ -1449,7 +1449,34 @@ __global__ __launch_bounds__(256) void k_schur_elem_mfma64(int bs, const SchurGr
     L0[e] = 0.0;
     L1[e] = 0.0;
   }
+  // element mapping and prefetch of the next pair as in k_schur_elem_mfma
+  const int c0 = tid & 63, r0 = tid >> 6;
+  const bool cin = c0 < bs;
+  double ra[NE], ry[NE], r2[NE];
+  auto fetch_a1y = [&](int it) {
+    const SchurItem s = items[it];
+    const double *a1 = (const double *)s.A1 + r0 * bs + c0;
+    const double *Y = (const double *)s.Y + (int64_t)r0 * s.ldy + c0;
+    const int64_t ys = 4 * (int64_t)s.ldy;
+#pragma unroll
+    for (int q = 0; q < NE; ++q)
+      if (cin && r0 + 4 * q < bs) {
+        ra[q] = a1[q * 4 * bs];
+        ry[q] = Y[q * ys];
+      }
+  };
+  auto fetch_a2 = [&](int it) {
+    const double *a2 = (const double *)items[it].A2 + r0 * bs + c0;
+#pragma unroll
+    for (int q = 0; q < NE; ++q)
+      if (cin && r0 + 4 * q < bs) r2[q] = a2[q * 4 * bs];
+  };
+  if (g.item_begin < g.item_end) {
+    fetch_a1y(g.item_begin);
+    fetch_a2(g.item_begin);
+  }
   __syncthreads();
+  double *l0 = L0 + r0 * LS + c0, *l1 = L1 + r0 * LS + c0;
   const double *ap = L0 + (wr * 32 + (lane & 15)) * LS + (lane >> 4);
   const double *bp = L1 + (lane >> 4) * LS + wc * 32 + (lane & 15);
   auto product = [&](f64x4 (&c)[2][2]) {
@@ -1463,16 +1490,15 @@ __global__ __launch_bounds__(256) void k_schur_elem_mfma64(int bs, const SchurGr
     }
   };
   for (int it = g.item_begin; it < g.item_end; ++it) {
-    const SchurItem s = items[it];
-    const double *a1 = (const double *)s.A1;
-    const double *a2 = (const double *)s.A2;
-    const double *Y = (const double *)s.Y;
-    for (int idx = tid; idx < bs * bs; idx += 256) {
-      const int r = idx / bs, c = idx - r * bs;
-      L0[r * LS + c] = a1[idx];
-      L1[r * LS + c] = Y[(int64_t)r * s.ldy + c];
-    }
+    const bool more = it + 1 < g.item_end;
+#pragma unroll
+    for (int q = 0; q < NE; ++q)
+      if (cin && r0 + 4 * q < bs) {
+        l0[q * 4 * LS] = ra[q];
+        l1[q * 4 * LS] = ry[q];
+      }
     __syncthreads();
+    if (more) fetch_a1y(it + 1);
     f64x4 t1[2][2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
@@ -1491,11 +1517,11 @@ __global__ __launch_bounds__(256) void k_schur_elem_mfma64(int bs, const SchurGr
           L0[row * LS + col] = (row < bs && col < bs) ? -t1[i][j][r] : 0.0;
         }
       }
-    for (int idx = tid; idx < bs * bs; idx += 256) {
-      const int r = idx / bs, c = idx - r * bs;
-      L1[r * LS + c] = a2[idx];
-    }
+#pragma unroll
+    for (int q = 0; q < NE; ++q)
+      if (cin && r0 + 4 * q < bs) l1[q * 4 * LS] = r2[q];
     __syncthreads();
+    if (more) fetch_a2(it + 1);
     product(acc);
     __syncthreads();
   }
