@@ -1218,13 +1218,23 @@ __global__ __launch_bounds__(256) void k_elim_extract(const ElimDesc *__restrict
   T *TB = (T *)d.TB;
   const int64_t ld = d.ld;
   for (int q = blockIdx.y; q < wb; q += gridDim.y) {
-    const int64_t src = (int64_t)d.piv[k0 + q] * ld;
-    for (int c = threadIdx.x; c < d.ncols; c += 256) {
-      if (c < cw1 && (lu || c >= k0)) {
-        TB[(int64_t)q * ld + c] = T(0);
-      } else {
-        TB[(int64_t)q * ld + c] = A[src + c];
-        A[src + c] = T(0);
+    T *__restrict__ row = A + (int64_t)d.piv[k0 + q] * ld;
+    T *__restrict__ tb = TB + (int64_t)q * ld;
+    // four loads in flight per thread before the stores
+    for (int c0 = threadIdx.x; c0 < d.ncols; c0 += 4 * 256) {
+      T v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int c = c0 + u * 256;
+        const bool keep = c < cw1 && (lu || c >= k0);   // the block's window stays
+        v[u] = (c < d.ncols && !keep) ? row[c] : T(0);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int c = c0 + u * 256;
+        if (c >= d.ncols) break;
+        tb[c] = v[u];
+        if (!(c < cw1 && (lu || c >= k0))) row[c] = T(0);
       }
     }
   }
@@ -1303,10 +1313,21 @@ __global__ __launch_bounds__(256) void k_row_gather(const RowGatherDesc *__restr
   const T *src = (const T *)d.src;
   T *dst = (T *)d.dst;
   for (int j = blockIdx.y; j < d.n; j += gridDim.y) {
-    const int64_t sr = (int64_t)d.piv[j] * d.lds;
-    for (int c = threadIdx.x; c < d.cols; c += blockDim.x) {
-      const int sc = d.colperm ? pinv[c] : c + d.col_off;
-      dst[(int64_t)j * d.ldd + c] = src[sr + sc];
+    const T *srow = src + (int64_t)d.piv[j] * d.lds;
+    T *drow = dst + (int64_t)j * d.ldd;
+    // four loads in flight per thread before the stores
+    for (int c0 = threadIdx.x; c0 < d.cols; c0 += 4 * 256) {
+      T v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int c = c0 + u * 256;
+        if (c < d.cols) v[u] = srow[d.colperm ? pinv[c] : c + d.col_off];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int c = c0 + u * 256;
+        if (c < d.cols) drow[c] = v[u];
+      }
     }
   }
 }
