@@ -1779,13 +1779,26 @@ __global__ __launch_bounds__(256, 3) void k_qrcp(const QrcpDesc *__restrict__ it
   // |R_00| is the largest column norm; the 1e-4 margin keeps a column whose
   // norm ties the threshold up to rounding
   const double thr = force_full ? 0.0 : eps * cmax * (1.0 - 1e-4);
-  auto live_group = [&](int g) {
-    bool a = false;
+  // A group's flags and norms, loaded together (one memory round trip; the
+  // empty statement keeps the compiler from moving the loads apart into
+  // the branches that use them).
+  auto load_group = [&](int g, int (&sg)[VN], double (&vg)[VN]) {
 #pragma unroll
     for (int q = 0; q < VN; ++q) {
-      const int j = g * VN + q;
-      if (!sel[j] && vn1[j] > thr) a = true;
+      sg[q] = sel[g * VN + q];
+      vg[q] = vn1[g * VN + q];
     }
+#pragma unroll
+    for (int q = 0; q < VN; ++q) asm volatile("" ::"v"(sg[q]), "v"(vg[q]));
+  };
+  auto live_group = [&](int g) {
+    int sg[VN];
+    double vg[VN];
+    load_group(g, sg, vg);
+    bool a = false;
+#pragma unroll
+    for (int q = 0; q < VN; ++q)
+      if (!sg[q] && vg[q] > thr) a = true;
     return a;
   };
   // Order-preserving filter of a list of groups (src == nullptr: all groups
@@ -1859,11 +1872,14 @@ __global__ __launch_bounds__(256, 3) void k_qrcp(const QrcpDesc *__restrict__ it
     int bi = INT_MAX;
     for (int qa = tid; qa < nact; qa += 256) {
       const int g = act[qa];
+      int sg[VN];
+      double vg[VN];
+      load_group(g, sg, vg);
 #pragma unroll
       for (int q = 0; q < VN; ++q) {
         const int j = g * VN + q;
-        if (sel[j]) continue;
-        const double v = vn1[j];
+        if (sg[q]) continue;
+        const double v = vg[q];
         if (v > bv || (v == bv && j < bi)) { bv = v; bi = j; }
       }
     }
@@ -1949,8 +1965,10 @@ __global__ __launch_bounds__(256, 3) void k_qrcp(const QrcpDesc *__restrict__ it
 #pragma unroll 1
         for (int q = 0; q < VN; ++q) {
           const int j = g * VN + q;
-          if (sel[j]) continue;
+          const int sj = sel[j];
           const double v = vn1[j];
+          asm volatile("" ::"v"(sj), "v"(v));   // both loads in one round trip
+          if (sj) continue;
           if (better(v, j, tv[BQ - 1], ti[BQ - 1])) {
             tv[BQ - 1] = v;
             ti[BQ - 1] = j;
@@ -2198,18 +2216,29 @@ __global__ __launch_bounds__(256, 3) void k_qrcp(const QrcpDesc *__restrict__ it
 #pragma unroll
         for (int q = 0; q < VN; ++q) {
           const int j = g * VN + q;
-          if (sel[j]) continue;
+          // the column's flag, norms and coordinates are loaded together
+          // (every index lies in the arrays), then used
+          const int sj = sel[j];
+          const double a = vn1[j];
+          const double b = vn2[j];
+          double2 h2[BQ / 2];
+#pragma unroll
+          for (int l = 0; l < BQ; l += 2)
+            h2[l / 2] = *reinterpret_cast<const double2 *>(hg + q * BQ + l);
+          // an empty statement that takes every loaded value keeps the
+          // loads together here (one memory round trip per column) instead
+          // of one after another inside the branches below
+          asm volatile("" ::"v"(sj), "v"(a), "v"(b));
+#pragma unroll
+          for (int l = 0; l < BQ / 2; ++l) asm volatile("" ::"v"(h2[l].x), "v"(h2[l].y));
+          if (sj) continue;
           double rk = 0.0;
 #pragma unroll
-          for (int l = 0; l < BQ; l += 2) {
-            const double2 h2 = *reinterpret_cast<const double2 *>(hg + q * BQ + l);
-            rk += ck[l] * h2.x + ck[l + 1] * h2.y;
-          }
-          const double a = vn1[j];
+          for (int l = 0; l < BQ; l += 2) rk += ck[l] * h2[l / 2].x + ck[l + 1] * h2[l / 2].y;
+          double v = a;                 // the column's norm after this step
           if (a != 0.0) {
             double temp = fabs(rk) / a;
             temp = fmax(0.0, (1.0 + temp) * (1.0 - temp));
-            const double b = vn2[j];
             const double t2 = temp * (a / b) * (a / b);
             if (t2 <= tol3z) {
               // The estimate fell below sqrt(tol3z) b ~ 1.2e-4 b; with the
@@ -2217,16 +2246,16 @@ __global__ __launch_bounds__(256, 3) void k_qrcp(const QrcpDesc *__restrict__ it
               // the stopping threshold the column can never be a pivot
               // before the method stops: it is dropped, not recomputed.
               if (2e-4 * b < thr) {
-                vn1[j] = 0.0;
+                v = 0.0;
               } else {
-                vn1[j] = -1.0;        // recomputed below
+                v = -1.0;             // recomputed below
                 atomicAdd(&s_nflag, 1);
               }
             } else {
-              vn1[j] = a * sqrt(temp);
+              v = a * sqrt(temp);
             }
+            vn1[j] = v;
           }
-          const double v = vn1[j];
           if (v > nbv || (v == nbv && j < nbi)) { nbv = v; nbi = j; }
         }
       }
