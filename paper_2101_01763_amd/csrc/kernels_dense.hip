@@ -2033,8 +2033,21 @@ __global__ __launch_bounds__(256, 3) void k_qrcp(const QrcpDesc *__restrict__ it
           for (int cq = 0; cq < BQ; ++cq) a[cq] = 0.0;
           if (t < k) {
             const T *qt = Qt + (int64_t)t * m;
-#pragma unroll 4
-            for (int r = rq; r < m; r += 4) {
+            // eight rows' loads in one round trip, then their products in
+            // row order
+            int r = rq;
+            for (; r + 28 < m; r += 32) {
+              T qv[8];
+#pragma unroll
+              for (int u = 0; u < 8; ++u) qv[u] = qt[r + 4 * u];
+#pragma unroll
+              for (int u = 0; u < 8; ++u) asm volatile("" ::"v"(qv[u]));
+#pragma unroll
+              for (int u = 0; u < 8; ++u)
+#pragma unroll
+                for (int cq = 0; cq < BQ; ++cq) a[cq] += double(qv[u]) * Bm[cq * MS + r + 4 * u];
+            }
+            for (; r < m; r += 4) {
               const double qv = double(qt[r]);
 #pragma unroll
               for (int cq = 0; cq < BQ; ++cq) a[cq] += qv * Bm[cq * MS + r];
@@ -2055,8 +2068,19 @@ __global__ __launch_bounds__(256, 3) void k_qrcp(const QrcpDesc *__restrict__ it
         double sv[BQ];
 #pragma unroll
         for (int cq = 0; cq < BQ; ++cq) sv[cq] = 0.0;
-#pragma unroll 4
-        for (int t = 0; t < k; ++t) {
+        int t = 0;
+        for (; t + 8 <= k; t += 8) {       // eight loads per round trip, products in order
+          T qv[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) qv[u] = Qt[(int64_t)(t + u) * m + r];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) asm volatile("" ::"v"(qv[u]));
+#pragma unroll
+          for (int u = 0; u < 8; ++u)
+#pragma unroll
+            for (int cq = 0; cq < BQ; ++cq) sv[cq] += P[(t + u) * BQ + cq] * double(qv[u]);
+        }
+        for (; t < k; ++t) {
           const double qv = double(Qt[(int64_t)t * m + r]);
 #pragma unroll
           for (int cq = 0; cq < BQ; ++cq) sv[cq] += P[t * BQ + cq] * qv;
