@@ -351,6 +351,21 @@ __global__ __launch_bounds__(256, 4) void k_gemm_f64_mfma(const GemmDesc *__rest
   }
   gdouble *C = (gdouble *)d.C;
   const double al = d.alpha, be = d.beta;
+  // C (when it is accumulated): every load from an in-range (clamped)
+  // address, all in one round trip
+  double cv[2][2][4];
+  if (be != 0.0)
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int gnc = min(n0 + wc * 32 + j * 16 + (lane & 15), d.N - 1);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int gm = m0 + wr * 32 + i * 16 + (lane >> 4) + 4 * r;
+          cv[i][j][r] = C[min(gm, d.M - 1) * d.ldc + gnc];
+        }
+      }
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -360,10 +375,9 @@ __global__ __launch_bounds__(256, 4) void k_gemm_f64_mfma(const GemmDesc *__rest
       for (int r = 0; r < 4; ++r) {
         const int gm = m0 + wr * 32 + i * 16 + (lane >> 4) + 4 * r;
         if (gm < d.M && gn < d.N) {
-          gdouble *c = C + gm * d.ldc + gn;
           double v = al * acc[i][j][r];
-          if (be != 0.0) v += be * (*c);
-          *c = v;
+          if (be != 0.0) v += be * cv[i][j][r];
+          C[gm * d.ldc + gn] = v;
         }
       }
     }
