@@ -2248,53 +2248,60 @@ __global__ __launch_bounds__(256, 3) void k_qrcp(const QrcpDesc *__restrict__ it
       // pivot search rides along on the new norms
       double nbv = -1.0;
       int nbi = INT_MAX;
+      // one column's downdate from its loaded flag, norms and coordinates
+      auto downdate = [&](int j, int sj, double a, double b, const double2 (&h2)[BQ / 2]) {
+        if (sj) return;
+        double rk = 0.0;
+#pragma unroll
+        for (int l = 0; l < BQ; l += 2) rk += ck[l] * h2[l / 2].x + ck[l + 1] * h2[l / 2].y;
+        double v = a;                   // the column's norm after this step
+        if (a != 0.0) {
+          double temp = fabs(rk) / a;
+          temp = fmax(0.0, (1.0 + temp) * (1.0 - temp));
+          const double t2 = temp * (a / b) * (a / b);
+          if (t2 <= tol3z) {
+            // The estimate fell below sqrt(tol3z) b ~ 1.2e-4 b; with the
+            // downdating error the true residual stays below 2e-4 b.  Under
+            // the stopping threshold the column can never be a pivot
+            // before the method stops: it is dropped, not recomputed.
+            if (2e-4 * b < thr) {
+              v = 0.0;
+            } else {
+              v = -1.0;               // recomputed below
+              atomicAdd(&s_nflag, 1);
+            }
+          } else {
+            v = a * sqrt(temp);
+          }
+          vn1[j] = v;
+        }
+        if (v > nbv || (v == nbv && j < nbi)) { nbv = v; nbi = j; }
+      };
       for (int qa = tid; qa < nact_cur; qa += 256) {
         const int g = act[qa];
         const double *hg = H + (int64_t)g * VN * BQ;
 #pragma unroll
-        for (int q = 0; q < VN; ++q) {
-          const int j = g * VN + q;
-          // the column's flag, norms and coordinates are loaded together
-          // (every index lies in the arrays), then used
-          const int sj = sel[j];
-          const double a = vn1[j];
-          const double b = vn2[j];
-          double2 h2[BQ / 2];
+        for (int q = 0; q < VN; q += 2) {
+          // two columns' flags, norms and coordinates are loaded together
+          // (every index lies in the arrays); an empty statement that takes
+          // every loaded value keeps the loads at this point (one memory
+          // round trip) instead of one after another in the branches
+          const int j0 = g * VN + q;
+          const int s0 = sel[j0], s1 = sel[j0 + 1];
+          const double a0 = vn1[j0], a1 = vn1[j0 + 1];
+          const double b0 = vn2[j0], b1 = vn2[j0 + 1];
+          double2 h0[BQ / 2], h1[BQ / 2];
 #pragma unroll
-          for (int l = 0; l < BQ; l += 2)
-            h2[l / 2] = *reinterpret_cast<const double2 *>(hg + q * BQ + l);
-          // an empty statement that takes every loaded value keeps the
-          // loads together here (one memory round trip per column) instead
-          // of one after another inside the branches below
-          asm volatile("" ::"v"(sj), "v"(a), "v"(b));
-#pragma unroll
-          for (int l = 0; l < BQ / 2; ++l) asm volatile("" ::"v"(h2[l].x), "v"(h2[l].y));
-          if (sj) continue;
-          double rk = 0.0;
-#pragma unroll
-          for (int l = 0; l < BQ; l += 2) rk += ck[l] * h2[l / 2].x + ck[l + 1] * h2[l / 2].y;
-          double v = a;                 // the column's norm after this step
-          if (a != 0.0) {
-            double temp = fabs(rk) / a;
-            temp = fmax(0.0, (1.0 + temp) * (1.0 - temp));
-            const double t2 = temp * (a / b) * (a / b);
-            if (t2 <= tol3z) {
-              // The estimate fell below sqrt(tol3z) b ~ 1.2e-4 b; with the
-              // downdating error the true residual stays below 2e-4 b.  Under
-              // the stopping threshold the column can never be a pivot
-              // before the method stops: it is dropped, not recomputed.
-              if (2e-4 * b < thr) {
-                v = 0.0;
-              } else {
-                v = -1.0;             // recomputed below
-                atomicAdd(&s_nflag, 1);
-              }
-            } else {
-              v = a * sqrt(temp);
-            }
-            vn1[j] = v;
+          for (int l = 0; l < BQ; l += 2) {
+            h0[l / 2] = *reinterpret_cast<const double2 *>(hg + q * BQ + l);
+            h1[l / 2] = *reinterpret_cast<const double2 *>(hg + (q + 1) * BQ + l);
           }
-          if (v > nbv || (v == nbv && j < nbi)) { nbv = v; nbi = j; }
+          asm volatile("" ::"v"(s0), "v"(a0), "v"(b0), "v"(s1), "v"(a1), "v"(b1));
+#pragma unroll
+          for (int l = 0; l < BQ / 2; ++l)
+            asm volatile("" ::"v"(h0[l].x), "v"(h0[l].y), "v"(h1[l].x), "v"(h1[l].y));
+          downdate(j0, s0, a0, b0, h0);
+          downdate(j0 + 1, s1, a1, b1, h1);
         }
       }
       __syncthreads();
