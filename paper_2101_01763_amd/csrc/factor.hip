@@ -1034,10 +1034,20 @@ int Factor::level0(const NDResult &nd, LevelState &S) {
     std::vector<SchurGroup> groups(tkey.size());
     std::vector<SchurItem> items(nitems);
     {
+      // consecutive targets come from one leaf's few neighbour clusters: a
+      // small direct-mapped cache in front of the cluster-pair search
+      struct PairHit {
+        int64_t key;
+        const Blk *blk;
+      };
+      std::vector<PairHit> hit(256, PairHit{-1, nullptr});
       int off = 0;
       for (size_t id = 0; id < tkey.size(); ++id) {
         const int ea = tkey[id].first, ec = tkey[id].second;
-        const Blk &B = pair_blk(ecl[ea], ecl[ec]);
+        const int64_t pk = int64_t(ecl[ea]) * ncl + ecl[ec];
+        PairHit &h = hit[size_t(uint64_t(pk) * 0x9E3779B97F4A7C15ull >> 56)];
+        if (h.key != pk) h = PairHit{pk, &pair_blk(ecl[ea], ecl[ec])};
+        const Blk &B = *h.blk;
         SchurGroup &g = groups[id];
         g.target = (char *)B.p + (size_t(epos[ea]) * b * B.cols + size_t(epos[ec]) * b) * tsz;
         g.ldt = B.cols;
@@ -1085,20 +1095,32 @@ int Factor::level0(const NDResult &nd, LevelState &S) {
   // ---- stored couplings and apply descriptors of level 0
   ApplyLevel &AL = lv[0];
   {
-    // element -> list of (partner element, block ptr)
-    using PairList = std::vector<std::vector<std::pair<int, void *>>>;
-    PairList fw_ns(K), fw_sn(K);   // indexed by separator element e
-    PairList bw_sn(K), bw_ns(K);   // indexed by leaf element f
+    // couplings indexed by separator element e and by leaf element f
+    // (counting sort, stable: a key's couplings keep their (leaf, coupling)
+    // order, which is the order the pull kernels accumulate them in)
+    std::vector<int> off_e(size_t(K) + 1, 0), off_f(size_t(K) + 1, 0);
     for (int s : leaves)
-      for (size_t i = 0; i < coup[s].size(); ++i) {
-        const auto &c = coup[s][i];
-        void *pns = cpl_ns(s, i), *psn = cpl_sn(s, i);
-        fw_ns[c.e].push_back({c.f, pns});
-        fw_sn[c.e].push_back({c.f, psn});
-        bw_sn[c.f].push_back({c.e, psn});
-        bw_ns[c.f].push_back({c.e, pns});
+      for (const auto &c : coup[s]) {
+        ++off_e[size_t(c.e) + 1];
+        ++off_f[size_t(c.f) + 1];
       }
-    auto build = [&](PairList &m, int trans, std::vector<PullGroup> &G, std::vector<PullItem> &I,
+    for (int e = 0; e < K; ++e) {
+      off_e[size_t(e) + 1] += off_e[size_t(e)];
+      off_f[size_t(e) + 1] += off_f[size_t(e)];
+    }
+    std::vector<std::pair<int, size_t>> by_e(ncp), by_f(ncp);   // (partner, coupling index)
+    {
+      std::vector<int> ce(off_e.begin(), off_e.end() - 1), cf(off_f.begin(), off_f.end() - 1);
+      for (int s : leaves)
+        for (size_t i = 0; i < coup[s].size(); ++i) {
+          const auto &c = coup[s][i];
+          by_e[size_t(ce[c.e]++)] = {c.f, cpl0[s] + i};
+          by_f[size_t(cf[c.f]++)] = {c.e, cpl0[s] + i};
+        }
+    }
+    // one pull group per key element; half = 0 takes A[e, f], 1 A[f, e]
+    auto build = [&](const std::vector<int> &off, const std::vector<std::pair<int, size_t>> &lst,
+                     int half, int trans, std::vector<PullGroup> &G, std::vector<PullItem> &I,
                      std::vector<int> &gs, bool all_leaf) {
       std::vector<int> keys;
       if (all_leaf) {
@@ -1107,17 +1129,20 @@ int Factor::level0(const NDResult &nd, LevelState &S) {
         std::sort(keys.begin(), keys.end());
       } else {
         for (int e = 0; e < K; ++e)
-          if (!m[e].empty()) keys.push_back(e);
+          if (off[size_t(e) + 1] > off[size_t(e)]) keys.push_back(e);
       }
+      G.reserve(keys.size());
+      I.reserve(lst.size());
+      gs.reserve(keys.size());
       for (int key : keys) {
         PullGroup g{};
         g.oslot = d_iota + int64_t(key) * b;
         g.rows = b;
         g.item_begin = int(I.size());
-        for (auto &pp : m[key]) {
+        for (int t = off[size_t(key)]; t < off[size_t(key) + 1]; ++t) {
           PullItem p{};
-          p.B = pp.second;
-          p.islot = d_iota + int64_t(pp.first) * b;
+          p.B = (char *)cb + (2 * lst[size_t(t)].second + size_t(half)) * b2 * tsz;
+          p.islot = d_iota + int64_t(lst[size_t(t)].first) * b;
           p.rows = p.cols = b;
           p.ldb = b;
           p.trans = trans;
@@ -1128,32 +1153,46 @@ int Factor::level0(const NDResult &nd, LevelState &S) {
         gs.push_back(members.empty() ? 0 : esys[size_t(key)]);
       }
     };
-    std::vector<PullGroup> G;
-    std::vector<PullItem> I;
-    std::vector<int> gs;
-    build(fw_ns, 0, G, I, gs, false);
-    defer([this, &AL, G, I, gs]() {
-      SP_TRY(AL.fw.set(*this, G, I));
-      return member_pull(0, &ApplyLevel::fw, G, I, gs);
-    });
-    G.clear(); I.clear(); gs.clear();
-    build(bw_sn, 0, G, I, gs, false);
-    defer([this, &AL, G, I, gs]() {
-      SP_TRY(AL.bw.set(*this, G, I));
-      return member_pull(0, &ApplyLevel::bw, G, I, gs);
-    });
-    G.clear(); I.clear(); gs.clear();
-    build(fw_sn, 1, G, I, gs, false);
-    defer([this, &AL, G, I, gs]() {
-      SP_TRY(AL.tfw.set(*this, G, I));
-      return member_pull(0, &ApplyLevel::tfw, G, I, gs);
-    });
-    G.clear(); I.clear(); gs.clear();
-    build(bw_ns, 1, G, I, gs, true);
-    defer([this, &AL, G, I, gs]() {
-      SP_TRY(AL.tbw.set(*this, G, I));
-      return member_pull(0, &ApplyLevel::tbw, G, I, gs);
-    });
+    {
+      std::vector<PullGroup> G;
+      std::vector<PullItem> I;
+      std::vector<int> gs;
+      build(off_e, by_e, 0, 0, G, I, gs, false);
+      defer([this, &AL, G = std::move(G), I = std::move(I), gs = std::move(gs)]() {
+        SP_TRY(AL.fw.set(*this, G, I));
+        return member_pull(0, &ApplyLevel::fw, G, I, gs);
+      });
+    }
+    {
+      std::vector<PullGroup> G;
+      std::vector<PullItem> I;
+      std::vector<int> gs;
+      build(off_f, by_f, 1, 0, G, I, gs, false);
+      defer([this, &AL, G = std::move(G), I = std::move(I), gs = std::move(gs)]() {
+        SP_TRY(AL.bw.set(*this, G, I));
+        return member_pull(0, &ApplyLevel::bw, G, I, gs);
+      });
+    }
+    {
+      std::vector<PullGroup> G;
+      std::vector<PullItem> I;
+      std::vector<int> gs;
+      build(off_e, by_e, 1, 1, G, I, gs, false);
+      defer([this, &AL, G = std::move(G), I = std::move(I), gs = std::move(gs)]() {
+        SP_TRY(AL.tfw.set(*this, G, I));
+        return member_pull(0, &ApplyLevel::tfw, G, I, gs);
+      });
+    }
+    {
+      std::vector<PullGroup> G;
+      std::vector<PullItem> I;
+      std::vector<int> gs;
+      build(off_f, by_f, 0, 1, G, I, gs, true);
+      defer([this, &AL, G = std::move(G), I = std::move(I), gs = std::move(gs)]() {
+        SP_TRY(AL.tbw.set(*this, G, I));
+        return member_pull(0, &ApplyLevel::tbw, G, I, gs);
+      });
+    }
     trace("pull sets", 0);
     std::vector<GemvDesc> gv;
     std::vector<const std::vector<int32_t> *> os;
