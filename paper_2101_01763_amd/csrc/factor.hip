@@ -1891,7 +1891,15 @@ int Factor::sparsify(int l, const NDResult &nd, LevelState &S, LevelState &Nx) {
     // one launch per (block width, completion) class; the LDS of a launch is
     // laid out for its largest m and its largest number of column groups,
     // which may come from different interfaces, so a class is cut into
-    // several launches where the two together would not fit
+    // several launches where the two together would not fit.  Within a
+    // launch the interfaces go largest first (m times columns): workgroups
+    // start in index order, so the small ones fill the last wave of the
+    // grid instead of a large one starting last and running alone.
+    std::vector<size_t> qord(ifs.size());
+    for (size_t q = 0; q < ifs.size(); ++q) qord[q] = q;
+    std::stable_sort(qord.begin(), qord.end(), [&](size_t a, size_t c) {
+      return int64_t(S.size[ifs[a]]) * ncols[ifs[a]] > int64_t(S.size[ifs[c]]) * ncols[ifs[c]];
+    });
     for (const int cq : {0, 1})
       for (const int bq : {8, 4, 2}) {
         std::vector<QrcpDesc> qc;
@@ -1906,7 +1914,7 @@ int Factor::sparsify(int l, const NDResult &nd, LevelState &S, LevelState &Nx) {
           mq = mg = 1;
           return SPAND_OK;
         };
-        for (size_t q = 0; q < ifs.size(); ++q) {
+        for (const size_t q : qord) {
           const int s = ifs[q];
           if (cq_in[s] != cq || bqs[s] != bq) continue;
           if (qrcp_lds_bytes(std::max(mq, S.size[s]), std::max(mg, grp[s]), bq) > QRCP_MAX_LDS)
