@@ -13,7 +13,7 @@ timed region; HBM traffic from the committed PMC measurement while its kernel
 source is unchanged), the HBM rooflines of the SpMV and of the preconditioner
 apply, the matrix-core roofline of the factorization's products, the
 achievable copy and matrix-core ceilings measured on the device, the
-survey's other C3 points (L = 12; eps = 0.1), the other factor precision
+other 256x256 p = 3 points (L = 12; eps = 0.1), the other factor precision
 (median of three steps in a child process), and the CPU oracle timed on a
 bounded sample of the same operator family.
 """
@@ -545,7 +545,7 @@ def main():
         out["roofline_factor_mfma"]["frac_of_measured"] = g["tflops"] / (
             ceil["mfma_f32_TFs"] if args.dtype == "f32" else ceil["mfma_f64_TFs"])
     if not args.no_secondary and args.workload == "c3":
-        # the survey's other C3 points, same process and precision: the
+        # the other 256x256 p = 3 points, same process and precision: the
         # element rule's L = 12, and the paper's other tolerance eps = 0.1
         sec = []
         for e2, L2 in ((eps, 12), (1e-1, L)):

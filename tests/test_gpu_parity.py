@@ -2,7 +2,8 @@
 same seeded inputs (C1-sized and small ragged grids).  Tolerances:
   * SpMV / pattern outer product: 1e-14 relative (float64 sums of 5 b x b
     blocks, same data);
-  * eps = 0 spaND apply vs the direct solve: 1e-12 (north-star bound);
+  * eps = 0 spaND apply vs the direct solve: 1e-12 (an exact factorization:
+    only rounding separates the two);
   * eps > 0 FP64 apply vs oracle apply: 1e-10 relative, when the ranks agree
     level by level (otherwise the paths legitimately differ);
   * s-step GMRES FP64: same iteration count, x within 1e-10 of the oracle's.
