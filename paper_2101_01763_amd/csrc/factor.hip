@@ -1276,7 +1276,16 @@ int GemvSet::set(Factor &F, std::vector<GemvDesc> items,
                  const std::vector<const std::vector<int32_t> *> &oslots, int trans, int rows) {
   n = int(items.size());
   if (!n) return SPAND_OK;
-  const int R = trans ? 256 : (rows > 0 ? rows : F.gemv_rows);
+  int R = trans ? 256 : (rows > 0 ? rows : F.gemv_rows);
+  if (!trans && rows <= 0) {
+    // a set of fewer than 4096 bands (16 per CU: the upper levels) takes
+    // shorter bands, down to one 16-row pass per workgroup: its launch is
+    // bound by the passes' latency, not by bytes.  Each row's sum is the
+    // same whatever the band.
+    int64_t tot = 0;
+    for (const auto &d : items) tot += d.rows;
+    while (R > 16 && tot < int64_t(R) * 4096) R /= 2;
+  }
   std::vector<GemvChunk> ch;
   std::vector<int32_t> sl;
   for (int i = 0; i < n; ++i) {
