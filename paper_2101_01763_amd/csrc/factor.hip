@@ -1153,46 +1153,22 @@ int Factor::level0(const NDResult &nd, LevelState &S) {
         gs.push_back(members.empty() ? 0 : esys[size_t(key)]);
       }
     };
-    {
+    // each set is uploaded at the next rank read-back
+    auto emit = [&](const std::vector<int> &off, const std::vector<std::pair<int, size_t>> &lst,
+                    int half, int trans, bool all_leaf, PullSet ApplyLevel::*which) {
       std::vector<PullGroup> G;
       std::vector<PullItem> I;
       std::vector<int> gs;
-      build(off_e, by_e, 0, 0, G, I, gs, false);
-      defer([this, &AL, G = std::move(G), I = std::move(I), gs = std::move(gs)]() {
-        SP_TRY(AL.fw.set(*this, G, I));
-        return member_pull(0, &ApplyLevel::fw, G, I, gs);
+      build(off, lst, half, trans, G, I, gs, all_leaf);
+      defer([this, &AL, which, G = std::move(G), I = std::move(I), gs = std::move(gs)]() {
+        SP_TRY((AL.*which).set(*this, G, I));
+        return member_pull(0, which, G, I, gs);
       });
-    }
-    {
-      std::vector<PullGroup> G;
-      std::vector<PullItem> I;
-      std::vector<int> gs;
-      build(off_f, by_f, 1, 0, G, I, gs, false);
-      defer([this, &AL, G = std::move(G), I = std::move(I), gs = std::move(gs)]() {
-        SP_TRY(AL.bw.set(*this, G, I));
-        return member_pull(0, &ApplyLevel::bw, G, I, gs);
-      });
-    }
-    {
-      std::vector<PullGroup> G;
-      std::vector<PullItem> I;
-      std::vector<int> gs;
-      build(off_e, by_e, 1, 1, G, I, gs, false);
-      defer([this, &AL, G = std::move(G), I = std::move(I), gs = std::move(gs)]() {
-        SP_TRY(AL.tfw.set(*this, G, I));
-        return member_pull(0, &ApplyLevel::tfw, G, I, gs);
-      });
-    }
-    {
-      std::vector<PullGroup> G;
-      std::vector<PullItem> I;
-      std::vector<int> gs;
-      build(off_f, by_f, 0, 1, G, I, gs, true);
-      defer([this, &AL, G = std::move(G), I = std::move(I), gs = std::move(gs)]() {
-        SP_TRY(AL.tbw.set(*this, G, I));
-        return member_pull(0, &ApplyLevel::tbw, G, I, gs);
-      });
-    }
+    };
+    emit(off_e, by_e, 0, 0, false, &ApplyLevel::fw);    // x_n -= A_ns t_s
+    emit(off_f, by_f, 1, 0, false, &ApplyLevel::bw);    // x_s -= A_sn x_n
+    emit(off_e, by_e, 1, 1, false, &ApplyLevel::tfw);   // x_n -= A_sn^T x_s
+    emit(off_f, by_f, 0, 1, true, &ApplyLevel::tbw);    // t_s = A_ns^T x_n
     trace("pull sets", 0);
     std::vector<GemvDesc> gv;
     std::vector<const std::vector<int32_t> *> os;
